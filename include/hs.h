@@ -1,0 +1,165 @@
+/*
+ * hs.h -- C ABI of the HIP library for exact data-series k-NN search
+ * (filter-and-refine over a collection resident in GPU memory).
+ *
+ * Method: Hercules (Echihabi et al., PVLDB 15(10), 2022), Sec. 3.3 query
+ * answering: a per-leaf LB_EAPCA bound over segment mean/std envelopes, a
+ * per-series LB_SAX bound (PAA over w segments against Gaussian breakpoints,
+ * alphabet 256), and exact squared-Euclidean refinement with a running k-th
+ * best-so-far distance (BSF_k) and early abandoning.
+ *
+ * Conventions for every entry point:
+ *  - Pointers named *_dev are device pointers; pointers without the suffix are
+ *    host pointers.  The caller owns and frees every device buffer (input
+ *    series, index memory, query workspace, outputs).  The library owns only
+ *    the opaque host handle returned by hs_build_summaries.
+ *  - `stream` is a hipStream_t passed as void* (NULL = the null stream).  All
+ *    device work is enqueued on it.  hs_build_summaries synchronises the
+ *    stream (the leaf partition runs on the host); hs_knn_exact synchronises
+ *    it once, at the end, to read the pool-overflow flags (see below).
+ *  - Return value: HS_OK (0) or a negative hs_status.  Argument errors are
+ *    detected before any work is enqueued.  On failure hs_last_error()
+ *    returns a thread-local, NUL-terminated message.  No C++ exception
+ *    crosses the ABI.
+ *  - Inputs are not z-normalised by the library (the paper normalises data
+ *    and queries up front; callers do it).
+ */
+#ifndef HS_H
+#define HS_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t hs_status;
+#define HS_OK 0
+#define HS_EINVAL (-1)   /* invalid argument (sizes, NULL pointers, non-finite input) */
+#define HS_ENOMEM (-2)   /* caller-provided buffer too small, or host allocation failed */
+#define HS_EHIP (-3)     /* a HIP runtime call failed */
+#define HS_EBUSY (-4)    /* reserved */
+
+/* Largest k accepted by hs_knn_exact (the per-workgroup top-k lives in LDS). */
+#define HS_KMAX 128
+
+/*
+ * Index parameters.
+ *  n          series length (points), 1 <= n <= 16384.
+ *  w          PAA / iSAX segments, 1 <= w <= 64, w divides n (Sec. 2: PAA
+ *             uses equal-length segments; the paper uses 16).
+ *  card_bits  bits per iSAX symbol; must be 8 (alphabet 256, Sec. 2).
+ *  leaf_size  leaf capacity tau (Sec. 3.1): a node holding more than tau
+ *             series is split, unless no H-split separates its series.
+ *  l_max      leaves refined in full by the approximate search that seeds
+ *             BSF_k (Sec. 3.3 step 1; 1 by default in the paper), >= 0.
+ *  seed_rows  additional seed: the seed_rows series of the l_max leaves with
+ *             the smallest LB_SAX are refined first (0 = refine the seed
+ *             leaves in storage order).  Access-path choice only.
+ *  eapca_th   Sec. 3.3 threshold: a query whose leaf pruning ratio is below
+ *             it skips the LB_SAX filter and scans its candidate leaves.
+ *             Access-path choice only; results do not depend on it.
+ */
+typedef struct {
+    int32_t n;
+    int32_t w;
+    int32_t card_bits;
+    int32_t leaf_size;
+    int32_t l_max;
+    int32_t seed_rows;
+    float eapca_th;
+    float reserved_f;
+} hs_params;
+
+typedef struct hs_index hs_index; /* opaque, library-owned host handle */
+
+/* Properties of a built index. */
+typedef struct {
+    int64_t n_series;    /* N */
+    int32_t n;           /* series length */
+    int32_t w;           /* PAA segments */
+    int32_t row_stride;  /* floats per stored row (n rounded up to 64) */
+    int32_t word_stride; /* bytes per stored iSAX word (w rounded up to 16) */
+    int64_t n_leaves;    /* L */
+    int64_t max_leaf;    /* largest leaf (series) */
+    int64_t index_bytes; /* device bytes the index occupies */
+} hs_index_info;
+
+/*
+ * Device bytes hs_build_summaries needs in `index_mem_dev` for N series:
+ * the leaf-ordered copy of the series (the LRDFile analogue, Sec. 3.1),
+ * the iSAX words in the same order (the LSDFile analogue), the id map,
+ * the leaf table and envelopes, plus build-time scratch.
+ * Errors: HS_EINVAL for N < 1, N >= 2^32, or invalid params.
+ */
+hs_status hs_index_bytes(int64_t N, const hs_params* params, int64_t* bytes);
+
+/*
+ * Build the index over x_dev (float32 [N][n], row-major, read only).
+ * Computes per series the EAPCA segment statistics and the iSAX word
+ * (Sec. 2), partitions the series into leaves by mean/std midpoint H-splits
+ * (Sec. 3.1; see DESIGN notes for the split policy), stores the series in
+ * leaf order, and computes every leaf's synopsis (Sec. 3.1, min/max of
+ * segment mean and std, rounded outward to float32).
+ * x_dev may be freed after the call returns.  index_mem_dev must hold
+ * hs_index_bytes() bytes and stay allocated until hs_index_free.
+ * Errors: HS_EINVAL (NULL pointers, bad params, N out of range, non-finite
+ * values in x), HS_ENOMEM (index_bytes too small or host memory), HS_EHIP.
+ */
+hs_status hs_build_summaries(const float* x_dev, int64_t N, const hs_params* params,
+                             void* index_mem_dev, int64_t index_bytes, void* stream,
+                             hs_index** out);
+
+/* Properties of a built index (host copy). */
+hs_status hs_get_info(const hs_index* idx, hs_index_info* out);
+
+/* Device bytes of query workspace hs_knn_exact needs for Q queries and k. */
+hs_status hs_query_workspace_bytes(const hs_index* idx, int32_t Q, int32_t k, int64_t* bytes);
+
+/*
+ * Per-query counters written by hs_knn_exact when stats_dev is not NULL
+ * (uint64 each).  Byte figures are algorithmic: what the method reads.
+ */
+typedef struct {
+    uint64_t leaves_kept;     /* candidate leaves after LB_EAPCA (seed leaves included) */
+    uint64_t rows_filtered;   /* series whose LB_SAX was evaluated */
+    uint64_t rows_refined;    /* series whose raw values were read */
+    uint64_t chunks_read;     /* 64-point chunks of raw values read (early abandoning stops early) */
+    uint64_t path;            /* 0 = LB_SAX path, 1 = skip-sequential (no LB_SAX) */
+    uint64_t rounds;          /* refinement rounds (1 unless the candidate pool overflowed) */
+    uint64_t reserved[2];
+} hs_query_stats;
+
+/*
+ * Exact k-NN of Q queries (Sec. 2 k-NN definition; Sec. 3.3 Exact-kNN).
+ *  q_dev     float32 [Q][n] queries, row-major.
+ *  ws_dev    workspace of at least hs_query_workspace_bytes(idx, Q, k).
+ *  ids_dev   int64 [Q][k] out: original row indices of x_dev.
+ *  d2_dev    float32 [Q][k] out: squared Euclidean distances computed in
+ *            float32 (fixed per-pair summation order).
+ *  stats_dev hs_query_stats [Q] out, or NULL.
+ * Each query's results are sorted by (d2, id) ascending; they are the exact
+ * k nearest series by the float32 distance, which agrees with float64 up to
+ * a relative error below 2e-6.
+ * Errors: HS_EINVAL (k < 1, k > HS_KMAX, k > N, Q < 0, NULL pointers),
+ * HS_ENOMEM (workspace too small), HS_EHIP.
+ */
+hs_status hs_knn_exact(hs_index* idx, const float* q_dev, int32_t Q, int32_t k, void* ws_dev,
+                       int64_t ws_bytes, int64_t* ids_dev, float* d2_dev, void* stats_dev,
+                       void* stream);
+
+/* Release the host handle (does not free index_mem_dev). NULL is allowed. */
+hs_status hs_index_free(hs_index* idx);
+
+/* Message of the last failure on this thread ("" if none). */
+const char* hs_last_error(void);
+
+/* Breakpoints used by the library: beta_1..beta_{card-1} as float32
+ * (Phi^-1(j/card), equiprobable N(0,1) regions), written to out[card-1]. */
+hs_status hs_breakpoints(int32_t card_bits, float* out);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HS_H */

@@ -1,0 +1,96 @@
+"""FP64 brute-force exact k-NN (oracle; test infrastructure only).
+
+Follows the k-NN query definition of Hercules Sec. 2 (the k series of the
+collection with the smallest distance to the query) under the squared
+Euclidean distance used for whole matching (Sec. 2, UCR-Suite paragraph:
+squared distances).  Ties are broken by the smaller row index; the result is
+sorted by (distance, id) ascending.
+
+``knn`` runs the C/OpenMP implementation in ``knn_brute.c`` (built by
+``oracle/build.py``); ``knn_numpy`` is an independent numpy twin for tiny
+inputs.  Both are plain definitions: no pruning, no early abandoning.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB = None
+
+
+def _lib():
+    global _LIB
+    if _LIB is None:
+        path = os.path.join(_HERE, "libknn_brute.so")
+        if not os.path.exists(path):
+            from . import build as _b
+            _b.build()
+        lib = ctypes.CDLL(path)
+        lib.oracle_knn_brute.restype = ctypes.c_int
+        lib.oracle_knn_brute.argtypes = [ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_void_p,
+                                         ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p,
+                                         ctypes.c_int32]
+        lib.oracle_pair_dist.restype = ctypes.c_int
+        lib.oracle_pair_dist.argtypes = [ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_void_p,
+                                         ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64,
+                                         ctypes.c_void_p]
+        _LIB = lib
+    return _LIB
+
+
+def knn(x: np.ndarray, q: np.ndarray, k: int, threads: int = 0):
+    """Exact k-NN of each row of ``q`` among the rows of ``x`` (float32 inputs).
+
+    Returns (ids int64 [Q, k], d2 float64 [Q, k]) sorted by (d2, id).
+    Raises ValueError on invalid arguments.
+    """
+    x = np.ascontiguousarray(x, dtype=np.float32)
+    q = np.ascontiguousarray(q, dtype=np.float32)
+    if x.ndim != 2 or q.ndim != 2 or x.shape[1] != q.shape[1]:
+        raise ValueError("x and q must be 2-D with equal row length")
+    N, n = x.shape
+    Q = q.shape[0]
+    ids = np.empty((Q, k), dtype=np.int64)
+    d2 = np.empty((Q, k), dtype=np.float64)
+    rc = _lib().oracle_knn_brute(x.ctypes.data, N, n, q.ctypes.data, Q, k, ids.ctypes.data, d2.ctypes.data,
+                                 int(threads))
+    if rc != 0:
+        raise ValueError(f"oracle_knn_brute failed ({rc})")
+    return ids, d2
+
+
+def pair_dist(x: np.ndarray, q: np.ndarray, qidx, rows) -> np.ndarray:
+    """FP64 squared distances d(q[qidx[p]], x[rows[p]]) for sampled pairs."""
+    x = np.ascontiguousarray(x, dtype=np.float32)
+    q = np.ascontiguousarray(q, dtype=np.float32)
+    qidx = np.ascontiguousarray(qidx, dtype=np.int32)
+    rows = np.ascontiguousarray(rows, dtype=np.int64)
+    if qidx.shape != rows.shape:
+        raise ValueError("qidx and rows must have the same shape")
+    out = np.empty(rows.shape, dtype=np.float64)
+    rc = _lib().oracle_pair_dist(x.ctypes.data, x.shape[0], x.shape[1], q.ctypes.data, q.shape[0],
+                                 qidx.ctypes.data, rows.ctypes.data, rows.size, out.ctypes.data)
+    if rc != 0:
+        raise ValueError(f"oracle_pair_dist failed ({rc})")
+    return out
+
+
+def knn_numpy(x: np.ndarray, q: np.ndarray, k: int):
+    """Numpy twin of ``knn`` for tiny inputs: full FP64 distance matrix."""
+    x64 = np.asarray(x, dtype=np.float64)
+    q64 = np.asarray(q, dtype=np.float64)
+    if k < 1 or k > x64.shape[0]:
+        raise ValueError("k out of range")
+    ids = np.empty((q64.shape[0], k), dtype=np.int64)
+    d2 = np.empty((q64.shape[0], k), dtype=np.float64)
+    rowid = np.arange(x64.shape[0])
+    for i, qq in enumerate(q64):
+        diff = x64 - qq[None, :]
+        d = np.einsum("ij,ij->i", diff, diff)
+        order = np.lexsort((rowid, d))[:k]   # primary key d, then id
+        ids[i] = order
+        d2[i] = d[order]
+    return ids, d2
