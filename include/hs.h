@@ -113,6 +113,14 @@ hs_status hs_build_summaries(const float* x_dev, int64_t N, const hs_params* par
 /* Properties of a built index (host copy). */
 hs_status hs_get_info(const hs_index* idx, hs_index_info* out);
 
+/* Copy the leaf table and the leaf synopses to host memory (synchronous).
+ * leaf_start: int64 [L + 1], leaf i holds stored positions
+ *             [leaf_start[i], leaf_start[i+1]);
+ * env:        float32 [L][w][4] = (mu_min, mu_max, sd_min, sd_max) per
+ *             segment (Sec. 3.1 synopsis), rounded outward.
+ * Either pointer may be NULL.  Errors: HS_EINVAL, HS_EHIP. */
+hs_status hs_get_leaves(const hs_index* idx, int64_t* leaf_start, float* env);
+
 /* Device bytes of query workspace hs_knn_exact needs for Q queries and k. */
 hs_status hs_query_workspace_bytes(const hs_index* idx, int32_t Q, int32_t k, int64_t* bytes);
 

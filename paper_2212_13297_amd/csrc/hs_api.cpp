@@ -1,0 +1,454 @@
+// Host side of the C ABI declared in include/hs.h: argument checking, device
+// memory layout, the leaf partition (host C++), and the query driver that
+// enqueues the kernels of hs_kernels.hip.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <future>
+#include <mutex>
+#include <new>
+#include <string>
+#include <utility>
+#include <vector>
+
+#include "hs_internal.h"
+
+using namespace hs;
+
+struct hs_index {
+    hs_params p;
+    IndexView view;
+    int device = 0;
+    int cus = 0;
+    int64_t max_leaf = 0;
+    int64_t index_bytes = 0;
+    int64_t* leaf_start_dev = nullptr;  // library-owned
+    float4* env_dev = nullptr;          // library-owned
+    float* beta_dev = nullptr;          // library-owned
+};
+
+namespace {
+
+thread_local std::string g_err;
+
+hs_status fail(hs_status code, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+#define HIP_TRY(expr)                                                                  \
+    do {                                                                               \
+        hipError_t e_ = (expr);                                                        \
+        if (e_ != hipSuccess) return fail(HS_EHIP, "%s: %s", #expr, hipGetErrorString(e_)); \
+    } while (0)
+
+int64_t align_up(int64_t v, int64_t a) { return (v + a - 1) / a * a; }
+
+int32_t row_stride(int32_t n) { return (int32_t)align_up(n, kChunk); }
+int32_t word_stride(int32_t w) { return (int32_t)align_up(w, 16); }
+
+hs_status check_params(const hs_params* p) {
+    if (!p) return fail(HS_EINVAL, "params is NULL");
+    if (p->n < 1 || p->n > 16384) return fail(HS_EINVAL, "n=%d out of range [1, 16384]", p->n);
+    if (p->w < 1 || p->w > 64) return fail(HS_EINVAL, "w=%d out of range [1, 64]", p->w);
+    if (p->n % p->w) return fail(HS_EINVAL, "w=%d does not divide n=%d", p->w, p->n);
+    if (p->card_bits != 8) return fail(HS_EINVAL, "card_bits=%d: only 8 (alphabet 256) is supported", p->card_bits);
+    if (p->leaf_size < 1) return fail(HS_EINVAL, "leaf_size=%d must be >= 1", p->leaf_size);
+    if (p->l_max < 0) return fail(HS_EINVAL, "l_max=%d must be >= 0", p->l_max);
+    if (p->seed_rows < 0) return fail(HS_EINVAL, "seed_rows=%d must be >= 0", p->seed_rows);
+    if (!(p->eapca_th >= 0.0f) || !std::isfinite(p->eapca_th)) return fail(HS_EINVAL, "eapca_th must be finite, >= 0");
+    return HS_OK;
+}
+
+// Gaussian breakpoints beta_j = Phi^-1(j / 256), j = 1..255, by bisection on
+// Phi(x) = erfc(-x / sqrt 2) / 2 in double precision, rounded to float32.
+void compute_breakpoints(float* out255) {
+    for (int j = 1; j < kCard; ++j) {
+        const double target = (double)j / kCard;
+        double lo = -40.0, hi = 40.0;
+        for (int it = 0; it < 200; ++it) {
+            const double mid = 0.5 * (lo + hi);
+            const double phi = 0.5 * std::erfc(-mid / std::sqrt(2.0));
+            if (phi < target) lo = mid; else hi = mid;
+        }
+        out255[j - 1] = (float)(0.5 * (lo + hi));
+    }
+    out255[kCard / 2 - 1] = 0.0f;  // Phi^-1(1/2) = 0 exactly
+}
+
+// ------------------------------------------------------------ leaf builder
+//
+// Top-down partition by H-splits (Hercules Sec. 3.1): a node with more than
+// tau series is split on one segment's mean or std at the midpoint of that
+// statistic's [min, max] range over the node; values below the midpoint go
+// left.  Policy (the paper defers to DSTree's heuristic without stating it):
+// the candidate with the largest segment_length * range^2, lowest segment
+// first and mean before std on ties, that leaves both children non-empty.
+// The partition is stable, so leaves hold ids in ascending order and the
+// final array order is the in-order leaf order.
+
+struct Partition {
+    int w = 0;
+    int64_t tau = 0;
+    float2* st = nullptr;    // [N][w] (mean, std) in current order
+    uint32_t* id = nullptr;  // [N] original id in current order
+    std::vector<float2> tmp_st;
+    std::vector<uint32_t> tmp_id;
+    std::mutex mu;
+    std::vector<std::pair<int64_t, int64_t>> leaves;
+
+    void add_leaf(int64_t b, int64_t e) {
+        std::lock_guard<std::mutex> g(mu);
+        leaves.emplace_back(b, e);
+    }
+
+    void run(int64_t b, int64_t e, int depth) {
+        while (true) {
+            const int64_t cnt = e - b;
+            if (cnt <= tau) {
+                add_leaf(b, e);
+                return;
+            }
+            std::vector<float> mn(2 * w, INFINITY), mx(2 * w, -INFINITY);
+            for (int64_t r = b; r < e; ++r) {
+                const float2* s = st + r * w;
+                for (int i = 0; i < w; ++i) {
+                    mn[2 * i] = std::min(mn[2 * i], s[i].x);
+                    mx[2 * i] = std::max(mx[2 * i], s[i].x);
+                    mn[2 * i + 1] = std::min(mn[2 * i + 1], s[i].y);
+                    mx[2 * i + 1] = std::max(mx[2 * i + 1], s[i].y);
+                }
+            }
+            // candidates ordered by score desc, then segment, then mean before std
+            std::vector<int> order(2 * w);
+            for (int c = 0; c < 2 * w; ++c) order[c] = c;
+            std::stable_sort(order.begin(), order.end(), [&](int a, int c) {
+                const double ra = (double)mx[a] - mn[a], rc = (double)mx[c] - mn[c];
+                return ra * ra > rc * rc;  // equal segment lengths: score ~ range^2
+            });
+            int64_t nl = -1;
+            double thr = 0.0;
+            int cand = -1;
+            for (int c : order) {
+                if (!(mx[c] > mn[c])) break;
+                thr = ((double)mn[c] + (double)mx[c]) / 2.0;
+                int64_t left = 0;
+                for (int64_t r = b; r < e; ++r) {
+                    const float2 v = st[r * w + c / 2];
+                    left += (double)((c & 1) ? v.y : v.x) < thr;
+                }
+                if (left > 0 && left < cnt) {
+                    nl = left;
+                    cand = c;
+                    break;
+                }
+            }
+            if (cand < 0) {
+                add_leaf(b, e);
+                return;
+            }
+            // stable partition through the scratch arrays
+            int64_t li = b, ri = b + nl;
+            for (int64_t r = b; r < e; ++r) {
+                const float2 v = st[r * w + cand / 2];
+                const bool goes_left = (double)((cand & 1) ? v.y : v.x) < thr;
+                const int64_t dst = goes_left ? li++ : ri++;
+                std::memcpy(&tmp_st[dst * w], &st[r * w], sizeof(float2) * w);
+                tmp_id[dst] = id[r];
+            }
+            std::memcpy(&st[b * w], &tmp_st[b * w], sizeof(float2) * w * cnt);
+            std::memcpy(&id[b], &tmp_id[b], sizeof(uint32_t) * cnt);
+            const int64_t mid = b + nl;
+            if (depth < 6 && cnt > (1 << 20)) {
+                auto fut = std::async(std::launch::async, [this, b, mid, depth] { run(b, mid, depth + 1); });
+                run(mid, e, depth + 1);
+                fut.get();
+                return;
+            }
+            run(b, mid, depth + 1);
+            b = mid;  // tail iteration on the right child
+            ++depth;
+        }
+    }
+};
+
+void carve(char*& cur, void** out, int64_t bytes) {
+    *out = cur;
+    cur += align_up(bytes, 256);
+}
+
+int64_t ws_layout(const hs_index* idx, int32_t Q, int32_t k, QueryWs* ws, char* base) {
+    const IndexView& ix = idx->view;
+    const int lm = (int)std::min<int64_t>(idx->p.l_max, ix.L);
+    int P = kPoolMin;
+    while (P < (lm + 2) * k && P < 8192) P <<= 1;
+    const int64_t items = std::max<int64_t>((int64_t)Q * ix.L, (int64_t)Q * lm) + 1;
+    char* cur = base;
+    QueryWs w{};
+    carve(cur, (void**)&w.qrow, (int64_t)Q * ix.stride * 4);
+    carve(cur, (void**)&w.qstat, (int64_t)Q * ix.w * 16);
+    carve(cur, (void**)&w.lut, (int64_t)Q * ix.w * kCard * 4);
+    carve(cur, (void**)&w.lbe, (int64_t)Q * ix.L * 4);
+    carve(cur, (void**)&w.bsf, (int64_t)Q * 4);
+    carve(cur, (void**)&w.pool_cnt, (int64_t)Q * 4);
+    carve(cur, (void**)&w.flags, (int64_t)Q * 4);
+    carve(cur, (void**)&w.kept, (int64_t)Q * 4);
+    carve(cur, (void**)&w.seed_key, (int64_t)Q * 8);
+    carve(cur, (void**)&w.pool, (int64_t)Q * P * 8);
+    carve(cur, (void**)&w.stats, (int64_t)Q * 64);
+    carve(cur, (void**)&w.items, items * 8);
+    carve(cur, (void**)&w.counters, 16);
+    w.item_cap = items;
+    w.P = P;
+    if (ws) *ws = w;
+    return (int64_t)(cur - base);
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* hs_last_error(void) { return g_err.c_str(); }
+
+hs_status hs_breakpoints(int32_t card_bits, float* out) {
+    if (card_bits != 8) return fail(HS_EINVAL, "card_bits must be 8");
+    if (!out) return fail(HS_EINVAL, "out is NULL");
+    compute_breakpoints(out);
+    return HS_OK;
+}
+
+hs_status hs_index_bytes(int64_t N, const hs_params* params, int64_t* bytes) {
+    hs_status s = check_params(params);
+    if (s) return s;
+    if (!bytes) return fail(HS_EINVAL, "bytes is NULL");
+    if (N < 1 || N >= (int64_t)1 << 32) return fail(HS_EINVAL, "N=%lld out of range [1, 2^32)", (long long)N);
+    const int64_t rows = align_up(N * row_stride(params->n) * 4, 256);
+    const int64_t ids = align_up(N * 4, 256);
+    const int64_t words = align_up(N * word_stride(params->w), 256);
+    *bytes = rows + ids + words;
+    return HS_OK;
+}
+
+hs_status hs_build_summaries(const float* x_dev, int64_t N, const hs_params* params, void* index_mem_dev,
+                             int64_t index_bytes, void* stream, hs_index** out) {
+    if (!out) return fail(HS_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!x_dev || !index_mem_dev) return fail(HS_EINVAL, "x_dev or index_mem_dev is NULL");
+    int64_t need = 0;
+    hs_status s = hs_index_bytes(N, params, &need);
+    if (s) return s;
+    if (index_bytes < need) return fail(HS_ENOMEM, "index_bytes=%lld < required %lld", (long long)index_bytes, (long long)need);
+    hipStream_t st = (hipStream_t)stream;
+    const hs_params p = *params;
+
+    hs_index* idx = new (std::nothrow) hs_index();
+    if (!idx) return fail(HS_ENOMEM, "host allocation failed");
+    idx->p = p;
+    HIP_TRY(hipGetDevice(&idx->device));
+    HIP_TRY(hipDeviceGetAttribute(&idx->cus, hipDeviceAttributeMultiprocessorCount, idx->device));
+
+    IndexView& ix = idx->view;
+    ix.N = N;
+    ix.n = p.n;
+    ix.w = p.w;
+    ix.stride = row_stride(p.n);
+    ix.wstride = word_stride(p.w);
+    char* cur = (char*)index_mem_dev;
+    carve(cur, (void**)&ix.rows, N * ix.stride * 4);
+    carve(cur, (void**)&ix.ids, N * 4);
+    carve(cur, (void**)&ix.words, N * ix.wstride);
+    idx->index_bytes = need;
+
+    // 1. segment statistics for the partition (float32 copies are enough to
+    //    choose splits; envelopes are recomputed in FP64 below)
+    float2* st_dev = nullptr;
+    uint32_t* bad_dev = nullptr;
+    auto cleanup = [&]() {
+        if (st_dev) (void)hipFree(st_dev);
+        if (bad_dev) (void)hipFree(bad_dev);
+    };
+    auto bail = [&](hs_status code) {
+        cleanup();
+        if (idx->leaf_start_dev) (void)hipFree(idx->leaf_start_dev);
+        if (idx->env_dev) (void)hipFree(idx->env_dev);
+        if (idx->beta_dev) (void)hipFree(idx->beta_dev);
+        delete idx;
+        return code;
+    };
+#define BUILD_TRY(expr)                                                                 \
+    do {                                                                                \
+        hipError_t e_ = (expr);                                                         \
+        if (e_ != hipSuccess) return bail(fail(HS_EHIP, "%s: %s", #expr, hipGetErrorString(e_))); \
+    } while (0)
+
+    BUILD_TRY(hipMalloc(&st_dev, sizeof(float2) * N * p.w));
+    BUILD_TRY(hipMalloc(&bad_dev, sizeof(uint32_t)));
+    BUILD_TRY(hipMemsetAsync(bad_dev, 0, sizeof(uint32_t), st));
+    BUILD_TRY(launch_series_stats(x_dev, N, p.n, p.w, st_dev, bad_dev, st));
+    Partition part;
+    part.w = p.w;
+    part.tau = p.leaf_size;
+    std::vector<float2> st_host;
+    std::vector<uint32_t> id_host;
+    try {
+        st_host.resize((size_t)N * p.w);
+        id_host.resize((size_t)N);
+        part.tmp_st.resize((size_t)N * p.w);
+        part.tmp_id.resize((size_t)N);
+    } catch (...) {
+        return bail(fail(HS_ENOMEM, "host allocation for the leaf partition failed"));
+    }
+    uint32_t bad = 0;
+    BUILD_TRY(hipMemcpyAsync(st_host.data(), st_dev, sizeof(float2) * N * p.w, hipMemcpyDeviceToHost, st));
+    BUILD_TRY(hipMemcpyAsync(&bad, bad_dev, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
+    BUILD_TRY(hipStreamSynchronize(st));
+    if (bad) return bail(fail(HS_EINVAL, "x contains NaN or Inf"));
+
+    // 2. host partition
+    for (int64_t i = 0; i < N; ++i) id_host[i] = (uint32_t)i;
+    part.st = st_host.data();
+    part.id = id_host.data();
+    part.run(0, N, 0);
+    std::sort(part.leaves.begin(), part.leaves.end());
+    const int64_t L = (int64_t)part.leaves.size();
+    std::vector<int64_t> leaf_start(L + 1);
+    int64_t max_leaf = 0;
+    for (int64_t i = 0; i < L; ++i) {
+        leaf_start[i] = part.leaves[i].first;
+        max_leaf = std::max(max_leaf, part.leaves[i].second - part.leaves[i].first);
+    }
+    leaf_start[L] = N;
+    ix.L = L;
+    idx->max_leaf = max_leaf;
+    std::vector<float2>().swap(part.tmp_st);
+    std::vector<float2>().swap(st_host);
+
+    // 3. leaf-ordered copy, words, envelopes
+    float beta_host[kCard + 1];
+    beta_host[0] = -INFINITY;
+    compute_breakpoints(beta_host + 1);
+    beta_host[kCard] = INFINITY;
+    BUILD_TRY(hipMalloc(&idx->leaf_start_dev, sizeof(int64_t) * (L + 1)));
+    BUILD_TRY(hipMalloc(&idx->env_dev, sizeof(float4) * L * p.w));
+    BUILD_TRY(hipMalloc(&idx->beta_dev, sizeof(float) * (kCard + 1)));
+    BUILD_TRY(hipMemcpyAsync(idx->leaf_start_dev, leaf_start.data(), sizeof(int64_t) * (L + 1),
+                             hipMemcpyHostToDevice, st));
+    BUILD_TRY(hipMemcpyAsync(idx->beta_dev, beta_host, sizeof(beta_host), hipMemcpyHostToDevice, st));
+    BUILD_TRY(hipMemcpyAsync((void*)ix.ids, id_host.data(), sizeof(uint32_t) * N, hipMemcpyHostToDevice, st));
+    ix.leaf_start = idx->leaf_start_dev;
+    ix.env = idx->env_dev;
+    ix.beta = idx->beta_dev;
+    BUILD_TRY(launch_gather_rows(x_dev, ix.ids, N, p.n, ix.stride, (float*)ix.rows, nullptr, st));
+    BUILD_TRY(launch_words(ix, (uint8_t*)ix.words, st));
+    BUILD_TRY(launch_envelopes(ix, idx->env_dev, st));
+    BUILD_TRY(hipStreamSynchronize(st));
+    cleanup();
+#undef BUILD_TRY
+    *out = idx;
+    return HS_OK;
+}
+
+hs_status hs_get_info(const hs_index* idx, hs_index_info* out) {
+    if (!idx || !out) return fail(HS_EINVAL, "NULL argument");
+    out->n_series = idx->view.N;
+    out->n = idx->view.n;
+    out->w = idx->view.w;
+    out->row_stride = idx->view.stride;
+    out->word_stride = idx->view.wstride;
+    out->n_leaves = idx->view.L;
+    out->max_leaf = idx->max_leaf;
+    out->index_bytes = idx->index_bytes;
+    return HS_OK;
+}
+
+hs_status hs_get_leaves(const hs_index* idx, int64_t* leaf_start, float* env) {
+    if (!idx) return fail(HS_EINVAL, "idx is NULL");
+    if (leaf_start)
+        HIP_TRY(hipMemcpy(leaf_start, idx->leaf_start_dev, sizeof(int64_t) * (idx->view.L + 1), hipMemcpyDeviceToHost));
+    if (env)
+        HIP_TRY(hipMemcpy(env, idx->env_dev, sizeof(float4) * idx->view.L * idx->view.w, hipMemcpyDeviceToHost));
+    return HS_OK;
+}
+
+hs_status hs_query_workspace_bytes(const hs_index* idx, int32_t Q, int32_t k, int64_t* bytes) {
+    if (!idx || !bytes) return fail(HS_EINVAL, "NULL argument");
+    if (Q < 0) return fail(HS_EINVAL, "Q=%d < 0", Q);
+    if (k < 1 || k > HS_KMAX) return fail(HS_EINVAL, "k=%d out of range [1, %d]", k, HS_KMAX);
+    *bytes = ws_layout(idx, Q, k, nullptr, nullptr);
+    return HS_OK;
+}
+
+hs_status hs_knn_exact(hs_index* idx, const float* q_dev, int32_t Q, int32_t k, void* ws_dev, int64_t ws_bytes,
+                       int64_t* ids_dev, float* d2_dev, void* stats_dev, void* stream) {
+    if (!idx) return fail(HS_EINVAL, "idx is NULL");
+    if (Q < 0) return fail(HS_EINVAL, "Q=%d < 0", Q);
+    if (k < 1 || k > HS_KMAX) return fail(HS_EINVAL, "k=%d out of range [1, %d]", k, HS_KMAX);
+    if ((int64_t)k > idx->view.N) return fail(HS_EINVAL, "k=%d > N=%lld", k, (long long)idx->view.N);
+    if (Q == 0) return HS_OK;
+    if (!q_dev || !ws_dev || !ids_dev || !d2_dev) return fail(HS_EINVAL, "NULL device pointer");
+    const int64_t need = ws_layout(idx, Q, k, nullptr, nullptr);
+    if (ws_bytes < need) return fail(HS_ENOMEM, "ws_bytes=%lld < required %lld", (long long)ws_bytes, (long long)need);
+    hipStream_t st = (hipStream_t)stream;
+    QueryWs ws;
+    ws_layout(idx, Q, k, &ws, (char*)ws_dev);
+    const IndexView& ix = idx->view;
+    const int lm = (int)std::min<int64_t>(idx->p.l_max, ix.L);
+
+    ScanParams sp{};
+    sp.Q = Q;
+    sp.k = k;
+    sp.eapca_th = idx->p.eapca_th;
+    sp.n_seed = lm;
+    auto* stats_out = (hs_query_stats*)stats_dev;
+
+    HIP_TRY(launch_query_prep(ix, q_dev, Q, ws, st));
+    HIP_TRY(launch_lb_eapca(ix, Q, ws, st));
+    // step 1: approximate search over the l_max smallest-LB_EAPCA leaves
+    HIP_TRY(launch_seed_select(ix, Q, idx->p.l_max, ws, st));
+    if (lm > 0) {
+        sp.final_pass = 0;
+        HIP_TRY(launch_leaf_scan(ix, sp, ws, idx->cus, st));
+        HIP_TRY(launch_merge(ix, sp, false, ws, nullptr, nullptr, nullptr, st));
+    }
+    // steps 2-4: candidate leaves, LB_SAX filter, refinement
+    HIP_TRY(launch_emit_main(ix, Q, false, ws, st));
+    HIP_TRY(launch_leaf_scan(ix, sp, ws, idx->cus, st));
+    sp.final_pass = 1;
+    HIP_TRY(launch_merge(ix, sp, false, ws, ids_dev, d2_dev, stats_out, st));
+
+    // rounds after a candidate-pool overflow: rescan the affected queries with
+    // the tightened BSF_k until no pool overflows (each round's merge keeps the
+    // best k seen so far and drops duplicates)
+    for (int round = 0;; ++round) {
+        uint32_t c[2] = {0, 0};
+        HIP_TRY(hipMemcpyAsync(c, ws.counters + 2, sizeof c, hipMemcpyDeviceToHost, st));
+        HIP_TRY(hipStreamSynchronize(st));
+        if (c[1]) return fail(HS_EINVAL, "%u queries contain NaN or Inf", c[1]);
+        if (c[0] == 0) break;
+        if (round >= 64) return fail(HS_EHIP, "candidate pool still overflowing after %d rounds", round);
+        HIP_TRY(launch_emit_main(ix, Q, true, ws, st));
+        HIP_TRY(launch_leaf_scan(ix, sp, ws, idx->cus, st));
+        HIP_TRY(launch_merge(ix, sp, true, ws, ids_dev, d2_dev, stats_out, st));
+    }
+    return HS_OK;
+}
+
+hs_status hs_index_free(hs_index* idx) {
+    if (!idx) return HS_OK;
+    if (idx->leaf_start_dev) (void)hipFree(idx->leaf_start_dev);
+    if (idx->env_dev) (void)hipFree(idx->env_dev);
+    if (idx->beta_dev) (void)hipFree(idx->beta_dev);
+    delete idx;
+    return HS_OK;
+}
+
+}  // extern "C"

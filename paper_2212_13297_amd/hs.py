@@ -1,0 +1,236 @@
+"""Python binding of the C ABI in ``include/hs.h`` (ctypes; argument marshalling only).
+
+The functions ``hs_*`` below carry the C names and signatures; ``Index`` wraps
+them for callers that hold data in torch tensors.  torch supplies device
+memory and the stream; every step of the search runs in the HIP library.
+Nothing here falls back to a CPU path: if the library is not built, loading
+raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libhercules_hip.so")
+
+HS_OK = 0
+HS_EINVAL = -1
+HS_ENOMEM = -2
+HS_EHIP = -3
+HS_EBUSY = -4
+HS_KMAX = 128
+
+
+class hs_params(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32), ("w", ctypes.c_int32), ("card_bits", ctypes.c_int32),
+                ("leaf_size", ctypes.c_int32), ("l_max", ctypes.c_int32), ("seed_rows", ctypes.c_int32),
+                ("eapca_th", ctypes.c_float), ("reserved_f", ctypes.c_float)]
+
+
+class hs_index_info(ctypes.Structure):
+    _fields_ = [("n_series", ctypes.c_int64), ("n", ctypes.c_int32), ("w", ctypes.c_int32),
+                ("row_stride", ctypes.c_int32), ("word_stride", ctypes.c_int32), ("n_leaves", ctypes.c_int64),
+                ("max_leaf", ctypes.c_int64), ("index_bytes", ctypes.c_int64)]
+
+
+class hs_query_stats(ctypes.Structure):
+    _fields_ = [("leaves_kept", ctypes.c_uint64), ("rows_filtered", ctypes.c_uint64),
+                ("rows_refined", ctypes.c_uint64), ("chunks_read", ctypes.c_uint64), ("path", ctypes.c_uint64),
+                ("rounds", ctypes.c_uint64), ("reserved", ctypes.c_uint64 * 2)]
+
+
+STATS_FIELDS = ["leaves_kept", "rows_filtered", "rows_refined", "chunks_read", "path", "rounds"]
+
+_P = ctypes.c_void_p
+_SIGS = {
+    "hs_index_bytes": (ctypes.c_int32, [ctypes.c_int64, ctypes.POINTER(hs_params), ctypes.POINTER(ctypes.c_int64)]),
+    "hs_build_summaries": (ctypes.c_int32, [_P, ctypes.c_int64, ctypes.POINTER(hs_params), _P, ctypes.c_int64, _P,
+                                            ctypes.POINTER(_P)]),
+    "hs_get_info": (ctypes.c_int32, [_P, ctypes.POINTER(hs_index_info)]),
+    "hs_get_leaves": (ctypes.c_int32, [_P, _P, _P]),
+    "hs_query_workspace_bytes": (ctypes.c_int32, [_P, ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(ctypes.c_int64)]),
+    "hs_knn_exact": (ctypes.c_int32, [_P, _P, ctypes.c_int32, ctypes.c_int32, _P, ctypes.c_int64, _P, _P, _P, _P]),
+    "hs_index_free": (ctypes.c_int32, [_P]),
+    "hs_last_error": (ctypes.c_char_p, []),
+    "hs_breakpoints": (ctypes.c_int32, [ctypes.c_int32, _P]),
+}
+
+_LIB = None
+
+
+def load():
+    """Load the built HIP library (raises if it has not been built)."""
+    global _LIB
+    if _LIB is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"HIP library not built: {LIB_PATH} (run __graft_entry__.build())")
+        lib = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGS.items():
+            fn = getattr(lib, name)
+            fn.restype = res
+            fn.argtypes = args
+        _LIB = lib
+    return _LIB
+
+
+class HSError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"hs error {code}: {msg}")
+        self.code = code
+
+
+def _check(code):
+    if code != HS_OK:
+        raise HSError(code, load().hs_last_error().decode())
+
+
+# ---------------------------------------------------------------- C names
+
+def hs_index_bytes(N: int, params: hs_params) -> int:
+    out = ctypes.c_int64()
+    _check(load().hs_index_bytes(N, ctypes.byref(params), ctypes.byref(out)))
+    return out.value
+
+
+def hs_build_summaries(x_ptr: int, N: int, params: hs_params, mem_ptr: int, mem_bytes: int, stream: int):
+    h = _P()
+    _check(load().hs_build_summaries(x_ptr, N, ctypes.byref(params), mem_ptr, mem_bytes, stream, ctypes.byref(h)))
+    return h
+
+
+def hs_get_info(h) -> hs_index_info:
+    info = hs_index_info()
+    _check(load().hs_get_info(h, ctypes.byref(info)))
+    return info
+
+
+def hs_get_leaves(h, info: hs_index_info):
+    import numpy as np
+    ls = np.empty(info.n_leaves + 1, dtype=np.int64)
+    env = np.empty((info.n_leaves, info.w, 4), dtype=np.float32)
+    _check(load().hs_get_leaves(h, ls.ctypes.data, env.ctypes.data))
+    return ls, env
+
+
+def hs_query_workspace_bytes(h, Q: int, k: int) -> int:
+    out = ctypes.c_int64()
+    _check(load().hs_query_workspace_bytes(h, Q, k, ctypes.byref(out)))
+    return out.value
+
+
+def hs_knn_exact(h, q_ptr: int, Q: int, k: int, ws_ptr: int, ws_bytes: int, ids_ptr: int, d2_ptr: int,
+                 stats_ptr: int, stream: int) -> None:
+    _check(load().hs_knn_exact(h, q_ptr, Q, k, ws_ptr, ws_bytes, ids_ptr, d2_ptr, stats_ptr, stream))
+
+
+def hs_index_free(h) -> None:
+    _check(load().hs_index_free(h))
+
+
+def hs_last_error() -> str:
+    return load().hs_last_error().decode()
+
+
+def hs_breakpoints(card_bits: int = 8):
+    import numpy as np
+    out = np.empty(255, dtype=np.float32)
+    _check(load().hs_breakpoints(card_bits, out.ctypes.data))
+    return out
+
+
+# ---------------------------------------------------------------- torch glue
+
+@dataclass
+class Params:
+    w: int = 16
+    leaf_size: int = 10_000
+    l_max: int = 1
+    seed_rows: int = 0
+    eapca_th: float = 0.0
+    card_bits: int = 8
+
+    def c(self, n: int) -> hs_params:
+        return hs_params(n, self.w, self.card_bits, self.leaf_size, self.l_max, self.seed_rows,
+                         float(self.eapca_th), 0.0)
+
+
+def _stream_ptr(stream):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return int(s.cuda_stream)
+
+
+class Index:
+    """An index over float32 series held in a CUDA (HIP) torch tensor."""
+
+    def __init__(self, x, params: Params | None = None, stream=None):
+        import torch
+        if not (x.is_cuda and x.dtype == torch.float32 and x.dim() == 2 and x.is_contiguous()):
+            raise ValueError("x must be a contiguous float32 [N, n] GPU tensor")
+        self.params = params or Params()
+        N, n = x.shape
+        self.n = n
+        cp = self.params.c(n)
+        nbytes = hs_index_bytes(N, cp)
+        self.device = x.device
+        self.mem = torch.empty(nbytes, dtype=torch.uint8, device=x.device)
+        self.h = hs_build_summaries(x.data_ptr(), N, cp, self.mem.data_ptr(), nbytes, _stream_ptr(stream))
+        self.info = hs_get_info(self.h)
+        self._ws = None
+
+    def layout(self):
+        """Views of the stored arrays inside the index memory (rows, ids, words)
+        plus the host copies of the leaf table and envelopes."""
+        import torch
+        N, info = self.info.n_series, self.info
+
+        def up(v):
+            return (v + 255) // 256 * 256
+
+        rb = N * info.row_stride * 4
+        ib = N * 4
+        rows = self.mem[:rb].view(torch.float32).view(N, info.row_stride)
+        ids = self.mem[up(rb):up(rb) + ib].view(torch.int32)
+        words = self.mem[up(rb) + up(ib):up(rb) + up(ib) + N * info.word_stride].view(N, info.word_stride)
+        ls, env = hs_get_leaves(self.h, info)
+        return rows, ids, words, ls, env
+
+    def workspace(self, Q: int, k: int):
+        import torch
+        need = hs_query_workspace_bytes(self.h, Q, k)
+        if self._ws is None or self._ws.numel() < need:
+            self._ws = torch.empty(need, dtype=torch.uint8, device=self.device)
+        return self._ws, need
+
+    def knn(self, q, k: int, stats: bool = False, stream=None, out=None):
+        """Exact k-NN: returns (ids int64 [Q, k], d2 float32 [Q, k]) [, stats dict of tensors]."""
+        import torch
+        if not (q.is_cuda and q.dtype == torch.float32 and q.dim() == 2 and q.shape[1] == self.n
+                and q.is_contiguous()):
+            raise ValueError("q must be a contiguous float32 [Q, n] GPU tensor")
+        Q = q.shape[0]
+        ws, nbytes = self.workspace(Q, k)
+        if out is None:
+            ids = torch.empty((Q, k), dtype=torch.int64, device=self.device)
+            d2 = torch.empty((Q, k), dtype=torch.float32, device=self.device)
+        else:
+            ids, d2 = out
+        st = torch.zeros((Q, 8), dtype=torch.int64, device=self.device) if stats else None
+        hs_knn_exact(self.h, q.data_ptr(), Q, k, ws.data_ptr(), nbytes, ids.data_ptr(), d2.data_ptr(),
+                     st.data_ptr() if st is not None else None, _stream_ptr(stream))
+        if stats:
+            return ids, d2, {f: st[:, i] for i, f in enumerate(STATS_FIELDS)}
+        return ids, d2
+
+    def close(self):
+        if getattr(self, "h", None):
+            hs_index_free(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,227 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 oracle.
+
+Covers the index build (stored copy, id map, iSAX words, leaf synopses), exact
+k-NN at several shapes (ragged n, several w, k, leaf sizes and seed sizes,
+noise levels 1/5/10 % and out-of-dataset queries), the access paths, edge
+cases, determinism and argument errors.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import brute
+from oracle import summaries as S
+from paper_2212_13297_amd import datagen as G
+
+from parity import check_knn
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda:0"
+
+
+def hs_mod():
+    from paper_2212_13297_amd import hs
+    return hs
+
+
+def make_index(x, **kw):
+    hs = hs_mod()
+    print(f"[build] N={x.shape[0]} n={x.shape[1]} {kw}", flush=True)
+    return hs.Index(torch.from_numpy(np.ascontiguousarray(x)).to(DEV), hs.Params(**kw))
+
+
+def run_knn(idx, q, k, **kw):
+    print(f"[knn] Q={q.shape[0]} k={k}", flush=True)
+    out = idx.knn(torch.from_numpy(np.ascontiguousarray(q)).to(DEV), k, **kw)
+    torch.cuda.synchronize()
+    return tuple(o.cpu().numpy() if hasattr(o, "cpu") else o for o in out)
+
+
+def workload(N, n, coll, per_level=3, ood=2):
+    x = G.random_walks(N, n, coll=coll)
+    q, _, _ = G.workload(x, [1, 5, 10], per_level, coll=coll)
+    if ood:
+        q = np.concatenate([q, G.ood_queries(ood, n, coll=coll)])
+    return x, q
+
+
+# ------------------------------------------------------------------ build
+
+def test_build_summaries_against_oracle():
+    N, n, w, tau = 30011, 256, 16, 700
+    x = G.random_walks(N, n, coll=11)
+    idx = make_index(x, w=w, leaf_size=tau)
+    rows, ids, words, ls, env = idx.layout()
+    rows, ids, words = rows.cpu().numpy(), ids.cpu().numpy().astype(np.int64), words.cpu().numpy()
+    info = idx.info
+    assert info.n_leaves == len(ls) - 1 and ls[0] == 0 and ls[-1] == N
+    assert np.all(np.diff(ls) > 0)
+    # the id map is a permutation and the stored rows are the inputs, zero padded
+    assert np.array_equal(np.sort(ids), np.arange(N))
+    assert np.array_equal(rows[:, :n], x[ids])
+    assert np.all(rows[:, n:] == 0)
+    sizes = np.diff(ls)
+    assert sizes.max() <= tau
+    for a, b in zip(ls[:-1], ls[1:]):
+        assert np.all(np.diff(ids[a:b]) > 0)     # stable partition: ids ascending in a leaf
+    # iSAX words: equal to the oracle's except where the PAA lies within 1e-6 of a breakpoint
+    beta = S.breakpoints(256)
+    paa = S.paa(x[ids], w)
+    ow = S.sax_word(paa, beta).astype(np.int64)
+    gw = words[:, :w].astype(np.int64)
+    diff = np.nonzero(ow != gw)
+    for r, c in zip(*diff):
+        near = np.min(np.abs(beta[1:-1] - paa[r, c]))
+        assert near < 1e-6 and abs(ow[r, c] - gw[r, c]) == 1, (r, c, paa[r, c], ow[r, c], gw[r, c])
+    # leaf synopses contain every member's FP64 segment statistics
+    ends = S.equal_segmentation(n, w)
+    mu, sd = S.segment_stats(x[ids], ends)
+    for i, (a, b) in enumerate(zip(ls[:-1], ls[1:])):
+        e = env[i].astype(np.float64)
+        assert np.all(mu[a:b] >= e[:, 0]) and np.all(mu[a:b] <= e[:, 1])
+        assert np.all(sd[a:b] >= e[:, 2]) and np.all(sd[a:b] <= e[:, 3])
+        syn = S.synopsis(mu[a:b], sd[a:b])
+        assert np.all(np.abs(syn - e) <= 1e-6 * (1 + np.abs(syn)))   # and are tight
+    idx.close()
+
+
+# ----------------------------------------------------------------- parity
+
+CASES = [
+    # N, n, w, tau, l_max, k
+    (100_000, 256, 16, 1000, 1, 1),      # the small plain configuration
+    (12_345, 200, 8, 333, 1, 7),         # n not a multiple of 64: padded rows
+    (20_000, 128, 16, 1000, 1, 100),     # k = 100
+    (20_000, 1024, 32, 500, 2, 10),      # long series, w = 32
+    (9_000, 256, 16, 100, 0, 10),        # no seed leaves
+    (9_000, 256, 16, 50, 5, 3),          # several seed leaves, small leaves
+    (5_000, 64, 4, 5_000, 1, 20),        # a single leaf
+]
+
+
+@pytest.mark.parametrize("N,n,w,tau,l_max,k", CASES)
+def test_knn_parity(N, n, w, tau, l_max, k):
+    x, q = workload(N, n, coll=N % 97 + n)
+    idx = make_index(x, w=w, leaf_size=tau, l_max=l_max)
+    ids, d2, st = run_knn(idx, q, k, stats=True)
+    check_knn(x, q, k, ids, d2)
+    st = {f: v.cpu().numpy() for f, v in st.items()}
+    assert np.all(st["rounds"] >= 1)
+    assert np.all(st["rows_refined"] >= k)
+    idx.close()
+
+
+def test_knn_k128_and_skip_sequential_path():
+    x, q = workload(15_000, 256, coll=5)
+    idx = make_index(x, w=16, leaf_size=400, eapca_th=1.1)   # every query skips LB_SAX
+    ids, d2, st = run_knn(idx, q, 128, stats=True)
+    check_knn(x, q, 128, ids, d2)
+    assert np.all(st["path"].cpu().numpy() == 1)
+    idx.close()
+
+
+def test_results_do_not_depend_on_access_path():
+    x, q = workload(30_000, 256, coll=6, per_level=4)
+    ref = None
+    for tau, l_max, eth in ((10_000, 1, 0.0), (300, 0, 0.0), (1000, 4, 0.0), (2000, 1, 1.1), (1, 1, 0.0)):
+        if tau == 1:
+            x2, q2 = x[:3000], q
+        else:
+            x2, q2 = x, q
+        idx = make_index(x2, w=16, leaf_size=tau, l_max=l_max, eapca_th=eth)
+        ids, d2 = run_knn(idx, q2, 10)
+        if tau == 1:
+            check_knn(x2, q2, 10, ids, d2)
+        elif ref is None:
+            ref = (ids, d2)
+            check_knn(x, q, 10, ids, d2)
+        else:
+            assert np.array_equal(ids, ref[0])
+            assert np.array_equal(d2, ref[1])    # per-pair summation order is fixed
+        idx.close()
+
+
+def test_batch_composition_does_not_change_results():
+    x, q = workload(20_000, 256, coll=8, per_level=5)
+    idx = make_index(x, w=16, leaf_size=500)
+    ids, d2 = run_knn(idx, q, 10)
+    for i in (0, 7, len(q) - 1):
+        a, b = run_knn(idx, q[i:i + 1], 10)
+        assert np.array_equal(a[0], ids[i]) and np.array_equal(b[0], d2[i])
+    idx.close()
+
+
+# ------------------------------------------------------------- edge cases
+
+def test_planted_ties_and_exact_matches():
+    x = G.random_walks(8000, 128, coll=9).copy()
+    x[5000] = x[17]
+    x[6001] = x[17]
+    x[7999] = x[17]
+    q = np.stack([x[17], x[4000], (x[100] + x[101]) / 2]).astype(np.float32)
+    idx = make_index(x, w=16, leaf_size=250)
+    ids, d2 = run_knn(idx, q, 4)
+    assert list(ids[0][:4]) == [17, 5000, 6001, 7999] and np.all(d2[0] == 0)
+    assert ids[1][0] == 4000 and d2[1][0] == 0
+    check_knn(x, q, 4, ids, d2)
+    idx.close()
+
+
+def test_tiny_collections():
+    x = G.random_walks(1, 64, coll=10)
+    idx = make_index(x, w=16, leaf_size=10)
+    ids, d2 = run_knn(idx, x + np.float32(0.5), 1)
+    assert ids[0, 0] == 0 and abs(d2[0, 0] - 64 * 0.25) < 1e-5
+    idx.close()
+    x = G.random_walks(50, 64, coll=10)
+    q = G.ood_queries(3, 64, coll=10)
+    idx = make_index(x, w=8, leaf_size=7)
+    ids, d2 = run_knn(idx, q, 50)                  # k = N: a full sort
+    check_knn(x, q, 50, ids, d2)
+    idx.close()
+
+
+def test_errors():
+    hs = hs_mod()
+    x = G.random_walks(500, 64, coll=12)
+    xt = torch.from_numpy(x).to(DEV)
+    with pytest.raises(hs.HSError) as e:
+        hs.Index(xt, hs.Params(w=7))
+    assert e.value.code == hs.HS_EINVAL
+    with pytest.raises(hs.HSError):
+        hs.Index(xt, hs.Params(card_bits=4))
+    bad = x.copy()
+    bad[3, 5] = np.nan
+    with pytest.raises(hs.HSError) as e:
+        hs.Index(torch.from_numpy(bad).to(DEV), hs.Params(w=8, leaf_size=50))
+    assert e.value.code == hs.HS_EINVAL
+    idx = hs.Index(xt, hs.Params(w=8, leaf_size=50))
+    qt = xt[:2].clone()
+    for k in (0, hs.HS_KMAX + 1, 501):
+        with pytest.raises(hs.HSError) as e:
+            idx.knn(qt, k)
+        assert e.value.code == hs.HS_EINVAL
+    qn = qt.clone()
+    qn[1, 0] = math.inf
+    with pytest.raises(hs.HSError) as e:
+        idx.knn(qn, 3)
+    assert e.value.code == hs.HS_EINVAL
+    ws, need = idx.workspace(2, 3)
+    ids = torch.empty((2, 3), dtype=torch.int64, device=DEV)
+    d2 = torch.empty((2, 3), dtype=torch.float32, device=DEV)
+    with pytest.raises(hs.HSError) as e:
+        hs.hs_knn_exact(idx.h, qt.data_ptr(), 2, 3, ws.data_ptr(), need - 1, ids.data_ptr(), d2.data_ptr(),
+                        None, 0)
+    assert e.value.code == hs.HS_ENOMEM
+    with pytest.raises(hs.HSError) as e:
+        hs.hs_knn_exact(idx.h, None, 2, 3, ws.data_ptr(), need, ids.data_ptr(), d2.data_ptr(), None, 0)
+    assert e.value.code == hs.HS_EINVAL
+    # Q = 0 is a no-op
+    hs.hs_knn_exact(idx.h, qt.data_ptr(), 0, 3, ws.data_ptr(), need, ids.data_ptr(), d2.data_ptr(), None, 0)
+    # the index still answers correctly after the failed calls
+    a, b = run_knn(idx, x[:2], 3)
+    check_knn(x, x[:2], 3, a, b)
+    idx.close()
