@@ -144,6 +144,17 @@ def test_results_do_not_depend_on_access_path():
         idx.close()
 
 
+def test_pool_overflow_takes_more_rounds():
+    # one series per leaf and a seed that cannot fill k: every leaf passes the
+    # leaf filter and appends its series, overflowing the 4096-entry pool
+    x, q = workload(6000, 64, coll=13, per_level=1, ood=1)
+    idx = make_index(x, w=8, leaf_size=1, l_max=1)
+    ids, d2, st = run_knn(idx, q, 10, stats=True)
+    check_knn(x, q, 10, ids, d2)
+    assert np.all(st["rounds"].cpu().numpy() >= 2)
+    idx.close()
+
+
 def test_batch_composition_does_not_change_results():
     x, q = workload(20_000, 256, coll=8, per_level=5)
     idx = make_index(x, w=16, leaf_size=500)
