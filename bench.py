@@ -1,0 +1,210 @@
+#!/usr/bin/env python3
+"""Benchmark: exact k-NN queries/s on one MI355X (plain float32 path).
+
+Workload (the plain-FP32 configuration): 10,000,000 z-normalised random-walk
+series of length 256 (float32, ~10 GB resident in HBM), 300 queries -- 100
+each built from dataset series with 1 %, 5 % and 10 % Gaussian noise (variance
+labels), re-normalised -- iSAX w = 16 at alphabet 256, leaves of 10,000
+series, k = 10 (k = 1 reported beside it).  One step answers the whole
+300-query batch through the C ABI; inputs are resident in HBM before timing.
+
+The JSON line also carries:
+  roofline      the leaf-scan kernel (LB_SAX filter + refinement, the dominant
+                kernel): algorithmic bytes it must read per launch (iSAX words
+                of the series it filters, 256-byte chunks of the series it
+                refines) over its average launch duration, timed with HIP
+                events on the stream it runs on, against the 8 TB/s HBM peak;
+  cpu_baseline  the FP64 oracle (C/OpenMP brute force) timed on the host cores
+                on a bounded sample of the same queries;
+  latency_ms    p50/p99 of single-query calls.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "exact k-NN queries/s at 1 GPU (plain FP32 vs BF16-bound+FP32 refine) + p99 latency"
+HBM_PEAK_GBS = 8000.0
+
+
+def log(msg):
+    print(f"[bench {time.strftime('%H:%M:%S')}] {msg}", file=sys.stderr, flush=True)
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--N", type=int, default=10_000_000)
+    ap.add_argument("--n", type=int, default=256)
+    ap.add_argument("--per-level", type=int, default=100)
+    ap.add_argument("--k", type=int, default=10)
+    ap.add_argument("--w", type=int, default=16)
+    ap.add_argument("--leaf", type=int, default=10_000)
+    ap.add_argument("--l-max", type=int, default=1)
+    ap.add_argument("--cpu-sample", type=int, default=24, help="queries timed on the CPU oracle")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--latency-queries", type=int, default=300)
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(the leaf-sharded design is described in DESIGN.md); run with --gpus 1.", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2212_13297_amd import datagen as G
+    from paper_2212_13297_amd import hs
+
+    dev = torch.device("cuda:0")
+    levels = [1, 5, 10]
+    log(f"generating {args.N} x {args.n} random walks")
+    t0 = time.time()
+    x = G.random_walks(args.N, args.n)
+    q, src, pct = G.workload(x, levels, args.per_level)
+    Q = q.shape[0]
+    log(f"generated in {time.time() - t0:.1f}s; uploading")
+    xt = torch.from_numpy(x).to(dev)
+    qt = torch.from_numpy(q).to(dev)
+    torch.cuda.synchronize()
+    params = hs.Params(w=args.w, leaf_size=args.leaf, l_max=args.l_max)
+    t0 = time.time()
+    idx = hs.Index(xt, params)
+    torch.cuda.synchronize()
+    build_s = time.time() - t0
+    info = idx.info
+    log(f"built index in {build_s:.1f}s: {info.n_leaves} leaves, max leaf {info.max_leaf}")
+    del xt
+    torch.cuda.empty_cache()
+
+    def run(k, steps, stats=False):
+        out = None
+        for _ in range(steps):
+            out = idx.knn(qt, k, stats=stats)
+        return out
+
+    log(f"warmup {args.warmup} steps")
+    run(args.k, args.warmup)
+    torch.cuda.synchronize()
+    hs.hs_profile_read(reset=True)
+    hs.hs_profile_enable(True)
+    log(f"timing {args.steps} steps, Q={Q}, k={args.k}")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ids, d2, st = run(args.k, args.steps, stats=True)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    hs.hs_profile_enable(False)
+    scan_ms, scan_launches = hs.hs_profile_read(reset=True)
+    ms_per_step = (t1 - t0) * 1000.0 / args.steps
+    qps = Q / (ms_per_step / 1000.0)
+    log(f"{ms_per_step:.3f} ms/step, {qps:.0f} queries/s")
+
+    stats = {f: v.cpu().numpy().astype(np.int64) for f, v in st.items()}
+    word_bytes = int(stats["rows_filtered"].sum()) * args.w
+    raw_bytes = int(stats["chunks_read"].sum()) * 64 * 4
+    scan_bytes_step = word_bytes + raw_bytes
+    launches_per_step = scan_launches / args.steps
+    avg_launch_ms = scan_ms / max(scan_launches, 1)
+    bytes_per_launch = scan_bytes_step / max(launches_per_step, 1e-9)
+    achieved = bytes_per_launch / (avg_launch_ms / 1000.0) / 1e9
+    env_bytes = Q * info.n_leaves * args.w * 16
+    path_bytes_step = scan_bytes_step + env_bytes + Q * args.k * 12
+
+    # k = 1 on the same batch
+    run(1, max(1, args.warmup // 2))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    run(1, args.steps)
+    torch.cuda.synchronize()
+    qps_k1 = Q * args.steps / (time.perf_counter() - t0)
+    log(f"k=1: {qps_k1:.0f} queries/s")
+
+    # single-query latency
+    lat = []
+    nl = min(args.latency_queries, Q)
+    for i in range(nl):
+        qi = qt[i:i + 1]
+        torch.cuda.synchronize()
+        a = time.perf_counter()
+        idx.knn(qi, args.k)
+        torch.cuda.synchronize()
+        lat.append((time.perf_counter() - a) * 1000.0)
+    lat = np.asarray(lat)
+    log(f"single-query latency p50 {np.percentile(lat, 50):.3f} ms p99 {np.percentile(lat, 99):.3f} ms")
+
+    cpu = None
+    parity = None
+    if not args.no_cpu_baseline and args.cpu_sample > 0:
+        from oracle import brute
+        sel = np.linspace(0, Q - 1, min(args.cpu_sample, Q)).round().astype(np.int64)
+        log(f"CPU oracle on {len(sel)} queries ({brute.threads()} threads)")
+        t0 = time.perf_counter()
+        oids, od = brute.knn(x, q[sel], args.k)
+        cpu_s = time.perf_counter() - t0
+        cpu = {"value": round(len(sel) / cpu_s, 4), "unit": "queries/s", "cores": brute.threads(),
+               "kind": "oracle",
+               "sample": f"{len(sel)} of the {Q} queries (evenly spaced over the 1/5/10% levels), k={args.k}, "
+                         f"FP64 brute force over all {args.N} series; {cpu_s:.1f} s"}
+        g_ids = ids.cpu().numpy()[sel]
+        g_d = d2.cpu().numpy()[sel].astype(np.float64)
+        same = int((g_ids == oids).all(axis=1).sum())
+        rel = float(np.max(np.abs(g_d - od) / np.maximum(od, 1e-30)))
+        parity = {"queries_checked": int(len(sel)), "identical_id_lists": same, "max_rel_d_err": rel}
+        log(f"CPU oracle {cpu['value']} q/s; parity {parity}")
+
+    out = {
+        "metric": METRIC,
+        "value": round(qps, 2),
+        "unit": "queries/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": f"random-walk {args.N}x{args.n} f32, {Q} queries ({args.per_level} each at "
+                        f"{'/'.join(map(str, levels))}% noise), k={args.k}, w={args.w}, card 256, "
+                        f"leaf {args.leaf}, l_max {args.l_max}",
+            "N": args.N, "n": args.n, "queries": Q, "k": args.k, "w": args.w, "leaf_size": args.leaf,
+            "l_max": args.l_max, "n_leaves": int(info.n_leaves), "form": "plain fp32",
+        },
+        "queries_per_s_k1": round(qps_k1, 2),
+        "latency_ms": {"p50": round(float(np.percentile(lat, 50)), 4),
+                       "p99": round(float(np.percentile(lat, 99)), 4), "mode": "one query per call",
+                       "queries": int(nl)},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "kernel": "k_leaf_scan", "launches_per_step": launches_per_step,
+                     "avg_launch_ms": round(avg_launch_ms, 4), "bytes_per_launch": int(bytes_per_launch)},
+        "algorithmic_bytes_per_step": {"words": word_bytes, "raw": raw_bytes, "envelopes": env_bytes,
+                                       "total": path_bytes_step},
+        "path_frac_of_hbm_peak": round(path_bytes_step / (ms_per_step / 1000.0) / 1e9 / HBM_PEAK_GBS, 4),
+        "pruning": {"leaves_kept_mean": float(stats["leaves_kept"].mean()),
+                    "rows_filtered_mean": float(stats["rows_filtered"].mean()),
+                    "rows_refined_mean": float(stats["rows_refined"].mean()),
+                    "rounds_max": int(stats["rounds"].max())},
+        "build_s": round(build_s, 2),
+        "cpu_baseline": cpu,
+        "parity_sample": parity,
+    }
+    print(json.dumps(out), flush=True)
+    idx.close()
+
+
+if __name__ == "__main__":
+    main()

@@ -156,6 +156,15 @@ hs_status hs_knn_exact(hs_index* idx, const float* q_dev, int32_t Q, int32_t k, 
                        int64_t ws_bytes, int64_t* ids_dev, float* d2_dev, void* stats_dev,
                        void* stream);
 
+/* Diagnostics.  While enabled, hs_knn_exact brackets every leaf-scan kernel
+ * launch (the LB_SAX filter + refinement, its dominant kernel) with HIP
+ * events on its stream and, after its own final synchronisation, adds their
+ * elapsed times to a process-wide accumulator.  Not meant for concurrent
+ * calls from several threads. */
+hs_status hs_profile_enable(int32_t on);
+/* Accumulated leaf-scan milliseconds and launch count; cleared if reset. */
+hs_status hs_profile_read(double* scan_ms, int64_t* scan_launches, int32_t reset);
+
 /* Release the host handle (does not free index_mem_dev). NULL is allowed. */
 hs_status hs_index_free(hs_index* idx);
 

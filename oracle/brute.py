@@ -37,8 +37,15 @@ def _lib():
         lib.oracle_pair_dist.argtypes = [ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_void_p,
                                          ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64,
                                          ctypes.c_void_p]
+        lib.oracle_threads.restype = ctypes.c_int
+        lib.oracle_threads.argtypes = []
         _LIB = lib
     return _LIB
+
+
+def threads() -> int:
+    """Threads the C oracle uses by default (OpenMP max threads)."""
+    return int(_lib().oracle_threads())
 
 
 def knn(x: np.ndarray, q: np.ndarray, k: int, threads: int = 0):

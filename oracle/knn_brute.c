@@ -133,3 +133,12 @@ int oracle_pair_dist(const float* x, int64_t N, int32_t n, const float* q, int32
     }
     return 0;
 }
+
+/* Threads the OpenMP runtime would use for the calls above (threads <= 0). */
+int oracle_threads(void) {
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}

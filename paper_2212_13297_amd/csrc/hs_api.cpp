@@ -35,6 +35,51 @@ namespace {
 
 thread_local std::string g_err;
 
+std::mutex g_prof_mu;
+bool g_prof_on = false;
+double g_prof_ms = 0.0;
+int64_t g_prof_launches = 0;
+
+// Events around leaf-scan launches while profiling is on.
+struct ScanTimer {
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> ev;
+    bool on = false;
+    ScanTimer() {
+        std::lock_guard<std::mutex> g(g_prof_mu);
+        on = g_prof_on;
+    }
+    hipError_t begin(hipStream_t st) {
+        if (!on) return hipSuccess;
+        hipEvent_t a, b;
+        hipError_t e = hipEventCreate(&a);
+        if (e != hipSuccess) return e;
+        e = hipEventCreate(&b);
+        if (e != hipSuccess) return e;
+        ev.emplace_back(a, b);
+        return hipEventRecord(a, st);
+    }
+    hipError_t end(hipStream_t st) { return on ? hipEventRecord(ev.back().second, st) : hipSuccess; }
+    // after the stream has been synchronised
+    void collect() {
+        double ms = 0.0;
+        for (auto& p : ev) {
+            float t = 0.0f;
+            if (hipEventElapsedTime(&t, p.first, p.second) == hipSuccess) ms += t;
+        }
+        if (on) {
+            std::lock_guard<std::mutex> g(g_prof_mu);
+            g_prof_ms += ms;
+            g_prof_launches += (int64_t)ev.size();
+        }
+    }
+    ~ScanTimer() {
+        for (auto& p : ev) {
+            (void)hipEventDestroy(p.first);
+            (void)hipEventDestroy(p.second);
+        }
+    }
+};
+
 hs_status fail(hs_status code, const char* fmt, ...) {
     char buf[512];
     va_list ap;
@@ -410,18 +455,27 @@ hs_status hs_knn_exact(hs_index* idx, const float* q_dev, int32_t Q, int32_t k, 
     sp.n_seed = lm;
     auto* stats_out = (hs_query_stats*)stats_dev;
 
+    ScanTimer timer;
+    auto scan = [&]() -> hipError_t {
+        hipError_t e = timer.begin(st);
+        if (e != hipSuccess) return e;
+        e = launch_leaf_scan(ix, sp, ws, idx->cus, st);
+        if (e != hipSuccess) return e;
+        return timer.end(st);
+    };
+
     HIP_TRY(launch_query_prep(ix, q_dev, Q, ws, st));
     HIP_TRY(launch_lb_eapca(ix, Q, ws, st));
     // step 1: approximate search over the l_max smallest-LB_EAPCA leaves
     HIP_TRY(launch_seed_select(ix, Q, idx->p.l_max, ws, st));
     if (lm > 0) {
         sp.final_pass = 0;
-        HIP_TRY(launch_leaf_scan(ix, sp, ws, idx->cus, st));
+        HIP_TRY(scan());
         HIP_TRY(launch_merge(ix, sp, false, ws, nullptr, nullptr, nullptr, st));
     }
     // steps 2-4: candidate leaves, LB_SAX filter, refinement
     HIP_TRY(launch_emit_main(ix, Q, false, ws, st));
-    HIP_TRY(launch_leaf_scan(ix, sp, ws, idx->cus, st));
+    HIP_TRY(scan());
     sp.final_pass = 1;
     HIP_TRY(launch_merge(ix, sp, false, ws, ids_dev, d2_dev, stats_out, st));
 
@@ -433,11 +487,31 @@ hs_status hs_knn_exact(hs_index* idx, const float* q_dev, int32_t Q, int32_t k, 
         HIP_TRY(hipMemcpyAsync(c, ws.counters + 2, sizeof c, hipMemcpyDeviceToHost, st));
         HIP_TRY(hipStreamSynchronize(st));
         if (c[1]) return fail(HS_EINVAL, "%u queries contain NaN or Inf", c[1]);
-        if (c[0] == 0) break;
+        if (c[0] == 0) {
+            timer.collect();
+            break;
+        }
         if (round >= 64) return fail(HS_EHIP, "candidate pool still overflowing after %d rounds", round);
         HIP_TRY(launch_emit_main(ix, Q, true, ws, st));
-        HIP_TRY(launch_leaf_scan(ix, sp, ws, idx->cus, st));
+        HIP_TRY(scan());
         HIP_TRY(launch_merge(ix, sp, true, ws, ids_dev, d2_dev, stats_out, st));
+    }
+    return HS_OK;
+}
+
+hs_status hs_profile_enable(int32_t on) {
+    std::lock_guard<std::mutex> g(g_prof_mu);
+    g_prof_on = on != 0;
+    return HS_OK;
+}
+
+hs_status hs_profile_read(double* scan_ms, int64_t* scan_launches, int32_t reset) {
+    std::lock_guard<std::mutex> g(g_prof_mu);
+    if (scan_ms) *scan_ms = g_prof_ms;
+    if (scan_launches) *scan_launches = g_prof_launches;
+    if (reset) {
+        g_prof_ms = 0.0;
+        g_prof_launches = 0;
     }
     return HS_OK;
 }

@@ -55,6 +55,9 @@ _SIGS = {
     "hs_index_free": (ctypes.c_int32, [_P]),
     "hs_last_error": (ctypes.c_char_p, []),
     "hs_breakpoints": (ctypes.c_int32, [ctypes.c_int32, _P]),
+    "hs_profile_enable": (ctypes.c_int32, [ctypes.c_int32]),
+    "hs_profile_read": (ctypes.c_int32, [ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64),
+                                         ctypes.c_int32]),
 }
 
 _LIB = None
@@ -138,6 +141,17 @@ def hs_breakpoints(card_bits: int = 8):
     out = np.empty(255, dtype=np.float32)
     _check(load().hs_breakpoints(card_bits, out.ctypes.data))
     return out
+
+
+def hs_profile_enable(on: bool) -> None:
+    _check(load().hs_profile_enable(1 if on else 0))
+
+
+def hs_profile_read(reset: bool = False):
+    ms = ctypes.c_double()
+    n = ctypes.c_int64()
+    _check(load().hs_profile_read(ctypes.byref(ms), ctypes.byref(n), 1 if reset else 0))
+    return ms.value, n.value
 
 
 # ---------------------------------------------------------------- torch glue
