@@ -51,14 +51,20 @@ typedef int32_t hs_status;
  *  card_bits  bits per iSAX symbol; must be 8 (alphabet 256, Sec. 2).
  *  leaf_size  leaf capacity tau (Sec. 3.1): a node holding more than tau
  *             series is split, unless no H-split separates its series.
- *  l_max      leaves refined in full by the approximate search that seeds
- *             BSF_k (Sec. 3.3 step 1; 1 by default in the paper), >= 0.
- *  seed_rows  additional seed: the seed_rows series of the l_max leaves with
- *             the smallest LB_SAX are refined first (0 = refine the seed
- *             leaves in storage order).  Access-path choice only.
+ *  l_max      leaves visited by the approximate search that seeds BSF_k
+ *             (Sec. 3.3 step 1; the paper's default is 1), 0 <= l_max;
+ *             values above 64 are treated as 64.  0 = no seed.
+ *  seed_rows  series of those leaves refined by the seed: the ones with the
+ *             smallest LB_SAX, at least max(seed_rows, 2k) of them (the
+ *             paper refines the whole leaves).  Access-path choice only.
  *  eapca_th   Sec. 3.3 threshold: a query whose leaf pruning ratio is below
  *             it skips the LB_SAX filter and scans its candidate leaves.
  *             Access-path choice only; results do not depend on it.
+ *  cand_per_query  candidate-list entries reserved per query in the query
+ *             workspace (0 = max(N/16, 4096)).  A query whose LB_SAX
+ *             survivors do not fit is answered by the fused filter+refine
+ *             kernel instead; results do not depend on it.
+ * Every field is validated by hs_index_bytes / hs_build_summaries.
  */
 typedef struct {
     int32_t n;
@@ -68,7 +74,7 @@ typedef struct {
     int32_t l_max;
     int32_t seed_rows;
     float eapca_th;
-    float reserved_f;
+    int32_t cand_per_query;
 } hs_params;
 
 typedef struct hs_index hs_index; /* opaque, library-owned host handle */

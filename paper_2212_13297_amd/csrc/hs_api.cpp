@@ -29,7 +29,19 @@ struct hs_index {
     int64_t* leaf_start_dev = nullptr;  // library-owned
     float4* env_dev = nullptr;          // library-owned
     float* beta_dev = nullptr;          // library-owned
+    int64_t* part_start_dev = nullptr;  // library-owned
+    uint32_t* part_leaf_dev = nullptr;  // library-owned
 };
+
+namespace {
+void free_owned(hs_index* idx) {
+    if (idx->leaf_start_dev) (void)hipFree(idx->leaf_start_dev);
+    if (idx->env_dev) (void)hipFree(idx->env_dev);
+    if (idx->beta_dev) (void)hipFree(idx->beta_dev);
+    if (idx->part_start_dev) (void)hipFree(idx->part_start_dev);
+    if (idx->part_leaf_dev) (void)hipFree(idx->part_leaf_dev);
+}
+}  // namespace
 
 namespace {
 
@@ -111,6 +123,7 @@ hs_status check_params(const hs_params* p) {
     if (p->l_max < 0) return fail(HS_EINVAL, "l_max=%d must be >= 0", p->l_max);
     if (p->seed_rows < 0) return fail(HS_EINVAL, "seed_rows=%d must be >= 0", p->seed_rows);
     if (!(p->eapca_th >= 0.0f) || !std::isfinite(p->eapca_th)) return fail(HS_EINVAL, "eapca_th must be finite, >= 0");
+    if (p->cand_per_query < 0) return fail(HS_EINVAL, "cand_per_query=%d must be >= 0", p->cand_per_query);
     return HS_OK;
 }
 
@@ -233,10 +246,15 @@ void carve(char*& cur, void** out, int64_t bytes) {
 
 int64_t ws_layout(const hs_index* idx, int32_t Q, int32_t k, QueryWs* ws, char* base) {
     const IndexView& ix = idx->view;
-    const int lm = (int)std::min<int64_t>(idx->p.l_max, ix.L);
-    int P = kPoolMin;
-    while (P < (lm + 2) * k && P < 8192) P <<= 1;
-    const int64_t items = std::max<int64_t>((int64_t)Q * ix.L, (int64_t)Q * lm) + 1;
+    const int P = kPoolMin;
+    const int64_t items = (int64_t)Q * ix.parts + 1;
+    // candidate list: up to 1/16 of the collection per query on average,
+    // between 64 Ki and 256 Mi entries; a query whose candidates do not fit
+    // is answered by the fused scan instead (no result changes)
+    const int64_t cpq = idx->p.cand_per_query;
+    const int64_t per_q = cpq > 0 ? cpq : std::max<int64_t>((ix.N + 15) / 16, 4096);
+    const int64_t floor_c = cpq > 0 ? 1 : (1 << 16);
+    const int64_t cand = std::min<int64_t>(std::max<int64_t>((int64_t)Q * per_q, floor_c), (int64_t)1 << 28);
     char* cur = base;
     QueryWs w{};
     carve(cur, (void**)&w.qrow, (int64_t)Q * ix.stride * 4);
@@ -247,12 +265,15 @@ int64_t ws_layout(const hs_index* idx, int32_t Q, int32_t k, QueryWs* ws, char* 
     carve(cur, (void**)&w.pool_cnt, (int64_t)Q * 4);
     carve(cur, (void**)&w.flags, (int64_t)Q * 4);
     carve(cur, (void**)&w.kept, (int64_t)Q * 4);
-    carve(cur, (void**)&w.seed_key, (int64_t)Q * 8);
     carve(cur, (void**)&w.pool, (int64_t)Q * P * 8);
     carve(cur, (void**)&w.stats, (int64_t)Q * 64);
     carve(cur, (void**)&w.items, items * 8);
-    carve(cur, (void**)&w.counters, 16);
+    carve(cur, (void**)&w.cand_pos, cand * 4);
+    carve(cur, (void**)&w.cand_q, cand * 4);
+    carve(cur, (void**)&w.cand_lb, cand * 4);
+    carve(cur, (void**)&w.counters, kNumCounters * 4);
     w.item_cap = items;
+    w.cand_cap = cand;
     w.P = P;
     if (ws) *ws = w;
     return (int64_t)(cur - base);
@@ -323,9 +344,7 @@ hs_status hs_build_summaries(const float* x_dev, int64_t N, const hs_params* par
     };
     auto bail = [&](hs_status code) {
         cleanup();
-        if (idx->leaf_start_dev) (void)hipFree(idx->leaf_start_dev);
-        if (idx->env_dev) (void)hipFree(idx->env_dev);
-        if (idx->beta_dev) (void)hipFree(idx->beta_dev);
+        free_owned(idx);
         delete idx;
         return code;
     };
@@ -376,6 +395,18 @@ hs_status hs_build_summaries(const float* x_dev, int64_t N, const hs_params* par
     idx->max_leaf = max_leaf;
     std::vector<float2>().swap(part.tmp_st);
     std::vector<float2>().swap(st_host);
+    // work items: every leaf cut into parts of at most kPartRows series
+    std::vector<int64_t> part_start;
+    std::vector<uint32_t> part_leaf;
+    for (int64_t i = 0; i < L; ++i) {
+        for (int64_t r = leaf_start[i]; r < leaf_start[i + 1]; r += kPartRows) {
+            part_start.push_back(r);
+            part_leaf.push_back((uint32_t)i);
+        }
+    }
+    const int64_t parts = (int64_t)part_leaf.size();
+    part_start.push_back(N);
+    ix.parts = parts;
 
     // 3. leaf-ordered copy, words, envelopes
     float beta_host[kCard + 1];
@@ -385,14 +416,22 @@ hs_status hs_build_summaries(const float* x_dev, int64_t N, const hs_params* par
     BUILD_TRY(hipMalloc(&idx->leaf_start_dev, sizeof(int64_t) * (L + 1)));
     BUILD_TRY(hipMalloc(&idx->env_dev, sizeof(float4) * L * p.w));
     BUILD_TRY(hipMalloc(&idx->beta_dev, sizeof(float) * (kCard + 1)));
+    BUILD_TRY(hipMalloc(&idx->part_start_dev, sizeof(int64_t) * (parts + 1)));
+    BUILD_TRY(hipMalloc(&idx->part_leaf_dev, sizeof(uint32_t) * parts));
     BUILD_TRY(hipMemcpyAsync(idx->leaf_start_dev, leaf_start.data(), sizeof(int64_t) * (L + 1),
+                             hipMemcpyHostToDevice, st));
+    BUILD_TRY(hipMemcpyAsync(idx->part_start_dev, part_start.data(), sizeof(int64_t) * (parts + 1),
+                             hipMemcpyHostToDevice, st));
+    BUILD_TRY(hipMemcpyAsync(idx->part_leaf_dev, part_leaf.data(), sizeof(uint32_t) * parts,
                              hipMemcpyHostToDevice, st));
     BUILD_TRY(hipMemcpyAsync(idx->beta_dev, beta_host, sizeof(beta_host), hipMemcpyHostToDevice, st));
     BUILD_TRY(hipMemcpyAsync((void*)ix.ids, id_host.data(), sizeof(uint32_t) * N, hipMemcpyHostToDevice, st));
     ix.leaf_start = idx->leaf_start_dev;
     ix.env = idx->env_dev;
     ix.beta = idx->beta_dev;
-    BUILD_TRY(launch_gather_rows(x_dev, ix.ids, N, p.n, ix.stride, (float*)ix.rows, nullptr, st));
+    ix.part_start = idx->part_start_dev;
+    ix.part_leaf = idx->part_leaf_dev;
+    BUILD_TRY(launch_gather_rows(x_dev, ix.ids, N, p.n, ix.stride, (float*)ix.rows, st));
     BUILD_TRY(launch_words(ix, (uint8_t*)ix.words, st));
     BUILD_TRY(launch_envelopes(ix, idx->env_dev, st));
     BUILD_TRY(hipStreamSynchronize(st));
@@ -446,54 +485,53 @@ hs_status hs_knn_exact(hs_index* idx, const float* q_dev, int32_t Q, int32_t k, 
     QueryWs ws;
     ws_layout(idx, Q, k, &ws, (char*)ws_dev);
     const IndexView& ix = idx->view;
-    const int lm = (int)std::min<int64_t>(idx->p.l_max, ix.L);
+    const int lm = (int)std::min<int64_t>(std::min<int64_t>(idx->p.l_max, ix.L), kMaxSeedLeaves);
 
     ScanParams sp{};
     sp.Q = Q;
     sp.k = k;
     sp.eapca_th = idx->p.eapca_th;
     sp.n_seed = lm;
+    sp.seed_rows = idx->p.seed_rows;
     auto* stats_out = (hs_query_stats*)stats_dev;
 
+    // profiling brackets the two dominant kernels: the LB_SAX filter and the refinement
     ScanTimer timer;
-    auto scan = [&]() -> hipError_t {
+    auto timed = [&](hipError_t (*fn)(const IndexView&, const ScanParams&, const QueryWs&, int, hipStream_t))
+        -> hipError_t {
         hipError_t e = timer.begin(st);
         if (e != hipSuccess) return e;
-        e = launch_leaf_scan(ix, sp, ws, idx->cus, st);
+        e = fn(ix, sp, ws, idx->cus, st);
         if (e != hipSuccess) return e;
         return timer.end(st);
     };
 
     HIP_TRY(launch_query_prep(ix, q_dev, Q, ws, st));
     HIP_TRY(launch_lb_eapca(ix, Q, ws, st));
-    // step 1: approximate search over the l_max smallest-LB_EAPCA leaves
-    HIP_TRY(launch_seed_select(ix, Q, idx->p.l_max, ws, st));
-    if (lm > 0) {
-        sp.final_pass = 0;
-        HIP_TRY(scan());
-        HIP_TRY(launch_merge(ix, sp, false, ws, nullptr, nullptr, nullptr, st));
-    }
-    // steps 2-4: candidate leaves, LB_SAX filter, refinement
-    HIP_TRY(launch_emit_main(ix, Q, false, ws, st));
-    HIP_TRY(scan());
+    // step 1: approximate search seeds BSF_k
+    HIP_TRY(launch_seed(ix, sp, ws, st));
+    // step 2: candidate leaves; step 3: LB_SAX filter; step 4: refinement
+    HIP_TRY(launch_emit(ix, sp, false, ws, st));
+    HIP_TRY(timed(launch_filter));
+    HIP_TRY(timed(launch_refine));
     sp.final_pass = 1;
     HIP_TRY(launch_merge(ix, sp, false, ws, ids_dev, d2_dev, stats_out, st));
 
-    // rounds after a candidate-pool overflow: rescan the affected queries with
-    // the tightened BSF_k until no pool overflows (each round's merge keeps the
-    // best k seen so far and drops duplicates)
+    // queries whose candidate list or result pool overflowed: rescan their
+    // candidate parts with the fused kernel and the tightened BSF_k until
+    // nothing overflows (each merge keeps the best k so far, without repeats)
     for (int round = 0;; ++round) {
         uint32_t c[2] = {0, 0};
-        HIP_TRY(hipMemcpyAsync(c, ws.counters + 2, sizeof c, hipMemcpyDeviceToHost, st));
+        HIP_TRY(hipMemcpyAsync(c, ws.counters + kCtrRedo, sizeof c, hipMemcpyDeviceToHost, st));
         HIP_TRY(hipStreamSynchronize(st));
         if (c[1]) return fail(HS_EINVAL, "%u queries contain NaN or Inf", c[1]);
         if (c[0] == 0) {
             timer.collect();
             break;
         }
-        if (round >= 64) return fail(HS_EHIP, "candidate pool still overflowing after %d rounds", round);
-        HIP_TRY(launch_emit_main(ix, Q, true, ws, st));
-        HIP_TRY(scan());
+        if (round >= 64) return fail(HS_EHIP, "result pool still overflowing after %d rounds", round);
+        HIP_TRY(launch_emit(ix, sp, true, ws, st));
+        HIP_TRY(timed(launch_leaf_scan));
         HIP_TRY(launch_merge(ix, sp, true, ws, ids_dev, d2_dev, stats_out, st));
     }
     return HS_OK;
@@ -518,9 +556,7 @@ hs_status hs_profile_read(double* scan_ms, int64_t* scan_launches, int32_t reset
 
 hs_status hs_index_free(hs_index* idx) {
     if (!idx) return HS_OK;
-    if (idx->leaf_start_dev) (void)hipFree(idx->leaf_start_dev);
-    if (idx->env_dev) (void)hipFree(idx->env_dev);
-    if (idx->beta_dev) (void)hipFree(idx->beta_dev);
+    free_owned(idx);
     delete idx;
     return HS_OK;
 }

@@ -11,8 +11,10 @@ namespace hs {
 
 constexpr int kCard = 256;          // iSAX alphabet (8-bit symbols)
 constexpr int kChunk = 64;          // points per refinement chunk (early-abandon granularity)
-constexpr int kTile = 256;          // series per LB_SAX tile = threads per scan workgroup
+constexpr int kTile = 256;          // threads per scan / filter / refine workgroup
+constexpr int kPartRows = 2048;     // series per work item: leaves are cut into parts of at most this many
 constexpr uint32_t kInfBits = 0x7f800000u;  // +inf as float bits
+constexpr int kMaxSeedLeaves = 64;  // l_max is clamped to this many leaves in the seed step
 
 // Relative slack on every prune comparison: a bound is compared against
 // BSF_k * (1 + kSlack).  It covers float32 rounding of LB_SAX sums and of the
@@ -22,16 +24,36 @@ constexpr double kSlack = 1e-5;
 // Pool of candidate results per query: (distance bits << 32 | original id).
 constexpr int kPoolMin = 4096;
 
+// query flags
+constexpr uint32_t kFlagOverflow = 1;    // the result pool overflowed in this round
+constexpr uint32_t kFlagCandLost = 2;    // candidates were dropped (candidate buffer full)
+constexpr uint32_t kFlagNonFinite = 4;   // the query holds NaN or Inf
+constexpr uint32_t kFlagRedo = 8;        // needs another round
+constexpr uint32_t kFlagInRound = 16;    // takes part in the current redo round
+constexpr uint32_t kFlagSkipSax = 32;    // skip-sequential path: no LB_SAX filter
+
+// counters[] slots
+constexpr int kCtrItems = 0;     // items emitted
+constexpr int kCtrWork = 1;      // work-distribution counter of the filter / scan kernels
+constexpr int kCtrRedo = 2;      // queries that need another round
+constexpr int kCtrNonFinite = 3; // queries with NaN / Inf
+constexpr int kCtrCand = 4;      // candidates appended by the filter
+constexpr int kCtrRefine = 5;    // work-distribution counter of the refine kernel
+constexpr int kNumCounters = 8;
+
 // Everything a kernel needs to know about an index.
 struct IndexView {
-    const float* rows;        // [N][stride] leaf-ordered series, zero padded
-    const uint32_t* ids;      // [N] original row id of each stored series
-    const uint8_t* words;     // [N][wstride] iSAX symbols
-    const int64_t* leaf_start;// [L + 1]
-    const float4* env;        // [L][w] (mu_min, mu_max, sd_min, sd_max), rounded outward
-    const float* beta;        // [257] float32 breakpoints, beta[0] = -inf, beta[256] = +inf
+    const float* rows;         // [N][stride] leaf-ordered series, zero padded
+    const uint32_t* ids;       // [N] original row id of each stored series
+    const uint8_t* words;      // [N][wstride] iSAX symbols
+    const int64_t* leaf_start; // [L + 1]
+    const float4* env;         // [L][w] (mu_min, mu_max, sd_min, sd_max), rounded outward
+    const float* beta;         // [257] float32 breakpoints, beta[0] = -inf, beta[256] = +inf
+    const int64_t* part_start; // [parts + 1] rows of part p: [part_start[p], part_start[p + 1])
+    const uint32_t* part_leaf; // [parts] leaf of each part
     int64_t N;
     int64_t L;
+    int64_t parts;
     int32_t n, w, stride, wstride;
 };
 
@@ -43,14 +65,17 @@ struct QueryWs {
     float* lbe;           // [Q][L] LB_EAPCA^2, rounded down
     uint32_t* bsf;        // [Q] float bits of the current BSF_k (monotone, atomicMin)
     uint32_t* pool_cnt;   // [Q]
-    uint32_t* flags;      // [Q] bit0 overflow, bit1 skip-sequential, bit2 non-finite query, bit3 redo
-    uint32_t* kept;       // [Q] candidate leaves emitted for the main pass
-    uint64_t* seed_key;   // [Q] largest (lbE bits, leaf) key among the seed leaves (0 if none)
+    uint32_t* flags;      // [Q] kFlag* bits
+    uint32_t* kept;       // [Q] candidate leaves after the leaf filter
     uint64_t* pool;       // [Q][P]
     unsigned long long* stats;  // [Q][8]
-    uint64_t* items;      // [cap] (q << 32 | leaf)
-    uint32_t* counters;   // [4]: 0 items, 1 work counter
+    uint64_t* items;      // [item_cap] (q << 32 | part)
+    uint32_t* cand_pos;   // [cand_cap] stored position of a candidate series
+    uint32_t* cand_q;     // [cand_cap] its query
+    float* cand_lb;       // [cand_cap] its LB_SAX
+    uint32_t* counters;   // [kNumCounters]
     int64_t item_cap;
+    int64_t cand_cap;
     int32_t P;
 };
 
@@ -58,25 +83,30 @@ struct ScanParams {
     int32_t Q, k;
     float eapca_th;
     int32_t final_pass;
-    int32_t n_seed;  // seed leaves per query: min(l_max, L)
+    int32_t n_seed;     // seed leaves per query: min(l_max, L, kMaxSeedLeaves)
+    int32_t seed_rows;  // series refined by the seed step
 };
 
 // kernel launchers (hs_kernels.hip); all asynchronous on `st`
 hipError_t launch_series_stats(const float* x, int64_t N, int32_t n, int32_t w, float2* st_out,
                                uint32_t* bad_flag, hipStream_t st);
 hipError_t launch_gather_rows(const float* x, const uint32_t* perm, int64_t N, int32_t n, int32_t stride,
-                              float* rows, uint32_t* ids, hipStream_t st);
+                              float* rows, hipStream_t st);
 hipError_t launch_words(const IndexView& ix, uint8_t* words, hipStream_t st);
 hipError_t launch_envelopes(const IndexView& ix, float4* env, hipStream_t st);
 
 hipError_t launch_query_prep(const IndexView& ix, const float* q, int32_t Q, const QueryWs& ws, hipStream_t st);
 hipError_t launch_lb_eapca(const IndexView& ix, int32_t Q, const QueryWs& ws, hipStream_t st);
-hipError_t launch_seed_select(const IndexView& ix, int32_t Q, int32_t l_max, const QueryWs& ws, hipStream_t st);
-hipError_t launch_emit_main(const IndexView& ix, int32_t Q, bool redo_only, const QueryWs& ws, hipStream_t st);
+hipError_t launch_seed(const IndexView& ix, const ScanParams& sp, const QueryWs& ws, hipStream_t st);
+hipError_t launch_emit(const IndexView& ix, const ScanParams& sp, bool redo_only, const QueryWs& ws,
+                       hipStream_t st);
+hipError_t launch_filter(const IndexView& ix, const ScanParams& sp, const QueryWs& ws, int device_cus,
+                         hipStream_t st);
+hipError_t launch_refine(const IndexView& ix, const ScanParams& sp, const QueryWs& ws, int device_cus,
+                         hipStream_t st);
 hipError_t launch_leaf_scan(const IndexView& ix, const ScanParams& sp, const QueryWs& ws, int device_cus,
                             hipStream_t st);
 hipError_t launch_merge(const IndexView& ix, const ScanParams& sp, bool redo_only, const QueryWs& ws,
                         int64_t* ids_out, float* d2_out, hs_query_stats* stats_out, hipStream_t st);
-hipError_t launch_reset_counters(const QueryWs& ws, hipStream_t st);
 
 }  // namespace hs

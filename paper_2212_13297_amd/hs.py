@@ -26,7 +26,7 @@ HS_KMAX = 128
 class hs_params(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int32), ("w", ctypes.c_int32), ("card_bits", ctypes.c_int32),
                 ("leaf_size", ctypes.c_int32), ("l_max", ctypes.c_int32), ("seed_rows", ctypes.c_int32),
-                ("eapca_th", ctypes.c_float), ("reserved_f", ctypes.c_float)]
+                ("eapca_th", ctypes.c_float), ("cand_per_query", ctypes.c_int32)]
 
 
 class hs_index_info(ctypes.Structure):
@@ -161,13 +161,14 @@ class Params:
     w: int = 16
     leaf_size: int = 10_000
     l_max: int = 1
-    seed_rows: int = 0
+    seed_rows: int = 256
     eapca_th: float = 0.0
     card_bits: int = 8
+    cand_per_query: int = 0
 
     def c(self, n: int) -> hs_params:
         return hs_params(n, self.w, self.card_bits, self.leaf_size, self.l_max, self.seed_rows,
-                         float(self.eapca_th), 0.0)
+                         float(self.eapca_th), self.cand_per_query)
 
 
 def _stream_ptr(stream):

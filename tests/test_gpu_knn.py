@@ -144,15 +144,30 @@ def test_results_do_not_depend_on_access_path():
         idx.close()
 
 
-def test_pool_overflow_takes_more_rounds():
-    # one series per leaf and a seed that cannot fill k: every leaf passes the
-    # leaf filter and appends its series, overflowing the 4096-entry pool
+def test_overflow_fallback_rounds():
+    # one series per leaf and a seed that cannot fill k: every series is an
+    # LB_SAX survivor, the 16-entry candidate lists overflow, and the fused
+    # fallback appends one entry per single-series item, overflowing the
+    # 4096-entry result pool too: the answer still matches the oracle
     x, q = workload(6000, 64, coll=13, per_level=1, ood=1)
-    idx = make_index(x, w=8, leaf_size=1, l_max=1)
+    idx = make_index(x, w=8, leaf_size=1, l_max=1, cand_per_query=16)
     ids, d2, st = run_knn(idx, q, 10, stats=True)
     check_knn(x, q, 10, ids, d2)
-    assert np.all(st["rounds"].cpu().numpy() >= 2)
+    assert np.all(st["rounds"].cpu().numpy() >= 3)
     idx.close()
+
+
+def test_candidate_list_fallback_matches_main_path():
+    x, q = workload(30_000, 256, coll=14, per_level=3)
+    a = make_index(x, w=16, leaf_size=1000)
+    b = make_index(x, w=16, leaf_size=1000, cand_per_query=64)
+    ia, da, sa = run_knn(a, q, 10, stats=True)
+    ib, db, sb = run_knn(b, q, 10, stats=True)
+    assert np.array_equal(ia, ib) and np.array_equal(da, db)
+    assert sb["rounds"].cpu().numpy().max() >= 2
+    check_knn(x, q, 10, ia, da)
+    a.close()
+    b.close()
 
 
 def test_batch_composition_does_not_change_results():
