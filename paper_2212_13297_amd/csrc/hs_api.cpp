@@ -479,6 +479,8 @@ hs_status hs_knn_exact(hs_index* idx, const float* q_dev, int32_t Q, int32_t k, 
     if ((int64_t)k > idx->view.N) return fail(HS_EINVAL, "k=%d > N=%lld", k, (long long)idx->view.N);
     if (Q == 0) return HS_OK;
     if (!q_dev || !ws_dev || !ids_dev || !d2_dev) return fail(HS_EINVAL, "NULL device pointer");
+    if ((int64_t)Q * idx->view.parts >= ((int64_t)1 << 31))
+        return fail(HS_EINVAL, "Q=%d too large for this index (Q * parts must stay below 2^31); split the batch", Q);
     const int64_t need = ws_layout(idx, Q, k, nullptr, nullptr);
     if (ws_bytes < need) return fail(HS_ENOMEM, "ws_bytes=%lld < required %lld", (long long)ws_bytes, (long long)need);
     hipStream_t st = (hipStream_t)stream;

@@ -39,6 +39,8 @@ constexpr int kCtrRedo = 2;      // queries that need another round
 constexpr int kCtrNonFinite = 3; // queries with NaN / Inf
 constexpr int kCtrCand = 4;      // candidates appended by the filter
 constexpr int kCtrRefine = 5;    // work-distribution counter of the refine kernel
+constexpr int kCtrCandEnd = 6;   // smallest base of a candidate range that did not fit (UINT32_MAX if none):
+                                 // entries at or above it were never written
 constexpr int kNumCounters = 8;
 
 // Everything a kernel needs to know about an index.

@@ -596,9 +596,21 @@ __global__ void __launch_bounds__(256) k_filter(IndexView ix, ScanParams sp, Que
             if (t == 0) {
                 uint32_t base = 0xffffffffu;
                 if (total > 0) {
-                    const uint32_t b = atomicAdd(&ws.counters[kCtrCand], (uint32_t)total);
-                    if ((int64_t)b + total <= ws.cand_cap) base = b;
-                    else atomicOr(&ws.flags[q], kFlagCandLost);
+                    // once the list is full no more ranges are reserved, so the
+                    // 32-bit counter overshoots the capacity by at most one
+                    // range per resident block
+                    if ((int64_t)load_relaxed(&ws.counters[kCtrCand]) >= ws.cand_cap) {
+                        atomicOr(&ws.flags[q], kFlagCandLost);
+                    } else {
+                        const uint32_t b = atomicAdd(&ws.counters[kCtrCand], (uint32_t)total);
+                        if ((int64_t)b + total <= ws.cand_cap) {
+                            base = b;
+                        } else {
+                            // this range is never written; the refine kernel stops below it
+                            atomicMin(&ws.counters[kCtrCandEnd], b);
+                            atomicOr(&ws.flags[q], kFlagCandLost);
+                        }
+                    }
                 }
                 s_base = base;
                 if (!skip) atomicAdd(&ws.stats[(int64_t)q * 8 + 1], (unsigned long long)(pe - pb));
@@ -639,7 +651,9 @@ __global__ void __launch_bounds__(256) k_refine(IndexView ix, ScanParams sp, Que
     const int t = threadIdx.x, lane = t & 63, sub = t & 15, grp = t >> 4;
     const int k = sp.k;
     const int nchunks = ix.stride / kChunk;
-    const int64_t ncand = min((int64_t)ws.counters[kCtrCand], ws.cand_cap);
+    // every entry below min(counter, first range that did not fit) was written
+    const int64_t ncand =
+        min(min((int64_t)ws.counters[kCtrCand], (int64_t)ws.counters[kCtrCandEnd]), ws.cand_cap);
     if (t == 0) {
         s_nres = 0;
         s_topn = 0;
@@ -904,14 +918,15 @@ __global__ void __launch_bounds__(1024) k_merge(IndexView ix, ScanParams sp, int
 }
 
 __global__ void k_set_counters(uint32_t* c, int first, int count) {
-    if ((int)threadIdx.x < count) c[first + threadIdx.x] = 0;
+    const int i = first + (int)threadIdx.x;
+    if ((int)threadIdx.x < count) c[i] = i == kCtrCandEnd ? 0xffffffffu : 0u;
 }
 
 __global__ void k_arm_redo(QueryWs ws, int32_t Q) {
     const int q = blockIdx.x * blockDim.x + threadIdx.x;
     if (q == 0) {
         for (int i = 0; i < kNumCounters; ++i)
-            if (i != kCtrNonFinite) ws.counters[i] = 0;
+            if (i != kCtrNonFinite) ws.counters[i] = i == kCtrCandEnd ? 0xffffffffu : 0u;
     }
     if (q >= Q) return;
     uint32_t f = ws.flags[q];
