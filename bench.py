@@ -51,6 +51,7 @@ def main():
     ap.add_argument("--w", type=int, default=16)
     ap.add_argument("--leaf", type=int, default=10_000)
     ap.add_argument("--l-max", type=int, default=1)
+    ap.add_argument("--seed-rows", type=int, default=256)
     ap.add_argument("--cpu-sample", type=int, default=24, help="queries timed on the CPU oracle")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--latency-queries", type=int, default=300)
@@ -77,7 +78,7 @@ def main():
     xt = torch.from_numpy(x).to(dev)
     qt = torch.from_numpy(q).to(dev)
     torch.cuda.synchronize()
-    params = hs.Params(w=args.w, leaf_size=args.leaf, l_max=args.l_max)
+    params = hs.Params(w=args.w, leaf_size=args.leaf, l_max=args.l_max, seed_rows=args.seed_rows)
     t0 = time.time()
     idx = hs.Index(xt, params)
     torch.cuda.synchronize()
@@ -197,6 +198,9 @@ def main():
         "pruning": {"leaves_kept_mean": float(stats["leaves_kept"].mean()),
                     "rows_filtered_mean": float(stats["rows_filtered"].mean()),
                     "rows_refined_mean": float(stats["rows_refined"].mean()),
+                    "candidates_mean": float(stats["candidates"].mean()),
+                    "per_level_refined_mean": [float(stats["rows_refined"][pct == p].mean()) for p in levels],
+                    "per_level_candidates_mean": [float(stats["candidates"][pct == p].mean()) for p in levels],
                     "rounds_max": int(stats["rounds"].max())},
         "build_s": round(build_s, 2),
         "cpu_baseline": cpu,

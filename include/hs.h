@@ -141,7 +141,8 @@ typedef struct {
     uint64_t chunks_read;     /* 64-point chunks of raw values read (early abandoning stops early) */
     uint64_t path;            /* 0 = LB_SAX path, 1 = skip-sequential (no LB_SAX) */
     uint64_t rounds;          /* refinement rounds (1 unless the candidate pool overflowed) */
-    uint64_t reserved[2];
+    uint64_t candidates;      /* LB_SAX survivors put on the candidate list (two-stage path) */
+    uint64_t reserved;
 } hs_query_stats;
 
 /*

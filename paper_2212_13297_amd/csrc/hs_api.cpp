@@ -254,7 +254,9 @@ int64_t ws_layout(const hs_index* idx, int32_t Q, int32_t k, QueryWs* ws, char* 
     const int64_t cpq = idx->p.cand_per_query;
     const int64_t per_q = cpq > 0 ? cpq : std::max<int64_t>((ix.N + 15) / 16, 4096);
     const int64_t floor_c = cpq > 0 ? 1 : (1 << 16);
-    const int64_t cand = std::min<int64_t>(std::max<int64_t>((int64_t)Q * per_q, floor_c), (int64_t)1 << 28);
+    const int64_t cand_total = std::min<int64_t>(std::max<int64_t>((int64_t)Q * per_q, floor_c), (int64_t)1 << 28);
+    const int64_t per_region = (cand_total + kRegions - 1) / kRegions;
+    const int64_t cand = per_region * kRegions;
     char* cur = base;
     QueryWs w{};
     carve(cur, (void**)&w.qrow, (int64_t)Q * ix.stride * 4);
@@ -272,8 +274,10 @@ int64_t ws_layout(const hs_index* idx, int32_t Q, int32_t k, QueryWs* ws, char* 
     carve(cur, (void**)&w.cand_q, cand * 4);
     carve(cur, (void**)&w.cand_lb, cand * 4);
     carve(cur, (void**)&w.counters, kNumCounters * 4);
+    carve(cur, (void**)&w.cand_cnt, kRegions * 4);
+    carve(cur, (void**)&w.cand_end, kRegions * 4);
     w.item_cap = items;
-    w.cand_cap = cand;
+    w.cand_cap = per_region;
     w.P = P;
     if (ws) *ws = w;
     return (int64_t)(cur - base);

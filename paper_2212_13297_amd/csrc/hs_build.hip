@@ -1,0 +1,146 @@
+// Index-build kernels (Hercules Sec. 2 summaries, Sec. 3.1 tree):
+//   series_stats  per (series, segment) mean and population std (FP64 math),
+//                 used by the host to choose the leaf splits
+//   gather_rows   leaf-ordered, zero-padded copy of the series
+//   words         iSAX symbol per (series, segment): FP64 PAA against the
+//                 float32 Gaussian breakpoints
+//   envelopes     per (leaf, segment) min/max of mean and std, rounded
+//                 outward to float32 so they contain the FP64 statistics
+#include "hs_device.h"
+
+namespace hs {
+namespace {
+
+__global__ void k_series_stats(const float* __restrict__ x, int64_t N, int32_t n, int32_t w,
+                               float2* __restrict__ out, uint32_t* bad) {
+    const int32_t l = n / w;
+    const int64_t total = N * (int64_t)w;
+    for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < total;
+         t += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t row = t / w;
+        const int32_t seg = (int32_t)(t - row * w);
+        const float* p = x + row * n + (int64_t)seg * l;
+        double s = 0.0;
+        bool ok = true;
+        for (int j = 0; j < l; ++j) {
+            float v = p[j];
+            ok &= isfinite(v);
+            s += (double)v;
+        }
+        const double mu = s / l;
+        double ss = 0.0;
+        for (int j = 0; j < l; ++j) {
+            double d = (double)p[j] - mu;
+            ss += d * d;
+        }
+        if (!ok) atomicOr(bad, 1u);
+        out[t] = make_float2((float)mu, (float)sqrt(ss / l));
+    }
+}
+
+__global__ void k_gather_rows(const float* __restrict__ x, const uint32_t* __restrict__ perm, int64_t N,
+                              int32_t n, int32_t stride, float* __restrict__ rows) {
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    for (int64_t pos = blockIdx.x * (int64_t)(blockDim.x >> 6) + wave; pos < N;
+         pos += (int64_t)gridDim.x * (blockDim.x >> 6)) {
+        const float* src = x + (int64_t)perm[pos] * n;
+        float* dst = rows + pos * stride;
+        for (int j = lane; j < stride; j += 64) dst[j] = j < n ? src[j] : 0.0f;
+    }
+}
+
+__global__ void k_words(IndexView ix, uint8_t* __restrict__ words) {
+    __shared__ float s_beta[kCard + 1];
+    for (int j = threadIdx.x; j <= kCard; j += blockDim.x) s_beta[j] = ix.beta[j];
+    __syncthreads();
+    const int32_t l = ix.n / ix.w;
+    const int64_t total = ix.N * (int64_t)ix.w;
+    for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < total;
+         t += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t pos = t / ix.w;
+        const int32_t seg = (int32_t)(t - pos * ix.w);
+        const float* p = ix.rows + pos * ix.stride + (int64_t)seg * l;
+        double s = 0.0;
+        for (int j = 0; j < l; ++j) s += (double)p[j];
+        const double paa = s / l;
+        // symbol = #{j in 1..255 : beta_j <= paa}: upper bound over beta[1..255]
+        int lo = 1, hi = kCard;  // answer index in [1, 256]; symbol = index - 1
+        while (lo < hi) {
+            int mid = (lo + hi) >> 1;
+            if ((double)s_beta[mid] <= paa) lo = mid + 1; else hi = mid;
+        }
+        words[pos * ix.wstride + seg] = (uint8_t)(lo - 1);
+    }
+}
+
+__global__ void __launch_bounds__(256) k_envelopes(IndexView ix, float4* __restrict__ env) {
+    __shared__ double s_red[256][4];
+    const int64_t leaf = blockIdx.x;
+    const int64_t b = ix.leaf_start[leaf], e = ix.leaf_start[leaf + 1];
+    const int32_t w = ix.w, l = ix.n / w;
+    const int G = 256 / w;  // threads per segment
+    const int t = threadIdx.x;
+    double mn = INFINITY, mx = -INFINITY, sn = INFINITY, sx = -INFINITY;
+    if (t < G * w) {
+        const int seg = t % w, grp = t / w;
+        for (int64_t r = b + grp; r < e; r += G) {
+            const float* p = ix.rows + r * ix.stride + (int64_t)seg * l;
+            double s = 0.0;
+            for (int j = 0; j < l; ++j) s += (double)p[j];
+            const double mu = s / l;
+            double ss = 0.0;
+            for (int j = 0; j < l; ++j) {
+                double d = (double)p[j] - mu;
+                ss += d * d;
+            }
+            const double sd = sqrt(ss / l);
+            mn = fmin(mn, mu);
+            mx = fmax(mx, mu);
+            sn = fmin(sn, sd);
+            sx = fmax(sx, sd);
+        }
+    }
+    s_red[t][0] = mn;
+    s_red[t][1] = mx;
+    s_red[t][2] = sn;
+    s_red[t][3] = sx;
+    __syncthreads();
+    if (t < w) {
+        for (int g = 1; g < G; ++g) {
+            const int o = g * w + t;
+            mn = fmin(mn, s_red[o][0]);
+            mx = fmax(mx, s_red[o][1]);
+            sn = fmin(sn, s_red[o][2]);
+            sx = fmax(sx, s_red[o][3]);
+        }
+        // outward rounding: the float32 box contains every member's FP64 statistic
+        env[leaf * w + t] = make_float4(__double2float_rd(mn), __double2float_ru(mx), __double2float_rd(sn),
+                                        __double2float_ru(sx));
+    }
+}
+
+}  // namespace
+
+hipError_t launch_series_stats(const float* x, int64_t N, int32_t n, int32_t w, float2* st_out, uint32_t* bad,
+                               hipStream_t st) {
+    hipLaunchKernelGGL(k_series_stats, dim3(grid_for(N * w, 256)), dim3(256), 0, st, x, N, n, w, st_out, bad);
+    return hipGetLastError();
+}
+
+hipError_t launch_gather_rows(const float* x, const uint32_t* perm, int64_t N, int32_t n, int32_t stride,
+                              float* rows, hipStream_t st) {
+    hipLaunchKernelGGL(k_gather_rows, dim3(grid_for(N, 4)), dim3(256), 0, st, x, perm, N, n, stride, rows);
+    return hipGetLastError();
+}
+
+hipError_t launch_words(const IndexView& ix, uint8_t* words, hipStream_t st) {
+    hipLaunchKernelGGL(k_words, dim3(grid_for(ix.N * ix.w, 256)), dim3(256), 0, st, ix, words);
+    return hipGetLastError();
+}
+
+hipError_t launch_envelopes(const IndexView& ix, float4* env, hipStream_t st) {
+    hipLaunchKernelGGL(k_envelopes, dim3((unsigned)ix.L), dim3(256), 0, st, ix, env);
+    return hipGetLastError();
+}
+
+}  // namespace hs

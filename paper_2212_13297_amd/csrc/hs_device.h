@@ -1,0 +1,206 @@
+// Device helpers shared by the query-side kernels (hs_query.hip, hs_scan.hip).
+//
+// Result keys are (float bits of d << 32 | original id): for d >= 0 the
+// unsigned order of the key is the (d, id) lexicographic order.
+//
+// Distances: 16 lanes own one series; lane l holds points 4l..4l+3 of every
+// 64-point chunk.  A chunk's partial is the lane's sequential fma chain over
+// its 4 points, summed over the 16 lanes by a xor butterfly (commutative, so
+// every lane holds the same value); d adds the chunk partials in chunk order.
+// Every kernel uses this order, so a (query, series) pair always gets the
+// same float32 distance.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+
+#include "hs_internal.h"
+
+namespace hs {
+namespace {
+
+__device__ __forceinline__ double gap(double v, double lo, double hi) {
+    return v < lo ? lo - v : (v > hi ? v - hi : 0.0);
+}
+
+__device__ __forceinline__ float bits_to_float(uint32_t b) { return __uint_as_float(b); }
+
+__device__ __forceinline__ uint32_t load_relaxed(const uint32_t* p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// A bound prunes only when it exceeds BSF_k by the relative slack.
+__device__ __forceinline__ double prune_limit(float bsf) { return (double)bsf * (1.0 + kSlack); }
+
+// LB_SAX of one stored series: sum over segments of the query's table entry
+// for the series' symbol (words are 16-byte aligned, W16 uint4 per word).
+template <int W16>
+__device__ __forceinline__ float lb_sax_word(const uint4 (&v)[W16], const float* s_lut, int w) {
+    float acc = 0.0f;
+#pragma unroll
+    for (int u = 0; u < W16; ++u) {
+        const uint32_t parts[4] = {v[u].x, v[u].y, v[u].z, v[u].w};
+#pragma unroll
+        for (int p = 0; p < 4; ++p) {
+#pragma unroll
+            for (int b = 0; b < 4; ++b) {
+                const int i = u * 16 + p * 4 + b;
+                if (i < w) acc += s_lut[i * kCard + ((parts[p] >> (8 * b)) & 0xffu)];
+            }
+        }
+    }
+    return acc;
+}
+
+template <int W16>
+__device__ __forceinline__ void load_word(const uint8_t* __restrict__ wp, uint4 (&v)[W16]) {
+#pragma unroll
+    for (int u = 0; u < W16; ++u) v[u] = *reinterpret_cast<const uint4*>(wp + 16 * u);
+}
+
+__device__ __forceinline__ float chunk_partial(float4 q, float4 x) {
+    const float t0 = q.x - x.x, t1 = q.y - x.y, t2 = q.z - x.z, t3 = q.w - x.w;
+    float p = t0 * t0;
+    p = fmaf(t1, t1, p);
+    p = fmaf(t2, t2, p);
+    p = fmaf(t3, t3, p);
+    p += __shfl_xor(p, 1, 16);
+    p += __shfl_xor(p, 2, 16);
+    p += __shfl_xor(p, 4, 16);
+    p += __shfl_xor(p, 8, 16);
+    return p;
+}
+
+// Squared distance of one series, computed by the 16 lanes of a group (all 16
+// active together).  xr / qr point at the lane's first point.  Chunks are
+// loaded two at a time; after each pair the running sum is compared with
+// thr and the series is abandoned once it exceeds it (the final sum can only
+// be larger).  `chunks` counts the chunks read.
+__device__ __forceinline__ float refine_row(const float* __restrict__ xr, const float* __restrict__ qr,
+                                           int nchunks, float thr, bool& alive, unsigned& chunks) {
+    float d = 0.0f;
+    alive = true;
+    for (int c = 0; c < nchunks; c += 2) {
+        const bool two = c + 1 < nchunks;
+        const float4 x0 = *reinterpret_cast<const float4*>(xr + c * kChunk);
+        float4 x1 = make_float4(0.f, 0.f, 0.f, 0.f);
+        if (two) x1 = *reinterpret_cast<const float4*>(xr + (c + 1) * kChunk);
+        d += chunk_partial(*reinterpret_cast<const float4*>(qr + c * kChunk), x0);
+        if (two) d += chunk_partial(*reinterpret_cast<const float4*>(qr + (c + 1) * kChunk), x1);
+        chunks += two ? 2u : 1u;
+        if (d > thr) {
+            alive = false;
+            break;
+        }
+    }
+    return d;
+}
+
+// Insert key into the ascending list top[0..n) of capacity k (one thread).
+__device__ __forceinline__ void topk_insert(unsigned long long* top, int& n, int k, unsigned long long key) {
+    if (n == k && key >= top[k - 1]) return;
+    int p = n < k ? n : k - 1;
+    while (p > 0 && top[p - 1] > key) {
+        top[p] = top[p - 1];
+        --p;
+    }
+    top[p] = key;
+    if (n < k) ++n;
+}
+
+// Publish a block's top-k for query q (one thread): tighten BSF_k with its
+// k-th distance, then append the entries that do not exceed BSF_k to the pool.
+__device__ __forceinline__ void flush_topk(const QueryWs& ws, int q, int k, const unsigned long long* top, int n) {
+    if (q < 0 || n == 0) return;
+    float g = bits_to_float(load_relaxed(&ws.bsf[q]));
+    if (n == k) {
+        const uint32_t kb = (uint32_t)(top[k - 1] >> 32);
+        if (bits_to_float(kb) < g) {
+            atomicMin(&ws.bsf[q], kb);
+            g = bits_to_float(kb);
+        }
+    }
+    int cnt = 0;
+    while (cnt < n && bits_to_float((uint32_t)(top[cnt] >> 32)) <= g) ++cnt;
+    if (cnt == 0) return;
+    const uint32_t base = atomicAdd(&ws.pool_cnt[q], (uint32_t)cnt);
+    for (int j = 0; j < cnt; ++j)
+        if (base + j < (uint32_t)ws.P) ws.pool[(int64_t)q * ws.P + base + j] = top[j];
+    if (base + cnt > (uint32_t)ws.P) atomicOr(&ws.flags[q], kFlagOverflow);
+}
+
+// Exclusive prefix sum over the 256 threads of a block; returns the offset of
+// this thread and writes the block total to *total.  s_w holds 4 ints.
+__device__ __forceinline__ int block_exclusive_scan(int v, int* s_w, int* total) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    int inc = v;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const int y = __shfl_up(inc, o, 64);
+        if (lane >= o) inc += y;
+    }
+    if (lane == 63) s_w[wave] = inc;
+    __syncthreads();
+    int off = 0, tot = 0;
+#pragma unroll
+    for (int i = 0; i < kTile / 64; ++i) {
+        const int c = s_w[i];
+        if (i < wave) off += c;
+        tot += c;
+    }
+    *total = tot;
+    __syncthreads();
+    return off + inc - v;
+}
+
+__device__ __forceinline__ uint64_t leaf_key(float lbe, int64_t leaf) {
+    return ((uint64_t)__float_as_uint(lbe) << 32) | (uint64_t)(uint32_t)leaf;
+}
+
+__device__ __forceinline__ unsigned long long block_min_u64(unsigned long long v, unsigned long long* s_tmp) {
+    for (int o = 32; o > 0; o >>= 1) {
+        unsigned long long other = __shfl_xor(v, o, 64);
+        v = other < v ? other : v;
+    }
+    const int wave = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) s_tmp[wave] = v;
+    __syncthreads();
+    unsigned long long r = s_tmp[0];
+    for (int i = 1; i < (int)(blockDim.x >> 6); ++i) r = s_tmp[i] < r ? s_tmp[i] : r;
+    __syncthreads();
+    return r;
+}
+
+// Contiguous share [lo, hi) of `total` work units for this block.
+__device__ __forceinline__ void block_range(int64_t total, int64_t& lo, int64_t& hi) {
+    lo = total * (int64_t)blockIdx.x / (int64_t)gridDim.x;
+    hi = total * ((int64_t)blockIdx.x + 1) / (int64_t)gridDim.x;
+}
+
+inline int grid_for(int64_t work, int block, int cap = 65536) {
+    int64_t g = (work + block - 1) / block;
+    if (g < 1) g = 1;
+    if (g > cap) g = cap;
+    return (int)g;
+}
+
+inline int w16_of(const IndexView& ix) { return (ix.wstride + 15) / 16; }
+
+inline int blocks_per_cu(size_t lds_bytes) {
+    int per_cu = (int)((160 * 1024) / (lds_bytes + 1024));
+    if (per_cu > 8) per_cu = 8;
+    if (per_cu < 1) per_cu = 1;
+    return per_cu;
+}
+
+}  // namespace
+}  // namespace hs
+
+#define HS_DISPATCH_W16(ix, KERNEL, ...)                                              \
+    switch (w16_of(ix)) {                                                            \
+        case 1: hipLaunchKernelGGL(KERNEL<1>, __VA_ARGS__); break;                   \
+        case 2: hipLaunchKernelGGL(KERNEL<2>, __VA_ARGS__); break;                   \
+        case 3: hipLaunchKernelGGL(KERNEL<3>, __VA_ARGS__); break;                   \
+        default: hipLaunchKernelGGL(KERNEL<4>, __VA_ARGS__); break;                  \
+    }

@@ -39,9 +39,10 @@ constexpr int kCtrRedo = 2;      // queries that need another round
 constexpr int kCtrNonFinite = 3; // queries with NaN / Inf
 constexpr int kCtrCand = 4;      // candidates appended by the filter
 constexpr int kCtrRefine = 5;    // work-distribution counter of the refine kernel
-constexpr int kCtrCandEnd = 6;   // smallest base of a candidate range that did not fit (UINT32_MAX if none):
-                                 // entries at or above it were never written
 constexpr int kNumCounters = 8;
+// The candidate list is split into kRegions regions with a counter each, so
+// that appends from different workgroups rarely hit the same address.
+constexpr int kRegions = 64;
 
 // Everything a kernel needs to know about an index.
 struct IndexView {
@@ -76,8 +77,10 @@ struct QueryWs {
     uint32_t* cand_q;     // [cand_cap] its query
     float* cand_lb;       // [cand_cap] its LB_SAX
     uint32_t* counters;   // [kNumCounters]
+    uint32_t* cand_cnt;   // [kRegions] entries reserved in each candidate region
+    uint32_t* cand_end;   // [kRegions] smallest base of a range that did not fit (UINT32_MAX if none)
     int64_t item_cap;
-    int64_t cand_cap;
+    int64_t cand_cap;     // entries per region
     int32_t P;
 };
 

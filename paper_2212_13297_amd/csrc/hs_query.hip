@@ -1,0 +1,401 @@
+// Query-side kernels around the scan (Hercules Sec. 3.3, Exact-kNN):
+//   init_counters  reset the per-call counters and candidate regions
+//   query_prep     query PAA / segment stats (FP64) and the LB_SAX table
+//   lb_eapca       LB_EAPCA of every (query, leaf)
+//   seed           step 1, approximate search: in the l_max leaves with the
+//                  smallest LB_EAPCA, refine the series with the smallest
+//                  LB_SAX; their k-th distance is the first BSF_k
+//   emit           step 2: (query, part) work items for the leaves whose
+//                  LB_EAPCA does not exceed BSF_k
+//   merge          per query: sort + dedupe the result pool, keep the top k,
+//                  tighten BSF_k, write the final (d, id) lists
+//   arm_redo       select the queries of the next fallback round
+#include "hs_device.h"
+
+namespace hs {
+namespace {
+
+__global__ void k_init_counters(QueryWs ws) {
+    const int t = threadIdx.x;
+    if (t < kNumCounters) ws.counters[t] = 0;
+    for (int r = t; r < kRegions; r += blockDim.x) {
+        ws.cand_cnt[r] = 0;
+        ws.cand_end[r] = 0xffffffffu;
+    }
+}
+
+__global__ void __launch_bounds__(256) k_query_prep(IndexView ix, const float* __restrict__ qin, QueryWs ws) {
+    __shared__ double s_paa[64];
+    __shared__ int s_bad;
+    const int q = blockIdx.x, t = threadIdx.x;
+    const float* src = qin + (int64_t)q * ix.n;
+    if (t == 0) s_bad = 0;
+    __syncthreads();
+    for (int j = t; j < ix.stride; j += blockDim.x) {
+        float v = j < ix.n ? src[j] : 0.0f;
+        if (!isfinite(v)) s_bad = 1;
+        ws.qrow[(int64_t)q * ix.stride + j] = v;
+    }
+    const int32_t l = ix.n / ix.w;
+    if (t < ix.w) {
+        const float* p = src + t * l;
+        double s = 0.0;
+        for (int j = 0; j < l; ++j) s += (double)p[j];
+        const double mu = s / l;
+        double ss = 0.0;
+        for (int j = 0; j < l; ++j) {
+            double d = (double)p[j] - mu;
+            ss += d * d;
+        }
+        s_paa[t] = mu;
+        ws.qstat[((int64_t)q * ix.w + t) * 2 + 0] = mu;
+        ws.qstat[((int64_t)q * ix.w + t) * 2 + 1] = sqrt(ss / l);
+    }
+    __syncthreads();
+    // LB_SAX table: (n/w) * distance^2 from the query's PAA value to each
+    // symbol's region, FP64, rounded down to float32
+    const double scale = (double)ix.n / ix.w;
+    for (int idx = t; idx < ix.w * kCard; idx += blockDim.x) {
+        const int i = idx / kCard, s = idx % kCard;
+        const double g = gap(s_paa[i], (double)ix.beta[s], (double)ix.beta[s + 1]);
+        ws.lut[(int64_t)q * ix.w * kCard + idx] = __double2float_rd(scale * g * g);
+    }
+    if (t == 0) {
+        ws.bsf[q] = kInfBits;
+        ws.pool_cnt[q] = 0;
+        ws.flags[q] = s_bad ? kFlagNonFinite : 0u;
+        ws.kept[q] = 0;
+        if (s_bad) atomicAdd(&ws.counters[kCtrNonFinite], 1u);
+    }
+    if (t < 8) ws.stats[(int64_t)q * 8 + t] = 0;
+}
+
+// LB_EAPCA^2 = sum_i l_i [gap(mu_q, [mu_min, mu_max])^2 + gap(sd_q, [sd_min, sd_max])^2]
+// in FP64, rounded down to float32.
+__global__ void __launch_bounds__(256) k_lb_eapca(IndexView ix, QueryWs ws) {
+    __shared__ double s_st[128];
+    const int q = blockIdx.y;
+    for (int j = threadIdx.x; j < 2 * ix.w; j += blockDim.x) s_st[j] = ws.qstat[(int64_t)q * ix.w * 2 + j];
+    __syncthreads();
+    const int64_t leaf = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (leaf >= ix.L) return;
+    const double l = (double)(ix.n / ix.w);
+    double acc = 0.0;
+    for (int i = 0; i < ix.w; ++i) {
+        const float4 e = ix.env[leaf * ix.w + i];
+        const double gm = gap(s_st[2 * i], (double)e.x, (double)e.y);
+        const double gs = gap(s_st[2 * i + 1], (double)e.z, (double)e.w);
+        acc += l * (gm * gm + gs * gs);
+    }
+    ws.lbe[(int64_t)q * ix.L + leaf] = __double2float_rd(acc);
+}
+
+// Step 1 (approximate search), one block per query.  The paper refines every
+// series of the L_max most promising leaves; here the same leaves are chosen
+// (smallest LB_EAPCA) but only their series with the smallest LB_SAX are
+// refined -- at least max(seed_rows, 2k) of them, cut at a histogram bin of
+// LB_SAX values.  The k best become the first pool entries and BSF_k.
+template <int W16>
+__global__ void __launch_bounds__(256) k_seed(IndexView ix, ScanParams sp, QueryWs ws) {
+    extern __shared__ float s_lut[];  // [w][256]
+    __shared__ unsigned long long s_top[HS_KMAX];
+    __shared__ unsigned long long s_res[kTile];
+    __shared__ uint32_t s_hits[kTile];
+    __shared__ uint32_t s_hist[2048];
+    __shared__ uint32_t s_leaves[kMaxSeedLeaves];
+    __shared__ unsigned long long s_tmp[4];
+    __shared__ int s_w[4];
+    __shared__ int s_nres, s_topn;
+    __shared__ float s_thr;
+    __shared__ uint32_t s_binlim;
+    __shared__ unsigned int s_ref, s_chunks;
+    const int q = blockIdx.x, t = threadIdx.x, sub = t & 15, grp = t >> 4;
+    const int k = sp.k, lm = sp.n_seed;
+    const int nchunks = ix.stride / kChunk;
+    for (int j = t; j < ix.w * kCard; j += blockDim.x) s_lut[j] = ws.lut[(int64_t)q * ix.w * kCard + j];
+    for (int j = t; j < 2048; j += blockDim.x) s_hist[j] = 0;
+    if (t == 0) {
+        s_nres = 0;
+        s_topn = 0;
+        s_thr = INFINITY;
+        s_ref = 0;
+        s_chunks = 0;
+    }
+    // the lm leaves with the smallest (LB_EAPCA, leaf id)
+    unsigned long long last = 0;
+    for (int r = 0; r < lm; ++r) {
+        unsigned long long best = ~0ull;
+        for (int64_t leaf = t; leaf < ix.L; leaf += blockDim.x) {
+            const unsigned long long key = leaf_key(ws.lbe[(int64_t)q * ix.L + leaf], leaf);
+            if ((r == 0 || key > last) && key < best) best = key;
+        }
+        best = block_min_u64(best, s_tmp);
+        last = best;
+        if (t == 0) s_leaves[r] = (uint32_t)(best & 0xffffffffu);
+    }
+    __syncthreads();
+    // histogram of LB_SAX over the seed leaves (bins: float bits >> 20)
+    int64_t rows = 0;
+    for (int li = 0; li < lm; ++li) {
+        const int64_t b = ix.leaf_start[s_leaves[li]], e = ix.leaf_start[s_leaves[li] + 1];
+        rows += e - b;
+        for (int64_t r = b + t; r < e; r += blockDim.x) {
+            uint4 v[W16];
+            load_word<W16>(ix.words + r * ix.wstride, v);
+            const float lb = lb_sax_word<W16>(v, s_lut, ix.w);
+            atomicAdd(&s_hist[min(__float_as_uint(lb) >> 20, 2047u)], 1u);
+        }
+    }
+    __syncthreads();
+    if (t == 0) {
+        const uint32_t want = (uint32_t)max(sp.seed_rows, 2 * k);
+        uint32_t cum = 0, lim = 2047;
+        for (uint32_t b = 0; b < 2048; ++b) {
+            cum += s_hist[b];
+            if (cum >= want) {
+                lim = b;
+                break;
+            }
+        }
+        s_binlim = lim;
+    }
+    __syncthreads();
+    const uint32_t lim = s_binlim;
+    unsigned my_chunks = 0, my_ref = 0;
+    for (int li = 0; li < lm; ++li) {
+        const int64_t b = ix.leaf_start[s_leaves[li]], e = ix.leaf_start[s_leaves[li] + 1];
+        for (int64_t tb = b; tb < e; tb += kTile) {
+            const int64_t r = tb + t;
+            bool pass = false;
+            if (r < e) {
+                uint4 v[W16];
+                load_word<W16>(ix.words + r * ix.wstride, v);
+                const float lb = lb_sax_word<W16>(v, s_lut, ix.w);
+                pass = (__float_as_uint(lb) >> 20) <= lim && (double)lb <= prune_limit(s_thr);
+            }
+            int nh;
+            const int off = block_exclusive_scan(pass ? 1 : 0, s_w, &nh);
+            if (pass) s_hits[off] = (uint32_t)(r - b);
+            __syncthreads();
+            const float thr = s_thr;
+            for (int h = grp; h < nh; h += kTile / 16) {
+                const int64_t pos = b + s_hits[h];
+                bool alive;
+                const float d = refine_row(ix.rows + pos * ix.stride + sub * 4,
+                                           ws.qrow + (int64_t)q * ix.stride + sub * 4, nchunks, thr, alive,
+                                           my_chunks);
+                if (sub == 0) {
+                    ++my_ref;
+                    if (alive)
+                        s_res[atomicAdd(&s_nres, 1)] = ((unsigned long long)__float_as_uint(d) << 32) | ix.ids[pos];
+                }
+            }
+            __syncthreads();
+            if (t == 0) {
+                int n = s_topn;
+                for (int i = 0; i < s_nres; ++i) topk_insert(s_top, n, k, s_res[i]);
+                s_topn = n;
+                s_nres = 0;
+                if (n == k) s_thr = bits_to_float((uint32_t)(s_top[k - 1] >> 32));
+            }
+            __syncthreads();
+        }
+    }
+    if (sub == 0) {
+        atomicAdd(&s_ref, my_ref);
+        atomicAdd(&s_chunks, my_chunks);
+    }
+    __syncthreads();
+    const int n = s_topn;
+    for (int j = t; j < n; j += blockDim.x) ws.pool[(int64_t)q * ws.P + j] = s_top[j];
+    if (t == 0) {
+        ws.pool_cnt[q] = (uint32_t)n;
+        if (n == k) ws.bsf[q] = (uint32_t)(s_top[k - 1] >> 32);
+        unsigned long long* st = ws.stats + (int64_t)q * 8;
+        st[1] += (unsigned long long)rows;
+        st[2] += s_ref;
+        st[3] += s_chunks;
+    }
+}
+
+// Step 2: one block per query; the (query, part) items of every leaf whose
+// LB_EAPCA does not exceed BSF_k, contiguous per query.  Also counts the
+// candidate leaves and picks the access path (eapca_th).
+__global__ void __launch_bounds__(256) k_emit(IndexView ix, ScanParams sp, int32_t redo_only, QueryWs ws) {
+    __shared__ int s_w[4];
+    __shared__ uint32_t s_base;
+    const int q = blockIdx.x, t = threadIdx.x;
+    const uint32_t f = ws.flags[q];
+    if (redo_only && !(f & kFlagInRound)) return;
+    const double thr = prune_limit(bits_to_float(ws.bsf[q]));
+    const float* lbe = ws.lbe + (int64_t)q * ix.L;
+    if (!redo_only) {
+        int kept = 0;
+        for (int64_t leaf = t; leaf < ix.L; leaf += blockDim.x) kept += (double)lbe[leaf] <= thr;
+        int tot;
+        block_exclusive_scan(kept, s_w, &tot);
+        if (t == 0) {
+            ws.kept[q] = (uint32_t)tot;
+            if (sp.eapca_th > 0.0f && (1.0 - (double)tot / (double)ix.L) < (double)sp.eapca_th)
+                ws.flags[q] = f | kFlagSkipSax;
+        }
+    }
+    int cnt = 0;
+    for (int64_t p = t; p < ix.parts; p += blockDim.x) cnt += (double)lbe[ix.part_leaf[p]] <= thr;
+    int total;
+    block_exclusive_scan(cnt, s_w, &total);
+    if (t == 0) s_base = total ? atomicAdd(&ws.counters[kCtrItems], (uint32_t)total) : 0u;
+    __syncthreads();
+    uint32_t base = s_base;
+    for (int64_t p0 = 0; p0 < ix.parts; p0 += blockDim.x) {
+        const int64_t p = p0 + t;
+        const bool c = p < ix.parts && (double)lbe[ix.part_leaf[p]] <= thr;
+        int tot;
+        const int off = block_exclusive_scan(c ? 1 : 0, s_w, &tot);
+        if (c && (int64_t)(base + off) < ws.item_cap) ws.items[base + off] = ((uint64_t)q << 32) | (uint32_t)p;
+        base += tot;
+    }
+}
+
+__global__ void __launch_bounds__(1024) k_merge(IndexView ix, ScanParams sp, int32_t redo_only, QueryWs ws,
+                                                int64_t* __restrict__ ids_out, float* __restrict__ d2_out,
+                                                hs_query_stats* __restrict__ stats_out) {
+    extern __shared__ unsigned long long s_keys[];  // [P]
+    __shared__ int s_u;
+    const int q = blockIdx.x, t = threadIdx.x;
+    if (redo_only && !(ws.flags[q] & kFlagInRound)) return;
+    const int k = sp.k;
+    uint32_t cnt = ws.pool_cnt[q];
+    if (cnt > (uint32_t)ws.P) cnt = ws.P;
+    int M = 1;
+    while (M < (int)cnt) M <<= 1;
+    for (int j = t; j < M; j += blockDim.x) s_keys[j] = j < (int)cnt ? ws.pool[(int64_t)q * ws.P + j] : ~0ull;
+    __syncthreads();
+    // bitonic sort, ascending
+    for (int size = 2; size <= M; size <<= 1) {
+        for (int stride = size >> 1; stride > 0; stride >>= 1) {
+            for (int i = t; i < M; i += blockDim.x) {
+                const int j = i ^ stride;
+                if (j > i) {
+                    const bool up = (i & size) == 0;
+                    const unsigned long long a = s_keys[i], c = s_keys[j];
+                    if ((a > c) == up) {
+                        s_keys[i] = c;
+                        s_keys[j] = a;
+                    }
+                }
+            }
+            __syncthreads();
+        }
+    }
+    if (t == 0) {
+        // drop duplicates (a series re-admitted in a later round), keep the first k
+        int u = 0;
+        unsigned long long prev = ~0ull;
+        for (int j = 0; j < (int)cnt && u < k; ++j) {
+            const unsigned long long key = s_keys[j];
+            if (u > 0 && key == prev) continue;
+            s_keys[u++] = key;
+            prev = key;
+        }
+        s_u = u;
+        const uint32_t f = ws.flags[q];
+        const bool again = (f & (kFlagOverflow | kFlagCandLost)) != 0;
+        uint32_t nf = f & ~(kFlagOverflow | kFlagCandLost);
+        if (again) {
+            nf |= kFlagRedo;
+            atomicAdd(&ws.counters[kCtrRedo], 1u);
+        }
+        ws.flags[q] = nf;
+        ws.pool_cnt[q] = (uint32_t)u;
+        if (u == k) atomicMin(&ws.bsf[q], (uint32_t)(s_keys[k - 1] >> 32));
+        if (sp.final_pass) ws.stats[(int64_t)q * 8 + 5] += 1;
+    }
+    __syncthreads();
+    const int u = s_u;
+    for (int j = t; j < u; j += blockDim.x) ws.pool[(int64_t)q * ws.P + j] = s_keys[j];
+    if (sp.final_pass) {
+        for (int j = t; j < k; j += blockDim.x) {
+            if (j < u) {
+                ids_out[(int64_t)q * k + j] = (int64_t)(s_keys[j] & 0xffffffffull);
+                d2_out[(int64_t)q * k + j] = bits_to_float((uint32_t)(s_keys[j] >> 32));
+            } else {
+                ids_out[(int64_t)q * k + j] = -1;
+                d2_out[(int64_t)q * k + j] = INFINITY;
+            }
+        }
+        if (stats_out && t == 0) {
+            const unsigned long long* st = ws.stats + (int64_t)q * 8;
+            hs_query_stats o;
+            o.leaves_kept = ws.kept[q];
+            o.rows_filtered = st[1];
+            o.rows_refined = st[2];
+            o.chunks_read = st[3];
+            o.path = (ws.flags[q] & kFlagSkipSax) ? 1 : 0;
+            o.rounds = st[5];
+            o.candidates = st[6];
+            o.reserved = 0;
+            stats_out[q] = o;
+        }
+    }
+}
+
+__global__ void k_reset_items(uint32_t* c) {
+    if (threadIdx.x == 0) {
+        c[kCtrItems] = 0;
+        c[kCtrWork] = 0;
+    }
+}
+
+__global__ void k_arm_redo(QueryWs ws, int32_t Q) {
+    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q == 0) {
+        ws.counters[kCtrItems] = 0;
+        ws.counters[kCtrWork] = 0;
+        ws.counters[kCtrRedo] = 0;
+    }
+    if (q >= Q) return;
+    uint32_t f = ws.flags[q];
+    f = (f & kFlagRedo) ? ((f & ~kFlagRedo) | kFlagInRound) : (f & ~kFlagInRound);
+    ws.flags[q] = f;
+}
+
+}  // namespace
+
+hipError_t launch_query_prep(const IndexView& ix, const float* q, int32_t Q, const QueryWs& ws, hipStream_t st) {
+    hipLaunchKernelGGL(k_init_counters, dim3(1), dim3(64), 0, st, ws);
+    hipLaunchKernelGGL(k_query_prep, dim3(Q), dim3(256), 0, st, ix, q, ws);
+    return hipGetLastError();
+}
+
+hipError_t launch_lb_eapca(const IndexView& ix, int32_t Q, const QueryWs& ws, hipStream_t st) {
+    hipLaunchKernelGGL(k_lb_eapca, dim3((unsigned)((ix.L + 255) / 256), Q), dim3(256), 0, st, ix, ws);
+    return hipGetLastError();
+}
+
+hipError_t launch_seed(const IndexView& ix, const ScanParams& sp, const QueryWs& ws, hipStream_t st) {
+    if (sp.n_seed <= 0) return hipSuccess;
+    const size_t lds = sizeof(float) * (size_t)ix.w * kCard;
+    HS_DISPATCH_W16(ix, k_seed, dim3(sp.Q), dim3(kTile), lds, st, ix, sp, ws);
+    return hipGetLastError();
+}
+
+hipError_t launch_emit(const IndexView& ix, const ScanParams& sp, bool redo_only, const QueryWs& ws,
+                       hipStream_t st) {
+    if (redo_only) {
+        hipLaunchKernelGGL(k_arm_redo, dim3((sp.Q + 255) / 256), dim3(256), 0, st, ws, sp.Q);
+    } else {
+        hipLaunchKernelGGL(k_reset_items, dim3(1), dim3(64), 0, st, ws.counters);
+    }
+    hipLaunchKernelGGL(k_emit, dim3(sp.Q), dim3(kTile), 0, st, ix, sp, redo_only ? 1 : 0, ws);
+    return hipGetLastError();
+}
+
+hipError_t launch_merge(const IndexView& ix, const ScanParams& sp, bool redo_only, const QueryWs& ws,
+                        int64_t* ids_out, float* d2_out, hs_query_stats* stats_out, hipStream_t st) {
+    hipLaunchKernelGGL(k_merge, dim3(sp.Q), dim3(1024), sizeof(unsigned long long) * ws.P, st, ix, sp,
+                       redo_only ? 1 : 0, ws, ids_out, d2_out, stats_out);
+    return hipGetLastError();
+}
+
+}  // namespace hs
