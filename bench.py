@@ -97,7 +97,7 @@ def main():
     log(f"warmup {args.warmup} steps")
     run(args.k, args.warmup)
     torch.cuda.synchronize()
-    hs.hs_profile_read(reset=True)
+    hs.profile_read_all(reset=True)
     hs.hs_profile_enable(True)
     log(f"timing {args.steps} steps, Q={Q}, k={args.k}")
     torch.cuda.synchronize()
@@ -106,21 +106,28 @@ def main():
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     hs.hs_profile_enable(False)
-    scan_ms, scan_launches = hs.hs_profile_read(reset=True)
+    prof = hs.profile_read_all(reset=True)
     ms_per_step = (t1 - t0) * 1000.0 / args.steps
     qps = Q / (ms_per_step / 1000.0)
-    log(f"{ms_per_step:.3f} ms/step, {qps:.0f} queries/s")
+    log(f"{ms_per_step:.3f} ms/step, {qps:.0f} queries/s; scan kernels {prof}")
 
     stats = {f: v.cpu().numpy().astype(np.int64) for f, v in st.items()}
+    # algorithmic bytes (the seed step's few thousand series per query are included)
     word_bytes = int(stats["rows_filtered"].sum()) * args.w
+    cand_bytes = int(stats["candidates"].sum()) * 12
     raw_bytes = int(stats["chunks_read"].sum()) * 64 * 4
-    scan_bytes_step = word_bytes + raw_bytes
-    launches_per_step = scan_launches / args.steps
-    avg_launch_ms = scan_ms / max(scan_launches, 1)
-    bytes_per_launch = scan_bytes_step / max(launches_per_step, 1e-9)
-    achieved = bytes_per_launch / (avg_launch_ms / 1000.0) / 1e9
+    kern = {}
+    for name, nbytes in (("filter", word_bytes + cand_bytes), ("refine", raw_bytes + cand_bytes)):
+        ms, launches = prof[name]
+        if launches:
+            avg = ms / launches
+            per_launch = nbytes / (launches / args.steps)
+            kern[name] = {"avg_launch_ms": round(avg, 4), "launches_per_step": launches / args.steps,
+                          "bytes_per_launch": int(per_launch), "GB_s": round(per_launch / (avg / 1e3) / 1e9, 2)}
+    dom = max(kern, key=lambda n: kern[n]["avg_launch_ms"] * kern[n]["launches_per_step"]) if kern else None
+    achieved = kern[dom]["GB_s"] if dom else 0.0
     env_bytes = Q * info.n_leaves * args.w * 16
-    path_bytes_step = scan_bytes_step + env_bytes + Q * args.k * 12
+    path_bytes_step = word_bytes + raw_bytes + env_bytes + Q * args.k * 12
 
     # k = 1 on the same batch
     run(1, max(1, args.warmup // 2))
@@ -190,8 +197,8 @@ def main():
                        "queries": int(nl)},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                     "kernel": "k_leaf_scan", "launches_per_step": launches_per_step,
-                     "avg_launch_ms": round(avg_launch_ms, 4), "bytes_per_launch": int(bytes_per_launch)},
+                     "kernel": f"k_{dom}" if dom else None, **(kern.get(dom, {}))},
+        "scan_kernels": kern,
         "algorithmic_bytes_per_step": {"words": word_bytes, "raw": raw_bytes, "envelopes": env_bytes,
                                        "total": path_bytes_step},
         "path_frac_of_hbm_peak": round(path_bytes_step / (ms_per_step / 1000.0) / 1e9 / HBM_PEAK_GBS, 4),

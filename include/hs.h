@@ -163,14 +163,19 @@ hs_status hs_knn_exact(hs_index* idx, const float* q_dev, int32_t Q, int32_t k, 
                        int64_t ws_bytes, int64_t* ids_dev, float* d2_dev, void* stats_dev,
                        void* stream);
 
-/* Diagnostics.  While enabled, hs_knn_exact brackets every leaf-scan kernel
- * launch (the LB_SAX filter + refinement, its dominant kernel) with HIP
- * events on its stream and, after its own final synchronisation, adds their
- * elapsed times to a process-wide accumulator.  Not meant for concurrent
- * calls from several threads. */
+/* Diagnostics.  While enabled, hs_knn_exact brackets every launch of its scan
+ * kernels (the dominant ones) with HIP events on its stream and, after its
+ * own final synchronisation, adds their elapsed times to process-wide
+ * accumulators, one per kind.  Not meant for concurrent calls from several
+ * threads. */
+#define HS_PROF_FILTER 0 /* LB_SAX filter (Sec. 3.3 step 3) */
+#define HS_PROF_REFINE 1 /* refinement of the candidates (step 4) */
+#define HS_PROF_FUSED 2  /* fused filter + refinement (overflow fallback) */
+#define HS_PROF_KINDS 3
 hs_status hs_profile_enable(int32_t on);
-/* Accumulated leaf-scan milliseconds and launch count; cleared if reset. */
-hs_status hs_profile_read(double* scan_ms, int64_t* scan_launches, int32_t reset);
+/* Accumulated milliseconds and launch count of one kind; cleared if reset.
+ * Errors: HS_EINVAL for an unknown kind. */
+hs_status hs_profile_read(int32_t kind, double* ms, int64_t* launches, int32_t reset);
 
 /* Release the host handle (does not free index_mem_dev). NULL is allowed. */
 hs_status hs_index_free(hs_index* idx);

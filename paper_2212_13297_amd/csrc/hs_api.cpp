@@ -49,45 +49,51 @@ thread_local std::string g_err;
 
 std::mutex g_prof_mu;
 bool g_prof_on = false;
-double g_prof_ms = 0.0;
-int64_t g_prof_launches = 0;
+double g_prof_ms[HS_PROF_KINDS] = {};
+int64_t g_prof_launches[HS_PROF_KINDS] = {};
 
-// Events around leaf-scan launches while profiling is on.
+// Events around the scan-kernel launches while profiling is on.
 struct ScanTimer {
-    std::vector<std::pair<hipEvent_t, hipEvent_t>> ev;
+    struct Rec {
+        hipEvent_t a, b;
+        int kind;
+    };
+    std::vector<Rec> ev;
     bool on = false;
     ScanTimer() {
         std::lock_guard<std::mutex> g(g_prof_mu);
         on = g_prof_on;
     }
-    hipError_t begin(hipStream_t st) {
+    hipError_t begin(hipStream_t st, int kind) {
         if (!on) return hipSuccess;
-        hipEvent_t a, b;
-        hipError_t e = hipEventCreate(&a);
+        Rec r{nullptr, nullptr, kind};
+        hipError_t e = hipEventCreate(&r.a);
         if (e != hipSuccess) return e;
-        e = hipEventCreate(&b);
-        if (e != hipSuccess) return e;
-        ev.emplace_back(a, b);
-        return hipEventRecord(a, st);
+        e = hipEventCreate(&r.b);
+        if (e != hipSuccess) {
+            (void)hipEventDestroy(r.a);
+            return e;
+        }
+        ev.push_back(r);
+        return hipEventRecord(r.a, st);
     }
-    hipError_t end(hipStream_t st) { return on ? hipEventRecord(ev.back().second, st) : hipSuccess; }
+    hipError_t end(hipStream_t st) { return on ? hipEventRecord(ev.back().b, st) : hipSuccess; }
     // after the stream has been synchronised
     void collect() {
-        double ms = 0.0;
-        for (auto& p : ev) {
+        if (!on) return;
+        std::lock_guard<std::mutex> g(g_prof_mu);
+        for (auto& r : ev) {
             float t = 0.0f;
-            if (hipEventElapsedTime(&t, p.first, p.second) == hipSuccess) ms += t;
-        }
-        if (on) {
-            std::lock_guard<std::mutex> g(g_prof_mu);
-            g_prof_ms += ms;
-            g_prof_launches += (int64_t)ev.size();
+            if (hipEventElapsedTime(&t, r.a, r.b) == hipSuccess) {
+                g_prof_ms[r.kind] += t;
+                g_prof_launches[r.kind] += 1;
+            }
         }
     }
     ~ScanTimer() {
-        for (auto& p : ev) {
-            (void)hipEventDestroy(p.first);
-            (void)hipEventDestroy(p.second);
+        for (auto& r : ev) {
+            (void)hipEventDestroy(r.a);
+            (void)hipEventDestroy(r.b);
         }
     }
 };
@@ -503,9 +509,10 @@ hs_status hs_knn_exact(hs_index* idx, const float* q_dev, int32_t Q, int32_t k, 
 
     // profiling brackets the two dominant kernels: the LB_SAX filter and the refinement
     ScanTimer timer;
-    auto timed = [&](hipError_t (*fn)(const IndexView&, const ScanParams&, const QueryWs&, int, hipStream_t))
+    auto timed = [&](int kind,
+                     hipError_t (*fn)(const IndexView&, const ScanParams&, const QueryWs&, int, hipStream_t))
         -> hipError_t {
-        hipError_t e = timer.begin(st);
+        hipError_t e = timer.begin(st, kind);
         if (e != hipSuccess) return e;
         e = fn(ix, sp, ws, idx->cus, st);
         if (e != hipSuccess) return e;
@@ -518,8 +525,8 @@ hs_status hs_knn_exact(hs_index* idx, const float* q_dev, int32_t Q, int32_t k, 
     HIP_TRY(launch_seed(ix, sp, ws, st));
     // step 2: candidate leaves; step 3: LB_SAX filter; step 4: refinement
     HIP_TRY(launch_emit(ix, sp, false, ws, st));
-    HIP_TRY(timed(launch_filter));
-    HIP_TRY(timed(launch_refine));
+    HIP_TRY(timed(HS_PROF_FILTER, launch_filter));
+    HIP_TRY(timed(HS_PROF_REFINE, launch_refine));
     sp.final_pass = 1;
     HIP_TRY(launch_merge(ix, sp, false, ws, ids_dev, d2_dev, stats_out, st));
 
@@ -537,7 +544,7 @@ hs_status hs_knn_exact(hs_index* idx, const float* q_dev, int32_t Q, int32_t k, 
         }
         if (round >= 64) return fail(HS_EHIP, "result pool still overflowing after %d rounds", round);
         HIP_TRY(launch_emit(ix, sp, true, ws, st));
-        HIP_TRY(timed(launch_leaf_scan));
+        HIP_TRY(timed(HS_PROF_FUSED, launch_leaf_scan));
         HIP_TRY(launch_merge(ix, sp, true, ws, ids_dev, d2_dev, stats_out, st));
     }
     return HS_OK;
@@ -549,13 +556,14 @@ hs_status hs_profile_enable(int32_t on) {
     return HS_OK;
 }
 
-hs_status hs_profile_read(double* scan_ms, int64_t* scan_launches, int32_t reset) {
+hs_status hs_profile_read(int32_t kind, double* ms, int64_t* launches, int32_t reset) {
+    if (kind < 0 || kind >= HS_PROF_KINDS) return fail(HS_EINVAL, "kind=%d out of range", kind);
     std::lock_guard<std::mutex> g(g_prof_mu);
-    if (scan_ms) *scan_ms = g_prof_ms;
-    if (scan_launches) *scan_launches = g_prof_launches;
+    if (ms) *ms = g_prof_ms[kind];
+    if (launches) *launches = g_prof_launches[kind];
     if (reset) {
-        g_prof_ms = 0.0;
-        g_prof_launches = 0;
+        g_prof_ms[kind] = 0.0;
+        g_prof_launches[kind] = 0;
     }
     return HS_OK;
 }

@@ -56,8 +56,8 @@ _SIGS = {
     "hs_last_error": (ctypes.c_char_p, []),
     "hs_breakpoints": (ctypes.c_int32, [ctypes.c_int32, _P]),
     "hs_profile_enable": (ctypes.c_int32, [ctypes.c_int32]),
-    "hs_profile_read": (ctypes.c_int32, [ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64),
-                                         ctypes.c_int32]),
+    "hs_profile_read": (ctypes.c_int32, [ctypes.c_int32, ctypes.POINTER(ctypes.c_double),
+                                         ctypes.POINTER(ctypes.c_int64), ctypes.c_int32]),
 }
 
 _LIB = None
@@ -147,11 +147,20 @@ def hs_profile_enable(on: bool) -> None:
     _check(load().hs_profile_enable(1 if on else 0))
 
 
-def hs_profile_read(reset: bool = False):
+HS_PROF_FILTER, HS_PROF_REFINE, HS_PROF_FUSED = 0, 1, 2
+PROF_KINDS = {"filter": HS_PROF_FILTER, "refine": HS_PROF_REFINE, "fused": HS_PROF_FUSED}
+
+
+def hs_profile_read(kind: int, reset: bool = False):
     ms = ctypes.c_double()
     n = ctypes.c_int64()
-    _check(load().hs_profile_read(ctypes.byref(ms), ctypes.byref(n), 1 if reset else 0))
+    _check(load().hs_profile_read(kind, ctypes.byref(ms), ctypes.byref(n), 1 if reset else 0))
     return ms.value, n.value
+
+
+def profile_read_all(reset: bool = False):
+    """{kind name: (milliseconds, launches)} for every scan-kernel kind."""
+    return {name: hs_profile_read(k, reset) for name, k in PROF_KINDS.items()}
 
 
 # ---------------------------------------------------------------- torch glue
