@@ -50,7 +50,7 @@ def main():
     ap.add_argument("--k", type=int, default=10)
     ap.add_argument("--w", type=int, default=16)
     ap.add_argument("--leaf", type=int, default=10_000)
-    ap.add_argument("--l-max", type=int, default=1)
+    ap.add_argument("--l-max", type=int, default=4)
     ap.add_argument("--seed-rows", type=int, default=256)
     ap.add_argument("--cpu-sample", type=int, default=24, help="queries timed on the CPU oracle")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -113,7 +113,7 @@ def main():
 
     stats = {f: v.cpu().numpy().astype(np.int64) for f, v in st.items()}
     # algorithmic bytes (the seed step's few thousand series per query are included)
-    word_bytes = int(stats["rows_filtered"].sum()) * args.w
+    word_bytes = int(stats["rows_filtered"].sum()) * args.w + int(stats["chunks_tested"].sum()) * args.w * 16
     cand_bytes = int(stats["candidates"].sum()) * 12
     raw_bytes = int(stats["chunks_read"].sum()) * 64 * 4
     kern = {}

@@ -142,7 +142,7 @@ typedef struct {
     uint64_t path;            /* 0 = LB_SAX path, 1 = skip-sequential (no LB_SAX) */
     uint64_t rounds;          /* refinement rounds (1 unless the candidate pool overflowed) */
     uint64_t candidates;      /* LB_SAX survivors put on the candidate list (two-stage path) */
-    uint64_t reserved;
+    uint64_t chunks_tested;   /* 64-series chunk envelopes whose LB_EAPCA was evaluated */
 } hs_query_stats;
 
 /*

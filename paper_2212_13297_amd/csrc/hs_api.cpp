@@ -31,6 +31,9 @@ struct hs_index {
     float* beta_dev = nullptr;          // library-owned
     int64_t* part_start_dev = nullptr;  // library-owned
     uint32_t* part_leaf_dev = nullptr;  // library-owned
+    int64_t* part_chunk_dev = nullptr;  // library-owned
+    int64_t* chunk_start_dev = nullptr; // library-owned
+    float4* cenv_dev = nullptr;         // library-owned
 };
 
 namespace {
@@ -40,6 +43,9 @@ void free_owned(hs_index* idx) {
     if (idx->beta_dev) (void)hipFree(idx->beta_dev);
     if (idx->part_start_dev) (void)hipFree(idx->part_start_dev);
     if (idx->part_leaf_dev) (void)hipFree(idx->part_leaf_dev);
+    if (idx->part_chunk_dev) (void)hipFree(idx->part_chunk_dev);
+    if (idx->chunk_start_dev) (void)hipFree(idx->chunk_start_dev);
+    if (idx->cenv_dev) (void)hipFree(idx->cenv_dev);
 }
 }  // namespace
 
@@ -175,13 +181,18 @@ struct Partition {
         leaves.emplace_back(b, e);
     }
 
-    void run(int64_t b, int64_t e, int depth) {
+    // Below the leaf level the same splits continue down to kChunkRows series
+    // (in_leaf): they only order the series inside their leaf, so that the
+    // leaf's fixed 64-series chunks hold similar series and get tight chunk
+    // envelopes.  Leaves are the nodes that first hold at most tau series.
+    void run(int64_t b, int64_t e, int depth, bool in_leaf) {
         while (true) {
             const int64_t cnt = e - b;
-            if (cnt <= tau) {
+            if (!in_leaf && cnt <= tau) {
                 add_leaf(b, e);
-                return;
+                in_leaf = true;
             }
+            if (in_leaf && cnt <= kChunkRows) return;
             std::vector<float> mn(2 * w, INFINITY), mx(2 * w, -INFINITY);
             for (int64_t r = b; r < e; ++r) {
                 const float2* s = st + r * w;
@@ -217,7 +228,7 @@ struct Partition {
                 }
             }
             if (cand < 0) {
-                add_leaf(b, e);
+                if (!in_leaf) add_leaf(b, e);
                 return;
             }
             // stable partition through the scratch arrays
@@ -233,12 +244,13 @@ struct Partition {
             std::memcpy(&id[b], &tmp_id[b], sizeof(uint32_t) * cnt);
             const int64_t mid = b + nl;
             if (depth < 6 && cnt > (1 << 20)) {
-                auto fut = std::async(std::launch::async, [this, b, mid, depth] { run(b, mid, depth + 1); });
-                run(mid, e, depth + 1);
+                auto fut = std::async(std::launch::async,
+                                      [this, b, mid, depth, in_leaf] { run(b, mid, depth + 1, in_leaf); });
+                run(mid, e, depth + 1, in_leaf);
                 fut.get();
                 return;
             }
-            run(b, mid, depth + 1);
+            run(b, mid, depth + 1, in_leaf);
             b = mid;  // tail iteration on the right child
             ++depth;
         }
@@ -267,6 +279,7 @@ int64_t ws_layout(const hs_index* idx, int32_t Q, int32_t k, QueryWs* ws, char* 
     QueryWs w{};
     carve(cur, (void**)&w.qrow, (int64_t)Q * ix.stride * 4);
     carve(cur, (void**)&w.qstat, (int64_t)Q * ix.w * 16);
+    carve(cur, (void**)&w.qst32, (int64_t)Q * ix.w * 16);
     carve(cur, (void**)&w.lut, (int64_t)Q * ix.w * kCard * 4);
     carve(cur, (void**)&w.lbe, (int64_t)Q * ix.L * 4);
     carve(cur, (void**)&w.bsf, (int64_t)Q * 4);
@@ -391,7 +404,7 @@ hs_status hs_build_summaries(const float* x_dev, int64_t N, const hs_params* par
     for (int64_t i = 0; i < N; ++i) id_host[i] = (uint32_t)i;
     part.st = st_host.data();
     part.id = id_host.data();
-    part.run(0, N, 0);
+    part.run(0, N, 0, false);
     std::sort(part.leaves.begin(), part.leaves.end());
     const int64_t L = (int64_t)part.leaves.size();
     std::vector<int64_t> leaf_start(L + 1);
@@ -405,18 +418,28 @@ hs_status hs_build_summaries(const float* x_dev, int64_t N, const hs_params* par
     idx->max_leaf = max_leaf;
     std::vector<float2>().swap(part.tmp_st);
     std::vector<float2>().swap(st_host);
-    // work items: every leaf cut into parts of at most kPartRows series
-    std::vector<int64_t> part_start;
+    // work items: every leaf cut into parts of at most kPartRows series;
+    // chunks: every leaf cut into kChunkRows-series chunks (parts start on a
+    // chunk boundary, so a part's chunks are consecutive)
+    std::vector<int64_t> part_start, chunk_start;
     std::vector<uint32_t> part_leaf;
+    std::vector<int64_t> part_chunk;
     for (int64_t i = 0; i < L; ++i) {
-        for (int64_t r = leaf_start[i]; r < leaf_start[i + 1]; r += kPartRows) {
-            part_start.push_back(r);
-            part_leaf.push_back((uint32_t)i);
+        for (int64_t r = leaf_start[i]; r < leaf_start[i + 1]; r += kChunkRows) {
+            if ((r - leaf_start[i]) % kPartRows == 0) {
+                part_start.push_back(r);
+                part_leaf.push_back((uint32_t)i);
+                part_chunk.push_back((int64_t)chunk_start.size());
+            }
+            chunk_start.push_back(r);
         }
     }
     const int64_t parts = (int64_t)part_leaf.size();
+    const int64_t chunks = (int64_t)chunk_start.size();
     part_start.push_back(N);
+    chunk_start.push_back(N);
     ix.parts = parts;
+    ix.chunks = chunks;
 
     // 3. leaf-ordered copy, words, envelopes
     float beta_host[kCard + 1];
@@ -428,6 +451,13 @@ hs_status hs_build_summaries(const float* x_dev, int64_t N, const hs_params* par
     BUILD_TRY(hipMalloc(&idx->beta_dev, sizeof(float) * (kCard + 1)));
     BUILD_TRY(hipMalloc(&idx->part_start_dev, sizeof(int64_t) * (parts + 1)));
     BUILD_TRY(hipMalloc(&idx->part_leaf_dev, sizeof(uint32_t) * parts));
+    BUILD_TRY(hipMalloc(&idx->part_chunk_dev, sizeof(int64_t) * parts));
+    BUILD_TRY(hipMalloc(&idx->chunk_start_dev, sizeof(int64_t) * (chunks + 1)));
+    BUILD_TRY(hipMalloc(&idx->cenv_dev, sizeof(float4) * chunks * p.w));
+    BUILD_TRY(hipMemcpyAsync(idx->part_chunk_dev, part_chunk.data(), sizeof(int64_t) * parts,
+                             hipMemcpyHostToDevice, st));
+    BUILD_TRY(hipMemcpyAsync(idx->chunk_start_dev, chunk_start.data(), sizeof(int64_t) * (chunks + 1),
+                             hipMemcpyHostToDevice, st));
     BUILD_TRY(hipMemcpyAsync(idx->leaf_start_dev, leaf_start.data(), sizeof(int64_t) * (L + 1),
                              hipMemcpyHostToDevice, st));
     BUILD_TRY(hipMemcpyAsync(idx->part_start_dev, part_start.data(), sizeof(int64_t) * (parts + 1),
@@ -441,9 +471,12 @@ hs_status hs_build_summaries(const float* x_dev, int64_t N, const hs_params* par
     ix.beta = idx->beta_dev;
     ix.part_start = idx->part_start_dev;
     ix.part_leaf = idx->part_leaf_dev;
+    ix.part_chunk = idx->part_chunk_dev;
+    ix.cenv = idx->cenv_dev;
     BUILD_TRY(launch_gather_rows(x_dev, ix.ids, N, p.n, ix.stride, (float*)ix.rows, st));
     BUILD_TRY(launch_words(ix, (uint8_t*)ix.words, st));
-    BUILD_TRY(launch_envelopes(ix, idx->env_dev, st));
+    BUILD_TRY(launch_envelopes(ix, idx->leaf_start_dev, L, idx->env_dev, st));
+    BUILD_TRY(launch_envelopes(ix, idx->chunk_start_dev, chunks, idx->cenv_dev, st));
     BUILD_TRY(hipStreamSynchronize(st));
     cleanup();
 #undef BUILD_TRY

@@ -73,10 +73,12 @@ __global__ void k_words(IndexView ix, uint8_t* __restrict__ words) {
     }
 }
 
-__global__ void __launch_bounds__(256) k_envelopes(IndexView ix, float4* __restrict__ env) {
+// One block per range [starts[i], starts[i + 1]) of stored series (a leaf or a chunk).
+__global__ void __launch_bounds__(256) k_envelopes(IndexView ix, const int64_t* __restrict__ starts,
+                                                   float4* __restrict__ env) {
     __shared__ double s_red[256][4];
     const int64_t leaf = blockIdx.x;
-    const int64_t b = ix.leaf_start[leaf], e = ix.leaf_start[leaf + 1];
+    const int64_t b = starts[leaf], e = starts[leaf + 1];
     const int32_t w = ix.w, l = ix.n / w;
     const int G = 256 / w;  // threads per segment
     const int t = threadIdx.x;
@@ -138,8 +140,9 @@ hipError_t launch_words(const IndexView& ix, uint8_t* words, hipStream_t st) {
     return hipGetLastError();
 }
 
-hipError_t launch_envelopes(const IndexView& ix, float4* env, hipStream_t st) {
-    hipLaunchKernelGGL(k_envelopes, dim3((unsigned)ix.L), dim3(256), 0, st, ix, env);
+hipError_t launch_envelopes(const IndexView& ix, const int64_t* starts, int64_t count, float4* env,
+                            hipStream_t st) {
+    if (count > 0) hipLaunchKernelGGL(k_envelopes, dim3((unsigned)count), dim3(256), 0, st, ix, starts, env);
     return hipGetLastError();
 }
 

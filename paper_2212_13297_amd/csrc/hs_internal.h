@@ -13,6 +13,7 @@ constexpr int kCard = 256;          // iSAX alphabet (8-bit symbols)
 constexpr int kChunk = 64;          // points per refinement chunk (early-abandon granularity)
 constexpr int kTile = 256;          // threads per scan / filter / refine workgroup
 constexpr int kPartRows = 2048;     // series per work item: leaves are cut into parts of at most this many
+constexpr int kChunkRows = 64;      // series per chunk envelope (one wavefront's rows in the filter)
 constexpr uint32_t kInfBits = 0x7f800000u;  // +inf as float bits
 constexpr int kMaxSeedLeaves = 64;  // l_max is clamped to this many leaves in the seed step
 
@@ -54,9 +55,12 @@ struct IndexView {
     const float* beta;         // [257] float32 breakpoints, beta[0] = -inf, beta[256] = +inf
     const int64_t* part_start; // [parts + 1] rows of part p: [part_start[p], part_start[p + 1])
     const uint32_t* part_leaf; // [parts] leaf of each part
+    const int64_t* part_chunk; // [parts] first chunk of each part
+    const float4* cenv;        // [chunks][w] chunk envelopes, same layout as env
     int64_t N;
     int64_t L;
     int64_t parts;
+    int64_t chunks;
     int32_t n, w, stride, wstride;
 };
 
@@ -64,6 +68,7 @@ struct IndexView {
 struct QueryWs {
     float* qrow;          // [Q][stride] zero-padded queries
     double* qstat;        // [Q][w][2] segment mean / std (FP64)
+    float4* qst32;        // [Q][w] float32 intervals holding them: (mu_lo, mu_hi, sd_lo, sd_hi)
     float* lut;           // [Q][w][256] LB_SAX table: (n/w) * gap^2, rounded down
     float* lbe;           // [Q][L] LB_EAPCA^2, rounded down
     uint32_t* bsf;        // [Q] float bits of the current BSF_k (monotone, atomicMin)
@@ -98,7 +103,8 @@ hipError_t launch_series_stats(const float* x, int64_t N, int32_t n, int32_t w, 
 hipError_t launch_gather_rows(const float* x, const uint32_t* perm, int64_t N, int32_t n, int32_t stride,
                               float* rows, hipStream_t st);
 hipError_t launch_words(const IndexView& ix, uint8_t* words, hipStream_t st);
-hipError_t launch_envelopes(const IndexView& ix, float4* env, hipStream_t st);
+hipError_t launch_envelopes(const IndexView& ix, const int64_t* starts, int64_t count, float4* env,
+                            hipStream_t st);
 
 hipError_t launch_query_prep(const IndexView& ix, const float* q, int32_t Q, const QueryWs& ws, hipStream_t st);
 hipError_t launch_lb_eapca(const IndexView& ix, int32_t Q, const QueryWs& ws, hipStream_t st);

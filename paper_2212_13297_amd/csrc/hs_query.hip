@@ -47,9 +47,12 @@ __global__ void __launch_bounds__(256) k_query_prep(IndexView ix, const float* _
             double d = (double)p[j] - mu;
             ss += d * d;
         }
+        const double sd = sqrt(ss / l);
         s_paa[t] = mu;
         ws.qstat[((int64_t)q * ix.w + t) * 2 + 0] = mu;
-        ws.qstat[((int64_t)q * ix.w + t) * 2 + 1] = sqrt(ss / l);
+        ws.qstat[((int64_t)q * ix.w + t) * 2 + 1] = sd;
+        ws.qst32[(int64_t)q * ix.w + t] =
+            make_float4(__double2float_rd(mu), __double2float_ru(mu), __double2float_rd(sd), __double2float_ru(sd));
     }
     __syncthreads();
     // LB_SAX table: (n/w) * distance^2 from the query's PAA value to each
@@ -334,7 +337,7 @@ __global__ void __launch_bounds__(1024) k_merge(IndexView ix, ScanParams sp, int
             o.path = (ws.flags[q] & kFlagSkipSax) ? 1 : 0;
             o.rounds = st[5];
             o.candidates = st[6];
-            o.reserved = 0;
+            o.chunks_tested = st[7];
             stats_out[q] = o;
         }
     }

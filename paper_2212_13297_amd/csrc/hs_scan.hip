@@ -26,17 +26,29 @@ __device__ __forceinline__ int64_t item_count(const QueryWs& ws) {
 
 // ------------------------------------------------------------------ filter
 
+// Each wavefront owns, at step j of an item, the 64 consecutive series
+// pb + 256 j + 64 wave + lane: exactly one chunk.  The chunk's LB_EAPCA
+// (float32 over outward-rounded intervals, a wave-wide sum, so the decision
+// is wave-uniform) is tested first; the iSAX words of a pruned chunk are
+// never read.
 template <int W16>
 __global__ void __launch_bounds__(256) k_filter(IndexView ix, ScanParams sp, QueryWs ws) {
     extern __shared__ float s_lut[];  // [w][256]
+    __shared__ float4 s_qst[64];      // query segment mean / std intervals
     __shared__ long long s_base;
     __shared__ int s_w[4];
-    const int t = threadIdx.x;
+    __shared__ unsigned int s_eval, s_tests;
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
     const int region = blockIdx.x % kRegions;
+    const float lseg = (float)(ix.n / ix.w);
     int64_t i0, i1;
     block_range(item_count(ws), i0, i1);
     int cur_q = -1;
-    unsigned long long acc_filt = 0, acc_cand = 0;  // thread 0: counters of cur_q
+    unsigned long long acc_filt = 0, acc_cand = 0, acc_tests = 0;  // thread 0: counters of cur_q
+    if (t == 0) {
+        s_eval = 0;
+        s_tests = 0;
+    }
     for (int64_t idx = i0; idx < i1; ++idx) {
         const uint64_t item = ws.items[idx];
         const int q = (int)(item >> 32);
@@ -45,20 +57,52 @@ __global__ void __launch_bounds__(256) k_filter(IndexView ix, ScanParams sp, Que
             if (t == 0 && cur_q >= 0) {
                 atomicAdd(&ws.stats[(int64_t)cur_q * 8 + 1], acc_filt);
                 atomicAdd(&ws.stats[(int64_t)cur_q * 8 + 6], acc_cand);
+                atomicAdd(&ws.stats[(int64_t)cur_q * 8 + 7], acc_tests);
             }
-            acc_filt = acc_cand = 0;
+            acc_filt = acc_cand = acc_tests = 0;
             for (int j = t; j < ix.w * kCard; j += blockDim.x) s_lut[j] = ws.lut[(int64_t)q * ix.w * kCard + j];
+            if (t < ix.w) s_qst[t] = ws.qst32[(int64_t)q * ix.w + t];
             cur_q = q;
             __syncthreads();
         }
         const bool skip = (ws.flags[q] & kFlagSkipSax) != 0;
         const double thr = prune_limit(bits_to_float(ws.bsf[q]));
         const int64_t pb = ix.part_start[p], pe = ix.part_start[p + 1];
+        uint32_t live = skip ? 0xffu : 0u;
+        unsigned my_eval = 0, my_tests = 0;
+        if (!skip) {
+            const int64_t c0 = ix.part_chunk[p];
+#pragma unroll
+            for (int j = 0; j < kRowsPerThread; ++j) {
+                const int64_t r0 = pb + j * kTile + wave * kChunkRows;
+                if (r0 < pe) {
+                    float term = 0.0f;
+                    if (lane < ix.w) {
+                        const float4 e = ix.cenv[(c0 + j * (kTile / kChunkRows) + wave) * ix.w + lane];
+                        const float4 s = s_qst[lane];
+                        const float gm = fmaxf(0.0f, fmaxf(e.x - s.y, s.x - e.y));
+                        const float gs = fmaxf(0.0f, fmaxf(e.z - s.w, s.z - e.w));
+                        term = lseg * (gm * gm + gs * gs);
+                    }
+#pragma unroll
+                    for (int o = 32; o > 0; o >>= 1) term += __shfl_xor(term, o, 64);
+                    ++my_tests;
+                    if ((double)term <= thr) {
+                        live |= 1u << j;
+                        my_eval += (unsigned)min((int64_t)kChunkRows, pe - r0);
+                    }
+                }
+            }
+            if (lane == 0) {
+                atomicAdd(&s_eval, my_eval);
+                atomicAdd(&s_tests, my_tests);
+            }
+        }
         uint4 v[kRowsPerThread][W16];
 #pragma unroll
         for (int j = 0; j < kRowsPerThread; ++j) {
             const int64_t r = pb + t + j * kTile;
-            if (!skip && r < pe) load_word<W16>(ix.words + r * ix.wstride, v[j]);
+            if (!skip && ((live >> j) & 1u) && r < pe) load_word<W16>(ix.words + r * ix.wstride, v[j]);
         }
         float lbv[kRowsPerThread];
         uint32_t mask = 0;
@@ -66,7 +110,7 @@ __global__ void __launch_bounds__(256) k_filter(IndexView ix, ScanParams sp, Que
         for (int j = 0; j < kRowsPerThread; ++j) {
             const int64_t r = pb + t + j * kTile;
             lbv[j] = 0.0f;
-            if (r < pe) {
+            if (((live >> j) & 1u) && r < pe) {
                 if (!skip) lbv[j] = lb_sax_word<W16>(v[j], s_lut, ix.w);
                 if ((double)lbv[j] <= thr) mask |= 1u << j;
             }
@@ -95,7 +139,11 @@ __global__ void __launch_bounds__(256) k_filter(IndexView ix, ScanParams sp, Que
                 }
             }
             s_base = base;
-            if (!skip) acc_filt += (unsigned long long)(pe - pb);
+            // s_eval / s_tests were complete at the scan's barriers
+            acc_filt += s_eval;
+            acc_tests += s_tests;
+            s_eval = 0;
+            s_tests = 0;
         }
         __syncthreads();
         const long long base = s_base;
@@ -117,6 +165,7 @@ __global__ void __launch_bounds__(256) k_filter(IndexView ix, ScanParams sp, Que
     if (t == 0 && cur_q >= 0) {
         atomicAdd(&ws.stats[(int64_t)cur_q * 8 + 1], acc_filt);
         atomicAdd(&ws.stats[(int64_t)cur_q * 8 + 6], acc_cand);
+        atomicAdd(&ws.stats[(int64_t)cur_q * 8 + 7], acc_tests);
     }
 }
 

@@ -38,10 +38,11 @@ class hs_index_info(ctypes.Structure):
 class hs_query_stats(ctypes.Structure):
     _fields_ = [("leaves_kept", ctypes.c_uint64), ("rows_filtered", ctypes.c_uint64),
                 ("rows_refined", ctypes.c_uint64), ("chunks_read", ctypes.c_uint64), ("path", ctypes.c_uint64),
-                ("rounds", ctypes.c_uint64), ("candidates", ctypes.c_uint64), ("reserved", ctypes.c_uint64)]
+                ("rounds", ctypes.c_uint64), ("candidates", ctypes.c_uint64), ("chunks_tested", ctypes.c_uint64)]
 
 
-STATS_FIELDS = ["leaves_kept", "rows_filtered", "rows_refined", "chunks_read", "path", "rounds", "candidates"]
+STATS_FIELDS = ["leaves_kept", "rows_filtered", "rows_refined", "chunks_read", "path", "rounds", "candidates",
+                "chunks_tested"]
 
 _P = ctypes.c_void_p
 _SIGS = {
