@@ -89,6 +89,7 @@ typedef struct {
     int64_t n_leaves;    /* L */
     int64_t max_leaf;    /* largest leaf (series) */
     int64_t index_bytes; /* device bytes the index occupies */
+    int64_t n_chunks;    /* 64-series chunks (each leaf cut from its first series) */
 } hs_index_info;
 
 /*
@@ -126,6 +127,15 @@ hs_status hs_get_info(const hs_index* idx, hs_index_info* out);
  *             segment (Sec. 3.1 synopsis), rounded outward.
  * Either pointer may be NULL.  Errors: HS_EINVAL, HS_EHIP. */
 hs_status hs_get_leaves(const hs_index* idx, int64_t* leaf_start, float* env);
+
+/* Copy the chunk table and the chunk envelopes to host memory (synchronous).
+ * Inside a leaf the series are ordered by further mean/std midpoint splits
+ * down to 64 series (Sec. 3.1 splitting rule, below the leaf level), and each
+ * leaf is cut into consecutive chunks of 64 series from its first one.
+ * chunk_start: int64 [n_chunks + 1]; cenv: float32 [n_chunks][w][4], the
+ * chunk's (mu_min, mu_max, sd_min, sd_max) per segment, rounded outward.
+ * Either pointer may be NULL.  Errors: HS_EINVAL, HS_EHIP. */
+hs_status hs_get_chunks(const hs_index* idx, int64_t* chunk_start, float* cenv);
 
 /* Device bytes of query workspace hs_knn_exact needs for Q queries and k. */
 hs_status hs_query_workspace_bytes(const hs_index* idx, int32_t Q, int32_t k, int64_t* bytes);

@@ -494,6 +494,7 @@ hs_status hs_get_info(const hs_index* idx, hs_index_info* out) {
     out->n_leaves = idx->view.L;
     out->max_leaf = idx->max_leaf;
     out->index_bytes = idx->index_bytes;
+    out->n_chunks = idx->view.chunks;
     return HS_OK;
 }
 
@@ -503,6 +504,17 @@ hs_status hs_get_leaves(const hs_index* idx, int64_t* leaf_start, float* env) {
         HIP_TRY(hipMemcpy(leaf_start, idx->leaf_start_dev, sizeof(int64_t) * (idx->view.L + 1), hipMemcpyDeviceToHost));
     if (env)
         HIP_TRY(hipMemcpy(env, idx->env_dev, sizeof(float4) * idx->view.L * idx->view.w, hipMemcpyDeviceToHost));
+    return HS_OK;
+}
+
+hs_status hs_get_chunks(const hs_index* idx, int64_t* chunk_start, float* cenv) {
+    if (!idx) return fail(HS_EINVAL, "idx is NULL");
+    if (chunk_start)
+        HIP_TRY(hipMemcpy(chunk_start, idx->chunk_start_dev, sizeof(int64_t) * (idx->view.chunks + 1),
+                          hipMemcpyDeviceToHost));
+    if (cenv)
+        HIP_TRY(hipMemcpy(cenv, idx->cenv_dev, sizeof(float4) * idx->view.chunks * idx->view.w,
+                          hipMemcpyDeviceToHost));
     return HS_OK;
 }
 

@@ -32,7 +32,7 @@ class hs_params(ctypes.Structure):
 class hs_index_info(ctypes.Structure):
     _fields_ = [("n_series", ctypes.c_int64), ("n", ctypes.c_int32), ("w", ctypes.c_int32),
                 ("row_stride", ctypes.c_int32), ("word_stride", ctypes.c_int32), ("n_leaves", ctypes.c_int64),
-                ("max_leaf", ctypes.c_int64), ("index_bytes", ctypes.c_int64)]
+                ("max_leaf", ctypes.c_int64), ("index_bytes", ctypes.c_int64), ("n_chunks", ctypes.c_int64)]
 
 
 class hs_query_stats(ctypes.Structure):
@@ -51,6 +51,7 @@ _SIGS = {
                                             ctypes.POINTER(_P)]),
     "hs_get_info": (ctypes.c_int32, [_P, ctypes.POINTER(hs_index_info)]),
     "hs_get_leaves": (ctypes.c_int32, [_P, _P, _P]),
+    "hs_get_chunks": (ctypes.c_int32, [_P, _P, _P]),
     "hs_query_workspace_bytes": (ctypes.c_int32, [_P, ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(ctypes.c_int64)]),
     "hs_knn_exact": (ctypes.c_int32, [_P, _P, ctypes.c_int32, ctypes.c_int32, _P, ctypes.c_int64, _P, _P, _P, _P]),
     "hs_index_free": (ctypes.c_int32, [_P]),
@@ -116,6 +117,14 @@ def hs_get_leaves(h, info: hs_index_info):
     env = np.empty((info.n_leaves, info.w, 4), dtype=np.float32)
     _check(load().hs_get_leaves(h, ls.ctypes.data, env.ctypes.data))
     return ls, env
+
+
+def hs_get_chunks(h, info: hs_index_info):
+    import numpy as np
+    cs = np.empty(info.n_chunks + 1, dtype=np.int64)
+    cenv = np.empty((info.n_chunks, info.w, 4), dtype=np.float32)
+    _check(load().hs_get_chunks(h, cs.ctypes.data, cenv.ctypes.data))
+    return cs, cenv
 
 
 def hs_query_workspace_bytes(h, Q: int, k: int) -> int:

@@ -65,8 +65,17 @@ def test_build_summaries_against_oracle():
     assert np.all(rows[:, n:] == 0)
     sizes = np.diff(ls)
     assert sizes.max() <= tau
-    for a, b in zip(ls[:-1], ls[1:]):
-        assert np.all(np.diff(ids[a:b]) > 0)     # stable partition: ids ascending in a leaf
+    # chunks: each leaf cut into 64-series chunks from its first series; the
+    # chunk envelopes contain their members' FP64 statistics
+    from paper_2212_13297_amd import hs
+    cs, cenv = hs.hs_get_chunks(idx.h, info)
+    expect = np.concatenate([np.arange(a, b, 64) for a, b in zip(ls[:-1], ls[1:])] + [[N]])
+    assert np.array_equal(cs, expect)
+    mu_c, sd_c = S.segment_stats(x[ids], S.equal_segmentation(n, w))
+    for i, (a, b) in enumerate(zip(cs[:-1], cs[1:])):
+        e = cenv[i].astype(np.float64)
+        assert np.all(mu_c[a:b] >= e[:, 0]) and np.all(mu_c[a:b] <= e[:, 1])
+        assert np.all(sd_c[a:b] >= e[:, 2]) and np.all(sd_c[a:b] <= e[:, 3])
     # iSAX words: equal to the oracle's except where the PAA lies within 1e-6 of a breakpoint
     beta = S.breakpoints(256)
     paa = S.paa(x[ids], w)
