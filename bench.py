@@ -148,7 +148,7 @@ def main():
         idx.knn(qi, args.k)
         torch.cuda.synchronize()
         lat.append((time.perf_counter() - a) * 1000.0)
-    lat = np.asarray(lat)
+    lat = np.asarray(lat if lat else [float("nan")])
     log(f"single-query latency p50 {np.percentile(lat, 50):.3f} ms p99 {np.percentile(lat, 99):.3f} ms")
 
     cpu = None
