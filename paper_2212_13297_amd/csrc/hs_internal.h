@@ -43,7 +43,7 @@ constexpr int kCtrRefine = 5;    // work-distribution counter of the refine kern
 constexpr int kNumCounters = 8;
 // The candidate list is split into kRegions regions with a counter each, so
 // that appends from different workgroups rarely hit the same address.
-constexpr int kRegions = 64;
+constexpr int kRegions = 256;
 
 // Everything a kernel needs to know about an index.
 struct IndexView {
