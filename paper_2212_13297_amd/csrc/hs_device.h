@@ -187,15 +187,32 @@ inline int grid_for(int64_t work, int block, int cap = 65536) {
 
 inline int w16_of(const IndexView& ix) { return (ix.wstride + 15) / 16; }
 
-inline int blocks_per_cu(size_t lds_bytes) {
-    int per_cu = (int)((160 * 1024) / (lds_bytes + 1024));
-    if (per_cu > 8) per_cu = 8;
-    if (per_cu < 1) per_cu = 1;
-    return per_cu;
+// Grid of a persistent kernel: as many workgroups as can be resident at once
+// (occupancy from the runtime for this kernel, block size and dynamic LDS),
+// so that static work ranges all run concurrently.
+template <typename K>
+inline int resident_grid(K kernel, int block, size_t dyn_lds, int cus) {
+    int per_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, block, dyn_lds) != hipSuccess || per_cu < 1)
+        per_cu = 1;
+    return cus * per_cu;
 }
 
 }  // namespace
 }  // namespace hs
+
+// Persistent launch of KERNEL<W16> with a resident grid of kTile-thread workgroups.
+#define HS_LAUNCH_RESIDENT(ix, KERNEL, lds, cus, st, ...)                                                   \
+    switch (w16_of(ix)) {                                                                                  \
+        case 1: hipLaunchKernelGGL(KERNEL<1>, dim3(resident_grid(KERNEL<1>, kTile, lds, cus)), dim3(kTile), \
+                                   lds, st, __VA_ARGS__); break;                                           \
+        case 2: hipLaunchKernelGGL(KERNEL<2>, dim3(resident_grid(KERNEL<2>, kTile, lds, cus)), dim3(kTile), \
+                                   lds, st, __VA_ARGS__); break;                                           \
+        case 3: hipLaunchKernelGGL(KERNEL<3>, dim3(resident_grid(KERNEL<3>, kTile, lds, cus)), dim3(kTile), \
+                                   lds, st, __VA_ARGS__); break;                                           \
+        default: hipLaunchKernelGGL(KERNEL<4>, dim3(resident_grid(KERNEL<4>, kTile, lds, cus)), dim3(kTile),\
+                                    lds, st, __VA_ARGS__); break;                                          \
+    }
 
 #define HS_DISPATCH_W16(ix, KERNEL, ...)                                              \
     switch (w16_of(ix)) {                                                            \

@@ -334,13 +334,14 @@ __global__ void __launch_bounds__(256) k_refine(IndexView ix, ScanParams sp, Que
 hipError_t launch_filter(const IndexView& ix, const ScanParams& sp, const QueryWs& ws, int device_cus,
                          hipStream_t st) {
     const size_t lds = sizeof(float) * (size_t)ix.w * kCard;
-    HS_DISPATCH_W16(ix, k_filter, dim3(device_cus * blocks_per_cu(lds + 1024)), dim3(kTile), lds, st, ix, sp, ws);
+    HS_LAUNCH_RESIDENT(ix, k_filter, lds, device_cus, st, ix, sp, ws);
     return hipGetLastError();
 }
 
 hipError_t launch_refine(const IndexView& ix, const ScanParams& sp, const QueryWs& ws, int device_cus,
                          hipStream_t st) {
-    hipLaunchKernelGGL(k_refine, dim3(device_cus * 8), dim3(kTile), 0, st, ix, sp, ws);
+    hipLaunchKernelGGL(k_refine, dim3(resident_grid(k_refine, kTile, 0, device_cus)), dim3(kTile), 0, st, ix, sp,
+                       ws);
     return hipGetLastError();
 }
 

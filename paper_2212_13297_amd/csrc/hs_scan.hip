@@ -120,8 +120,7 @@ __global__ void __launch_bounds__(256) k_leaf_scan(IndexView ix, ScanParams sp, 
 hipError_t launch_leaf_scan(const IndexView& ix, const ScanParams& sp, const QueryWs& ws, int device_cus,
                             hipStream_t st) {
     const size_t lds = sizeof(float) * ((size_t)ix.stride + (size_t)ix.w * kCard);
-    HS_DISPATCH_W16(ix, k_leaf_scan, dim3(device_cus * blocks_per_cu(lds + sizeof(ScanShared))), dim3(kTile), lds,
-                    st, ix, sp, ws);
+    HS_LAUNCH_RESIDENT(ix, k_leaf_scan, lds, device_cus, st, ix, sp, ws);
     return hipGetLastError();
 }
 
