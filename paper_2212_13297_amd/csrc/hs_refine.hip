@@ -1,0 +1,194 @@
+// Refinement of the candidate list (Hercules Sec. 3.3, step 4): the exact
+// float32 squared distance with early abandoning for every candidate, first
+// re-checked against the current BSF_k; per-wavefront top-k, BSF_k published
+// with atomicMin, results appended to the per-query pool.
+//
+// Every wavefront owns a contiguous range of the candidate list (regions are
+// ordered by query, so a range holds long runs of one query) and never waits
+// for another wavefront: the metadata of its next 16 candidates is loaded
+// while the current ones are refined, each 16-lane group refines two series
+// at a time (their next two 64-point chunks loaded together), and the
+// admitted results reach lane 0 by shuffles; lane 0 alone keeps the
+// wavefront's top-k in LDS.
+#include "hs_device.h"
+
+namespace hs {
+namespace {
+
+constexpr int kStep = 16;  // candidates per wavefront step: 4 groups x 4
+
+struct Meta {
+    int q;
+    uint32_t pos;
+    float lb;
+};
+
+// Candidate c of the flattened region list; lanes 0..15 call this for c = base + lane.
+__device__ __forceinline__ Meta load_meta(const QueryWs& ws, const long long* s_start, long long c, long long cend) {
+    Meta m{-1, 0u, 0.0f};
+    if (c < cend) {
+        int lo = 0, hi = kRegions;
+        while (hi - lo > 1) {
+            const int mid = (lo + hi) >> 1;
+            if (s_start[mid] <= c) lo = mid; else hi = mid;
+        }
+        const int64_t slot = (int64_t)lo * ws.cand_cap + (c - s_start[lo]);
+        m.q = (int)ws.cand_q[slot];
+        m.pos = ws.cand_pos[slot];
+        m.lb = ws.cand_lb[slot];
+    }
+    return m;
+}
+
+__global__ void __launch_bounds__(256) k_refine(IndexView ix, ScanParams sp, QueryWs ws) {
+    __shared__ unsigned long long s_top[kTile / 64][HS_KMAX];
+    __shared__ long long s_start[kRegions + 1];
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6, sub = t & 15, grp = (t >> 4) & 3;
+    const int gbase = lane & ~15;
+    const int k = sp.k;
+    const int nchunks = ix.stride / kChunk;
+    if (t == 0) {
+        // every entry of a region below min(counter, first range that did not fit) was written
+        long long acc = 0;
+        for (int r = 0; r < kRegions; ++r) {
+            s_start[r] = acc;
+            acc += min(min((long long)ws.cand_cnt[r], (long long)ws.cand_end[r]), (long long)ws.cand_cap);
+        }
+        s_start[kRegions] = acc;
+    }
+    __syncthreads();
+    const long long T = s_start[kRegions];
+    const long long gw = (long long)blockIdx.x * (kTile / 64) + wave, GW = (long long)gridDim.x * (kTile / 64);
+    const long long cbeg = T * gw / GW, cend = T * (gw + 1) / GW;
+    unsigned long long* top = s_top[wave];
+
+    // wavefront state, uniform: the query of the top-k and its k-th distance
+    int cur_q = -1;
+    float lk = INFINITY;
+    int topn = 0;                                     // lane 0
+    int st_q = -1;                                    // lane 0: counters of st_q
+    unsigned long long st_ref = 0, st_ch = 0;
+
+    Meta m = lane < kStep ? load_meta(ws, s_start, cbeg + lane, cend) : Meta{-1, 0u, 0.0f};
+    float mb = m.q >= 0 ? bits_to_float(load_relaxed(&ws.bsf[m.q])) : 0.0f;
+    for (long long cb = cbeg; cb < cend; cb += kStep) {
+        // next step's metadata in flight while this step is refined
+        const Meta nm = lane < kStep ? load_meta(ws, s_start, cb + kStep + lane, cend) : Meta{-1, 0u, 0.0f};
+
+        unsigned long long res[4];  // admitted keys of this group (group-uniform), ~0 = none
+        int resq[4];
+        unsigned chs[4];            // chunks read per candidate (0: not refined)
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            int q[2];
+            uint32_t pos[2];
+            float thr[2], d[2];
+            bool alive[2], refined[2];
+            unsigned ch[2] = {0u, 0u};
+#pragma unroll
+            for (int j = 0; j < 2; ++j) {
+                const int src = grp * 4 + 2 * h + j;
+                q[j] = __shfl(m.q, src, 64);
+                pos[j] = __shfl(m.pos, src, 64);
+                const float lb = __shfl(m.lb, src, 64);
+                thr[j] = __shfl(mb, src, 64);
+                if (q[j] == cur_q) thr[j] = fminf(thr[j], lk);
+                refined[j] = q[j] >= 0 && (double)lb <= prune_limit(thr[j]);
+                alive[j] = refined[j];
+                d[j] = 0.0f;
+            }
+            for (int c = 0; c < nchunks; c += 2) {
+                const bool two = c + 1 < nchunks;
+                float4 x0[2], x1[2];
+#pragma unroll
+                for (int j = 0; j < 2; ++j) {
+                    if (alive[j]) {
+                        const float* xr = ix.rows + (int64_t)pos[j] * ix.stride + sub * 4 + c * kChunk;
+                        x0[j] = *reinterpret_cast<const float4*>(xr);
+                        x1[j] = two ? *reinterpret_cast<const float4*>(xr + kChunk) : make_float4(0.f, 0.f, 0.f, 0.f);
+                    }
+                }
+#pragma unroll
+                for (int j = 0; j < 2; ++j) {
+                    if (alive[j]) {
+                        const float* qr = ws.qrow + (int64_t)q[j] * ix.stride + sub * 4 + c * kChunk;
+                        d[j] += chunk_partial(*reinterpret_cast<const float4*>(qr), x0[j]);
+                        if (two) d[j] += chunk_partial(*reinterpret_cast<const float4*>(qr + kChunk), x1[j]);
+                        ch[j] += two ? 2u : 1u;
+                        if (d[j] > thr[j]) alive[j] = false;
+                    }
+                }
+            }
+#pragma unroll
+            for (int j = 0; j < 2; ++j) {
+                chs[2 * h + j] = refined[j] ? ch[j] : 0u;
+                res[2 * h + j] = (refined[j] && alive[j])
+                                     ? (((unsigned long long)__float_as_uint(d[j]) << 32) | ix.ids[pos[j]])
+                                     : ~0ull;
+                resq[2 * h + j] = q[j];
+            }
+        }
+
+        // lane 0 takes the 4 groups' results and counters one by one
+        int new_q = cur_q;
+        float new_lk = lk;
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+            const unsigned long long key = __shfl(res[i & 3], (i >> 2) * 16, 64);
+            const int kq = __shfl(resq[i & 3], (i >> 2) * 16, 64);
+            const unsigned kch = __shfl(chs[i & 3], (i >> 2) * 16, 64);
+            if (lane == 0) {
+                if (key != ~0ull) {
+                    if (kq != new_q) {
+                        flush_topk(ws, new_q, k, top, topn);
+                        new_q = kq;
+                        topn = 0;
+                    }
+                    topk_insert(top, topn, k, key);
+                }
+                if (kch) {  // counters, one update per change of query
+                    if (kq != st_q) {
+                        if (st_q >= 0) {
+                            atomicAdd(&ws.stats[(int64_t)st_q * 8 + 2], st_ref);
+                            atomicAdd(&ws.stats[(int64_t)st_q * 8 + 3], st_ch);
+                        }
+                        st_q = kq;
+                        st_ref = st_ch = 0;
+                    }
+                    st_ref += 1;
+                    st_ch += kch;
+                }
+            }
+        }
+        if (lane == 0) {
+            new_lk = INFINITY;
+            if (new_q >= 0 && topn == k) {
+                const uint32_t kb = (uint32_t)(top[k - 1] >> 32);
+                new_lk = bits_to_float(kb);
+                if (new_lk < bits_to_float(load_relaxed(&ws.bsf[new_q]))) atomicMin(&ws.bsf[new_q], kb);
+            }
+        }
+        cur_q = __shfl(new_q, 0, 64);
+        lk = __shfl(new_lk, 0, 64);
+        m = nm;
+        mb = m.q >= 0 ? bits_to_float(load_relaxed(&ws.bsf[m.q])) : 0.0f;
+    }
+    if (lane == 0) {
+        flush_topk(ws, cur_q, k, top, topn);
+        if (st_q >= 0) {
+            atomicAdd(&ws.stats[(int64_t)st_q * 8 + 2], st_ref);
+            atomicAdd(&ws.stats[(int64_t)st_q * 8 + 3], st_ch);
+        }
+    }
+}
+
+}  // namespace
+
+hipError_t launch_refine(const IndexView& ix, const ScanParams& sp, const QueryWs& ws, int device_cus,
+                         hipStream_t st) {
+    hipLaunchKernelGGL(k_refine, dim3(resident_grid(k_refine, kTile, 0, device_cus)), dim3(kTile), 0, st, ix, sp,
+                       ws);
+    return hipGetLastError();
+}
+
+}  // namespace hs
