@@ -34,6 +34,7 @@ struct hs_index {
     int64_t* part_chunk_dev = nullptr;  // library-owned
     int64_t* chunk_start_dev = nullptr; // library-owned
     float4* cenv_dev = nullptr;         // library-owned
+    int filter_waves = 4;               // wavefronts of the filter kernel (candidate slices)
 };
 
 namespace {
@@ -273,8 +274,9 @@ int64_t ws_layout(const hs_index* idx, int32_t Q, int32_t k, QueryWs* ws, char* 
     const int64_t per_q = cpq > 0 ? cpq : std::max<int64_t>((ix.N + 15) / 16, 4096);
     const int64_t floor_c = cpq > 0 ? 1 : (1 << 16);
     const int64_t cand_total = std::min<int64_t>(std::max<int64_t>((int64_t)Q * per_q, floor_c), (int64_t)1 << 28);
-    const int64_t per_region = (cand_total + kRegions - 1) / kRegions;
-    const int64_t cand = per_region * kRegions;
+    const int n_slices = idx->filter_waves;
+    const int64_t slice_cap = (cand_total + n_slices - 1) / n_slices;
+    const int64_t cand = slice_cap * n_slices;
     char* cur = base;
     QueryWs w{};
     carve(cur, (void**)&w.qrow, (int64_t)Q * ix.stride * 4);
@@ -289,14 +291,18 @@ int64_t ws_layout(const hs_index* idx, int32_t Q, int32_t k, QueryWs* ws, char* 
     carve(cur, (void**)&w.pool, (int64_t)Q * P * 8);
     carve(cur, (void**)&w.stats, (int64_t)Q * 64);
     carve(cur, (void**)&w.items, items * 8);
+    carve(cur, (void**)&w.slice_pos, cand * 4);
+    carve(cur, (void**)&w.slice_q, cand * 4);
+    carve(cur, (void**)&w.slice_lb, cand * 4);
+    carve(cur, (void**)&w.slice_cnt, (int64_t)n_slices * 4);
+    carve(cur, (void**)&w.slice_start, ((int64_t)n_slices + 1) * 4);
     carve(cur, (void**)&w.cand_pos, cand * 4);
     carve(cur, (void**)&w.cand_q, cand * 4);
     carve(cur, (void**)&w.cand_lb, cand * 4);
     carve(cur, (void**)&w.counters, kNumCounters * 4);
-    carve(cur, (void**)&w.cand_cnt, kRegions * 4);
-    carve(cur, (void**)&w.cand_end, kRegions * 4);
     w.item_cap = items;
-    w.cand_cap = per_region;
+    w.slice_cap = slice_cap;
+    w.n_slices = n_slices;
     w.P = P;
     if (ws) *ws = w;
     return (int64_t)(cur - base);
@@ -440,6 +446,7 @@ hs_status hs_build_summaries(const float* x_dev, int64_t N, const hs_params* par
     chunk_start.push_back(N);
     ix.parts = parts;
     ix.chunks = chunks;
+    idx->filter_waves = filter_waves(ix, idx->cus);
 
     // 3. leaf-ordered copy, words, envelopes
     float beta_host[kCard + 1];
@@ -571,6 +578,7 @@ hs_status hs_knn_exact(hs_index* idx, const float* q_dev, int32_t Q, int32_t k, 
     // step 2: candidate leaves; step 3: LB_SAX filter; step 4: refinement
     HIP_TRY(launch_emit(ix, sp, false, ws, st));
     HIP_TRY(timed(HS_PROF_FILTER, launch_filter));
+    HIP_TRY(launch_compact(ws, st));
     HIP_TRY(timed(HS_PROF_REFINE, launch_refine));
     sp.final_pass = 1;
     HIP_TRY(launch_merge(ix, sp, false, ws, ids_dev, d2_dev, stats_out, st));

@@ -1,31 +1,33 @@
 // The LB_SAX filter (Hercules Sec. 3.3, step 3): the series of every
-// (query, part) item whose bounds do not exceed BSF_k are appended to a
-// candidate list for the refine kernel.
+// (query, part) item whose bounds do not exceed BSF_k become candidates for
+// the refine kernel.
 //
-// Wavefronts never wait for each other on the hot path: workgroup barriers
-// happen only when a workgroup switches to another query's LB_SAX table.
-// Work is split into contiguous static ranges per workgroup, and the
-// candidate list into kRegions regions with a counter each.
+// Every wavefront appends to a private slice of the candidate buffer with a
+// counter in a register (no atomics), and wavefronts never wait for each
+// other except when their workgroup switches to another query's LB_SAX table
+// (items are ordered by query and each workgroup takes a contiguous range).
+// After the filter, slice_prefix and compact concatenate the slices into the
+// dense candidate list.
 #include "hs_device.h"
 
 namespace hs {
 namespace {
 
-constexpr int kSlots = kPartRows / (kChunkRows * (kTile / 64));  // chunks per wave per item (8)
+constexpr int kWaves = kTile / 64;                 // wavefronts per workgroup
+constexpr int kSlots = 8;                          // chunks per wavefront per round
+constexpr int kRoundSpan = kSlots * kWaves;        // chunks per round (2048 series)
 
 __device__ __forceinline__ int64_t item_count(const QueryWs& ws) {
     return min((int64_t)ws.counters[kCtrItems], ws.item_cap);
 }
 
-// ------------------------------------------------------------------ filter
-//
-// Wave `wave` owns chunks wave + 4 s (s = 0..7) of the item's part: lane l
-// handles series pb + 64 (wave + 4 s) + l.  First the chunks' LB_EAPCA
-// (float32 over outward-rounded intervals, summed over L = pow2 >= w lanes;
-// the butterfly leaves every lane of a group the same value) decides which
-// chunks are read at all; then the words of the live chunks are loaded
-// together and each lane evaluates LB_SAX of its series; the wave's
-// survivors are appended with one reservation.
+// A part is processed in rounds of kRoundSpan chunks; in a round, wave
+// `wave` owns chunks rb + wave + 4 s (s = 0..7): lane l handles the series
+// 64 chunk + l.  First the chunks' LB_EAPCA (float32 over outward-rounded
+// intervals, summed over L = pow2 >= w lanes; the butterfly leaves every lane
+// of a group the same value) decides which chunks are read at all; then the
+// words of the live chunks are loaded together and each lane evaluates
+// LB_SAX of its series.
 template <int W16>
 __global__ void __launch_bounds__(256) k_filter(IndexView ix, ScanParams sp, QueryWs ws) {
     extern __shared__ float s_lut[];  // [w][256]
@@ -36,6 +38,11 @@ __global__ void __launch_bounds__(256) k_filter(IndexView ix, ScanParams sp, Que
     while (L < ix.w) L <<= 1;
     const int cpp = 64 / L;  // chunk envelopes tested per pass
     const uint64_t lt_mask = (1ull << lane) - 1ull;
+    const int64_t slice = (int64_t)blockIdx.x * kWaves + wave;
+    uint32_t* spos = ws.slice_pos + slice * ws.slice_cap;
+    uint32_t* sq = ws.slice_q + slice * ws.slice_cap;
+    float* slb = ws.slice_lb + slice * ws.slice_cap;
+    uint32_t cnt = 0;  // entries in this wave's slice (uniform)
     int64_t i0, i1;
     block_range(item_count(ws), i0, i1);
     int cur_q = -1;
@@ -62,119 +69,164 @@ __global__ void __launch_bounds__(256) k_filter(IndexView ix, ScanParams sp, Que
         const int64_t pb = ix.part_start[p], pe = ix.part_start[p + 1];
         const int64_t c0 = ix.part_chunk[p];
         const int nch = (int)((pe - pb + kChunkRows - 1) / kChunkRows);
-
-        // 1. chunk envelopes
-        uint32_t live = 0;
-        if (skip) {
-            live = 0xffu;
-        } else {
-            for (int sb = 0; sb < kSlots; sb += cpp) {
-                const int s = sb + lane / L, seg = lane % L;
-                const int ch = wave + (kTile / 64) * s;
-                const bool valid = s < kSlots && ch < nch;
-                float term = 0.0f;
-                if (valid && seg < ix.w) {
-                    const float4 e = ix.cenv[(c0 + ch) * ix.w + seg];
-                    const float4 qs = s_qst[seg];
-                    const float gm = fmaxf(0.0f, fmaxf(e.x - qs.y, qs.x - e.y));
-                    const float gs = fmaxf(0.0f, fmaxf(e.z - qs.w, qs.z - e.w));
-                    term = lseg * (gm * gm + gs * gs);
-                }
-                for (int o = L >> 1; o > 0; o >>= 1) term += __shfl_xor(term, o, 64);
-                const uint64_t tested = __ballot(valid && seg == 0);
-                const uint64_t ok = __ballot(valid && seg == 0 && (double)term <= thr);
-                a_tests += (unsigned long long)__popcll(tested);
-                for (int i = 0; i < cpp && sb + i < kSlots; ++i)
-                    if ((ok >> (i * L)) & 1ull) live |= 1u << (sb + i);
-            }
-        }
-
-        // 2. words of the live chunks, all loads in flight together
-        uint4 v[kSlots][W16];
-#pragma unroll
-        for (int s = 0; s < kSlots; ++s) {
-            const int64_t r = pb + (int64_t)(wave + (kTile / 64) * s) * kChunkRows + lane;
-            if (!skip && ((live >> s) & 1u) && r < pe) load_word<W16>(ix.words + r * ix.wstride, v[s]);
-        }
-
-        // 3. LB_SAX and the wave's survivors
-        float lbv[kSlots];
-        uint32_t mask = 0;
-        unsigned evaluated = 0;
-#pragma unroll
-        for (int s = 0; s < kSlots; ++s) {
-            const int64_t r0 = pb + (int64_t)(wave + (kTile / 64) * s) * kChunkRows;
-            const int64_t r = r0 + lane;
-            lbv[s] = 0.0f;
-            if ((live >> s) & 1u) {
-                if (r0 < pe) evaluated += (unsigned)min((int64_t)kChunkRows, pe - r0);
-                if (r < pe) {
-                    if (!skip) lbv[s] = lb_sax_word<W16>(v[s], s_lut, ix.w);
-                    if ((double)lbv[s] <= thr) mask |= 1u << s;
+        bool lost = false;
+        for (int rb = 0; rb < nch; rb += kRoundSpan) {
+            // 1. chunk envelopes
+            uint32_t live = 0;
+            if (skip) {
+                live = 0xffu;
+            } else {
+                for (int sb = 0; sb < kSlots; sb += cpp) {
+                    const int s = sb + lane / L, seg = lane % L;
+                    const int ch = rb + wave + kWaves * s;
+                    const bool valid = s < kSlots && ch < nch;
+                    float term = 0.0f;
+                    if (valid && seg < ix.w) {
+                        const float4 e = ix.cenv[(c0 + ch) * ix.w + seg];
+                        const float4 qs = s_qst[seg];
+                        const float gm = fmaxf(0.0f, fmaxf(e.x - qs.y, qs.x - e.y));
+                        const float gs = fmaxf(0.0f, fmaxf(e.z - qs.w, qs.z - e.w));
+                        term = lseg * (gm * gm + gs * gs);
+                    }
+                    for (int o = L >> 1; o > 0; o >>= 1) term += __shfl_xor(term, o, 64);
+                    const uint64_t tested = __ballot(valid && seg == 0);
+                    const uint64_t ok = __ballot(valid && seg == 0 && (double)term <= thr);
+                    a_tests += (unsigned long long)__popcll(tested);
+                    for (int i = 0; i < cpp && sb + i < kSlots; ++i)
+                        if ((ok >> (i * L)) & 1ull) live |= 1u << (sb + i);
                 }
             }
-        }
-        uint64_t bal[kSlots];
-        int total = 0;
+
+            // 2. words of the live chunks, all loads in flight together
+            uint4 v[kSlots][W16];
 #pragma unroll
-        for (int s = 0; s < kSlots; ++s) {
-            bal[s] = __ballot((mask >> s) & 1u);
-            total += __popcll(bal[s]);
-        }
-        if (!skip) a_filt += evaluated;
-        if (total > 0) {
-            // a query's candidates go to region q mod kRegions: long runs of one
-            // query for the refine kernel, and few wavefronts per counter
-            const int region = q % kRegions;
-            long long base = -1;
-            if (lane == 0) {
-                // once a region is full no more ranges are reserved in it, so
-                // its 32-bit counter overshoots the capacity by at most one
-                // range per wavefront mapped to it
-                uint32_t* cnt = &ws.cand_cnt[region];
-                if ((int64_t)load_relaxed(cnt) >= ws.cand_cap) {
-                    atomicOr(&ws.flags[q], kFlagCandLost);
-                } else {
-                    const uint32_t b = atomicAdd(cnt, (uint32_t)total);
-                    if ((int64_t)b + total <= ws.cand_cap) {
-                        base = (long long)region * ws.cand_cap + b;
-                    } else {
-                        // this range is never written; the refine kernel stops below it
-                        atomicMin(&ws.cand_end[region], b);
-                        atomicOr(&ws.flags[q], kFlagCandLost);
+            for (int s = 0; s < kSlots; ++s) {
+                const int64_t r = pb + (int64_t)(rb + wave + kWaves * s) * kChunkRows + lane;
+                if (!skip && ((live >> s) & 1u) && r < pe) load_word<W16>(ix.words + r * ix.wstride, v[s]);
+            }
+
+            // 3. LB_SAX and the wave's survivors
+            float lbv[kSlots];
+            uint32_t mask = 0;
+            unsigned evaluated = 0;
+#pragma unroll
+            for (int s = 0; s < kSlots; ++s) {
+                const int64_t r0 = pb + (int64_t)(rb + wave + kWaves * s) * kChunkRows;
+                const int64_t r = r0 + lane;
+                lbv[s] = 0.0f;
+                if ((live >> s) & 1u) {
+                    if (r0 < pe) evaluated += (unsigned)min((int64_t)kChunkRows, pe - r0);
+                    if (r < pe) {
+                        if (!skip) lbv[s] = lb_sax_word<W16>(v[s], s_lut, ix.w);
+                        if ((double)lbv[s] <= thr) mask |= 1u << s;
                     }
                 }
             }
-            base = __shfl(base, 0, 64);
-            if (base >= 0) {
-                a_cand += (unsigned long long)total;
-                long long off = base;
+            if (!skip) a_filt += evaluated;
+            uint32_t total = 0;
 #pragma unroll
-                for (int s = 0; s < kSlots; ++s) {
-                    if ((mask >> s) & 1u) {
-                        const long long slot = off + __popcll(bal[s] & lt_mask);
-                        ws.cand_pos[slot] = (uint32_t)(pb + (int64_t)(wave + (kTile / 64) * s) * kChunkRows + lane);
-                        ws.cand_q[slot] = (uint32_t)q;
-                        ws.cand_lb[slot] = lbv[s];
-                    }
-                    off += __popcll(bal[s]);
-                }
+            for (int s = 0; s < kSlots; ++s) total += (uint32_t)__popcll(__ballot((mask >> s) & 1u));
+            if (total == 0) continue;
+            if ((int64_t)cnt + total > ws.slice_cap) {
+                lost = true;  // the slice is full: this query takes the fallback path
+                continue;
             }
+            uint32_t off = cnt;
+#pragma unroll
+            for (int s = 0; s < kSlots; ++s) {
+                const uint64_t bal = __ballot((mask >> s) & 1u);
+                if ((mask >> s) & 1u) {
+                    const uint32_t slot = off + (uint32_t)__popcll(bal & lt_mask);
+                    spos[slot] = (uint32_t)(pb + (int64_t)(rb + wave + kWaves * s) * kChunkRows + lane);
+                    sq[slot] = (uint32_t)q;
+                    slb[slot] = lbv[s];
+                }
+                off += (uint32_t)__popcll(bal);
+            }
+            cnt += total;
+            a_cand += total;
+        }
+        if (lost && lane == 0) atomicOr(&ws.flags[q], kFlagCandLost);
+    }
+    if (lane == 0) {
+        ws.slice_cnt[slice] = cnt;
+        if (cur_q >= 0) {
+            atomicAdd(&ws.stats[(int64_t)cur_q * 8 + 1], a_filt);
+            atomicAdd(&ws.stats[(int64_t)cur_q * 8 + 6], a_cand);
+            atomicAdd(&ws.stats[(int64_t)cur_q * 8 + 7], a_tests);
         }
     }
-    if (lane == 0 && cur_q >= 0) {
-        atomicAdd(&ws.stats[(int64_t)cur_q * 8 + 1], a_filt);
-        atomicAdd(&ws.stats[(int64_t)cur_q * 8 + 6], a_cand);
-        atomicAdd(&ws.stats[(int64_t)cur_q * 8 + 7], a_tests);
+}
+
+// Exclusive prefix of the slice counts (one workgroup); the total goes to
+// counters[kCtrCand].
+__global__ void __launch_bounds__(1024) k_slice_prefix(QueryWs ws) {
+    __shared__ uint32_t s_part[1024];
+    const int t = threadIdx.x, n = ws.n_slices;
+    const int per = (n + 1023) / 1024;
+    const int a = min(n, t * per), b = min(n, a + per);
+    uint32_t sum = 0;
+    for (int i = a; i < b; ++i) sum += ws.slice_cnt[i];
+    s_part[t] = sum;
+    __syncthreads();
+    for (int o = 1; o < 1024; o <<= 1) {  // inclusive Hillis-Steele scan
+        const uint32_t v = t >= o ? s_part[t - o] : 0u;
+        __syncthreads();
+        s_part[t] += v;
+        __syncthreads();
     }
+    uint32_t run = s_part[t] - sum;
+    for (int i = a; i < b; ++i) {
+        ws.slice_start[i] = run;
+        run += ws.slice_cnt[i];
+    }
+    if (t == 1023) {
+        ws.slice_start[n] = s_part[1023];
+        ws.counters[kCtrCand] = s_part[1023];
+    }
+}
+
+// One workgroup per slice: copy its entries to their place in the list.
+__global__ void __launch_bounds__(256) k_compact(QueryWs ws) {
+    const int64_t s = blockIdx.x;
+    const uint32_t c = ws.slice_cnt[s], dst = ws.slice_start[s];
+    const int64_t src = s * ws.slice_cap;
+    for (uint32_t i = threadIdx.x; i < c; i += blockDim.x) {
+        ws.cand_pos[dst + i] = ws.slice_pos[src + i];
+        ws.cand_q[dst + i] = ws.slice_q[src + i];
+        ws.cand_lb[dst + i] = ws.slice_lb[src + i];
+    }
+}
+
+template <int W16>
+int filter_blocks(const IndexView& ix, int cus) {
+    return resident_grid(k_filter<W16>, kTile, sizeof(float) * (size_t)ix.w * kCard, cus);
 }
 
 }  // namespace
 
+int filter_waves(const IndexView& ix, int device_cus) {
+    int blocks = 1;
+    switch (w16_of(ix)) {
+        case 1: blocks = filter_blocks<1>(ix, device_cus); break;
+        case 2: blocks = filter_blocks<2>(ix, device_cus); break;
+        case 3: blocks = filter_blocks<3>(ix, device_cus); break;
+        default: blocks = filter_blocks<4>(ix, device_cus); break;
+    }
+    return blocks * kWaves;
+}
+
 hipError_t launch_filter(const IndexView& ix, const ScanParams& sp, const QueryWs& ws, int device_cus,
                          hipStream_t st) {
     const size_t lds = sizeof(float) * (size_t)ix.w * kCard;
-    HS_LAUNCH_RESIDENT(ix, k_filter, lds, device_cus, st, ix, sp, ws);
+    const dim3 grid(ws.n_slices / kWaves);  // one slice per wavefront
+    HS_DISPATCH_W16(ix, k_filter, grid, dim3(kTile), lds, st, ix, sp, ws);
+    return hipGetLastError();
+}
+
+hipError_t launch_compact(const QueryWs& ws, hipStream_t st) {
+    hipLaunchKernelGGL(k_slice_prefix, dim3(1), dim3(1024), 0, st, ws);
+    hipLaunchKernelGGL(k_compact, dim3(ws.n_slices), dim3(256), 0, st, ws);
     return hipGetLastError();
 }
 

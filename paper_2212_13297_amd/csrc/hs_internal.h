@@ -12,7 +12,7 @@ namespace hs {
 constexpr int kCard = 256;          // iSAX alphabet (8-bit symbols)
 constexpr int kChunk = 64;          // points per refinement chunk (early-abandon granularity)
 constexpr int kTile = 256;          // threads per scan / filter / refine workgroup
-constexpr int kPartRows = 2048;     // series per work item: leaves are cut into parts of at most this many
+constexpr int kPartRows = 8192;     // series per work item: leaves are cut into parts of at most this many
 constexpr int kChunkRows = 64;      // series per chunk envelope (one wavefront's rows in the filter)
 constexpr uint32_t kInfBits = 0x7f800000u;  // +inf as float bits
 constexpr int kMaxSeedLeaves = 64;  // l_max is clamped to this many leaves in the seed step
@@ -41,9 +41,6 @@ constexpr int kCtrNonFinite = 3; // queries with NaN / Inf
 constexpr int kCtrCand = 4;      // candidates appended by the filter
 constexpr int kCtrRefine = 5;    // work-distribution counter of the refine kernel
 constexpr int kNumCounters = 8;
-// The candidate list is split into kRegions regions with a counter each, so
-// that appends from different workgroups rarely hit the same address.
-constexpr int kRegions = 256;
 
 // Everything a kernel needs to know about an index.
 struct IndexView {
@@ -78,14 +75,20 @@ struct QueryWs {
     uint64_t* pool;       // [Q][P]
     unsigned long long* stats;  // [Q][8]
     uint64_t* items;      // [item_cap] (q << 32 | part)
-    uint32_t* cand_pos;   // [cand_cap] stored position of a candidate series
-    uint32_t* cand_q;     // [cand_cap] its query
-    float* cand_lb;       // [cand_cap] its LB_SAX
+    // filter output: one private slice per filter wavefront
+    uint32_t* slice_pos;  // [n_slices][slice_cap] stored position of a candidate series
+    uint32_t* slice_q;    // [n_slices][slice_cap] its query
+    float* slice_lb;      // [n_slices][slice_cap] its LB_SAX
+    uint32_t* slice_cnt;  // [n_slices] entries written in each slice
+    uint32_t* slice_start;// [n_slices + 1] exclusive prefix of slice_cnt
+    // the candidate list: the slices concatenated (refine input)
+    uint32_t* cand_pos;   // [n_slices * slice_cap]
+    uint32_t* cand_q;
+    float* cand_lb;
     uint32_t* counters;   // [kNumCounters]
-    uint32_t* cand_cnt;   // [kRegions] entries reserved in each candidate region
-    uint32_t* cand_end;   // [kRegions] smallest base of a range that did not fit (UINT32_MAX if none)
     int64_t item_cap;
-    int64_t cand_cap;     // entries per region
+    int64_t slice_cap;    // entries per slice
+    int32_t n_slices;
     int32_t P;
 };
 
@@ -111,8 +114,12 @@ hipError_t launch_lb_eapca(const IndexView& ix, int32_t Q, const QueryWs& ws, hi
 hipError_t launch_seed(const IndexView& ix, const ScanParams& sp, const QueryWs& ws, hipStream_t st);
 hipError_t launch_emit(const IndexView& ix, const ScanParams& sp, bool redo_only, const QueryWs& ws,
                        hipStream_t st);
+// wavefronts the filter launches for this index (one private candidate slice each)
+int filter_waves(const IndexView& ix, int device_cus);
 hipError_t launch_filter(const IndexView& ix, const ScanParams& sp, const QueryWs& ws, int device_cus,
                          hipStream_t st);
+// concatenate the filter's slices into the candidate list
+hipError_t launch_compact(const QueryWs& ws, hipStream_t st);
 hipError_t launch_refine(const IndexView& ix, const ScanParams& sp, const QueryWs& ws, int device_cus,
                          hipStream_t st);
 hipError_t launch_leaf_scan(const IndexView& ix, const ScanParams& sp, const QueryWs& ws, int device_cus,

@@ -18,10 +18,6 @@ namespace {
 __global__ void k_init_counters(QueryWs ws) {
     const int t = threadIdx.x;
     if (t < kNumCounters) ws.counters[t] = 0;
-    for (int r = t; r < kRegions; r += blockDim.x) {
-        ws.cand_cnt[r] = 0;
-        ws.cand_end[r] = 0xffffffffu;
-    }
 }
 
 __global__ void __launch_bounds__(256) k_query_prep(IndexView ix, const float* __restrict__ qin, QueryWs ws) {

@@ -23,41 +23,23 @@ struct Meta {
     float lb;
 };
 
-// Candidate c of the flattened region list; lanes 0..15 call this for c = base + lane.
-__device__ __forceinline__ Meta load_meta(const QueryWs& ws, const long long* s_start, long long c, long long cend) {
+// Candidate c of the list; lanes 0..15 call this for c = base + lane.
+__device__ __forceinline__ Meta load_meta(const QueryWs& ws, long long c, long long cend) {
     Meta m{-1, 0u, 0.0f};
     if (c < cend) {
-        int lo = 0, hi = kRegions;
-        while (hi - lo > 1) {
-            const int mid = (lo + hi) >> 1;
-            if (s_start[mid] <= c) lo = mid; else hi = mid;
-        }
-        const int64_t slot = (int64_t)lo * ws.cand_cap + (c - s_start[lo]);
-        m.q = (int)ws.cand_q[slot];
-        m.pos = ws.cand_pos[slot];
-        m.lb = ws.cand_lb[slot];
+        m.q = (int)ws.cand_q[c];
+        m.pos = ws.cand_pos[c];
+        m.lb = ws.cand_lb[c];
     }
     return m;
 }
 
 __global__ void __launch_bounds__(256) k_refine(IndexView ix, ScanParams sp, QueryWs ws) {
     __shared__ unsigned long long s_top[kTile / 64][HS_KMAX];
-    __shared__ long long s_start[kRegions + 1];
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6, sub = t & 15, grp = (t >> 4) & 3;
-    const int gbase = lane & ~15;
     const int k = sp.k;
     const int nchunks = ix.stride / kChunk;
-    if (t == 0) {
-        // every entry of a region below min(counter, first range that did not fit) was written
-        long long acc = 0;
-        for (int r = 0; r < kRegions; ++r) {
-            s_start[r] = acc;
-            acc += min(min((long long)ws.cand_cnt[r], (long long)ws.cand_end[r]), (long long)ws.cand_cap);
-        }
-        s_start[kRegions] = acc;
-    }
-    __syncthreads();
-    const long long T = s_start[kRegions];
+    const long long T = ws.counters[kCtrCand];
     const long long gw = (long long)blockIdx.x * (kTile / 64) + wave, GW = (long long)gridDim.x * (kTile / 64);
     const long long cbeg = T * gw / GW, cend = T * (gw + 1) / GW;
     unsigned long long* top = s_top[wave];
@@ -69,11 +51,11 @@ __global__ void __launch_bounds__(256) k_refine(IndexView ix, ScanParams sp, Que
     int st_q = -1;                                    // lane 0: counters of st_q
     unsigned long long st_ref = 0, st_ch = 0;
 
-    Meta m = lane < kStep ? load_meta(ws, s_start, cbeg + lane, cend) : Meta{-1, 0u, 0.0f};
+    Meta m = lane < kStep ? load_meta(ws, cbeg + lane, cend) : Meta{-1, 0u, 0.0f};
     float mb = m.q >= 0 ? bits_to_float(load_relaxed(&ws.bsf[m.q])) : 0.0f;
     for (long long cb = cbeg; cb < cend; cb += kStep) {
         // next step's metadata in flight while this step is refined
-        const Meta nm = lane < kStep ? load_meta(ws, s_start, cb + kStep + lane, cend) : Meta{-1, 0u, 0.0f};
+        const Meta nm = lane < kStep ? load_meta(ws, cb + kStep + lane, cend) : Meta{-1, 0u, 0.0f};
 
         unsigned long long res[4];  // admitted keys of this group (group-uniform), ~0 = none
         int resq[4];
