@@ -208,7 +208,9 @@ def main():
                     "candidates_mean": float(stats["candidates"].mean()),
                     "per_level_refined_mean": [float(stats["rows_refined"][pct == p].mean()) for p in levels],
                     "per_level_candidates_mean": [float(stats["candidates"][pct == p].mean()) for p in levels],
-                    "rounds_max": int(stats["rounds"].max())},
+                    "rounds_max": int(stats["rounds"].max()),
+                    "queries_on_fallback": int((stats["rounds"] > 1).sum()),
+                    "candidates_max": int(stats["candidates"].max())},
         "build_s": round(build_s, 2),
         "cpu_baseline": cpu,
         "parity_sample": parity,

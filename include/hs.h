@@ -61,7 +61,7 @@ typedef int32_t hs_status;
  *             it skips the LB_SAX filter and scans its candidate leaves.
  *             Access-path choice only; results do not depend on it.
  *  cand_per_query  candidate-list entries reserved per query in the query
- *             workspace (0 = max(N/16, 4096)).  A query whose LB_SAX
+ *             workspace (0 = max(N/8, 4096)).  A query whose LB_SAX
  *             survivors do not fit is answered by the fused filter+refine
  *             kernel instead; results do not depend on it.
  * Every field is validated by hs_index_bytes / hs_build_summaries.

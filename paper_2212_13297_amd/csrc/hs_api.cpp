@@ -267,13 +267,13 @@ int64_t ws_layout(const hs_index* idx, int32_t Q, int32_t k, QueryWs* ws, char* 
     const IndexView& ix = idx->view;
     const int P = kPoolMin;
     const int64_t items = (int64_t)Q * ix.parts + 1;
-    // candidate list: up to 1/16 of the collection per query on average,
-    // between 64 Ki and 256 Mi entries; a query whose candidates do not fit
+    // candidate list: up to 1/8 of the collection per query on average,
+    // between 64 Ki and 512 Mi entries; a query whose candidates do not fit
     // is answered by the fused scan instead (no result changes)
     const int64_t cpq = idx->p.cand_per_query;
-    const int64_t per_q = cpq > 0 ? cpq : std::max<int64_t>((ix.N + 15) / 16, 4096);
+    const int64_t per_q = cpq > 0 ? cpq : std::max<int64_t>((ix.N + 7) / 8, 4096);
     const int64_t floor_c = cpq > 0 ? 1 : (1 << 16);
-    const int64_t cand_total = std::min<int64_t>(std::max<int64_t>((int64_t)Q * per_q, floor_c), (int64_t)1 << 28);
+    const int64_t cand_total = std::min<int64_t>(std::max<int64_t>((int64_t)Q * per_q, floor_c), (int64_t)1 << 29);
     const int n_slices = idx->filter_waves;
     const int64_t slice_cap = (cand_total + n_slices - 1) / n_slices;
     const int64_t cand = slice_cap * n_slices;

@@ -21,6 +21,25 @@ __device__ __forceinline__ int64_t item_count(const QueryWs& ws) {
     return min((int64_t)ws.counters[kCtrItems], ws.item_cap);
 }
 
+// Envelope passes per round: a pass tests 64 / L chunks (L = pow2 >= w lanes each).
+template <int W16>
+constexpr int max_passes() {
+    return W16 == 1 ? 2 : (W16 == 2 ? 4 : 8);
+}
+
+// Load the chunk envelopes a wave tests in round rb (one float4 per lane and pass).
+template <int W16>
+__device__ __forceinline__ void load_cenv(const IndexView& ix, int64_t c0, int nch, int rb, int wave, int lane,
+                                          int L, int cpp, float4 (&ce)[max_passes<W16>()]) {
+#pragma unroll
+    for (int i = 0; i < max_passes<W16>(); ++i) {
+        const int s = i * cpp + lane / L, seg = lane % L;
+        const int ch = rb + wave + kWaves * s;
+        ce[i] = make_float4(0.f, 0.f, 0.f, 0.f);
+        if (i * cpp < kSlots && s < kSlots && ch < nch && seg < ix.w) ce[i] = ix.cenv[(c0 + ch) * ix.w + seg];
+    }
+}
+
 // A part is processed in rounds of kRoundSpan chunks; in a round, wave
 // `wave` owns chunks rb + wave + 4 s (s = 0..7): lane l handles the series
 // 64 chunk + l.  First the chunks' LB_EAPCA (float32 over outward-rounded
@@ -70,19 +89,24 @@ __global__ void __launch_bounds__(256) k_filter(IndexView ix, ScanParams sp, Que
         const int64_t c0 = ix.part_chunk[p];
         const int nch = (int)((pe - pb + kChunkRows - 1) / kChunkRows);
         bool lost = false;
+        float4 ce[max_passes<W16>()];
+        if (!skip) load_cenv<W16>(ix, c0, nch, 0, wave, lane, L, cpp, ce);
         for (int rb = 0; rb < nch; rb += kRoundSpan) {
-            // 1. chunk envelopes
+            // 1. chunk envelopes (loaded during the previous round)
             uint32_t live = 0;
             if (skip) {
                 live = 0xffu;
             } else {
-                for (int sb = 0; sb < kSlots; sb += cpp) {
+#pragma unroll
+                for (int i = 0; i < max_passes<W16>(); ++i) {
+                    const int sb = i * cpp;
+                    if (sb >= kSlots) break;
                     const int s = sb + lane / L, seg = lane % L;
                     const int ch = rb + wave + kWaves * s;
                     const bool valid = s < kSlots && ch < nch;
                     float term = 0.0f;
                     if (valid && seg < ix.w) {
-                        const float4 e = ix.cenv[(c0 + ch) * ix.w + seg];
+                        const float4 e = ce[i];
                         const float4 qs = s_qst[seg];
                         const float gm = fmaxf(0.0f, fmaxf(e.x - qs.y, qs.x - e.y));
                         const float gs = fmaxf(0.0f, fmaxf(e.z - qs.w, qs.z - e.w));
@@ -92,18 +116,20 @@ __global__ void __launch_bounds__(256) k_filter(IndexView ix, ScanParams sp, Que
                     const uint64_t tested = __ballot(valid && seg == 0);
                     const uint64_t ok = __ballot(valid && seg == 0 && (double)term <= thr);
                     a_tests += (unsigned long long)__popcll(tested);
-                    for (int i = 0; i < cpp && sb + i < kSlots; ++i)
-                        if ((ok >> (i * L)) & 1ull) live |= 1u << (sb + i);
+                    for (int j = 0; j < cpp && sb + j < kSlots; ++j)
+                        if ((ok >> (j * L)) & 1ull) live |= 1u << (sb + j);
                 }
             }
 
-            // 2. words of the live chunks, all loads in flight together
+            // 2. words of the live chunks, all loads in flight together, and
+            //    the next round's envelopes behind them
             uint4 v[kSlots][W16];
 #pragma unroll
             for (int s = 0; s < kSlots; ++s) {
                 const int64_t r = pb + (int64_t)(rb + wave + kWaves * s) * kChunkRows + lane;
                 if (!skip && ((live >> s) & 1u) && r < pe) load_word<W16>(ix.words + r * ix.wstride, v[s]);
             }
+            if (!skip && rb + kRoundSpan < nch) load_cenv<W16>(ix, c0, nch, rb + kRoundSpan, wave, lane, L, cpp, ce);
 
             // 3. LB_SAX and the wave's survivors
             float lbv[kSlots];
