@@ -274,9 +274,11 @@ int64_t ws_layout(const hs_index* idx, int32_t Q, int32_t k, QueryWs* ws, char* 
     const int64_t per_q = cpq > 0 ? cpq : std::max<int64_t>((ix.N + 7) / 8, 4096);
     const int64_t floor_c = cpq > 0 ? 1 : (1 << 16);
     const int64_t cand_total = std::min<int64_t>(std::max<int64_t>((int64_t)Q * per_q, floor_c), (int64_t)1 << 29);
+    // 3/4 in the filter wavefronts' private slices, 1/4 in a shared overflow slice
     const int n_slices = idx->filter_waves;
-    const int64_t slice_cap = (cand_total + n_slices - 1) / n_slices;
-    const int64_t cand = slice_cap * n_slices;
+    const int64_t slice_cap = (cand_total * 3 / 4 + n_slices - 1) / n_slices;
+    const int64_t ovf_cap = std::max<int64_t>(cand_total / 4, cpq > 0 ? 1 : 4096);
+    const int64_t cand = slice_cap * n_slices + ovf_cap;
     char* cur = base;
     QueryWs w{};
     carve(cur, (void**)&w.qrow, (int64_t)Q * ix.stride * 4);
@@ -294,14 +296,15 @@ int64_t ws_layout(const hs_index* idx, int32_t Q, int32_t k, QueryWs* ws, char* 
     carve(cur, (void**)&w.slice_pos, cand * 4);
     carve(cur, (void**)&w.slice_q, cand * 4);
     carve(cur, (void**)&w.slice_lb, cand * 4);
-    carve(cur, (void**)&w.slice_cnt, (int64_t)n_slices * 4);
-    carve(cur, (void**)&w.slice_start, ((int64_t)n_slices + 1) * 4);
+    carve(cur, (void**)&w.slice_cnt, ((int64_t)n_slices + 1) * 4);
+    carve(cur, (void**)&w.slice_start, ((int64_t)n_slices + 2) * 4);
     carve(cur, (void**)&w.cand_pos, cand * 4);
     carve(cur, (void**)&w.cand_q, cand * 4);
     carve(cur, (void**)&w.cand_lb, cand * 4);
     carve(cur, (void**)&w.counters, kNumCounters * 4);
     w.item_cap = items;
     w.slice_cap = slice_cap;
+    w.ovf_cap = ovf_cap;
     w.n_slices = n_slices;
     w.P = P;
     if (ws) *ws = w;

@@ -153,23 +153,48 @@ __global__ void __launch_bounds__(256) k_filter(IndexView ix, ScanParams sp, Que
 #pragma unroll
             for (int s = 0; s < kSlots; ++s) total += (uint32_t)__popcll(__ballot((mask >> s) & 1u));
             if (total == 0) continue;
-            if ((int64_t)cnt + total > ws.slice_cap) {
-                lost = true;  // the slice is full: this query takes the fallback path
-                continue;
-            }
+            uint32_t* dpos = spos;
+            uint32_t* dq = sq;
+            float* dlb = slb;
             uint32_t off = cnt;
+            const bool own = (int64_t)cnt + total <= ws.slice_cap;
+            if (!own) {
+                // the private slice is full: reserve a range of the shared
+                // overflow slice; once that is full too, the query takes the
+                // fallback path.  Reservations stop at capacity, so the 32-bit
+                // counter overshoots it by at most one range per wavefront.
+                long long b = -1;
+                if (lane == 0) {
+                    uint32_t* oc = &ws.counters[kCtrOvf];
+                    if ((int64_t)load_relaxed(oc) < ws.ovf_cap) {
+                        const uint32_t r = atomicAdd(oc, total);
+                        if ((int64_t)r + total <= ws.ovf_cap) b = r;
+                        else atomicMin(&ws.counters[kCtrOvfEnd], r);  // never written: the list stops below it
+                    }
+                }
+                b = __shfl(b, 0, 64);
+                if (b < 0) {
+                    lost = true;
+                    continue;
+                }
+                const int64_t ob = (int64_t)ws.n_slices * ws.slice_cap;
+                dpos = ws.slice_pos + ob;
+                dq = ws.slice_q + ob;
+                dlb = ws.slice_lb + ob;
+                off = (uint32_t)b;
+            }
 #pragma unroll
             for (int s = 0; s < kSlots; ++s) {
                 const uint64_t bal = __ballot((mask >> s) & 1u);
                 if ((mask >> s) & 1u) {
                     const uint32_t slot = off + (uint32_t)__popcll(bal & lt_mask);
-                    spos[slot] = (uint32_t)(pb + (int64_t)(rb + wave + kWaves * s) * kChunkRows + lane);
-                    sq[slot] = (uint32_t)q;
-                    slb[slot] = lbv[s];
+                    dpos[slot] = (uint32_t)(pb + (int64_t)(rb + wave + kWaves * s) * kChunkRows + lane);
+                    dq[slot] = (uint32_t)q;
+                    dlb[slot] = lbv[s];
                 }
                 off += (uint32_t)__popcll(bal);
             }
-            cnt += total;
+            if (own) cnt += total;
             a_cand += total;
         }
         if (lost && lane == 0) atomicOr(&ws.flags[q], kFlagCandLost);
@@ -188,7 +213,13 @@ __global__ void __launch_bounds__(256) k_filter(IndexView ix, ScanParams sp, Que
 // counters[kCtrCand].
 __global__ void __launch_bounds__(1024) k_slice_prefix(QueryWs ws) {
     __shared__ uint32_t s_part[1024];
-    const int t = threadIdx.x, n = ws.n_slices;
+    const int t = threadIdx.x, n = ws.n_slices + 1;  // the private slices and the overflow slice
+    if (t == 0) {
+        // every overflow entry below min(counter, first range that did not fit) was written
+        const int64_t c = min(min((int64_t)ws.counters[kCtrOvf], (int64_t)ws.counters[kCtrOvfEnd]), ws.ovf_cap);
+        ws.slice_cnt[ws.n_slices] = (uint32_t)c;
+    }
+    __syncthreads();
     const int per = (n + 1023) / 1024;
     const int a = min(n, t * per), b = min(n, a + per);
     uint32_t sum = 0;
@@ -252,7 +283,7 @@ hipError_t launch_filter(const IndexView& ix, const ScanParams& sp, const QueryW
 
 hipError_t launch_compact(const QueryWs& ws, hipStream_t st) {
     hipLaunchKernelGGL(k_slice_prefix, dim3(1), dim3(1024), 0, st, ws);
-    hipLaunchKernelGGL(k_compact, dim3(ws.n_slices), dim3(256), 0, st, ws);
+    hipLaunchKernelGGL(k_compact, dim3(ws.n_slices + 1), dim3(256), 0, st, ws);
     return hipGetLastError();
 }
 

@@ -40,6 +40,9 @@ constexpr int kCtrRedo = 2;      // queries that need another round
 constexpr int kCtrNonFinite = 3; // queries with NaN / Inf
 constexpr int kCtrCand = 4;      // candidates appended by the filter
 constexpr int kCtrRefine = 5;    // work-distribution counter of the refine kernel
+constexpr int kCtrOvf = 6;       // entries reserved in the overflow slice
+constexpr int kCtrOvfEnd = 7;    // smallest base of an overflow range that did not fit (UINT32_MAX if none):
+                                 // overflow entries at or above it were never written
 constexpr int kNumCounters = 8;
 
 // Everything a kernel needs to know about an index.
@@ -88,6 +91,7 @@ struct QueryWs {
     uint32_t* counters;   // [kNumCounters]
     int64_t item_cap;
     int64_t slice_cap;    // entries per slice
+    int64_t ovf_cap;      // entries of the shared overflow slice (slice index n_slices)
     int32_t n_slices;
     int32_t P;
 };

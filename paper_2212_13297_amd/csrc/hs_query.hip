@@ -17,7 +17,7 @@ namespace {
 
 __global__ void k_init_counters(QueryWs ws) {
     const int t = threadIdx.x;
-    if (t < kNumCounters) ws.counters[t] = 0;
+    if (t < kNumCounters) ws.counters[t] = t == kCtrOvfEnd ? 0xffffffffu : 0u;
 }
 
 __global__ void __launch_bounds__(256) k_query_prep(IndexView ix, const float* __restrict__ qin, QueryWs ws) {

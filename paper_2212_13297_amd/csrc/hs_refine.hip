@@ -60,16 +60,16 @@ __global__ void __launch_bounds__(256) k_refine(IndexView ix, ScanParams sp, Que
         unsigned long long res[4];  // admitted keys of this group (group-uniform), ~0 = none
         int resq[4];
         unsigned chs[4];            // chunks read per candidate (0: not refined)
+        float nmb = 0.0f;           // next step's BSF_k, loaded behind this step's first rows
+        {
+            int q[4];
+            uint32_t pos[4];
+            float thr[4], d[4];
+            bool alive[4], refined[4];
+            unsigned ch[4] = {0u, 0u, 0u, 0u};
 #pragma unroll
-        for (int h = 0; h < 2; ++h) {
-            int q[2];
-            uint32_t pos[2];
-            float thr[2], d[2];
-            bool alive[2], refined[2];
-            unsigned ch[2] = {0u, 0u};
-#pragma unroll
-            for (int j = 0; j < 2; ++j) {
-                const int src = grp * 4 + 2 * h + j;
+            for (int j = 0; j < 4; ++j) {
+                const int src = grp * 4 + j;
                 q[j] = __shfl(m.q, src, 64);
                 pos[j] = __shfl(m.pos, src, 64);
                 const float lb = __shfl(m.lb, src, 64);
@@ -81,33 +81,46 @@ __global__ void __launch_bounds__(256) k_refine(IndexView ix, ScanParams sp, Que
             }
             for (int c = 0; c < nchunks; c += 2) {
                 const bool two = c + 1 < nchunks;
-                float4 x0[2], x1[2];
+                float4 x0[4], x1[4];
 #pragma unroll
-                for (int j = 0; j < 2; ++j) {
+                for (int j = 0; j < 4; ++j) {
                     if (alive[j]) {
                         const float* xr = ix.rows + (int64_t)pos[j] * ix.stride + sub * 4 + c * kChunk;
                         x0[j] = *reinterpret_cast<const float4*>(xr);
                         x1[j] = two ? *reinterpret_cast<const float4*>(xr + kChunk) : make_float4(0.f, 0.f, 0.f, 0.f);
                     }
                 }
+                if (c == 0 && nm.q >= 0) nmb = bits_to_float(load_relaxed(&ws.bsf[nm.q]));
+                // the group's candidates almost always share a query: its chunks are
+                // loaded once and reloaded only for a candidate of another query
+                const float* q0 = ws.qrow + (int64_t)q[0] * ix.stride + sub * 4 + c * kChunk;
+                float4 qa = make_float4(0.f, 0.f, 0.f, 0.f), qb = qa;
+                if (q[0] >= 0) {
+                    qa = *reinterpret_cast<const float4*>(q0);
+                    if (two) qb = *reinterpret_cast<const float4*>(q0 + kChunk);
+                }
 #pragma unroll
-                for (int j = 0; j < 2; ++j) {
+                for (int j = 0; j < 4; ++j) {
                     if (alive[j]) {
-                        const float* qr = ws.qrow + (int64_t)q[j] * ix.stride + sub * 4 + c * kChunk;
-                        d[j] += chunk_partial(*reinterpret_cast<const float4*>(qr), x0[j]);
-                        if (two) d[j] += chunk_partial(*reinterpret_cast<const float4*>(qr + kChunk), x1[j]);
+                        float4 a = qa, b = qb;
+                        if (q[j] != q[0]) {
+                            const float* qr = ws.qrow + (int64_t)q[j] * ix.stride + sub * 4 + c * kChunk;
+                            a = *reinterpret_cast<const float4*>(qr);
+                            if (two) b = *reinterpret_cast<const float4*>(qr + kChunk);
+                        }
+                        d[j] += chunk_partial(a, x0[j]);
+                        if (two) d[j] += chunk_partial(b, x1[j]);
                         ch[j] += two ? 2u : 1u;
                         if (d[j] > thr[j]) alive[j] = false;
                     }
                 }
             }
 #pragma unroll
-            for (int j = 0; j < 2; ++j) {
-                chs[2 * h + j] = refined[j] ? ch[j] : 0u;
-                res[2 * h + j] = (refined[j] && alive[j])
-                                     ? (((unsigned long long)__float_as_uint(d[j]) << 32) | ix.ids[pos[j]])
-                                     : ~0ull;
-                resq[2 * h + j] = q[j];
+            for (int j = 0; j < 4; ++j) {
+                chs[j] = refined[j] ? ch[j] : 0u;
+                res[j] = (refined[j] && alive[j]) ? (((unsigned long long)__float_as_uint(d[j]) << 32) | ix.ids[pos[j]])
+                                                  : ~0ull;
+                resq[j] = q[j];
             }
         }
 
@@ -153,7 +166,7 @@ __global__ void __launch_bounds__(256) k_refine(IndexView ix, ScanParams sp, Que
         cur_q = __shfl(new_q, 0, 64);
         lk = __shfl(new_lk, 0, 64);
         m = nm;
-        mb = m.q >= 0 ? bits_to_float(load_relaxed(&ws.bsf[m.q])) : 0.0f;
+        mb = nmb;
     }
     if (lane == 0) {
         flush_topk(ws, cur_q, k, top, topn);
