@@ -10,9 +10,12 @@
  *
  * Conventions for every entry point:
  *  - Pointers named *_dev are device pointers; pointers without the suffix are
- *    host pointers.  The caller owns and frees every device buffer (input
- *    series, index memory, query workspace, outputs).  The library owns only
- *    the opaque host handle returned by hs_build_summaries.
+ *    host pointers.  The caller owns and frees every large device buffer
+ *    (input series, index memory, low-precision copy, query workspace,
+ *    outputs).  The library owns the opaque host handle returned by
+ *    hs_build_summaries and the index's small device tables (leaf, part and
+ *    chunk tables, envelopes, breakpoints: O(N / 64) entries), which
+ *    hs_index_free releases.
  *  - `stream` is a hipStream_t passed as void* (NULL = the null stream).  All
  *    device work is enqueued on it.  hs_build_summaries synchronises the
  *    stream (the leaf partition runs on the host); hs_knn_exact synchronises
@@ -146,7 +149,7 @@ hs_status hs_query_workspace_bytes(const hs_index* idx, int32_t Q, int32_t k, in
  */
 typedef struct {
     uint64_t leaves_kept;     /* candidate leaves after LB_EAPCA (seed leaves included) */
-    uint64_t rows_filtered;   /* series whose LB_SAX was evaluated */
+    uint64_t rows_filtered;   /* series whose LB_SAX (precision form: matrix-core bound) was evaluated */
     uint64_t rows_refined;    /* series whose raw values were read */
     uint64_t chunks_read;     /* 64-point chunks of raw values read (early abandoning stops early) */
     uint64_t path;            /* 0 = LB_SAX path, 1 = skip-sequential (no LB_SAX) */
@@ -173,15 +176,62 @@ hs_status hs_knn_exact(hs_index* idx, const float* q_dev, int32_t Q, int32_t k, 
                        int64_t ws_bytes, int64_t* ids_dev, float* d2_dev, void* stats_dev,
                        void* stream);
 
-/* Diagnostics.  While enabled, hs_knn_exact brackets every launch of its scan
- * kernels (the dominant ones) with HIP events on its stream and, after its
- * own final synchronisation, adds their elapsed times to process-wide
- * accumulators, one per kind.  Not meant for concurrent calls from several
- * threads. */
+/*
+ * Precision form (beside the paper's method; it returns the same exact k-NN).
+ * A low-precision copy x~ of every stored series (bf16 or fp16, round to
+ * nearest even) replaces LB_SAX as the per-series filter of Sec. 3.3 step 3:
+ * a matrix-core pass computes q~.x~ in float32 for every (query, series)
+ * pair of the candidate leaves and derives a rigorous lower bound of the
+ * squared distance,
+ *   LB = max(0, sqrt((1-g)(||q~||^2 + ||x~||^2) - 2 q~.x~) - eps_q - eps_x)^2,
+ * eps = ||v - v~||_2, g = K 2^-23 / (1 - K 2^-23) for K = row_stride
+ * (float32 accumulation error), evaluated in float64 for every pair that a
+ * float32 test with proven margins does not already drop.  Pairs with
+ * LB <= BSF_k (1 + 1e-5) are refined from the float32 series with a
+ * compensated float32 distance (TwoSum / exact-product transformations).
+ */
+#define HS_SHADOW_BF16 1
+#define HS_SHADOW_FP16 2
+
+/* Device bytes of the low-precision copy of kind HS_SHADOW_*: N x row_stride
+ * 16-bit values plus N x 8 bytes of norms (plus 256 bytes of scratch).
+ * Errors: HS_EINVAL (NULL, unknown kind). */
+hs_status hs_shadow_bytes(const hs_index* idx, int32_t kind, int64_t* bytes);
+
+/* Build the low-precision copy into caller-owned device memory shadow_dev
+ * (hs_shadow_bytes bytes, kept allocated until hs_index_free or the next
+ * hs_build_shadow).  Per series it stores x~ in leaf order, ||x~||^2
+ * (computed in float64, stored rounded down) and ||x - x~||_2 (stored
+ * rounded up).  Synchronises the stream.  An index holds one copy; a new
+ * call replaces it.
+ * Errors: HS_EINVAL (NULL, unknown kind, a value beyond the fp16 range for
+ * HS_SHADOW_FP16), HS_ENOMEM (shadow_bytes too small), HS_EHIP. */
+hs_status hs_build_shadow(hs_index* idx, int32_t kind, void* shadow_dev, int64_t shadow_bytes, void* stream);
+
+/*
+ * Exact k-NN of Q queries through the precision form.  Arguments as for
+ * hs_knn_exact (same workspace size), plus
+ *  err_dev   float64 [Q][k] out, or NULL: a-priori bound of
+ *            |d2 - d(q, x)| for each result, d the exact squared distance
+ *            (compensated float32: (2^-23 + (4 K + 64) 2^-48) d2).
+ * d2 is the compensated float32 distance.  The id lists equal
+ * hs_knn_exact's up to ties within the distances' error.
+ * Errors: as hs_knn_exact; HS_EINVAL if the index has no low-precision copy
+ * or a query is beyond the fp16 range of an HS_SHADOW_FP16 copy.
+ */
+hs_status hs_knn_mixed(hs_index* idx, const float* q_dev, int32_t Q, int32_t k, void* ws_dev, int64_t ws_bytes,
+                       int64_t* ids_dev, float* d2_dev, double* err_dev, void* stats_dev, void* stream);
+
+/* Diagnostics.  While enabled, hs_knn_exact and hs_knn_mixed bracket every
+ * launch of their scan kernels (the dominant ones) with HIP events on their
+ * stream and, after their own final synchronisation, add the elapsed times
+ * to process-wide accumulators, one per kind.  Not meant for concurrent
+ * calls from several threads. */
 #define HS_PROF_FILTER 0 /* LB_SAX filter (Sec. 3.3 step 3) */
 #define HS_PROF_REFINE 1 /* refinement of the candidates (step 4) */
 #define HS_PROF_FUSED 2  /* fused filter + refinement (overflow fallback) */
-#define HS_PROF_KINDS 3
+#define HS_PROF_BOUND 3  /* matrix-core bounding pass of the precision form */
+#define HS_PROF_KINDS 4
 hs_status hs_profile_enable(int32_t on);
 /* Accumulated milliseconds and launch count of one kind; cleared if reset.
  * Errors: HS_EINVAL for an unknown kind. */

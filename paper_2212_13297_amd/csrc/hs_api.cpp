@@ -35,6 +35,7 @@ struct hs_index {
     int64_t* chunk_start_dev = nullptr; // library-owned
     float4* cenv_dev = nullptr;         // library-owned
     int filter_waves = 4;               // wavefronts of the filter kernel (candidate slices)
+    ShadowView shadow{};                // low-precision copy (caller-owned memory), kind 0 = none
 };
 
 namespace {
@@ -302,6 +303,10 @@ int64_t ws_layout(const hs_index* idx, int32_t Q, int32_t k, QueryWs* ws, char* 
     carve(cur, (void**)&w.cand_q, cand * 4);
     carve(cur, (void**)&w.cand_lb, cand * 4);
     carve(cur, (void**)&w.counters, kNumCounters * 4);
+    const int32_t Qpad = (Q + kBoundQueries - 1) / kBoundQueries * kBoundQueries;
+    carve(cur, (void**)&w.qlow, (int64_t)Qpad * ix.stride * 2);
+    carve(cur, (void**)&w.qnorm, (int64_t)Q * 16);
+    w.Qpad = Qpad;
     w.item_cap = items;
     w.slice_cap = slice_cap;
     w.ovf_cap = ovf_cap;
@@ -536,12 +541,22 @@ hs_status hs_query_workspace_bytes(const hs_index* idx, int32_t Q, int32_t k, in
     return HS_OK;
 }
 
-hs_status hs_knn_exact(hs_index* idx, const float* q_dev, int32_t Q, int32_t k, void* ws_dev, int64_t ws_bytes,
-                       int64_t* ids_dev, float* d2_dev, void* stats_dev, void* stream) {
+}  // extern "C"
+
+namespace {
+
+// Relative error bound of a compensated float32 distance over K stored points:
+// one rounding of the final sum plus second-order terms of the residues.
+double comp_err_rel(int K) { return std::ldexp(1.0, -23) + (4.0 * K + 64.0) * std::ldexp(1.0, -48); }
+
+// The query driver shared by the plain and the precision form.
+hs_status run_knn(hs_index* idx, const float* q_dev, int32_t Q, int32_t k, void* ws_dev, int64_t ws_bytes,
+                  int64_t* ids_dev, float* d2_dev, double* err_dev, void* stats_dev, void* stream, bool mixed) {
     if (!idx) return fail(HS_EINVAL, "idx is NULL");
     if (Q < 0) return fail(HS_EINVAL, "Q=%d < 0", Q);
     if (k < 1 || k > HS_KMAX) return fail(HS_EINVAL, "k=%d out of range [1, %d]", k, HS_KMAX);
     if ((int64_t)k > idx->view.N) return fail(HS_EINVAL, "k=%d > N=%lld", k, (long long)idx->view.N);
+    if (mixed && idx->shadow.kind == 0) return fail(HS_EINVAL, "the index has no low-precision copy (hs_build_shadow)");
     if (Q == 0) return HS_OK;
     if (!q_dev || !ws_dev || !ids_dev || !d2_dev) return fail(HS_EINVAL, "NULL device pointer");
     if ((int64_t)Q * idx->view.parts >= ((int64_t)1 << 31))
@@ -553,6 +568,7 @@ hs_status hs_knn_exact(hs_index* idx, const float* q_dev, int32_t Q, int32_t k, 
     ws_layout(idx, Q, k, &ws, (char*)ws_dev);
     const IndexView& ix = idx->view;
     const int lm = (int)std::min<int64_t>(std::min<int64_t>(idx->p.l_max, ix.L), kMaxSeedLeaves);
+    const int form = mixed ? kComp : kPlain;
 
     ScanParams sp{};
     sp.Q = Q;
@@ -561,30 +577,35 @@ hs_status hs_knn_exact(hs_index* idx, const float* q_dev, int32_t Q, int32_t k, 
     sp.n_seed = lm;
     sp.seed_rows = idx->p.seed_rows;
     auto* stats_out = (hs_query_stats*)stats_dev;
+    const double err_rel = mixed ? comp_err_rel(ix.stride) : 0.0;
 
-    // profiling brackets the two dominant kernels: the LB_SAX filter and the refinement
+    // profiling brackets the dominant kernels
     ScanTimer timer;
-    auto timed = [&](int kind,
-                     hipError_t (*fn)(const IndexView&, const ScanParams&, const QueryWs&, int, hipStream_t))
-        -> hipError_t {
+    auto timed = [&](int kind, auto&& launch) -> hipError_t {
         hipError_t e = timer.begin(st, kind);
         if (e != hipSuccess) return e;
-        e = fn(ix, sp, ws, idx->cus, st);
+        e = launch();
         if (e != hipSuccess) return e;
         return timer.end(st);
     };
 
     HIP_TRY(launch_query_prep(ix, q_dev, Q, ws, st));
+    if (mixed) HIP_TRY(launch_query_low(ix, idx->shadow.kind, Q, ws, st));
     HIP_TRY(launch_lb_eapca(ix, Q, ws, st));
     // step 1: approximate search seeds BSF_k
-    HIP_TRY(launch_seed(ix, sp, ws, st));
-    // step 2: candidate leaves; step 3: LB_SAX filter; step 4: refinement
+    HIP_TRY(launch_seed(ix, sp, ws, form, st));
+    // step 2: candidate leaves; step 3: per-series filter (LB_SAX, or the
+    // matrix-core bound of the precision form); step 4: refinement
     HIP_TRY(launch_emit(ix, sp, false, ws, st));
-    HIP_TRY(timed(HS_PROF_FILTER, launch_filter));
+    if (mixed) {
+        HIP_TRY(timed(HS_PROF_BOUND, [&] { return launch_bound(ix, idx->shadow, sp, ws, st); }));
+    } else {
+        HIP_TRY(timed(HS_PROF_FILTER, [&] { return launch_filter(ix, sp, ws, idx->cus, st); }));
+    }
     HIP_TRY(launch_compact(ws, st));
-    HIP_TRY(timed(HS_PROF_REFINE, launch_refine));
+    HIP_TRY(timed(HS_PROF_REFINE, [&] { return launch_refine(ix, sp, ws, idx->cus, form, st); }));
     sp.final_pass = 1;
-    HIP_TRY(launch_merge(ix, sp, false, ws, ids_dev, d2_dev, stats_out, st));
+    HIP_TRY(launch_merge(ix, sp, false, ws, ids_dev, d2_dev, err_dev, err_rel, stats_out, st));
 
     // queries whose candidate list or result pool overflowed: rescan their
     // candidate parts with the fused kernel and the tightened BSF_k until
@@ -593,16 +614,74 @@ hs_status hs_knn_exact(hs_index* idx, const float* q_dev, int32_t Q, int32_t k, 
         uint32_t c[2] = {0, 0};
         HIP_TRY(hipMemcpyAsync(c, ws.counters + kCtrRedo, sizeof c, hipMemcpyDeviceToHost, st));
         HIP_TRY(hipStreamSynchronize(st));
-        if (c[1]) return fail(HS_EINVAL, "%u queries contain NaN or Inf", c[1]);
+        if (c[1]) return fail(HS_EINVAL, "%u queries contain NaN or Inf%s", c[1],
+                              mixed && idx->shadow.kind == kShadowF16 ? " or values beyond the fp16 range" : "");
         if (c[0] == 0) {
             timer.collect();
             break;
         }
         if (round >= 64) return fail(HS_EHIP, "result pool still overflowing after %d rounds", round);
         HIP_TRY(launch_emit(ix, sp, true, ws, st));
-        HIP_TRY(timed(HS_PROF_FUSED, launch_leaf_scan));
-        HIP_TRY(launch_merge(ix, sp, true, ws, ids_dev, d2_dev, stats_out, st));
+        HIP_TRY(timed(HS_PROF_FUSED, [&] { return launch_leaf_scan(ix, sp, ws, idx->cus, form, st); }));
+        HIP_TRY(launch_merge(ix, sp, true, ws, ids_dev, d2_dev, err_dev, err_rel, stats_out, st));
     }
+    return HS_OK;
+}
+
+int64_t shadow_layout(const IndexView& ix, uint16_t** rows, float2** norms, uint32_t** flag, char* base) {
+    char* cur = base;
+    void* a;
+    carve(cur, &a, ix.N * ix.stride * 2);
+    if (rows) *rows = (uint16_t*)a;
+    carve(cur, &a, ix.N * 8);
+    if (norms) *norms = (float2*)a;
+    carve(cur, &a, 256);
+    if (flag) *flag = (uint32_t*)a;
+    return (int64_t)(cur - base);
+}
+
+}  // namespace
+
+extern "C" {
+
+hs_status hs_knn_exact(hs_index* idx, const float* q_dev, int32_t Q, int32_t k, void* ws_dev, int64_t ws_bytes,
+                       int64_t* ids_dev, float* d2_dev, void* stats_dev, void* stream) {
+    return run_knn(idx, q_dev, Q, k, ws_dev, ws_bytes, ids_dev, d2_dev, nullptr, stats_dev, stream, false);
+}
+
+hs_status hs_knn_mixed(hs_index* idx, const float* q_dev, int32_t Q, int32_t k, void* ws_dev, int64_t ws_bytes,
+                       int64_t* ids_dev, float* d2_dev, double* err_dev, void* stats_dev, void* stream) {
+    return run_knn(idx, q_dev, Q, k, ws_dev, ws_bytes, ids_dev, d2_dev, err_dev, stats_dev, stream, true);
+}
+
+hs_status hs_shadow_bytes(const hs_index* idx, int32_t kind, int64_t* bytes) {
+    if (!idx || !bytes) return fail(HS_EINVAL, "NULL argument");
+    if (kind != kShadowBf16 && kind != kShadowF16) return fail(HS_EINVAL, "unknown shadow kind %d", kind);
+    *bytes = shadow_layout(idx->view, nullptr, nullptr, nullptr, nullptr);
+    return HS_OK;
+}
+
+hs_status hs_build_shadow(hs_index* idx, int32_t kind, void* shadow_dev, int64_t shadow_bytes, void* stream) {
+    if (!idx || !shadow_dev) return fail(HS_EINVAL, "NULL argument");
+    if (kind != kShadowBf16 && kind != kShadowF16) return fail(HS_EINVAL, "unknown shadow kind %d", kind);
+    const int64_t need = shadow_layout(idx->view, nullptr, nullptr, nullptr, nullptr);
+    if (shadow_bytes < need)
+        return fail(HS_ENOMEM, "shadow_bytes=%lld < required %lld", (long long)shadow_bytes, (long long)need);
+    hipStream_t st = (hipStream_t)stream;
+    uint16_t* rows;
+    float2* norms;
+    uint32_t* flag;
+    shadow_layout(idx->view, &rows, &norms, &flag, (char*)shadow_dev);
+    idx->shadow = ShadowView{};
+    HIP_TRY(hipMemsetAsync(flag, 0, 4, st));
+    HIP_TRY(launch_shadow(idx->view, kind, rows, norms, flag, st));
+    uint32_t bad = 0;
+    HIP_TRY(hipMemcpyAsync(&bad, flag, 4, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    if (bad) return fail(HS_EINVAL, "a series value lies beyond the fp16 range; use HS_SHADOW_BF16");
+    idx->shadow.rows = rows;
+    idx->shadow.norms = norms;
+    idx->shadow.kind = kind;
     return HS_OK;
 }
 

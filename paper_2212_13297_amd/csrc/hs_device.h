@@ -72,29 +72,100 @@ __device__ __forceinline__ float chunk_partial(float4 q, float4 x) {
     return p;
 }
 
+// Knuth's TwoSum: s = fl(a + b) and e such that a + b = s + e exactly.
+// Contraction is off: no step may be fused with a product.
+__device__ __forceinline__ void two_sum(float a, float b, float& s, float& e) {
+#pragma clang fp contract(off)
+    s = a + b;
+    const float bb = s - a;
+    e = (a - (s - bb)) + (b - bb);
+}
+
+// Compensated partial of one 64-point chunk (precision form): the chunk's
+// squared distance as hi + lo.  Per point, q - x = dv + ev exactly (TwoSum)
+// and dv^2 = p + pe exactly (fma); the points' p are summed with TwoSum, every
+// rounding residue goes to lo.  The butterfly combines (hi, lo) pairs the same
+// way; TwoSum's residue is exact, so all 16 lanes end with identical values.
+__device__ __forceinline__ float chunk_partial_comp(float4 q, float4 x, float& lo_out) {
+#pragma clang fp contract(off)
+    const float qa[4] = {q.x, q.y, q.z, q.w}, xa[4] = {x.x, x.y, x.z, x.w};
+    float hi = 0.0f, lo = 0.0f;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+        float dv, ev;
+        two_sum(qa[v], -xa[v], dv, ev);
+        const float p = dv * dv;
+        const float pe = fmaf(dv, dv, -p);
+        const float r = fmaf(ev, (dv + dv) + ev, pe);  // (dv + ev)^2 - p
+        float t, te;
+        two_sum(hi, p, t, te);
+        hi = t;
+        lo += te + r;
+    }
+#pragma unroll
+    for (int m = 1; m < 16; m <<= 1) {
+        const float oh = __shfl_xor(hi, m, 16), ol = __shfl_xor(lo, m, 16);
+        float t, te;
+        two_sum(hi, oh, t, te);
+        hi = t;
+        lo = (lo + ol) + te;
+    }
+    lo_out = lo;
+    return hi;
+}
+
+// Running squared distance of one (query, series) pair in form F.
+template <int F>
+struct Dist;
+
+template <>
+struct Dist<kPlain> {
+    float s = 0.0f;
+    __device__ __forceinline__ void add(float4 q, float4 x) { s += chunk_partial(q, x); }
+    __device__ __forceinline__ float value() const { return s; }
+};
+
+template <>
+struct Dist<kComp> {
+    float s = 0.0f, c = 0.0f;
+    __device__ __forceinline__ void add(float4 q, float4 x) {
+#pragma clang fp contract(off)
+        float lo, t, te;
+        const float hi = chunk_partial_comp(q, x, lo);
+        two_sum(s, hi, t, te);
+        s = t;
+        c += lo + te;
+    }
+    __device__ __forceinline__ float value() const {
+#pragma clang fp contract(off)
+        return s + c;
+    }
+};
+
 // Squared distance of one series, computed by the 16 lanes of a group (all 16
 // active together).  xr / qr point at the lane's first point.  Chunks are
 // loaded two at a time; after each pair the running sum is compared with
 // thr and the series is abandoned once it exceeds it (the final sum can only
 // be larger).  `chunks` counts the chunks read.
+template <int F>
 __device__ __forceinline__ float refine_row(const float* __restrict__ xr, const float* __restrict__ qr,
                                            int nchunks, float thr, bool& alive, unsigned& chunks) {
-    float d = 0.0f;
+    Dist<F> d;
     alive = true;
     for (int c = 0; c < nchunks; c += 2) {
         const bool two = c + 1 < nchunks;
         const float4 x0 = *reinterpret_cast<const float4*>(xr + c * kChunk);
         float4 x1 = make_float4(0.f, 0.f, 0.f, 0.f);
         if (two) x1 = *reinterpret_cast<const float4*>(xr + (c + 1) * kChunk);
-        d += chunk_partial(*reinterpret_cast<const float4*>(qr + c * kChunk), x0);
-        if (two) d += chunk_partial(*reinterpret_cast<const float4*>(qr + (c + 1) * kChunk), x1);
+        d.add(*reinterpret_cast<const float4*>(qr + c * kChunk), x0);
+        if (two) d.add(*reinterpret_cast<const float4*>(qr + (c + 1) * kChunk), x1);
         chunks += two ? 2u : 1u;
-        if (d > thr) {
+        if (d.value() > thr) {
             alive = false;
             break;
         }
     }
-    return d;
+    return d.value();
 }
 
 // Insert key into the ascending list top[0..n) of capacity k (one thread).
@@ -220,4 +291,25 @@ inline int resident_grid(K kernel, int block, size_t dyn_lds, int cus) {
         case 2: hipLaunchKernelGGL(KERNEL<2>, __VA_ARGS__); break;                   \
         case 3: hipLaunchKernelGGL(KERNEL<3>, __VA_ARGS__); break;                   \
         default: hipLaunchKernelGGL(KERNEL<4>, __VA_ARGS__); break;                  \
+    }
+
+// The same two dispatches for kernels templated on <W16, F> (F a constant).
+#define HS_LAUNCH_RESIDENT_F(ix, KERNEL, F, lds, cus, st, ...)                                        \
+    switch (w16_of(ix)) {                                                                            \
+        case 1: KERNEL<1, F><<<dim3(resident_grid(KERNEL<1, F>, kTile, lds, cus)), dim3(kTile), lds, st>>>( \
+                    __VA_ARGS__); break;                                                             \
+        case 2: KERNEL<2, F><<<dim3(resident_grid(KERNEL<2, F>, kTile, lds, cus)), dim3(kTile), lds, st>>>( \
+                    __VA_ARGS__); break;                                                             \
+        case 3: KERNEL<3, F><<<dim3(resident_grid(KERNEL<3, F>, kTile, lds, cus)), dim3(kTile), lds, st>>>( \
+                    __VA_ARGS__); break;                                                             \
+        default: KERNEL<4, F><<<dim3(resident_grid(KERNEL<4, F>, kTile, lds, cus)), dim3(kTile), lds, st>>>( \
+                     __VA_ARGS__); break;                                                            \
+    }
+
+#define HS_DISPATCH_W16_F(ix, KERNEL, F, grid, block, lds, st, ...)                  \
+    switch (w16_of(ix)) {                                                            \
+        case 1: KERNEL<1, F><<<grid, block, lds, st>>>(__VA_ARGS__); break;          \
+        case 2: KERNEL<2, F><<<grid, block, lds, st>>>(__VA_ARGS__); break;          \
+        case 3: KERNEL<3, F><<<grid, block, lds, st>>>(__VA_ARGS__); break;          \
+        default: KERNEL<4, F><<<grid, block, lds, st>>>(__VA_ARGS__); break;         \
     }

@@ -45,6 +45,24 @@ constexpr int kCtrOvfEnd = 7;    // smallest base of an overflow range that did 
                                  // overflow entries at or above it were never written
 constexpr int kNumCounters = 8;
 
+// Distance forms of the refinement (template argument F of the kernels that
+// refine): float32 sum in a fixed order, or compensated float32 (error-free
+// transformations on every step, error ~2^-23 relative).
+constexpr int kPlain = 0;
+constexpr int kComp = 1;
+
+// Low-precision copy of the series (precision form)
+constexpr int kShadowBf16 = 1;  // HS_SHADOW_BF16
+constexpr int kShadowF16 = 2;   // HS_SHADOW_FP16
+constexpr int kBoundQueries = 128;  // queries per workgroup of the bounding pass (4 wavefronts x 32)
+constexpr int kBoundRows = 32;      // series per tile of the bounding pass
+
+struct ShadowView {
+    const uint16_t* rows;  // [N][stride] bf16 / fp16 bits of the stored series, zero padded
+    const float2* norms;   // [N] (||x~||^2 rounded down, ||x - x~||_2 rounded up), float32
+    int32_t kind;          // kShadowBf16 / kShadowF16
+};
+
 // Everything a kernel needs to know about an index.
 struct IndexView {
     const float* rows;         // [N][stride] leaf-ordered series, zero padded
@@ -89,6 +107,10 @@ struct QueryWs {
     uint32_t* cand_q;
     float* cand_lb;
     uint32_t* counters;   // [kNumCounters]
+    // precision form
+    uint16_t* qlow;       // [Qpad][stride] low-precision queries (zero rows beyond Q)
+    double2* qnorm;       // [Q] (||q~||^2, ||q - q~||_2 rounded up)
+    int32_t Qpad;         // Q rounded up to kBoundQueries
     int64_t item_cap;
     int64_t slice_cap;    // entries per slice
     int64_t ovf_cap;      // entries of the shared overflow slice (slice index n_slices)
@@ -115,7 +137,7 @@ hipError_t launch_envelopes(const IndexView& ix, const int64_t* starts, int64_t 
 
 hipError_t launch_query_prep(const IndexView& ix, const float* q, int32_t Q, const QueryWs& ws, hipStream_t st);
 hipError_t launch_lb_eapca(const IndexView& ix, int32_t Q, const QueryWs& ws, hipStream_t st);
-hipError_t launch_seed(const IndexView& ix, const ScanParams& sp, const QueryWs& ws, hipStream_t st);
+hipError_t launch_seed(const IndexView& ix, const ScanParams& sp, const QueryWs& ws, int form, hipStream_t st);
 hipError_t launch_emit(const IndexView& ix, const ScanParams& sp, bool redo_only, const QueryWs& ws,
                        hipStream_t st);
 // wavefronts the filter launches for this index (one private candidate slice each)
@@ -124,11 +146,22 @@ hipError_t launch_filter(const IndexView& ix, const ScanParams& sp, const QueryW
                          hipStream_t st);
 // concatenate the filter's slices into the candidate list
 hipError_t launch_compact(const QueryWs& ws, hipStream_t st);
-hipError_t launch_refine(const IndexView& ix, const ScanParams& sp, const QueryWs& ws, int device_cus,
+hipError_t launch_refine(const IndexView& ix, const ScanParams& sp, const QueryWs& ws, int device_cus, int form,
                          hipStream_t st);
-hipError_t launch_leaf_scan(const IndexView& ix, const ScanParams& sp, const QueryWs& ws, int device_cus,
+hipError_t launch_leaf_scan(const IndexView& ix, const ScanParams& sp, const QueryWs& ws, int device_cus, int form,
                             hipStream_t st);
+// err_out (may be NULL): err_rel * d2 per result
 hipError_t launch_merge(const IndexView& ix, const ScanParams& sp, bool redo_only, const QueryWs& ws,
-                        int64_t* ids_out, float* d2_out, hs_query_stats* stats_out, hipStream_t st);
+                        int64_t* ids_out, float* d2_out, double* err_out, double err_rel, hs_query_stats* stats_out,
+                        hipStream_t st);
+
+// precision form (hs_precision.hip)
+hipError_t launch_shadow(const IndexView& ix, int kind, uint16_t* rows, float2* norms, uint32_t* bad_flag,
+                         hipStream_t st);
+hipError_t launch_query_low(const IndexView& ix, int kind, int32_t Q, const QueryWs& ws, hipStream_t st);
+// grid of the bounding pass: at most `max_waves` wavefronts (one candidate slice each)
+int bound_grid(int32_t Q, int max_waves);
+hipError_t launch_bound(const IndexView& ix, const ShadowView& sv, const ScanParams& sp, const QueryWs& ws,
+                        hipStream_t st);
 
 }  // namespace hs

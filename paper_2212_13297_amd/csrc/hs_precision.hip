@@ -1,0 +1,443 @@
+// Precision form of the query path.  It computes the same exact k-NN as the
+// plain method (Hercules Sec. 3.3); only the per-series filter changes.  A
+// bf16 or fp16 copy x~ of every stored series feeds a matrix-core pass that
+// computes q~.x~ for every (query, series) pair of the candidate leaves, in
+// float32.  From it a rigorous lower bound of the true squared distance
+// follows (triangle inequality plus the accumulation error bound):
+//
+//   sqrt(d(q, x)) >= sqrt(d(q~, x~)) - eps_q - eps_x,   eps = ||v - v~||_2
+//   d(q~, x~) = ||q~||^2 + ||x~||^2 - 2 q~.x~
+//            >= (1 - g) (||q~||^2 + ||x~||^2) - 2 acc,  |acc - q~.x~| <= g ||q~|| ||x~||
+//
+// with g = K u' / (1 - K u'), K the accumulation length and u' = 2^-23 (twice
+// the float32 unit roundoff, so any rounding of the matrix core's additions is
+// covered; bf16 x bf16 and fp16 x fp16 products are exact in float32) and
+// 2 ||q~|| ||x~|| <= ||q~||^2 + ||x~||^2.  A pair is dropped only when that
+// bound exceeds BSF_k (1 + slack); a float32 test with proven margins discards
+// the clear cases, every pair it keeps is decided in float64, and the float64
+// bound travels with the candidate to the refinement (compensated float32).
+#include "hs_device.h"
+
+namespace hs {
+namespace {
+
+typedef __attribute__((__vector_size__(16 * sizeof(float)))) float f32x16;
+
+constexpr int kKBlock = 256;           // K elements staged per block
+constexpr int kKSteps = kKBlock / 16;  // 32x32x16 steps per block
+constexpr int kLdsRow = kKBlock + 8;   // 16-bit elements per staged row (padded against bank conflicts)
+
+template <int KIND>
+struct Low;
+
+template <>
+struct Low<kShadowBf16> {
+    typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 v8;
+    static __device__ __forceinline__ uint16_t encode(float v) {  // round to nearest even (finite v)
+        const uint32_t b = __float_as_uint(v);
+        return (uint16_t)((b + 0x7fffu + ((b >> 16) & 1u)) >> 16);
+    }
+    static __device__ __forceinline__ float decode(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
+    static __device__ __forceinline__ bool representable(float) { return true; }
+    static __device__ __forceinline__ f32x16 mma(uint4 a, uint4 b, f32x16 c) {
+        return __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(v8, a), __builtin_bit_cast(v8, b), c, 0, 0,
+                                                      0);
+    }
+};
+
+template <>
+struct Low<kShadowF16> {
+    typedef __attribute__((__vector_size__(8 * sizeof(_Float16)))) _Float16 v8;
+    static __device__ __forceinline__ uint16_t encode(float v) { return __builtin_bit_cast(uint16_t, (_Float16)v); }
+    static __device__ __forceinline__ float decode(uint16_t h) { return (float)__builtin_bit_cast(_Float16, h); }
+    static __device__ __forceinline__ bool representable(float v) { return fabsf(v) <= 65504.0f; }
+    static __device__ __forceinline__ f32x16 mma(uint4 a, uint4 b, f32x16 c) {
+        return __builtin_amdgcn_mfma_f32_32x32x16_f16(__builtin_bit_cast(v8, a), __builtin_bit_cast(v8, b), c, 0, 0,
+                                                     0);
+    }
+};
+
+// One wavefront per series: the low-precision copy and, in float64,
+// ||x~||^2 (stored rounded down) and ||x - x~||_2 (stored rounded up).
+template <int KIND>
+__global__ void __launch_bounds__(256) k_shadow(IndexView ix, uint16_t* __restrict__ out, float2* __restrict__ norms,
+                                                uint32_t* __restrict__ bad) {
+    const int lane = threadIdx.x & 63;
+    const int64_t w0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int64_t nw = ((int64_t)gridDim.x * blockDim.x) >> 6;
+    for (int64_t r = w0; r < ix.N; r += nw) {
+        const float* xr = ix.rows + r * ix.stride;
+        uint16_t* orow = out + r * ix.stride;
+        double s2 = 0.0, e2 = 0.0;
+        bool ok = true;
+        for (int j = lane; j < ix.stride; j += 64) {
+            const float v = xr[j];
+            ok = ok && Low<KIND>::representable(v);
+            const uint16_t h = Low<KIND>::encode(v);
+            const double lv = (double)Low<KIND>::decode(h);
+            orow[j] = h;
+            s2 += lv * lv;
+            const double e = (double)v - lv;
+            e2 += e * e;
+        }
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) {
+            s2 += __shfl_xor(s2, o, 64);
+            e2 += __shfl_xor(e2, o, 64);
+        }
+        if (__ballot(!ok) != 0ull && lane == 0) atomicOr(bad, 1u);
+        // float64 sums carry a relative error below 2^-40 for any stride the
+        // index accepts; the factors push the stored values past it
+        if (lane == 0)
+            norms[r] = make_float2(__double2float_rd(s2 * (1.0 - 0x1p-40)), __double2float_ru(sqrt(e2) * (1.0 + 0x1p-40)));
+    }
+}
+
+// One wavefront per (padded) query: q~, ||q~||^2 and ||q - q~||_2 in float64.
+template <int KIND>
+__global__ void __launch_bounds__(64) k_query_low(IndexView ix, int32_t Q, QueryWs ws) {
+    const int q = blockIdx.x, lane = threadIdx.x;
+    uint16_t* orow = ws.qlow + (int64_t)q * ix.stride;
+    if (q >= Q) {
+        for (int j = lane; j < ix.stride; j += 64) orow[j] = 0;
+        return;
+    }
+    const float* qr = ws.qrow + (int64_t)q * ix.stride;
+    double s2 = 0.0, e2 = 0.0;
+    bool ok = true;
+    for (int j = lane; j < ix.stride; j += 64) {
+        const float v = qr[j];
+        ok = ok && Low<KIND>::representable(v);
+        const uint16_t h = Low<KIND>::encode(v);
+        const double lv = (double)Low<KIND>::decode(h);
+        orow[j] = h;
+        s2 += lv * lv;
+        const double e = (double)v - lv;
+        e2 += e * e;
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        s2 += __shfl_xor(s2, o, 64);
+        e2 += __shfl_xor(e2, o, 64);
+    }
+    // a query outside the fp16 range is reported like a non-finite one
+    if (__ballot(!ok) != 0ull && lane == 0 && !(ws.flags[q] & kFlagNonFinite)) {
+        ws.flags[q] |= kFlagNonFinite;
+        atomicAdd(&ws.counters[kCtrNonFinite], 1u);
+    }
+    if (lane == 0) ws.qnorm[q] = make_double2(s2 * (1.0 - 0x1p-40), sqrt(e2) * (1.0 + 0x1p-40));
+}
+
+// Constants of the float32 test (derivation in the header comment of the
+// bounding kernel below).
+struct BoundConsts {
+    float k1;   // 1 - g, rounded down
+    float k2;   // 1 + 8u
+    float k3;   // 8u
+    double g;   // g for the float64 decision (plus 2^-40 for the float64 norms)
+};
+
+// Which q-group and row range a workgroup takes.  With enough workgroups the
+// G q-groups of one row range run on the same XCD (workgroup b sits on XCD
+// b % 8), next to each other in launch order, so the staged series are read
+// from HBM about once and from that XCD's L2 by the other q-groups.
+struct BoundMap {
+    int R;   // row ranges
+    int G;   // q-groups (kBoundQueries queries each)
+    int GS;  // q-group stride of one workgroup
+    int used;
+    int xcd_aware;
+};
+
+__device__ __forceinline__ void bound_block(const BoundMap& m, int b, int& g0, int& r) {
+    if (m.xcd_aware) {
+        const int x = b & 7, tt = b >> 3;
+        g0 = tt % m.G;
+        r = (tt / m.G) * 8 + x;
+    } else {
+        g0 = b % m.GS;
+        r = b / m.GS;
+    }
+}
+
+// The bounding pass.  Workgroup = 4 wavefronts x 32 queries (one q-group);
+// it walks its row range part by part (a part lies in one leaf) in tiles of
+// 32 series.  Per tile and K-block the 32 x 256 low-precision series are
+// staged in LDS (double buffered: the next stage's global loads are in flight
+// during this stage's matrix-core steps) and every wavefront computes the
+// 32 x 32 block acc[series][query] with 16 v_mfma 32x32x16 steps; its query
+// fragments stay in registers when the series fit one K-block.
+//
+// Output layout of the 32x32 block: lane l holds query (l mod 32) and, in
+// accumulator r, series 8 (r / 4) + 4 (l / 32) + (r mod 4).
+//
+// Float32 test, per pair (u = 2^-24, T = ||q~||^2 + ||x~||^2 from the stored,
+// rounded-down norms, sT = sqrt(BSF_k (1 + slack)) + eps_q rounded up):
+//   a   = fma(-2, acc, fl(T) k1)          a   <= d(q~, x~) + 4.1 u T
+//   rhs = fma((sT + eps_x)^2, k2, T k3)    rhs >= (sT + eps_x)^2 + 7.9 u T
+// a > rhs therefore implies sqrt(d(q~, x~)) > sT + eps_x, i.e. the bound
+// exceeds BSF_k (1 + slack): the pair is dropped.  Otherwise the bound is
+// evaluated in float64 and decides.
+template <int KIND>
+__global__ void __launch_bounds__(256) k_bound(IndexView ix, ShadowView sv, ScanParams sp, QueryWs ws,
+                                               BoundConsts bc, BoundMap bm) {
+#pragma clang fp contract(off)
+    __shared__ __attribute__((aligned(16))) uint16_t s_tile[2][kBoundRows * kLdsRow];
+    __shared__ float2 s_norm[2][kBoundRows];
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6, j = lane & 31, half = lane >> 5;
+    const int K = ix.stride, nkb = (K + kKBlock - 1) / kKBlock;
+    const uint64_t lt_mask = (1ull << lane) - 1ull;
+
+    const int64_t slice = (int64_t)blockIdx.x * (kTile / 64) + wave;
+    uint32_t* spos = ws.slice_pos + slice * ws.slice_cap;
+    uint32_t* sq = ws.slice_q + slice * ws.slice_cap;
+    float* slb = ws.slice_lb + slice * ws.slice_cap;
+    uint32_t cnt = 0;  // entries in this wavefront's slice (uniform)
+
+    if ((int)blockIdx.x < bm.used) {
+        int g0, r;
+        bound_block(bm, blockIdx.x, g0, r);
+        const int64_t row0 = ix.N * r / bm.R, row1 = ix.N * (r + 1) / bm.R;
+        // first part that ends after row0
+        int64_t lo = 0, hi = ix.parts;
+        while (lo < hi) {
+            const int64_t mid = (lo + hi) >> 1;
+            if (ix.part_start[mid + 1] <= row0) lo = mid + 1;
+            else hi = mid;
+        }
+        const int64_t p_first = lo;
+
+        for (int g = g0; g < bm.G; g += bm.GS) {
+            const int qj = g * kBoundQueries + wave * 32 + j;
+            const bool qvalid = qj < sp.Q && !(ws.flags[qj] & kFlagNonFinite);
+            float qn32 = 0.0f, sT = 0.0f, bsf_j = 0.0f;
+            if (qvalid) {
+                const double2 qn = ws.qnorm[qj];
+                bsf_j = bits_to_float(ws.bsf[qj]);
+                qn32 = __double2float_rd(qn.x);
+                sT = __double2float_ru((sqrt(prune_limit(bsf_j)) + qn.y) * (1.0 + 0x1p-40));
+            }
+            const uint16_t* qlow = ws.qlow + (int64_t)(g * kBoundQueries + wave * 32 + j) * K + 8 * half;
+            uint4 bq[kKSteps];
+            if (nkb == 1) {
+#pragma unroll
+                for (int s = 0; s < kKSteps; ++s)
+                    bq[s] = s * 16 < K ? *reinterpret_cast<const uint4*>(qlow + s * 16) : make_uint4(0, 0, 0, 0);
+            }
+            unsigned long long tested = 0, cands = 0;
+            bool lost = false;
+
+            for (int64_t p = p_first; p < ix.parts && ix.part_start[p] < row1; ++p) {
+                const int64_t ps = max(ix.part_start[p], row0), pe = min(ix.part_start[p + 1], row1);
+                if (pe <= ps) continue;
+                const int64_t leaf = ix.part_leaf[p];
+                const bool keep = qvalid && (double)ws.lbe[(int64_t)qj * ix.L + leaf] <= prune_limit(bsf_j);
+                const bool wkeep = __ballot(keep) != 0ull;
+                if (!__syncthreads_or(wkeep ? 1 : 0)) continue;
+                const int64_t ntiles = (pe - ps + kBoundRows - 1) / kBoundRows;
+                const int64_t nst = ntiles * nkb;
+
+                // stage s: tile s / nkb, K-block s % nkb.  Thread t moves uint4
+                // number t + 256 i (i < 4) of the 32 x 256 block: row (that / 32),
+                // 8-element column (that % 32); rows past the collection are
+                // clamped (their results are masked).
+                uint4 pre[4];
+                float2 pre_n = make_float2(0.f, 0.f);
+                auto stage_load = [&](int64_t s) {
+                    const int64_t tr0 = ps + (s / nkb) * kBoundRows;
+                    const int kb = (int)(s % nkb);
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) {
+                        const int e = t + 256 * i, rr = e >> 5, cc = (e & 31) * 8 + kb * kKBlock;
+                        const int64_t row = min(tr0 + rr, ix.N - 1);
+                        pre[i] = cc < K ? *reinterpret_cast<const uint4*>(sv.rows + row * K + cc) : make_uint4(0, 0, 0, 0);
+                    }
+                    if (kb == 0 && t < kBoundRows) pre_n = sv.norms[min(tr0 + t, ix.N - 1)];
+                };
+                auto stage_store = [&](int64_t s) {
+                    uint16_t* dst = s_tile[s & 1];
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) {
+                        const int e = t + 256 * i, rr = e >> 5, cc = (e & 31) * 8;
+                        *reinterpret_cast<uint4*>(dst + rr * kLdsRow + cc) = pre[i];
+                    }
+                    if ((s % nkb) == 0 && t < kBoundRows) s_norm[(s / nkb) & 1][t] = pre_n;
+                };
+                stage_load(0);
+                stage_store(0);
+                __syncthreads();
+                f32x16 acc = {};
+                for (int64_t s = 0; s < nst; ++s) {
+                    const int64_t tile = s / nkb;
+                    const int kb = (int)(s % nkb);
+                    if (s + 1 < nst) stage_load(s + 1);
+                    if (wkeep) {
+                        if (nkb > 1) {
+#pragma unroll
+                            for (int u = 0; u < kKSteps; ++u) {
+                                const int c = kb * kKBlock + u * 16;
+                                bq[u] = c < K ? *reinterpret_cast<const uint4*>(qlow + c) : make_uint4(0, 0, 0, 0);
+                            }
+                        }
+                        const uint16_t* arow = s_tile[s & 1] + j * kLdsRow + 8 * half;
+#pragma unroll
+                        for (int u = 0; u < kKSteps; ++u)
+                            acc = Low<KIND>::mma(*reinterpret_cast<const uint4*>(arow + u * 16), bq[u], acc);
+                    }
+                    if (kb == nkb - 1) {
+                        if (wkeep) {
+                            const int64_t tr0 = ps + tile * kBoundRows;
+                            const int nrows = (int)min((int64_t)kBoundRows, pe - tr0);
+                            if (keep && half == 0) tested += (unsigned long long)nrows;
+                            const float2* nrm = s_norm[tile & 1];
+                            uint32_t mask = 0;
+#pragma unroll
+                            for (int r = 0; r < 16; ++r) {
+                                const int i = 8 * (r >> 2) + 4 * half + (r & 3);
+                                const float2 nm = nrm[i];
+                                const float tt = qn32 + nm.x;
+                                const float a = fmaf(-2.0f, acc[r], tt * bc.k1);
+                                const float sx = sT + nm.y;
+                                const float rhs = fmaf(sx * sx, bc.k2, tt * bc.k3);
+                                if (keep && i < nrows && a <= rhs) mask |= 1u << r;
+                            }
+                            if (__ballot(mask != 0u) != 0ull) {
+                                // float64 decision on the pairs the float32 test kept
+                                double2 qn = make_double2(0.0, 0.0);
+                                if (mask) qn = ws.qnorm[qj];
+                                const double lim = prune_limit(bsf_j);
+                                uint32_t fm = 0;
+                                for (int r = 0; r < 16; ++r) {
+                                    if (!((mask >> r) & 1u)) continue;
+                                    const int i = 8 * (r >> 2) + 4 * half + (r & 3);
+                                    const float2 nm = nrm[i];
+                                    const double D = (1.0 - bc.g) * (qn.x + (double)nm.x) - 2.0 * (double)acc[r];
+                                    const double lr = fmax(sqrt(fmax(D, 0.0)) - qn.y - (double)nm.y, 0.0);
+                                    if (lr * lr <= lim) fm |= 1u << r;
+                                }
+                                uint32_t total = 0;
+#pragma unroll
+                                for (int r = 0; r < 16; ++r) total += (uint32_t)__popcll(__ballot((fm >> r) & 1u));
+                                if (total) {
+                                    uint32_t* dpos = spos;
+                                    uint32_t* dq = sq;
+                                    float* dlb = slb;
+                                    uint32_t off = cnt;
+                                    const bool own = (int64_t)cnt + total <= ws.slice_cap;
+                                    bool ok = true;
+                                    if (!own) {
+                                        // private slice full: a range of the shared overflow
+                                        // slice, as in the LB_SAX filter
+                                        long long b = -1;
+                                        if (lane == 0) {
+                                            uint32_t* oc = &ws.counters[kCtrOvf];
+                                            if ((int64_t)load_relaxed(oc) < ws.ovf_cap) {
+                                                const uint32_t rr = atomicAdd(oc, total);
+                                                if ((int64_t)rr + total <= ws.ovf_cap) b = rr;
+                                                else atomicMin(&ws.counters[kCtrOvfEnd], rr);
+                                            }
+                                        }
+                                        b = __shfl(b, 0, 64);
+                                        if (b < 0) {
+                                            ok = false;
+                                            if (fm) lost = true;
+                                        } else {
+                                            const int64_t ob = (int64_t)ws.n_slices * ws.slice_cap;
+                                            dpos = ws.slice_pos + ob;
+                                            dq = ws.slice_q + ob;
+                                            dlb = ws.slice_lb + ob;
+                                            off = (uint32_t)b;
+                                        }
+                                    }
+                                    if (ok) {
+                                        for (int r = 0; r < 16; ++r) {
+                                            const uint64_t bal = __ballot((fm >> r) & 1u);
+                                            if ((fm >> r) & 1u) {
+                                                const int i = 8 * (r >> 2) + 4 * half + (r & 3);
+                                                const float2 nm = nrm[i];
+                                                const double D =
+                                                    (1.0 - bc.g) * (qn.x + (double)nm.x) - 2.0 * (double)acc[r];
+                                                const double lr =
+                                                    fmax(sqrt(fmax(D, 0.0)) - qn.y - (double)nm.y, 0.0);
+                                                const uint32_t slot = off + (uint32_t)__popcll(bal & lt_mask);
+                                                dpos[slot] = (uint32_t)(tr0 + i);
+                                                dq[slot] = (uint32_t)qj;
+                                                dlb[slot] = __double2float_rd(lr * lr);
+                                            }
+                                            off += (uint32_t)__popcll(bal);
+                                        }
+                                        if (own) cnt += total;
+                                        cands += (unsigned long long)__popc(fm);
+                                    }
+                                }
+                            }
+                        }
+                        acc = f32x16{};
+                    }
+                    if (s + 1 < nst) stage_store(s + 1);
+                    __syncthreads();
+                }
+            }
+            // per-query counters: lanes l and l + 32 hold the same query
+            cands += __shfl_down(cands, 32, 64);
+            if (half == 0 && qvalid) {
+                if (tested) atomicAdd(&ws.stats[(int64_t)qj * 8 + 1], tested);
+                if (cands) atomicAdd(&ws.stats[(int64_t)qj * 8 + 6], cands);
+            }
+            if (lost) atomicOr(&ws.flags[qj], kFlagCandLost);
+        }
+    }
+    if (lane == 0) ws.slice_cnt[slice] = cnt;
+}
+
+}  // namespace
+
+hipError_t launch_shadow(const IndexView& ix, int kind, uint16_t* rows, float2* norms, uint32_t* bad_flag,
+                         hipStream_t st) {
+    const int grid = grid_for(ix.N * 64, 256, 1 << 16);
+    if (kind == kShadowF16)
+        k_shadow<kShadowF16><<<dim3(grid), dim3(256), 0, st>>>(ix, rows, norms, bad_flag);
+    else
+        k_shadow<kShadowBf16><<<dim3(grid), dim3(256), 0, st>>>(ix, rows, norms, bad_flag);
+    return hipGetLastError();
+}
+
+hipError_t launch_query_low(const IndexView& ix, int kind, int32_t Q, const QueryWs& ws, hipStream_t st) {
+    if (kind == kShadowF16)
+        k_query_low<kShadowF16><<<dim3(ws.Qpad), dim3(64), 0, st>>>(ix, Q, ws);
+    else
+        k_query_low<kShadowBf16><<<dim3(ws.Qpad), dim3(64), 0, st>>>(ix, Q, ws);
+    return hipGetLastError();
+}
+
+hipError_t launch_bound(const IndexView& ix, const ShadowView& sv, const ScanParams& sp, const QueryWs& ws,
+                        hipStream_t st) {
+    const int grid = ws.n_slices / (kTile / 64);  // one candidate slice per wavefront
+    BoundMap bm{};
+    bm.G = ws.Qpad / kBoundQueries;
+    if (bm.G * 8 <= grid) {
+        bm.xcd_aware = 1;
+        bm.GS = bm.G;
+        bm.R = 8 * (grid / (8 * bm.G));
+    } else {
+        bm.xcd_aware = 0;
+        bm.GS = bm.G < grid ? bm.G : grid;
+        bm.R = grid / bm.GS;
+    }
+    bm.used = bm.R * bm.GS;
+    // g: accumulation error factor for K additions at twice the unit roundoff
+    const double u2 = std::ldexp(1.0, -23), Kd = (double)ix.stride;
+    const double g = Kd * u2 / (1.0 - Kd * u2);
+    BoundConsts bc;
+    bc.k1 = std::nextafter((float)(1.0 - g), 0.0f);
+    bc.k2 = (float)(1.0 + 8.0 * std::ldexp(1.0, -24)) ;
+    bc.k3 = (float)(8.0 * std::ldexp(1.0, -24));
+    bc.g = g + std::ldexp(1.0, -40);
+    if (sv.kind == kShadowF16)
+        k_bound<kShadowF16><<<dim3(grid), dim3(kTile), 0, st>>>(ix, sv, sp, ws, bc, bm);
+    else
+        k_bound<kShadowBf16><<<dim3(grid), dim3(kTile), 0, st>>>(ix, sv, sp, ws, bc, bm);
+    return hipGetLastError();
+}
+
+}  // namespace hs

@@ -94,7 +94,7 @@ __global__ void __launch_bounds__(256) k_lb_eapca(IndexView ix, QueryWs ws) {
 // (smallest LB_EAPCA) but only their series with the smallest LB_SAX are
 // refined -- at least max(seed_rows, 2k) of them, cut at a histogram bin of
 // LB_SAX values.  The k best become the first pool entries and BSF_k.
-template <int W16>
+template <int W16, int F>
 __global__ void __launch_bounds__(256) k_seed(IndexView ix, ScanParams sp, QueryWs ws) {
     extern __shared__ float s_lut[];  // [w][256]
     __shared__ unsigned long long s_top[HS_KMAX];
@@ -180,7 +180,7 @@ __global__ void __launch_bounds__(256) k_seed(IndexView ix, ScanParams sp, Query
             for (int h = grp; h < nh; h += kTile / 16) {
                 const int64_t pos = b + s_hits[h];
                 bool alive;
-                const float d = refine_row(ix.rows + pos * ix.stride + sub * 4,
+                const float d = refine_row<F>(ix.rows + pos * ix.stride + sub * 4,
                                            ws.qrow + (int64_t)q * ix.stride + sub * 4, nchunks, thr, alive,
                                            my_chunks);
                 if (sub == 0) {
@@ -258,6 +258,7 @@ __global__ void __launch_bounds__(256) k_emit(IndexView ix, ScanParams sp, int32
 
 __global__ void __launch_bounds__(1024) k_merge(IndexView ix, ScanParams sp, int32_t redo_only, QueryWs ws,
                                                 int64_t* __restrict__ ids_out, float* __restrict__ d2_out,
+                                                double* __restrict__ err_out, double err_rel,
                                                 hs_query_stats* __restrict__ stats_out) {
     extern __shared__ unsigned long long s_keys[];  // [P]
     __shared__ int s_u;
@@ -316,11 +317,14 @@ __global__ void __launch_bounds__(1024) k_merge(IndexView ix, ScanParams sp, int
     if (sp.final_pass) {
         for (int j = t; j < k; j += blockDim.x) {
             if (j < u) {
+                const float d = bits_to_float((uint32_t)(s_keys[j] >> 32));
                 ids_out[(int64_t)q * k + j] = (int64_t)(s_keys[j] & 0xffffffffull);
-                d2_out[(int64_t)q * k + j] = bits_to_float((uint32_t)(s_keys[j] >> 32));
+                d2_out[(int64_t)q * k + j] = d;
+                if (err_out) err_out[(int64_t)q * k + j] = err_rel * (double)d;
             } else {
                 ids_out[(int64_t)q * k + j] = -1;
                 d2_out[(int64_t)q * k + j] = INFINITY;
+                if (err_out) err_out[(int64_t)q * k + j] = INFINITY;
             }
         }
         if (stats_out && t == 0) {
@@ -372,10 +376,14 @@ hipError_t launch_lb_eapca(const IndexView& ix, int32_t Q, const QueryWs& ws, hi
     return hipGetLastError();
 }
 
-hipError_t launch_seed(const IndexView& ix, const ScanParams& sp, const QueryWs& ws, hipStream_t st) {
+hipError_t launch_seed(const IndexView& ix, const ScanParams& sp, const QueryWs& ws, int form, hipStream_t st) {
     if (sp.n_seed <= 0) return hipSuccess;
     const size_t lds = sizeof(float) * (size_t)ix.w * kCard;
-    HS_DISPATCH_W16(ix, k_seed, dim3(sp.Q), dim3(kTile), lds, st, ix, sp, ws);
+    if (form == kComp) {
+        HS_DISPATCH_W16_F(ix, k_seed, kComp, dim3(sp.Q), dim3(kTile), lds, st, ix, sp, ws);
+    } else {
+        HS_DISPATCH_W16_F(ix, k_seed, kPlain, dim3(sp.Q), dim3(kTile), lds, st, ix, sp, ws);
+    }
     return hipGetLastError();
 }
 
@@ -391,9 +399,10 @@ hipError_t launch_emit(const IndexView& ix, const ScanParams& sp, bool redo_only
 }
 
 hipError_t launch_merge(const IndexView& ix, const ScanParams& sp, bool redo_only, const QueryWs& ws,
-                        int64_t* ids_out, float* d2_out, hs_query_stats* stats_out, hipStream_t st) {
+                        int64_t* ids_out, float* d2_out, double* err_out, double err_rel,
+                        hs_query_stats* stats_out, hipStream_t st) {
     hipLaunchKernelGGL(k_merge, dim3(sp.Q), dim3(1024), sizeof(unsigned long long) * ws.P, st, ix, sp,
-                       redo_only ? 1 : 0, ws, ids_out, d2_out, stats_out);
+                       redo_only ? 1 : 0, ws, ids_out, d2_out, err_out, err_rel, stats_out);
     return hipGetLastError();
 }
 

@@ -34,6 +34,7 @@ __device__ __forceinline__ Meta load_meta(const QueryWs& ws, long long c, long l
     return m;
 }
 
+template <int F>
 __global__ void __launch_bounds__(256) k_refine(IndexView ix, ScanParams sp, QueryWs ws) {
     __shared__ unsigned long long s_top[kTile / 64][HS_KMAX];
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6, sub = t & 15, grp = (t >> 4) & 3;
@@ -64,7 +65,8 @@ __global__ void __launch_bounds__(256) k_refine(IndexView ix, ScanParams sp, Que
         {
             int q[4];
             uint32_t pos[4];
-            float thr[4], d[4];
+            float thr[4];
+            Dist<F> d[4];
             bool alive[4], refined[4];
             unsigned ch[4] = {0u, 0u, 0u, 0u};
 #pragma unroll
@@ -77,7 +79,6 @@ __global__ void __launch_bounds__(256) k_refine(IndexView ix, ScanParams sp, Que
                 if (q[j] == cur_q) thr[j] = fminf(thr[j], lk);
                 refined[j] = q[j] >= 0 && (double)lb <= prune_limit(thr[j]);
                 alive[j] = refined[j];
-                d[j] = 0.0f;
             }
             for (int c = 0; c < nchunks; c += 2) {
                 const bool two = c + 1 < nchunks;
@@ -108,17 +109,17 @@ __global__ void __launch_bounds__(256) k_refine(IndexView ix, ScanParams sp, Que
                             a = *reinterpret_cast<const float4*>(qr);
                             if (two) b = *reinterpret_cast<const float4*>(qr + kChunk);
                         }
-                        d[j] += chunk_partial(a, x0[j]);
-                        if (two) d[j] += chunk_partial(b, x1[j]);
+                        d[j].add(a, x0[j]);
+                        if (two) d[j].add(b, x1[j]);
                         ch[j] += two ? 2u : 1u;
-                        if (d[j] > thr[j]) alive[j] = false;
+                        if (d[j].value() > thr[j]) alive[j] = false;
                     }
                 }
             }
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
                 chs[j] = refined[j] ? ch[j] : 0u;
-                res[j] = (refined[j] && alive[j]) ? (((unsigned long long)__float_as_uint(d[j]) << 32) | ix.ids[pos[j]])
+                res[j] = (refined[j] && alive[j]) ? (((unsigned long long)__float_as_uint(d[j].value()) << 32) | ix.ids[pos[j]])
                                                   : ~0ull;
                 resq[j] = q[j];
             }
@@ -179,10 +180,12 @@ __global__ void __launch_bounds__(256) k_refine(IndexView ix, ScanParams sp, Que
 
 }  // namespace
 
-hipError_t launch_refine(const IndexView& ix, const ScanParams& sp, const QueryWs& ws, int device_cus,
+hipError_t launch_refine(const IndexView& ix, const ScanParams& sp, const QueryWs& ws, int device_cus, int form,
                          hipStream_t st) {
-    hipLaunchKernelGGL(k_refine, dim3(resident_grid(k_refine, kTile, 0, device_cus)), dim3(kTile), 0, st, ix, sp,
-                       ws);
+    if (form == kComp)
+        k_refine<kComp><<<dim3(resident_grid(k_refine<kComp>, kTile, 0, device_cus)), dim3(kTile), 0, st>>>(ix, sp, ws);
+    else
+        k_refine<kPlain><<<dim3(resident_grid(k_refine<kPlain>, kTile, 0, device_cus)), dim3(kTile), 0, st>>>(ix, sp, ws);
     return hipGetLastError();
 }
 

@@ -18,7 +18,7 @@ struct ScanShared {
     unsigned int st_filt, st_ref, st_chunks;
 };
 
-template <int W16>
+template <int W16, int F>
 __global__ void __launch_bounds__(256) k_leaf_scan(IndexView ix, ScanParams sp, QueryWs ws) {
     extern __shared__ float s_dyn[];
     __shared__ ScanShared sh;
@@ -76,7 +76,7 @@ __global__ void __launch_bounds__(256) k_leaf_scan(IndexView ix, ScanParams sp, 
             for (int h = grp; h < nh; h += kTile / 16) {
                 const int64_t pos = b + sh.hits[h];
                 bool alive;
-                const float d = refine_row(ix.rows + pos * ix.stride + sub * 4, s_q + sub * 4, nchunks, thr, alive,
+                const float d = refine_row<F>(ix.rows + pos * ix.stride + sub * 4, s_q + sub * 4, nchunks, thr, alive,
                                            my_chunks);
                 if (sub == 0) {
                     ++my_ref;
@@ -117,10 +117,14 @@ __global__ void __launch_bounds__(256) k_leaf_scan(IndexView ix, ScanParams sp, 
 
 }  // namespace
 
-hipError_t launch_leaf_scan(const IndexView& ix, const ScanParams& sp, const QueryWs& ws, int device_cus,
+hipError_t launch_leaf_scan(const IndexView& ix, const ScanParams& sp, const QueryWs& ws, int device_cus, int form,
                             hipStream_t st) {
     const size_t lds = sizeof(float) * ((size_t)ix.stride + (size_t)ix.w * kCard);
-    HS_LAUNCH_RESIDENT(ix, k_leaf_scan, lds, device_cus, st, ix, sp, ws);
+    if (form == kComp) {
+        HS_LAUNCH_RESIDENT_F(ix, k_leaf_scan, kComp, lds, device_cus, st, ix, sp, ws);
+    } else {
+        HS_LAUNCH_RESIDENT_F(ix, k_leaf_scan, kPlain, lds, device_cus, st, ix, sp, ws);
+    }
     return hipGetLastError();
 }
 

@@ -21,6 +21,8 @@ HS_ENOMEM = -2
 HS_EHIP = -3
 HS_EBUSY = -4
 HS_KMAX = 128
+HS_SHADOW_BF16 = 1
+HS_SHADOW_FP16 = 2
 
 
 class hs_params(ctypes.Structure):
@@ -54,6 +56,10 @@ _SIGS = {
     "hs_get_chunks": (ctypes.c_int32, [_P, _P, _P]),
     "hs_query_workspace_bytes": (ctypes.c_int32, [_P, ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(ctypes.c_int64)]),
     "hs_knn_exact": (ctypes.c_int32, [_P, _P, ctypes.c_int32, ctypes.c_int32, _P, ctypes.c_int64, _P, _P, _P, _P]),
+    "hs_shadow_bytes": (ctypes.c_int32, [_P, ctypes.c_int32, ctypes.POINTER(ctypes.c_int64)]),
+    "hs_build_shadow": (ctypes.c_int32, [_P, ctypes.c_int32, _P, ctypes.c_int64, _P]),
+    "hs_knn_mixed": (ctypes.c_int32, [_P, _P, ctypes.c_int32, ctypes.c_int32, _P, ctypes.c_int64, _P, _P, _P, _P,
+                                      _P]),
     "hs_index_free": (ctypes.c_int32, [_P]),
     "hs_last_error": (ctypes.c_char_p, []),
     "hs_breakpoints": (ctypes.c_int32, [ctypes.c_int32, _P]),
@@ -138,6 +144,21 @@ def hs_knn_exact(h, q_ptr: int, Q: int, k: int, ws_ptr: int, ws_bytes: int, ids_
     _check(load().hs_knn_exact(h, q_ptr, Q, k, ws_ptr, ws_bytes, ids_ptr, d2_ptr, stats_ptr, stream))
 
 
+def hs_shadow_bytes(h, kind: int) -> int:
+    out = ctypes.c_int64()
+    _check(load().hs_shadow_bytes(h, kind, ctypes.byref(out)))
+    return out.value
+
+
+def hs_build_shadow(h, kind: int, mem_ptr: int, mem_bytes: int, stream: int) -> None:
+    _check(load().hs_build_shadow(h, kind, mem_ptr, mem_bytes, stream))
+
+
+def hs_knn_mixed(h, q_ptr: int, Q: int, k: int, ws_ptr: int, ws_bytes: int, ids_ptr: int, d2_ptr: int,
+                 err_ptr: int, stats_ptr: int, stream: int) -> None:
+    _check(load().hs_knn_mixed(h, q_ptr, Q, k, ws_ptr, ws_bytes, ids_ptr, d2_ptr, err_ptr, stats_ptr, stream))
+
+
 def hs_index_free(h) -> None:
     _check(load().hs_index_free(h))
 
@@ -157,8 +178,8 @@ def hs_profile_enable(on: bool) -> None:
     _check(load().hs_profile_enable(1 if on else 0))
 
 
-HS_PROF_FILTER, HS_PROF_REFINE, HS_PROF_FUSED = 0, 1, 2
-PROF_KINDS = {"filter": HS_PROF_FILTER, "refine": HS_PROF_REFINE, "fused": HS_PROF_FUSED}
+HS_PROF_FILTER, HS_PROF_REFINE, HS_PROF_FUSED, HS_PROF_BOUND = 0, 1, 2, 3
+PROF_KINDS = {"filter": HS_PROF_FILTER, "refine": HS_PROF_REFINE, "fused": HS_PROF_FUSED, "bound": HS_PROF_BOUND}
 
 
 def hs_profile_read(kind: int, reset: bool = False):
@@ -213,6 +234,16 @@ class Index:
         self.h = hs_build_summaries(x.data_ptr(), N, cp, self.mem.data_ptr(), nbytes, _stream_ptr(stream))
         self.info = hs_get_info(self.h)
         self._ws = None
+        self.shadow = None
+        self.shadow_kind = 0
+
+    def build_shadow(self, kind: int = HS_SHADOW_BF16, stream=None):
+        """Build the low-precision copy that the precision form (knn_mixed) reads."""
+        import torch
+        nbytes = hs_shadow_bytes(self.h, kind)
+        mem = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        hs_build_shadow(self.h, kind, mem.data_ptr(), nbytes, _stream_ptr(stream))
+        self.shadow, self.shadow_kind = mem, kind
 
     def layout(self):
         """Views of the stored arrays inside the index memory (rows, ids, words)
@@ -238,13 +269,32 @@ class Index:
             self._ws = torch.empty(need, dtype=torch.uint8, device=self.device)
         return self._ws, need
 
-    def knn(self, q, k: int, stats: bool = False, stream=None, out=None):
-        """Exact k-NN: returns (ids int64 [Q, k], d2 float32 [Q, k]) [, stats dict of tensors]."""
+    def _check_q(self, q):
         import torch
         if not (q.is_cuda and q.dtype == torch.float32 and q.dim() == 2 and q.shape[1] == self.n
                 and q.is_contiguous()):
             raise ValueError("q must be a contiguous float32 [Q, n] GPU tensor")
-        Q = q.shape[0]
+        return q.shape[0]
+
+    def knn_mixed(self, q, k: int, stats: bool = False, stream=None):
+        """Exact k-NN through the precision form: (ids, d2, err float64 [Q, k]) [, stats]."""
+        import torch
+        Q = self._check_q(q)
+        ws, nbytes = self.workspace(Q, k)
+        ids = torch.empty((Q, k), dtype=torch.int64, device=self.device)
+        d2 = torch.empty((Q, k), dtype=torch.float32, device=self.device)
+        err = torch.empty((Q, k), dtype=torch.float64, device=self.device)
+        st = torch.zeros((Q, 8), dtype=torch.int64, device=self.device) if stats else None
+        hs_knn_mixed(self.h, q.data_ptr(), Q, k, ws.data_ptr(), nbytes, ids.data_ptr(), d2.data_ptr(),
+                     err.data_ptr(), st.data_ptr() if st is not None else None, _stream_ptr(stream))
+        if stats:
+            return ids, d2, err, {f: st[:, i] for i, f in enumerate(STATS_FIELDS)}
+        return ids, d2, err
+
+    def knn(self, q, k: int, stats: bool = False, stream=None, out=None):
+        """Exact k-NN: returns (ids int64 [Q, k], d2 float32 [Q, k]) [, stats dict of tensors]."""
+        import torch
+        Q = self._check_q(q)
         ws, nbytes = self.workspace(Q, k)
         if out is None:
             ids = torch.empty((Q, k), dtype=torch.int64, device=self.device)
