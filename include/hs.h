@@ -2,7 +2,7 @@
  * hs.h -- C ABI of the HIP library for exact data-series k-NN search
  * (filter-and-refine over a collection resident in GPU memory).
  *
- * Method: Hercules (Echihabi et al., PVLDB 15(10), 2022), Sec. 3.3 query
+ * Method: Hercules (Echihabi et al., PVLDB 15(10), 2022), Sec. 3.4 query
  * answering: a per-leaf LB_EAPCA bound over segment mean/std envelopes, a
  * per-series LB_SAX bound (PAA over w segments against Gaussian breakpoints,
  * alphabet 256), and exact squared-Euclidean refinement with a running k-th
@@ -52,15 +52,15 @@ typedef int32_t hs_status;
  *  w          PAA / iSAX segments, 1 <= w <= 64, w divides n (Sec. 2: PAA
  *             uses equal-length segments; the paper uses 16).
  *  card_bits  bits per iSAX symbol; must be 8 (alphabet 256, Sec. 2).
- *  leaf_size  leaf capacity tau (Sec. 3.1): a node holding more than tau
+ *  leaf_size  leaf capacity tau (Sec. 3.2): a node holding more than tau
  *             series is split, unless no H-split separates its series.
  *  l_max      leaves visited by the approximate search that seeds BSF_k
- *             (Sec. 3.3 step 1; the paper's default is 1), 0 <= l_max;
+ *             (Sec. 3.4 step 1; the paper's default is 1), 0 <= l_max;
  *             values above 64 are treated as 64.  0 = no seed.
  *  seed_rows  series of those leaves refined by the seed: the ones with the
  *             smallest LB_SAX, at least max(seed_rows, 2k) of them (the
  *             paper refines the whole leaves).  Access-path choice only.
- *  eapca_th   Sec. 3.3 threshold: a query whose leaf pruning ratio is below
+ *  eapca_th   Sec. 3.4 threshold: a query whose leaf pruning ratio is below
  *             it skips the LB_SAX filter and scans its candidate leaves.
  *             Access-path choice only; results do not depend on it.
  *  cand_per_query  candidate-list entries reserved per query in the query
@@ -97,7 +97,7 @@ typedef struct {
 
 /*
  * Device bytes hs_build_summaries needs in `index_mem_dev` for N series:
- * the leaf-ordered copy of the series (the LRDFile analogue, Sec. 3.1),
+ * the leaf-ordered copy of the series (the LRDFile analogue, Sec. 3.3),
  * the iSAX words in the same order (the LSDFile analogue), the id map,
  * the leaf table and envelopes, plus build-time scratch.
  * Errors: HS_EINVAL for N < 1, N >= 2^32, or invalid params.
@@ -108,8 +108,8 @@ hs_status hs_index_bytes(int64_t N, const hs_params* params, int64_t* bytes);
  * Build the index over x_dev (float32 [N][n], row-major, read only).
  * Computes per series the EAPCA segment statistics and the iSAX word
  * (Sec. 2), partitions the series into leaves by mean/std midpoint H-splits
- * (Sec. 3.1; see DESIGN notes for the split policy), stores the series in
- * leaf order, and computes every leaf's synopsis (Sec. 3.1, min/max of
+ * (Sec. 3.2; see DESIGN notes for the split policy), stores the series in
+ * leaf order, and computes every leaf's synopsis (Sec. 3.2, min/max of
  * segment mean and std, rounded outward to float32).
  * x_dev may be freed after the call returns.  index_mem_dev must hold
  * hs_index_bytes() bytes and stay allocated until hs_index_free.
@@ -127,13 +127,13 @@ hs_status hs_get_info(const hs_index* idx, hs_index_info* out);
  * leaf_start: int64 [L + 1], leaf i holds stored positions
  *             [leaf_start[i], leaf_start[i+1]);
  * env:        float32 [L][w][4] = (mu_min, mu_max, sd_min, sd_max) per
- *             segment (Sec. 3.1 synopsis), rounded outward.
+ *             segment (Sec. 3.2 synopsis), rounded outward.
  * Either pointer may be NULL.  Errors: HS_EINVAL, HS_EHIP. */
 hs_status hs_get_leaves(const hs_index* idx, int64_t* leaf_start, float* env);
 
 /* Copy the chunk table and the chunk envelopes to host memory (synchronous).
  * Inside a leaf the series are ordered by further mean/std midpoint splits
- * down to 64 series (Sec. 3.1 splitting rule, below the leaf level), and each
+ * down to 64 series (Sec. 3.2 splitting rule, below the leaf level), and each
  * leaf is cut into consecutive chunks of 64 series from its first one.
  * chunk_start: int64 [n_chunks + 1]; cenv: float32 [n_chunks][w][4], the
  * chunk's (mu_min, mu_max, sd_min, sd_max) per segment, rounded outward.
@@ -159,7 +159,7 @@ typedef struct {
 } hs_query_stats;
 
 /*
- * Exact k-NN of Q queries (Sec. 2 k-NN definition; Sec. 3.3 Exact-kNN).
+ * Exact k-NN of Q queries (Sec. 2 k-NN definition; Sec. 3.4 Exact-kNN).
  *  q_dev     float32 [Q][n] queries, row-major.
  *  ws_dev    workspace of at least hs_query_workspace_bytes(idx, Q, k).
  *  ids_dev   int64 [Q][k] out: original row indices of x_dev.
@@ -179,7 +179,7 @@ hs_status hs_knn_exact(hs_index* idx, const float* q_dev, int32_t Q, int32_t k, 
 /*
  * Precision form (beside the paper's method; it returns the same exact k-NN).
  * A low-precision copy x~ of every stored series (bf16 or fp16, round to
- * nearest even) replaces LB_SAX as the per-series filter of Sec. 3.3 step 3:
+ * nearest even) replaces LB_SAX as the per-series filter of Sec. 3.4 step 3:
  * a matrix-core pass computes q~.x~ in float32 for every (query, series)
  * pair of the candidate leaves and derives a rigorous lower bound of the
  * squared distance,
@@ -227,7 +227,7 @@ hs_status hs_knn_mixed(hs_index* idx, const float* q_dev, int32_t Q, int32_t k, 
  * stream and, after their own final synchronisation, add the elapsed times
  * to process-wide accumulators, one per kind.  Not meant for concurrent
  * calls from several threads. */
-#define HS_PROF_FILTER 0 /* LB_SAX filter (Sec. 3.3 step 3) */
+#define HS_PROF_FILTER 0 /* LB_SAX filter (Sec. 3.4 step 3) */
 #define HS_PROF_REFINE 1 /* refinement of the candidates (step 4) */
 #define HS_PROF_FUSED 2  /* fused filter + refinement (overflow fallback) */
 #define HS_PROF_BOUND 3  /* matrix-core bounding pass of the precision form */

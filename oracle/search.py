@@ -1,6 +1,6 @@
 """Serial FP64 run of Hercules' exact k-NN search (oracle; test infrastructure only).
 
-Takes the steps of the paper's exact search (Sec. 3.3, the Exact-kNN
+Takes the steps of the paper's exact search (Sec. 3.4, the Exact-kNN
 algorithm and its four steps) in order, over a flat list of leaves built by
 ``summaries.build_leaves``:
 

@@ -7,10 +7,10 @@ Written from Hercules (PVLDB 15(10), 2022):
   (iSAX), 16 segments and an alphabet of 256 symbols.
 * EAPCA: Sec. 2 -- each segment represented by its mean and standard
   deviation.
-* Node synopsis: Sec. 3.1 (The Hercules Tree) -- per segment of the node's
+* Node synopsis: Sec. 3.2 (The Hercules Tree) -- per segment of the node's
   segmentation, the min/max over the node's series of the segment mean and of
   the segment standard deviation.
-* H-split: Sec. 3.1 -- split on one segment's mean (or standard deviation) at
+* H-split: Sec. 3.2 -- split on one segment's mean (or standard deviation) at
   the midpoint of its [min, max] range: values below the midpoint go left,
   values at or above it go right (the worked example splits at -0.075 for the
   range [-0.25, 0.10]).
@@ -85,7 +85,7 @@ def sax_word(paa_vals: np.ndarray, beta: np.ndarray) -> np.ndarray:
 def lb_sax(paa_q: np.ndarray, word: np.ndarray, beta: np.ndarray, n: int) -> np.ndarray:
     """Squared LB_SAX between the query's PAA and iSAX words (Sec. 2; the
     query side uses PAA(S_Q), not its word, as in the CSWorker step of
-    Sec. 3.3).
+    Sec. 3.4).
 
     lb^2 = (n / w) * sum_i delta_i^2, delta_i the distance from paa_q[i] to the
     symbol's region [beta_s, beta_{s+1}].  Valid because, per segment,
@@ -116,7 +116,7 @@ def equal_segmentation(n: int, m: int) -> np.ndarray:
 
 def segment_stats(x: np.ndarray, ends: np.ndarray):
     """EAPCA of each row over the segmentation with right endpoints ``ends``
-    (Sec. 2 EAPCA; Sec. 3.1 segmentation SG = {r_1..r_m}, r_0 = 0).
+    (Sec. 2 EAPCA; Sec. 3.2 segmentation SG = {r_1..r_m}, r_0 = 0).
 
     Segment i covers points [r_{i-1}, r_i).  mu = mean, sigma = population
     standard deviation.  x: [..., n].  Returns (mu, sigma), each [..., m].
@@ -137,7 +137,7 @@ def segment_stats(x: np.ndarray, ends: np.ndarray):
 
 def synopsis(mu: np.ndarray, sd: np.ndarray) -> np.ndarray:
     """Node synopsis z_i = (mu_min, mu_max, sd_min, sd_max) per segment over the
-    node's series (Sec. 3.1).  mu, sd: [rows, m].  Returns [m, 4] FP64."""
+    node's series (Sec. 3.2).  mu, sd: [rows, m].  Returns [m, 4] FP64."""
     mu = np.asarray(mu, dtype=np.float64)
     sd = np.asarray(sd, dtype=np.float64)
     return np.stack([mu.min(0), mu.max(0), sd.min(0), sd.max(0)], axis=-1)
@@ -170,7 +170,7 @@ def lb_eapca(mu_q: np.ndarray, sd_q: np.ndarray, syn: np.ndarray, ends: np.ndarr
 # ------------------------------------------------------------------ H-split
 
 def hsplit_threshold(vmin: float, vmax: float) -> float:
-    """Midpoint of a segment statistic's [min, max] range (Sec. 3.1)."""
+    """Midpoint of a segment statistic's [min, max] range (Sec. 3.2)."""
     return (vmin + vmax) / 2.0
 
 
@@ -206,7 +206,7 @@ def choose_split(mu: np.ndarray, sd: np.ndarray, ends: np.ndarray):
 
 def build_leaves(x: np.ndarray, w: int, tau: int):
     """Leaf partition by repeated H-splits of every node holding more than
-    ``tau`` series (Sec. 3.1 splitting, applied top-down to the whole batch).
+    ``tau`` series (Sec. 3.2 splitting, applied top-down to the whole batch).
 
     Returns (leaves, ends): ``leaves`` is a list of int64 arrays of row ids in
     in-order (left before right) leaf order, ids ascending inside each leaf;

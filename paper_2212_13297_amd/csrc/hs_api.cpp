@@ -159,7 +159,7 @@ void compute_breakpoints(float* out255) {
 
 // ------------------------------------------------------------ leaf builder
 //
-// Top-down partition by H-splits (Hercules Sec. 3.1): a node with more than
+// Top-down partition by H-splits (Hercules Sec. 3.2): a node with more than
 // tau series is split on one segment's mean or std at the midpoint of that
 // statistic's [min, max] range over the node; values below the midpoint go
 // left.  Policy (the paper defers to DSTree's heuristic without stating it):

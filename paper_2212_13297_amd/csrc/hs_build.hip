@@ -1,4 +1,4 @@
-// Index-build kernels (Hercules Sec. 2 summaries, Sec. 3.1 tree):
+// Index-build kernels (Hercules Sec. 2 summaries, Sec. 3.2 tree):
 //   series_stats  per (series, segment) mean and population std (FP64 math),
 //                 used by the host to choose the leaf splits
 //   gather_rows   leaf-ordered, zero-padded copy of the series

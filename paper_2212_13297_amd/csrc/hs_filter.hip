@@ -1,4 +1,4 @@
-// The LB_SAX filter (Hercules Sec. 3.3, step 3): the series of every
+// The LB_SAX filter (Hercules Sec. 3.4, step 3): the series of every
 // (query, part) item whose bounds do not exceed BSF_k become candidates for
 // the refine kernel.
 //

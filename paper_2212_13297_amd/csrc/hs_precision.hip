@@ -1,5 +1,5 @@
 // Precision form of the query path.  It computes the same exact k-NN as the
-// plain method (Hercules Sec. 3.3); only the per-series filter changes.  A
+// plain method (Hercules Sec. 3.4); only the per-series filter changes.  A
 // bf16 or fp16 copy x~ of every stored series feeds a matrix-core pass that
 // computes q~.x~ for every (query, series) pair of the candidate leaves, in
 // float32.  From it a rigorous lower bound of the true squared distance

@@ -1,4 +1,4 @@
-// Query-side kernels around the scan (Hercules Sec. 3.3, Exact-kNN):
+// Query-side kernels around the scan (Hercules Sec. 3.4, Exact-kNN):
 //   init_counters  reset the per-call counters and candidate regions
 //   query_prep     query PAA / segment stats (FP64) and the LB_SAX table
 //   lb_eapca       LB_EAPCA of every (query, leaf)

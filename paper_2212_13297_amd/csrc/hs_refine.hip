@@ -1,4 +1,4 @@
-// Refinement of the candidate list (Hercules Sec. 3.3, step 4): the exact
+// Refinement of the candidate list (Hercules Sec. 3.4, step 4): the exact
 // float32 squared distance with early abandoning for every candidate, first
 // re-checked against the current BSF_k; per-wavefront top-k, BSF_k published
 // with atomicMin, results appended to the per-query pool.

@@ -1,4 +1,4 @@
-// Fused filter + refine per (query, part) item (Hercules Sec. 3.3, steps 3
+// Fused filter + refine per (query, part) item (Hercules Sec. 3.4, steps 3
 // and 4 without a candidate list): the path of queries whose candidate list
 // or result pool overflowed.  Work is split into contiguous static ranges per
 // workgroup; items are ordered by query, so the query row and LB_SAX table

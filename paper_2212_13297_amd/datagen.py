@@ -5,7 +5,7 @@ z-normalisation of the inputs). None of the search method's arithmetic (PAA,
 iSAX, EAPCA, distances, bounds) lives here, so both the HIP path and the CPU
 oracle can take their inputs from it without sharing any of that arithmetic.
 
-Recipe (Hercules, Sec. 5.1 "Datasets" and "Queries"):
+Recipe (Hercules, Sec. 4.1 "Datasets" and "Queries"):
 
 * A series is a random walk: i.i.d. N(0, 1) steps, cumulatively summed, then
   z-normalised (population standard deviation) and cast to float32.  The

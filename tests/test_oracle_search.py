@@ -1,4 +1,4 @@
-"""Pins for the oracle's serial run of the exact search (Hercules Sec. 3.3).
+"""Pins for the oracle's serial run of the exact search (Hercules Sec. 3.4).
 
 The paper's central claim is that the search is exact: every access path
 returns the k-NN of the plain definition.  The serial FP64 filter-and-refine

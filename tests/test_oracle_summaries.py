@@ -1,4 +1,4 @@
-"""Pins for the oracle's summaries and lower bounds (Hercules Sec. 2, Sec. 3.1).
+"""Pins for the oracle's summaries and lower bounds (Hercules Sec. 2, Sec. 3.2).
 
 Each function is tied to something other than its own formula: the normal CDF
 computed independently with erfc, scipy's quantile function, closed forms of
