@@ -145,6 +145,110 @@ def run_mixed(args, hs, torch, idx, qt, Q, plain_ids, plain_stats):
     return out
 
 
+def run_serving(args, hs, torch, G, idx256, x256):
+    """Serving form: three collections (20M x 128, 10M x 256 -- the headline
+    index -- and 2M x 1024 at scale 1), a Poisson stream of requests with the
+    collection uniform, k ~ U{1..100} and noise variance ~ U[1 %, 10 %];
+    latency = completion - scheduled arrival on the server's clock."""
+    dev = torch.device("cuda:0")
+    scale = args.serve_scale
+    specs = [(max(1000, int(20_000_000 * scale)), 128, 16), (None, 256, 16), (max(1000, int(2_000_000 * scale)), 1024, 32)]
+    xs, idxs = [], []
+    for c, (N, n, w) in enumerate(specs):
+        if N is None:
+            xs.append(x256)
+            idxs.append(idx256)
+            continue
+        t0 = time.time()
+        xc = G.random_walks(N, n, coll=100 + c)
+        xt = torch.from_numpy(xc).to(dev)
+        ic = hs.Index(xt, hs.Params(w=w, leaf_size=args.leaf, l_max=args.l_max, seed_rows=args.seed_rows))
+        torch.cuda.synchronize()
+        del xt
+        torch.cuda.empty_cache()
+        xs.append(xc)
+        idxs.append(ic)
+        log(f"serving collection {c}: {N} x {n} built in {time.time() - t0:.1f}s")
+    budget = int(args.serve_budget_gb * (1 << 30))
+    srv = hs.Server(idxs, [0, 0, 0], budget_bytes=budget, streams_per_coll=2, max_slots=8192, max_batch=256)
+
+    rng = np.random.default_rng(G.SEED_ARRIVAL)
+    total_s = args.serve_warmup + args.serve_seconds
+    arrivals = G.poisson_arrivals(args.serve_rate, total_s, seed=G.SEED_ARRIVAL)
+    R = len(arrivals)
+    coll = rng.integers(0, 3, R)
+    ks = rng.integers(1, 101, R)
+    var = rng.uniform(0.01, 0.10, R)
+    qs = []
+    for i in range(R):
+        xc = xs[coll[i]]
+        q = xc[rng.integers(0, len(xc))].astype(np.float64) + rng.standard_normal(xc.shape[1]) * np.sqrt(var[i])
+        qs.append(((q - q.mean()) / q.std()).astype(np.float32))
+    log(f"serving: {R} requests over {total_s:.0f}s at {args.serve_rate:.0f}/s")
+
+    done = {}
+    arr_srv = np.empty(R)
+    busy = 0
+    t0p = time.perf_counter()
+    t0s = hs.hs_server_now()
+    i = 0
+    while i < R or len(done) < R:
+        now = time.perf_counter() - t0p
+        while i < R and arrivals[i] <= now:
+            if srv.submit(int(coll[i]), qs[i], int(ks[i]), i):
+                arr_srv[i] = t0s + arrivals[i]
+                i += 1
+            else:
+                busy += 1
+                break
+        for r in srv.poll():
+            done[r["tag"]] = r
+        if time.perf_counter() - t0p > total_s + 120:
+            raise RuntimeError("serving run did not finish")
+    wall = time.perf_counter() - t0p
+    meas = [t for t in range(R) if arrivals[t] >= args.serve_warmup]
+    lat = np.array([(done[t]["t_done"] - arr_srv[t]) * 1000.0 for t in meas])
+    ok = all(done[t]["status"] == 0 for t in range(R))
+    span = max(done[t]["t_done"] for t in meas) - (t0s + args.serve_warmup)
+    info = srv.info()
+    # spot-check: server results equal the eager entry point on the same query
+    same = 0
+    checked = list(range(0, R, max(1, R // 50)))
+    for t in checked:
+        c = int(coll[t])
+        qt1 = torch.from_numpy(qs[t][None, :].copy()).to(dev)
+        e_ids, e_d2 = idxs[c].knn(qt1, int(ks[t]))
+        torch.cuda.synchronize()
+        same += int(list(e_ids.cpu().numpy()[0]) == done[t]["ids"] and list(e_d2.cpu().numpy()[0]) == done[t]["d2"])
+    # saturation: everything submitted at once, completion rate
+    S = min(R, 20000)
+    t1 = hs.hs_server_now()
+    for t in range(S):
+        while not srv.submit(int(coll[t]), qs[t], int(ks[t]), R + t):
+            for r in srv.poll():
+                done[r["tag"]] = r
+    while len([1 for tg in done if tg >= R]) < S:
+        for r in srv.poll():
+            done[r["tag"]] = r
+    sat_s = max(done[R + t]["t_done"] for t in range(S)) - t1
+    info2 = srv.info()
+    out = {"value": round(len(meas) / span, 2), "unit": "queries/s", "offered_rate": args.serve_rate,
+           "latency_ms": {"p50": round(float(np.percentile(lat, 50)), 4), "p99": round(float(np.percentile(lat, 99)), 4),
+                          "mean": round(float(lat.mean()), 4), "from": "scheduled arrival"},
+           "requests_measured": len(meas), "requests_total": R, "all_ok": bool(ok), "busy_retries": busy,
+           "batches": info["batches"], "mean_batch": round(info["queries"] / max(1, info["batches"]), 2),
+           "graphs": info2["graphs"], "identical_to_eager": f"{same}/{len(checked)}",
+           "saturation_queries_per_s": round(S / sat_s, 2), "saturation_requests": S,
+           "collections": [f"{len(xc)}x{xc.shape[1]}" for xc in xs], "k": "U{1..100}",
+           "noise_variance": "U[0.01, 0.10]", "wall_s": round(wall, 1)}
+    log(f"serving: {out}")
+    srv.close()
+    for c, ic in enumerate(idxs):
+        if ic is not idx256:
+            ic.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -161,9 +265,16 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=180, help="queries timed on the CPU oracle")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--latency-queries", type=int, default=300)
-    ap.add_argument("--forms", default="plain,mixed",
+    ap.add_argument("--forms", default="plain,mixed,serving",
                     help="plain: the paper's filter-and-refine (always timed, the headline value); mixed: also "
-                         "the precision form (bf16 copy, matrix-core bound, compensated refine) on the same index")
+                         "the precision form (bf16 copy, matrix-core bound, compensated refine) on the same index; "
+                         "serving: the continuous-batching server over three collections under Poisson arrivals")
+    ap.add_argument("--serve-rate", type=float, default=2000.0, help="Poisson arrival rate (queries/s)")
+    ap.add_argument("--serve-seconds", type=float, default=30.0, help="measured arrival window (s)")
+    ap.add_argument("--serve-warmup", type=float, default=5.0, help="arrivals before the measured window (s)")
+    ap.add_argument("--serve-scale", type=float, default=1.0,
+                    help="fraction of the serving collections' sizes (1.0 = 20M x 128, 10M x 256, 2M x 1024)")
+    ap.add_argument("--serve-budget-gb", type=float, default=48.0, help="device budget of the server (GB)")
     ap.add_argument("--profile-run", action="store_true",
                     help="only the warmup and timed k-NN steps (no k=1 pass, latency or CPU oracle), so a "
                          "profiler's per-kernel averages cover exactly the launches timed here; also copies "
@@ -281,6 +392,9 @@ def main():
     mixed = None
     if "mixed" in args.forms.split(","):
         mixed = run_mixed(args, hs, torch, idx, qt, Q, ids, st)
+    serving = None
+    if "serving" in args.forms.split(",") and not args.profile_run:
+        serving = run_serving(args, hs, torch, G, idx, x)
 
     cpu = None
     parity = None
@@ -348,6 +462,7 @@ def main():
         "cpu_baseline": cpu,
         "parity_sample": parity,
         "precision_form": mixed,
+        "serving_form": serving,
     }
     print(json.dumps(out), flush=True)
     idx.close()

@@ -222,6 +222,102 @@ hs_status hs_build_shadow(hs_index* idx, int32_t kind, void* shadow_dev, int64_t
 hs_status hs_knn_mixed(hs_index* idx, const float* q_dev, int32_t Q, int32_t k, void* ws_dev, int64_t ws_bytes,
                        int64_t* ids_dev, float* d2_dev, double* err_dev, void* stats_dev, void* stream);
 
+/*
+ * Serving form (beside the paper's method, which answers one query batch at a
+ * time; the paper's interactive workload is a stream of queries arriving
+ * asynchronously, Sec. 4.1).  A server holds C indexes ("collections",
+ * possibly of different series lengths) and answers requests of any k as
+ * they arrive, by continuous batching:
+ *  - hs_submit copies the query and queues the request if one of max_slots
+ *    slots is free (HS_EBUSY otherwise; the caller retries later);
+ *  - a dispatcher thread forms a batch from the head of a collection's queue
+ *    whenever one of that collection's streams is idle, and launches the
+ *    whole query path for the batch as one HIP graph, captured once per
+ *    (stream, batch size, k) and replayed; batches of other collections and
+ *    on the collection's other streams keep running on the device meanwhile;
+ *  - each stream owns an equal, fixed region of the caller's budget buffer
+ *    (budget_bytes / (C * streams_per_coll)) for its batch's query state, so
+ *    a batch takes at most as many queries as that region holds (the HBM
+ *    budget of admission);
+ *  - hs_poll hands out completions.  A request's result is its exact top-k
+ *    by (d2, id): the same ids and the same float32 distances as when it is
+ *    answered alone (hs_knn_exact / hs_knn_mixed), whatever the mix.
+ * forms[c]: 0 = plain path (hs_knn_exact), 1 = precision form (hs_knn_mixed;
+ * the collection must have a low-precision copy).  forms may be NULL (all 0).
+ * The indexes and the budget buffer must outlive the server.  hs_submit and
+ * hs_poll may be called from any thread; the server's own thread makes all
+ * HIP calls on the device that was current at hs_server_create.
+ */
+typedef struct hs_server hs_server;
+
+typedef struct {
+    int32_t streams_per_coll; /* streams, and budget regions, per collection (1..8) */
+    int32_t max_slots;        /* requests in the server at once (queued + running), >= 1 */
+    int32_t max_batch;        /* largest batch, a power of two in [1, 1024] */
+    int32_t reserved;         /* 0 */
+} hs_server_config;
+
+typedef struct {
+    uint64_t tag;            /* the caller's tag */
+    int32_t coll;            /* collection */
+    int32_t k;               /* neighbours requested */
+    hs_status status;        /* HS_OK, or the error that failed its batch */
+    int32_t batch;           /* requests in the batch it ran in */
+    double t_submit;         /* seconds on hs_server_now's clock: hs_submit accepted it */
+    double t_launch;         /* its batch was launched */
+    double t_done;           /* its batch was seen complete */
+    int64_t ids[HS_KMAX];    /* first k entries: original row ids, by (d2, id) ascending */
+    float d2[HS_KMAX];       /* squared distances (float32; compensated in the precision form) */
+    double err[HS_KMAX];     /* precision form: bound of |d2 - d|; plain form: 0 */
+} hs_completion;
+
+typedef struct {
+    int64_t in_system;       /* requests queued or running */
+    int64_t batches;         /* batches launched */
+    int64_t queries;         /* requests launched */
+    int64_t padded_queries;  /* query rows launched (batches run at power-of-two sizes) */
+    int64_t graphs;          /* graphs captured */
+    int64_t failed;          /* 1 after a device failure (hs_submit then returns HS_EHIP) */
+} hs_server_stats;
+
+/* Errors: HS_EINVAL (NULL, C < 1, bad config or form, precision form
+ * without a copy), HS_ENOMEM (a region cannot hold one query of some
+ * collection, or host memory), HS_EHIP. */
+hs_status hs_server_create(hs_index* const* colls, const int32_t* forms, int32_t C, void* budget_dev,
+                           int64_t budget_bytes, const hs_server_config* cfg, hs_server** out);
+/* q_host: float32 [n] of the collection (copied before return).
+ * Errors: HS_EINVAL (collection, k out of [1, min(N, HS_KMAX)], NaN/Inf, or a
+ * value beyond the fp16 range for an fp16 precision-form collection),
+ * HS_EBUSY (no free slot), HS_EHIP (the server failed earlier). */
+hs_status hs_submit(hs_server* srv, int32_t coll, const float* q_host, int32_t k, uint64_t tag);
+/* Up to max completions, oldest first; *got of them written. */
+hs_status hs_poll(hs_server* srv, hs_completion* out, int32_t max, int32_t* got);
+hs_status hs_server_info(hs_server* srv, hs_server_stats* out);
+/* Waits for running batches, drops queued requests, releases the server. */
+hs_status hs_server_destroy(hs_server* srv);
+/* Seconds on the server's monotonic clock. */
+double hs_server_now(void);
+
+/*
+ * The server's admission scheduler on its own (host logic, no device calls),
+ * for callers that drive their own loop and for testing.  max_q: int32
+ * [C][8], the largest batch (0 or a power of two) a stream region of
+ * collection c holds when the batch's k falls in bucket b (k <= 2^b).
+ * hs_sched_next forms the next batch of (coll, stream) if that stream is idle:
+ * FIFO order, as many requests as fit at the batch's k bucket; *count = 0 if
+ * none.  tags must hold max_tags >= the largest max_q entry.  The stream stays
+ * busy until hs_sched_complete.  hs_sched_submit: HS_EBUSY when max_slots
+ * requests are in the system, HS_EINVAL for a k no region holds.
+ */
+typedef struct hs_sched hs_sched;
+hs_status hs_sched_create(int32_t C, int32_t streams, int32_t max_slots, const int32_t* max_q, hs_sched** out);
+hs_status hs_sched_submit(hs_sched* s, int32_t coll, int32_t k, uint64_t tag);
+hs_status hs_sched_next(hs_sched* s, int32_t coll, int32_t stream, int32_t* q_pad, int32_t* k_batch, uint64_t* tags,
+                        int32_t max_tags, int32_t* count);
+hs_status hs_sched_complete(hs_sched* s, int32_t coll, int32_t stream);
+hs_status hs_sched_in_system(hs_sched* s, int32_t* n);
+hs_status hs_sched_destroy(hs_sched* s);
+
 /* Diagnostics.  While enabled, hs_knn_exact and hs_knn_mixed bracket every
  * launch of their scan kernels (the dominant ones) with HIP events on their
  * stream and, after their own final synchronisation, add the elapsed times

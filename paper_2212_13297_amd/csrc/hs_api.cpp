@@ -15,28 +15,9 @@
 #include <utility>
 #include <vector>
 
-#include "hs_internal.h"
+#include "hs_host.h"
 
 using namespace hs;
-
-struct hs_index {
-    hs_params p;
-    IndexView view;
-    int device = 0;
-    int cus = 0;
-    int64_t max_leaf = 0;
-    int64_t index_bytes = 0;
-    int64_t* leaf_start_dev = nullptr;  // library-owned
-    float4* env_dev = nullptr;          // library-owned
-    float* beta_dev = nullptr;          // library-owned
-    int64_t* part_start_dev = nullptr;  // library-owned
-    uint32_t* part_leaf_dev = nullptr;  // library-owned
-    int64_t* part_chunk_dev = nullptr;  // library-owned
-    int64_t* chunk_start_dev = nullptr; // library-owned
-    float4* cenv_dev = nullptr;         // library-owned
-    int filter_waves = 4;               // wavefronts of the filter kernel (candidate slices)
-    ShadowView shadow{};                // low-precision copy (caller-owned memory), kind 0 = none
-};
 
 namespace {
 void free_owned(hs_index* idx) {
@@ -59,6 +40,10 @@ std::mutex g_prof_mu;
 bool g_prof_on = false;
 double g_prof_ms[HS_PROF_KINDS] = {};
 int64_t g_prof_launches[HS_PROF_KINDS] = {};
+
+}  // namespace
+
+namespace hs {
 
 // Events around the scan-kernel launches while profiling is on.
 struct ScanTimer {
@@ -115,12 +100,6 @@ hs_status fail(hs_status code, const char* fmt, ...) {
     g_err = buf;
     return code;
 }
-
-#define HIP_TRY(expr)                                                                  \
-    do {                                                                               \
-        hipError_t e_ = (expr);                                                        \
-        if (e_ != hipSuccess) return fail(HS_EHIP, "%s: %s", #expr, hipGetErrorString(e_)); \
-    } while (0)
 
 int64_t align_up(int64_t v, int64_t a) { return (v + a - 1) / a * a; }
 
@@ -549,83 +528,121 @@ namespace {
 // one rounding of the final sum plus second-order terms of the residues.
 double comp_err_rel(int K) { return std::ldexp(1.0, -23) + (4.0 * K + 64.0) * std::ldexp(1.0, -48); }
 
-// The query driver shared by the plain and the precision form.
-hs_status run_knn(hs_index* idx, const float* q_dev, int32_t Q, int32_t k, void* ws_dev, int64_t ws_bytes,
-                  int64_t* ids_dev, float* d2_dev, double* err_dev, void* stats_dev, void* stream, bool mixed) {
+}  // namespace
+
+namespace hs {
+
+hs_status knn_prepare(hs_index* idx, int32_t Q, int32_t k, void* ws_dev, int64_t ws_bytes, bool mixed,
+                      KnnCall* c) {
     if (!idx) return fail(HS_EINVAL, "idx is NULL");
     if (Q < 0) return fail(HS_EINVAL, "Q=%d < 0", Q);
     if (k < 1 || k > HS_KMAX) return fail(HS_EINVAL, "k=%d out of range [1, %d]", k, HS_KMAX);
     if ((int64_t)k > idx->view.N) return fail(HS_EINVAL, "k=%d > N=%lld", k, (long long)idx->view.N);
     if (mixed && idx->shadow.kind == 0) return fail(HS_EINVAL, "the index has no low-precision copy (hs_build_shadow)");
-    if (Q == 0) return HS_OK;
-    if (!q_dev || !ws_dev || !ids_dev || !d2_dev) return fail(HS_EINVAL, "NULL device pointer");
     if ((int64_t)Q * idx->view.parts >= ((int64_t)1 << 31))
         return fail(HS_EINVAL, "Q=%d too large for this index (Q * parts must stay below 2^31); split the batch", Q);
+    c->idx = idx;
+    c->mixed = mixed;
+    c->form = mixed ? kComp : kPlain;
+    c->err_rel = mixed ? comp_err_rel(idx->view.stride) : 0.0;
+    if (Q == 0) return HS_OK;
+    if (!ws_dev) return fail(HS_EINVAL, "NULL workspace");
     const int64_t need = ws_layout(idx, Q, k, nullptr, nullptr);
     if (ws_bytes < need) return fail(HS_ENOMEM, "ws_bytes=%lld < required %lld", (long long)ws_bytes, (long long)need);
-    hipStream_t st = (hipStream_t)stream;
-    QueryWs ws;
-    ws_layout(idx, Q, k, &ws, (char*)ws_dev);
+    ws_layout(idx, Q, k, &c->ws, (char*)ws_dev);
     const IndexView& ix = idx->view;
-    const int lm = (int)std::min<int64_t>(std::min<int64_t>(idx->p.l_max, ix.L), kMaxSeedLeaves);
-    const int form = mixed ? kComp : kPlain;
+    c->sp = ScanParams{};
+    c->sp.Q = Q;
+    c->sp.k = k;
+    c->sp.eapca_th = idx->p.eapca_th;
+    c->sp.n_seed = (int)std::min<int64_t>(std::min<int64_t>(idx->p.l_max, ix.L), kMaxSeedLeaves);
+    c->sp.seed_rows = idx->p.seed_rows;
+    return HS_OK;
+}
 
-    ScanParams sp{};
-    sp.Q = Q;
-    sp.k = k;
-    sp.eapca_th = idx->p.eapca_th;
-    sp.n_seed = lm;
-    sp.seed_rows = idx->p.seed_rows;
-    auto* stats_out = (hs_query_stats*)stats_dev;
-    const double err_rel = mixed ? comp_err_rel(ix.stride) : 0.0;
-
-    // profiling brackets the dominant kernels
-    ScanTimer timer;
+// Steps 1-4 and the first merge, all stream-ordered launches (no host
+// synchronisation, no memset), so the sequence can be captured in a graph.
+// redo_host (pinned, may be NULL): receives counters[kCtrRedo], [kCtrNonFinite].
+hs_status knn_enqueue(const KnnCall& c, const float* q_dev, int64_t* ids_dev, float* d2_dev, double* err_dev,
+                      hs_query_stats* stats_out, hipStream_t st, uint32_t* redo_host, ScanTimer* timer) {
+    const IndexView& ix = c.idx->view;
+    const QueryWs& ws = c.ws;
+    ScanParams sp = c.sp;
     auto timed = [&](int kind, auto&& launch) -> hipError_t {
-        hipError_t e = timer.begin(st, kind);
+        hipError_t e = timer ? timer->begin(st, kind) : hipSuccess;
         if (e != hipSuccess) return e;
         e = launch();
         if (e != hipSuccess) return e;
-        return timer.end(st);
+        return timer ? timer->end(st) : hipSuccess;
     };
-
-    HIP_TRY(launch_query_prep(ix, q_dev, Q, ws, st));
-    if (mixed) HIP_TRY(launch_query_low(ix, idx->shadow.kind, Q, ws, st));
-    HIP_TRY(launch_lb_eapca(ix, Q, ws, st));
+    HIP_TRY(launch_query_prep(ix, q_dev, sp.Q, ws, st));
+    if (c.mixed) HIP_TRY(launch_query_low(ix, c.idx->shadow.kind, sp.Q, ws, st));
+    HIP_TRY(launch_lb_eapca(ix, sp.Q, ws, st));
     // step 1: approximate search seeds BSF_k
-    HIP_TRY(launch_seed(ix, sp, ws, form, st));
+    HIP_TRY(launch_seed(ix, sp, ws, c.form, st));
     // step 2: candidate leaves; step 3: per-series filter (LB_SAX, or the
     // matrix-core bound of the precision form); step 4: refinement
     HIP_TRY(launch_emit(ix, sp, false, ws, st));
-    if (mixed) {
-        HIP_TRY(timed(HS_PROF_BOUND, [&] { return launch_bound(ix, idx->shadow, sp, ws, st); }));
+    if (c.mixed) {
+        HIP_TRY(timed(HS_PROF_BOUND, [&] { return launch_bound(ix, c.idx->shadow, sp, ws, st); }));
     } else {
-        HIP_TRY(timed(HS_PROF_FILTER, [&] { return launch_filter(ix, sp, ws, idx->cus, st); }));
+        HIP_TRY(timed(HS_PROF_FILTER, [&] { return launch_filter(ix, sp, ws, c.idx->cus, st); }));
     }
     HIP_TRY(launch_compact(ws, st));
-    HIP_TRY(timed(HS_PROF_REFINE, [&] { return launch_refine(ix, sp, ws, idx->cus, form, st); }));
+    HIP_TRY(timed(HS_PROF_REFINE, [&] { return launch_refine(ix, sp, ws, c.idx->cus, c.form, st); }));
     sp.final_pass = 1;
-    HIP_TRY(launch_merge(ix, sp, false, ws, ids_dev, d2_dev, err_dev, err_rel, stats_out, st));
+    HIP_TRY(launch_merge(ix, sp, false, ws, ids_dev, d2_dev, err_dev, c.err_rel, stats_out, st));
+    if (redo_host)
+        HIP_TRY(hipMemcpyAsync(redo_host, ws.counters + kCtrRedo, 2 * sizeof(uint32_t), hipMemcpyDeviceToHost, st));
+    return HS_OK;
+}
 
-    // queries whose candidate list or result pool overflowed: rescan their
-    // candidate parts with the fused kernel and the tightened BSF_k until
-    // nothing overflows (each merge keeps the best k so far, without repeats)
+// Queries whose candidate list or result pool overflowed: rescan their
+// candidate parts with the fused kernel and the tightened BSF_k until nothing
+// overflows (each merge keeps the best k so far, without repeats).  Synchronises.
+hs_status knn_finish(const KnnCall& c, int64_t* ids_dev, float* d2_dev, double* err_dev, hs_query_stats* stats_out,
+                     hipStream_t st, ScanTimer* timer) {
+    const IndexView& ix = c.idx->view;
+    const QueryWs& ws = c.ws;
+    ScanParams sp = c.sp;
+    sp.final_pass = 1;
     for (int round = 0;; ++round) {
-        uint32_t c[2] = {0, 0};
-        HIP_TRY(hipMemcpyAsync(c, ws.counters + kCtrRedo, sizeof c, hipMemcpyDeviceToHost, st));
+        uint32_t cnt[2] = {0, 0};
+        HIP_TRY(hipMemcpyAsync(cnt, ws.counters + kCtrRedo, sizeof cnt, hipMemcpyDeviceToHost, st));
         HIP_TRY(hipStreamSynchronize(st));
-        if (c[1]) return fail(HS_EINVAL, "%u queries contain NaN or Inf%s", c[1],
-                              mixed && idx->shadow.kind == kShadowF16 ? " or values beyond the fp16 range" : "");
-        if (c[0] == 0) {
-            timer.collect();
-            break;
-        }
+        if (cnt[1])
+            return fail(HS_EINVAL, "%u queries contain NaN or Inf%s", cnt[1],
+                        c.mixed && c.idx->shadow.kind == kShadowF16 ? " or values beyond the fp16 range" : "");
+        if (cnt[0] == 0) break;
         if (round >= 64) return fail(HS_EHIP, "result pool still overflowing after %d rounds", round);
         HIP_TRY(launch_emit(ix, sp, true, ws, st));
-        HIP_TRY(timed(HS_PROF_FUSED, [&] { return launch_leaf_scan(ix, sp, ws, idx->cus, form, st); }));
-        HIP_TRY(launch_merge(ix, sp, true, ws, ids_dev, d2_dev, err_dev, err_rel, stats_out, st));
+        hipError_t e = timer ? timer->begin(st, HS_PROF_FUSED) : hipSuccess;
+        if (e == hipSuccess) e = launch_leaf_scan(ix, sp, ws, c.idx->cus, c.form, st);
+        if (e == hipSuccess && timer) e = timer->end(st);
+        HIP_TRY(e);
+        HIP_TRY(launch_merge(ix, sp, true, ws, ids_dev, d2_dev, err_dev, c.err_rel, stats_out, st));
     }
+    if (timer) timer->collect();
     return HS_OK;
+}
+
+}  // namespace hs
+
+namespace {
+
+// The query driver shared by the plain and the precision form.
+hs_status run_knn(hs_index* idx, const float* q_dev, int32_t Q, int32_t k, void* ws_dev, int64_t ws_bytes,
+                  int64_t* ids_dev, float* d2_dev, double* err_dev, void* stats_dev, void* stream, bool mixed) {
+    KnnCall c;
+    hs_status s = knn_prepare(idx, Q, k, ws_dev, ws_bytes, mixed, &c);
+    if (s || Q == 0) return s;
+    if (!q_dev || !ids_dev || !d2_dev) return fail(HS_EINVAL, "NULL device pointer");
+    hipStream_t st = (hipStream_t)stream;
+    auto* stats_out = (hs_query_stats*)stats_dev;
+    ScanTimer timer;
+    s = knn_enqueue(c, q_dev, ids_dev, d2_dev, err_dev, stats_out, st, nullptr, &timer);
+    if (s) return s;
+    return knn_finish(c, ids_dev, d2_dev, err_dev, stats_out, st, &timer);
 }
 
 int64_t shadow_layout(const IndexView& ix, uint16_t** rows, float2** norms, uint32_t** flag, char* base) {

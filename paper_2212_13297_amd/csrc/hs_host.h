@@ -1,0 +1,63 @@
+// Host-side declarations shared by the C ABI implementation (hs_api.cpp) and
+// the serving loop (hs_server.cpp).  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "hs_internal.h"
+
+struct hs_index {
+    hs_params p;
+    hs::IndexView view;
+    int device = 0;
+    int cus = 0;
+    int64_t max_leaf = 0;
+    int64_t index_bytes = 0;
+    int64_t* leaf_start_dev = nullptr;  // library-owned
+    float4* env_dev = nullptr;          // library-owned
+    float* beta_dev = nullptr;          // library-owned
+    int64_t* part_start_dev = nullptr;  // library-owned
+    uint32_t* part_leaf_dev = nullptr;  // library-owned
+    int64_t* part_chunk_dev = nullptr;  // library-owned
+    int64_t* chunk_start_dev = nullptr; // library-owned
+    float4* cenv_dev = nullptr;         // library-owned
+    int filter_waves = 4;               // wavefronts of the filter kernel (candidate slices)
+    hs::ShadowView shadow{};            // low-precision copy (caller-owned memory), kind 0 = none
+};
+
+namespace hs {
+
+// Records the message for hs_last_error (this thread) and returns code.
+hs_status fail(hs_status code, const char* fmt, ...);
+
+#define HIP_TRY(expr)                                                                        \
+    do {                                                                                     \
+        hipError_t e_ = (expr);                                                              \
+        if (e_ != hipSuccess) return hs::fail(HS_EHIP, "%s: %s", #expr, hipGetErrorString(e_)); \
+    } while (0)
+
+int64_t align_up(int64_t v, int64_t a);
+
+// Query workspace layout for Q queries (bytes; fills *ws when base is given).
+int64_t ws_layout(const hs_index* idx, int32_t Q, int32_t k, QueryWs* ws, char* base);
+
+struct ScanTimer;
+
+// One k-NN call, validated and laid out in its workspace.
+struct KnnCall {
+    hs_index* idx = nullptr;
+    bool mixed = false;
+    int form = kPlain;
+    double err_rel = 0.0;
+    QueryWs ws{};
+    ScanParams sp{};
+};
+
+hs_status knn_prepare(hs_index* idx, int32_t Q, int32_t k, void* ws_dev, int64_t ws_bytes, bool mixed, KnnCall* c);
+hs_status knn_enqueue(const KnnCall& c, const float* q_dev, int64_t* ids_dev, float* d2_dev, double* err_dev,
+                      hs_query_stats* stats_out, hipStream_t st, uint32_t* redo_host, ScanTimer* timer);
+hs_status knn_finish(const KnnCall& c, int64_t* ids_dev, float* d2_dev, double* err_dev, hs_query_stats* stats_out,
+                     hipStream_t st, ScanTimer* timer);
+
+}  // namespace hs

@@ -43,6 +43,23 @@ class hs_query_stats(ctypes.Structure):
                 ("rounds", ctypes.c_uint64), ("candidates", ctypes.c_uint64), ("chunks_tested", ctypes.c_uint64)]
 
 
+class hs_server_config(ctypes.Structure):
+    _fields_ = [("streams_per_coll", ctypes.c_int32), ("max_slots", ctypes.c_int32), ("max_batch", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
+
+
+class hs_completion(ctypes.Structure):
+    _fields_ = [("tag", ctypes.c_uint64), ("coll", ctypes.c_int32), ("k", ctypes.c_int32),
+                ("status", ctypes.c_int32), ("batch", ctypes.c_int32), ("t_submit", ctypes.c_double),
+                ("t_launch", ctypes.c_double), ("t_done", ctypes.c_double), ("ids", ctypes.c_int64 * HS_KMAX),
+                ("d2", ctypes.c_float * HS_KMAX), ("err", ctypes.c_double * HS_KMAX)]
+
+
+class hs_server_stats(ctypes.Structure):
+    _fields_ = [("in_system", ctypes.c_int64), ("batches", ctypes.c_int64), ("queries", ctypes.c_int64),
+                ("padded_queries", ctypes.c_int64), ("graphs", ctypes.c_int64), ("failed", ctypes.c_int64)]
+
+
 STATS_FIELDS = ["leaves_kept", "rows_filtered", "rows_refined", "chunks_read", "path", "rounds", "candidates",
                 "chunks_tested"]
 
@@ -60,6 +77,21 @@ _SIGS = {
     "hs_build_shadow": (ctypes.c_int32, [_P, ctypes.c_int32, _P, ctypes.c_int64, _P]),
     "hs_knn_mixed": (ctypes.c_int32, [_P, _P, ctypes.c_int32, ctypes.c_int32, _P, ctypes.c_int64, _P, _P, _P, _P,
                                       _P]),
+    "hs_server_create": (ctypes.c_int32, [_P, _P, ctypes.c_int32, _P, ctypes.c_int64,
+                                          ctypes.POINTER(hs_server_config), ctypes.POINTER(_P)]),
+    "hs_submit": (ctypes.c_int32, [_P, ctypes.c_int32, _P, ctypes.c_int32, ctypes.c_uint64]),
+    "hs_poll": (ctypes.c_int32, [_P, _P, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)]),
+    "hs_server_info": (ctypes.c_int32, [_P, ctypes.POINTER(hs_server_stats)]),
+    "hs_server_destroy": (ctypes.c_int32, [_P]),
+    "hs_server_now": (ctypes.c_double, []),
+    "hs_sched_create": (ctypes.c_int32, [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, _P, ctypes.POINTER(_P)]),
+    "hs_sched_submit": (ctypes.c_int32, [_P, ctypes.c_int32, ctypes.c_int32, ctypes.c_uint64]),
+    "hs_sched_next": (ctypes.c_int32, [_P, ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32),
+                                       ctypes.POINTER(ctypes.c_int32), _P, ctypes.c_int32,
+                                       ctypes.POINTER(ctypes.c_int32)]),
+    "hs_sched_complete": (ctypes.c_int32, [_P, ctypes.c_int32, ctypes.c_int32]),
+    "hs_sched_in_system": (ctypes.c_int32, [_P, ctypes.POINTER(ctypes.c_int32)]),
+    "hs_sched_destroy": (ctypes.c_int32, [_P]),
     "hs_index_free": (ctypes.c_int32, [_P]),
     "hs_last_error": (ctypes.c_char_p, []),
     "hs_breakpoints": (ctypes.c_int32, [ctypes.c_int32, _P]),
@@ -157,6 +189,87 @@ def hs_build_shadow(h, kind: int, mem_ptr: int, mem_bytes: int, stream: int) -> 
 def hs_knn_mixed(h, q_ptr: int, Q: int, k: int, ws_ptr: int, ws_bytes: int, ids_ptr: int, d2_ptr: int,
                  err_ptr: int, stats_ptr: int, stream: int) -> None:
     _check(load().hs_knn_mixed(h, q_ptr, Q, k, ws_ptr, ws_bytes, ids_ptr, d2_ptr, err_ptr, stats_ptr, stream))
+
+
+def hs_server_create(handles, forms, budget_ptr: int, budget_bytes: int, cfg: hs_server_config):
+    C = len(handles)
+    arr = (_P * C)(*[h.value if isinstance(h, _P) else h for h in handles])
+    fa = (ctypes.c_int32 * C)(*forms)
+    out = _P()
+    _check(load().hs_server_create(ctypes.cast(arr, _P), ctypes.cast(fa, _P), C, budget_ptr, budget_bytes,
+                                   ctypes.byref(cfg), ctypes.byref(out)))
+    return out
+
+
+def hs_submit(srv, coll: int, q_ptr: int, k: int, tag: int) -> int:
+    """Returns HS_OK or HS_EBUSY; raises on other errors."""
+    code = load().hs_submit(srv, coll, q_ptr, k, tag)
+    if code not in (HS_OK, HS_EBUSY):
+        _check(code)
+    return code
+
+
+def hs_poll(srv, buf, max_n: int) -> int:
+    got = ctypes.c_int32()
+    _check(load().hs_poll(srv, ctypes.cast(buf, _P), max_n, ctypes.byref(got)))
+    return got.value
+
+
+def hs_server_info(srv) -> hs_server_stats:
+    st = hs_server_stats()
+    _check(load().hs_server_info(srv, ctypes.byref(st)))
+    return st
+
+
+def hs_server_destroy(srv) -> None:
+    _check(load().hs_server_destroy(srv))
+
+
+def hs_server_now() -> float:
+    return load().hs_server_now()
+
+
+def hs_sched_create(C: int, streams: int, max_slots: int, max_q):
+    import numpy as np
+    mq = np.ascontiguousarray(np.asarray(max_q, dtype=np.int32).reshape(C, 8))
+    out = _P()
+    _check(load().hs_sched_create(C, streams, max_slots, mq.ctypes.data, ctypes.byref(out)))
+    return out
+
+
+def hs_sched_submit(h, coll: int, k: int, tag: int) -> int:
+    code = load().hs_sched_submit(h, coll, k, tag)
+    if code not in (HS_OK, HS_EBUSY):
+        _check(code)
+    return code
+
+
+def hs_sched_next(h, coll: int, stream: int, max_tags: int = 1024):
+    """(q_pad, k_batch, [tags]) or None when no batch forms."""
+    import numpy as np
+    qp = ctypes.c_int32()
+    kb = ctypes.c_int32()
+    cnt = ctypes.c_int32()
+    tags = np.zeros(max_tags, dtype=np.uint64)
+    _check(load().hs_sched_next(h, coll, stream, ctypes.byref(qp), ctypes.byref(kb), tags.ctypes.data, max_tags,
+                                ctypes.byref(cnt)))
+    if cnt.value == 0:
+        return None
+    return qp.value, kb.value, tags[:cnt.value].tolist()
+
+
+def hs_sched_complete(h, coll: int, stream: int) -> None:
+    _check(load().hs_sched_complete(h, coll, stream))
+
+
+def hs_sched_in_system(h) -> int:
+    n = ctypes.c_int32()
+    _check(load().hs_sched_in_system(h, ctypes.byref(n)))
+    return n.value
+
+
+def hs_sched_destroy(h) -> None:
+    _check(load().hs_sched_destroy(h))
 
 
 def hs_index_free(h) -> None:
@@ -311,6 +424,60 @@ class Index:
     def close(self):
         if getattr(self, "h", None):
             hs_index_free(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Server:
+    """Continuous-batching server over several Index objects (serving form)."""
+
+    def __init__(self, indexes, forms=None, budget_bytes: int = 4 << 30, streams_per_coll: int = 2,
+                 max_slots: int = 4096, max_batch: int = 256):
+        import torch
+        self.indexes = list(indexes)
+        self.forms = list(forms) if forms is not None else [0] * len(self.indexes)
+        dev = self.indexes[0].device
+        self.budget = torch.empty(budget_bytes, dtype=torch.uint8, device=dev)
+        torch.cuda.synchronize()
+        cfg = hs_server_config(streams_per_coll, max_slots, max_batch, 0)
+        self.h = hs_server_create([ix.h for ix in self.indexes], self.forms, self.budget.data_ptr(),
+                                  budget_bytes, cfg)
+        self._buf = (hs_completion * 1024)()
+
+    def submit(self, coll: int, q, k: int, tag: int) -> bool:
+        """Queue one request (q: float32 numpy [n]); False if every slot is busy."""
+        import numpy as np
+        q = np.ascontiguousarray(q, dtype=np.float32)
+        if 0 <= coll < len(self.indexes) and (q.ndim != 1 or q.shape[0] != self.indexes[coll].n):
+            raise ValueError("q must be float32 [n] of the collection")
+        return hs_submit(self.h, coll, q.ctypes.data, k, tag) == HS_OK
+
+    def poll(self):
+        """List of completions (dicts with tag, coll, k, status, batch, times, ids, d2, err)."""
+        out = []
+        while True:
+            got = hs_poll(self.h, self._buf, len(self._buf))
+            for i in range(got):
+                c = self._buf[i]
+                k = c.k
+                out.append({"tag": c.tag, "coll": c.coll, "k": k, "status": c.status, "batch": c.batch,
+                            "t_submit": c.t_submit, "t_launch": c.t_launch, "t_done": c.t_done,
+                            "ids": list(c.ids[:k]), "d2": list(c.d2[:k]), "err": list(c.err[:k])})
+            if got < len(self._buf):
+                return out
+
+    def info(self) -> dict:
+        st = hs_server_info(self.h)
+        return {f: getattr(st, f) for f, _ in hs_server_stats._fields_}
+
+    def close(self):
+        if getattr(self, "h", None):
+            hs_server_destroy(self.h)
             self.h = None
 
     def __del__(self):

@@ -1,0 +1,180 @@
+"""GPU tests of the serving form (hs_server_*): continuous batching over
+collections of different series lengths, requests of different k, plain and
+precision-form collections.
+
+The central property: every request's result is the same alone and in the
+mix -- identical ids and identical float32 distances -- and equal to the
+eager entry point's (hs_knn_exact / hs_knn_mixed) on the same query, which the
+oracle checks as in the other parity tests.  Graph replays are exercised by
+many batches of each captured shape, with eager calls and synchronisations
+between them.
+"""
+import time
+
+import numpy as np
+import pytest
+
+from paper_2212_13297_amd import datagen as G
+
+from parity import check_knn
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda:0"
+
+
+def hs_mod():
+    from paper_2212_13297_amd import hs
+    return hs
+
+
+def build_collections():
+    hs = hs_mod()
+    specs = [(30000, 128, 8, 1000), (20000, 256, 16, 1000), (6000, 1024, 32, 500)]
+    xs, idxs = [], []
+    for c, (N, n, w, leaf) in enumerate(specs):
+        print(f"[build] collection {c}: N={N} n={n}", flush=True)
+        x = G.random_walks(N, n, coll=70 + c)
+        xs.append(x)
+        idx = hs.Index(torch.from_numpy(x).to(DEV), hs.Params(w=w, leaf_size=leaf, l_max=2))
+        idxs.append(idx)
+    idxs[1].build_shadow(hs.HS_SHADOW_BF16)
+    torch.cuda.synchronize()
+    return xs, idxs
+
+
+def requests(xs, m, seed):
+    rng = np.random.default_rng(seed)
+    out = []
+    for i in range(m):
+        c = int(rng.integers(0, len(xs)))
+        x = xs[c]
+        src = int(rng.integers(0, len(x)))
+        p = float(rng.uniform(1, 10))
+        q = x[src].astype(np.float64) + rng.standard_normal(x.shape[1]) * np.sqrt(p / 100)
+        q = ((q - q.mean()) / q.std()).astype(np.float32)
+        k = int(rng.integers(1, 101))
+        out.append((c, q, k))
+    return out
+
+
+def drain(srv, want, timeout=120.0):
+    got = {}
+    t0 = time.time()
+    while len(got) < want:
+        for c in srv.poll():
+            got[c["tag"]] = c
+        if time.time() - t0 > timeout:
+            raise TimeoutError(f"{len(got)} of {want} completions after {timeout} s")
+        time.sleep(0.0005)
+    return got
+
+
+def eager(idx, q, k, mixed):
+    qt = torch.from_numpy(q[None, :].copy()).to(DEV)
+    if mixed:
+        ids, d2, err = idx.knn_mixed(qt, k)
+    else:
+        ids, d2 = idx.knn(qt, k)
+    torch.cuda.synchronize()
+    return ids.cpu().numpy()[0], d2.cpu().numpy()[0]
+
+
+def test_alone_equals_mix_equals_eager():
+    hs = hs_mod()
+    xs, idxs = build_collections()
+    forms = [0, 1, 0]
+    srv = hs.Server(idxs, forms, budget_bytes=3 << 30, streams_per_coll=2, max_slots=512, max_batch=64)
+    reqs = requests(xs, 120, seed=5)
+    # alone: one request in the server at a time
+    alone = {}
+    for t, (c, q, k) in enumerate(reqs[:30]):
+        assert srv.submit(c, q, k, t)
+        alone[t] = drain(srv, 1)[t]
+    # mix: everything at once (the first 30 again, under new tags), several batches per stream
+    for t, (c, q, k) in enumerate(reqs):
+        while not srv.submit(c, q, k, 1000 + t):
+            time.sleep(0.001)
+    mix = drain(srv, len(reqs))
+    info = srv.info()
+    print(f"[server] {info}", flush=True)
+    assert info["batches"] >= 2 and info["failed"] == 0
+    for t in range(30):
+        a, b = alone[t], mix[1000 + t]
+        assert a["status"] == 0 and b["status"] == 0
+        assert a["ids"] == b["ids"] and a["d2"] == b["d2"], f"request {t}: alone != mix"
+    # every mixed result equals the eager entry point on the same query, and the oracle
+    by_coll = {}
+    for t, (c, q, k) in enumerate(reqs):
+        r = mix[1000 + t]
+        assert r["status"] == 0 and r["k"] == k and len(r["ids"]) == k
+        ids, d2 = eager(idxs[c], q, k, forms[c] == 1)
+        assert list(ids) == r["ids"] and list(d2) == r["d2"], f"request {t}: server != eager"
+        if forms[c] == 1:
+            assert all(e > 0 for e in r["err"])
+        by_coll.setdefault(c, []).append((q, k, r))
+    for c, items in by_coll.items():
+        for kk in sorted({k for _, k, _ in items})[:4]:
+            sel = [(q, r) for q, k, r in items if k == kk]
+            qs = np.stack([q for q, _ in sel])
+            check_knn(xs[c], qs, kk, np.array([r["ids"] for _, r in sel]), np.array([r["d2"] for _, r in sel]))
+    srv.close()
+    for ix in idxs:
+        ix.close()
+
+
+def test_busy_slots_and_stream_of_arrivals():
+    hs = hs_mod()
+    xs, idxs = build_collections()
+    srv = hs.Server(idxs, [0, 0, 0], budget_bytes=1 << 30, streams_per_coll=1, max_slots=8, max_batch=8)
+    reqs = requests(xs, 200, seed=9)
+    busy = 0
+    done = {}
+    t = 0
+    t0 = time.time()
+    while t < len(reqs):
+        c, q, k = reqs[t]
+        if srv.submit(c, q, k, t):
+            t += 1
+        else:
+            busy += 1
+            for r in srv.poll():
+                done[r["tag"]] = r
+            time.sleep(0.0002)
+        assert time.time() - t0 < 120
+    done.update(drain(srv, len(reqs) - len(done)))
+    assert busy > 0, "max_slots=8 never filled"
+    assert sorted(done) == list(range(len(reqs)))
+    for r in done.values():
+        assert r["status"] == 0 and r["batch"] <= 8
+        assert r["t_submit"] <= r["t_launch"] <= r["t_done"]
+    # spot-check against the eager path
+    for t in range(0, len(reqs), 25):
+        c, q, k = reqs[t]
+        ids, d2 = eager(idxs[c], q, k, False)
+        assert list(ids) == done[t]["ids"] and list(d2) == done[t]["d2"]
+    srv.close()
+    for ix in idxs:
+        ix.close()
+
+
+def test_server_argument_errors():
+    hs = hs_mod()
+    xs, idxs = build_collections()
+    with pytest.raises(hs.HSError):
+        hs.Server(idxs, [0, 0, 1], budget_bytes=1 << 30)   # collection 2 has no low-precision copy
+    with pytest.raises(hs.HSError):
+        hs.Server(idxs, [0, 0, 0], budget_bytes=1 << 12)   # region cannot hold one query
+    srv = hs.Server(idxs, [0, 0, 0], budget_bytes=1 << 30, max_slots=4, max_batch=4)
+    with pytest.raises(hs.HSError):
+        srv.submit(0, np.full(128, np.nan, np.float32), 3, 0)
+    with pytest.raises(hs.HSError):
+        srv.submit(0, xs[0][0], 0, 0)
+    with pytest.raises(hs.HSError):
+        srv.submit(5, xs[0][0], 3, 0)
+    with pytest.raises(ValueError):
+        srv.submit(1, xs[0][0], 3, 0)                      # wrong length for collection 1
+    srv.close()
+    for ix in idxs:
+        ix.close()
