@@ -278,9 +278,6 @@ int64_t ws_layout(const hs_index* idx, int32_t Q, int32_t k, QueryWs* ws, char* 
     carve(cur, (void**)&w.slice_lb, cand * 4);
     carve(cur, (void**)&w.slice_cnt, ((int64_t)n_slices + 1) * 4);
     carve(cur, (void**)&w.slice_start, ((int64_t)n_slices + 2) * 4);
-    carve(cur, (void**)&w.cand_pos, cand * 4);
-    carve(cur, (void**)&w.cand_q, cand * 4);
-    carve(cur, (void**)&w.cand_lb, cand * 4);
     carve(cur, (void**)&w.counters, kNumCounters * 4);
     const int32_t Qpad = (Q + kBoundQueries - 1) / kBoundQueries * kBoundQueries;
     carve(cur, (void**)&w.qlow, (int64_t)Qpad * ix.stride * 2);
@@ -584,11 +581,11 @@ hs_status knn_enqueue(const KnnCall& c, const float* q_dev, int64_t* ids_dev, fl
     // matrix-core bound of the precision form); step 4: refinement
     HIP_TRY(launch_emit(ix, sp, false, ws, st));
     if (c.mixed) {
-        HIP_TRY(timed(HS_PROF_BOUND, [&] { return launch_bound(ix, c.idx->shadow, sp, ws, st); }));
+        HIP_TRY(timed(HS_PROF_BOUND, [&] { return launch_bound(ix, c.idx->shadow, sp, ws, c.idx->cus, st); }));
     } else {
         HIP_TRY(timed(HS_PROF_FILTER, [&] { return launch_filter(ix, sp, ws, c.idx->cus, st); }));
     }
-    HIP_TRY(launch_compact(ws, st));
+    HIP_TRY(launch_slice_prefix(ws, st));
     HIP_TRY(timed(HS_PROF_REFINE, [&] { return launch_refine(ix, sp, ws, c.idx->cus, c.form, st); }));
     sp.final_pass = 1;
     HIP_TRY(launch_merge(ix, sp, false, ws, ids_dev, d2_dev, err_dev, c.err_rel, stats_out, st));

@@ -6,8 +6,9 @@
 // counter in a register (no atomics), and wavefronts never wait for each
 // other except when their workgroup switches to another query's LB_SAX table
 // (items are ordered by query and each workgroup takes a contiguous range).
-// After the filter, slice_prefix and compact concatenate the slices into the
-// dense candidate list.
+// After the filter, slice_prefix computes where each slice starts in the
+// candidate list, the slices' concatenation, which the refine kernel reads
+// in place.
 #include "hs_device.h"
 
 namespace hs {
@@ -243,18 +244,6 @@ __global__ void __launch_bounds__(1024) k_slice_prefix(QueryWs ws) {
     }
 }
 
-// One workgroup per slice: copy its entries to their place in the list.
-__global__ void __launch_bounds__(256) k_compact(QueryWs ws) {
-    const int64_t s = blockIdx.x;
-    const uint32_t c = ws.slice_cnt[s], dst = ws.slice_start[s];
-    const int64_t src = s * ws.slice_cap;
-    for (uint32_t i = threadIdx.x; i < c; i += blockDim.x) {
-        ws.cand_pos[dst + i] = ws.slice_pos[src + i];
-        ws.cand_q[dst + i] = ws.slice_q[src + i];
-        ws.cand_lb[dst + i] = ws.slice_lb[src + i];
-    }
-}
-
 template <int W16>
 int filter_blocks(const IndexView& ix, int cus) {
     return resident_grid(k_filter<W16>, kTile, sizeof(float) * (size_t)ix.w * kCard, cus);
@@ -281,9 +270,8 @@ hipError_t launch_filter(const IndexView& ix, const ScanParams& sp, const QueryW
     return hipGetLastError();
 }
 
-hipError_t launch_compact(const QueryWs& ws, hipStream_t st) {
+hipError_t launch_slice_prefix(const QueryWs& ws, hipStream_t st) {
     hipLaunchKernelGGL(k_slice_prefix, dim3(1), dim3(1024), 0, st, ws);
-    hipLaunchKernelGGL(k_compact, dim3(ws.n_slices + 1), dim3(256), 0, st, ws);
     return hipGetLastError();
 }
 

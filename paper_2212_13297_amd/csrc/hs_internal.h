@@ -102,10 +102,6 @@ struct QueryWs {
     float* slice_lb;      // [n_slices][slice_cap] its LB_SAX
     uint32_t* slice_cnt;  // [n_slices] entries written in each slice
     uint32_t* slice_start;// [n_slices + 1] exclusive prefix of slice_cnt
-    // the candidate list: the slices concatenated (refine input)
-    uint32_t* cand_pos;   // [n_slices * slice_cap]
-    uint32_t* cand_q;
-    float* cand_lb;
     uint32_t* counters;   // [kNumCounters]
     // precision form
     uint16_t* qlow;       // [Qpad][stride] low-precision queries (zero rows beyond Q)
@@ -144,8 +140,8 @@ hipError_t launch_emit(const IndexView& ix, const ScanParams& sp, bool redo_only
 int filter_waves(const IndexView& ix, int device_cus);
 hipError_t launch_filter(const IndexView& ix, const ScanParams& sp, const QueryWs& ws, int device_cus,
                          hipStream_t st);
-// concatenate the filter's slices into the candidate list
-hipError_t launch_compact(const QueryWs& ws, hipStream_t st);
+// where each of the filter's slices starts in the candidate list (their concatenation)
+hipError_t launch_slice_prefix(const QueryWs& ws, hipStream_t st);
 hipError_t launch_refine(const IndexView& ix, const ScanParams& sp, const QueryWs& ws, int device_cus, int form,
                          hipStream_t st);
 hipError_t launch_leaf_scan(const IndexView& ix, const ScanParams& sp, const QueryWs& ws, int device_cus, int form,
@@ -162,6 +158,6 @@ hipError_t launch_query_low(const IndexView& ix, int kind, int32_t Q, const Quer
 // grid of the bounding pass: at most `max_waves` wavefronts (one candidate slice each)
 int bound_grid(int32_t Q, int max_waves);
 hipError_t launch_bound(const IndexView& ix, const ShadowView& sv, const ScanParams& sp, const QueryWs& ws,
-                        hipStream_t st);
+                        int device_cus, hipStream_t st);
 
 }  // namespace hs

@@ -16,6 +16,8 @@
 // bound exceeds BSF_k (1 + slack); a float32 test with proven margins discards
 // the clear cases, every pair it keeps is decided in float64, and the float64
 // bound travels with the candidate to the refinement (compensated float32).
+#include <algorithm>
+
 #include "hs_device.h"
 
 namespace hs {
@@ -128,13 +130,10 @@ __global__ void __launch_bounds__(64) k_query_low(IndexView ix, int32_t Q, Query
     if (lane == 0) ws.qnorm[q] = make_double2(s2 * (1.0 - 0x1p-40), sqrt(e2) * (1.0 + 0x1p-40));
 }
 
-// Constants of the float32 test (derivation in the header comment of the
-// bounding kernel below).
+// Constants of the float32 test.
 struct BoundConsts {
-    float k1;   // 1 - g, rounded down
-    float k2;   // 1 + 8u
-    float k3;   // 8u
-    double g;   // g for the float64 decision (plus 2^-40 for the float64 norms)
+    double g;   // accumulation factor g (plus 2^-40 for the float64 norms)
+    double m;   // margin factor 2u of the folded constants (u = 2^-24)
 };
 
 // Which q-group and row range a workgroup takes.  With enough workgroups the
@@ -164,28 +163,33 @@ __device__ __forceinline__ void bound_block(const BoundMap& m, int b, int& g0, i
 // it walks its row range part by part (a part lies in one leaf) in tiles of
 // 32 series.  Per tile and K-block the 32 x 256 low-precision series are
 // staged in LDS (double buffered: the next stage's global loads are in flight
-// during this stage's matrix-core steps) and every wavefront computes the
-// 32 x 32 block acc[series][query] with 16 v_mfma 32x32x16 steps; its query
-// fragments stay in registers when the series fit one K-block.
+// during this stage's matrix-core steps).  Every wavefront computes the 32 x 32 block
+// acc[series][query] with 16 v_mfma 32x32x16 steps; its query fragments stay
+// in registers when the series fit one K-block.
 //
 // Output layout of the 32x32 block: lane l holds query (l mod 32) and, in
 // accumulator r, series 8 (r / 4) + 4 (l / 32) + (r mod 4).
 //
-// Float32 test, per pair (u = 2^-24, T = ||q~||^2 + ||x~||^2 from the stored,
-// rounded-down norms, sT = sqrt(BSF_k (1 + slack)) + eps_q rounded up):
-//   a   = fma(-2, acc, fl(T) k1)          a   <= d(q~, x~) + 4.1 u T
-//   rhs = fma((sT + eps_x)^2, k2, T k3)    rhs >= (sT + eps_x)^2 + 7.9 u T
-// a > rhs therefore implies sqrt(d(q~, x~)) > sT + eps_x, i.e. the bound
-// exceeds BSF_k (1 + slack): the pair is dropped.  Otherwise the bound is
-// evaluated in float64 and decides.
-template <int KIND>
+// Float32 test.  With sT = sqrt(BSF_k (1 + slack)) + eps_q (rounded up), the
+// pair is dropped iff (1 - g)(||q~||^2 + ||x~||^2) - 2 acc > (sT + eps_x)^2,
+// i.e. iff acc < alpha_q + beta_x - sT eps_x with
+//   alpha_q = ((1 - g)||q~||^2 - sT^2) / 2,  beta_x = ((1 - g)||x~||^2 - eps_x^2) / 2.
+// alpha and beta are computed in float64, lowered by 2u (||q~||^2 + sT^2) and
+// 2u (||x~||^2 + eps_x^2) and rounded down; that margin exceeds the error of
+// the two float32 roundings of fma(-sT, eps_x, alpha + beta) (at most 1.5 u of
+// the same magnitudes), so acc < that float32 value implies the exact
+// condition.  Pairs that pass are decided in float64.
+template <int KIND, bool ONE>
 __global__ void __launch_bounds__(256) k_bound(IndexView ix, ShadowView sv, ScanParams sp, QueryWs ws,
                                                BoundConsts bc, BoundMap bm) {
 #pragma clang fp contract(off)
     __shared__ __attribute__((aligned(16))) uint16_t s_tile[2][kBoundRows * kLdsRow];
-    __shared__ float2 s_norm[2][kBoundRows];
+    __shared__ float2 s_norm[2][kBoundRows];  // (beta', eps_x) per staged series
+    __shared__ float s_xn[2][kBoundRows];     // ||x~||^2 per staged series
+    __shared__ float s_acc[kTile / 64][16 * 64];  // per wavefront: its accumulators, on the rare float64 path
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6, j = lane & 31, half = lane >> 5;
-    const int K = ix.stride, nkb = (K + kKBlock - 1) / kKBlock;
+    // ONE: the series fit one K-block (stride <= 256) and the query fragments stay in registers
+    const int K = ix.stride, nkb = ONE ? 1 : (K + kKBlock - 1) / kKBlock;
     const uint64_t lt_mask = (1ull << lane) - 1ull;
 
     const int64_t slice = (int64_t)blockIdx.x * (kTile / 64) + wave;
@@ -193,6 +197,10 @@ __global__ void __launch_bounds__(256) k_bound(IndexView ix, ShadowView sv, Scan
     uint32_t* sq = ws.slice_q + slice * ws.slice_cap;
     float* slb = ws.slice_lb + slice * ws.slice_cap;
     uint32_t cnt = 0;  // entries in this wavefront's slice (uniform)
+    // slices of wavefronts beyond this grid stay empty
+    for (int64_t e = (int64_t)gridDim.x * (kTile / 64) + (int64_t)blockIdx.x * kTile + t; e < ws.n_slices;
+         e += (int64_t)gridDim.x * kTile)
+        ws.slice_cnt[e] = 0;
 
     if ((int)blockIdx.x < bm.used) {
         int g0, r;
@@ -210,19 +218,23 @@ __global__ void __launch_bounds__(256) k_bound(IndexView ix, ShadowView sv, Scan
         for (int g = g0; g < bm.G; g += bm.GS) {
             const int qj = g * kBoundQueries + wave * 32 + j;
             const bool qvalid = qj < sp.Q && !(ws.flags[qj] & kFlagNonFinite);
-            float qn32 = 0.0f, sT = 0.0f, bsf_j = 0.0f;
+            float alpha = -3.0e38f, sT = 0.0f, bsf_j = 0.0f;
             if (qvalid) {
                 const double2 qn = ws.qnorm[qj];
                 bsf_j = bits_to_float(ws.bsf[qj]);
-                qn32 = __double2float_rd(qn.x);
-                sT = __double2float_ru((sqrt(prune_limit(bsf_j)) + qn.y) * (1.0 + 0x1p-40));
+                const double T = prune_limit(bsf_j);
+                if (T < 1e300) {  // no BSF_k yet: every pair passes the float32 test
+                    sT = __double2float_ru((sqrt(T) + qn.y) * (1.0 + 0x1p-40));
+                    const double s2 = (double)sT * (double)sT;
+                    alpha = __double2float_rd(0.5 * ((1.0 - bc.g) * qn.x - s2) - bc.m * (qn.x + s2));
+                }
             }
             const uint16_t* qlow = ws.qlow + (int64_t)(g * kBoundQueries + wave * 32 + j) * K + 8 * half;
             uint4 bq[kKSteps];
-            if (nkb == 1) {
+            if (ONE) {
 #pragma unroll
-                for (int s = 0; s < kKSteps; ++s)
-                    bq[s] = s * 16 < K ? *reinterpret_cast<const uint4*>(qlow + s * 16) : make_uint4(0, 0, 0, 0);
+                for (int u = 0; u < kKSteps; ++u)
+                    bq[u] = u * 16 < K ? *reinterpret_cast<const uint4*>(qlow + u * 16) : make_uint4(0, 0, 0, 0);
             }
             unsigned long long tested = 0, cands = 0;
             bool lost = false;
@@ -241,48 +253,67 @@ __global__ void __launch_bounds__(256) k_bound(IndexView ix, ShadowView sv, Scan
                 // number t + 256 i (i < 4) of the 32 x 256 block: row (that / 32),
                 // 8-element column (that % 32); rows past the collection are
                 // clamped (their results are masked).
-                uint4 pre[4];
-                float2 pre_n = make_float2(0.f, 0.f);
-                auto stage_load = [&](int64_t s) {
+                uint4 pa[4];
+                float2 na = make_float2(0.f, 0.f);
+                auto stage_load = [&](int64_t s, uint4 (&pre)[4], float2& pn) {
+                    // branch-free: every address is clamped into the buffers (values
+                    // past the row are zeroed when stored, rows past the collection
+                    // are masked), so the loads stay in flight until their store
                     const int64_t tr0 = ps + (s / nkb) * kBoundRows;
                     const int kb = (int)(s % nkb);
 #pragma unroll
                     for (int i = 0; i < 4; ++i) {
                         const int e = t + 256 * i, rr = e >> 5, cc = (e & 31) * 8 + kb * kKBlock;
                         const int64_t row = min(tr0 + rr, ix.N - 1);
-                        pre[i] = cc < K ? *reinterpret_cast<const uint4*>(sv.rows + row * K + cc) : make_uint4(0, 0, 0, 0);
+                        pre[i] = *reinterpret_cast<const uint4*>(sv.rows + row * K + min(cc, K - 8));
                     }
-                    if (kb == 0 && t < kBoundRows) pre_n = sv.norms[min(tr0 + t, ix.N - 1)];
+                    pn = sv.norms[min(tr0 + (t & (kBoundRows - 1)), ix.N - 1)];
                 };
-                auto stage_store = [&](int64_t s) {
+                auto stage_store = [&](int64_t s, const uint4 (&pre)[4], float2 pn) {
                     uint16_t* dst = s_tile[s & 1];
+                    const int kb = (int)(s % nkb);
 #pragma unroll
                     for (int i = 0; i < 4; ++i) {
                         const int e = t + 256 * i, rr = e >> 5, cc = (e & 31) * 8;
-                        *reinterpret_cast<uint4*>(dst + rr * kLdsRow + cc) = pre[i];
+                        *reinterpret_cast<uint4*>(dst + rr * kLdsRow + cc) =
+                            cc + kb * kKBlock < K ? pre[i] : make_uint4(0, 0, 0, 0);
                     }
-                    if ((s % nkb) == 0 && t < kBoundRows) s_norm[(s / nkb) & 1][t] = pre_n;
+                    if (kb == 0 && t < kBoundRows) {
+                        const double xd = pn.x, ed = pn.y;
+                        const float beta = __double2float_rd(0.5 * ((1.0 - bc.g) * xd - ed * ed) - bc.m * (xd + ed * ed));
+                        s_norm[(s / nkb) & 1][t] = make_float2(beta, pn.y);
+                        s_xn[(s / nkb) & 1][t] = pn.x;
+                    }
                 };
-                stage_load(0);
-                stage_store(0);
+                stage_load(0, pa, na);
+                stage_store(0, pa, na);
                 __syncthreads();
                 f32x16 acc = {};
                 for (int64_t s = 0; s < nst; ++s) {
                     const int64_t tile = s / nkb;
                     const int kb = (int)(s % nkb);
-                    if (s + 1 < nst) stage_load(s + 1);
+                    // the next stage's loads are in flight during this stage's steps
+                    if (s + 1 < nst) stage_load(s + 1, pa, na);
                     if (wkeep) {
-                        if (nkb > 1) {
+                        if (!ONE) {
 #pragma unroll
                             for (int u = 0; u < kKSteps; ++u) {
                                 const int c = kb * kKBlock + u * 16;
                                 bq[u] = c < K ? *reinterpret_cast<const uint4*>(qlow + c) : make_uint4(0, 0, 0, 0);
                             }
                         }
+                        // A fragments from LDS in groups of 4, each group's loads
+                        // issued while the previous group's steps execute
                         const uint16_t* arow = s_tile[s & 1] + j * kLdsRow + 8 * half;
 #pragma unroll
-                        for (int u = 0; u < kKSteps; ++u)
-                            acc = Low<KIND>::mma(*reinterpret_cast<const uint4*>(arow + u * 16), bq[u], acc);
+                        for (int u0 = 0; u0 < kKSteps; u0 += 4) {
+                            uint4 a[4];
+#pragma unroll
+                            for (int v = 0; v < 4; ++v) a[v] = *reinterpret_cast<const uint4*>(arow + (u0 + v) * 16);
+#pragma unroll
+                            for (int v = 0; v < 4; ++v) acc = Low<KIND>::mma(a[v], bq[u0 + v], acc);
+                            __builtin_amdgcn_sched_barrier(0);
+                        }
                     }
                     if (kb == nkb - 1) {
                         if (wkeep) {
@@ -290,19 +321,23 @@ __global__ void __launch_bounds__(256) k_bound(IndexView ix, ShadowView sv, Scan
                             const int nrows = (int)min((int64_t)kBoundRows, pe - tr0);
                             if (keep && half == 0) tested += (unsigned long long)nrows;
                             const float2* nrm = s_norm[tile & 1];
+                            const float* xnr = s_xn[tile & 1];
                             uint32_t mask = 0;
 #pragma unroll
                             for (int r = 0; r < 16; ++r) {
                                 const int i = 8 * (r >> 2) + 4 * half + (r & 3);
                                 const float2 nm = nrm[i];
-                                const float tt = qn32 + nm.x;
-                                const float a = fmaf(-2.0f, acc[r], tt * bc.k1);
-                                const float sx = sT + nm.y;
-                                const float rhs = fmaf(sx * sx, bc.k2, tt * bc.k3);
-                                if (keep && i < nrows && a <= rhs) mask |= 1u << r;
+                                const float thr = fmaf(-sT, nm.y, alpha + nm.x);
+                                if (acc[r] >= thr && i < nrows) mask |= 1u << r;
                             }
+                            if (!keep) mask = 0;
                             if (__ballot(mask != 0u) != 0ull) {
-                                // float64 decision on the pairs the float32 test kept
+                                // rare: the pairs the float32 test kept are decided in
+                                // float64; the accumulators go through LDS so that the
+                                // loops below index them without unrolling
+                                float* sacc = s_acc[wave];
+#pragma unroll
+                                for (int r = 0; r < 16; ++r) sacc[r * 64 + lane] = acc[r];
                                 double2 qn = make_double2(0.0, 0.0);
                                 if (mask) qn = ws.qnorm[qj];
                                 const double lim = prune_limit(bsf_j);
@@ -311,12 +346,11 @@ __global__ void __launch_bounds__(256) k_bound(IndexView ix, ShadowView sv, Scan
                                     if (!((mask >> r) & 1u)) continue;
                                     const int i = 8 * (r >> 2) + 4 * half + (r & 3);
                                     const float2 nm = nrm[i];
-                                    const double D = (1.0 - bc.g) * (qn.x + (double)nm.x) - 2.0 * (double)acc[r];
+                                    const double D = (1.0 - bc.g) * (qn.x + (double)xnr[i]) - 2.0 * (double)sacc[r * 64 + lane];
                                     const double lr = fmax(sqrt(fmax(D, 0.0)) - qn.y - (double)nm.y, 0.0);
                                     if (lr * lr <= lim) fm |= 1u << r;
                                 }
                                 uint32_t total = 0;
-#pragma unroll
                                 for (int r = 0; r < 16; ++r) total += (uint32_t)__popcll(__ballot((fm >> r) & 1u));
                                 if (total) {
                                     uint32_t* dpos = spos;
@@ -355,8 +389,8 @@ __global__ void __launch_bounds__(256) k_bound(IndexView ix, ShadowView sv, Scan
                                             if ((fm >> r) & 1u) {
                                                 const int i = 8 * (r >> 2) + 4 * half + (r & 3);
                                                 const float2 nm = nrm[i];
-                                                const double D =
-                                                    (1.0 - bc.g) * (qn.x + (double)nm.x) - 2.0 * (double)acc[r];
+                                                const double D = (1.0 - bc.g) * (qn.x + (double)xnr[i]) -
+                                                                 2.0 * (double)sacc[r * 64 + lane];
                                                 const double lr =
                                                     fmax(sqrt(fmax(D, 0.0)) - qn.y - (double)nm.y, 0.0);
                                                 const uint32_t slot = off + (uint32_t)__popcll(bal & lt_mask);
@@ -374,7 +408,7 @@ __global__ void __launch_bounds__(256) k_bound(IndexView ix, ShadowView sv, Scan
                         }
                         acc = f32x16{};
                     }
-                    if (s + 1 < nst) stage_store(s + 1);
+                    if (s + 1 < nst) stage_store(s + 1, pa, na);
                     __syncthreads();
                 }
             }
@@ -411,8 +445,18 @@ hipError_t launch_query_low(const IndexView& ix, int kind, int32_t Q, const Quer
 }
 
 hipError_t launch_bound(const IndexView& ix, const ShadowView& sv, const ScanParams& sp, const QueryWs& ws,
-                        hipStream_t st) {
-    const int grid = ws.n_slices / (kTile / 64);  // one candidate slice per wavefront
+                        int device_cus, hipStream_t st) {
+    // one candidate slice per wavefront; no more workgroups than are resident
+    int grid = ws.n_slices / (kTile / 64);
+    const bool one = ix.stride <= kKBlock;
+    int resident;
+    if (sv.kind == kShadowF16)
+        resident = one ? resident_grid(k_bound<kShadowF16, true>, kTile, 0, device_cus)
+                       : resident_grid(k_bound<kShadowF16, false>, kTile, 0, device_cus);
+    else
+        resident = one ? resident_grid(k_bound<kShadowBf16, true>, kTile, 0, device_cus)
+                       : resident_grid(k_bound<kShadowBf16, false>, kTile, 0, device_cus);
+    grid = std::max(1, std::min(grid, resident));
     BoundMap bm{};
     bm.G = ws.Qpad / kBoundQueries;
     if (bm.G * 8 <= grid) {
@@ -427,16 +471,16 @@ hipError_t launch_bound(const IndexView& ix, const ShadowView& sv, const ScanPar
     bm.used = bm.R * bm.GS;
     // g: accumulation error factor for K additions at twice the unit roundoff
     const double u2 = std::ldexp(1.0, -23), Kd = (double)ix.stride;
-    const double g = Kd * u2 / (1.0 - Kd * u2);
     BoundConsts bc;
-    bc.k1 = std::nextafter((float)(1.0 - g), 0.0f);
-    bc.k2 = (float)(1.0 + 8.0 * std::ldexp(1.0, -24)) ;
-    bc.k3 = (float)(8.0 * std::ldexp(1.0, -24));
-    bc.g = g + std::ldexp(1.0, -40);
-    if (sv.kind == kShadowF16)
-        k_bound<kShadowF16><<<dim3(grid), dim3(kTile), 0, st>>>(ix, sv, sp, ws, bc, bm);
-    else
-        k_bound<kShadowBf16><<<dim3(grid), dim3(kTile), 0, st>>>(ix, sv, sp, ws, bc, bm);
+    bc.g = Kd * u2 / (1.0 - Kd * u2) + std::ldexp(1.0, -40);
+    bc.m = 2.0 * std::ldexp(1.0, -24);
+    if (sv.kind == kShadowF16) {
+        if (one) k_bound<kShadowF16, true><<<dim3(grid), dim3(kTile), 0, st>>>(ix, sv, sp, ws, bc, bm);
+        else k_bound<kShadowF16, false><<<dim3(grid), dim3(kTile), 0, st>>>(ix, sv, sp, ws, bc, bm);
+    } else {
+        if (one) k_bound<kShadowBf16, true><<<dim3(grid), dim3(kTile), 0, st>>>(ix, sv, sp, ws, bc, bm);
+        else k_bound<kShadowBf16, false><<<dim3(grid), dim3(kTile), 0, st>>>(ix, sv, sp, ws, bc, bm);
+    }
     return hipGetLastError();
 }
 

@@ -23,13 +23,31 @@ struct Meta {
     float lb;
 };
 
+// The candidate list is the concatenation of the filter's slices (the private
+// slices, then the overflow slice); slice_start holds their exclusive prefix.
+// Slice of list entry c: the last s with slice_start[s] <= c, searched from the
+// lane's previous slice (entries are visited in increasing order, so the hint
+// is almost always right and otherwise a short binary search finds it).
+__device__ __forceinline__ int slice_of(const QueryWs& ws, long long c, int hint) {
+    if ((long long)ws.slice_start[hint + 1] > c) return hint;
+    int lo = hint + 1, hi = ws.n_slices;  // answer in [lo, hi]
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if ((long long)ws.slice_start[mid] <= c) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
 // Candidate c of the list; lanes 0..15 call this for c = base + lane.
-__device__ __forceinline__ Meta load_meta(const QueryWs& ws, long long c, long long cend) {
+__device__ __forceinline__ Meta load_meta(const QueryWs& ws, long long c, long long cend, int& hint) {
     Meta m{-1, 0u, 0.0f};
     if (c < cend) {
-        m.q = (int)ws.cand_q[c];
-        m.pos = ws.cand_pos[c];
-        m.lb = ws.cand_lb[c];
+        hint = slice_of(ws, c, hint);
+        const long long e = (long long)hint * ws.slice_cap + (c - (long long)ws.slice_start[hint]);
+        m.q = (int)ws.slice_q[e];
+        m.pos = ws.slice_pos[e];
+        m.lb = ws.slice_lb[e];
     }
     return m;
 }
@@ -40,7 +58,7 @@ __global__ void __launch_bounds__(256) k_refine(IndexView ix, ScanParams sp, Que
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6, sub = t & 15, grp = (t >> 4) & 3;
     const int k = sp.k;
     const int nchunks = ix.stride / kChunk;
-    const long long T = ws.counters[kCtrCand];
+    const long long T = ws.slice_start[ws.n_slices + 1];
     const long long gw = (long long)blockIdx.x * (kTile / 64) + wave, GW = (long long)gridDim.x * (kTile / 64);
     const long long cbeg = T * gw / GW, cend = T * (gw + 1) / GW;
     unsigned long long* top = s_top[wave];
@@ -52,11 +70,12 @@ __global__ void __launch_bounds__(256) k_refine(IndexView ix, ScanParams sp, Que
     int st_q = -1;                                    // lane 0: counters of st_q
     unsigned long long st_ref = 0, st_ch = 0;
 
-    Meta m = lane < kStep ? load_meta(ws, cbeg + lane, cend) : Meta{-1, 0u, 0.0f};
+    int hint = 0;  // lane's slice
+    Meta m = lane < kStep ? load_meta(ws, cbeg + lane, cend, hint) : Meta{-1, 0u, 0.0f};
     float mb = m.q >= 0 ? bits_to_float(load_relaxed(&ws.bsf[m.q])) : 0.0f;
     for (long long cb = cbeg; cb < cend; cb += kStep) {
         // next step's metadata in flight while this step is refined
-        const Meta nm = lane < kStep ? load_meta(ws, cb + kStep + lane, cend) : Meta{-1, 0u, 0.0f};
+        const Meta nm = lane < kStep ? load_meta(ws, cb + kStep + lane, cend, hint) : Meta{-1, 0u, 0.0f};
 
         unsigned long long res[4];  // admitted keys of this group (group-uniform), ~0 = none
         int resq[4];
