@@ -6,7 +6,7 @@
 // Every wavefront owns a contiguous range of the candidate list (regions are
 // ordered by query, so a range holds long runs of one query) and never waits
 // for another wavefront: the metadata of its next 16 candidates is loaded
-// while the current ones are refined, each 16-lane group refines two series
+// while the current ones are refined, each 16-lane group refines four series
 // at a time (their next two 64-point chunks loaded together), and the
 // admitted results reach lane 0 by shuffles; lane 0 alone keeps the
 // wavefront's top-k in LDS.
@@ -39,12 +39,23 @@ __device__ __forceinline__ int slice_of(const QueryWs& ws, long long c, int hint
     return lo;
 }
 
-// Candidate c of the list; lanes 0..15 call this for c = base + lane.
-__device__ __forceinline__ Meta load_meta(const QueryWs& ws, long long c, long long cend, int& hint) {
+// Candidate c of the list; lanes 0..15 call this for c = base + lane.  The
+// lane keeps its slice's first entry and end in registers: only a step across
+// a slice end loads the prefix again.
+struct SliceCursor {
+    int s = 0;
+    long long begin = 0, end = 0;
+};
+
+__device__ __forceinline__ Meta load_meta(const QueryWs& ws, long long c, long long cend, SliceCursor& cur) {
     Meta m{-1, 0u, 0.0f};
     if (c < cend) {
-        hint = slice_of(ws, c, hint);
-        const long long e = (long long)hint * ws.slice_cap + (c - (long long)ws.slice_start[hint]);
+        if (c >= cur.end) {
+            cur.s = slice_of(ws, c, cur.s);
+            cur.begin = ws.slice_start[cur.s];
+            cur.end = ws.slice_start[cur.s + 1];
+        }
+        const long long e = (long long)cur.s * ws.slice_cap + (c - cur.begin);
         m.q = (int)ws.slice_q[e];
         m.pos = ws.slice_pos[e];
         m.lb = ws.slice_lb[e];
@@ -70,12 +81,12 @@ __global__ void __launch_bounds__(256) k_refine(IndexView ix, ScanParams sp, Que
     int st_q = -1;                                    // lane 0: counters of st_q
     unsigned long long st_ref = 0, st_ch = 0;
 
-    int hint = 0;  // lane's slice
-    Meta m = lane < kStep ? load_meta(ws, cbeg + lane, cend, hint) : Meta{-1, 0u, 0.0f};
+    SliceCursor cur;  // lane's slice (end 0: found on the first load)
+    Meta m = lane < kStep ? load_meta(ws, cbeg + lane, cend, cur) : Meta{-1, 0u, 0.0f};
     float mb = m.q >= 0 ? bits_to_float(load_relaxed(&ws.bsf[m.q])) : 0.0f;
     for (long long cb = cbeg; cb < cend; cb += kStep) {
         // next step's metadata in flight while this step is refined
-        const Meta nm = lane < kStep ? load_meta(ws, cb + kStep + lane, cend, hint) : Meta{-1, 0u, 0.0f};
+        const Meta nm = lane < kStep ? load_meta(ws, cb + kStep + lane, cend, cur) : Meta{-1, 0u, 0.0f};
 
         unsigned long long res[4];  // admitted keys of this group (group-uniform), ~0 = none
         int resq[4];
