@@ -253,7 +253,7 @@ def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
-    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--N", type=int, default=10_000_000)
     ap.add_argument("--n", type=int, default=256)
     ap.add_argument("--per-level", type=int, default=100)

@@ -5,17 +5,15 @@
 //
 // Every wavefront owns a contiguous range of the candidate list (regions are
 // ordered by query, so a range holds long runs of one query) and never waits
-// for another wavefront: the metadata of its next 16 candidates is loaded
-// while the current ones are refined, each 16-lane group refines four series
-// at a time (their next two 64-point chunks loaded together), and the
-// admitted results reach lane 0 by shuffles; lane 0 alone keeps the
-// wavefront's top-k in LDS.
+// for another wavefront: the metadata of its next 4 NC candidates is loaded
+// while the current ones are refined, each 16-lane group refines NC series at
+// a time (CB 64-point chunks of each loaded together), and the admitted
+// results reach lane 0 by shuffles; lane 0 alone keeps the wavefront's top-k
+// in LDS.
 #include "hs_device.h"
 
 namespace hs {
 namespace {
-
-constexpr int kStep = 16;  // candidates per wavefront step: 4 groups x 4
 
 struct Meta {
     int q;
@@ -63,8 +61,11 @@ __device__ __forceinline__ Meta load_meta(const QueryWs& ws, long long c, long l
     return m;
 }
 
-template <int F>
+// F: distance form.  NC: series in flight per 16-lane group; CB: 64-point
+// chunks loaded together per series between two abandoning checks.
+template <int F, int NC, int CB>
 __global__ void __launch_bounds__(256) k_refine(IndexView ix, ScanParams sp, QueryWs ws) {
+    constexpr int kStep = 4 * NC;  // candidates per wavefront step: 4 groups x NC
     __shared__ unsigned long long s_top[kTile / 64][HS_KMAX];
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6, sub = t & 15, grp = (t >> 4) & 3;
     const int k = sp.k;
@@ -88,20 +89,20 @@ __global__ void __launch_bounds__(256) k_refine(IndexView ix, ScanParams sp, Que
         // next step's metadata in flight while this step is refined
         const Meta nm = lane < kStep ? load_meta(ws, cb + kStep + lane, cend, cur) : Meta{-1, 0u, 0.0f};
 
-        unsigned long long res[4];  // admitted keys of this group (group-uniform), ~0 = none
-        int resq[4];
-        unsigned chs[4];            // chunks read per candidate (0: not refined)
+        unsigned long long res[NC];  // admitted keys of this group (group-uniform), ~0 = none
+        int resq[NC];
+        unsigned chs[NC];            // chunks read per candidate (0: not refined)
         float nmb = 0.0f;           // next step's BSF_k, loaded behind this step's first rows
         {
-            int q[4];
-            uint32_t pos[4];
-            float thr[4];
-            Dist<F> d[4];
-            bool alive[4], refined[4];
-            unsigned ch[4] = {0u, 0u, 0u, 0u};
+            int q[NC];
+            uint32_t pos[NC];
+            float thr[NC];
+            Dist<F> d[NC];
+            bool alive[NC], refined[NC];
+            unsigned ch[NC];
 #pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                const int src = grp * 4 + j;
+            for (int j = 0; j < NC; ++j) {
+                const int src = grp * NC + j;
                 q[j] = __shfl(m.q, src, 64);
                 pos[j] = __shfl(m.pos, src, 64);
                 const float lb = __shfl(m.lb, src, 64);
@@ -109,45 +110,47 @@ __global__ void __launch_bounds__(256) k_refine(IndexView ix, ScanParams sp, Que
                 if (q[j] == cur_q) thr[j] = fminf(thr[j], lk);
                 refined[j] = q[j] >= 0 && (double)lb <= prune_limit(thr[j]);
                 alive[j] = refined[j];
+                ch[j] = 0u;
             }
-            for (int c = 0; c < nchunks; c += 2) {
-                const bool two = c + 1 < nchunks;
-                float4 x0[4], x1[4];
+            for (int c = 0; c < nchunks; c += CB) {
+                float4 x[NC][CB];
 #pragma unroll
-                for (int j = 0; j < 4; ++j) {
+                for (int j = 0; j < NC; ++j) {
                     if (alive[j]) {
                         const float* xr = ix.rows + (int64_t)pos[j] * ix.stride + sub * 4 + c * kChunk;
-                        x0[j] = *reinterpret_cast<const float4*>(xr);
-                        x1[j] = two ? *reinterpret_cast<const float4*>(xr + kChunk) : make_float4(0.f, 0.f, 0.f, 0.f);
+#pragma unroll
+                        for (int b = 0; b < CB; ++b)
+                            x[j][b] = c + b < nchunks ? *reinterpret_cast<const float4*>(xr + b * kChunk)
+                                                      : make_float4(0.f, 0.f, 0.f, 0.f);
                     }
                 }
                 if (c == 0 && nm.q >= 0) nmb = bits_to_float(load_relaxed(&ws.bsf[nm.q]));
                 // the group's candidates almost always share a query: its chunks are
                 // loaded once and reloaded only for a candidate of another query
                 const float* q0 = ws.qrow + (int64_t)q[0] * ix.stride + sub * 4 + c * kChunk;
-                float4 qa = make_float4(0.f, 0.f, 0.f, 0.f), qb = qa;
-                if (q[0] >= 0) {
-                    qa = *reinterpret_cast<const float4*>(q0);
-                    if (two) qb = *reinterpret_cast<const float4*>(q0 + kChunk);
-                }
+                float4 qa[CB];
 #pragma unroll
-                for (int j = 0; j < 4; ++j) {
+                for (int b = 0; b < CB; ++b)
+                    qa[b] = (q[0] >= 0 && c + b < nchunks) ? *reinterpret_cast<const float4*>(q0 + b * kChunk)
+                                                          : make_float4(0.f, 0.f, 0.f, 0.f);
+#pragma unroll
+                for (int j = 0; j < NC; ++j) {
                     if (alive[j]) {
-                        float4 a = qa, b = qb;
-                        if (q[j] != q[0]) {
-                            const float* qr = ws.qrow + (int64_t)q[j] * ix.stride + sub * 4 + c * kChunk;
-                            a = *reinterpret_cast<const float4*>(qr);
-                            if (two) b = *reinterpret_cast<const float4*>(qr + kChunk);
+                        const float* qr = ws.qrow + (int64_t)q[j] * ix.stride + sub * 4 + c * kChunk;
+#pragma unroll
+                        for (int b = 0; b < CB; ++b) {
+                            if (c + b < nchunks) {
+                                const float4 a = q[j] != q[0] ? *reinterpret_cast<const float4*>(qr + b * kChunk) : qa[b];
+                                d[j].add(a, x[j][b]);
+                                ch[j] += 1u;
+                            }
                         }
-                        d[j].add(a, x0[j]);
-                        if (two) d[j].add(b, x1[j]);
-                        ch[j] += two ? 2u : 1u;
                         if (d[j].value() > thr[j]) alive[j] = false;
                     }
                 }
             }
 #pragma unroll
-            for (int j = 0; j < 4; ++j) {
+            for (int j = 0; j < NC; ++j) {
                 chs[j] = refined[j] ? ch[j] : 0u;
                 res[j] = (refined[j] && alive[j]) ? (((unsigned long long)__float_as_uint(d[j].value()) << 32) | ix.ids[pos[j]])
                                                   : ~0ull;
@@ -159,10 +162,10 @@ __global__ void __launch_bounds__(256) k_refine(IndexView ix, ScanParams sp, Que
         int new_q = cur_q;
         float new_lk = lk;
 #pragma unroll
-        for (int i = 0; i < 16; ++i) {
-            const unsigned long long key = __shfl(res[i & 3], (i >> 2) * 16, 64);
-            const int kq = __shfl(resq[i & 3], (i >> 2) * 16, 64);
-            const unsigned kch = __shfl(chs[i & 3], (i >> 2) * 16, 64);
+        for (int i = 0; i < kStep; ++i) {
+            const unsigned long long key = __shfl(res[i % NC], (i / NC) * 16, 64);
+            const int kq = __shfl(resq[i % NC], (i / NC) * 16, 64);
+            const unsigned kch = __shfl(chs[i % NC], (i / NC) * 16, 64);
             if (lane == 0) {
                 if (key != ~0ull) {
                     if (kq != new_q) {
@@ -212,10 +215,19 @@ __global__ void __launch_bounds__(256) k_refine(IndexView ix, ScanParams sp, Que
 
 hipError_t launch_refine(const IndexView& ix, const ScanParams& sp, const QueryWs& ws, int device_cus, int form,
                          hipStream_t st) {
-    if (form == kComp)
-        k_refine<kComp><<<dim3(resident_grid(k_refine<kComp>, kTile, 0, device_cus)), dim3(kTile), 0, st>>>(ix, sp, ws);
-    else
-        k_refine<kPlain><<<dim3(resident_grid(k_refine<kPlain>, kTile, 0, device_cus)), dim3(kTile), 0, st>>>(ix, sp, ws);
+    // series of at least 256 points: two in flight per group, four chunks
+    // (1 KB of a row) per load; shorter series: four in flight, two chunks
+#define HS_REFINE(FF, NC, CB) \
+    k_refine<FF, NC, CB><<<dim3(resident_grid(k_refine<FF, NC, CB>, kTile, 0, device_cus)), dim3(kTile), 0, st>>>(ix, sp, ws)
+    const bool wide = ix.stride >= 4 * kChunk;
+    if (form == kComp) {
+        if (wide) HS_REFINE(kComp, 2, 4);
+        else HS_REFINE(kComp, 4, 2);
+    } else {
+        if (wide) HS_REFINE(kPlain, 2, 4);
+        else HS_REFINE(kPlain, 4, 2);
+    }
+#undef HS_REFINE
     return hipGetLastError();
 }
 
