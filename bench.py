@@ -47,6 +47,7 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_scan_kernels_random_w
 KERNEL_SOURCES = {
     "k_filter": ["hs_filter.hip", "hs_device.h", "hs_internal.h"],
     "k_refine": ["hs_refine.hip", "hs_device.h", "hs_internal.h"],
+    "k_bound": ["hs_precision.hip", "hs_device.h", "hs_internal.h"],
 }
 
 
@@ -129,6 +130,7 @@ def run_mixed(args, hs, torch, idx, qt, Q, plain_ids, plain_stats):
         nbytes = (int(stats["chunks_read"].sum()) * 256 + int(stats["candidates"].sum()) * 12) / (rl / args.steps)
         kern["refine"] = {"avg_launch_ms": round(avg, 4), "launches_per_step": rl / args.steps,
                           "bytes_per_launch": int(nbytes), "GB_s": round(nbytes / (avg / 1e3) / 1e9, 2)}
+    traffic = measured_traffic("k_bound", {"N": args.N, "n": args.n, "Q": Q, "k": args.k})
     out = {"value": round(qps, 2), "unit": "queries/s", "ms_per_step": round(ms, 4), "dtype": "bf16 bound, f32 refine",
            "identical_id_lists_vs_plain": same, "queries": Q,
            "max_err_bound_rel": float((err / d2.double()).max().item()),
@@ -136,7 +138,8 @@ def run_mixed(args, hs, torch, idx, qt, Q, plain_ids, plain_stats):
            "kernels": kern,
            "roofline": ({"bound": "mfma", "achieved": kern["bound"]["TFLOP_s"], "peak": MFMA_PEAK_TFLOPS["bf16"],
                          "unit": "TFLOP/s", "frac": round(kern["bound"]["TFLOP_s"] / MFMA_PEAK_TFLOPS["bf16"], 4),
-                         "kernel": "k_bound"} if "bound" in kern else None),
+                         "kernel": "k_bound", "traffic": traffic.get("bytes_per_launch") if traffic else None,
+                         "traffic_detail": traffic} if "bound" in kern else None),
            "pruning": {"rows_bounded_mean": float(stats["rows_filtered"].mean()),
                        "candidates_mean": float(stats["candidates"].mean()),
                        "rows_refined_mean": float(stats["rows_refined"].mean()),
