@@ -260,6 +260,7 @@ def main():
     ap.add_argument("--N", type=int, default=10_000_000)
     ap.add_argument("--n", type=int, default=256)
     ap.add_argument("--per-level", type=int, default=100)
+    ap.add_argument("--levels", default="1,5,10", help="noise levels (variance, percent) of the queries")
     ap.add_argument("--k", type=int, default=10)
     ap.add_argument("--w", type=int, default=16)
     ap.add_argument("--leaf", type=int, default=10_000)
@@ -295,7 +296,7 @@ def main():
     from paper_2212_13297_amd import hs
 
     dev = torch.device("cuda:0")
-    levels = [1, 5, 10]
+    levels = [int(v) for v in args.levels.split(",")]
     log(f"generating {args.N} x {args.n} random walks")
     t0 = time.time()
     x = G.random_walks(args.N, args.n)
@@ -410,7 +411,7 @@ def main():
         cpu_s = time.perf_counter() - t0
         cpu = {"value": round(len(sel) / cpu_s, 4), "unit": "queries/s", "cores": brute.threads(),
                "kind": "oracle",
-               "sample": f"{len(sel)} of the {Q} queries (evenly spaced over the 1/5/10% levels), k={args.k}, "
+               "sample": f"{len(sel)} of the {Q} queries (evenly spaced over the {'/'.join(map(str, levels))}% levels), k={args.k}, "
                          f"FP64 brute force over all {args.N} series; {cpu_s:.1f} s"}
         g_ids = ids.cpu().numpy()[sel]
         g_d = d2.cpu().numpy()[sel].astype(np.float64)

@@ -193,8 +193,9 @@ hs_status hs_knn_exact(hs_index* idx, const float* q_dev, int32_t Q, int32_t k, 
 #define HS_SHADOW_BF16 1
 #define HS_SHADOW_FP16 2
 
-/* Device bytes of the low-precision copy of kind HS_SHADOW_*: N x row_stride
- * 16-bit values plus N x 8 bytes of norms (plus 256 bytes of scratch).
+/* Device bytes of the low-precision copy of kind HS_SHADOW_*: (N + 32) x
+ * row_stride 16-bit values and (N + 32) x 8 bytes of norms (the last 32 rows
+ * are zero padding), plus 256 bytes of scratch.
  * Errors: HS_EINVAL (NULL, unknown kind). */
 hs_status hs_shadow_bytes(const hs_index* idx, int32_t kind, int64_t* bytes);
 

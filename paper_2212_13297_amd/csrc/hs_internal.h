@@ -58,8 +58,8 @@ constexpr int kBoundQueries = 128;  // queries per workgroup of the bounding pas
 constexpr int kBoundRows = 32;      // series per tile of the bounding pass
 
 struct ShadowView {
-    const uint16_t* rows;  // [N][stride] bf16 / fp16 bits of the stored series, zero padded
-    const float2* norms;   // [N] (||x~||^2 rounded down, ||x - x~||_2 rounded up), float32
+    const uint16_t* rows;  // [N + kBoundRows][stride] bf16 / fp16 bits of the stored series, zero padded
+    const float2* norms;   // [N + kBoundRows] (||x~||^2 rounded down, ||x - x~||_2 rounded up), float32
     int32_t kind;          // kShadowBf16 / kShadowF16
 };
 

@@ -133,7 +133,7 @@ __global__ void __launch_bounds__(64) k_query_low(IndexView ix, int32_t Q, Query
 // Constants of the float32 test.
 struct BoundConsts {
     double g;   // accumulation factor g (plus 2^-40 for the float64 norms)
-    double m;   // margin factor 2u of the folded constants (u = 2^-24)
+    double m;   // margin factor 3u of the folded constants (u = 2^-24)
 };
 
 // Which q-group and row range a workgroup takes.  With enough workgroups the
@@ -172,13 +172,16 @@ __device__ __forceinline__ void bound_block(const BoundMap& m, int b, int& g0, i
 //
 // Float32 test.  With sT = sqrt(BSF_k (1 + slack)) + eps_q (rounded up), the
 // pair is dropped iff (1 - g)(||q~||^2 + ||x~||^2) - 2 acc > (sT + eps_x)^2,
-// i.e. iff acc < alpha_q + beta_x - sT eps_x with
+// i.e. iff acc - beta_x + sT eps_x < alpha_q with
 //   alpha_q = ((1 - g)||q~||^2 - sT^2) / 2,  beta_x = ((1 - g)||x~||^2 - eps_x^2) / 2.
-// alpha and beta are computed in float64, lowered by 2u (||q~||^2 + sT^2) and
-// 2u (||x~||^2 + eps_x^2) and rounded down; that margin exceeds the error of
-// the two float32 roundings of fma(-sT, eps_x, alpha + beta) (at most 1.5 u of
-// the same magnitudes), so acc < that float32 value implies the exact
-// condition.  Pairs that pass are decided in float64.
+// alpha and beta are computed in float64, lowered by 3u M_q and 3u M_x
+// (M_q = ||q~||^2 + sT^2, M_x = ||x~||^2 + eps_x^2, u = 2^-24) and rounded
+// down.  e = fma(sT, eps_x, acc - beta) carries two float32 roundings, at most
+// 2u (M_q + M_x) in all (|acc| <= (||q~||^2 + ||x~||^2) / 2 (1 + g),
+// sT eps_x <= (sT^2 + eps_x^2) / 2), below the margin; so e < alpha implies
+// the exact condition.  A lane first takes the largest e of its 16 pairs
+// (3 operations per pair); only when it reaches alpha are the pairs tested
+// one by one and decided in float64.
 template <int KIND, bool ONE>
 __global__ void __launch_bounds__(256) k_bound(IndexView ix, ShadowView sv, ScanParams sp, QueryWs ws,
                                                BoundConsts bc, BoundMap bm) {
@@ -216,7 +219,10 @@ __global__ void __launch_bounds__(256) k_bound(IndexView ix, ShadowView sv, Scan
         const int64_t p_first = lo;
 
         for (int g = g0; g < bm.G; g += bm.GS) {
-            const int qj = g * kBoundQueries + wave * 32 + j;
+            // queries are dealt to the q-groups round-robin (query g + G i in
+            // group g), so the groups of a row range carry the same load and
+            // stay close enough for the staged series to be shared in L2
+            const int qj = g + bm.G * (wave * 32 + j);
             const bool qvalid = qj < sp.Q && !(ws.flags[qj] & kFlagNonFinite);
             float alpha = -3.0e38f, sT = 0.0f, bsf_j = 0.0f;
             if (qvalid) {
@@ -229,7 +235,7 @@ __global__ void __launch_bounds__(256) k_bound(IndexView ix, ShadowView sv, Scan
                     alpha = __double2float_rd(0.5 * ((1.0 - bc.g) * qn.x - s2) - bc.m * (qn.x + s2));
                 }
             }
-            const uint16_t* qlow = ws.qlow + (int64_t)(g * kBoundQueries + wave * 32 + j) * K + 8 * half;
+            const uint16_t* qlow = ws.qlow + (int64_t)qj * K + 8 * half;
             uint4 bq[kKSteps];
             if (ONE) {
 #pragma unroll
@@ -256,18 +262,18 @@ __global__ void __launch_bounds__(256) k_bound(IndexView ix, ShadowView sv, Scan
                 uint4 pa[4];
                 float2 na = make_float2(0.f, 0.f);
                 auto stage_load = [&](int64_t s, uint4 (&pre)[4], float2& pn) {
-                    // branch-free: every address is clamped into the buffers (values
-                    // past the row are zeroed when stored, rows past the collection
-                    // are masked), so the loads stay in flight until their store
+                    // branch-free, from the tile's first row (the copy is padded by
+                    // a tile, so no row clamp); columns past K read other values of
+                    // the copy that are zeroed when stored
                     const int64_t tr0 = ps + (s / nkb) * kBoundRows;
                     const int kb = (int)(s % nkb);
+                    const uint16_t* base = sv.rows + tr0 * K;
 #pragma unroll
                     for (int i = 0; i < 4; ++i) {
-                        const int e = t + 256 * i, rr = e >> 5, cc = (e & 31) * 8 + kb * kKBlock;
-                        const int64_t row = min(tr0 + rr, ix.N - 1);
-                        pre[i] = *reinterpret_cast<const uint4*>(sv.rows + row * K + min(cc, K - 8));
+                        const int e = t + 256 * i, cc = (e & 31) * 8 + kb * kKBlock;
+                        pre[i] = *reinterpret_cast<const uint4*>(base + ((e >> 5) * K + min(cc, K - 8)));
                     }
-                    pn = sv.norms[min(tr0 + (t & (kBoundRows - 1)), ix.N - 1)];
+                    pn = sv.norms[tr0 + (t & (kBoundRows - 1))];
                 };
                 auto stage_store = [&](int64_t s, const uint4 (&pre)[4], float2 pn) {
                     uint16_t* dst = s_tile[s & 1];
@@ -322,15 +328,25 @@ __global__ void __launch_bounds__(256) k_bound(IndexView ix, ShadowView sv, Scan
                             if (keep && half == 0) tested += (unsigned long long)nrows;
                             const float2* nrm = s_norm[tile & 1];
                             const float* xnr = s_xn[tile & 1];
-                            uint32_t mask = 0;
+                            // common path: 3 operations per pair, one test per lane
+                            float mx = -INFINITY;
 #pragma unroll
                             for (int r = 0; r < 16; ++r) {
-                                const int i = 8 * (r >> 2) + 4 * half + (r & 3);
-                                const float2 nm = nrm[i];
-                                const float thr = fmaf(-sT, nm.y, alpha + nm.x);
-                                if (acc[r] >= thr && i < nrows) mask |= 1u << r;
+                                const float2 nm = nrm[8 * (r >> 2) + 4 * half + (r & 3)];
+                                mx = fmaxf(mx, fmaf(sT, nm.y, acc[r] - nm.x));
                             }
-                            if (!keep) mask = 0;
+                            const bool any = keep && mx >= alpha;
+                            uint32_t mask = 0;
+                            if (__ballot(any) != 0ull) {
+                                // the lanes' exact float32 masks (rows of this part only)
+#pragma unroll
+                                for (int r = 0; r < 16; ++r) {
+                                    const int i = 8 * (r >> 2) + 4 * half + (r & 3);
+                                    const float2 nm = nrm[i];
+                                    if (fmaf(sT, nm.y, acc[r] - nm.x) >= alpha && i < nrows) mask |= 1u << r;
+                                }
+                                if (!keep) mask = 0;
+                            }
                             if (__ballot(mask != 0u) != 0ull) {
                                 // rare: the pairs the float32 test kept are decided in
                                 // float64; the accumulators go through LDS so that the
@@ -473,7 +489,7 @@ hipError_t launch_bound(const IndexView& ix, const ShadowView& sv, const ScanPar
     const double u2 = std::ldexp(1.0, -23), Kd = (double)ix.stride;
     BoundConsts bc;
     bc.g = Kd * u2 / (1.0 - Kd * u2) + std::ldexp(1.0, -40);
-    bc.m = 2.0 * std::ldexp(1.0, -24);
+    bc.m = 3.0 * std::ldexp(1.0, -24);
     if (sv.kind == kShadowF16) {
         if (one) k_bound<kShadowF16, true><<<dim3(grid), dim3(kTile), 0, st>>>(ix, sv, sp, ws, bc, bm);
         else k_bound<kShadowF16, false><<<dim3(grid), dim3(kTile), 0, st>>>(ix, sv, sp, ws, bc, bm);

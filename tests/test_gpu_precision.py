@@ -80,8 +80,10 @@ def test_shadow_copy_against_oracle(kind):
     rows = rows.cpu().numpy()
     stride = idx.info.row_stride
     sh = idx.shadow.cpu().numpy()
+    pad = 32  # zero rows after the copy
     low_bits = sh[:N * stride * 2].view(np.uint16).reshape(N, stride)
-    norms = sh[(N * stride * 2 + 255) // 256 * 256:][:N * 8].view(np.float32).reshape(N, 2)
+    assert not np.any(sh[N * stride * 2:(N + pad) * stride * 2])
+    norms = sh[((N + pad) * stride * 2 + 255) // 256 * 256:][:N * 8].view(np.float32).reshape(N, 2)
     if kind == P.BF16:
         low = (low_bits.astype(np.uint32) << 16).view(np.float32)
     else:
