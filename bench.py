@@ -173,7 +173,8 @@ def run_serving(args, hs, torch, G, idx256, x256):
         idxs.append(ic)
         log(f"serving collection {c}: {N} x {n} built in {time.time() - t0:.1f}s")
     budget = int(args.serve_budget_gb * (1 << 30))
-    srv = hs.Server(idxs, [0, 0, 0], budget_bytes=budget, streams_per_coll=2, max_slots=8192, max_batch=256)
+    srv = hs.Server(idxs, [0, 0, 0], budget_bytes=budget, streams_per_coll=args.serve_streams, max_slots=8192,
+                    max_batch=256)
 
     rng = np.random.default_rng(G.SEED_ARRIVAL)
     total_s = args.serve_warmup + args.serve_seconds
@@ -279,6 +280,7 @@ def main():
     ap.add_argument("--serve-scale", type=float, default=1.0,
                     help="fraction of the serving collections' sizes (1.0 = 20M x 128, 10M x 256, 2M x 1024)")
     ap.add_argument("--serve-budget-gb", type=float, default=48.0, help="device budget of the server (GB)")
+    ap.add_argument("--serve-streams", type=int, default=3, help="server streams per collection")
     ap.add_argument("--profile-run", action="store_true",
                     help="only the warmup and timed k-NN steps (no k=1 pass, latency or CPU oracle), so a "
                          "profiler's per-kernel averages cover exactly the launches timed here; also copies "
@@ -290,6 +292,11 @@ def main():
         print("bench.py measures one GPU only: this build has no multi-GPU path "
               "(the leaf-sharded design is described in DESIGN.md); run with --gpus 1.", file=sys.stderr)
         sys.exit(2)
+
+    if "serving" in args.forms.split(","):
+        # the server runs streams_per_coll streams per collection; give each its
+        # own hardware queue (set before the HIP runtime starts)
+        os.environ.setdefault("GPU_MAX_HW_QUEUES", str(min(16, 3 * args.serve_streams + 1)))
 
     import torch
     from paper_2212_13297_amd import datagen as G

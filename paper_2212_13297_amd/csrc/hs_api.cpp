@@ -248,12 +248,13 @@ int64_t ws_layout(const hs_index* idx, int32_t Q, int32_t k, QueryWs* ws, char* 
     const int P = kPoolMin;
     const int64_t items = (int64_t)Q * ix.parts + 1;
     // candidate list: up to 1/8 of the collection per query on average,
-    // between 64 Ki and 512 Mi entries; a query whose candidates do not fit
-    // is answered by the fused scan instead (no result changes)
+    // between 64 Ki and 2 Gi entries (24 GB with the slices' 12 bytes each; the
+    // 32-bit slice prefix stays below 2^32); a query whose candidates do not
+    // fit is answered by the fused scan instead (no result changes)
     const int64_t cpq = idx->p.cand_per_query;
     const int64_t per_q = cpq > 0 ? cpq : std::max<int64_t>((ix.N + 7) / 8, 4096);
     const int64_t floor_c = cpq > 0 ? 1 : (1 << 16);
-    const int64_t cand_total = std::min<int64_t>(std::max<int64_t>((int64_t)Q * per_q, floor_c), (int64_t)1 << 29);
+    const int64_t cand_total = std::min<int64_t>(std::max<int64_t>((int64_t)Q * per_q, floor_c), (int64_t)1 << 31);
     // 3/4 in the filter wavefronts' private slices, 1/4 in a shared overflow slice
     const int n_slices = idx->filter_waves;
     const int64_t slice_cap = (cand_total * 3 / 4 + n_slices - 1) / n_slices;
