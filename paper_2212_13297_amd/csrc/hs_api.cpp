@@ -330,11 +330,14 @@ hs_status hs_build_summaries(const float* x_dev, int64_t N, const hs_params* par
     hipStream_t st = (hipStream_t)stream;
     const hs_params p = *params;
 
+    int device = 0, cus = 0;
+    HIP_TRY(hipGetDevice(&device));
+    HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device));
     hs_index* idx = new (std::nothrow) hs_index();
     if (!idx) return fail(HS_ENOMEM, "host allocation failed");
     idx->p = p;
-    HIP_TRY(hipGetDevice(&idx->device));
-    HIP_TRY(hipDeviceGetAttribute(&idx->cus, hipDeviceAttributeMultiprocessorCount, idx->device));
+    idx->device = device;
+    idx->cus = cus;
 
     IndexView& ix = idx->view;
     ix.N = N;

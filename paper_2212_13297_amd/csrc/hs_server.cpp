@@ -160,13 +160,16 @@ hs_status launch_batch(hs_server* s, StreamSlot& sl) {
 }
 
 // The slot's graph has completed: overflow rounds, then completions.
-void finish_batch(hs_server* s, StreamSlot& sl) {
+// failed: the batch could not be launched (its requests complete with that status).
+void finish_batch(hs_server* s, StreamSlot& sl, hs_status failed = HS_OK) {
     const SchedBatch& b = sl.batch;
     const int k_run = sl.k_run;
     const int qp = b.q_pad;
-    hs_status status = HS_OK;
+    hs_status status = failed;
     std::string msg;
-    if (sl.redo_host[1]) {
+    if (failed) {
+        msg = "batch launch failed";
+    } else if (sl.redo_host[1]) {
         status = HS_EINVAL;
         msg = "non-finite query in a batch";
     } else if (sl.redo_host[0]) {
@@ -229,7 +232,7 @@ void dispatcher(hs_server* s) {
             } else {
                 record_error(s, std::string("dispatcher: ") + hipGetErrorString(e));
                 (void)hipStreamSynchronize(sl.st);
-                finish_batch(s, sl);
+                finish_batch(s, sl, HS_EHIP);
             }
         }
         if (s->stop.load() && !inflight) {
@@ -270,10 +273,7 @@ void dispatcher(hs_server* s) {
                             sl.d2_host[i] = INFINITY;
                         }
                         sl.k_run = std::max(1, sl.batch.k_batch);
-                        finish_batch(s, sl);
-                        std::lock_guard<std::mutex> g(s->mu);
-                        for (size_t i = s->done.size() - sl.batch.reqs.size(); i < s->done.size(); ++i)
-                            s->done[i].status = st;
+                        finish_batch(s, sl, st);
                     }
                     progress = true;
                 }
