@@ -93,32 +93,31 @@ __global__ void __launch_bounds__(256) k_lb_eapca(IndexView ix, QueryWs ws) {
 // series of the L_max most promising leaves; here the same leaves are chosen
 // (smallest LB_EAPCA) but only their series with the smallest LB_SAX are
 // refined -- at least max(seed_rows, 2k) of them, cut at a histogram bin of
-// LB_SAX values.  The k best become the first pool entries and BSF_k.
+// LB_SAX values, at most kSeedList.  The selected series are gathered into a
+// list, refined together (16 lanes per series; no abandoning, the block has no
+// BSF_k yet), and the k best by (d, id), found by a bitonic sort of the list's
+// keys, become the first pool entries and BSF_k.
+constexpr int kSeedList = 2048;
+
 template <int W16, int F>
 __global__ void __launch_bounds__(256) k_seed(IndexView ix, ScanParams sp, QueryWs ws) {
     extern __shared__ float s_lut[];  // [w][256]
-    __shared__ unsigned long long s_top[HS_KMAX];
-    __shared__ unsigned long long s_res[kTile];
-    __shared__ uint32_t s_hits[kTile];
     __shared__ uint32_t s_hist[2048];
+    __shared__ unsigned long long s_keys[kSeedList];
+    __shared__ uint32_t s_list[kSeedList];
     __shared__ uint32_t s_leaves[kMaxSeedLeaves];
     __shared__ unsigned long long s_tmp[4];
     __shared__ int s_w[4];
-    __shared__ int s_nres, s_topn;
-    __shared__ float s_thr;
     __shared__ uint32_t s_binlim;
-    __shared__ unsigned int s_ref, s_chunks;
+    __shared__ int s_cnt;
     const int q = blockIdx.x, t = threadIdx.x, sub = t & 15, grp = t >> 4;
     const int k = sp.k, lm = sp.n_seed;
     const int nchunks = ix.stride / kChunk;
     for (int j = t; j < ix.w * kCard; j += blockDim.x) s_lut[j] = ws.lut[(int64_t)q * ix.w * kCard + j];
     for (int j = t; j < 2048; j += blockDim.x) s_hist[j] = 0;
     if (t == 0) {
-        s_nres = 0;
-        s_topn = 0;
-        s_thr = INFINITY;
-        s_ref = 0;
-        s_chunks = 0;
+        s_cnt = 0;
+        s_binlim = 2047;
     }
     // the lm leaves with the smallest (LB_EAPCA, leaf id)
     unsigned long long last = 0;
@@ -146,74 +145,95 @@ __global__ void __launch_bounds__(256) k_seed(IndexView ix, ScanParams sp, Query
         }
     }
     __syncthreads();
-    if (t == 0) {
+    // the cut: the first bin at which the cumulative count reaches the target
+    // (thread t owns bins 8t .. 8t + 7)
+    {
         const uint32_t want = (uint32_t)max(sp.seed_rows, 2 * k);
-        uint32_t cum = 0, lim = 2047;
-        for (uint32_t b = 0; b < 2048; ++b) {
-            cum += s_hist[b];
-            if (cum >= want) {
-                lim = b;
-                break;
-            }
+        int c8 = 0;
+#pragma unroll
+        for (int b = 0; b < 8; ++b) c8 += (int)s_hist[8 * t + b];
+        int tot;
+        uint32_t cum = (uint32_t)block_exclusive_scan(c8, s_w, &tot);
+        for (int b = 0; b < 8; ++b) {
+            const uint32_t before = cum;
+            cum += s_hist[8 * t + b];
+            if (before < want && cum >= want) s_binlim = 8 * t + b;  // one thread finds the crossing
         }
-        s_binlim = lim;
     }
     __syncthreads();
     const uint32_t lim = s_binlim;
-    unsigned my_chunks = 0, my_ref = 0;
+    // gather the series whose LB_SAX bin does not exceed the cut (8 per thread
+    // per pass, one block scan per pass)
     for (int li = 0; li < lm; ++li) {
         const int64_t b = ix.leaf_start[s_leaves[li]], e = ix.leaf_start[s_leaves[li] + 1];
-        for (int64_t tb = b; tb < e; tb += kTile) {
-            const int64_t r = tb + t;
-            bool pass = false;
-            if (r < e) {
-                uint4 v[W16];
-                load_word<W16>(ix.words + r * ix.wstride, v);
-                const float lb = lb_sax_word<W16>(v, s_lut, ix.w);
-                pass = (__float_as_uint(lb) >> 20) <= lim && (double)lb <= prune_limit(s_thr);
+        for (int64_t tb = b; tb < e; tb += 8 * (int64_t)blockDim.x) {
+            uint32_t pm = 0;
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                const int64_t r = tb + t + (int64_t)blockDim.x * j;
+                if (r < e) {
+                    uint4 v[W16];
+                    load_word<W16>(ix.words + r * ix.wstride, v);
+                    const float lb = lb_sax_word<W16>(v, s_lut, ix.w);
+                    if ((__float_as_uint(lb) >> 20) <= lim) pm |= 1u << j;
+                }
             }
-            int nh;
-            const int off = block_exclusive_scan(pass ? 1 : 0, s_w, &nh);
-            if (pass) s_hits[off] = (uint32_t)(r - b);
-            __syncthreads();
-            const float thr = s_thr;
-            for (int h = grp; h < nh; h += kTile / 16) {
-                const int64_t pos = b + s_hits[h];
-                bool alive;
-                const float d = refine_row<F>(ix.rows + pos * ix.stride + sub * 4,
-                                           ws.qrow + (int64_t)q * ix.stride + sub * 4, nchunks, thr, alive,
-                                           my_chunks);
-                if (sub == 0) {
-                    ++my_ref;
-                    if (alive)
-                        s_res[atomicAdd(&s_nres, 1)] = ((unsigned long long)__float_as_uint(d) << 32) | ix.ids[pos];
+            int tot;
+            const int off = block_exclusive_scan(__popc(pm), s_w, &tot);
+            const int base = s_cnt;
+            int o = base + off;
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                if ((pm >> j) & 1u) {
+                    if (o < kSeedList) s_list[o] = (uint32_t)(tb + t + (int64_t)blockDim.x * j);
+                    ++o;
                 }
             }
             __syncthreads();
-            if (t == 0) {
-                int n = s_topn;
-                for (int i = 0; i < s_nres; ++i) topk_insert(s_top, n, k, s_res[i]);
-                s_topn = n;
-                s_nres = 0;
-                if (n == k) s_thr = bits_to_float((uint32_t)(s_top[k - 1] >> 32));
+            if (t == 0) s_cnt = min(base + tot, kSeedList);
+            __syncthreads();
+        }
+    }
+    const int M = s_cnt;
+    // refine the list
+    for (int i = grp; i < M; i += kTile / 16) {
+        const int64_t pos = s_list[i];
+        bool alive;
+        unsigned ch = 0;
+        const float d = refine_row<F>(ix.rows + pos * ix.stride + sub * 4, ws.qrow + (int64_t)q * ix.stride + sub * 4,
+                                      nchunks, INFINITY, alive, ch);
+        if (sub == 0) s_keys[i] = ((unsigned long long)__float_as_uint(d) << 32) | ix.ids[pos];
+    }
+    int Mp = 1;
+    while (Mp < M) Mp <<= 1;
+    for (int i = M + t; i < Mp; i += blockDim.x) s_keys[i] = ~0ull;
+    __syncthreads();
+    // bitonic sort of the keys, ascending
+    for (int size = 2; size <= Mp; size <<= 1) {
+        for (int stride = size >> 1; stride > 0; stride >>= 1) {
+            for (int i = t; i < Mp; i += blockDim.x) {
+                const int j2 = i ^ stride;
+                if (j2 > i) {
+                    const bool up = (i & size) == 0;
+                    const unsigned long long a = s_keys[i], c = s_keys[j2];
+                    if ((a > c) == up) {
+                        s_keys[i] = c;
+                        s_keys[j2] = a;
+                    }
+                }
             }
             __syncthreads();
         }
     }
-    if (sub == 0) {
-        atomicAdd(&s_ref, my_ref);
-        atomicAdd(&s_chunks, my_chunks);
-    }
-    __syncthreads();
-    const int n = s_topn;
-    for (int j = t; j < n; j += blockDim.x) ws.pool[(int64_t)q * ws.P + j] = s_top[j];
+    const int n = min(k, M);
+    for (int j = t; j < n; j += blockDim.x) ws.pool[(int64_t)q * ws.P + j] = s_keys[j];
     if (t == 0) {
         ws.pool_cnt[q] = (uint32_t)n;
-        if (n == k) ws.bsf[q] = (uint32_t)(s_top[k - 1] >> 32);
+        if (n == k) ws.bsf[q] = (uint32_t)(s_keys[k - 1] >> 32);
         unsigned long long* st = ws.stats + (int64_t)q * 8;
         st[1] += (unsigned long long)rows;
-        st[2] += s_ref;
-        st[3] += s_chunks;
+        st[2] += (unsigned long long)M;
+        st[3] += (unsigned long long)M * nchunks;
     }
 }
 
