@@ -33,11 +33,25 @@ __device__ __forceinline__ uint32_t load_relaxed(const uint32_t* p) {
 // A bound prunes only when it exceeds BSF_k by the relative slack.
 __device__ __forceinline__ double prune_limit(float bsf) { return (double)bsf * (1.0 + kSlack); }
 
+// The LB_SAX table in LDS has 16 W16 segment rows: the query's w rows, then
+// zero rows for the padding segments (whose stored symbols are 0), so the
+// lookups below need no test on w.
+template <int W16>
+constexpr int lut_floats() {
+    return 16 * W16 * kCard;
+}
+
+template <int W16>
+__device__ __forceinline__ void load_lut(float* s_lut, const float* __restrict__ src, int w, int t, int nt) {
+    for (int j = t; j < lut_floats<W16>(); j += nt) s_lut[j] = j < w * kCard ? src[j] : 0.0f;
+}
+
 // LB_SAX of one stored series: sum over segments of the query's table entry
 // for the series' symbol (words are 16-byte aligned, W16 uint4 per word).
+// Branch-free, four partial sums, so the table loads issue together.
 template <int W16>
-__device__ __forceinline__ float lb_sax_word(const uint4 (&v)[W16], const float* s_lut, int w) {
-    float acc = 0.0f;
+__device__ __forceinline__ float lb_sax_word(const uint4 (&v)[W16], const float* s_lut) {
+    float acc[4] = {0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
     for (int u = 0; u < W16; ++u) {
         const uint32_t parts[4] = {v[u].x, v[u].y, v[u].z, v[u].w};
@@ -46,11 +60,11 @@ __device__ __forceinline__ float lb_sax_word(const uint4 (&v)[W16], const float*
 #pragma unroll
             for (int b = 0; b < 4; ++b) {
                 const int i = u * 16 + p * 4 + b;
-                if (i < w) acc += s_lut[i * kCard + ((parts[p] >> (8 * b)) & 0xffu)];
+                acc[b] += s_lut[i * kCard + ((parts[p] >> (8 * b)) & 0xffu)];
             }
         }
     }
-    return acc;
+    return (acc[0] + acc[1]) + (acc[2] + acc[3]);
 }
 
 template <int W16>

@@ -50,7 +50,7 @@ __device__ __forceinline__ void load_cenv(const IndexView& ix, int64_t c0, int n
 // LB_SAX of its series.
 template <int W16>
 __global__ void __launch_bounds__(256) k_filter(IndexView ix, ScanParams sp, QueryWs ws) {
-    extern __shared__ float s_lut[];  // [w][256]
+    extern __shared__ float s_lut[];  // [16 W16][256], rows beyond w zero
     __shared__ float4 s_qst[64];      // query segment mean / std intervals
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
     const float lseg = (float)(ix.n / ix.w);
@@ -79,7 +79,7 @@ __global__ void __launch_bounds__(256) k_filter(IndexView ix, ScanParams sp, Que
             }
             a_filt = a_cand = a_tests = 0;
             __syncthreads();  // no wave still reads the previous table
-            for (int j = t; j < ix.w * kCard; j += blockDim.x) s_lut[j] = ws.lut[(int64_t)q * ix.w * kCard + j];
+            load_lut<W16>(s_lut, ws.lut + (int64_t)q * ix.w * kCard, ix.w, t, blockDim.x);
             if (t < ix.w) s_qst[t] = ws.qst32[(int64_t)q * ix.w + t];
             cur_q = q;
             __syncthreads();
@@ -144,7 +144,7 @@ __global__ void __launch_bounds__(256) k_filter(IndexView ix, ScanParams sp, Que
                 if ((live >> s) & 1u) {
                     if (r0 < pe) evaluated += (unsigned)min((int64_t)kChunkRows, pe - r0);
                     if (r < pe) {
-                        if (!skip) lbv[s] = lb_sax_word<W16>(v[s], s_lut, ix.w);
+                        if (!skip) lbv[s] = lb_sax_word<W16>(v[s], s_lut);
                         if ((double)lbv[s] <= thr) mask |= 1u << s;
                     }
                 }
@@ -246,7 +246,7 @@ __global__ void __launch_bounds__(1024) k_slice_prefix(QueryWs ws) {
 
 template <int W16>
 int filter_blocks(const IndexView& ix, int cus) {
-    return resident_grid(k_filter<W16>, kTile, sizeof(float) * (size_t)ix.w * kCard, cus);
+    return resident_grid(k_filter<W16>, kTile, sizeof(float) * (size_t)lut_floats<W16>(), cus);
 }
 
 }  // namespace
@@ -264,7 +264,7 @@ int filter_waves(const IndexView& ix, int device_cus) {
 
 hipError_t launch_filter(const IndexView& ix, const ScanParams& sp, const QueryWs& ws, int device_cus,
                          hipStream_t st) {
-    const size_t lds = sizeof(float) * (size_t)ix.w * kCard;
+    const size_t lds = sizeof(float) * (size_t)16 * w16_of(ix) * kCard;
     const dim3 grid(ws.n_slices / kWaves);  // one slice per wavefront
     HS_DISPATCH_W16(ix, k_filter, grid, dim3(kTile), lds, st, ix, sp, ws);
     return hipGetLastError();

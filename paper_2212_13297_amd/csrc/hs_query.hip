@@ -101,7 +101,7 @@ constexpr int kSeedList = 2048;
 
 template <int W16, int F>
 __global__ void __launch_bounds__(256) k_seed(IndexView ix, ScanParams sp, QueryWs ws) {
-    extern __shared__ float s_lut[];  // [w][256]
+    extern __shared__ float s_lut[];  // [16 W16][256], rows beyond w zero
     __shared__ uint32_t s_hist[2048];
     __shared__ unsigned long long s_keys[kSeedList];
     __shared__ uint32_t s_list[kSeedList];
@@ -113,7 +113,7 @@ __global__ void __launch_bounds__(256) k_seed(IndexView ix, ScanParams sp, Query
     const int q = blockIdx.x, t = threadIdx.x, sub = t & 15, grp = t >> 4;
     const int k = sp.k, lm = sp.n_seed;
     const int nchunks = ix.stride / kChunk;
-    for (int j = t; j < ix.w * kCard; j += blockDim.x) s_lut[j] = ws.lut[(int64_t)q * ix.w * kCard + j];
+    load_lut<W16>(s_lut, ws.lut + (int64_t)q * ix.w * kCard, ix.w, t, blockDim.x);
     for (int j = t; j < 2048; j += blockDim.x) s_hist[j] = 0;
     if (t == 0) {
         s_cnt = 0;
@@ -140,7 +140,7 @@ __global__ void __launch_bounds__(256) k_seed(IndexView ix, ScanParams sp, Query
         for (int64_t r = b + t; r < e; r += blockDim.x) {
             uint4 v[W16];
             load_word<W16>(ix.words + r * ix.wstride, v);
-            const float lb = lb_sax_word<W16>(v, s_lut, ix.w);
+            const float lb = lb_sax_word<W16>(v, s_lut);
             atomicAdd(&s_hist[min(__float_as_uint(lb) >> 20, 2047u)], 1u);
         }
     }
@@ -174,7 +174,7 @@ __global__ void __launch_bounds__(256) k_seed(IndexView ix, ScanParams sp, Query
                 if (r < e) {
                     uint4 v[W16];
                     load_word<W16>(ix.words + r * ix.wstride, v);
-                    const float lb = lb_sax_word<W16>(v, s_lut, ix.w);
+                    const float lb = lb_sax_word<W16>(v, s_lut);
                     if ((__float_as_uint(lb) >> 20) <= lim) pm |= 1u << j;
                 }
             }
@@ -398,7 +398,7 @@ hipError_t launch_lb_eapca(const IndexView& ix, int32_t Q, const QueryWs& ws, hi
 
 hipError_t launch_seed(const IndexView& ix, const ScanParams& sp, const QueryWs& ws, int form, hipStream_t st) {
     if (sp.n_seed <= 0) return hipSuccess;
-    const size_t lds = sizeof(float) * (size_t)ix.w * kCard;
+    const size_t lds = sizeof(float) * (size_t)16 * w16_of(ix) * kCard;
     if (form == kComp) {
         HS_DISPATCH_W16_F(ix, k_seed, kComp, dim3(sp.Q), dim3(kTile), lds, st, ix, sp, ws);
     } else {

@@ -23,7 +23,7 @@ __global__ void __launch_bounds__(256) k_leaf_scan(IndexView ix, ScanParams sp, 
     extern __shared__ float s_dyn[];
     __shared__ ScanShared sh;
     float* s_q = s_dyn;                // [stride]
-    float* s_lut = s_dyn + ix.stride;  // [w][256]
+    float* s_lut = s_dyn + ix.stride;  // [16 W16][256]
     const int t = threadIdx.x;
     const int grp = t >> 4, sub = t & 15;
     const int nchunks = ix.stride / kChunk;
@@ -38,7 +38,7 @@ __global__ void __launch_bounds__(256) k_leaf_scan(IndexView ix, ScanParams sp, 
         const int64_t part = (int64_t)(uint32_t)item;
         if (q != cur_q) {
             for (int j = t; j < ix.stride; j += blockDim.x) s_q[j] = ws.qrow[(int64_t)q * ix.stride + j];
-            for (int j = t; j < ix.w * kCard; j += blockDim.x) s_lut[j] = ws.lut[(int64_t)q * ix.w * kCard + j];
+            load_lut<W16>(s_lut, ws.lut + (int64_t)q * ix.w * kCard, ix.w, t, blockDim.x);
             cur_q = q;
         }
         if (t == 0) {
@@ -64,7 +64,7 @@ __global__ void __launch_bounds__(256) k_leaf_scan(IndexView ix, ScanParams sp, 
                 } else {
                     uint4 v[W16];
                     load_word<W16>(ix.words + r * ix.wstride, v);
-                    const float lb = lb_sax_word<W16>(v, s_lut, ix.w);
+                    const float lb = lb_sax_word<W16>(v, s_lut);
                     ++my_filt;
                     pass = (double)lb <= prune_limit(thr);
                 }
@@ -119,7 +119,7 @@ __global__ void __launch_bounds__(256) k_leaf_scan(IndexView ix, ScanParams sp, 
 
 hipError_t launch_leaf_scan(const IndexView& ix, const ScanParams& sp, const QueryWs& ws, int device_cus, int form,
                             hipStream_t st) {
-    const size_t lds = sizeof(float) * ((size_t)ix.stride + (size_t)ix.w * kCard);
+    const size_t lds = sizeof(float) * ((size_t)ix.stride + (size_t)16 * w16_of(ix) * kCard);
     if (form == kComp) {
         HS_LAUNCH_RESIDENT_F(ix, k_leaf_scan, kComp, lds, device_cus, st, ix, sp, ws);
     } else {
