@@ -283,6 +283,8 @@ int64_t ws_layout(const hs_index* idx, int32_t Q, int32_t k, QueryWs* ws, char* 
     const int32_t Qpad = (Q + kBoundQueries - 1) / kBoundQueries * kBoundQueries;
     carve(cur, (void**)&w.qlow, (int64_t)Qpad * ix.stride * 2);
     carve(cur, (void**)&w.qnorm, (int64_t)Q * 16);
+    carve(cur, (void**)&w.best_leaf, (int64_t)Qpad * 4);
+    carve(cur, (void**)&w.qorder, (int64_t)Qpad * 4);
     w.Qpad = Qpad;
     w.item_cap = items;
     w.slice_cap = slice_cap;
@@ -585,6 +587,7 @@ hs_status knn_enqueue(const KnnCall& c, const float* q_dev, int64_t* ids_dev, fl
     // matrix-core bound of the precision form); step 4: refinement
     HIP_TRY(launch_emit(ix, sp, false, ws, st));
     if (c.mixed) {
+        HIP_TRY(launch_query_order(sp.Q, ws, st));
         HIP_TRY(timed(HS_PROF_BOUND, [&] { return launch_bound(ix, c.idx->shadow, sp, ws, c.idx->cus, st); }));
     } else {
         HIP_TRY(timed(HS_PROF_FILTER, [&] { return launch_filter(ix, sp, ws, c.idx->cus, st); }));

@@ -106,6 +106,8 @@ struct QueryWs {
     // precision form
     uint16_t* qlow;       // [Qpad][stride] low-precision queries (zero rows beyond Q)
     double2* qnorm;       // [Q] (||q~||^2, ||q - q~||_2 rounded up)
+    uint32_t* best_leaf;  // [Qpad] the query's smallest-LB_EAPCA leaf (written by the seed)
+    int32_t* qorder;      // [Qpad] queries in bounding-pass order (-1 beyond Q)
     int32_t Qpad;         // Q rounded up to kBoundQueries
     int64_t item_cap;
     int64_t slice_cap;    // entries per slice
@@ -155,8 +157,9 @@ hipError_t launch_merge(const IndexView& ix, const ScanParams& sp, bool redo_onl
 hipError_t launch_shadow(const IndexView& ix, int kind, uint16_t* rows, float2* norms, uint32_t* bad_flag,
                          hipStream_t st);
 hipError_t launch_query_low(const IndexView& ix, int kind, int32_t Q, const QueryWs& ws, hipStream_t st);
-// grid of the bounding pass: at most `max_waves` wavefronts (one candidate slice each)
-int bound_grid(int32_t Q, int max_waves);
+// order the queries by their best leaf (queries of one wavefront then keep
+// similar leaves, so the bounding pass skips more)
+hipError_t launch_query_order(int32_t Q, const QueryWs& ws, hipStream_t st);
 hipError_t launch_bound(const IndexView& ix, const ShadowView& sv, const ScanParams& sp, const QueryWs& ws,
                         int device_cus, hipStream_t st);
 

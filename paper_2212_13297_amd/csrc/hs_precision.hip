@@ -130,6 +130,44 @@ __global__ void __launch_bounds__(64) k_query_low(IndexView ix, int32_t Q, Query
     if (lane == 0) ws.qnorm[q] = make_double2(s2 * (1.0 - 0x1p-40), sqrt(e2) * (1.0 + 0x1p-40));
 }
 
+// Queries in the bounding pass's order: by their smallest-LB_EAPCA leaf (leaf
+// numbers follow the split tree, so neighbouring leaves hold similar series),
+// then by query.  Queries of one wavefront then keep similar leaves, and a
+// wavefront skips a part only when none of its queries keeps the leaf.  One
+// workgroup, bitonic sort in LDS (Q <= kOrderMax; beyond that, query order).
+constexpr int kOrderMax = 4096;
+
+__global__ void __launch_bounds__(1024) k_query_order(int32_t Q, QueryWs ws) {
+    __shared__ unsigned long long s_key[kOrderMax];
+    const int t = threadIdx.x;
+    if (Q > kOrderMax) {
+        for (int i = t; i < ws.Qpad; i += blockDim.x) ws.qorder[i] = i < Q ? i : -1;
+        return;
+    }
+    int P = 1;
+    while (P < Q) P <<= 1;
+    for (int i = t; i < P; i += blockDim.x)
+        s_key[i] = i < Q ? (((unsigned long long)ws.best_leaf[i] << 32) | (unsigned)i) : ~0ull;
+    __syncthreads();
+    for (int size = 2; size <= P; size <<= 1) {
+        for (int stride = size >> 1; stride > 0; stride >>= 1) {
+            for (int i = t; i < P; i += blockDim.x) {
+                const int j2 = i ^ stride;
+                if (j2 > i) {
+                    const bool up = (i & size) == 0;
+                    const unsigned long long a = s_key[i], c = s_key[j2];
+                    if ((a > c) == up) {
+                        s_key[i] = c;
+                        s_key[j2] = a;
+                    }
+                }
+            }
+            __syncthreads();
+        }
+    }
+    for (int i = t; i < ws.Qpad; i += blockDim.x) ws.qorder[i] = i < Q ? (int)(s_key[i] & 0xffffffffu) : -1;
+}
+
 // Constants of the float32 test.
 struct BoundConsts {
     double g;   // accumulation factor g (plus 2^-40 for the float64 norms)
@@ -219,11 +257,13 @@ __global__ void __launch_bounds__(256) k_bound(IndexView ix, ShadowView sv, Scan
         const int64_t p_first = lo;
 
         for (int g = g0; g < bm.G; g += bm.GS) {
-            // queries are dealt to the q-groups round-robin (query g + G i in
-            // group g), so the groups of a row range carry the same load and
-            // stay close enough for the staged series to be shared in L2
-            const int qj = g + bm.G * (wave * 32 + j);
-            const bool qvalid = qj < sp.Q && !(ws.flags[qj] & kFlagNonFinite);
+            // q-group g takes positions g 128 .. g 128 + 127 of the query order
+            // (queries sorted by their best leaf), so the queries of one
+            // wavefront tend to keep the same leaves and skip the same parts
+            const int pos = g * kBoundQueries + wave * 32 + j;
+            const int qo = ws.qorder[pos];
+            const bool qvalid = qo >= 0 && !(ws.flags[qo] & kFlagNonFinite);
+            const int qj = qo >= 0 ? qo : pos;  // padded positions read a zero row of the query copy
             float alpha = -3.0e38f, sT = 0.0f, bsf_j = 0.0f;
             if (qvalid) {
                 const double2 qn = ws.qnorm[qj];
@@ -457,6 +497,11 @@ hipError_t launch_query_low(const IndexView& ix, int kind, int32_t Q, const Quer
         k_query_low<kShadowF16><<<dim3(ws.Qpad), dim3(64), 0, st>>>(ix, Q, ws);
     else
         k_query_low<kShadowBf16><<<dim3(ws.Qpad), dim3(64), 0, st>>>(ix, Q, ws);
+    return hipGetLastError();
+}
+
+hipError_t launch_query_order(int32_t Q, const QueryWs& ws, hipStream_t st) {
+    k_query_order<<<dim3(1), dim3(1024), 0, st>>>(Q, ws);
     return hipGetLastError();
 }
 
