@@ -51,7 +51,7 @@ __device__ __forceinline__ void load_lut(float* s_lut, const float* __restrict__
 // Branch-free, four partial sums, so the table loads issue together.
 template <int W16>
 __device__ __forceinline__ float lb_sax_word(const uint4 (&v)[W16], const float* s_lut) {
-    float acc[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+    float acc[4];
 #pragma unroll
     for (int u = 0; u < W16; ++u) {
         const uint32_t parts[4] = {v[u].x, v[u].y, v[u].z, v[u].w};
@@ -60,11 +60,29 @@ __device__ __forceinline__ float lb_sax_word(const uint4 (&v)[W16], const float*
 #pragma unroll
             for (int b = 0; b < 4; ++b) {
                 const int i = u * 16 + p * 4 + b;
-                acc[b] += s_lut[i * kCard + ((parts[p] >> (8 * b)) & 0xffu)];
+                const float e = s_lut[i * kCard + ((parts[p] >> (8 * b)) & 0xffu)];
+                acc[b] = i < 4 ? e : acc[b] + e;  // table entries are >= 0
             }
         }
     }
     return (acc[0] + acc[1]) + (acc[2] + acc[3]);
+}
+
+// Raw buffer loads.  A load whose offset lies past the resource's byte size
+// returns zeros and reads no memory, so a masked-out load is an ordinary
+// instruction with no traffic: loads need no branch around them, every load
+// is issued, and the waits before their uses get fixed counts.
+typedef unsigned int u32x4_t __attribute__((ext_vector_type(4)));
+constexpr uint32_t kNoLoad = 0x80000000u;   // past every resource this library builds (sizes < 2^31)
+constexpr int kBufferWord3 = 0x00020000;    // resource word 3 for CDNA raw buffers (32-bit data format)
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t buffer_rsrc(const void* base, uint32_t bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, (int)bytes, kBufferWord3);
+}
+
+__device__ __forceinline__ uint4 buffer_load16(__amdgpu_buffer_rsrc_t r, uint32_t off) {
+    const u32x4_t v = __builtin_amdgcn_raw_buffer_load_b128(r, (int)off, 0, 0);
+    return make_uint4(v.x, v.y, v.z, v.w);
 }
 
 template <int W16>

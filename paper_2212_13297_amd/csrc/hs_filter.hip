@@ -3,211 +3,263 @@
 // the refine kernel.
 //
 // Every wavefront appends to a private slice of the candidate buffer with a
-// counter in a register (no atomics), and wavefronts never wait for each
-// other except when their workgroup switches to another query's LB_SAX table
-// (items are ordered by query and each workgroup takes a contiguous range).
-// After the filter, slice_prefix computes where each slice starts in the
-// candidate list, the slices' concatenation, which the refine kernel reads
-// in place.
+// counter in a register (no atomics).  Items are ordered by query and each
+// workgroup takes a contiguous range, staged in LDS a window at a time (a
+// window holds items of one query); the workgroup's wavefronts wait for each
+// other only between windows.  After the filter, slice_prefix computes where
+// each slice starts in the candidate list, the slices' concatenation, which
+// the refine kernel reads in place.
 #include "hs_device.h"
 
 namespace hs {
 namespace {
 
-constexpr int kWaves = kTile / 64;                 // wavefronts per workgroup
-constexpr int kSlots = 8;                          // chunks per wavefront per round
-constexpr int kRoundSpan = kSlots * kWaves;        // chunks per round (2048 series)
+constexpr int kWaves = kTile / 64;  // wavefronts per workgroup
+constexpr int kWin = 256;           // items per window
+constexpr int kBatch = 8;           // chunks whose words one wavefront loads together
+constexpr int kQueue = 128;         // live-chunk queue per wavefront (power of two)
 
 __device__ __forceinline__ int64_t item_count(const QueryWs& ws) {
     return min((int64_t)ws.counters[kCtrItems], ws.item_cap);
 }
 
-// Envelope passes per round: a pass tests 64 / L chunks (L = pow2 >= w lanes each).
-template <int W16>
-constexpr int max_passes() {
-    return W16 == 1 ? 2 : (W16 == 2 ? 4 : 8);
-}
+// Per-wavefront output and counters.
+struct FilterOut {
+    uint32_t* spos;
+    uint32_t* sq;
+    float* slb;
+    uint32_t cnt;  // entries in this wavefront's slice (uniform)
+    unsigned long long filt, cand, tests;
+    bool lost;
+};
 
-// Load the chunk envelopes a wave tests in round rb (one float4 per lane and pass).
+// LB_SAX of up to kBatch queued chunks (rows [r0, r1) each, r1 - r0 <= 64)
+// and the wavefront's survivors.  Lane l takes series r0 + l of every chunk;
+// the word loads of all chunks are issued before the first table lookup, and
+// rows past a chunk (or slots past the batch) load zeros from no memory.
+// skip: the skip-sequential path, where every series is a candidate with
+// bound 0 and no word is read.
 template <int W16>
-__device__ __forceinline__ void load_cenv(const IndexView& ix, int64_t c0, int nch, int rb, int wave, int lane,
-                                          int L, int cpp, float4 (&ce)[max_passes<W16>()]) {
+__device__ __forceinline__ void filter_batch(const IndexView& ix, const QueryWs& ws, const uint2* queue,
+                                             uint32_t head, int nb, int q, float thr, bool skip,
+                                             const float* s_lut, int lane, FilterOut& o) {
+    const uint32_t wb = (uint32_t)ix.wstride;
+    uint32_t r0[kBatch], r1[kBatch];
+    uint4 v[kBatch][W16];
 #pragma unroll
-    for (int i = 0; i < max_passes<W16>(); ++i) {
-        const int s = i * cpp + lane / L, seg = lane % L;
-        const int ch = rb + wave + kWaves * s;
-        ce[i] = make_float4(0.f, 0.f, 0.f, 0.f);
-        if (i * cpp < kSlots && s < kSlots && ch < nch && seg < ix.w) ce[i] = ix.cenv[(c0 + ch) * ix.w + seg];
+    for (int s = 0; s < kBatch; ++s) {
+        const uint2 e = queue[(head + s) & (kQueue - 1)];
+        r0[s] = __builtin_amdgcn_readfirstlane(e.x);
+        r1[s] = s < nb ? __builtin_amdgcn_readfirstlane(e.y) : r0[s];
+        const __amdgpu_buffer_rsrc_t rs =
+            buffer_rsrc(ix.words + (int64_t)r0[s] * wb, skip ? 0u : (r1[s] - r0[s]) * wb);
+#pragma unroll
+        for (int u = 0; u < W16; ++u) v[s][u] = buffer_load16(rs, (uint32_t)lane * wb + 16u * u);
     }
+    const uint64_t lt_mask = (1ull << lane) - 1ull;
+    float lbv[kBatch];
+    uint32_t mask = 0;
+#pragma unroll
+    for (int s = 0; s < kBatch; ++s) {
+        lbv[s] = 0.0f;
+        if (s < nb) {
+            if (!skip) lbv[s] = lb_sax_word<W16>(v[s], s_lut);
+            o.filt += r1[s] - r0[s];
+            if ((uint32_t)lane < r1[s] - r0[s] && lbv[s] <= thr) mask |= 1u << s;
+        }
+    }
+    uint32_t total = 0;
+#pragma unroll
+    for (int s = 0; s < kBatch; ++s) total += (uint32_t)__popcll(__ballot((mask >> s) & 1u));
+    if (total == 0) return;
+    uint32_t* dpos = o.spos;
+    uint32_t* dq = o.sq;
+    float* dlb = o.slb;
+    uint32_t off = o.cnt;
+    const bool own = (int64_t)o.cnt + total <= ws.slice_cap;
+    if (!own) {
+        // the private slice is full: reserve a range of the shared overflow
+        // slice; once that is full too, the query takes the fallback path.
+        // Reservations stop at capacity, so the 32-bit counter overshoots it
+        // by at most one range per wavefront.
+        long long b = -1;
+        if (lane == 0) {
+            uint32_t* oc = &ws.counters[kCtrOvf];
+            if ((int64_t)load_relaxed(oc) < ws.ovf_cap) {
+                const uint32_t rr = atomicAdd(oc, total);
+                if ((int64_t)rr + total <= ws.ovf_cap) b = rr;
+                else atomicMin(&ws.counters[kCtrOvfEnd], rr);  // never written: the list stops below it
+            }
+        }
+        b = __shfl(b, 0, 64);
+        if (b < 0) {
+            o.lost = true;
+            return;
+        }
+        const int64_t ob = (int64_t)ws.n_slices * ws.slice_cap;
+        dpos = ws.slice_pos + ob;
+        dq = ws.slice_q + ob;
+        dlb = ws.slice_lb + ob;
+        off = (uint32_t)b;
+    }
+#pragma unroll
+    for (int s = 0; s < kBatch; ++s) {
+        const uint64_t bal = __ballot((mask >> s) & 1u);
+        if ((mask >> s) & 1u) {
+            const uint32_t slot = off + (uint32_t)__popcll(bal & lt_mask);
+            dpos[slot] = r0[s] + (uint32_t)lane;
+            dq[slot] = (uint32_t)q;
+            dlb[slot] = lbv[s];
+        }
+        off += (uint32_t)__popcll(bal);
+    }
+    if (own) o.cnt += total;
+    o.cand += total;
 }
 
-// A part is processed in rounds of kRoundSpan chunks; in a round, wave
-// `wave` owns chunks rb + wave + 4 s (s = 0..7): lane l handles the series
-// 64 chunk + l.  First the chunks' LB_EAPCA (float32 over outward-rounded
-// intervals, summed over L = pow2 >= w lanes; the butterfly leaves every lane
-// of a group the same value) decides which chunks are read at all; then the
-// words of the live chunks are loaded together and each lane evaluates
-// LB_SAX of its series.
+// Every wavefront walks the items of the window; of item j's chunks it owns
+// wave, wave + 4, wave + 8, ...  Its chunk envelopes are tested kPass at a
+// time (a test spans L = pow2 >= w lanes, one segment each, so a load covers
+// 64 / L chunks); LB_EAPCA is float32 over outward-rounded intervals, summed
+// over the L lanes by a butterfly.  Chunks that pass join the wavefront's
+// queue in LDS, and every kBatch queued chunks go through filter_batch, so
+// the LB_SAX work comes in full batches whatever fraction of chunks pass.
 template <int W16>
 __global__ void __launch_bounds__(256) k_filter(IndexView ix, ScanParams sp, QueryWs ws) {
-    extern __shared__ float s_lut[];  // [16 W16][256], rows beyond w zero
-    __shared__ float4 s_qst[64];      // query segment mean / std intervals
+    // the table first, at a fixed LDS address, so its row offsets fold into
+    // the lookups' immediate offsets
+    __shared__ float s_lut[lut_floats<W16>()];  // [16 W16][256], rows beyond w zero
+    __shared__ uint2 s_queue[kWaves][kQueue];   // (r0, r1) of live chunks
+    __shared__ uint32_t s_pb[kWin], s_pe[kWin], s_c0[kWin];
+    __shared__ float4 s_qst[64];                // query segment mean / std intervals
+    __shared__ int s_end;
+    constexpr int kPass = 4;  // envelope loads in flight together
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
-    const float lseg = (float)(ix.n / ix.w);
     int L = 1;
     while (L < ix.w) L <<= 1;
-    const int cpp = 64 / L;  // chunk envelopes tested per pass
+    const int cpp = 64 / L;                 // chunks per envelope load
+    const int seg = lane % L;
+    const bool seg_ok = seg < ix.w;
+    const bool head_lane = seg == 0;
+    const float lseg = (float)(ix.n / ix.w);
     const uint64_t lt_mask = (1ull << lane) - 1ull;
+    // envelope of owned chunk number s = i cpp + lane / L of an item: chunk wave + 4 s
+    const int lane_chunk = wave + kWaves * (lane / L);
+    const uint32_t lane_eoff = (uint32_t)((lane_chunk * ix.w + seg) * 16);
+    const uint32_t pass_eoff = (uint32_t)(kWaves * cpp * ix.w * 16);
+    uint2* queue = s_queue[wave];
+
     const int64_t slice = (int64_t)blockIdx.x * kWaves + wave;
-    uint32_t* spos = ws.slice_pos + slice * ws.slice_cap;
-    uint32_t* sq = ws.slice_q + slice * ws.slice_cap;
-    float* slb = ws.slice_lb + slice * ws.slice_cap;
-    uint32_t cnt = 0;  // entries in this wave's slice (uniform)
+    FilterOut o{ws.slice_pos + slice * ws.slice_cap, ws.slice_q + slice * ws.slice_cap,
+                ws.slice_lb + slice * ws.slice_cap, 0u, 0ull, 0ull, 0ull, false};
     int64_t i0, i1;
     block_range(item_count(ws), i0, i1);
+    int64_t idx = i0;
     int cur_q = -1;
-    unsigned long long a_filt = 0, a_cand = 0, a_tests = 0;  // this wave's counters of cur_q
-    for (int64_t idx = i0; idx < i1; ++idx) {
-        const uint64_t item = ws.items[idx];
-        const int q = (int)(item >> 32);
-        const int64_t p = (int64_t)(uint32_t)item;
+    while (idx < i1) {
+        const int n = (int)min((int64_t)kWin, i1 - idx);
+        const int q = (int)(ws.items[idx] >> 32);
+        __syncthreads();  // no wave still reads the previous window or table
+        if (t == 0) s_end = n;
+        __syncthreads();
+        for (int j = t; j < n; j += blockDim.x) {
+            const uint64_t it = ws.items[idx + j];
+            const int64_t p = (int64_t)(uint32_t)it;
+            if ((int)(it >> 32) != q) atomicMin(&s_end, j);
+            s_pb[j] = (uint32_t)ix.part_start[p];
+            s_pe[j] = (uint32_t)ix.part_start[p + 1];
+            s_c0[j] = (uint32_t)ix.part_chunk[p];
+        }
         if (q != cur_q) {
-            if (lane == 0 && cur_q >= 0) {
-                atomicAdd(&ws.stats[(int64_t)cur_q * 8 + 1], a_filt);
-                atomicAdd(&ws.stats[(int64_t)cur_q * 8 + 6], a_cand);
-                atomicAdd(&ws.stats[(int64_t)cur_q * 8 + 7], a_tests);
-            }
-            a_filt = a_cand = a_tests = 0;
-            __syncthreads();  // no wave still reads the previous table
             load_lut<W16>(s_lut, ws.lut + (int64_t)q * ix.w * kCard, ix.w, t, blockDim.x);
             if (t < ix.w) s_qst[t] = ws.qst32[(int64_t)q * ix.w + t];
             cur_q = q;
-            __syncthreads();
         }
+        __syncthreads();
+        const int m = s_end;  // the window's items of query q
         const bool skip = (ws.flags[q] & kFlagSkipSax) != 0;
-        const double thr = prune_limit(bits_to_float(ws.bsf[q]));
-        const int64_t pb = ix.part_start[p], pe = ix.part_start[p + 1];
-        const int64_t c0 = ix.part_chunk[p];
-        const int nch = (int)((pe - pb + kChunkRows - 1) / kChunkRows);
-        bool lost = false;
-        float4 ce[max_passes<W16>()];
-        if (!skip) load_cenv<W16>(ix, c0, nch, 0, wave, lane, L, cpp, ce);
-        for (int rb = 0; rb < nch; rb += kRoundSpan) {
-            // 1. chunk envelopes (loaded during the previous round)
-            uint32_t live = 0;
+        // largest float32 not above the prune limit: for a float32 bound b,
+        // b <= thr exactly when (double) b <= limit
+        const float thr = __double2float_rd(prune_limit(bits_to_float(ws.bsf[q])));
+        const float4 qs = s_qst[seg];
+        o.filt = o.cand = o.tests = 0;
+        o.lost = false;
+        uint32_t head = 0, tail = 0;  // queue positions (uniform)
+
+        for (int j = 0; j < m; ++j) {
+            const uint32_t pb = s_pb[j], pe = s_pe[j], c0 = s_c0[j];
+            const int nch = (int)((pe - pb + kChunkRows - 1) / kChunkRows);
+            const int owned = nch > wave ? (nch - wave + kWaves - 1) / kWaves : 0;
             if (skip) {
-                live = 0xffu;
-            } else {
+                // skip-sequential path: every chunk of the item is queued
+                // untested, and every series becomes a candidate
+                for (int s0 = 0; s0 < owned; s0 += 64) {
+                    const int s = s0 + lane;
+                    if (s < owned) {
+                        const uint32_t a = pb + (uint32_t)((wave + kWaves * s) * kChunkRows);
+                        queue[(tail + (uint32_t)s - (uint32_t)s0) & (kQueue - 1)] = make_uint2(a, min(pe, a + kChunkRows));
+                    }
+                    const uint32_t add = (uint32_t)min(64, owned - s0);
+                    // drain as the queue fills (at most kBatch - 1 + 64 < kQueue entries)
+                    tail += add;
+                    __builtin_amdgcn_wave_barrier();
+                    while (tail - head >= kBatch) {
+                        filter_batch<W16>(ix, ws, queue, head, kBatch, q, thr, true, s_lut, lane, o);
+                        head += kBatch;
+                    }
+                }
+                continue;
+            }
+            const __amdgpu_buffer_rsrc_t rs = buffer_rsrc(ix.cenv + (int64_t)c0 * ix.w, (uint32_t)(nch * ix.w * 16));
+            for (int i0p = 0; i0p * cpp < owned; i0p += kPass) {
+                // kPass envelope loads in flight; chunks past the part load zeros
+                u32x4_t ce[kPass];
 #pragma unroll
-                for (int i = 0; i < max_passes<W16>(); ++i) {
-                    const int sb = i * cpp;
-                    if (sb >= kSlots) break;
-                    const int s = sb + lane / L, seg = lane % L;
-                    const int ch = rb + wave + kWaves * s;
-                    const bool valid = s < kSlots && ch < nch;
+                for (int i = 0; i < kPass; ++i)
+                    ce[i] = __builtin_amdgcn_raw_buffer_load_b128(
+                        rs, (int)(lane_eoff + (uint32_t)(i0p + i) * pass_eoff), 0, 0);
+#pragma unroll
+                for (int i = 0; i < kPass; ++i) {
+                    const int sb = (i0p + i) * cpp;  // first owned chunk number of this load
+                    if (sb >= owned) break;
+                    const bool valid = sb + lane / L < owned;
                     float term = 0.0f;
-                    if (valid && seg < ix.w) {
-                        const float4 e = ce[i];
-                        const float4 qs = s_qst[seg];
-                        const float gm = fmaxf(0.0f, fmaxf(e.x - qs.y, qs.x - e.y));
-                        const float gs = fmaxf(0.0f, fmaxf(e.z - qs.w, qs.z - e.w));
+                    if (seg_ok) {
+                        const float ex = __uint_as_float(ce[i].x), ey = __uint_as_float(ce[i].y);
+                        const float ez = __uint_as_float(ce[i].z), ew = __uint_as_float(ce[i].w);
+                        const float gm = fmaxf(0.0f, fmaxf(ex - qs.y, qs.x - ey));
+                        const float gs = fmaxf(0.0f, fmaxf(ez - qs.w, qs.z - ew));
                         term = lseg * (gm * gm + gs * gs);
                     }
-                    for (int o = L >> 1; o > 0; o >>= 1) term += __shfl_xor(term, o, 64);
-                    const uint64_t tested = __ballot(valid && seg == 0);
-                    const uint64_t ok = __ballot(valid && seg == 0 && (double)term <= thr);
-                    a_tests += (unsigned long long)__popcll(tested);
-                    for (int j = 0; j < cpp && sb + j < kSlots; ++j)
-                        if ((ok >> (j * L)) & 1ull) live |= 1u << (sb + j);
-                }
-            }
-
-            // 2. words of the live chunks, all loads in flight together, and
-            //    the next round's envelopes behind them
-            uint4 v[kSlots][W16];
-#pragma unroll
-            for (int s = 0; s < kSlots; ++s) {
-                const int64_t r = pb + (int64_t)(rb + wave + kWaves * s) * kChunkRows + lane;
-                if (!skip && ((live >> s) & 1u) && r < pe) load_word<W16>(ix.words + r * ix.wstride, v[s]);
-            }
-            if (!skip && rb + kRoundSpan < nch) load_cenv<W16>(ix, c0, nch, rb + kRoundSpan, wave, lane, L, cpp, ce);
-
-            // 3. LB_SAX and the wave's survivors
-            float lbv[kSlots];
-            uint32_t mask = 0;
-            unsigned evaluated = 0;
-#pragma unroll
-            for (int s = 0; s < kSlots; ++s) {
-                const int64_t r0 = pb + (int64_t)(rb + wave + kWaves * s) * kChunkRows;
-                const int64_t r = r0 + lane;
-                lbv[s] = 0.0f;
-                if ((live >> s) & 1u) {
-                    if (r0 < pe) evaluated += (unsigned)min((int64_t)kChunkRows, pe - r0);
-                    if (r < pe) {
-                        if (!skip) lbv[s] = lb_sax_word<W16>(v[s], s_lut);
-                        if ((double)lbv[s] <= thr) mask |= 1u << s;
+                    for (int sh = L >> 1; sh > 0; sh >>= 1) term += __shfl_xor(term, sh, 64);
+                    const bool live = valid && head_lane && term <= thr;
+                    o.tests += (unsigned long long)__popcll(__ballot(valid && head_lane));
+                    const uint64_t lm = __ballot(live);
+                    if (live) {
+                        const uint32_t a = pb + (uint32_t)((lane_chunk + kWaves * sb) * kChunkRows);
+                        queue[(tail + (uint32_t)__popcll(lm & lt_mask)) & (kQueue - 1)] =
+                            make_uint2(a, min(pe, a + kChunkRows));
+                    }
+                    tail += (uint32_t)__popcll(lm);
+                    __builtin_amdgcn_wave_barrier();
+                    while (tail - head >= kBatch) {
+                        filter_batch<W16>(ix, ws, queue, head, kBatch, q, thr, false, s_lut, lane, o);
+                        head += kBatch;
                     }
                 }
             }
-            if (!skip) a_filt += evaluated;
-            uint32_t total = 0;
-#pragma unroll
-            for (int s = 0; s < kSlots; ++s) total += (uint32_t)__popcll(__ballot((mask >> s) & 1u));
-            if (total == 0) continue;
-            uint32_t* dpos = spos;
-            uint32_t* dq = sq;
-            float* dlb = slb;
-            uint32_t off = cnt;
-            const bool own = (int64_t)cnt + total <= ws.slice_cap;
-            if (!own) {
-                // the private slice is full: reserve a range of the shared
-                // overflow slice; once that is full too, the query takes the
-                // fallback path.  Reservations stop at capacity, so the 32-bit
-                // counter overshoots it by at most one range per wavefront.
-                long long b = -1;
-                if (lane == 0) {
-                    uint32_t* oc = &ws.counters[kCtrOvf];
-                    if ((int64_t)load_relaxed(oc) < ws.ovf_cap) {
-                        const uint32_t r = atomicAdd(oc, total);
-                        if ((int64_t)r + total <= ws.ovf_cap) b = r;
-                        else atomicMin(&ws.counters[kCtrOvfEnd], r);  // never written: the list stops below it
-                    }
-                }
-                b = __shfl(b, 0, 64);
-                if (b < 0) {
-                    lost = true;
-                    continue;
-                }
-                const int64_t ob = (int64_t)ws.n_slices * ws.slice_cap;
-                dpos = ws.slice_pos + ob;
-                dq = ws.slice_q + ob;
-                dlb = ws.slice_lb + ob;
-                off = (uint32_t)b;
-            }
-#pragma unroll
-            for (int s = 0; s < kSlots; ++s) {
-                const uint64_t bal = __ballot((mask >> s) & 1u);
-                if ((mask >> s) & 1u) {
-                    const uint32_t slot = off + (uint32_t)__popcll(bal & lt_mask);
-                    dpos[slot] = (uint32_t)(pb + (int64_t)(rb + wave + kWaves * s) * kChunkRows + lane);
-                    dq[slot] = (uint32_t)q;
-                    dlb[slot] = lbv[s];
-                }
-                off += (uint32_t)__popcll(bal);
-            }
-            if (own) cnt += total;
-            a_cand += total;
         }
-        if (lost && lane == 0) atomicOr(&ws.flags[q], kFlagCandLost);
-    }
-    if (lane == 0) {
-        ws.slice_cnt[slice] = cnt;
-        if (cur_q >= 0) {
-            atomicAdd(&ws.stats[(int64_t)cur_q * 8 + 1], a_filt);
-            atomicAdd(&ws.stats[(int64_t)cur_q * 8 + 6], a_cand);
-            atomicAdd(&ws.stats[(int64_t)cur_q * 8 + 7], a_tests);
+        if (tail != head)
+            filter_batch<W16>(ix, ws, queue, head, (int)(tail - head), q, thr, skip, s_lut, lane, o);
+        idx += m;
+        if (lane == 0) {
+            atomicAdd(&ws.stats[(int64_t)q * 8 + 1], skip ? 0ull : o.filt);
+            atomicAdd(&ws.stats[(int64_t)q * 8 + 6], o.cand);
+            atomicAdd(&ws.stats[(int64_t)q * 8 + 7], o.tests);
+            if (o.lost) atomicOr(&ws.flags[q], kFlagCandLost);
         }
     }
+    if (lane == 0) ws.slice_cnt[slice] = o.cnt;
 }
 
 // Exclusive prefix of the slice counts (one workgroup); the total goes to
@@ -246,7 +298,7 @@ __global__ void __launch_bounds__(1024) k_slice_prefix(QueryWs ws) {
 
 template <int W16>
 int filter_blocks(const IndexView& ix, int cus) {
-    return resident_grid(k_filter<W16>, kTile, sizeof(float) * (size_t)lut_floats<W16>(), cus);
+    return resident_grid(k_filter<W16>, kTile, 0, cus);
 }
 
 }  // namespace
@@ -264,9 +316,8 @@ int filter_waves(const IndexView& ix, int device_cus) {
 
 hipError_t launch_filter(const IndexView& ix, const ScanParams& sp, const QueryWs& ws, int device_cus,
                          hipStream_t st) {
-    const size_t lds = sizeof(float) * (size_t)16 * w16_of(ix) * kCard;
     const dim3 grid(ws.n_slices / kWaves);  // one slice per wavefront
-    HS_DISPATCH_W16(ix, k_filter, grid, dim3(kTile), lds, st, ix, sp, ws);
+    HS_DISPATCH_W16(ix, k_filter, grid, dim3(kTile), 0, st, ix, sp, ws);
     return hipGetLastError();
 }
 
