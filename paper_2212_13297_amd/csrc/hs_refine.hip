@@ -79,6 +79,7 @@ __global__ void __launch_bounds__(256) k_refine(IndexView ix, ScanParams sp, Que
     int cur_q = -1;
     float lk = INFINITY;
     int topn = 0;                                     // lane 0
+    float pub = INFINITY;                             // lane 0: k-th distance last published for cur_q
     int st_q = -1;                                    // lane 0: counters of st_q
     unsigned long long st_ref = 0, st_ch = 0;
 
@@ -191,10 +192,17 @@ __global__ void __launch_bounds__(256) k_refine(IndexView ix, ScanParams sp, Que
         }
         if (lane == 0) {
             new_lk = INFINITY;
+            if (new_q != cur_q) pub = INFINITY;
             if (new_q >= 0 && topn == k) {
                 const uint32_t kb = (uint32_t)(top[k - 1] >> 32);
                 new_lk = bits_to_float(kb);
-                if (new_lk < bits_to_float(load_relaxed(&ws.bsf[new_q]))) atomicMin(&ws.bsf[new_q], kb);
+                // BSF_k only decreases: every improvement of this wavefront's
+                // k-th distance is published, without reading the global value
+                // back (a load here would hold up the next step)
+                if (new_lk < pub) {
+                    atomicMin(&ws.bsf[new_q], kb);
+                    pub = new_lk;
+                }
             }
         }
         cur_q = __shfl(new_q, 0, 64);
