@@ -91,16 +91,28 @@ __device__ __forceinline__ void load_word(const uint8_t* __restrict__ wp, uint4 
     for (int u = 0; u < W16; ++u) v[u] = *reinterpret_cast<const uint4*>(wp + 16 * u);
 }
 
+// The value of lane l ^ m (m = 1, 2, 4, 8) within a row of 16 lanes, by a
+// data-parallel-primitive move (no LDS).  xor 1 and xor 2 are quad
+// permutations; for m = 4 and 8 the value must already be the same in each
+// aligned group of m lanes (true after the earlier butterfly steps), where
+// the half-row mirror (l -> 7 - l in each 8 lanes) and the row mirror
+// (l -> 15 - l) pick a lane of the partner group.
+template <int M>
+__device__ __forceinline__ float row_xor(float v) {
+    constexpr int ctrl = M == 1 ? 0xB1 : (M == 2 ? 0x4E : (M == 4 ? 0x141 : 0x140));
+    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), ctrl, 0xF, 0xF, false));
+}
+
 __device__ __forceinline__ float chunk_partial(float4 q, float4 x) {
     const float t0 = q.x - x.x, t1 = q.y - x.y, t2 = q.z - x.z, t3 = q.w - x.w;
     float p = t0 * t0;
     p = fmaf(t1, t1, p);
     p = fmaf(t2, t2, p);
     p = fmaf(t3, t3, p);
-    p += __shfl_xor(p, 1, 16);
-    p += __shfl_xor(p, 2, 16);
-    p += __shfl_xor(p, 4, 16);
-    p += __shfl_xor(p, 8, 16);
+    p += row_xor<1>(p);
+    p += row_xor<2>(p);
+    p += row_xor<4>(p);
+    p += row_xor<8>(p);
     return p;
 }
 
@@ -134,14 +146,16 @@ __device__ __forceinline__ float chunk_partial_comp(float4 q, float4 x, float& l
         hi = t;
         lo += te + r;
     }
-#pragma unroll
-    for (int m = 1; m < 16; m <<= 1) {
-        const float oh = __shfl_xor(hi, m, 16), ol = __shfl_xor(lo, m, 16);
+    auto step = [&](float oh, float ol) {
         float t, te;
         two_sum(hi, oh, t, te);
         hi = t;
         lo = (lo + ol) + te;
-    }
+    };
+    step(row_xor<1>(hi), row_xor<1>(lo));
+    step(row_xor<2>(hi), row_xor<2>(lo));
+    step(row_xor<4>(hi), row_xor<4>(lo));
+    step(row_xor<8>(hi), row_xor<8>(lo));
     lo_out = lo;
     return hi;
 }

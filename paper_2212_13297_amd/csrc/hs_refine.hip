@@ -5,15 +5,15 @@
 //
 // Every wavefront owns a contiguous range of the candidate list (regions are
 // ordered by query, so a range holds long runs of one query) and never waits
-// for another wavefront: the metadata of its next 4 NC candidates is loaded
-// while the current ones are refined, each 16-lane group refines NC series at
-// a time (CB 64-point chunks of each loaded together), and the admitted
-// results reach lane 0 by shuffles; lane 0 alone keeps the wavefront's top-k
-// in LDS.
+// for another wavefront.  Its 16-lane groups refine a few series each, one
+// 64-point chunk per round, abandoning a series as soon as its running
+// distance exceeds the limit and taking the next candidate in its place.
 #include "hs_device.h"
 
 namespace hs {
 namespace {
+
+constexpr int kRefineSlots = 4;  // candidates in flight per 16-lane group
 
 struct Meta {
     int q;
@@ -37,168 +37,270 @@ __device__ __forceinline__ int slice_of(const QueryWs& ws, long long c, int hint
     return lo;
 }
 
-// Candidate c of the list; lanes 0..15 call this for c = base + lane.  The
-// lane keeps its slice's first entry and end in registers: only a step across
-// a slice end loads the prefix again.
+// Candidate c of the list, read by every lane of a wavefront for consecutive
+// c.  The lane keeps its slice's first entry and end in registers: only a
+// step across a slice end loads the prefix again.  A lane past cend reads
+// entry cend - 1 and marks it invalid, so the loads do not depend on c.
 struct SliceCursor {
     int s = 0;
     long long begin = 0, end = 0;
 };
 
 __device__ __forceinline__ Meta load_meta(const QueryWs& ws, long long c, long long cend, SliceCursor& cur) {
-    Meta m{-1, 0u, 0.0f};
-    if (c < cend) {
-        if (c >= cur.end) {
-            cur.s = slice_of(ws, c, cur.s);
-            cur.begin = ws.slice_start[cur.s];
-            cur.end = ws.slice_start[cur.s + 1];
-        }
-        const long long e = (long long)cur.s * ws.slice_cap + (c - cur.begin);
-        m.q = (int)ws.slice_q[e];
-        m.pos = ws.slice_pos[e];
-        m.lb = ws.slice_lb[e];
+    const long long cc = min(c, cend - 1);
+    if (cc >= cur.end) {
+        cur.s = slice_of(ws, cc, cur.s);
+        cur.begin = ws.slice_start[cur.s];
+        cur.end = ws.slice_start[cur.s + 1];
     }
+    const long long e = (long long)cur.s * ws.slice_cap + (cc - cur.begin);
+    Meta m;
+    m.q = (int)ws.slice_q[e];
+    m.pos = ws.slice_pos[e];
+    m.lb = ws.slice_lb[e];
+    if (c >= cend) m.q = -1;
     return m;
 }
 
-// F: distance form.  NC: series in flight per 16-lane group; CB: 64-point
-// chunks loaded together per series between two abandoning checks.
-template <int F, int NC, int CB>
+// F: distance form.  NS: candidates in flight per 16-lane group.
+//
+// Every wavefront owns a contiguous range of the candidate list.  Each of its
+// four groups keeps NS slots; a round loads one 64-point chunk of every
+// slot's series (and the query's chunk), adds the chunk's partial to the
+// slot's running distance, and retires the slots whose distance exceeds
+// their limit (abandoned) or whose series is complete.  Retired slots take
+// the next candidates of the range at once, so every round reads NS useful
+// chunks per group however early candidates are abandoned.
+//
+// The candidates' metadata pass through a ring of 128 entries in LDS per
+// wavefront (the next 64 are loaded while the current ones are handed out).
+// A slot's limit is the smaller of the last BSF_k read for its query and the
+// wavefront's own k-th distance; an older BSF_k is only a looser limit.
+// Counters accumulate per group in registers; only rounds that complete a
+// series within its limit, or retire a candidate of another query, go
+// through lane 0, which alone keeps the wavefront's top-k in LDS and
+// publishes its improvements with atomicMin.
+template <int F, int NS>
 __global__ void __launch_bounds__(256) k_refine(IndexView ix, ScanParams sp, QueryWs ws) {
-    constexpr int kStep = 4 * NC;  // candidates per wavefront step: 4 groups x NC
+    constexpr int kRing = 128;
     __shared__ unsigned long long s_top[kTile / 64][HS_KMAX];
+    __shared__ uint4 s_ring[kTile / 64][kRing];  // (q, pos, lb bits, -) of candidate i at (i - cbeg) mod 128
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6, sub = t & 15, grp = (t >> 4) & 3;
     const int k = sp.k;
     const int nchunks = ix.stride / kChunk;
     const long long T = ws.slice_start[ws.n_slices + 1];
     const long long gw = (long long)blockIdx.x * (kTile / 64) + wave, GW = (long long)gridDim.x * (kTile / 64);
     const long long cbeg = T * gw / GW, cend = T * (gw + 1) / GW;
+    if (cbeg >= cend) return;
     unsigned long long* top = s_top[wave];
+    uint4* ring = s_ring[wave];
 
     // wavefront state, uniform: the query of the top-k and its k-th distance
     int cur_q = -1;
     float lk = INFINITY;
     int topn = 0;                                     // lane 0
     float pub = INFINITY;                             // lane 0: k-th distance last published for cur_q
-    int st_q = -1;                                    // lane 0: counters of st_q
-    unsigned long long st_ref = 0, st_ch = 0;
+    // refined series and chunks read for query st_q (uniform), per group
+    int st_q = -1;
+    uint32_t g_ref = 0u, g_ch = 0u;
+    auto flush_counters = [&]() {
+        uint32_t r = 0u, c = 0u;
+#pragma unroll
+        for (int g = 0; g < 4; ++g) {
+            r += (uint32_t)__builtin_amdgcn_readlane(g_ref, 16 * g);
+            c += (uint32_t)__builtin_amdgcn_readlane(g_ch, 16 * g);
+        }
+        if (lane == 0 && st_q >= 0 && r) {
+            atomicAdd(&ws.stats[(int64_t)st_q * 8 + 2], (unsigned long long)r);
+            atomicAdd(&ws.stats[(int64_t)st_q * 8 + 3], (unsigned long long)c);
+        }
+        g_ref = g_ch = 0u;
+    };
 
-    SliceCursor cur;  // lane's slice (end 0: found on the first load)
-    Meta m = lane < kStep ? load_meta(ws, cbeg + lane, cend, cur) : Meta{-1, 0u, 0.0f};
-    float mb = m.q >= 0 ? bits_to_float(load_relaxed(&ws.bsf[m.q])) : 0.0f;
-    for (long long cb = cbeg; cb < cend; cb += kStep) {
-        // next step's metadata in flight while this step is refined
-        const Meta nm = lane < kStep ? load_meta(ws, cb + kStep + lane, cend, cur) : Meta{-1, 0u, 0.0f};
+    SliceCursor cur;
+    long long mb = cbeg;  // the ring holds candidates mb .. mb + 127
+    int bq, pq;           // query of the last BSF_k read and of the one in flight
+    float bv, pv;
+    {
+        const Meta a = load_meta(ws, mb + lane, cend, cur);
+        const Meta b = load_meta(ws, mb + 64 + lane, cend, cur);
+        ring[lane] = make_uint4((uint32_t)a.q, a.pos, __float_as_uint(a.lb), 0u);
+        ring[64 + lane] = make_uint4((uint32_t)b.q, b.pos, __float_as_uint(b.lb), 0u);
+        bq = pq = __builtin_amdgcn_readfirstlane(a.q);
+        bv = pv = bits_to_float(load_relaxed(&ws.bsf[max(bq, 0)]));
+    }
+    Meta pend{-1, 0u, 0.0f};  // the next 64 entries, written to the ring after this round's loads
+    bool has_pend = false;
+    long long next = cbeg;  // next candidate to hand out (uniform)
 
-        unsigned long long res[NC];  // admitted keys of this group (group-uniform), ~0 = none
-        int resq[NC];
-        unsigned chs[NC];            // chunks read per candidate (0: not refined)
-        float nmb = 0.0f;           // next step's BSF_k, loaded behind this step's first rows
-        {
-            int q[NC];
-            uint32_t pos[NC];
-            float thr[NC];
-            Dist<F> d[NC];
-            bool alive[NC], refined[NC];
-            unsigned ch[NC];
+    // slots, each the same in the 16 lanes of its group
+    int sq[NS];            // query (-1: empty)
+    uint32_t spos[NS];     // stored position of the series
+    int sc[NS];            // chunks added so far
+    float sthr[NS];        // abandoning limit
+    const float* xp[NS];   // the lane's first point of the series and of the query
+    const float* qp[NS];
+    Dist<F> sd[NS];
+    bool fin[NS];          // slot wants a candidate
 #pragma unroll
-            for (int j = 0; j < NC; ++j) {
-                const int src = grp * NC + j;
-                q[j] = __shfl(m.q, src, 64);
-                pos[j] = __shfl(m.pos, src, 64);
-                const float lb = __shfl(m.lb, src, 64);
-                thr[j] = __shfl(mb, src, 64);
-                if (q[j] == cur_q) thr[j] = fminf(thr[j], lk);
-                refined[j] = q[j] >= 0 && (double)lb <= prune_limit(thr[j]);
-                alive[j] = refined[j];
-                ch[j] = 0u;
-            }
-            for (int c = 0; c < nchunks; c += CB) {
-                float4 x[NC][CB];
-#pragma unroll
-                for (int j = 0; j < NC; ++j) {
-                    if (alive[j]) {
-                        const float* xr = ix.rows + (int64_t)pos[j] * ix.stride + sub * 4 + c * kChunk;
-#pragma unroll
-                        for (int b = 0; b < CB; ++b)
-                            x[j][b] = c + b < nchunks ? *reinterpret_cast<const float4*>(xr + b * kChunk)
-                                                      : make_float4(0.f, 0.f, 0.f, 0.f);
-                    }
+    for (int s = 0; s < NS; ++s) {
+        sq[s] = -1;
+        spos[s] = 0u;
+        sc[s] = 0;
+        sthr[s] = INFINITY;
+        xp[s] = ix.rows + sub * 4;
+        qp[s] = ws.qrow + sub * 4;
+        fin[s] = true;
+    }
+
+    for (;;) {
+        // hand out candidates to the slots that want one, in slot order
+        // (group g, slot s) -> g NS + s; a candidate whose LB_SAX exceeds its
+        // limit is skipped and the slot asks again
+        for (;;) {
+            if (next - mb >= 64) {
+                // the ring moves on by 64: the next 64 entries are loaded (and
+                // written after this round's loads), the BSF_k read at the last
+                // move is taken over and the next one is issued
+                if (has_pend) {
+                    ring[((int)(mb + 64 - cbeg) & (kRing - 1)) + lane] =
+                        make_uint4((uint32_t)pend.q, pend.pos, __float_as_uint(pend.lb), 0u);
+                    has_pend = false;
                 }
-                if (c == 0 && nm.q >= 0) nmb = bits_to_float(load_relaxed(&ws.bsf[nm.q]));
-                // the group's candidates almost always share a query: its chunks are
-                // loaded once and reloaded only for a candidate of another query
-                const float* q0 = ws.qrow + (int64_t)q[0] * ix.stride + sub * 4 + c * kChunk;
-                float4 qa[CB];
+                mb += 64;
+                pend = load_meta(ws, mb + 64 + lane, cend, cur);
+                has_pend = true;
+                bq = pq;
+                bv = pv;
+                pq = __builtin_amdgcn_readfirstlane((int)ring[(int)(mb - cbeg) & (kRing - 1)].x);
+                pv = bits_to_float(load_relaxed(&ws.bsf[max(pq, 0)]));
+            }
+            if (has_pend && next + 4 * NS > mb + 64) {
+                // this hand-out reaches the entries still in flight (after many
+                // skipped candidates): they are written now
+                ring[((int)(mb + 64 - cbeg) & (kRing - 1)) + lane] =
+                    make_uint4((uint32_t)pend.q, pend.pos, __float_as_uint(pend.lb), 0u);
+                has_pend = false;
+            }
+            int rank[NS], nf = 0;
 #pragma unroll
-                for (int b = 0; b < CB; ++b)
-                    qa[b] = (q[0] >= 0 && c + b < nchunks) ? *reinterpret_cast<const float4*>(q0 + b * kChunk)
-                                                          : make_float4(0.f, 0.f, 0.f, 0.f);
+            for (int s = 0; s < NS; ++s) {
+                rank[s] = nf;
+                nf += fin[s] ? 1 : 0;
+            }
+            const int f0 = __builtin_amdgcn_readlane(nf, 0), f1 = __builtin_amdgcn_readlane(nf, 16),
+                      f2 = __builtin_amdgcn_readlane(nf, 32), f3 = __builtin_amdgcn_readlane(nf, 48);
+            const int total = f0 + f1 + f2 + f3;
+            if (total == 0) break;
+            const int goff = (grp > 0 ? f0 : 0) + (grp > 1 ? f1 : 0) + (grp > 2 ? f2 : 0);
+            bool again = false;
 #pragma unroll
-                for (int j = 0; j < NC; ++j) {
-                    if (alive[j]) {
-                        const float* qr = ws.qrow + (int64_t)q[j] * ix.stride + sub * 4 + c * kChunk;
-#pragma unroll
-                        for (int b = 0; b < CB; ++b) {
-                            if (c + b < nchunks) {
-                                const float4 a = q[j] != q[0] ? *reinterpret_cast<const float4*>(qr + b * kChunk) : qa[b];
-                                d[j].add(a, x[j][b]);
-                                ch[j] += 1u;
-                            }
-                        }
-                        if (d[j].value() > thr[j]) alive[j] = false;
-                    }
+            for (int s = 0; s < NS; ++s) {
+                if (!__ballot(fin[s])) continue;
+                if (fin[s]) {
+                    const long long i = next + goff + rank[s];
+                    const uint4 e = ring[(int)(i - cbeg) & (kRing - 1)];
+                    const int q = i < cend ? (int)e.x : -1;
+                    float lim = q == bq ? bv : INFINITY;
+                    if (q == cur_q) lim = fminf(lim, lk);
+                    const uint32_t pos = q >= 0 ? e.y : 0u;
+                    sq[s] = q;
+                    spos[s] = pos;
+                    sc[s] = 0;
+                    sd[s] = Dist<F>{};
+                    sthr[s] = lim;
+                    xp[s] = ix.rows + (int64_t)pos * ix.stride + sub * 4;
+                    qp[s] = ws.qrow + (int64_t)max(q, 0) * ix.stride + sub * 4;
+                    fin[s] = q >= 0 && (double)__uint_as_float(e.z) > prune_limit(lim);  // skipped: ask again
+                    again = again || fin[s];
                 }
             }
+            next += total;
+            if (!__ballot(again)) break;
+        }
+        bool any = false;
 #pragma unroll
-            for (int j = 0; j < NC; ++j) {
-                chs[j] = refined[j] ? ch[j] : 0u;
-                res[j] = (refined[j] && alive[j]) ? (((unsigned long long)__float_as_uint(d[j].value()) << 32) | ix.ids[pos[j]])
-                                                  : ~0ull;
-                resq[j] = q[j];
+        for (int s = 0; s < NS; ++s) any = any || sq[s] >= 0;
+        if (!__ballot(any)) break;
+
+        // one chunk of every slot's series; empty slots read chunk 0 of row 0
+        float4 x[NS], qv[NS];
+#pragma unroll
+        for (int s = 0; s < NS; ++s) {
+            x[s] = *reinterpret_cast<const float4*>(xp[s] + sc[s] * kChunk);
+            qv[s] = *reinterpret_cast<const float4*>(qp[s] + sc[s] * kChunk);
+        }
+        bool adm[NS];
+        bool slow = false;
+#pragma unroll
+        for (int s = 0; s < NS; ++s) {
+            adm[s] = false;
+            fin[s] = false;
+            if (sq[s] >= 0) {
+                sd[s].add(qv[s], x[s]);
+                sc[s] += 1;
+                const bool over = sd[s].value() > sthr[s];
+                fin[s] = over || sc[s] == nchunks;
+                adm[s] = fin[s] && !over;
+                slow = slow || adm[s] || (fin[s] && sq[s] != st_q);
             }
         }
+        if (has_pend) {
+            ring[((int)(mb + 64 - cbeg) & (kRing - 1)) + lane] =
+                make_uint4((uint32_t)pend.q, pend.pos, __float_as_uint(pend.lb), 0u);
+            has_pend = false;
+        }
 
-        // lane 0 takes the 4 groups' results and counters one by one
+        if (!__ballot(slow)) {
+            // common round: nothing admitted, every retired candidate of st_q
+#pragma unroll
+            for (int s = 0; s < NS; ++s)
+                if (fin[s]) {
+                    g_ref += 1u;
+                    g_ch += (uint32_t)sc[s];
+                }
+            continue;
+        }
+        // retirements one by one, in slot order
         int new_q = cur_q;
-        float new_lk = lk;
 #pragma unroll
-        for (int i = 0; i < kStep; ++i) {
-            const unsigned long long key = __shfl(res[i % NC], (i / NC) * 16, 64);
-            const int kq = __shfl(resq[i % NC], (i / NC) * 16, 64);
-            const unsigned kch = __shfl(chs[i % NC], (i / NC) * 16, 64);
-            if (lane == 0) {
-                if (key != ~0ull) {
-                    if (kq != new_q) {
-                        flush_topk(ws, new_q, k, top, topn);
-                        new_q = kq;
-                        topn = 0;
-                    }
-                    topk_insert(top, topn, k, key);
+        for (int s = 0; s < NS; ++s) {
+            const uint64_t b = __ballot(fin[s]);
+#pragma unroll
+            for (int g = 0; g < 4; ++g) {
+                if (!((b >> (16 * g)) & 1ull)) continue;
+                const int kq = __builtin_amdgcn_readlane(sq[s], 16 * g);
+                if (kq != st_q) {
+                    flush_counters();
+                    st_q = kq;
                 }
-                if (kch) {  // counters, one update per change of query
-                    if (kq != st_q) {
-                        if (st_q >= 0) {
-                            atomicAdd(&ws.stats[(int64_t)st_q * 8 + 2], st_ref);
-                            atomicAdd(&ws.stats[(int64_t)st_q * 8 + 3], st_ch);
+                if (grp == g) {
+                    g_ref += 1u;
+                    g_ch += (uint32_t)sc[s];
+                }
+                if (__builtin_amdgcn_readlane((int)adm[s], 16 * g)) {
+                    const float v = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(sd[s].value()), 16 * g));
+                    const uint32_t kp = (uint32_t)__builtin_amdgcn_readlane(spos[s], 16 * g);
+                    if (lane == 0) {
+                        if (kq != new_q) {
+                            flush_topk(ws, new_q, k, top, topn);
+                            new_q = kq;
+                            topn = 0;
                         }
-                        st_q = kq;
-                        st_ref = st_ch = 0;
+                        topk_insert(top, topn, k, ((unsigned long long)__float_as_uint(v) << 32) | ix.ids[kp]);
                     }
-                    st_ref += 1;
-                    st_ch += kch;
                 }
             }
         }
+        float new_lk = INFINITY;
         if (lane == 0) {
-            new_lk = INFINITY;
             if (new_q != cur_q) pub = INFINITY;
             if (new_q >= 0 && topn == k) {
                 const uint32_t kb = (uint32_t)(top[k - 1] >> 32);
                 new_lk = bits_to_float(kb);
                 // BSF_k only decreases: every improvement of this wavefront's
                 // k-th distance is published, without reading the global value
-                // back (a load here would hold up the next step)
+                // back (a load here would hold up the next round)
                 if (new_lk < pub) {
                     atomicMin(&ws.bsf[new_q], kb);
                     pub = new_lk;
@@ -207,34 +309,22 @@ __global__ void __launch_bounds__(256) k_refine(IndexView ix, ScanParams sp, Que
         }
         cur_q = __shfl(new_q, 0, 64);
         lk = __shfl(new_lk, 0, 64);
-        m = nm;
-        mb = nmb;
+#pragma unroll
+        for (int s = 0; s < NS; ++s)
+            if (sq[s] == cur_q) sthr[s] = fminf(sthr[s], lk);
     }
-    if (lane == 0) {
-        flush_topk(ws, cur_q, k, top, topn);
-        if (st_q >= 0) {
-            atomicAdd(&ws.stats[(int64_t)st_q * 8 + 2], st_ref);
-            atomicAdd(&ws.stats[(int64_t)st_q * 8 + 3], st_ch);
-        }
-    }
+    if (lane == 0) flush_topk(ws, cur_q, k, top, topn);
+    flush_counters();
 }
 
 }  // namespace
 
 hipError_t launch_refine(const IndexView& ix, const ScanParams& sp, const QueryWs& ws, int device_cus, int form,
                          hipStream_t st) {
-    // series of at least 256 points: two in flight per group, four chunks
-    // (1 KB of a row) per load; shorter series: four in flight, two chunks
-#define HS_REFINE(FF, NC, CB) \
-    k_refine<FF, NC, CB><<<dim3(resident_grid(k_refine<FF, NC, CB>, kTile, 0, device_cus)), dim3(kTile), 0, st>>>(ix, sp, ws)
-    const bool wide = ix.stride >= 4 * kChunk;
-    if (form == kComp) {
-        if (wide) HS_REFINE(kComp, 2, 4);
-        else HS_REFINE(kComp, 4, 2);
-    } else {
-        if (wide) HS_REFINE(kPlain, 2, 4);
-        else HS_REFINE(kPlain, 4, 2);
-    }
+#define HS_REFINE(FF, NS) \
+    k_refine<FF, NS><<<dim3(resident_grid(k_refine<FF, NS>, kTile, 0, device_cus)), dim3(kTile), 0, st>>>(ix, sp, ws)
+    if (form == kComp) HS_REFINE(kComp, kRefineSlots);
+    else HS_REFINE(kPlain, kRefineSlots);
 #undef HS_REFINE
     return hipGetLastError();
 }
