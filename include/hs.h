@@ -194,16 +194,18 @@ hs_status hs_knn_exact(hs_index* idx, const float* q_dev, int32_t Q, int32_t k, 
 #define HS_SHADOW_FP16 2
 
 /* Device bytes of the low-precision copy of kind HS_SHADOW_*: (N + 32) x
- * row_stride 16-bit values and (N + 32) x 8 bytes of norms (the last 32 rows
- * are zero padding), plus 256 bytes of scratch.
+ * row_stride 16-bit values and (N + 32) x 16 bytes of per-series constants
+ * (the last 32 rows are zero padding), plus 256 bytes of scratch.
  * Errors: HS_EINVAL (NULL, unknown kind). */
 hs_status hs_shadow_bytes(const hs_index* idx, int32_t kind, int64_t* bytes);
 
 /* Build the low-precision copy into caller-owned device memory shadow_dev
  * (hs_shadow_bytes bytes, kept allocated until hs_index_free or the next
- * hs_build_shadow).  Per series it stores x~ in leaf order, ||x~||^2
- * (computed in float64, stored rounded down) and ||x - x~||_2 (stored
- * rounded up).  Synchronises the stream.  An index holds one copy; a new
+ * hs_build_shadow).  Per series it stores x~ in leaf order and four floats:
+ * beta (the series' term of the bounding pass's float32 test, computed in
+ * float64 from the next two, rounded down), ||x - x~||_2 (float64, stored
+ * rounded up), ||x~||^2 (float64, stored rounded down) and 0.  Synchronises
+ * the stream.  An index holds one copy; a new
  * call replaces it.
  * Errors: HS_EINVAL (NULL, unknown kind, a value beyond the fp16 range for
  * HS_SHADOW_FP16), HS_ENOMEM (shadow_bytes too small), HS_EHIP. */

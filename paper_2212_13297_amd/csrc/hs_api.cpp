@@ -651,13 +651,13 @@ hs_status run_knn(hs_index* idx, const float* q_dev, int32_t Q, int32_t k, void*
 
 // The copy is followed by kBoundRows zero rows (and zero norms), so the
 // bounding pass may stage a whole tile past the last series.
-int64_t shadow_layout(const IndexView& ix, uint16_t** rows, float2** norms, uint32_t** flag, char* base) {
+int64_t shadow_layout(const IndexView& ix, uint16_t** rows, float4** norms, uint32_t** flag, char* base) {
     char* cur = base;
     void* a;
     carve(cur, &a, (ix.N + kBoundRows) * ix.stride * 2);
     if (rows) *rows = (uint16_t*)a;
-    carve(cur, &a, (ix.N + kBoundRows) * 8);
-    if (norms) *norms = (float2*)a;
+    carve(cur, &a, (ix.N + kBoundRows) * 16);
+    if (norms) *norms = (float4*)a;
     carve(cur, &a, 256);
     if (flag) *flag = (uint32_t*)a;
     return (int64_t)(cur - base);
@@ -692,13 +692,13 @@ hs_status hs_build_shadow(hs_index* idx, int32_t kind, void* shadow_dev, int64_t
         return fail(HS_ENOMEM, "shadow_bytes=%lld < required %lld", (long long)shadow_bytes, (long long)need);
     hipStream_t st = (hipStream_t)stream;
     uint16_t* rows;
-    float2* norms;
+    float4* norms;
     uint32_t* flag;
     shadow_layout(idx->view, &rows, &norms, &flag, (char*)shadow_dev);
     idx->shadow = ShadowView{};
     HIP_TRY(hipMemsetAsync(flag, 0, 4, st));
     HIP_TRY(hipMemsetAsync(rows + idx->view.N * idx->view.stride, 0, (size_t)kBoundRows * idx->view.stride * 2, st));
-    HIP_TRY(hipMemsetAsync(norms + idx->view.N, 0, (size_t)kBoundRows * 8, st));
+    HIP_TRY(hipMemsetAsync(norms + idx->view.N, 0, (size_t)kBoundRows * 16, st));
     HIP_TRY(launch_shadow(idx->view, kind, rows, norms, flag, st));
     uint32_t bad = 0;
     HIP_TRY(hipMemcpyAsync(&bad, flag, 4, hipMemcpyDeviceToHost, st));

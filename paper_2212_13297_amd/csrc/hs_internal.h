@@ -59,7 +59,8 @@ constexpr int kBoundRows = 32;      // series per tile of the bounding pass
 
 struct ShadowView {
     const uint16_t* rows;  // [N + kBoundRows][stride] bf16 / fp16 bits of the stored series, zero padded
-    const float2* norms;   // [N + kBoundRows] (||x~||^2 rounded down, ||x - x~||_2 rounded up), float32
+    const float4* norms;   // [N + kBoundRows] (beta, ||x - x~||_2 rounded up, ||x~||^2 rounded down, 0), float32;
+                           // beta = ((1 - g) ||x~||^2 - eps^2) / 2 - 3u (||x~||^2 + eps^2), float64, rounded down
     int32_t kind;          // kShadowBf16 / kShadowF16
 };
 
@@ -154,7 +155,7 @@ hipError_t launch_merge(const IndexView& ix, const ScanParams& sp, bool redo_onl
                         hipStream_t st);
 
 // precision form (hs_precision.hip)
-hipError_t launch_shadow(const IndexView& ix, int kind, uint16_t* rows, float2* norms, uint32_t* bad_flag,
+hipError_t launch_shadow(const IndexView& ix, int kind, uint16_t* rows, float4* norms, uint32_t* bad_flag,
                          hipStream_t st);
 hipError_t launch_query_low(const IndexView& ix, int kind, int32_t Q, const QueryWs& ws, hipStream_t st);
 // order the queries by their best leaf (queries of one wavefront then keep

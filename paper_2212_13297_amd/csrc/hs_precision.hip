@@ -59,11 +59,31 @@ struct Low<kShadowF16> {
     }
 };
 
+// Constants of the float32 test.
+struct BoundConsts {
+    double g;   // accumulation factor g (plus 2^-40 for the float64 norms)
+    double m;   // margin factor 3u of the folded constants (u = 2^-24)
+};
+
+// The constants for series of stride K: g for K float32 additions at twice the
+// unit roundoff (plus 2^-40 for the float64 norms), m = 3u.
+BoundConsts bound_consts(int K) {
+    const double u2 = std::ldexp(1.0, -23), Kd = (double)K;
+    return BoundConsts{Kd * u2 / (1.0 - Kd * u2) + std::ldexp(1.0, -40), 3.0 * std::ldexp(1.0, -24)};
+}
+
+// beta_x of the float32 test from the stored ||x~||^2 and eps_x (float64,
+// lowered by 3u M_x, rounded down).
+__device__ __forceinline__ float beta_of(float xn, float eps, const BoundConsts& bc) {
+    const double xd = xn, ed = eps;
+    return __double2float_rd(0.5 * ((1.0 - bc.g) * xd - ed * ed) - bc.m * (xd + ed * ed));
+}
+
 // One wavefront per series: the low-precision copy and, in float64,
-// ||x~||^2 (stored rounded down) and ||x - x~||_2 (stored rounded up).
+// ||x~||^2 (stored rounded down), ||x - x~||_2 (stored rounded up) and beta_x.
 template <int KIND>
-__global__ void __launch_bounds__(256) k_shadow(IndexView ix, uint16_t* __restrict__ out, float2* __restrict__ norms,
-                                                uint32_t* __restrict__ bad) {
+__global__ void __launch_bounds__(256) k_shadow(IndexView ix, uint16_t* __restrict__ out, float4* __restrict__ norms,
+                                                uint32_t* __restrict__ bad, BoundConsts bc) {
     const int lane = threadIdx.x & 63;
     const int64_t w0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
     const int64_t nw = ((int64_t)gridDim.x * blockDim.x) >> 6;
@@ -90,8 +110,11 @@ __global__ void __launch_bounds__(256) k_shadow(IndexView ix, uint16_t* __restri
         if (__ballot(!ok) != 0ull && lane == 0) atomicOr(bad, 1u);
         // float64 sums carry a relative error below 2^-40 for any stride the
         // index accepts; the factors push the stored values past it
-        if (lane == 0)
-            norms[r] = make_float2(__double2float_rd(s2 * (1.0 - 0x1p-40)), __double2float_ru(sqrt(e2) * (1.0 + 0x1p-40)));
+        if (lane == 0) {
+            const float xn = __double2float_rd(s2 * (1.0 - 0x1p-40));
+            const float eps = __double2float_ru(sqrt(e2) * (1.0 + 0x1p-40));
+            norms[r] = make_float4(beta_of(xn, eps, bc), eps, xn, 0.0f);
+        }
     }
 }
 
@@ -167,12 +190,6 @@ __global__ void __launch_bounds__(1024) k_query_order(int32_t Q, QueryWs ws) {
     }
     for (int i = t; i < ws.Qpad; i += blockDim.x) ws.qorder[i] = i < Q ? (int)(s_key[i] & 0xffffffffu) : -1;
 }
-
-// Constants of the float32 test.
-struct BoundConsts {
-    double g;   // accumulation factor g (plus 2^-40 for the float64 norms)
-    double m;   // margin factor 3u of the folded constants (u = 2^-24)
-};
 
 // Which q-group and row range a workgroup takes.  With enough workgroups the
 // G q-groups of one row range run on the same XCD (workgroup b sits on XCD
@@ -300,8 +317,8 @@ __global__ void __launch_bounds__(256) k_bound(IndexView ix, ShadowView sv, Scan
                 // 8-element column (that % 32); rows past the collection are
                 // clamped (their results are masked).
                 uint4 pa[4];
-                float2 na = make_float2(0.f, 0.f);
-                auto stage_load = [&](int64_t s, uint4 (&pre)[4], float2& pn) {
+                float4 na = make_float4(0.f, 0.f, 0.f, 0.f);
+                auto stage_load = [&](int64_t s, uint4 (&pre)[4], float4& pn) {
                     // branch-free, from the tile's first row (the copy is padded by
                     // a tile, so no row clamp); columns past K read other values of
                     // the copy that are zeroed when stored
@@ -315,7 +332,7 @@ __global__ void __launch_bounds__(256) k_bound(IndexView ix, ShadowView sv, Scan
                     }
                     pn = sv.norms[tr0 + (t & (kBoundRows - 1))];
                 };
-                auto stage_store = [&](int64_t s, const uint4 (&pre)[4], float2 pn) {
+                auto stage_store = [&](int64_t s, const uint4 (&pre)[4], float4 pn) {
                     uint16_t* dst = s_tile[s & 1];
                     const int kb = (int)(s % nkb);
 #pragma unroll
@@ -325,10 +342,8 @@ __global__ void __launch_bounds__(256) k_bound(IndexView ix, ShadowView sv, Scan
                             cc + kb * kKBlock < K ? pre[i] : make_uint4(0, 0, 0, 0);
                     }
                     if (kb == 0 && t < kBoundRows) {
-                        const double xd = pn.x, ed = pn.y;
-                        const float beta = __double2float_rd(0.5 * ((1.0 - bc.g) * xd - ed * ed) - bc.m * (xd + ed * ed));
-                        s_norm[(s / nkb) & 1][t] = make_float2(beta, pn.y);
-                        s_xn[(s / nkb) & 1][t] = pn.x;
+                        s_norm[(s / nkb) & 1][t] = make_float2(pn.x, pn.y);
+                        s_xn[(s / nkb) & 1][t] = pn.z;
                     }
                 };
                 stage_load(0, pa, na);
@@ -482,13 +497,14 @@ __global__ void __launch_bounds__(256) k_bound(IndexView ix, ShadowView sv, Scan
 
 }  // namespace
 
-hipError_t launch_shadow(const IndexView& ix, int kind, uint16_t* rows, float2* norms, uint32_t* bad_flag,
+hipError_t launch_shadow(const IndexView& ix, int kind, uint16_t* rows, float4* norms, uint32_t* bad_flag,
                          hipStream_t st) {
     const int grid = grid_for(ix.N * 64, 256, 1 << 16);
+    const BoundConsts bc = bound_consts(ix.stride);
     if (kind == kShadowF16)
-        k_shadow<kShadowF16><<<dim3(grid), dim3(256), 0, st>>>(ix, rows, norms, bad_flag);
+        k_shadow<kShadowF16><<<dim3(grid), dim3(256), 0, st>>>(ix, rows, norms, bad_flag, bc);
     else
-        k_shadow<kShadowBf16><<<dim3(grid), dim3(256), 0, st>>>(ix, rows, norms, bad_flag);
+        k_shadow<kShadowBf16><<<dim3(grid), dim3(256), 0, st>>>(ix, rows, norms, bad_flag, bc);
     return hipGetLastError();
 }
 
@@ -530,11 +546,7 @@ hipError_t launch_bound(const IndexView& ix, const ShadowView& sv, const ScanPar
         bm.R = grid / bm.GS;
     }
     bm.used = bm.R * bm.GS;
-    // g: accumulation error factor for K additions at twice the unit roundoff
-    const double u2 = std::ldexp(1.0, -23), Kd = (double)ix.stride;
-    BoundConsts bc;
-    bc.g = Kd * u2 / (1.0 - Kd * u2) + std::ldexp(1.0, -40);
-    bc.m = 3.0 * std::ldexp(1.0, -24);
+    const BoundConsts bc = bound_consts(ix.stride);
     if (sv.kind == kShadowF16) {
         if (one) k_bound<kShadowF16, true><<<dim3(grid), dim3(kTile), 0, st>>>(ix, sv, sp, ws, bc, bm);
         else k_bound<kShadowF16, false><<<dim3(grid), dim3(kTile), 0, st>>>(ix, sv, sp, ws, bc, bm);

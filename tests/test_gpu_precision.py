@@ -83,7 +83,7 @@ def test_shadow_copy_against_oracle(kind):
     pad = 32  # zero rows after the copy
     low_bits = sh[:N * stride * 2].view(np.uint16).reshape(N, stride)
     assert not np.any(sh[N * stride * 2:(N + pad) * stride * 2])
-    norms = sh[((N + pad) * stride * 2 + 255) // 256 * 256:][:N * 8].view(np.float32).reshape(N, 2)
+    norms = sh[((N + pad) * stride * 2 + 255) // 256 * 256:][:N * 16].view(np.float32).reshape(N, 4)
     if kind == P.BF16:
         low = (low_bits.astype(np.uint32) << 16).view(np.float32)
     else:
@@ -91,8 +91,18 @@ def test_shadow_copy_against_oracle(kind):
     np.testing.assert_array_equal(low, P.round_low(rows, kind))
     xn = np.sum(low.astype(np.float64) ** 2, axis=1)
     eps = np.sqrt(np.sum((rows.astype(np.float64) - low.astype(np.float64)) ** 2, axis=1))
-    assert np.all(norms[:, 0] <= xn) and np.all(norms[:, 0] >= xn * (1 - 1e-6))
+    assert np.all(norms[:, 2] <= xn) and np.all(norms[:, 2] >= xn * (1 - 1e-6))
     assert np.all(norms[:, 1] >= eps) and np.all(norms[:, 1] <= eps * (1 + 1e-6) + 1e-37)
+    assert np.all(norms[:, 3] == 0.0)
+    # beta = ((1 - g) xn - eps^2) / 2 - 3u (xn + eps^2) from the stored xn and eps,
+    # rounded down to float32 (g: accumulation factor of `stride` additions)
+    u2 = 2.0 ** -23
+    g = stride * u2 / (1.0 - stride * u2) + 2.0 ** -40
+    xs, es = norms[:, 2].astype(np.float64), norms[:, 1].astype(np.float64)
+    beta = 0.5 * ((1.0 - g) * xs - es * es) - 3.0 * 2.0 ** -24 * (xs + es * es)
+    b32 = norms[:, 0]
+    assert np.all(b32.astype(np.float64) <= beta)
+    assert np.all(np.nextafter(b32, np.float32(np.inf)).astype(np.float64) > beta)
 
 
 # N, n, w, k, leaf, l_max, per_level, kind
