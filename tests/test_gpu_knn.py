@@ -180,6 +180,20 @@ def test_candidate_list_fallback_matches_main_path():
     b.close()
 
 
+def test_filter_windows_and_single_chunk_series():
+    # thousands of small leaves and out-of-distribution queries: a workgroup
+    # of the LB_SAX filter takes several 256-item windows, and 64-point series
+    # are refined in one chunk each
+    x = G.random_walks(200_000, 64, coll=21)
+    q = G.ood_queries(64, 64, coll=21)
+    idx = make_index(x, w=8, leaf_size=16)
+    ids, d2, st = run_knn(idx, q, 10, stats=True)
+    check_knn(x, q, 10, ids, d2)
+    kept = st["leaves_kept"].cpu().numpy()
+    assert kept.sum() > 256 * 1024  # more items than one window per workgroup of a full grid
+    idx.close()
+
+
 def test_batch_composition_does_not_change_results():
     x, q = workload(20_000, 256, coll=8, per_level=5)
     idx = make_index(x, w=16, leaf_size=500)
