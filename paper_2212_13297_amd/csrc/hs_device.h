@@ -100,7 +100,9 @@ __device__ __forceinline__ void load_word(const uint8_t* __restrict__ wp, uint4 
 template <int M>
 __device__ __forceinline__ float row_xor(float v) {
     constexpr int ctrl = M == 1 ? 0xB1 : (M == 2 ? 0x4E : (M == 4 ? 0x141 : 0x140));
-    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), ctrl, 0xF, 0xF, false));
+    // (the patterns never read outside the row, so bound_ctrl does not change
+    // the value; set, it lets the move fuse into the consuming add)
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), ctrl, 0xF, 0xF, true));
 }
 
 __device__ __forceinline__ float chunk_partial(float4 q, float4 x) {

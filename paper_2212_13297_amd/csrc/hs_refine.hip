@@ -62,6 +62,10 @@ __device__ __forceinline__ Meta load_meta(const QueryWs& ws, long long c, long l
     return m;
 }
 
+__device__ __forceinline__ uint4 ring_entry(const Meta& m) {
+    return make_uint4((uint32_t)m.q, m.pos, __float_as_uint(__double2float_rd((double)m.lb / (1.0 + kSlack))), 0u);
+}
+
 // F: distance form.  NS: candidates in flight per 16-lane group.
 //
 // Every wavefront owns a contiguous range of the candidate list.  Each of its
@@ -84,7 +88,9 @@ template <int F, int NS>
 __global__ void __launch_bounds__(256) k_refine(IndexView ix, ScanParams sp, QueryWs ws) {
     constexpr int kRing = 128;
     __shared__ unsigned long long s_top[kTile / 64][HS_KMAX];
-    __shared__ uint4 s_ring[kTile / 64][kRing];  // (q, pos, lb bits, -) of candidate i at (i - cbeg) mod 128
+    // (q, pos, lbs, -) of candidate i at (i - cbeg) mod 128, lbs = LB_SAX / (1 + slack)
+    // rounded down: lbs > limit implies LB_SAX > limit (1 + slack), the skip test
+    __shared__ uint4 s_ring[kTile / 64][kRing];
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6, sub = t & 15, grp = (t >> 4) & 3;
     const int k = sp.k;
     const int nchunks = ix.stride / kChunk;
@@ -92,6 +98,7 @@ __global__ void __launch_bounds__(256) k_refine(IndexView ix, ScanParams sp, Que
     const long long gw = (long long)blockIdx.x * (kTile / 64) + wave, GW = (long long)gridDim.x * (kTile / 64);
     const long long cbeg = T * gw / GW, cend = T * (gw + 1) / GW;
     if (cbeg >= cend) return;
+    const int nrel = (int)(cend - cbeg);  // candidates of this wavefront (< 2^31)
     unsigned long long* top = s_top[wave];
     uint4* ring = s_ring[wave];
 
@@ -124,8 +131,8 @@ __global__ void __launch_bounds__(256) k_refine(IndexView ix, ScanParams sp, Que
     {
         const Meta a = load_meta(ws, mb + lane, cend, cur);
         const Meta b = load_meta(ws, mb + 64 + lane, cend, cur);
-        ring[lane] = make_uint4((uint32_t)a.q, a.pos, __float_as_uint(a.lb), 0u);
-        ring[64 + lane] = make_uint4((uint32_t)b.q, b.pos, __float_as_uint(b.lb), 0u);
+        ring[lane] = ring_entry(a);
+        ring[64 + lane] = ring_entry(b);
         bq = pq = __builtin_amdgcn_readfirstlane(a.q);
         bv = pv = bits_to_float(load_relaxed(&ws.bsf[max(bq, 0)]));
     }
@@ -163,8 +170,7 @@ __global__ void __launch_bounds__(256) k_refine(IndexView ix, ScanParams sp, Que
                 // written after this round's loads), the BSF_k read at the last
                 // move is taken over and the next one is issued
                 if (has_pend) {
-                    ring[((int)(mb + 64 - cbeg) & (kRing - 1)) + lane] =
-                        make_uint4((uint32_t)pend.q, pend.pos, __float_as_uint(pend.lb), 0u);
+                    ring[((int)(mb + 64 - cbeg) & (kRing - 1)) + lane] = ring_entry(pend);
                     has_pend = false;
                 }
                 mb += 64;
@@ -178,8 +184,7 @@ __global__ void __launch_bounds__(256) k_refine(IndexView ix, ScanParams sp, Que
             if (has_pend && next + 4 * NS > mb + 64) {
                 // this hand-out reaches the entries still in flight (after many
                 // skipped candidates): they are written now
-                ring[((int)(mb + 64 - cbeg) & (kRing - 1)) + lane] =
-                    make_uint4((uint32_t)pend.q, pend.pos, __float_as_uint(pend.lb), 0u);
+                ring[((int)(mb + 64 - cbeg) & (kRing - 1)) + lane] = ring_entry(pend);
                 has_pend = false;
             }
             int rank[NS], nf = 0;
@@ -192,15 +197,15 @@ __global__ void __launch_bounds__(256) k_refine(IndexView ix, ScanParams sp, Que
                       f2 = __builtin_amdgcn_readlane(nf, 32), f3 = __builtin_amdgcn_readlane(nf, 48);
             const int total = f0 + f1 + f2 + f3;
             if (total == 0) break;
-            const int goff = (grp > 0 ? f0 : 0) + (grp > 1 ? f1 : 0) + (grp > 2 ? f2 : 0);
+            const int goff = (int)(next - cbeg) + (grp > 0 ? f0 : 0) + (grp > 1 ? f1 : 0) + (grp > 2 ? f2 : 0);
             bool again = false;
 #pragma unroll
             for (int s = 0; s < NS; ++s) {
                 if (!__ballot(fin[s])) continue;
                 if (fin[s]) {
-                    const long long i = next + goff + rank[s];
-                    const uint4 e = ring[(int)(i - cbeg) & (kRing - 1)];
-                    const int q = i < cend ? (int)e.x : -1;
+                    const int ri = goff + rank[s];  // candidate cbeg + ri
+                    const uint4 e = ring[ri & (kRing - 1)];
+                    const int q = ri < nrel ? (int)e.x : -1;
                     float lim = q == bq ? bv : INFINITY;
                     if (q == cur_q) lim = fminf(lim, lk);
                     const uint32_t pos = q >= 0 ? e.y : 0u;
@@ -211,7 +216,7 @@ __global__ void __launch_bounds__(256) k_refine(IndexView ix, ScanParams sp, Que
                     sthr[s] = lim;
                     xp[s] = ix.rows + (int64_t)pos * ix.stride + sub * 4;
                     qp[s] = ws.qrow + (int64_t)max(q, 0) * ix.stride + sub * 4;
-                    fin[s] = q >= 0 && (double)__uint_as_float(e.z) > prune_limit(lim);  // skipped: ask again
+                    fin[s] = q >= 0 && __uint_as_float(e.z) > lim;  // skipped: ask again
                     again = again || fin[s];
                 }
             }
@@ -246,8 +251,7 @@ __global__ void __launch_bounds__(256) k_refine(IndexView ix, ScanParams sp, Que
             }
         }
         if (has_pend) {
-            ring[((int)(mb + 64 - cbeg) & (kRing - 1)) + lane] =
-                make_uint4((uint32_t)pend.q, pend.pos, __float_as_uint(pend.lb), 0u);
+            ring[((int)(mb + 64 - cbeg) & (kRing - 1)) + lane] = ring_entry(pend);
             has_pend = false;
         }
 
