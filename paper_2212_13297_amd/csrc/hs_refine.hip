@@ -109,19 +109,22 @@ __global__ void __launch_bounds__(256) k_refine(IndexView ix, ScanParams sp, Que
     float pub = INFINITY;                             // lane 0: k-th distance last published for cur_q
     // refined series and chunks read for query st_q (uniform), per group
     int st_q = -1;
-    uint32_t g_ref = 0u, g_ch = 0u;
+    uint32_t g_ref = 0u;  // < 2^31 candidates per wavefront
+    unsigned long long g_ch = 0ull;
     auto flush_counters = [&]() {
-        uint32_t r = 0u, c = 0u;
+        unsigned long long r = 0ull, c = 0ull;
 #pragma unroll
         for (int g = 0; g < 4; ++g) {
             r += (uint32_t)__builtin_amdgcn_readlane(g_ref, 16 * g);
-            c += (uint32_t)__builtin_amdgcn_readlane(g_ch, 16 * g);
+            c += ((unsigned long long)(uint32_t)__builtin_amdgcn_readlane((uint32_t)(g_ch >> 32), 16 * g) << 32) |
+                 (uint32_t)__builtin_amdgcn_readlane((uint32_t)g_ch, 16 * g);
         }
         if (lane == 0 && st_q >= 0 && r) {
-            atomicAdd(&ws.stats[(int64_t)st_q * 8 + 2], (unsigned long long)r);
-            atomicAdd(&ws.stats[(int64_t)st_q * 8 + 3], (unsigned long long)c);
+            atomicAdd(&ws.stats[(int64_t)st_q * 8 + 2], r);
+            atomicAdd(&ws.stats[(int64_t)st_q * 8 + 3], c);
         }
-        g_ref = g_ch = 0u;
+        g_ref = 0u;
+        g_ch = 0ull;
     };
 
     SliceCursor cur;
@@ -261,7 +264,7 @@ __global__ void __launch_bounds__(256) k_refine(IndexView ix, ScanParams sp, Que
             for (int s = 0; s < NS; ++s)
                 if (fin[s]) {
                     g_ref += 1u;
-                    g_ch += (uint32_t)sc[s];
+                    g_ch += (unsigned long long)sc[s];
                 }
             continue;
         }
@@ -280,7 +283,7 @@ __global__ void __launch_bounds__(256) k_refine(IndexView ix, ScanParams sp, Que
                 }
                 if (grp == g) {
                     g_ref += 1u;
-                    g_ch += (uint32_t)sc[s];
+                    g_ch += (unsigned long long)sc[s];
                 }
                 if (__builtin_amdgcn_readlane((int)adm[s], 16 * g)) {
                     const float v = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(sd[s].value()), 16 * g));
