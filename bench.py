@@ -120,11 +120,16 @@ def run_mixed(args, hs, torch, idx, qt, Q, plain_ids, plain_stats):
         # algorithmic work of the bounding pass: one q~.x~ (2K flop) per bounded
         # (query, series) pair; the low-precision rows and norms it must read once
         flops = 2.0 * K * float(stats["rows_filtered"].sum()) / (bl / args.steps)
+        # what the matrix cores computed: every (query, series) pair of the
+        # tiles each wavefront of 32 queries took (padding queries not counted)
+        xflops = 2.0 * K * float(stats["chunks_tested"].sum()) / (bl / args.steps)
         kern["bound"] = {"avg_launch_ms": round(avg, 4), "launches_per_step": bl / args.steps,
                          "flops_per_launch": int(flops),
                          "TFLOP_s": round(flops / (avg / 1e3) / 1e12, 2),
-                         "shadow_bytes": int(info.n_series * (2 * K + 8)),
-                         "shadow_GB_s": round(info.n_series * (2 * K + 8) / (avg / 1e3) / 1e9, 2)}
+                         "executed_flops_per_launch": int(xflops),
+                         "executed_TFLOP_s": round(xflops / (avg / 1e3) / 1e12, 2),
+                         "shadow_bytes": int(info.n_series * (2 * K + 16)),
+                         "shadow_GB_s": round(info.n_series * (2 * K + 16) / (avg / 1e3) / 1e9, 2)}
     rms, rl = prof["refine"]
     if rl:
         avg = rms / rl
@@ -139,6 +144,7 @@ def run_mixed(args, hs, torch, idx, qt, Q, plain_ids, plain_stats):
            "kernels": kern,
            "roofline": ({"bound": "mfma", "achieved": kern["bound"]["TFLOP_s"], "peak": MFMA_PEAK_TFLOPS["bf16"],
                          "unit": "TFLOP/s", "frac": round(kern["bound"]["TFLOP_s"] / MFMA_PEAK_TFLOPS["bf16"], 4),
+                         "executed_frac": round(kern["bound"]["executed_TFLOP_s"] / MFMA_PEAK_TFLOPS["bf16"], 4),
                          "kernel": "k_bound", "traffic": traffic.get("bytes_per_launch") if traffic else None,
                          "traffic_detail": traffic} if "bound" in kern else None),
            "pruning": {"rows_bounded_mean": float(stats["rows_filtered"].mean()),
@@ -335,6 +341,10 @@ def main():
     build_s = time.time() - t0
     info = idx.info
     log(f"built index in {build_s:.1f}s: {info.n_leaves} leaves, max leaf {info.max_leaf}")
+    # an achievable read-stream rate on this GPU, beside the nominal peak: the
+    # library's read probe over the input (5 passes)
+    read_gbs = hs.read_probe_gbs(xt, passes=5)
+    log(f"read stream (probe over {xt.numel() * 4 / 1e9:.2f} GB): {read_gbs:.0f} GB/s")
     del xt
     torch.cuda.empty_cache()
 
@@ -468,6 +478,8 @@ def main():
                        "queries": int(nl)},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "achievable_read_GB_s": round(read_gbs, 1),
+                     "frac_of_achievable": round(achieved / read_gbs, 4),
                      "traffic": traffic.get("bytes_per_launch") if traffic else None,
                      "traffic_detail": traffic,
                      "kernel": f"k_{dom}" if dom else None, **(kern.get(dom, {}))},

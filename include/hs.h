@@ -155,7 +155,9 @@ typedef struct {
     uint64_t path;            /* 0 = LB_SAX path, 1 = skip-sequential (no LB_SAX) */
     uint64_t rounds;          /* refinement rounds (1 unless the candidate pool overflowed) */
     uint64_t candidates;      /* LB_SAX survivors put on the candidate list (two-stage path) */
-    uint64_t chunks_tested;   /* 64-series chunk envelopes whose LB_EAPCA was evaluated */
+    uint64_t chunks_tested;   /* 64-series chunk envelopes whose LB_EAPCA was evaluated; precision
+                                 form: series whose dot product with this query the matrix cores
+                                 computed (every series of a tile its wavefront of 32 queries took) */
 } hs_query_stats;
 
 /*
@@ -335,6 +337,17 @@ hs_status hs_profile_enable(int32_t on);
 /* Accumulated milliseconds and launch count of one kind; cleared if reset.
  * Errors: HS_EINVAL for an unknown kind. */
 hs_status hs_profile_read(int32_t kind, double* ms, int64_t* launches, int32_t reset);
+
+/* Diagnostics: the device's achievable read-stream rate, reported beside
+ * the nominal HBM peak.  Reads the first `bytes` of device memory buf_dev
+ * (a multiple of 16, at least 1 MiB; contents do not matter, only read)
+ * once to warm up and then `passes` times, each pass a grid of 8 workgroups
+ * per compute unit reading 16-byte units; *ms = event-timed milliseconds of
+ * the timed passes.  sink_dev: 4 caller-owned device bytes that the probe may
+ * write (it practically never does).  Synchronises the stream.
+ * Errors: HS_EINVAL (NULL, bytes or passes out of range), HS_EHIP. */
+hs_status hs_read_probe(const void* buf_dev, int64_t bytes, int32_t passes, uint32_t* sink_dev, void* stream,
+                        double* ms);
 
 /* Release the host handle (does not free index_mem_dev). NULL is allowed. */
 hs_status hs_index_free(hs_index* idx);

@@ -728,6 +728,32 @@ hs_status hs_profile_read(int32_t kind, double* ms, int64_t* launches, int32_t r
     return HS_OK;
 }
 
+hs_status hs_read_probe(const void* buf_dev, int64_t bytes, int32_t passes, uint32_t* sink_dev, void* stream,
+                        double* ms) {
+    if (!buf_dev || !sink_dev || !ms) return fail(HS_EINVAL, "NULL argument");
+    if (bytes < (1 << 20) || bytes % 16 || passes < 1)
+        return fail(HS_EINVAL, "bytes=%lld (a multiple of 16, at least 1 MiB), passes=%d (>= 1)", (long long)bytes, passes);
+    hipStream_t st = (hipStream_t)stream;
+    int device = 0, cus = 0;
+    HIP_TRY(hipGetDevice(&device));
+    HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device));
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    hipError_t e = hipEventCreate(&e0);
+    if (e == hipSuccess) e = hipEventCreate(&e1);
+    if (e == hipSuccess) e = launch_read_probe(buf_dev, bytes, sink_dev, cus, st);  // warm-up pass
+    if (e == hipSuccess) e = hipEventRecord(e0, st);
+    for (int32_t i = 0; i < passes && e == hipSuccess; ++i) e = launch_read_probe(buf_dev, bytes, sink_dev, cus, st);
+    if (e == hipSuccess) e = hipEventRecord(e1, st);
+    if (e == hipSuccess) e = hipEventSynchronize(e1);
+    float t = 0.0f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&t, e0, e1);
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    if (e != hipSuccess) return fail(HS_EHIP, "read probe: %s", hipGetErrorString(e));
+    *ms = (double)t;
+    return HS_OK;
+}
+
 hs_status hs_index_free(hs_index* idx) {
     if (!idx) return HS_OK;
     free_owned(idx);

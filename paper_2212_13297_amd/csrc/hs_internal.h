@@ -131,6 +131,7 @@ hipError_t launch_series_stats(const float* x, int64_t N, int32_t n, int32_t w, 
 hipError_t launch_gather_rows(const float* x, const uint32_t* perm, int64_t N, int32_t n, int32_t stride,
                               float* rows, hipStream_t st);
 hipError_t launch_words(const IndexView& ix, uint8_t* words, hipStream_t st);
+hipError_t launch_read_probe(const void* buf, int64_t bytes, uint32_t* sink, int device_cus, hipStream_t st);
 hipError_t launch_envelopes(const IndexView& ix, const int64_t* starts, int64_t count, float4* env,
                             hipStream_t st);
 

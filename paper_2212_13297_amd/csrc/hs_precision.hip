@@ -299,7 +299,7 @@ __global__ void __launch_bounds__(256) k_bound(IndexView ix, ShadowView sv, Scan
                 for (int u = 0; u < kKSteps; ++u)
                     bq[u] = u * 16 < K ? *reinterpret_cast<const uint4*>(qlow + u * 16) : make_uint4(0, 0, 0, 0);
             }
-            unsigned long long tested = 0, cands = 0;
+            unsigned long long tested = 0, cands = 0, staged = 0;  // staged: pairs the matrix cores evaluated
             bool lost = false;
 
             for (int64_t p = p_first; p < ix.parts && ix.part_start[p] < row1; ++p) {
@@ -380,7 +380,10 @@ __global__ void __launch_bounds__(256) k_bound(IndexView ix, ShadowView sv, Scan
                         if (wkeep) {
                             const int64_t tr0 = ps + tile * kBoundRows;
                             const int nrows = (int)min((int64_t)kBoundRows, pe - tr0);
-                            if (keep && half == 0) tested += (unsigned long long)nrows;
+                            if (half == 0) {
+                                staged += (unsigned long long)nrows;
+                                if (keep) tested += (unsigned long long)nrows;
+                            }
                             const float2* nrm = s_norm[tile & 1];
                             const float* xnr = s_xn[tile & 1];
                             // common path: 3 operations per pair, one test per lane
@@ -488,6 +491,7 @@ __global__ void __launch_bounds__(256) k_bound(IndexView ix, ShadowView sv, Scan
             if (half == 0 && qvalid) {
                 if (tested) atomicAdd(&ws.stats[(int64_t)qj * 8 + 1], tested);
                 if (cands) atomicAdd(&ws.stats[(int64_t)qj * 8 + 6], cands);
+                if (staged) atomicAdd(&ws.stats[(int64_t)qj * 8 + 7], staged);
             }
             if (lost) atomicOr(&ws.flags[qj], kFlagCandLost);
         }

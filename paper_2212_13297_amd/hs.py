@@ -98,6 +98,7 @@ _SIGS = {
     "hs_profile_enable": (ctypes.c_int32, [ctypes.c_int32]),
     "hs_profile_read": (ctypes.c_int32, [ctypes.c_int32, ctypes.POINTER(ctypes.c_double),
                                          ctypes.POINTER(ctypes.c_int64), ctypes.c_int32]),
+    "hs_read_probe": (ctypes.c_int32, [_P, ctypes.c_int64, ctypes.c_int32, _P, _P, ctypes.POINTER(ctypes.c_double)]),
 }
 
 _LIB = None
@@ -300,6 +301,21 @@ def hs_profile_read(kind: int, reset: bool = False):
     n = ctypes.c_int64()
     _check(load().hs_profile_read(kind, ctypes.byref(ms), ctypes.byref(n), 1 if reset else 0))
     return ms.value, n.value
+
+
+def hs_read_probe(buf_dev: int, nbytes: int, passes: int, sink_dev: int, stream: int) -> float:
+    ms = ctypes.c_double()
+    _check(load().hs_read_probe(buf_dev, nbytes, passes, sink_dev, stream, ctypes.byref(ms)))
+    return ms.value
+
+
+def read_probe_gbs(buf, passes: int = 5, stream=None) -> float:
+    """Achievable read-stream rate (GB/s) over the device tensor buf."""
+    import torch
+    nbytes = (buf.numel() * buf.element_size()) // 16 * 16
+    sink = torch.zeros(1, dtype=torch.int32, device=buf.device)
+    ms = hs_read_probe(buf.data_ptr(), nbytes, passes, sink.data_ptr(), _stream_ptr(stream))
+    return nbytes * passes / (ms / 1e3) / 1e9
 
 
 def profile_read_all(reset: bool = False):

@@ -56,3 +56,16 @@ def test_index_bytes_and_param_validation():
         with pytest.raises(hs.HSError):
             hs.hs_index_bytes(badN, p)
     assert "N=" in hs.hs_last_error()
+
+
+def test_read_probe_rejects_bad_arguments():
+    import ctypes
+    from paper_2212_13297_amd import hs
+    lib = hs.load()
+    ms = ctypes.c_double()
+    sink = ctypes.c_uint32()
+    # argument errors are reported before any device call
+    assert lib.hs_read_probe(None, 1 << 20, 1, ctypes.addressof(sink), None, ctypes.byref(ms)) == -1
+    assert lib.hs_read_probe(ctypes.addressof(sink), 1 << 20, 1, None, None, ctypes.byref(ms)) == -1
+    assert lib.hs_read_probe(ctypes.addressof(sink), 1000, 1, ctypes.addressof(sink), None, ctypes.byref(ms)) == -1
+    assert lib.hs_read_probe(ctypes.addressof(sink), 1 << 20, 0, ctypes.addressof(sink), None, ctypes.byref(ms)) == -1

@@ -275,3 +275,13 @@ def test_errors():
     a, b = run_knn(idx, x[:2], 3)
     check_knn(x, x[:2], 3, a, b)
     idx.close()
+
+
+def test_read_probe_reads_without_writing():
+    hs = hs_mod()
+    buf = torch.arange(1 << 22, dtype=torch.int32, device=DEV)  # 16 MiB
+    before = buf.clone()
+    gbs = hs.read_probe_gbs(buf, passes=3)
+    torch.cuda.synchronize()
+    assert 10.0 < gbs < 20000.0
+    assert torch.equal(buf, before)
