@@ -195,14 +195,39 @@ __global__ void __launch_bounds__(256) k_seed(IndexView ix, ScanParams sp, Query
         }
     }
     const int M = s_cnt;
-    // refine the list
-    for (int i = grp; i < M; i += kTile / 16) {
-        const int64_t pos = s_list[i];
-        bool alive;
-        unsigned ch = 0;
-        const float d = refine_row<F>(ix.rows + pos * ix.stride + sub * 4, ws.qrow + (int64_t)q * ix.stride + sub * 4,
-                                      nchunks, INFINITY, alive, ch);
-        if (sub == 0) s_keys[i] = ((unsigned long long)__float_as_uint(d) << 32) | ix.ids[pos];
+    // refine the list: a group takes kSeedRows rows at a time and loads their
+    // chunks (kSeedChunks per row) together; each row adds its chunks in
+    // chunk order, as everywhere
+    constexpr int kSeedRows = 4, kSeedChunks = 4;
+    const float* qr = ws.qrow + (int64_t)q * ix.stride + sub * 4;
+    for (int i0 = grp * kSeedRows; i0 < M; i0 += (kTile / 16) * kSeedRows) {
+        int64_t pos[kSeedRows];
+#pragma unroll
+        for (int r = 0; r < kSeedRows; ++r) pos[r] = s_list[min(i0 + r, M - 1)];
+        Dist<F> d[kSeedRows];
+        for (int c = 0; c < nchunks; c += kSeedChunks) {
+            float4 qa[kSeedChunks], xa[kSeedRows][kSeedChunks];
+#pragma unroll
+            for (int b = 0; b < kSeedChunks; ++b)
+                qa[b] = c + b < nchunks ? *reinterpret_cast<const float4*>(qr + (c + b) * kChunk)
+                                        : make_float4(0.f, 0.f, 0.f, 0.f);
+#pragma unroll
+            for (int r = 0; r < kSeedRows; ++r)
+#pragma unroll
+                for (int b = 0; b < kSeedChunks; ++b)
+                    xa[r][b] = c + b < nchunks
+                                   ? *reinterpret_cast<const float4*>(ix.rows + pos[r] * ix.stride + sub * 4 + (c + b) * kChunk)
+                                   : make_float4(0.f, 0.f, 0.f, 0.f);
+#pragma unroll
+            for (int r = 0; r < kSeedRows; ++r)
+#pragma unroll
+                for (int b = 0; b < kSeedChunks; ++b)
+                    if (c + b < nchunks) d[r].add(qa[b], xa[r][b]);
+        }
+#pragma unroll
+        for (int r = 0; r < kSeedRows; ++r)
+            if (i0 + r < M && sub == 0)
+                s_keys[i0 + r] = ((unsigned long long)__float_as_uint(d[r].value()) << 32) | ix.ids[pos[r]];
     }
     int Mp = 1;
     while (Mp < M) Mp <<= 1;
