@@ -137,11 +137,21 @@ __global__ void __launch_bounds__(256) k_seed(IndexView ix, ScanParams sp, Query
     for (int li = 0; li < lm; ++li) {
         const int64_t b = ix.leaf_start[s_leaves[li]], e = ix.leaf_start[s_leaves[li] + 1];
         rows += e - b;
-        for (int64_t r = b + t; r < e; r += blockDim.x) {
-            uint4 v[W16];
-            load_word<W16>(ix.words + r * ix.wstride, v);
-            const float lb = lb_sax_word<W16>(v, s_lut);
-            atomicAdd(&s_hist[min(__float_as_uint(lb) >> 20, 2047u)], 1u);
+        // 8 rows per thread per pass, their word loads in flight together
+        for (int64_t tb = b; tb < e; tb += 8 * (int64_t)blockDim.x) {
+            uint4 v[8][W16];
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                const int64_t r = min(tb + t + (int64_t)blockDim.x * j, e - 1);
+                load_word<W16>(ix.words + r * ix.wstride, v[j]);
+            }
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                if (tb + t + (int64_t)blockDim.x * j < e) {
+                    const float lb = lb_sax_word<W16>(v[j], s_lut);
+                    atomicAdd(&s_hist[min(__float_as_uint(lb) >> 20, 2047u)], 1u);
+                }
+            }
         }
     }
     __syncthreads();
