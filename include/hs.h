@@ -206,8 +206,12 @@ hs_status hs_shadow_bytes(const hs_index* idx, int32_t kind, int64_t* bytes);
  * hs_build_shadow).  Per series it stores x~ in leaf order and four floats:
  * beta (the series' term of the bounding pass's float32 test, computed in
  * float64 from the next two, rounded down), ||x - x~||_2 (float64, stored
- * rounded up), ||x~||^2 (float64, stored rounded down) and 0.  Synchronises
- * the stream.  An index holds one copy; a new
+ * rounded up), ||x~||^2 (float64, stored rounded down) and, for series of
+ * at most 256 points, the augmented unit: two low-precision values (a* in the
+ * low 16 bits, ebar >= ||x - x~||_2 in the high 16 bits) that the bounding
+ * pass's extra matrix-core step adds, a* covering -(||x~||^2 - eps^2)/2 plus
+ * the series' share of the accumulation error bound.  Synchronises the
+ * stream.  An index holds one copy; a new
  * call replaces it.
  * Errors: HS_EINVAL (NULL, unknown kind, a value beyond the fp16 range for
  * HS_SHADOW_FP16), HS_ENOMEM (shadow_bytes too small), HS_EHIP. */

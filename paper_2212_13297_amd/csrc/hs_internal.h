@@ -59,8 +59,9 @@ constexpr int kBoundRows = 32;      // series per tile of the bounding pass
 
 struct ShadowView {
     const uint16_t* rows;  // [N + kBoundRows][stride] bf16 / fp16 bits of the stored series, zero padded
-    const float4* norms;   // [N + kBoundRows] (beta, ||x - x~||_2 rounded up, ||x~||^2 rounded down, 0), float32;
-                           // beta = ((1 - g) ||x~||^2 - eps^2) / 2 - 3u (||x~||^2 + eps^2), float64, rounded down
+    const float4* norms;   // [N + kBoundRows] (beta, ||x - x~||_2 rounded up, ||x~||^2 rounded down, aug), float32;
+                           // beta = ((1 - g) ||x~||^2 - eps^2) / 2 - 3u (||x~||^2 + eps^2), float64, rounded down;
+                           // aug: bits of the augmented unit (a*, ebar) as two low-precision values
     int32_t kind;          // kShadowBf16 / kShadowF16
 };
 

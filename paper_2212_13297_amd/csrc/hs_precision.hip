@@ -40,6 +40,11 @@ struct Low<kShadowBf16> {
         return (uint16_t)((b + 0x7fffu + ((b >> 16) & 1u)) >> 16);
     }
     static __device__ __forceinline__ float decode(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
+    // the smallest bf16 value >= v (finite v; truncation moves a negative value up)
+    static __device__ __forceinline__ uint16_t encode_up(float v) {
+        const uint32_t b = __float_as_uint(v);
+        return (uint16_t)((b >> 16) + (((b & 0xffffu) != 0u && !(b >> 31)) ? 1u : 0u));
+    }
     static __device__ __forceinline__ bool representable(float) { return true; }
     static __device__ __forceinline__ f32x16 mma(uint4 a, uint4 b, f32x16 c) {
         return __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(v8, a), __builtin_bit_cast(v8, b), c, 0, 0,
@@ -52,6 +57,12 @@ struct Low<kShadowF16> {
     typedef __attribute__((__vector_size__(8 * sizeof(_Float16)))) _Float16 v8;
     static __device__ __forceinline__ uint16_t encode(float v) { return __builtin_bit_cast(uint16_t, (_Float16)v); }
     static __device__ __forceinline__ float decode(uint16_t h) { return (float)__builtin_bit_cast(_Float16, h); }
+    // the smallest fp16 value >= v (finite v; +inf past the range)
+    static __device__ __forceinline__ uint16_t encode_up(float v) {
+        uint16_t h = encode(v);
+        if (decode(h) < v) h = h == 0x8000u ? (uint16_t)1u : (h & 0x8000u ? (uint16_t)(h - 1u) : (uint16_t)(h + 1u));
+        return h;
+    }
     static __device__ __forceinline__ bool representable(float v) { return fabsf(v) <= 65504.0f; }
     static __device__ __forceinline__ f32x16 mma(uint4 a, uint4 b, f32x16 c) {
         return __builtin_amdgcn_mfma_f32_32x32x16_f16(__builtin_bit_cast(v8, a), __builtin_bit_cast(v8, b), c, 0, 0,
@@ -63,13 +74,35 @@ struct Low<kShadowF16> {
 struct BoundConsts {
     double g;   // accumulation factor g (plus 2^-40 for the float64 norms)
     double m;   // margin factor 3u of the folded constants (u = 2^-24)
+    double g2;  // accumulation factor of K + 2 products (the augmented step, series of <= 256 points)
 };
 
 // The constants for series of stride K: g for K float32 additions at twice the
-// unit roundoff (plus 2^-40 for the float64 norms), m = 3u.
+// unit roundoff (plus 2^-40 for the float64 norms), m = 3u, g2 for K + 2.
 BoundConsts bound_consts(int K) {
-    const double u2 = std::ldexp(1.0, -23), Kd = (double)K;
-    return BoundConsts{Kd * u2 / (1.0 - Kd * u2) + std::ldexp(1.0, -40), 3.0 * std::ldexp(1.0, -24)};
+    const double u2 = std::ldexp(1.0, -23), Kd = (double)K, K2 = Kd + 2.0;
+    return BoundConsts{Kd * u2 / (1.0 - Kd * u2) + std::ldexp(1.0, -40), 3.0 * std::ldexp(1.0, -24),
+                       K2 * u2 / (1.0 - K2 * u2) + std::ldexp(1.0, -40)};
+}
+
+// The augmented unit of a series for the bounding pass of series of at most
+// 256 points.  The matrix cores add a* x 1 + ebar x sTbar to q~.x~, with
+// ebar >= eps_x and sTbar >= sT rounded up to the low precision, and
+// a* >= -B0 + g2 R, B0 = (||x~||^2 - eps_x^2) / 2 (from the stored values,
+// so at most the true one) and R >= ||x~||^2 / 2 + |a*| + ebar^2 / 2 the
+// series' share of the accumulation error bound of the K + 2 products.
+// Returned as the two low-precision bit patterns (a* low half, ebar high).
+template <int KIND>
+__device__ __forceinline__ uint32_t augmented_unit(float xn, float eps, const BoundConsts& bc) {
+    const uint16_t eb = Low<KIND>::encode_up(eps);
+    const double ebar = (double)Low<KIND>::decode(eb), xd = xn;
+    const double B0 = 0.5 * (xd - (double)eps * (double)eps);
+    // |a*| <= |B0| + g2 R_0 before rounding; twice that covers the rounding
+    const double R = 0.5 * xd * (1.0 + 0x1p-38) + 2.0 * (fabs(B0) + bc.g2 * (xd + 2.0 * fabs(B0) + ebar * ebar)) +
+                     0.5 * ebar * ebar;
+    const double v = -B0 + bc.g2 * R;
+    const float av = __double2float_ru(v + fabs(v) * 0x1p-20 + 1e-30);  // >= v whatever its sign
+    return (uint32_t)Low<KIND>::encode_up(av) | ((uint32_t)eb << 16);
 }
 
 // beta_x of the float32 test from the stored ||x~||^2 and eps_x (float64,
@@ -113,7 +146,7 @@ __global__ void __launch_bounds__(256) k_shadow(IndexView ix, uint16_t* __restri
         if (lane == 0) {
             const float xn = __double2float_rd(s2 * (1.0 - 0x1p-40));
             const float eps = __double2float_ru(sqrt(e2) * (1.0 + 0x1p-40));
-            norms[r] = make_float4(beta_of(xn, eps, bc), eps, xn, 0.0f);
+            norms[r] = make_float4(beta_of(xn, eps, bc), eps, xn, __uint_as_float(augmented_unit<KIND>(xn, eps, bc)));
         }
     }
 }
@@ -237,6 +270,16 @@ __device__ __forceinline__ void bound_block(const BoundMap& m, int b, int& g0, i
 // the exact condition.  A lane first takes the largest e of its 16 pairs
 // (3 operations per pair); only when it reaches alpha are the pairs tested
 // one by one and decided in float64.
+//
+// Series of at most 256 points (ONE) fold the series' terms into the matrix
+// cores: one more step adds a* x 1 + ebar x sTbar (the augmented unit), so
+// acc >= q~.x~ + a* + eps_x sT up to the error of K + 2 products, at most
+// g2 (Q_q + R_x) with Q_q = ||q~||^2 / 2 (1 + 2^-38) + sTbar^2 / 2 in alpha and
+// R_x in a*.  Then acc < alpha with
+//   alpha_q = (||q~||^2 - sT^2) / 2 - g2 Q_q - 2^-40 (||q~||^2 + sT^2)
+// implies the exact condition, and the per-lane test is a max over the 16
+// accumulators.  The float64 decision subtracts a* and ebar sTbar again and
+// takes the accumulation bound g2 S of the K + 2 products.
 template <int KIND, bool ONE>
 __global__ void __launch_bounds__(256) k_bound(IndexView ix, ShadowView sv, ScanParams sp, QueryWs ws,
                                                BoundConsts bc, BoundMap bm) {
@@ -244,6 +287,7 @@ __global__ void __launch_bounds__(256) k_bound(IndexView ix, ShadowView sv, Scan
     __shared__ __attribute__((aligned(16))) uint16_t s_tile[2][kBoundRows * kLdsRow];
     __shared__ float2 s_norm[2][kBoundRows];  // (beta', eps_x) per staged series
     __shared__ float s_xn[2][kBoundRows];     // ||x~||^2 per staged series
+    __shared__ float2 s_aug[2][kBoundRows];   // ONE: (a*, ebar) per staged series, decoded
     __shared__ float s_acc[kTile / 64][16 * 64];  // per wavefront: its accumulators, on the rare float64 path
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6, j = lane & 31, half = lane >> 5;
     // ONE: the series fit one K-block (stride <= 256) and the query fragments stay in registers
@@ -281,7 +325,8 @@ __global__ void __launch_bounds__(256) k_bound(IndexView ix, ShadowView sv, Scan
             const int qo = ws.qorder[pos];
             const bool qvalid = qo >= 0 && !(ws.flags[qo] & kFlagNonFinite);
             const int qj = qo >= 0 ? qo : pos;  // padded positions read a zero row of the query copy
-            float alpha = -3.0e38f, sT = 0.0f, bsf_j = 0.0f;
+            float alpha = -3.0e38f, sT = 0.0f, sTb = 0.0f, bsf_j = 0.0f;
+            uint4 bq_aug = make_uint4(0, 0, 0, 0);  // ONE: (1, sTbar) at k = 256, 257 (half 0)
             if (qvalid) {
                 const double2 qn = ws.qnorm[qj];
                 bsf_j = bits_to_float(ws.bsf[qj]);
@@ -289,7 +334,19 @@ __global__ void __launch_bounds__(256) k_bound(IndexView ix, ShadowView sv, Scan
                 if (T < 1e300) {  // no BSF_k yet: every pair passes the float32 test
                     sT = __double2float_ru((sqrt(T) + qn.y) * (1.0 + 0x1p-40));
                     const double s2 = (double)sT * (double)sT;
-                    alpha = __double2float_rd(0.5 * ((1.0 - bc.g) * qn.x - s2) - bc.m * (qn.x + s2));
+                    if (ONE) {
+                        // acc = q~.x~ + a* + ebar sTbar (K + 2 products); the
+                        // query's share of their error bound lowers alpha
+                        const uint16_t sb = Low<KIND>::encode_up(sT);
+                        sTb = Low<KIND>::decode(sb);
+                        const double Qs = 0.5 * qn.x * (1.0 + 0x1p-38) + 0.5 * (double)sTb * (double)sTb;
+                        alpha = __double2float_rd(0.5 * (qn.x - s2) - bc.g2 * Qs - 0x1p-40 * (qn.x + s2));
+                        bq_aug.x = half == 0 ? ((uint32_t)Low<KIND>::encode(1.0f) | ((uint32_t)sb << 16)) : 0u;
+                    } else {
+                        alpha = __double2float_rd(0.5 * ((1.0 - bc.g) * qn.x - s2) - bc.m * (qn.x + s2));
+                    }
+                } else if (ONE) {
+                    bq_aug.x = half == 0 ? (uint32_t)Low<KIND>::encode(1.0f) : 0u;
                 }
             }
             const uint16_t* qlow = ws.qlow + (int64_t)qj * K + 8 * half;
@@ -344,6 +401,13 @@ __global__ void __launch_bounds__(256) k_bound(IndexView ix, ShadowView sv, Scan
                     if (kb == 0 && t < kBoundRows) {
                         s_norm[(s / nkb) & 1][t] = make_float2(pn.x, pn.y);
                         s_xn[(s / nkb) & 1][t] = pn.z;
+                        if (ONE) {
+                            // the series' augmented unit in its row's padding: (a*, ebar, 0, ...)
+                            const uint32_t au = __float_as_uint(pn.w);
+                            *reinterpret_cast<uint4*>(dst + t * kLdsRow + kKBlock) = make_uint4(au, 0u, 0u, 0u);
+                            s_aug[(s / nkb) & 1][t] = make_float2(Low<KIND>::decode((uint16_t)(au & 0xffffu)),
+                                                                  Low<KIND>::decode((uint16_t)(au >> 16)));
+                        }
                     }
                 };
                 stage_load(0, pa, na);
@@ -375,6 +439,12 @@ __global__ void __launch_bounds__(256) k_bound(IndexView ix, ShadowView sv, Scan
                             for (int v = 0; v < 4; ++v) acc = Low<KIND>::mma(a[v], bq[u0 + v], acc);
                             __builtin_amdgcn_sched_barrier(0);
                         }
+                        if (ONE) {
+                            // the augmented step: k = 256 .. 271, only (a*, ebar) x (1, sTbar) nonzero
+                            const uint4 aa = half == 0 ? *reinterpret_cast<const uint4*>(arow + kKBlock)
+                                                       : make_uint4(0, 0, 0, 0);
+                            acc = Low<KIND>::mma(aa, bq_aug, acc);
+                        }
                     }
                     if (kb == nkb - 1) {
                         if (wkeep) {
@@ -386,12 +456,19 @@ __global__ void __launch_bounds__(256) k_bound(IndexView ix, ShadowView sv, Scan
                             }
                             const float2* nrm = s_norm[tile & 1];
                             const float* xnr = s_xn[tile & 1];
-                            // common path: 3 operations per pair, one test per lane
+                            const float2* aug = s_aug[tile & 1];
+                            // common path: one test per lane; ONE: the accumulators
+                            // already hold acc - beta + sT eps_x, a max suffices;
+                            // otherwise 3 operations per pair
                             float mx = -INFINITY;
 #pragma unroll
                             for (int r = 0; r < 16; ++r) {
-                                const float2 nm = nrm[8 * (r >> 2) + 4 * half + (r & 3)];
-                                mx = fmaxf(mx, fmaf(sT, nm.y, acc[r] - nm.x));
+                                if (ONE) {
+                                    mx = fmaxf(mx, acc[r]);
+                                } else {
+                                    const float2 nm = nrm[8 * (r >> 2) + 4 * half + (r & 3)];
+                                    mx = fmaxf(mx, fmaf(sT, nm.y, acc[r] - nm.x));
+                                }
                             }
                             const bool any = keep && mx >= alpha;
                             uint32_t mask = 0;
@@ -401,7 +478,8 @@ __global__ void __launch_bounds__(256) k_bound(IndexView ix, ShadowView sv, Scan
                                 for (int r = 0; r < 16; ++r) {
                                     const int i = 8 * (r >> 2) + 4 * half + (r & 3);
                                     const float2 nm = nrm[i];
-                                    if (fmaf(sT, nm.y, acc[r] - nm.x) >= alpha && i < nrows) mask |= 1u << r;
+                                    const float e = ONE ? acc[r] : fmaf(sT, nm.y, acc[r] - nm.x);
+                                    if (e >= alpha && i < nrows) mask |= 1u << r;
                                 }
                                 if (!keep) mask = 0;
                             }
@@ -415,12 +493,21 @@ __global__ void __launch_bounds__(256) k_bound(IndexView ix, ShadowView sv, Scan
                                 double2 qn = make_double2(0.0, 0.0);
                                 if (mask) qn = ws.qnorm[qj];
                                 const double lim = prune_limit(bsf_j);
+                                // lower bound of d(q~, x~) for the pair of accumulator r, row i
+                                auto pair_d = [&](int r, int i) -> double {
+                                    const double ac = (double)sacc[r * 64 + lane];
+                                    if (!ONE) return (1.0 - bc.g) * (qn.x + (double)xnr[i]) - 2.0 * ac;
+                                    // q~.x~ <= acc - a* - ebar sTbar + g2 S (the K + 2 products)
+                                    const double a = aug[i].x, eb = aug[i].y, es = eb * (double)sTb;
+                                    const double S = 0.5 * (qn.x + (double)xnr[i]) * (1.0 + 0x1p-38) + fabs(a) + es;
+                                    return qn.x + (double)xnr[i] - 2.0 * (ac - a - es + bc.g2 * S);
+                                };
                                 uint32_t fm = 0;
                                 for (int r = 0; r < 16; ++r) {
                                     if (!((mask >> r) & 1u)) continue;
                                     const int i = 8 * (r >> 2) + 4 * half + (r & 3);
                                     const float2 nm = nrm[i];
-                                    const double D = (1.0 - bc.g) * (qn.x + (double)xnr[i]) - 2.0 * (double)sacc[r * 64 + lane];
+                                    const double D = pair_d(r, i);
                                     const double lr = fmax(sqrt(fmax(D, 0.0)) - qn.y - (double)nm.y, 0.0);
                                     if (lr * lr <= lim) fm |= 1u << r;
                                 }
@@ -463,8 +550,7 @@ __global__ void __launch_bounds__(256) k_bound(IndexView ix, ShadowView sv, Scan
                                             if ((fm >> r) & 1u) {
                                                 const int i = 8 * (r >> 2) + 4 * half + (r & 3);
                                                 const float2 nm = nrm[i];
-                                                const double D = (1.0 - bc.g) * (qn.x + (double)xnr[i]) -
-                                                                 2.0 * (double)sacc[r * 64 + lane];
+                                                const double D = pair_d(r, i);
                                                 const double lr =
                                                     fmax(sqrt(fmax(D, 0.0)) - qn.y - (double)nm.y, 0.0);
                                                 const uint32_t slot = off + (uint32_t)__popcll(bal & lt_mask);

@@ -93,7 +93,14 @@ def test_shadow_copy_against_oracle(kind):
     eps = np.sqrt(np.sum((rows.astype(np.float64) - low.astype(np.float64)) ** 2, axis=1))
     assert np.all(norms[:, 2] <= xn) and np.all(norms[:, 2] >= xn * (1 - 1e-6))
     assert np.all(norms[:, 1] >= eps) and np.all(norms[:, 1] <= eps * (1 + 1e-6) + 1e-37)
-    assert np.all(norms[:, 3] == 0.0)
+    # the augmented unit (a*, ebar) of the bounding pass, two low-precision values
+    au = norms[:, 3].view(np.uint32)
+    if kind == P.BF16:
+        dec = lambda b: (b.astype(np.uint32) << 16).view(np.float32).astype(np.float64)
+    else:
+        dec = lambda b: b.astype(np.uint16).view(np.float16).astype(np.float64)
+    a_st, eb = dec(au & 0xFFFF), dec(au >> 16)
+    assert np.all(eb >= norms[:, 1].astype(np.float64))
     # beta = ((1 - g) xn - eps^2) / 2 - 3u (xn + eps^2) from the stored xn and eps,
     # rounded down to float32 (g: accumulation factor of `stride` additions)
     u2 = 2.0 ** -23
@@ -103,6 +110,11 @@ def test_shadow_copy_against_oracle(kind):
     b32 = norms[:, 0]
     assert np.all(b32.astype(np.float64) <= beta)
     assert np.all(np.nextafter(b32, np.float32(np.inf)).astype(np.float64) > beta)
+    # a* >= -B0 + g2 (||x~||^2 / 2 + |a*| + ebar^2 / 2), B0 from the stored values,
+    # g2 the accumulation factor of stride + 2 products
+    g2 = (stride + 2) * u2 / (1.0 - (stride + 2) * u2)
+    B0 = 0.5 * (xs - es * es)
+    assert np.all(a_st >= -B0 + g2 * (0.5 * xn + np.abs(a_st) + 0.5 * eb * eb))
 
 
 # N, n, w, k, leaf, l_max, per_level, kind
