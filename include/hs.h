@@ -171,8 +171,8 @@ typedef struct {
  * Each query's results are sorted by (d2, id) ascending; they are the exact
  * k nearest series by the float32 distance, which agrees with float64 up to
  * a relative error below 2e-6.
- * Errors: HS_EINVAL (k < 1, k > HS_KMAX, k > N, Q < 0, NULL pointers),
- * HS_ENOMEM (workspace too small), HS_EHIP.
+ * Errors: HS_EINVAL (k < 1, k > HS_KMAX, k > N, Q < 0, Q >= 2^24, NULL
+ * pointers), HS_ENOMEM (workspace too small), HS_EHIP.
  */
 hs_status hs_knn_exact(hs_index* idx, const float* q_dev, int32_t Q, int32_t k, void* ws_dev,
                        int64_t ws_bytes, int64_t* ids_dev, float* d2_dev, void* stats_dev,

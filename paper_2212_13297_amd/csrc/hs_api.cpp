@@ -276,7 +276,7 @@ int64_t ws_layout(const hs_index* idx, int32_t Q, int32_t k, QueryWs* ws, char* 
     carve(cur, (void**)&w.items, items * 8);
     carve(cur, (void**)&w.slice_pos, cand * 4);
     carve(cur, (void**)&w.slice_q, cand * 4);
-    carve(cur, (void**)&w.slice_lb, cand * 4);
+    carve(cur, (void**)&w.slice_part, cand * 4);
     carve(cur, (void**)&w.slice_cnt, ((int64_t)n_slices + 1) * 4);
     carve(cur, (void**)&w.slice_start, ((int64_t)n_slices + 2) * 4);
     carve(cur, (void**)&w.counters, kNumCounters * 4);
@@ -535,6 +535,17 @@ double comp_err_rel(int K) { return std::ldexp(1.0, -23) + (4.0 * K + 64.0) * st
 
 namespace hs {
 
+// The refine's chunk order needs quarters of the word that cover whole
+// quarters of chunks: n = stride = 256 2^e and w a multiple of 16.
+static int32_t chunk_order_lg(const IndexView& ix) {
+    if (ix.n != ix.stride || ix.w % 16 != 0 || ix.n % 256 != 0) return -1;
+    const int cpq = ix.n / 256;
+    if (cpq & (cpq - 1)) return -1;
+    int lg = 0;
+    while ((1 << lg) < cpq) ++lg;
+    return lg;
+}
+
 hs_status knn_prepare(hs_index* idx, int32_t Q, int32_t k, void* ws_dev, int64_t ws_bytes, bool mixed,
                       KnnCall* c) {
     if (!idx) return fail(HS_EINVAL, "idx is NULL");
@@ -542,6 +553,7 @@ hs_status knn_prepare(hs_index* idx, int32_t Q, int32_t k, void* ws_dev, int64_t
     if (k < 1 || k > HS_KMAX) return fail(HS_EINVAL, "k=%d out of range [1, %d]", k, HS_KMAX);
     if ((int64_t)k > idx->view.N) return fail(HS_EINVAL, "k=%d > N=%lld", k, (long long)idx->view.N);
     if (mixed && idx->shadow.kind == 0) return fail(HS_EINVAL, "the index has no low-precision copy (hs_build_shadow)");
+    if (Q >= (1 << 24)) return fail(HS_EINVAL, "Q=%d: at most 2^24 - 1 queries per call", Q);
     if ((int64_t)Q * idx->view.parts >= ((int64_t)1 << 31))
         return fail(HS_EINVAL, "Q=%d too large for this index (Q * parts must stay below 2^31); split the batch", Q);
     c->idx = idx;
@@ -560,6 +572,9 @@ hs_status knn_prepare(hs_index* idx, int32_t Q, int32_t k, void* ws_dev, int64_t
     c->sp.eapca_th = idx->p.eapca_th;
     c->sp.n_seed = (int)std::min<int64_t>(std::min<int64_t>(idx->p.l_max, ix.L), kMaxSeedLeaves);
     c->sp.seed_rows = idx->p.seed_rows;
+    c->sp.order_lg = chunk_order_lg(ix);
+    // g = (m - 1) u / (1 - (m - 1) u) for m chunk partials, u = 2^-24; 4 m u + 2^-20 covers 2 g and the rounding
+    c->sp.order_marg = (float)(1.0 + 4.0 * (double)(ix.stride / kChunk) * std::ldexp(1.0, -24) + std::ldexp(1.0, -20));
     return HS_OK;
 }
 

@@ -68,6 +68,38 @@ __device__ __forceinline__ float lb_sax_word(const uint4 (&v)[W16], const float*
     return (acc[0] + acc[1]) + (acc[2] + acc[3]);
 }
 
+// The same bound split by quarters of the word: a[p] sums the symbols of
+// segments [p w/4, (p + 1) w/4) when w = 16 W16 (the bound is
+// (a0 + a1) + (a2 + a3)).  The refine reads a series' chunks in the order of
+// these partial bounds, largest first.
+template <int W16>
+__device__ __forceinline__ void lb_sax_quarters(const uint4 (&v)[W16], const float* s_lut, float (&a)[4]) {
+#pragma unroll
+    for (int u = 0; u < W16; ++u) {
+        const uint32_t parts[4] = {v[u].x, v[u].y, v[u].z, v[u].w};
+#pragma unroll
+        for (int p = 0; p < 4; ++p) {
+#pragma unroll
+            for (int b = 0; b < 4; ++b) {
+                const int i = u * 16 + p * 4 + b;
+                const int qt = i / (4 * W16);
+                const float e = s_lut[i * kCard + ((parts[p] >> (8 * b)) & 0xffu)];
+                a[qt] = i % (4 * W16) == 0 ? e : a[qt] + e;  // table entries are >= 0
+            }
+        }
+    }
+}
+
+// Four non-negative float32 values in one word: byte p is the high byte of
+// a_p as fp16 rounded toward zero (5 exponent and 2 mantissa bits), so the
+// value it stands for, that byte followed by a zero byte, is at most a_p, and
+// bytes order as the values do.
+__device__ __forceinline__ uint32_t pack_quarters(float a0, float a1, float a2, float a3) {
+    const uint32_t h01 = __builtin_bit_cast(uint32_t, __builtin_amdgcn_cvt_pkrtz(a0, a1));
+    const uint32_t h23 = __builtin_bit_cast(uint32_t, __builtin_amdgcn_cvt_pkrtz(a2, a3));
+    return __builtin_amdgcn_perm(h23, h01, 0x07050301u);  // bytes 1, 3 of h01, then of h23
+}
+
 // Raw buffer loads.  A load whose offset lies past the resource's byte size
 // returns zeros and reads no memory, so a masked-out load is an ordinary
 // instruction with no traffic: loads need no branch around them, every load

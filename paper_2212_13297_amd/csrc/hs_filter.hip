@@ -27,7 +27,7 @@ __device__ __forceinline__ int64_t item_count(const QueryWs& ws) {
 struct FilterOut {
     uint32_t* spos;
     uint32_t* sq;
-    float* slb;
+    uint32_t* spart;
     uint32_t cnt;  // entries in this wavefront's slice (uniform)
     unsigned long long filt, cand, tests;
     bool lost;
@@ -57,15 +57,21 @@ __device__ __forceinline__ void filter_batch(const IndexView& ix, const QueryWs&
         for (int u = 0; u < W16; ++u) v[s][u] = buffer_load16(rs, (uint32_t)lane * wb + 16u * u);
     }
     const uint64_t lt_mask = (1ull << lane) - 1ull;
-    float lbv[kBatch];
+    uint32_t pk[kBatch];  // the bounds by quarters
     uint32_t mask = 0;
 #pragma unroll
     for (int s = 0; s < kBatch; ++s) {
-        lbv[s] = 0.0f;
+        pk[s] = 0u;
         if (s < nb) {
-            if (!skip) lbv[s] = lb_sax_word<W16>(v[s], s_lut);
+            float lb = 0.0f;
+            if (!skip) {
+                float a[4];
+                lb_sax_quarters<W16>(v[s], s_lut, a);
+                lb = (a[0] + a[1]) + (a[2] + a[3]);
+                pk[s] = pack_quarters(a[0], a[1], a[2], a[3]);
+            }
             o.filt += r1[s] - r0[s];
-            if ((uint32_t)lane < r1[s] - r0[s] && lbv[s] <= thr) mask |= 1u << s;
+            if ((uint32_t)lane < r1[s] - r0[s] && lb <= thr) mask |= 1u << s;
         }
     }
     uint32_t total = 0;
@@ -74,7 +80,7 @@ __device__ __forceinline__ void filter_batch(const IndexView& ix, const QueryWs&
     if (total == 0) return;
     uint32_t* dpos = o.spos;
     uint32_t* dq = o.sq;
-    float* dlb = o.slb;
+    uint32_t* dpart = o.spart;
     uint32_t off = o.cnt;
     const bool own = (int64_t)o.cnt + total <= ws.slice_cap;
     if (!own) {
@@ -99,7 +105,7 @@ __device__ __forceinline__ void filter_batch(const IndexView& ix, const QueryWs&
         const int64_t ob = (int64_t)ws.n_slices * ws.slice_cap;
         dpos = ws.slice_pos + ob;
         dq = ws.slice_q + ob;
-        dlb = ws.slice_lb + ob;
+        dpart = ws.slice_part + ob;
         off = (uint32_t)b;
     }
 #pragma unroll
@@ -109,7 +115,7 @@ __device__ __forceinline__ void filter_batch(const IndexView& ix, const QueryWs&
             const uint32_t slot = off + (uint32_t)__popcll(bal & lt_mask);
             dpos[slot] = r0[s] + (uint32_t)lane;
             dq[slot] = (uint32_t)q;
-            dlb[slot] = lbv[s];
+            dpart[slot] = pk[s];
         }
         off += (uint32_t)__popcll(bal);
     }
@@ -151,7 +157,7 @@ __global__ void __launch_bounds__(256) k_filter(IndexView ix, ScanParams sp, Que
 
     const int64_t slice = (int64_t)blockIdx.x * kWaves + wave;
     FilterOut o{ws.slice_pos + slice * ws.slice_cap, ws.slice_q + slice * ws.slice_cap,
-                ws.slice_lb + slice * ws.slice_cap, 0u, 0ull, 0ull, 0ull, false};
+                ws.slice_part + slice * ws.slice_cap, 0u, 0ull, 0ull, 0ull, false};
     int64_t i0, i1;
     block_range(item_count(ws), i0, i1);
     int64_t idx = i0;

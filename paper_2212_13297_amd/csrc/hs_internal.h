@@ -101,7 +101,7 @@ struct QueryWs {
     // filter output: one private slice per filter wavefront
     uint32_t* slice_pos;  // [n_slices][slice_cap] stored position of a candidate series
     uint32_t* slice_q;    // [n_slices][slice_cap] its query
-    float* slice_lb;      // [n_slices][slice_cap] its LB_SAX
+    uint32_t* slice_part; // [n_slices][slice_cap] its LB_SAX by quarters: four bytes, the high bytes of fp16 values rounded toward zero
     uint32_t* slice_cnt;  // [n_slices] entries written in each slice
     uint32_t* slice_start;// [n_slices + 1] exclusive prefix of slice_cnt
     uint32_t* counters;   // [kNumCounters]
@@ -124,6 +124,13 @@ struct ScanParams {
     int32_t final_pass;
     int32_t n_seed;     // seed leaves per query: min(l_max, L, kMaxSeedLeaves)
     int32_t seed_rows;  // series refined by the seed step
+    // chunk order of the refine: -1 natural order; otherwise log2 of the
+    // chunks per quarter of the series (stride = n = 256 2^order_lg, w a
+    // multiple of 16), and order_marg >= (1 + g) / (1 - g), g the float32
+    // summation bound of nchunks partials: a reordered running distance above
+    // limit * order_marg proves the natural-order one above the limit
+    int32_t order_lg;
+    float order_marg;
 };
 
 // kernel launchers (hs_kernels.hip); all asynchronous on `st`

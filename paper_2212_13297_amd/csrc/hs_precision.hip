@@ -297,7 +297,7 @@ __global__ void __launch_bounds__(256) k_bound(IndexView ix, ShadowView sv, Scan
     const int64_t slice = (int64_t)blockIdx.x * (kTile / 64) + wave;
     uint32_t* spos = ws.slice_pos + slice * ws.slice_cap;
     uint32_t* sq = ws.slice_q + slice * ws.slice_cap;
-    float* slb = ws.slice_lb + slice * ws.slice_cap;
+    uint32_t* spart = ws.slice_part + slice * ws.slice_cap;
     uint32_t cnt = 0;  // entries in this wavefront's slice (uniform)
     // slices of wavefronts beyond this grid stay empty
     for (int64_t e = (int64_t)gridDim.x * (kTile / 64) + (int64_t)blockIdx.x * kTile + t; e < ws.n_slices;
@@ -516,7 +516,7 @@ __global__ void __launch_bounds__(256) k_bound(IndexView ix, ShadowView sv, Scan
                                 if (total) {
                                     uint32_t* dpos = spos;
                                     uint32_t* dq = sq;
-                                    float* dlb = slb;
+                                    uint32_t* dpart = spart;
                                     uint32_t off = cnt;
                                     const bool own = (int64_t)cnt + total <= ws.slice_cap;
                                     bool ok = true;
@@ -540,7 +540,7 @@ __global__ void __launch_bounds__(256) k_bound(IndexView ix, ShadowView sv, Scan
                                             const int64_t ob = (int64_t)ws.n_slices * ws.slice_cap;
                                             dpos = ws.slice_pos + ob;
                                             dq = ws.slice_q + ob;
-                                            dlb = ws.slice_lb + ob;
+                                            dpart = ws.slice_part + ob;
                                             off = (uint32_t)b;
                                         }
                                     }
@@ -556,7 +556,8 @@ __global__ void __launch_bounds__(256) k_bound(IndexView ix, ShadowView sv, Scan
                                                 const uint32_t slot = off + (uint32_t)__popcll(bal & lt_mask);
                                                 dpos[slot] = (uint32_t)(tr0 + i);
                                                 dq[slot] = (uint32_t)qj;
-                                                dlb[slot] = __double2float_rd(lr * lr);
+                                                // the bound as the first quarter (natural chunk order)
+                                                dpart[slot] = pack_quarters(__double2float_rd(lr * lr), 0.0f, 0.0f, 0.0f);
                                             }
                                             off += (uint32_t)__popcll(bal);
                                         }

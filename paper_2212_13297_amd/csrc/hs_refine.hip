@@ -14,11 +14,12 @@ namespace hs {
 namespace {
 
 constexpr int kRefineSlots = 4;  // candidates in flight per 16-lane group
+constexpr uint32_t kNaturalPerm = 0xE4u;  // quarters 0, 1, 2, 3
 
 struct Meta {
     int q;
     uint32_t pos;
-    float lb;
+    uint32_t part;  // LB_SAX by quarters, four bytes
 };
 
 // The candidate list is the concatenation of the filter's slices (the private
@@ -57,13 +58,50 @@ __device__ __forceinline__ Meta load_meta(const QueryWs& ws, long long c, long l
     Meta m;
     m.q = (int)ws.slice_q[e];
     m.pos = ws.slice_pos[e];
-    m.lb = ws.slice_lb[e];
+    m.part = ws.slice_part[e];
     if (c >= cend) m.q = -1;
     return m;
 }
 
-__device__ __forceinline__ uint4 ring_entry(const Meta& m) {
-    return make_uint4((uint32_t)m.q, m.pos, __float_as_uint(__double2float_rd((double)m.lb / (1.0 + kSlack))), 0u);
+// The order in which a series' quarters are read: the largest partial bound
+// first, equal bounds in natural order.  Quarter j of the order sits in bits
+// 2j and 2j + 1.  The bytes of the packed bounds order as their values; the
+// sort keys carry 3 - p in their low two bits.
+__device__ __forceinline__ uint32_t chunk_perm(uint32_t part) {
+    uint32_t k[4];
+#pragma unroll
+    for (int p = 0; p < 4; ++p) k[p] = (((part >> (8 * p)) & 0xffu) << 2) | (uint32_t)(3 - p);
+    auto ce = [](uint32_t& x, uint32_t& y) {
+        const uint32_t hi = max(x, y), lo = min(x, y);
+        x = hi;
+        y = lo;
+    };
+    ce(k[0], k[1]);
+    ce(k[2], k[3]);
+    ce(k[0], k[2]);
+    ce(k[1], k[3]);
+    ce(k[1], k[2]);
+    uint32_t perm = 0u;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) perm |= (3u - (k[j] & 3u)) << (2 * j);
+    return perm;
+}
+
+// Ring entry (q | perm << 24, pos, lbs, bsf): lbs = LB_SAX / (1 + slack)
+// rounded down, from the exact float64 sum of the four packed partials (each
+// at most the float32 one), so lbs > limit implies LB_SAX > limit (1 + slack);
+// bsf, a BSF_k of the entry's query read before it is handed out (+inf until
+// then).  An entry without a candidate has x = 0xffffffff.
+__device__ __forceinline__ uint4 ring_entry(const Meta& m, bool ord) {
+    double lb = 0.0;
+#pragma unroll
+    for (int p = 0; p < 4; ++p) {
+        const _Float16 h = __builtin_bit_cast(_Float16, (uint16_t)(((m.part >> (8 * p)) & 0xffu) << 8));
+        lb += (double)(float)h;
+    }
+    const uint32_t perm = ord ? chunk_perm(m.part) : kNaturalPerm;
+    return make_uint4(m.q < 0 ? 0xffffffffu : ((uint32_t)m.q | perm << 24), m.pos,
+                      __float_as_uint(__double2float_rd(lb / (1.0 + kSlack))), 0x7f800000u);
 }
 
 // F: distance form.  NS: candidates in flight per 16-lane group.
@@ -77,23 +115,31 @@ __device__ __forceinline__ uint4 ring_entry(const Meta& m) {
 // chunks per group however early candidates are abandoned.
 //
 // The candidates' metadata pass through a ring of 128 entries in LDS per
-// wavefront (the next 64 are loaded while the current ones are handed out).
-// A slot's limit is the smaller of the last BSF_k read for its query and the
-// wavefront's own k-th distance; an older BSF_k is only a looser limit.
+// wavefront (the next 64 are loaded while the current ones are handed out),
+// each with a BSF_k of its own query, read once its metadata has arrived.  A
+// slot's limit is the smaller of that BSF_k and, for the query of the
+// wavefront's top-k, its own k-th distance; an older BSF_k is only a looser
+// limit.
 // Counters accumulate per group in registers; only rounds that complete a
 // series within its limit, or retire a candidate of another query, go
 // through lane 0, which alone keeps the wavefront's top-k in LDS and
 // publishes its improvements with atomicMin.
 template <int F, int NS>
-__global__ void __launch_bounds__(256) k_refine(IndexView ix, ScanParams sp, QueryWs ws) {
+__global__ void __launch_bounds__(256, 4) k_refine(IndexView ix, ScanParams sp, QueryWs ws) {
     constexpr int kRing = 128;
     __shared__ unsigned long long s_top[kTile / 64][HS_KMAX];
-    // (q, pos, lbs, -) of candidate i at (i - cbeg) mod 128, lbs = LB_SAX / (1 + slack)
-    // rounded down: lbs > limit implies LB_SAX > limit (1 + slack), the skip test
+    // ring_entry of candidate i at (i - cbeg) mod 128
     __shared__ uint4 s_ring[kTile / 64][kRing];
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6, sub = t & 15, grp = (t >> 4) & 3;
     const int k = sp.k;
     const int nchunks = ix.stride / kChunk;
+    // chunk order: quarters in the ring entry's order, chunks of a quarter in
+    // natural order; a reordered running distance is tested against
+    // limit * marg, which proves the natural-order distance above the limit
+    const int olg = sp.order_lg;
+    const bool ord = olg >= 0;
+    const int omask = ord ? (1 << olg) - 1 : 0;
+    const float marg = ord ? sp.order_marg : 1.0f;
     const long long T = ws.slice_start[ws.n_slices + 1];
     const long long gw = (long long)blockIdx.x * (kTile / 64) + wave, GW = (long long)gridDim.x * (kTile / 64);
     const long long cbeg = T * gw / GW, cend = T * (gw + 1) / GW;
@@ -129,24 +175,45 @@ __global__ void __launch_bounds__(256) k_refine(IndexView ix, ScanParams sp, Que
 
     SliceCursor cur;
     long long mb = cbeg;  // the ring holds candidates mb .. mb + 127
-    int bq, pq;           // query of the last BSF_k read and of the one in flight
-    float bv, pv;
+    // BSF_k of the query of the entry at ring index snap_idx (this lane's entry
+    // of the last window written), requested when the window was written and
+    // stored into the ring a round later (snap_due)
+    float nsnap;
+    int snap_idx = 0;
+    bool snap_due = false;
     {
         const Meta a = load_meta(ws, mb + lane, cend, cur);
         const Meta b = load_meta(ws, mb + 64 + lane, cend, cur);
-        ring[lane] = ring_entry(a);
-        ring[64 + lane] = ring_entry(b);
-        bq = pq = __builtin_amdgcn_readfirstlane(a.q);
-        bv = pv = bits_to_float(load_relaxed(&ws.bsf[max(bq, 0)]));
+        uint4 ea = ring_entry(a, ord);
+        ea.w = load_relaxed(&ws.bsf[max(a.q, 0)]);
+        ring[lane] = ea;
+        ring[64 + lane] = ring_entry(b, ord);
+        nsnap = bits_to_float(load_relaxed(&ws.bsf[max(b.q, 0)]));
+        snap_idx = 64 + lane;
+        snap_due = true;
     }
-    Meta pend{-1, 0u, 0.0f};  // the next 64 entries, written to the ring after this round's loads
+    Meta pend{-1, 0u, 0u};  // the next 64 entries, written to the ring after this round's loads
     bool has_pend = false;
+    auto write_snap = [&]() {
+        reinterpret_cast<uint32_t*>(&ring[snap_idx])[3] = __float_as_uint(nsnap);
+        snap_due = false;
+    };
+    // pend goes into the ring and the BSF_k of its queries is requested
+    auto write_pend = [&]() {
+        if (snap_due) write_snap();
+        snap_idx = ((int)(mb + 64 - cbeg) & (kRing - 1)) + lane;
+        ring[snap_idx] = ring_entry(pend, ord);
+        nsnap = bits_to_float(load_relaxed(&ws.bsf[max(pend.q, 0)]));
+        snap_due = true;
+        has_pend = false;
+    };
     long long next = cbeg;  // next candidate to hand out (uniform)
 
     // slots, each the same in the 16 lanes of its group
     int sq[NS];            // query (-1: empty)
     uint32_t spos[NS];     // stored position of the series
     int sc[NS];            // chunks added so far
+    uint32_t sperm[NS];    // order of the quarters
     float sthr[NS];        // abandoning limit
     const float* xp[NS];   // the lane's first point of the series and of the query
     const float* qp[NS];
@@ -157,6 +224,7 @@ __global__ void __launch_bounds__(256) k_refine(IndexView ix, ScanParams sp, Que
         sq[s] = -1;
         spos[s] = 0u;
         sc[s] = 0;
+        sperm[s] = kNaturalPerm;
         sthr[s] = INFINITY;
         xp[s] = ix.rows + sub * 4;
         qp[s] = ws.qrow + sub * 4;
@@ -169,26 +237,19 @@ __global__ void __launch_bounds__(256) k_refine(IndexView ix, ScanParams sp, Que
         // limit is skipped and the slot asks again
         for (;;) {
             if (next - mb >= 64) {
-                // the ring moves on by 64: the next 64 entries are loaded (and
-                // written after this round's loads), the BSF_k read at the last
-                // move is taken over and the next one is issued
-                if (has_pend) {
-                    ring[((int)(mb + 64 - cbeg) & (kRing - 1)) + lane] = ring_entry(pend);
-                    has_pend = false;
-                }
+                // the ring moves on by 64: the entries now handed out have
+                // their BSF_k, and the next 64 entries are loaded (written
+                // after this round's loads)
+                if (has_pend) write_pend();
+                if (snap_due) write_snap();
                 mb += 64;
                 pend = load_meta(ws, mb + 64 + lane, cend, cur);
                 has_pend = true;
-                bq = pq;
-                bv = pv;
-                pq = __builtin_amdgcn_readfirstlane((int)ring[(int)(mb - cbeg) & (kRing - 1)].x);
-                pv = bits_to_float(load_relaxed(&ws.bsf[max(pq, 0)]));
             }
             if (has_pend && next + 4 * NS > mb + 64) {
                 // this hand-out reaches the entries still in flight (after many
                 // skipped candidates): they are written now
-                ring[((int)(mb + 64 - cbeg) & (kRing - 1)) + lane] = ring_entry(pend);
-                has_pend = false;
+                write_pend();
             }
             int rank[NS], nf = 0;
 #pragma unroll
@@ -208,13 +269,14 @@ __global__ void __launch_bounds__(256) k_refine(IndexView ix, ScanParams sp, Que
                 if (fin[s]) {
                     const int ri = goff + rank[s];  // candidate cbeg + ri
                     const uint4 e = ring[ri & (kRing - 1)];
-                    const int q = ri < nrel ? (int)e.x : -1;
-                    float lim = q == bq ? bv : INFINITY;
+                    const int q = ri < nrel && e.x != 0xffffffffu ? (int)(e.x & 0xffffffu) : -1;
+                    float lim = __uint_as_float(e.w);
                     if (q == cur_q) lim = fminf(lim, lk);
                     const uint32_t pos = q >= 0 ? e.y : 0u;
                     sq[s] = q;
                     spos[s] = pos;
                     sc[s] = 0;
+                    sperm[s] = e.x >> 24;
                     sd[s] = Dist<F>{};
                     sthr[s] = lim;
                     xp[s] = ix.rows + (int64_t)pos * ix.stride + sub * 4;
@@ -231,12 +293,14 @@ __global__ void __launch_bounds__(256) k_refine(IndexView ix, ScanParams sp, Que
         for (int s = 0; s < NS; ++s) any = any || sq[s] >= 0;
         if (!__ballot(any)) break;
 
-        // one chunk of every slot's series; empty slots read chunk 0 of row 0
+        // one chunk of every slot's series (its next in the slot's order);
+        // empty slots read a chunk of row 0
         float4 x[NS], qv[NS];
 #pragma unroll
         for (int s = 0; s < NS; ++s) {
-            x[s] = *reinterpret_cast<const float4*>(xp[s] + sc[s] * kChunk);
-            qv[s] = *reinterpret_cast<const float4*>(qp[s] + sc[s] * kChunk);
+            const int c = ord ? ((int)((sperm[s] >> ((sc[s] >> olg) << 1)) & 3u) << olg) | (sc[s] & omask) : sc[s];
+            x[s] = *reinterpret_cast<const float4*>(xp[s] + c * kChunk);
+            qv[s] = *reinterpret_cast<const float4*>(qp[s] + c * kChunk);
         }
         bool adm[NS];
         bool slow = false;
@@ -247,16 +311,14 @@ __global__ void __launch_bounds__(256) k_refine(IndexView ix, ScanParams sp, Que
             if (sq[s] >= 0) {
                 sd[s].add(qv[s], x[s]);
                 sc[s] += 1;
-                const bool over = sd[s].value() > sthr[s];
+                const bool over = sd[s].value() > sthr[s] * marg;
                 fin[s] = over || sc[s] == nchunks;
                 adm[s] = fin[s] && !over;
                 slow = slow || adm[s] || (fin[s] && sq[s] != st_q);
             }
         }
-        if (has_pend) {
-            ring[((int)(mb + 64 - cbeg) & (kRing - 1)) + lane] = ring_entry(pend);
-            has_pend = false;
-        }
+        if (snap_due) write_snap();
+        if (has_pend) write_pend();
 
         if (!__ballot(slow)) {
             // common round: nothing admitted, every retired candidate of st_q
@@ -267,6 +329,31 @@ __global__ void __launch_bounds__(256) k_refine(IndexView ix, ScanParams sp, Que
                     g_ch += (unsigned long long)sc[s];
                 }
             continue;
+        }
+        if (ord) {
+            // a series read out of natural order and completed within its
+            // limit gets its distance again in natural order, the one every
+            // kernel computes for the pair (results and their keys agree)
+            bool rc[NS], anyrc = false;
+#pragma unroll
+            for (int s = 0; s < NS; ++s) {
+                rc[s] = adm[s] && sperm[s] != kNaturalPerm;
+                anyrc = anyrc || rc[s];
+            }
+            if (__ballot(anyrc)) {
+#pragma unroll
+                for (int s = 0; s < NS; ++s) {
+                    if (!__ballot(rc[s])) continue;
+                    if (rc[s]) {
+                        Dist<F> d{};
+                        for (int c = 0; c < nchunks; ++c)
+                            d.add(*reinterpret_cast<const float4*>(qp[s] + c * kChunk),
+                                  *reinterpret_cast<const float4*>(xp[s] + c * kChunk));
+                        sd[s] = d;
+                        sc[s] += nchunks;  // chunks read again
+                    }
+                }
+            }
         }
         // retirements one by one, in slot order
         int new_q = cur_q;

@@ -269,6 +269,11 @@ def test_errors():
     with pytest.raises(hs.HSError) as e:
         hs.hs_knn_exact(idx.h, None, 2, 3, ws.data_ptr(), need, ids.data_ptr(), d2.data_ptr(), None, 0)
     assert e.value.code == hs.HS_EINVAL
+    # at most 2^24 - 1 queries per call (rejected before any access to the arrays)
+    with pytest.raises(hs.HSError) as e:
+        hs.hs_knn_exact(idx.h, qt.data_ptr(), 1 << 24, 3, ws.data_ptr(), need, ids.data_ptr(), d2.data_ptr(),
+                        None, 0)
+    assert e.value.code == hs.HS_EINVAL
     # Q = 0 is a no-op
     hs.hs_knn_exact(idx.h, qt.data_ptr(), 0, 3, ws.data_ptr(), need, ids.data_ptr(), d2.data_ptr(), None, 0)
     # the index still answers correctly after the failed calls
