@@ -105,10 +105,35 @@ CASES = [
     (12_345, 200, 8, 333, 1, 7),         # n not a multiple of 64: padded rows
     (20_000, 128, 16, 1000, 1, 100),     # k = 100
     (20_000, 1024, 32, 500, 2, 10),      # long series, w = 32
+    (15_000, 512, 16, 400, 1, 10),       # two chunks per quarter in the refine's chunk order
     (9_000, 256, 16, 100, 0, 10),        # no seed leaves
     (9_000, 256, 16, 50, 5, 3),          # several seed leaves, small leaves
     (5_000, 64, 4, 5_000, 1, 20),        # a single leaf
 ]
+
+
+@pytest.mark.parametrize("n,w", [(256, 16), (1024, 32)])
+def test_distance_independent_of_path(n, w):
+    # A pair's float32 distance is the same whether the seed step (natural
+    # chunk order) or the refine (chunks read in LB_SAX order, distance of an
+    # admitted series summed again in natural order) produced it: without
+    # seed leaves every result comes from the refine.
+    x, q = workload(6000, n, coll=n + w, per_level=4)
+    a = make_index(x, w=w, leaf_size=150, l_max=0)
+    b = make_index(x, w=w, leaf_size=150, l_max=6)
+    ia, da = run_knn(a, q, 10)
+    ib, db = run_knn(b, q, 10)
+    check_knn(x, q, 10, ia, da)
+    common = 0
+    for i in range(q.shape[0]):
+        mb = dict(zip(ib[i].tolist(), db[i].tolist()))
+        for j, d in zip(ia[i].tolist(), da[i].tolist()):
+            if j in mb:
+                assert np.float32(d).view(np.uint32) == np.float32(mb[j]).view(np.uint32), (i, j, d, mb[j])
+                common += 1
+    assert common >= 5 * q.shape[0]
+    a.close()
+    b.close()
 
 
 @pytest.mark.parametrize("N,n,w,tau,l_max,k", CASES)
