@@ -277,6 +277,7 @@ __global__ void __launch_bounds__(1024) k_slice_prefix(QueryWs ws) {
         // every overflow entry below min(counter, first range that did not fit) was written
         const int64_t c = min(min((int64_t)ws.counters[kCtrOvf], (int64_t)ws.counters[kCtrOvfEnd]), ws.ovf_cap);
         ws.slice_cnt[ws.n_slices] = (uint32_t)c;
+        ws.counters[kCtrRefine] = 0u;  // the refine's segment counter
     }
     __syncthreads();
     const int per = (n + 1023) / 1024;

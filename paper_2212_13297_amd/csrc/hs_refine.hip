@@ -14,6 +14,7 @@ namespace hs {
 namespace {
 
 constexpr int kRefineSlots = 4;  // candidates in flight per 16-lane group
+constexpr int kSeg = 512;        // candidates per segment of a long list (a multiple of 64, >= 128)
 constexpr uint32_t kNaturalPerm = 0xE4u;  // quarters 0, 1, 2, 3
 
 struct Meta {
@@ -40,15 +41,17 @@ __device__ __forceinline__ int slice_of(const QueryWs& ws, long long c, int hint
 
 // Candidate c of the list, read by every lane of a wavefront for consecutive
 // c.  The lane keeps its slice's first entry and end in registers: only a
-// step across a slice end loads the prefix again.  A lane past cend reads
-// entry cend - 1 and marks it invalid, so the loads do not depend on c.
+// step across a slice end loads the prefix again (a lane's c only grows).  A
+// lane without a candidate reads entry T - 1 and marks it invalid, so the
+// loads do not depend on c.
 struct SliceCursor {
     int s = 0;
     long long begin = 0, end = 0;
 };
 
-__device__ __forceinline__ Meta load_meta(const QueryWs& ws, long long c, long long cend, SliceCursor& cur) {
-    const long long cc = min(c, cend - 1);
+__device__ __forceinline__ Meta load_meta(const QueryWs& ws, long long c, bool valid, long long T,
+                                          SliceCursor& cur) {
+    const long long cc = valid ? c : T - 1;
     if (cc >= cur.end) {
         cur.s = slice_of(ws, cc, cur.s);
         cur.begin = ws.slice_start[cur.s];
@@ -59,7 +62,7 @@ __device__ __forceinline__ Meta load_meta(const QueryWs& ws, long long c, long l
     m.q = (int)ws.slice_q[e];
     m.pos = ws.slice_pos[e];
     m.part = ws.slice_part[e];
-    if (c >= cend) m.q = -1;
+    if (!valid) m.q = -1;
     return m;
 }
 
@@ -128,7 +131,7 @@ template <int F, int NS>
 __global__ void __launch_bounds__(256, 4) k_refine(IndexView ix, ScanParams sp, QueryWs ws) {
     constexpr int kRing = 128;
     __shared__ unsigned long long s_top[kTile / 64][HS_KMAX];
-    // ring_entry of candidate i at (i - cbeg) mod 128
+    // ring_entry of the stream's candidate v at v mod 128
     __shared__ uint4 s_ring[kTile / 64][kRing];
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6, sub = t & 15, grp = (t >> 4) & 3;
     const int k = sp.k;
@@ -142,9 +145,34 @@ __global__ void __launch_bounds__(256, 4) k_refine(IndexView ix, ScanParams sp, 
     const float marg = ord ? sp.order_marg : 1.0f;
     const long long T = ws.slice_start[ws.n_slices + 1];
     const long long gw = (long long)blockIdx.x * (kTile / 64) + wave, GW = (long long)gridDim.x * (kTile / 64);
-    const long long cbeg = T * gw / GW, cend = T * (gw + 1) / GW;
-    if (cbeg >= cend) return;
-    const int nrel = (int)(cend - cbeg);  // candidates of this wavefront (< 2^31)
+    // The wavefront's stream of candidates: list entries startA .. startA +
+    // lenA - 1 at stream positions vbase .., then startB .. startB + lenB - 1.
+    // A long list is cut into segments of kSeg, the wavefront's first by its
+    // index and each next one taken from a counter when the ring reaches it
+    // (wavefronts that meet costly candidates take fewer); a short one into
+    // one contiguous range per wavefront.
+    const long long nseg = (T + kSeg - 1) / kSeg;
+    const bool dyn = nseg >= 2 * GW;
+    long long vbase = 0, startA, lenA, startB = 0, lenB = 0;
+    bool have_b = !dyn;
+    if (dyn) {
+        startA = gw * kSeg;
+        lenA = kSeg;
+    } else {
+        startA = T * gw / GW;
+        lenA = T * (gw + 1) / GW - startA;
+    }
+    if (lenA <= 0) return;
+    // list index c of stream position v (false: past the stream's end)
+    auto vmap = [&](long long v, long long& c) -> bool {
+        const long long off = v - vbase;
+        if (off < lenA) {
+            c = startA + off;
+            return true;
+        }
+        c = startB + (off - lenA);
+        return off - lenA < lenB;
+    };
     unsigned long long* top = s_top[wave];
     uint4* ring = s_ring[wave];
 
@@ -174,7 +202,7 @@ __global__ void __launch_bounds__(256, 4) k_refine(IndexView ix, ScanParams sp, 
     };
 
     SliceCursor cur;
-    long long mb = cbeg;  // the ring holds candidates mb .. mb + 127
+    long long mb = 0;  // the ring holds stream positions mb .. mb + 127
     // BSF_k of the query of the entry at ring index snap_idx (this lane's entry
     // of the last window written), requested when the window was written and
     // stored into the ring a round later (snap_due)
@@ -182,8 +210,10 @@ __global__ void __launch_bounds__(256, 4) k_refine(IndexView ix, ScanParams sp, 
     int snap_idx = 0;
     bool snap_due = false;
     {
-        const Meta a = load_meta(ws, mb + lane, cend, cur);
-        const Meta b = load_meta(ws, mb + 64 + lane, cend, cur);
+        long long ca, cb;
+        const bool va = vmap(lane, ca), vb = vmap(64 + lane, cb);
+        const Meta a = load_meta(ws, ca, va, T, cur);
+        const Meta b = load_meta(ws, cb, vb, T, cur);
         uint4 ea = ring_entry(a, ord);
         ea.w = load_relaxed(&ws.bsf[max(a.q, 0)]);
         ring[lane] = ea;
@@ -201,13 +231,13 @@ __global__ void __launch_bounds__(256, 4) k_refine(IndexView ix, ScanParams sp, 
     // pend goes into the ring and the BSF_k of its queries is requested
     auto write_pend = [&]() {
         if (snap_due) write_snap();
-        snap_idx = ((int)(mb + 64 - cbeg) & (kRing - 1)) + lane;
+        snap_idx = ((int)(mb + 64) & (kRing - 1)) + lane;
         ring[snap_idx] = ring_entry(pend, ord);
         nsnap = bits_to_float(load_relaxed(&ws.bsf[max(pend.q, 0)]));
         snap_due = true;
         has_pend = false;
     };
-    long long next = cbeg;  // next candidate to hand out (uniform)
+    long long next = 0;  // stream position of the next candidate to hand out (uniform)
 
     // slots, each the same in the 16 lanes of its group
     int sq[NS];            // query (-1: empty)
@@ -243,7 +273,28 @@ __global__ void __launch_bounds__(256, 4) k_refine(IndexView ix, ScanParams sp, 
                 if (has_pend) write_pend();
                 if (snap_due) write_snap();
                 mb += 64;
-                pend = load_meta(ws, mb + 64 + lane, cend, cur);
+                if (dyn) {
+                    if (mb - vbase >= lenA) {
+                        // segment A is handed out: B moves up
+                        vbase += lenA;
+                        startA = startB;
+                        lenA = lenB;
+                        lenB = 0;
+                        have_b = false;
+                    }
+                    if (!have_b && mb + 64 >= vbase + lenA) {
+                        // the entries loaded next lie past segment A: take the next segment
+                        uint32_t r = 0u;
+                        if (lane == 0) r = atomicAdd(&ws.counters[kCtrRefine], 1u);
+                        const long long sg = GW + (long long)__builtin_amdgcn_readfirstlane(r);
+                        startB = sg * kSeg;
+                        lenB = sg < nseg ? min((long long)kSeg, T - startB) : 0;
+                        have_b = true;
+                    }
+                }
+                long long cp;
+                const bool vp = vmap(mb + 64 + lane, cp);
+                pend = load_meta(ws, cp, vp, T, cur);
                 has_pend = true;
             }
             if (has_pend && next + 4 * NS > mb + 64) {
@@ -261,15 +312,15 @@ __global__ void __launch_bounds__(256, 4) k_refine(IndexView ix, ScanParams sp, 
                       f2 = __builtin_amdgcn_readlane(nf, 32), f3 = __builtin_amdgcn_readlane(nf, 48);
             const int total = f0 + f1 + f2 + f3;
             if (total == 0) break;
-            const int goff = (int)(next - cbeg) + (grp > 0 ? f0 : 0) + (grp > 1 ? f1 : 0) + (grp > 2 ? f2 : 0);
+            const int goff = (int)next + (grp > 0 ? f0 : 0) + (grp > 1 ? f1 : 0) + (grp > 2 ? f2 : 0);
             bool again = false;
 #pragma unroll
             for (int s = 0; s < NS; ++s) {
                 if (!__ballot(fin[s])) continue;
                 if (fin[s]) {
-                    const int ri = goff + rank[s];  // candidate cbeg + ri
+                    const int ri = goff + rank[s];  // stream position
                     const uint4 e = ring[ri & (kRing - 1)];
-                    const int q = ri < nrel && e.x != 0xffffffffu ? (int)(e.x & 0xffffffu) : -1;
+                    const int q = e.x != 0xffffffffu ? (int)(e.x & 0xffffffu) : -1;  // -1 past the stream's end
                     float lim = __uint_as_float(e.w);
                     if (q == cur_q) lim = fminf(lim, lk);
                     const uint32_t pos = q >= 0 ? e.y : 0u;
