@@ -136,6 +136,27 @@ def test_distance_independent_of_path(n, w):
     b.close()
 
 
+def test_long_candidate_list():
+    # White-noise queries (z-normalised) keep nearly every series as a
+    # candidate: the refine then deals its list out in segments from a counter
+    # (a list of at least two segments per wavefront) rather than one range
+    # each.
+    N, n, k = 200_000, 256, 10
+    x = G.random_walks(N, n, coll=77)
+    g = np.random.Generator(np.random.PCG64(np.random.SeedSequence([77, 1])))
+    noise = g.standard_normal((64, n))
+    noise = ((noise - noise.mean(1, keepdims=True)) / noise.std(1, keepdims=True)).astype(np.float32)
+    q = np.concatenate([noise, G.workload(x, [10], 8, coll=77)[0]])
+    idx = make_index(x, w=16, leaf_size=2000, l_max=1, cand_per_query=N)
+    ids, d2, st = run_knn(idx, q, k, stats=True)
+    cands = int(st["candidates"].sum().item())
+    print(f"[long list] candidates {cands}", flush=True)
+    assert cands >= 2 * 4096 * 512
+    assert int(st["rounds"].max().item()) == 1  # no overflow fallback
+    check_knn(x, q, k, ids, d2)
+    idx.close()
+
+
 @pytest.mark.parametrize("N,n,w,tau,l_max,k", CASES)
 def test_knn_parity(N, n, w, tau, l_max, k):
     x, q = workload(N, n, coll=N % 97 + n)
