@@ -3,10 +3,10 @@
 // the refine kernel.
 //
 // Every wavefront appends to a private slice of the candidate buffer with a
-// counter in a register (no atomics).  Items are ordered by query and each
-// workgroup takes a contiguous range, staged in LDS a window at a time (a
-// window holds items of one query); the workgroup's wavefronts wait for each
-// other only between windows.  After the filter, slice_prefix computes where
+// counter in a register (no atomics).  Items are ordered by query; workgroups
+// take units of consecutive items from a counter and stage them in LDS a
+// window at a time (a window holds items of one query); the workgroup's
+// wavefronts wait for each other only between windows.  After the filter, slice_prefix computes where
 // each slice starts in the candidate list, the slices' concatenation, which
 // the refine kernel reads in place.
 #include "hs_device.h"
@@ -18,6 +18,7 @@ constexpr int kWaves = kTile / 64;  // wavefronts per workgroup
 constexpr int kWin = 256;           // items per window
 constexpr int kBatch = 8;           // chunks whose words one wavefront loads together
 constexpr int kQueue = 128;         // live-chunk queue per wavefront (power of two)
+constexpr int kUnit = 16;           // items per unit of work
 
 __device__ __forceinline__ int64_t item_count(const QueryWs& ws) {
     return min((int64_t)ws.counters[kCtrItems], ws.item_cap);
@@ -131,7 +132,7 @@ __device__ __forceinline__ void filter_batch(const IndexView& ix, const QueryWs&
 // queue in LDS, and every kBatch queued chunks go through filter_batch, so
 // the LB_SAX work comes in full batches whatever fraction of chunks pass.
 template <int W16>
-__global__ void __launch_bounds__(256) k_filter(IndexView ix, ScanParams sp, QueryWs ws) {
+__global__ void __launch_bounds__(256, 4) k_filter(IndexView ix, ScanParams sp, QueryWs ws) {
     // the table first, at a fixed LDS address, so its row offsets fold into
     // the lookups' immediate offsets
     __shared__ float s_lut[lut_floats<W16>()];  // [16 W16][256], rows beyond w zero
@@ -139,6 +140,7 @@ __global__ void __launch_bounds__(256) k_filter(IndexView ix, ScanParams sp, Que
     __shared__ uint32_t s_pb[kWin], s_pe[kWin], s_c0[kWin];
     __shared__ float4 s_qst[64];                // query segment mean / std intervals
     __shared__ int s_end;
+    __shared__ long long s_unit;
     constexpr int kPass = 4;  // envelope loads in flight together
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
     int L = 1;
@@ -158,12 +160,14 @@ __global__ void __launch_bounds__(256) k_filter(IndexView ix, ScanParams sp, Que
     const int64_t slice = (int64_t)blockIdx.x * kWaves + wave;
     FilterOut o{ws.slice_pos + slice * ws.slice_cap, ws.slice_q + slice * ws.slice_cap,
                 ws.slice_part + slice * ws.slice_cap, 0u, 0ull, 0ull, 0ull, false};
-    int64_t i0, i1;
-    block_range(item_count(ws), i0, i1);
-    int64_t idx = i0;
+    // Items are dealt out in units of kUnit: a workgroup's first unit by its
+    // index, each next one from a counter once it has filtered the last, so
+    // workgroups whose items keep many candidates take fewer units.
+    const int64_t total = item_count(ws);
+    int64_t idx = (int64_t)blockIdx.x * kUnit, uend = min(total, idx + kUnit);
     int cur_q = -1;
-    while (idx < i1) {
-        const int n = (int)min((int64_t)kWin, i1 - idx);
+    while (idx < uend) {
+        const int n = (int)min((int64_t)kWin, uend - idx);
         const int q = (int)(ws.items[idx] >> 32);
         __syncthreads();  // no wave still reads the previous window or table
         if (t == 0) s_end = n;
@@ -263,6 +267,13 @@ __global__ void __launch_bounds__(256) k_filter(IndexView ix, ScanParams sp, Que
             atomicAdd(&ws.stats[(int64_t)q * 8 + 6], o.cand);
             atomicAdd(&ws.stats[(int64_t)q * 8 + 7], o.tests);
             if (o.lost) atomicOr(&ws.flags[q], kFlagCandLost);
+        }
+        if (idx >= uend) {
+            __syncthreads();  // every wave has read s_unit and the window
+            if (t == 0) s_unit = (long long)gridDim.x + (long long)atomicAdd(&ws.counters[kCtrWork], 1u);
+            __syncthreads();
+            idx = s_unit * kUnit;
+            uend = min(total, idx + kUnit);
         }
     }
     if (lane == 0) ws.slice_cnt[slice] = o.cnt;

@@ -147,7 +147,7 @@ def test_long_candidate_list():
     noise = g.standard_normal((64, n))
     noise = ((noise - noise.mean(1, keepdims=True)) / noise.std(1, keepdims=True)).astype(np.float32)
     q = np.concatenate([noise, G.workload(x, [10], 8, coll=77)[0]])
-    idx = make_index(x, w=16, leaf_size=2000, l_max=1, cand_per_query=N)
+    idx = make_index(x, w=16, leaf_size=2000, l_max=1, cand_per_query=2 * N)
     ids, d2, st = run_knn(idx, q, k, stats=True)
     cands = int(st["candidates"].sum().item())
     print(f"[long list] candidates {cands}", flush=True)
