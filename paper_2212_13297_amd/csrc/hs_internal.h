@@ -43,7 +43,8 @@ constexpr int kCtrRefine = 5;    // work-distribution counter of the refine kern
 constexpr int kCtrOvf = 6;       // entries reserved in the overflow slice
 constexpr int kCtrOvfEnd = 7;    // smallest base of an overflow range that did not fit (UINT32_MAX if none):
                                  // overflow entries at or above it were never written
-constexpr int kNumCounters = 8;
+constexpr int kCtrBound = 8;     // 8 slots: the bounding pass's work counter of each XCD
+constexpr int kNumCounters = 16;
 
 // Distance forms of the refinement (template argument F of the kernels that
 // refine): float32 sum in a fixed order, or compensated float32 (error-free

@@ -234,6 +234,7 @@ struct BoundMap {
     int GS;  // q-group stride of one workgroup
     int used;
     int xcd_aware;
+    int nper;  // xcd_aware: (row range, q-group) items per XCD, dealt from the XCD's counter
 };
 
 __device__ __forceinline__ void bound_block(const BoundMap& m, int b, int& g0, int& r) {
@@ -289,6 +290,7 @@ __global__ void __launch_bounds__(256) k_bound(IndexView ix, ShadowView sv, Scan
     __shared__ float s_xn[2][kBoundRows];     // ||x~||^2 per staged series
     __shared__ float2 s_aug[2][kBoundRows];   // ONE: (a*, ebar) per staged series, decoded
     __shared__ float s_acc[kTile / 64][16 * 64];  // per wavefront: its accumulators, on the rare float64 path
+    __shared__ int s_item;
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6, j = lane & 31, half = lane >> 5;
     // ONE: the series fit one K-block (stride <= 256) and the query fragments stay in registers
     const int K = ix.stride, nkb = ONE ? 1 : (K + kKBlock - 1) / kKBlock;
@@ -304,9 +306,30 @@ __global__ void __launch_bounds__(256) k_bound(IndexView ix, ShadowView sv, Scan
          e += (int64_t)gridDim.x * kTile)
         ws.slice_cnt[e] = 0;
 
-    if ((int)blockIdx.x < bm.used) {
-        int g0, r;
-        bound_block(bm, blockIdx.x, g0, r);
+    // Work items (q-group g, row range r).  XCD-aware: the workgroups of XCD x
+    // (b mod 8) take items i = u G + g, r = 8 u + x, from the XCD's counter, so
+    // the q-groups of one row range run at about the same time on one XCD
+    // (its L2 serves them the same series) and every workgroup keeps taking
+    // items while any are left.  Otherwise a fixed item per workgroup.
+    int wi = 0;
+    for (;;) {
+        int g, r;
+        if (bm.xcd_aware) {
+            __syncthreads();  // every wave has read s_item
+            if (t == 0) s_item = (int)atomicAdd(&ws.counters[kCtrBound + (blockIdx.x & 7)], 1u);
+            __syncthreads();
+            const int it = s_item;
+            if (it >= bm.nper) break;
+            g = it % bm.G;
+            r = (it / bm.G) * 8 + (int)(blockIdx.x & 7);
+        } else {
+            if ((int)blockIdx.x >= bm.used) break;
+            int g0;
+            bound_block(bm, blockIdx.x, g0, r);
+            g = g0 + wi * bm.GS;
+            if (g >= bm.G) break;
+            ++wi;
+        }
         const int64_t row0 = ix.N * r / bm.R, row1 = ix.N * (r + 1) / bm.R;
         // first part that ends after row0
         int64_t lo = 0, hi = ix.parts;
@@ -317,7 +340,7 @@ __global__ void __launch_bounds__(256) k_bound(IndexView ix, ShadowView sv, Scan
         }
         const int64_t p_first = lo;
 
-        for (int g = g0; g < bm.G; g += bm.GS) {
+        {
             // q-group g takes positions g 128 .. g 128 + 127 of the query order
             // (queries sorted by their best leaf), so the queries of one
             // wavefront tend to keep the same leaves and skip the same parts
@@ -628,9 +651,11 @@ hipError_t launch_bound(const IndexView& ix, const ShadowView& sv, const ScanPar
     BoundMap bm{};
     bm.G = ws.Qpad / kBoundQueries;
     if (bm.G * 8 <= grid) {
+        // about 4 items per workgroup, dealt out per XCD
         bm.xcd_aware = 1;
         bm.GS = bm.G;
-        bm.R = 8 * (grid / (8 * bm.G));
+        bm.R = 8 * std::max(1, (int)std::min<int64_t>(4 * (grid / (8 * bm.G)), ix.N / (8 * 64)));
+        bm.nper = (bm.R / 8) * bm.G;
     } else {
         bm.xcd_aware = 0;
         bm.GS = bm.G < grid ? bm.G : grid;
