@@ -66,11 +66,20 @@ __device__ __forceinline__ Meta load_meta(const QueryWs& ws, long long c, bool v
     return m;
 }
 
+typedef _Float16 half2_t __attribute__((ext_vector_type(2)));
+
+// The value a byte of the packed quarter bounds stands for.
+__device__ __forceinline__ float quarter_value(uint32_t byte) {
+    return (float)__builtin_bit_cast(_Float16, (uint16_t)(byte << 8));
+}
+
 // The order in which a series' quarters are read: the largest partial bound
 // first, equal bounds in natural order.  Quarter j of the order sits in bits
 // 2j and 2j + 1.  The bytes of the packed bounds order as their values; the
-// sort keys carry 3 - p in their low two bits.
-__device__ __forceinline__ uint32_t chunk_perm(uint32_t part) {
+// sort keys carry 3 - p in their low two bits.  rem: the bounds of the
+// quarters still unread after the first one and after the first two, each
+// divided by (1 + slack), as two fp16 rounded toward zero.
+__device__ __forceinline__ uint32_t chunk_perm(uint32_t part, uint32_t& rem) {
     uint32_t k[4];
 #pragma unroll
     for (int p = 0; p < 4; ++p) k[p] = (((part >> (8 * p)) & 0xffu) << 2) | (uint32_t)(3 - p);
@@ -87,6 +96,10 @@ __device__ __forceinline__ uint32_t chunk_perm(uint32_t part) {
     uint32_t perm = 0u;
 #pragma unroll
     for (int j = 0; j < 4; ++j) perm |= (3u - (k[j] & 3u)) << (2 * j);
+    const double v2 = quarter_value(k[2] >> 2), v3 = quarter_value(k[3] >> 2);
+    const double r2 = v2 + v3, r1 = (double)quarter_value(k[1] >> 2) + r2;  // exact
+    rem = __builtin_bit_cast(uint32_t, __builtin_amdgcn_cvt_pkrtz(__double2float_rd(r1 / (1.0 + kSlack)),
+                                                                   __double2float_rd(r2 / (1.0 + kSlack))));
     return perm;
 }
 
@@ -94,15 +107,14 @@ __device__ __forceinline__ uint32_t chunk_perm(uint32_t part) {
 // rounded down, from the exact float64 sum of the four packed partials (each
 // at most the float32 one), so lbs > limit implies LB_SAX > limit (1 + slack);
 // bsf, a BSF_k of the entry's query read before it is handed out (+inf until
-// then).  An entry without a candidate has x = 0xffffffff.
-__device__ __forceinline__ uint4 ring_entry(const Meta& m, bool ord) {
+// then).  An entry without a candidate has x = 0xffffffff.  rem: chunk_perm's
+// (0 in natural order).
+__device__ __forceinline__ uint4 ring_entry(const Meta& m, bool ord, uint32_t& rem) {
     double lb = 0.0;
 #pragma unroll
-    for (int p = 0; p < 4; ++p) {
-        const _Float16 h = __builtin_bit_cast(_Float16, (uint16_t)(((m.part >> (8 * p)) & 0xffu) << 8));
-        lb += (double)(float)h;
-    }
-    const uint32_t perm = ord ? chunk_perm(m.part) : kNaturalPerm;
+    for (int p = 0; p < 4; ++p) lb += (double)quarter_value((m.part >> (8 * p)) & 0xffu);
+    rem = 0u;
+    const uint32_t perm = ord ? chunk_perm(m.part, rem) : kNaturalPerm;
     return make_uint4(m.q < 0 ? 0xffffffffu : ((uint32_t)m.q | perm << 24), m.pos,
                       __float_as_uint(__double2float_rd(lb / (1.0 + kSlack))), 0x7f800000u);
 }
@@ -133,6 +145,7 @@ __global__ void __launch_bounds__(256, 4) k_refine(IndexView ix, ScanParams sp, 
     __shared__ unsigned long long s_top[kTile / 64][HS_KMAX];
     // ring_entry of the stream's candidate v at v mod 128
     __shared__ uint4 s_ring[kTile / 64][kRing];
+    __shared__ uint32_t s_rem[kTile / 64][kRing];  // the entries' rem (chunk_perm)
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6, sub = t & 15, grp = (t >> 4) & 3;
     const int k = sp.k;
     const int nchunks = ix.stride / kChunk;
@@ -142,6 +155,7 @@ __global__ void __launch_bounds__(256, 4) k_refine(IndexView ix, ScanParams sp, 
     const int olg = sp.order_lg;
     const bool ord = olg >= 0;
     const int omask = ord ? (1 << olg) - 1 : 0;
+    const int cpq = omask + 1;  // chunks per quarter
     const float marg = ord ? sp.order_marg : 1.0f;
     const long long T = ws.slice_start[ws.n_slices + 1];
     const long long gw = (long long)blockIdx.x * (kTile / 64) + wave, GW = (long long)gridDim.x * (kTile / 64);
@@ -175,6 +189,7 @@ __global__ void __launch_bounds__(256, 4) k_refine(IndexView ix, ScanParams sp, 
     };
     unsigned long long* top = s_top[wave];
     uint4* ring = s_ring[wave];
+    uint32_t* rring = s_rem[wave];
 
     // wavefront state, uniform: the query of the top-k and its k-th distance
     int cur_q = -1;
@@ -214,10 +229,10 @@ __global__ void __launch_bounds__(256, 4) k_refine(IndexView ix, ScanParams sp, 
         const bool va = vmap(lane, ca), vb = vmap(64 + lane, cb);
         const Meta a = load_meta(ws, ca, va, T, cur);
         const Meta b = load_meta(ws, cb, vb, T, cur);
-        uint4 ea = ring_entry(a, ord);
+        uint4 ea = ring_entry(a, ord, rring[lane]);
         ea.w = load_relaxed(&ws.bsf[max(a.q, 0)]);
         ring[lane] = ea;
-        ring[64 + lane] = ring_entry(b, ord);
+        ring[64 + lane] = ring_entry(b, ord, rring[64 + lane]);
         nsnap = bits_to_float(load_relaxed(&ws.bsf[max(b.q, 0)]));
         snap_idx = 64 + lane;
         snap_due = true;
@@ -232,7 +247,9 @@ __global__ void __launch_bounds__(256, 4) k_refine(IndexView ix, ScanParams sp, 
     auto write_pend = [&]() {
         if (snap_due) write_snap();
         snap_idx = ((int)(mb + 64) & (kRing - 1)) + lane;
-        ring[snap_idx] = ring_entry(pend, ord);
+        uint32_t rw;
+        ring[snap_idx] = ring_entry(pend, ord, rw);
+        rring[snap_idx] = rw;
         nsnap = bits_to_float(load_relaxed(&ws.bsf[max(pend.q, 0)]));
         snap_due = true;
         has_pend = false;
@@ -241,9 +258,9 @@ __global__ void __launch_bounds__(256, 4) k_refine(IndexView ix, ScanParams sp, 
 
     // slots, each the same in the 16 lanes of its group
     int sq[NS];            // query (-1: empty)
-    uint32_t spos[NS];     // stored position of the series
     int sc[NS];            // chunks added so far
     uint32_t sperm[NS];    // order of the quarters
+    uint32_t srem[NS];     // bounds of the quarters unread after one and after two (fp16 pair)
     float sthr[NS];        // abandoning limit
     const float* xp[NS];   // the lane's first point of the series and of the query
     const float* qp[NS];
@@ -252,9 +269,9 @@ __global__ void __launch_bounds__(256, 4) k_refine(IndexView ix, ScanParams sp, 
 #pragma unroll
     for (int s = 0; s < NS; ++s) {
         sq[s] = -1;
-        spos[s] = 0u;
         sc[s] = 0;
         sperm[s] = kNaturalPerm;
+        srem[s] = 0u;
         sthr[s] = INFINITY;
         xp[s] = ix.rows + sub * 4;
         qp[s] = ws.qrow + sub * 4;
@@ -325,9 +342,9 @@ __global__ void __launch_bounds__(256, 4) k_refine(IndexView ix, ScanParams sp, 
                     if (q == cur_q) lim = fminf(lim, lk);
                     const uint32_t pos = q >= 0 ? e.y : 0u;
                     sq[s] = q;
-                    spos[s] = pos;
                     sc[s] = 0;
                     sperm[s] = e.x >> 24;
+                    srem[s] = rring[ri & (kRing - 1)];
                     sd[s] = Dist<F>{};
                     sthr[s] = lim;
                     xp[s] = ix.rows + (int64_t)pos * ix.stride + sub * 4;
@@ -362,7 +379,14 @@ __global__ void __launch_bounds__(256, 4) k_refine(IndexView ix, ScanParams sp, 
             if (sq[s] >= 0) {
                 sd[s].add(qv[s], x[s]);
                 sc[s] += 1;
-                const bool over = sd[s].value() > sthr[s] * marg;
+                // cascade: after the first and the second quarter, the bounds of
+                // the quarters still unread are added to the running distance
+                float rest = 0.0f;
+                if (ord) {
+                    const half2_t h = __builtin_bit_cast(half2_t, srem[s]);
+                    rest = sc[s] == cpq ? (float)h.x : (sc[s] == 2 * cpq ? (float)h.y : 0.0f);
+                }
+                const bool over = sd[s].value() + rest > sthr[s] * marg;
                 fin[s] = over || sc[s] == nchunks;
                 adm[s] = fin[s] && !over;
                 slow = slow || adm[s] || (fin[s] && sq[s] != st_q);
@@ -425,7 +449,9 @@ __global__ void __launch_bounds__(256, 4) k_refine(IndexView ix, ScanParams sp, 
                 }
                 if (__builtin_amdgcn_readlane((int)adm[s], 16 * g)) {
                     const float v = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(sd[s].value()), 16 * g));
-                    const uint32_t kp = (uint32_t)__builtin_amdgcn_readlane(spos[s], 16 * g);
+                    // stored position of the series, from the lane's pointer (sub * 4 < stride)
+                    const uint32_t kp = (uint32_t)__builtin_amdgcn_readlane(
+                        (int)(uint32_t)((xp[s] - ix.rows) / ix.stride), 16 * g);
                     if (lane == 0) {
                         if (kq != new_q) {
                             flush_topk(ws, new_q, k, top, topn);
