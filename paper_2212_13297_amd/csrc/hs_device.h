@@ -281,8 +281,10 @@ __device__ __forceinline__ void flush_topk(const QueryWs& ws, int q, int k, cons
     if (base + cnt > (uint32_t)ws.P) atomicOr(&ws.flags[q], kFlagOverflow);
 }
 
-// Exclusive prefix sum over the 256 threads of a block; returns the offset of
-// this thread and writes the block total to *total.  s_w holds 4 ints.
+// Exclusive prefix sum over the 64 NW threads of a block (256 by default);
+// returns the offset of this thread and writes the block total to *total.
+// s_w holds NW ints.
+template <int NW = kTile / 64>
 __device__ __forceinline__ int block_exclusive_scan(int v, int* s_w, int* total) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     int inc = v;
@@ -295,7 +297,7 @@ __device__ __forceinline__ int block_exclusive_scan(int v, int* s_w, int* total)
     __syncthreads();
     int off = 0, tot = 0;
 #pragma unroll
-    for (int i = 0; i < kTile / 64; ++i) {
+    for (int i = 0; i < NW; ++i) {
         const int c = s_w[i];
         if (i < wave) off += c;
         tot += c;

@@ -98,16 +98,20 @@ __global__ void __launch_bounds__(256) k_lb_eapca(IndexView ix, QueryWs ws) {
 // BSF_k yet), and the k best by (d, id), found by a bitonic sort of the list's
 // keys, become the first pool entries and BSF_k.
 constexpr int kSeedList = 2048;
+constexpr int kSeedThreads = 512;  // one workgroup per query (two fit a CU: a batch of 512 queries runs at once)
+constexpr int kSeedWaves = kSeedThreads / 64;
+constexpr int kSeedBins = 2048 / kSeedThreads;  // histogram bins per thread
 
 template <int W16, int F>
-__global__ void __launch_bounds__(256) k_seed(IndexView ix, ScanParams sp, QueryWs ws) {
+__global__ void __launch_bounds__(kSeedThreads) k_seed(IndexView ix, ScanParams sp, QueryWs ws) {
+    constexpr int kPassRows = W16 == 1 ? 8 : (W16 == 2 ? 4 : 2);  // rows per thread per pass
     extern __shared__ float s_lut[];  // [16 W16][256], rows beyond w zero
     __shared__ uint32_t s_hist[2048];
     __shared__ unsigned long long s_keys[kSeedList];
     __shared__ uint32_t s_list[kSeedList];
     __shared__ uint32_t s_leaves[kMaxSeedLeaves];
-    __shared__ unsigned long long s_tmp[4];
-    __shared__ int s_w[4];
+    __shared__ unsigned long long s_tmp[kSeedWaves];
+    __shared__ int s_w[kSeedWaves];
     __shared__ uint32_t s_binlim;
     __shared__ int s_cnt;
     const int q = blockIdx.x, t = threadIdx.x, sub = t & 15, grp = t >> 4;
@@ -137,16 +141,16 @@ __global__ void __launch_bounds__(256) k_seed(IndexView ix, ScanParams sp, Query
     for (int li = 0; li < lm; ++li) {
         const int64_t b = ix.leaf_start[s_leaves[li]], e = ix.leaf_start[s_leaves[li] + 1];
         rows += e - b;
-        // 8 rows per thread per pass, their word loads in flight together
-        for (int64_t tb = b; tb < e; tb += 8 * (int64_t)blockDim.x) {
-            uint4 v[8][W16];
+        // kPassRows rows per thread per pass, their word loads in flight together
+        for (int64_t tb = b; tb < e; tb += kPassRows * (int64_t)blockDim.x) {
+            uint4 v[kPassRows][W16];
 #pragma unroll
-            for (int j = 0; j < 8; ++j) {
+            for (int j = 0; j < kPassRows; ++j) {
                 const int64_t r = min(tb + t + (int64_t)blockDim.x * j, e - 1);
                 load_word<W16>(ix.words + r * ix.wstride, v[j]);
             }
 #pragma unroll
-            for (int j = 0; j < 8; ++j) {
+            for (int j = 0; j < kPassRows; ++j) {
                 if (tb + t + (int64_t)blockDim.x * j < e) {
                     const float lb = lb_sax_word<W16>(v[j], s_lut);
                     atomicAdd(&s_hist[min(__float_as_uint(lb) >> 20, 2047u)], 1u);
@@ -156,30 +160,30 @@ __global__ void __launch_bounds__(256) k_seed(IndexView ix, ScanParams sp, Query
     }
     __syncthreads();
     // the cut: the first bin at which the cumulative count reaches the target
-    // (thread t owns bins 8t .. 8t + 7)
+    // (thread t owns bins kSeedBins t .. kSeedBins t + kSeedBins - 1)
     {
         const uint32_t want = (uint32_t)max(sp.seed_rows, 2 * k);
         int c8 = 0;
 #pragma unroll
-        for (int b = 0; b < 8; ++b) c8 += (int)s_hist[8 * t + b];
+        for (int b = 0; b < kSeedBins; ++b) c8 += (int)s_hist[kSeedBins * t + b];
         int tot;
-        uint32_t cum = (uint32_t)block_exclusive_scan(c8, s_w, &tot);
-        for (int b = 0; b < 8; ++b) {
+        uint32_t cum = (uint32_t)block_exclusive_scan<kSeedWaves>(c8, s_w, &tot);
+        for (int b = 0; b < kSeedBins; ++b) {
             const uint32_t before = cum;
-            cum += s_hist[8 * t + b];
-            if (before < want && cum >= want) s_binlim = 8 * t + b;  // one thread finds the crossing
+            cum += s_hist[kSeedBins * t + b];
+            if (before < want && cum >= want) s_binlim = kSeedBins * t + b;  // one thread finds the crossing
         }
     }
     __syncthreads();
     const uint32_t lim = s_binlim;
-    // gather the series whose LB_SAX bin does not exceed the cut (8 per thread
-    // per pass, one block scan per pass)
+    // gather the series whose LB_SAX bin does not exceed the cut (kPassRows per
+    // thread per pass, one block scan per pass)
     for (int li = 0; li < lm; ++li) {
         const int64_t b = ix.leaf_start[s_leaves[li]], e = ix.leaf_start[s_leaves[li] + 1];
-        for (int64_t tb = b; tb < e; tb += 8 * (int64_t)blockDim.x) {
+        for (int64_t tb = b; tb < e; tb += kPassRows * (int64_t)blockDim.x) {
             uint32_t pm = 0;
 #pragma unroll
-            for (int j = 0; j < 8; ++j) {
+            for (int j = 0; j < kPassRows; ++j) {
                 const int64_t r = tb + t + (int64_t)blockDim.x * j;
                 if (r < e) {
                     uint4 v[W16];
@@ -189,11 +193,11 @@ __global__ void __launch_bounds__(256) k_seed(IndexView ix, ScanParams sp, Query
                 }
             }
             int tot;
-            const int off = block_exclusive_scan(__popc(pm), s_w, &tot);
+            const int off = block_exclusive_scan<kSeedWaves>(__popc(pm), s_w, &tot);
             const int base = s_cnt;
             int o = base + off;
 #pragma unroll
-            for (int j = 0; j < 8; ++j) {
+            for (int j = 0; j < kPassRows; ++j) {
                 if ((pm >> j) & 1u) {
                     if (o < kSeedList) s_list[o] = (uint32_t)(tb + t + (int64_t)blockDim.x * j);
                     ++o;
@@ -210,7 +214,7 @@ __global__ void __launch_bounds__(256) k_seed(IndexView ix, ScanParams sp, Query
     // chunk order, as everywhere
     constexpr int kSeedRows = 4, kSeedChunks = 4;
     const float* qr = ws.qrow + (int64_t)q * ix.stride + sub * 4;
-    for (int i0 = grp * kSeedRows; i0 < M; i0 += (kTile / 16) * kSeedRows) {
+    for (int i0 = grp * kSeedRows; i0 < M; i0 += (kSeedThreads / 16) * kSeedRows) {
         int64_t pos[kSeedRows];
 #pragma unroll
         for (int r = 0; r < kSeedRows; ++r) pos[r] = s_list[min(i0 + r, M - 1)];
@@ -436,9 +440,9 @@ hipError_t launch_seed(const IndexView& ix, const ScanParams& sp, const QueryWs&
     if (sp.n_seed <= 0) return hipSuccess;
     const size_t lds = sizeof(float) * (size_t)16 * w16_of(ix) * kCard;
     if (form == kComp) {
-        HS_DISPATCH_W16_F(ix, k_seed, kComp, dim3(sp.Q), dim3(kTile), lds, st, ix, sp, ws);
+        HS_DISPATCH_W16_F(ix, k_seed, kComp, dim3(sp.Q), dim3(kSeedThreads), lds, st, ix, sp, ws);
     } else {
-        HS_DISPATCH_W16_F(ix, k_seed, kPlain, dim3(sp.Q), dim3(kTile), lds, st, ix, sp, ws);
+        HS_DISPATCH_W16_F(ix, k_seed, kPlain, dim3(sp.Q), dim3(kSeedThreads), lds, st, ix, sp, ws);
     }
     return hipGetLastError();
 }
