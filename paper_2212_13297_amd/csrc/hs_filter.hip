@@ -6,9 +6,9 @@
 // counter in a register (no atomics).  Items are ordered by query; workgroups
 // take units of consecutive items from a counter and stage them in LDS a
 // window at a time (a window holds items of one query); the workgroup's
-// wavefronts wait for each other only between windows.  After the filter, slice_prefix computes where
-// each slice starts in the candidate list, the slices' concatenation, which
-// the refine kernel reads in place.
+// wavefronts wait for each other only between windows.  After the filter,
+// slice_prefix computes where each slice starts in the candidate list, the
+// slices' concatenation, which the refine kernel reads in place.
 #include "hs_device.h"
 
 namespace hs {
@@ -18,7 +18,7 @@ constexpr int kWaves = kTile / 64;  // wavefronts per workgroup
 constexpr int kWin = 256;           // items per window
 constexpr int kBatch = 8;           // chunks whose words one wavefront loads together
 constexpr int kQueue = 128;         // live-chunk queue per wavefront (power of two)
-constexpr int kUnit = 16;           // items per unit of work
+constexpr int kUnit = 16;           // most items per unit of work
 
 __device__ __forceinline__ int64_t item_count(const QueryWs& ws) {
     return min((int64_t)ws.counters[kCtrItems], ws.item_cap);
@@ -160,11 +160,14 @@ __global__ void __launch_bounds__(256, 4) k_filter(IndexView ix, ScanParams sp, 
     const int64_t slice = (int64_t)blockIdx.x * kWaves + wave;
     FilterOut o{ws.slice_pos + slice * ws.slice_cap, ws.slice_q + slice * ws.slice_cap,
                 ws.slice_part + slice * ws.slice_cap, 0u, 0ull, 0ull, 0ull, false};
-    // Items are dealt out in units of kUnit: a workgroup's first unit by its
-    // index, each next one from a counter once it has filtered the last, so
-    // workgroups whose items keep many candidates take fewer units.
+    // Items are dealt out in units of up to kUnit (fewer for a short item
+    // list, so that a small batch still spreads over the GPU): a workgroup's
+    // first unit by its index, each next one from a counter once it has
+    // filtered the last, so workgroups whose items keep many candidates take
+    // fewer units.
     const int64_t total = item_count(ws);
-    int64_t idx = (int64_t)blockIdx.x * kUnit, uend = min(total, idx + kUnit);
+    const int64_t unit = max((int64_t)1, min((int64_t)kUnit, total / ((int64_t)gridDim.x * 4)));
+    int64_t idx = (int64_t)blockIdx.x * unit, uend = min(total, idx + unit);
     int cur_q = -1;
     while (idx < uend) {
         const int n = (int)min((int64_t)kWin, uend - idx);
@@ -272,8 +275,8 @@ __global__ void __launch_bounds__(256, 4) k_filter(IndexView ix, ScanParams sp, 
             __syncthreads();  // every wave has read s_unit and the window
             if (t == 0) s_unit = (long long)gridDim.x + (long long)atomicAdd(&ws.counters[kCtrWork], 1u);
             __syncthreads();
-            idx = s_unit * kUnit;
-            uend = min(total, idx + kUnit);
+            idx = s_unit * unit;
+            uend = min(total, idx + unit);
         }
     }
     if (lane == 0) ws.slice_cnt[slice] = o.cnt;
