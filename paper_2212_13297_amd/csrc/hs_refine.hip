@@ -139,7 +139,9 @@ __device__ __forceinline__ uint4 ring_entry(const Meta& m, bool ord, uint32_t& r
 // series within its limit, or retire a candidate of another query, go
 // through lane 0, which alone keeps the wavefront's top-k in LDS and
 // publishes its improvements with atomicMin.
-template <int F, int NS>
+// Q1: one chunk per quarter in the chunk order (n = 256): the chunk index is a
+// field of the order word and the cascade's bounds shift out as it is read.
+template <int F, int NS, bool Q1>
 __global__ void __launch_bounds__(256, 4) k_refine(IndexView ix, ScanParams sp, QueryWs ws) {
     constexpr int kRing = 128;
     __shared__ unsigned long long s_top[kTile / 64][HS_KMAX];
@@ -261,7 +263,7 @@ __global__ void __launch_bounds__(256, 4) k_refine(IndexView ix, ScanParams sp, 
     int sc[NS];            // chunks added so far
     uint32_t sperm[NS];    // order of the quarters
     uint32_t srem[NS];     // bounds of the quarters unread after one and after two (fp16 pair)
-    float sthr[NS];        // abandoning limit
+    float sthr[NS];        // abandoning limit times marg
     const float* xp[NS];   // the lane's first point of the series and of the query
     const float* qp[NS];
     Dist<F> sd[NS];
@@ -346,7 +348,7 @@ __global__ void __launch_bounds__(256, 4) k_refine(IndexView ix, ScanParams sp, 
                     sperm[s] = e.x >> 24;
                     srem[s] = rring[ri & (kRing - 1)];
                     sd[s] = Dist<F>{};
-                    sthr[s] = lim;
+                    sthr[s] = lim * marg;
                     xp[s] = ix.rows + (int64_t)pos * ix.stride + sub * 4;
                     qp[s] = ws.qrow + (int64_t)max(q, 0) * ix.stride + sub * 4;
                     fin[s] = q >= 0 && __uint_as_float(e.z) > lim;  // skipped: ask again
@@ -366,7 +368,9 @@ __global__ void __launch_bounds__(256, 4) k_refine(IndexView ix, ScanParams sp, 
         float4 x[NS], qv[NS];
 #pragma unroll
         for (int s = 0; s < NS; ++s) {
-            const int c = ord ? ((int)((sperm[s] >> ((sc[s] >> olg) << 1)) & 3u) << olg) | (sc[s] & omask) : sc[s];
+            const int c = Q1    ? (int)((sperm[s] >> (2 * sc[s])) & 3u)
+                          : ord ? ((int)((sperm[s] >> ((sc[s] >> olg) << 1)) & 3u) << olg) | (sc[s] & omask)
+                                : sc[s];
             x[s] = *reinterpret_cast<const float4*>(xp[s] + c * kChunk);
             qv[s] = *reinterpret_cast<const float4*>(qp[s] + c * kChunk);
         }
@@ -382,11 +386,14 @@ __global__ void __launch_bounds__(256, 4) k_refine(IndexView ix, ScanParams sp, 
                 // cascade: after the first and the second quarter, the bounds of
                 // the quarters still unread are added to the running distance
                 float rest = 0.0f;
-                if (ord) {
+                if (Q1) {
+                    rest = (float)__builtin_bit_cast(half2_t, srem[s]).x;
+                    srem[s] >>= 16;
+                } else if (ord) {
                     const half2_t h = __builtin_bit_cast(half2_t, srem[s]);
                     rest = sc[s] == cpq ? (float)h.x : (sc[s] == 2 * cpq ? (float)h.y : 0.0f);
                 }
-                const bool over = sd[s].value() + rest > sthr[s] * marg;
+                const bool over = sd[s].value() + rest > sthr[s];
                 fin[s] = over || sc[s] == nchunks;
                 adm[s] = fin[s] && !over;
                 slow = slow || adm[s] || (fin[s] && sq[s] != st_q);
@@ -482,7 +489,7 @@ __global__ void __launch_bounds__(256, 4) k_refine(IndexView ix, ScanParams sp, 
         lk = __shfl(new_lk, 0, 64);
 #pragma unroll
         for (int s = 0; s < NS; ++s)
-            if (sq[s] == cur_q) sthr[s] = fminf(sthr[s], lk);
+            if (sq[s] == cur_q) sthr[s] = fminf(sthr[s], lk * marg);
     }
     if (lane == 0) flush_topk(ws, cur_q, k, top, topn);
     flush_counters();
@@ -492,10 +499,16 @@ __global__ void __launch_bounds__(256, 4) k_refine(IndexView ix, ScanParams sp, 
 
 hipError_t launch_refine(const IndexView& ix, const ScanParams& sp, const QueryWs& ws, int device_cus, int form,
                          hipStream_t st) {
-#define HS_REFINE(FF, NS) \
-    k_refine<FF, NS><<<dim3(resident_grid(k_refine<FF, NS>, kTile, 0, device_cus)), dim3(kTile), 0, st>>>(ix, sp, ws)
-    if (form == kComp) HS_REFINE(kComp, kRefineSlots);
-    else HS_REFINE(kPlain, kRefineSlots);
+#define HS_REFINE(FF, NS, QQ) \
+    k_refine<FF, NS, QQ><<<dim3(resident_grid(k_refine<FF, NS, QQ>, kTile, 0, device_cus)), dim3(kTile), 0, st>>>(ix, sp, ws)
+    const bool q1 = sp.order_lg == 0;
+    if (form == kComp) {
+        if (q1) HS_REFINE(kComp, kRefineSlots, true);
+        else HS_REFINE(kComp, kRefineSlots, false);
+    } else {
+        if (q1) HS_REFINE(kPlain, kRefineSlots, true);
+        else HS_REFINE(kPlain, kRefineSlots, false);
+    }
 #undef HS_REFINE
     return hipGetLastError();
 }
