@@ -258,6 +258,8 @@ __global__ void __launch_bounds__(256, 4) k_refine(IndexView ix, ScanParams sp, 
     };
     long long next = 0;  // stream position of the next candidate to hand out (uniform)
 
+    const float* rows_sub = ix.rows + sub * 4;  // the lane's first point of stored row 0 and of query 0
+    const float* qrow_sub = ws.qrow + sub * 4;
     // slots, each the same in the 16 lanes of its group
     int sq[NS];            // query (-1: empty)
     int sc[NS];            // chunks added so far
@@ -275,8 +277,8 @@ __global__ void __launch_bounds__(256, 4) k_refine(IndexView ix, ScanParams sp, 
         sperm[s] = kNaturalPerm;
         srem[s] = 0u;
         sthr[s] = INFINITY;
-        xp[s] = ix.rows + sub * 4;
-        qp[s] = ws.qrow + sub * 4;
+        xp[s] = rows_sub;
+        qp[s] = qrow_sub;
         fin[s] = true;
     }
 
@@ -349,8 +351,9 @@ __global__ void __launch_bounds__(256, 4) k_refine(IndexView ix, ScanParams sp, 
                     srem[s] = rring[ri & (kRing - 1)];
                     sd[s] = Dist<F>{};
                     sthr[s] = lim * marg;
-                    xp[s] = ix.rows + (int64_t)pos * ix.stride + sub * 4;
-                    qp[s] = ws.qrow + (int64_t)max(q, 0) * ix.stride + sub * 4;
+                    // one 32 x 32 -> 64-bit multiply each (pos, q and stride are non-negative)
+                    xp[s] = rows_sub + (uint64_t)pos * (uint32_t)ix.stride;
+                    qp[s] = qrow_sub + (uint64_t)(uint32_t)max(q, 0) * (uint32_t)ix.stride;
                     fin[s] = q >= 0 && __uint_as_float(e.z) > lim;  // skipped: ask again
                     again = again || fin[s];
                 }
