@@ -274,6 +274,32 @@ def run_serving(args, hs, torch, G, idx256, x256):
     return out
 
 
+def run_ablation(args, torch, variants, q, pct, levels, ref_ids):
+    """Plain form per noise level under each access-path variant: queries/s
+    (each level's queries as one batch, 3 timed calls after 1 warm-up) and
+    whether the id lists equal the default index's."""
+    out = {}
+    ref = ref_ids.cpu().numpy()
+    for name, ix in variants.items():
+        row = {}
+        for p in levels:
+            sel = np.where(pct == p)[0]
+            qt = torch.from_numpy(np.ascontiguousarray(q[sel])).to("cuda:0")
+            ix.knn(qt, args.k)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(3):
+                res = ix.knn(qt, args.k)
+            torch.cuda.synchronize()
+            dt = (time.perf_counter() - t0) / 3
+            same = int((res[0].cpu().numpy() == ref[sel]).all(axis=1).sum())
+            row[f"{p}%"] = {"queries_per_s": round(len(sel) / dt, 1), "ms": round(dt * 1e3, 3),
+                            "identical_id_lists": f"{same}/{len(sel)}"}
+        out[name] = row
+        log(f"ablation {name}: {row}")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -294,7 +320,9 @@ def main():
     ap.add_argument("--forms", default="plain,mixed,serving",
                     help="plain: the paper's filter-and-refine (always timed, the headline value); mixed: also "
                          "the precision form (bf16 copy, matrix-core bound, compensated refine) on the same index; "
-                         "serving: the continuous-batching server over three collections under Poisson arrivals")
+                         "serving: the continuous-batching server over three collections under Poisson arrivals; "
+                         "ablation: the plain form per noise level with the LB_SAX filter always on (the default), "
+                         "skipped (NoSAX) and skipped below the paper's leaf-pruning threshold 0.25")
     ap.add_argument("--serve-rate", type=float, default=2000.0, help="Poisson arrival rate (queries/s)")
     ap.add_argument("--serve-seconds", type=float, default=30.0, help="measured arrival window (s)")
     ap.add_argument("--serve-warmup", type=float, default=5.0, help="arrivals before the measured window (s)")
@@ -345,6 +373,13 @@ def main():
     # library's read probe over the input (5 passes)
     read_gbs = hs.read_probe_gbs(xt, passes=5)
     log(f"read stream (probe over {xt.numel() * 4 / 1e9:.2f} GB): {read_gbs:.0f} GB/s")
+    # ablation indexes: same data and leaves, other access-path thresholds (eapca_th)
+    abl_idx = {}
+    if "ablation" in args.forms.split(",") and not args.profile_run:
+        for name, th in (("nosax", 1.1), ("thresh_0.25", 0.25)):
+            abl_idx[name] = hs.Index(xt, hs.Params(w=args.w, leaf_size=args.leaf, l_max=args.l_max,
+                                                   seed_rows=args.seed_rows, eapca_th=th))
+        torch.cuda.synchronize()
     del xt
     torch.cuda.empty_cache()
 
@@ -432,6 +467,12 @@ def main():
     if "serving" in args.forms.split(",") and not args.profile_run:
         serving = run_serving(args, hs, torch, G, idx, x)
 
+    ablation = None
+    if abl_idx:
+        ablation = run_ablation(args, torch, {"sax": idx, **abl_idx}, q, pct, levels, ids)
+        for v in abl_idx.values():
+            v.close()
+
     cpu = None
     parity = None
     if not args.no_cpu_baseline and not args.profile_run and args.cpu_sample > 0:
@@ -501,6 +542,7 @@ def main():
         "parity_sample": parity,
         "precision_form": mixed,
         "serving_form": serving,
+        "ablation": ablation,
     }
     print(json.dumps(out), flush=True)
     idx.close()
