@@ -3,11 +3,12 @@
 // re-checked against the current BSF_k; per-wavefront top-k, BSF_k published
 // with atomicMin, results appended to the per-query pool.
 //
-// Every wavefront owns a contiguous range of the candidate list (regions are
-// ordered by query, so a range holds long runs of one query) and never waits
-// for another wavefront.  Its 16-lane groups refine a few series each, one
-// 64-point chunk per round, abandoning a series as soon as its running
-// distance exceeds the limit and taking the next candidate in its place.
+// Wavefronts take runs of consecutive candidates (the list is ordered by
+// query, so a run holds long stretches of one query) and never wait for one
+// another.  Their 16-lane groups refine a few series each, one 64-point chunk
+// per round, in the order of the series' LB_SAX quarter bounds, abandoning a
+// series as soon as its running distance, plus the bounds of its unread
+// quarters, exceeds the limit, and taking the next candidate in its place.
 #include "hs_device.h"
 
 namespace hs {
@@ -121,13 +122,16 @@ __device__ __forceinline__ uint4 ring_entry(const Meta& m, bool ord, uint32_t& r
 
 // F: distance form.  NS: candidates in flight per 16-lane group.
 //
-// Every wavefront owns a contiguous range of the candidate list.  Each of its
-// four groups keeps NS slots; a round loads one 64-point chunk of every
-// slot's series (and the query's chunk), adds the chunk's partial to the
-// slot's running distance, and retires the slots whose distance exceeds
-// their limit (abandoned) or whose series is complete.  Retired slots take
-// the next candidates of the range at once, so every round reads NS useful
-// chunks per group however early candidates are abandoned.
+// A wavefront refines a stream of candidates: one contiguous range of a short
+// list, or segments of kSeg of a long one, its first by its index and each
+// next one from a counter when its ring reaches it (so wavefronts that meet
+// costly candidates take fewer segments).  Each of its four groups keeps NS
+// slots; a round loads one 64-point chunk of every slot's series (and the
+// query's chunk), adds the chunk's partial to the slot's running distance,
+// and retires the slots whose distance exceeds their limit (abandoned) or
+// whose series is complete.  Retired slots take the next candidates of the
+// stream at once, so every round reads NS useful chunks per group however
+// early candidates are abandoned.
 //
 // The candidates' metadata pass through a ring of 128 entries in LDS per
 // wavefront (the next 64 are loaded while the current ones are handed out),
