@@ -188,6 +188,29 @@ def test_mixed_without_seed():
     check_err(x, q, ids, d2, err)
 
 
+def test_mixed_white_noise_queries():
+    # White-noise queries (z-normalised) are far from every series: LB_SAX
+    # keeps nearly all of them, the matrix-core bound about one in 120.  The
+    # results, their error bounds and the plain form's id lists still agree.
+    N, n, k = 200_000, 256, 10
+    x = G.random_walks(N, n, coll=78)
+    g = np.random.Generator(np.random.PCG64(np.random.SeedSequence([78, 1])))
+    noise = g.standard_normal((64, n))
+    noise = ((noise - noise.mean(1, keepdims=True)) / noise.std(1, keepdims=True)).astype(np.float32)
+    q = np.concatenate([noise, G.workload(x, [10], 8, coll=78)[0]])
+    idx = make_index(x, P.BF16, w=16, leaf_size=2000, l_max=1, cand_per_query=2 * N)
+    ids, d2, err, st = knn_mixed(idx, q, k, stats=True)
+    # a query whose candidates spread over hundreds of wavefronts can fill its
+    # result pool with their flushed top-k lists and take the fallback round
+    print(f"[white noise, precision form] candidates {int(st['candidates'].sum())}, "
+          f"fallback rounds on {int((st['rounds'] > 1).sum())} queries", flush=True)
+    check_knn(x, q, k, ids, d2)
+    check_err(x, q, ids, d2, err)
+    pids, _ = knn_plain(idx, q, k)
+    assert np.array_equal(ids, pids)
+    idx.close()
+
+
 def test_mixed_errors():
     hs = hs_mod()
     x = G.random_walks(3000, 64, coll=65)
