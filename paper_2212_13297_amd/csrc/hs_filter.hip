@@ -16,7 +16,7 @@ namespace {
 
 constexpr int kWaves = kTile / 64;  // wavefronts per workgroup
 constexpr int kWin = 256;           // items per window
-constexpr int kBatch = 8;           // chunks whose words one wavefront loads together
+constexpr int kBatch = 6;           // chunks whose words one wavefront loads together
 constexpr int kQueue = 128;         // live-chunk queue per wavefront (power of two)
 constexpr int kUnit = 16;           // most items per unit of work
 
