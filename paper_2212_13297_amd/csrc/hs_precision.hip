@@ -651,10 +651,10 @@ hipError_t launch_bound(const IndexView& ix, const ShadowView& sv, const ScanPar
     BoundMap bm{};
     bm.G = ws.Qpad / kBoundQueries;
     if (bm.G * 8 <= grid) {
-        // about 4 items per workgroup, dealt out per XCD
+        // about 8 items per workgroup, dealt out per XCD
         bm.xcd_aware = 1;
         bm.GS = bm.G;
-        bm.R = 8 * std::max(1, (int)std::min<int64_t>(4 * (grid / (8 * bm.G)), ix.N / (8 * 64)));
+        bm.R = 8 * std::max(1, (int)std::min<int64_t>(8 * (grid / (8 * bm.G)), ix.N / (8 * 64)));
         bm.nper = (bm.R / 8) * bm.G;
     } else {
         bm.xcd_aware = 0;
