@@ -165,17 +165,25 @@ typedef struct {
  *  q_dev     float32 [Q][n] queries, row-major.
  *  ws_dev    workspace of at least hs_query_workspace_bytes(idx, Q, k).
  *  ids_dev   int64 [Q][k] out: original row indices of x_dev.
- *  d2_dev    float32 [Q][k] out: squared Euclidean distances computed in
- *            float32 (fixed per-pair summation order).
+ *  d2_dev    float32 [Q][k] out: squared Euclidean distances, each the
+ *            compensated float32 sum of the pair (error-free transformations
+ *            on every step, a fixed natural order), so a pair always gets the
+ *            same value whatever the batch or the access path.
+ *  err_dev   float64 [Q][k] out, or NULL: a-priori bound of |d2 - d| for
+ *            each result, d the exact squared distance:
+ *            (2^-23 + (4 K + 64) 2^-48) d2 for K = row_stride stored points.
  *  stats_dev hs_query_stats [Q] out, or NULL.
- * Each query's results are sorted by (d2, id) ascending; they are the exact
- * k nearest series by the float32 distance, which agrees with float64 up to
- * a relative error below 2e-6.
+ * Each query's results are sorted by (d2, id) ascending and are the exact k
+ * nearest series by d2.  Early abandoning tests a cheaper running sum against
+ * the limit times a margin that covers its larger error, so no series whose
+ * d2 is within the limit is abandoned.  With d2 within 1.2e-7 relative of d,
+ * the id set differs from the exact k-NN only among series whose exact
+ * distances lie within 2.4e-7 relative of the k-th.
  * Errors: HS_EINVAL (k < 1, k > HS_KMAX, k > N, Q < 0, Q >= 2^24, NULL
- * pointers), HS_ENOMEM (workspace too small), HS_EHIP.
+ * pointers, NaN/Inf in a query), HS_ENOMEM (workspace too small), HS_EHIP.
  */
 hs_status hs_knn_exact(hs_index* idx, const float* q_dev, int32_t Q, int32_t k, void* ws_dev,
-                       int64_t ws_bytes, int64_t* ids_dev, float* d2_dev, void* stats_dev,
+                       int64_t ws_bytes, int64_t* ids_dev, float* d2_dev, double* err_dev, void* stats_dev,
                        void* stream);
 
 /*
@@ -218,13 +226,10 @@ hs_status hs_shadow_bytes(const hs_index* idx, int32_t kind, int64_t* bytes);
 hs_status hs_build_shadow(hs_index* idx, int32_t kind, void* shadow_dev, int64_t shadow_bytes, void* stream);
 
 /*
- * Exact k-NN of Q queries through the precision form.  Arguments as for
- * hs_knn_exact (same workspace size), plus
- *  err_dev   float64 [Q][k] out, or NULL: a-priori bound of
- *            |d2 - d(q, x)| for each result, d the exact squared distance
- *            (compensated float32: (2^-23 + (4 K + 64) 2^-48) d2).
- * d2 is the compensated float32 distance.  The id lists equal
- * hs_knn_exact's up to ties within the distances' error.
+ * Exact k-NN of Q queries through the precision form.  Arguments, result
+ * keys (the compensated float32 distance d2) and error bounds as for
+ * hs_knn_exact (same workspace size): the ids and distances equal
+ * hs_knn_exact's.
  * Errors: as hs_knn_exact; HS_EINVAL if the index has no low-precision copy
  * or a query is beyond the fp16 range of an HS_SHADOW_FP16 copy.
  */
@@ -277,7 +282,7 @@ typedef struct {
     double t_done;           /* its batch was seen complete */
     int64_t ids[HS_KMAX];    /* first k entries: original row ids, by (d2, id) ascending */
     float d2[HS_KMAX];       /* squared distances (float32; compensated in the precision form) */
-    double err[HS_KMAX];     /* precision form: bound of |d2 - d|; plain form: 0 */
+    double err[HS_KMAX];     /* a-priori bound of |d2 - d| (as hs_knn_exact's err_dev) */
 } hs_completion;
 
 typedef struct {

@@ -267,7 +267,7 @@ int64_t ws_layout(const hs_index* idx, int32_t Q, int32_t k, QueryWs* ws, char* 
     carve(cur, (void**)&w.qst32, (int64_t)Q * ix.w * 16);
     carve(cur, (void**)&w.lut, (int64_t)Q * ix.w * kCard * 4);
     carve(cur, (void**)&w.lbe, (int64_t)Q * ix.L * 4);
-    carve(cur, (void**)&w.bsf, (int64_t)Q * 4);
+    carve(cur, (void**)&w.bkey, (int64_t)Q * 8);
     carve(cur, (void**)&w.pool_cnt, (int64_t)Q * 4);
     carve(cur, (void**)&w.flags, (int64_t)Q * 4);
     carve(cur, (void**)&w.kept, (int64_t)Q * 4);
@@ -531,6 +531,26 @@ namespace {
 // one rounding of the final sum plus second-order terms of the residues.
 double comp_err_rel(int K) { return std::ldexp(1.0, -23) + (4.0 * K + 64.0) * std::ldexp(1.0, -48); }
 
+// Abandoning margin for K stored points (m = K / 64 chunks).  A running
+// distance v, plain float32 partials added in any chunk order plus one
+// addition of the cascade's bounds, passes through at most m + 10 roundings
+// per term (2 for the difference squared, 4 in the lane's fma chain, 4 in the
+// butterfly, m - 1 running additions, 1 for the bounds); with two to spare,
+// v <= d (1 + g), g = (m + 12) u / (1 - (m + 12) u), u = 2^-24.  The
+// compensated running form is tighter.  The result key c satisfies
+// c >= d (1 - e_c), and fl(limit * marg) >= limit * marg (1 - u).  So
+// v > fl(limit * marg) implies c > limit when
+// marg >= (1 + g) / ((1 - u)(1 - e_c)); the float32 value is rounded up.
+float abandon_margin(int K) {
+    const double u = std::ldexp(1.0, -24);
+    const double r = (double)(K / kChunk + 12) * u;
+    const double g = r / (1.0 - r);
+    const double mg = (1.0 + g) / ((1.0 - u) * (1.0 - comp_err_rel(K)));
+    float mf = (float)mg;
+    if ((double)mf < mg) mf = std::nextafter(mf, INFINITY);
+    return mf;
+}
+
 }  // namespace
 
 namespace hs {
@@ -559,7 +579,8 @@ hs_status knn_prepare(hs_index* idx, int32_t Q, int32_t k, void* ws_dev, int64_t
     c->idx = idx;
     c->mixed = mixed;
     c->form = mixed ? kComp : kPlain;
-    c->err_rel = mixed ? comp_err_rel(idx->view.stride) : 0.0;
+    // both forms key their results by the compensated distance
+    c->err_rel = comp_err_rel(idx->view.stride);
     if (Q == 0) return HS_OK;
     if (!ws_dev) return fail(HS_EINVAL, "NULL workspace");
     const int64_t need = ws_layout(idx, Q, k, nullptr, nullptr);
@@ -573,8 +594,7 @@ hs_status knn_prepare(hs_index* idx, int32_t Q, int32_t k, void* ws_dev, int64_t
     c->sp.n_seed = (int)std::min<int64_t>(std::min<int64_t>(idx->p.l_max, ix.L), kMaxSeedLeaves);
     c->sp.seed_rows = idx->p.seed_rows;
     c->sp.order_lg = chunk_order_lg(ix);
-    // g = (m - 1) u / (1 - (m - 1) u) for m chunk partials, u = 2^-24; 4 m u + 2^-20 covers 2 g and the rounding
-    c->sp.order_marg = (float)(1.0 + 4.0 * (double)(ix.stride / kChunk) * std::ldexp(1.0, -24) + std::ldexp(1.0, -20));
+    c->sp.marg = abandon_margin(ix.stride);
     return HS_OK;
 }
 
@@ -683,8 +703,8 @@ int64_t shadow_layout(const IndexView& ix, uint16_t** rows, float4** norms, uint
 extern "C" {
 
 hs_status hs_knn_exact(hs_index* idx, const float* q_dev, int32_t Q, int32_t k, void* ws_dev, int64_t ws_bytes,
-                       int64_t* ids_dev, float* d2_dev, void* stats_dev, void* stream) {
-    return run_knn(idx, q_dev, Q, k, ws_dev, ws_bytes, ids_dev, d2_dev, nullptr, stats_dev, stream, false);
+                       int64_t* ids_dev, float* d2_dev, double* err_dev, void* stats_dev, void* stream) {
+    return run_knn(idx, q_dev, Q, k, ws_dev, ws_bytes, ids_dev, d2_dev, err_dev, stats_dev, stream, false);
 }
 
 hs_status hs_knn_mixed(hs_index* idx, const float* q_dev, int32_t Q, int32_t k, void* ws_dev, int64_t ws_bytes,

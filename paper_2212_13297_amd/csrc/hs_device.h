@@ -6,9 +6,16 @@
 // Distances: 16 lanes own one series; lane l holds points 4l..4l+3 of every
 // 64-point chunk.  A chunk's partial is the lane's sequential fma chain over
 // its 4 points, summed over the 16 lanes by a xor butterfly (commutative, so
-// every lane holds the same value); d adds the chunk partials in chunk order.
-// Every kernel uses this order, so a (query, series) pair always gets the
-// same float32 distance.
+// every lane holds the same value).  Two forms:
+//  - the running distance that early abandoning tests: plain float32 partials
+//    (or compensated ones in the precision form) added in whatever chunk
+//    order the kernel reads;
+//  - the result key of a series that completes within its limit: the
+//    compensated distance (Dist<kComp>) summed in natural chunk order, whose
+//    relative error is below 2^-23 + (4K + 64) 2^-48 for K stored points.
+// Every kernel keys its results the same way, so a (query, series) pair
+// always gets the same float32 distance, and the abandoning limit carries a
+// margin (ScanParams::marg) that covers the running form's larger error.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -28,6 +35,16 @@ __device__ __forceinline__ float bits_to_float(uint32_t b) { return __uint_as_fl
 
 __device__ __forceinline__ uint32_t load_relaxed(const uint32_t* p) {
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ unsigned long long load_relaxed64(const unsigned long long* p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// BSF_k of query q as float bits: the high word of its result key bound
+// (little-endian), read on its own.
+__device__ __forceinline__ uint32_t bsf_bits(const QueryWs& ws, int q) {
+    return load_relaxed(reinterpret_cast<const uint32_t*>(ws.bkey + q) + 1);
 }
 
 // A bound prunes only when it exceeds BSF_k by the relative slack.
@@ -222,11 +239,24 @@ struct Dist<kComp> {
     }
 };
 
+// Result key distance of one series: the compensated distance in natural
+// chunk order, by the 16 lanes of a group (all 16 active together).  xr / qr
+// point at the lane's first point.
+__device__ __forceinline__ float key_distance(const float* __restrict__ xr, const float* __restrict__ qr,
+                                              int nchunks) {
+    Dist<kComp> d;
+    for (int c = 0; c < nchunks; ++c)
+        d.add(*reinterpret_cast<const float4*>(qr + c * kChunk), *reinterpret_cast<const float4*>(xr + c * kChunk));
+    return d.value();
+}
+
 // Squared distance of one series, computed by the 16 lanes of a group (all 16
 // active together).  xr / qr point at the lane's first point.  Chunks are
-// loaded two at a time; after each pair the running sum is compared with
-// thr and the series is abandoned once it exceeds it (the final sum can only
-// be larger).  `chunks` counts the chunks read.
+// loaded two at a time; after each pair the running sum (form F) is compared
+// with thr (the limit times ScanParams::marg) and the series is abandoned once
+// it exceeds it.  A series that completes gets its result key distance: the
+// running sum itself in the compensated form, else key_distance (the chunks
+// are read again).  `chunks` counts the chunks read.
 template <int F>
 __device__ __forceinline__ float refine_row(const float* __restrict__ xr, const float* __restrict__ qr,
                                            int nchunks, float thr, bool& alive, unsigned& chunks) {
@@ -245,7 +275,9 @@ __device__ __forceinline__ float refine_row(const float* __restrict__ xr, const 
             break;
         }
     }
-    return d.value();
+    if (F == kComp || !alive) return d.value();
+    chunks += (unsigned)nchunks;
+    return key_distance(xr, qr, nchunks);
 }
 
 // Insert key into the ascending list top[0..n) of capacity k (one thread).
@@ -260,20 +292,19 @@ __device__ __forceinline__ void topk_insert(unsigned long long* top, int& n, int
     if (n < k) ++n;
 }
 
-// Publish a block's top-k for query q (one thread): tighten BSF_k with its
-// k-th distance, then append the entries that do not exceed BSF_k to the pool.
+// Publish a block's top-k for query q (one thread): tighten the query's key
+// bound with its k-th key, then append the entries whose keys do not exceed
+// the bound to the pool.  Keys, not distances, are compared, so series tied
+// at the k-th distance beyond the k-th id are not appended again and again.
 __device__ __forceinline__ void flush_topk(const QueryWs& ws, int q, int k, const unsigned long long* top, int n) {
     if (q < 0 || n == 0) return;
-    float g = bits_to_float(load_relaxed(&ws.bsf[q]));
-    if (n == k) {
-        const uint32_t kb = (uint32_t)(top[k - 1] >> 32);
-        if (bits_to_float(kb) < g) {
-            atomicMin(&ws.bsf[q], kb);
-            g = bits_to_float(kb);
-        }
+    unsigned long long g = load_relaxed64(&ws.bkey[q]);
+    if (n == k && top[k - 1] < g) {
+        atomicMin(&ws.bkey[q], top[k - 1]);
+        g = top[k - 1];
     }
     int cnt = 0;
-    while (cnt < n && bits_to_float((uint32_t)(top[cnt] >> 32)) <= g) ++cnt;
+    while (cnt < n && top[cnt] <= g) ++cnt;
     if (cnt == 0) return;
     const uint32_t base = atomicAdd(&ws.pool_cnt[q], (uint32_t)cnt);
     for (int j = 0; j < cnt; ++j)

@@ -193,7 +193,7 @@ __global__ void __launch_bounds__(256, 4) k_filter(IndexView ix, ScanParams sp, 
         const bool skip = (ws.flags[q] & kFlagSkipSax) != 0;
         // largest float32 not above the prune limit: for a float32 bound b,
         // b <= thr exactly when (double) b <= limit
-        const float thr = __double2float_rd(prune_limit(bits_to_float(ws.bsf[q])));
+        const float thr = __double2float_rd(prune_limit(bits_to_float(bsf_bits(ws, q))));
         const float4 qs = s_qst[seg];
         o.filt = o.cand = o.tests = 0;
         o.lost = false;

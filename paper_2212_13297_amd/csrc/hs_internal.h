@@ -15,6 +15,8 @@ constexpr int kTile = 256;          // threads per scan / filter / refine workgr
 constexpr int kPartRows = 8192;     // series per work item: leaves are cut into parts of at most this many
 constexpr int kChunkRows = 64;      // series per chunk envelope (one wavefront's rows in the filter)
 constexpr uint32_t kInfBits = 0x7f800000u;  // +inf as float bits
+// result key bound before any result: distance +inf, the largest id
+constexpr unsigned long long kInfKey = ((unsigned long long)kInfBits << 32) | 0xffffffffull;
 constexpr int kMaxSeedLeaves = 64;  // l_max is clamped to this many leaves in the seed step
 
 // Relative slack on every prune comparison: a bound is compared against
@@ -92,7 +94,10 @@ struct QueryWs {
     float4* qst32;        // [Q][w] float32 intervals holding them: (mu_lo, mu_hi, sd_lo, sd_hi)
     float* lut;           // [Q][w][256] LB_SAX table: (n/w) * gap^2, rounded down
     float* lbe;           // [Q][L] LB_EAPCA^2, rounded down
-    uint32_t* bsf;        // [Q] float bits of the current BSF_k (monotone, atomicMin)
+    // [Q] the smallest k-th result key (d bits << 32 | id) known so far, an
+    // upper bound of the final k-th key (monotone, atomicMin); its high word
+    // is BSF_k as float bits
+    unsigned long long* bkey;
     uint32_t* pool_cnt;   // [Q]
     uint32_t* flags;      // [Q] kFlag* bits
     uint32_t* kept;       // [Q] candidate leaves after the leaf filter
@@ -127,11 +132,16 @@ struct ScanParams {
     int32_t seed_rows;  // series refined by the seed step
     // chunk order of the refine: -1 natural order; otherwise log2 of the
     // chunks per quarter of the series (stride = n = 256 2^order_lg, w a
-    // multiple of 16), and order_marg >= (1 + g) / (1 - g), g the float32
-    // summation bound of nchunks partials: a reordered running distance above
-    // limit * order_marg proves the natural-order one above the limit
+    // multiple of 16)
     int32_t order_lg;
-    float order_marg;
+    // abandoning margin: a running distance (any chunk order, either form,
+    // plus the cascade's bounds of unread quarters) above fl(limit * marg)
+    // proves the pair's result key, its compensated natural-order distance,
+    // above the limit.  marg >= (1 + g) / ((1 - u)(1 - e_c)): g bounds the
+    // running sum's relative excess over the exact distance (m + 12 roundings
+    // for m chunks), e_c the compensated distance's relative error, u = 2^-24
+    // the rounding of the product
+    float marg;
 };
 
 // kernel launchers (hs_kernels.hip); all asynchronous on `st`

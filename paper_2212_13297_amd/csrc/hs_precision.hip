@@ -352,7 +352,7 @@ __global__ void __launch_bounds__(256) k_bound(IndexView ix, ShadowView sv, Scan
             uint4 bq_aug = make_uint4(0, 0, 0, 0);  // ONE: (1, sTbar) at k = 256, 257 (half 0)
             if (qvalid) {
                 const double2 qn = ws.qnorm[qj];
-                bsf_j = bits_to_float(ws.bsf[qj]);
+                bsf_j = bits_to_float(bsf_bits(ws, qj));
                 const double T = prune_limit(bsf_j);
                 if (T < 1e300) {  // no BSF_k yet: every pair passes the float32 test
                     sT = __double2float_ru((sqrt(T) + qn.y) * (1.0 + 0x1p-40));

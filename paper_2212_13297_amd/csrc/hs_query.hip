@@ -60,7 +60,7 @@ __global__ void __launch_bounds__(256) k_query_prep(IndexView ix, const float* _
         ws.lut[(int64_t)q * ix.w * kCard + idx] = __double2float_rd(scale * g * g);
     }
     if (t == 0) {
-        ws.bsf[q] = kInfBits;
+        ws.bkey[q] = kInfKey;
         ws.pool_cnt[q] = 0;
         ws.flags[q] = s_bad ? kFlagNonFinite : 0u;
         ws.kept[q] = 0;
@@ -96,13 +96,14 @@ __global__ void __launch_bounds__(256) k_lb_eapca(IndexView ix, QueryWs ws) {
 // LB_SAX values, at most kSeedList.  The selected series are gathered into a
 // list, refined together (16 lanes per series; no abandoning, the block has no
 // BSF_k yet), and the k best by (d, id), found by a bitonic sort of the list's
-// keys, become the first pool entries and BSF_k.
+// keys, become the first pool entries and BSF_k.  Every distance here is a
+// result key (compensated, natural chunk order).
 constexpr int kSeedList = 2048;
 constexpr int kSeedThreads = 512;  // one workgroup per query (two fit a CU: a batch of 512 queries runs at once)
 constexpr int kSeedWaves = kSeedThreads / 64;
 constexpr int kSeedBins = 2048 / kSeedThreads;  // histogram bins per thread
 
-template <int W16, int F>
+template <int W16>
 __global__ void __launch_bounds__(kSeedThreads) k_seed(IndexView ix, ScanParams sp, QueryWs ws) {
     constexpr int kPassRows = W16 == 1 ? 8 : (W16 == 2 ? 4 : 2);  // rows per thread per pass
     extern __shared__ float s_lut[];  // [16 W16][256], rows beyond w zero
@@ -218,7 +219,7 @@ __global__ void __launch_bounds__(kSeedThreads) k_seed(IndexView ix, ScanParams 
         int64_t pos[kSeedRows];
 #pragma unroll
         for (int r = 0; r < kSeedRows; ++r) pos[r] = s_list[min(i0 + r, M - 1)];
-        Dist<F> d[kSeedRows];
+        Dist<kComp> d[kSeedRows];
         for (int c = 0; c < nchunks; c += kSeedChunks) {
             float4 qa[kSeedChunks], xa[kSeedRows][kSeedChunks];
 #pragma unroll
@@ -269,7 +270,7 @@ __global__ void __launch_bounds__(kSeedThreads) k_seed(IndexView ix, ScanParams 
     if (t == 0) {
         if (ws.best_leaf) ws.best_leaf[q] = s_leaves[0];
         ws.pool_cnt[q] = (uint32_t)n;
-        if (n == k) ws.bsf[q] = (uint32_t)(s_keys[k - 1] >> 32);
+        if (n == k) ws.bkey[q] = s_keys[k - 1];
         unsigned long long* st = ws.stats + (int64_t)q * 8;
         st[1] += (unsigned long long)rows;
         st[2] += (unsigned long long)M;
@@ -286,7 +287,7 @@ __global__ void __launch_bounds__(256) k_emit(IndexView ix, ScanParams sp, int32
     const int q = blockIdx.x, t = threadIdx.x;
     const uint32_t f = ws.flags[q];
     if (redo_only && !(f & kFlagInRound)) return;
-    const double thr = prune_limit(bits_to_float(ws.bsf[q]));
+    const double thr = prune_limit(bits_to_float(bsf_bits(ws, q)));
     const float* lbe = ws.lbe + (int64_t)q * ix.L;
     if (!redo_only) {
         int kept = 0;
@@ -368,7 +369,7 @@ __global__ void __launch_bounds__(1024) k_merge(IndexView ix, ScanParams sp, int
         }
         ws.flags[q] = nf;
         ws.pool_cnt[q] = (uint32_t)u;
-        if (u == k) atomicMin(&ws.bsf[q], (uint32_t)(s_keys[k - 1] >> 32));
+        if (u == k) atomicMin(&ws.bkey[q], s_keys[k - 1]);
         if (sp.final_pass) ws.stats[(int64_t)q * 8 + 5] += 1;
     }
     __syncthreads();
@@ -438,12 +439,9 @@ hipError_t launch_lb_eapca(const IndexView& ix, int32_t Q, const QueryWs& ws, hi
 
 hipError_t launch_seed(const IndexView& ix, const ScanParams& sp, const QueryWs& ws, int form, hipStream_t st) {
     if (sp.n_seed <= 0) return hipSuccess;
+    (void)form;  // the seed keys its results in the compensated form for both forms
     const size_t lds = sizeof(float) * (size_t)16 * w16_of(ix) * kCard;
-    if (form == kComp) {
-        HS_DISPATCH_W16_F(ix, k_seed, kComp, dim3(sp.Q), dim3(kSeedThreads), lds, st, ix, sp, ws);
-    } else {
-        HS_DISPATCH_W16_F(ix, k_seed, kPlain, dim3(sp.Q), dim3(kSeedThreads), lds, st, ix, sp, ws);
-    }
+    HS_DISPATCH_W16(ix, k_seed, dim3(sp.Q), dim3(kSeedThreads), lds, st, ix, sp, ws);
     return hipGetLastError();
 }
 

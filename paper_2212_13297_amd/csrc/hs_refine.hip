@@ -156,13 +156,13 @@ __global__ void __launch_bounds__(256, 4) k_refine(IndexView ix, ScanParams sp, 
     const int k = sp.k;
     const int nchunks = ix.stride / kChunk;
     // chunk order: quarters in the ring entry's order, chunks of a quarter in
-    // natural order; a reordered running distance is tested against
-    // limit * marg, which proves the natural-order distance above the limit
+    // natural order; the running distance is tested against limit * marg,
+    // which proves the result key (compensated, natural order) above the limit
     const int olg = sp.order_lg;
     const bool ord = olg >= 0;
     const int omask = ord ? (1 << olg) - 1 : 0;
     const int cpq = omask + 1;  // chunks per quarter
-    const float marg = ord ? sp.order_marg : 1.0f;
+    const float marg = sp.marg;
     const long long T = ws.slice_start[ws.n_slices + 1];
     const long long gw = (long long)blockIdx.x * (kTile / 64) + wave, GW = (long long)gridDim.x * (kTile / 64);
     // The wavefront's stream of candidates: list entries startA .. startA +
@@ -201,7 +201,7 @@ __global__ void __launch_bounds__(256, 4) k_refine(IndexView ix, ScanParams sp, 
     int cur_q = -1;
     float lk = INFINITY;
     int topn = 0;                                     // lane 0
-    float pub = INFINITY;                             // lane 0: k-th distance last published for cur_q
+    unsigned long long pub = kInfKey;                 // lane 0: k-th key last published for cur_q
     // refined series and chunks read for query st_q (uniform), per group
     int st_q = -1;
     uint32_t g_ref = 0u;  // < 2^31 candidates per wavefront
@@ -236,10 +236,10 @@ __global__ void __launch_bounds__(256, 4) k_refine(IndexView ix, ScanParams sp, 
         const Meta a = load_meta(ws, ca, va, T, cur);
         const Meta b = load_meta(ws, cb, vb, T, cur);
         uint4 ea = ring_entry(a, ord, rring[lane]);
-        ea.w = load_relaxed(&ws.bsf[max(a.q, 0)]);
+        ea.w = bsf_bits(ws, max(a.q, 0));
         ring[lane] = ea;
         ring[64 + lane] = ring_entry(b, ord, rring[64 + lane]);
-        nsnap = bits_to_float(load_relaxed(&ws.bsf[max(b.q, 0)]));
+        nsnap = bits_to_float(bsf_bits(ws, max(b.q, 0)));
         snap_idx = 64 + lane;
         snap_due = true;
     }
@@ -256,7 +256,7 @@ __global__ void __launch_bounds__(256, 4) k_refine(IndexView ix, ScanParams sp, 
         uint32_t rw;
         ring[snap_idx] = ring_entry(pend, ord, rw);
         rring[snap_idx] = rw;
-        nsnap = bits_to_float(load_relaxed(&ws.bsf[max(pend.q, 0)]));
+        nsnap = bits_to_float(bsf_bits(ws, max(pend.q, 0)));
         snap_due = true;
         has_pend = false;
     };
@@ -419,14 +419,17 @@ __global__ void __launch_bounds__(256, 4) k_refine(IndexView ix, ScanParams sp, 
                 }
             continue;
         }
-        if (ord) {
-            // a series read out of natural order and completed within its
-            // limit gets its distance again in natural order, the one every
-            // kernel computes for the pair (results and their keys agree)
+        // a series completed within its limit gets its result key distance,
+        // the compensated one in natural chunk order that every kernel keys
+        // the pair with: read again unless the running sum already is that
+        // (precision form, natural order)
+        float kv[NS];
+        {
             bool rc[NS], anyrc = false;
 #pragma unroll
             for (int s = 0; s < NS; ++s) {
-                rc[s] = adm[s] && sperm[s] != kNaturalPerm;
+                kv[s] = sd[s].value();
+                rc[s] = adm[s] && (F == kPlain || sperm[s] != kNaturalPerm);
                 anyrc = anyrc || rc[s];
             }
             if (__ballot(anyrc)) {
@@ -434,11 +437,7 @@ __global__ void __launch_bounds__(256, 4) k_refine(IndexView ix, ScanParams sp, 
                 for (int s = 0; s < NS; ++s) {
                     if (!__ballot(rc[s])) continue;
                     if (rc[s]) {
-                        Dist<F> d{};
-                        for (int c = 0; c < nchunks; ++c)
-                            d.add(*reinterpret_cast<const float4*>(qp[s] + c * kChunk),
-                                  *reinterpret_cast<const float4*>(xp[s] + c * kChunk));
-                        sd[s] = d;
+                        kv[s] = key_distance(xp[s], qp[s], nchunks);
                         sc[s] += nchunks;  // chunks read again
                     }
                 }
@@ -462,7 +461,7 @@ __global__ void __launch_bounds__(256, 4) k_refine(IndexView ix, ScanParams sp, 
                     g_ch += (unsigned long long)sc[s];
                 }
                 if (__builtin_amdgcn_readlane((int)adm[s], 16 * g)) {
-                    const float v = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(sd[s].value()), 16 * g));
+                    const float v = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(kv[s]), 16 * g));
                     // stored position of the series, from the lane's pointer (sub * 4 < stride)
                     const uint32_t kp = (uint32_t)__builtin_amdgcn_readlane(
                         (int)(uint32_t)((xp[s] - ix.rows) / ix.stride), 16 * g);
@@ -479,16 +478,16 @@ __global__ void __launch_bounds__(256, 4) k_refine(IndexView ix, ScanParams sp, 
         }
         float new_lk = INFINITY;
         if (lane == 0) {
-            if (new_q != cur_q) pub = INFINITY;
+            if (new_q != cur_q) pub = kInfKey;
             if (new_q >= 0 && topn == k) {
-                const uint32_t kb = (uint32_t)(top[k - 1] >> 32);
-                new_lk = bits_to_float(kb);
-                // BSF_k only decreases: every improvement of this wavefront's
-                // k-th distance is published, without reading the global value
-                // back (a load here would hold up the next round)
-                if (new_lk < pub) {
-                    atomicMin(&ws.bsf[new_q], kb);
-                    pub = new_lk;
+                const unsigned long long kk = top[k - 1];
+                new_lk = bits_to_float((uint32_t)(kk >> 32));
+                // the key bound only decreases: every improvement of this
+                // wavefront's k-th key is published, without reading the
+                // global value back (a load here would hold up the next round)
+                if (kk < pub) {
+                    atomicMin(&ws.bkey[new_q], kk);
+                    pub = kk;
                 }
             }
         }

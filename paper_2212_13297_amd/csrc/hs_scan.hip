@@ -47,7 +47,7 @@ __global__ void __launch_bounds__(256) k_leaf_scan(IndexView ix, ScanParams sp, 
             sh.st_filt = 0;
             sh.st_ref = 0;
             sh.st_chunks = 0;
-            sh.thr = bits_to_float(load_relaxed(&ws.bsf[q]));
+            sh.thr = bits_to_float(bsf_bits(ws, q));
         }
         const bool skip_sax = (ws.flags[q] & kFlagSkipSax) != 0;
         const int64_t b = ix.part_start[part], e = ix.part_start[part + 1];
@@ -76,8 +76,8 @@ __global__ void __launch_bounds__(256) k_leaf_scan(IndexView ix, ScanParams sp, 
             for (int h = grp; h < nh; h += kTile / 16) {
                 const int64_t pos = b + sh.hits[h];
                 bool alive;
-                const float d = refine_row<F>(ix.rows + pos * ix.stride + sub * 4, s_q + sub * 4, nchunks, thr, alive,
-                                           my_chunks);
+                const float d = refine_row<F>(ix.rows + pos * ix.stride + sub * 4, s_q + sub * 4, nchunks,
+                                              thr * sp.marg, alive, my_chunks);
                 if (sub == 0) {
                     ++my_ref;
                     if (alive)
@@ -90,7 +90,7 @@ __global__ void __launch_bounds__(256) k_leaf_scan(IndexView ix, ScanParams sp, 
                 for (int i = 0; i < sh.nres; ++i) topk_insert(sh.top, n, k, sh.res[i]);
                 sh.topn = n;
                 sh.nres = 0;
-                const float g = bits_to_float(load_relaxed(&ws.bsf[q]));
+                const float g = bits_to_float(bsf_bits(ws, q));
                 const float lk = n == k ? bits_to_float((uint32_t)(sh.top[k - 1] >> 32)) : INFINITY;
                 sh.thr = fminf(g, lk);
             }

@@ -128,13 +128,13 @@ hs_status launch_batch(hs_server* s, StreamSlot& sl) {
         hipError_t e = hipMemcpyAsync(sl.q_dev, sl.q_host, (size_t)qp * n * 4, hipMemcpyHostToDevice, sl.st);
         hs_status hs_st = e == hipSuccess ? HS_OK : fail(HS_EHIP, "capture: %s", hipGetErrorString(e));
         if (!hs_st)
-            hs_st = knn_enqueue(ge.call, sl.q_dev, sl.ids_dev, sl.d2_dev, ge.call.mixed ? sl.err_dev : nullptr,
+            hs_st = knn_enqueue(ge.call, sl.q_dev, sl.ids_dev, sl.d2_dev, sl.err_dev,
                                 nullptr, sl.st, sl.redo_host, nullptr);
         if (!hs_st) {
             e = hipMemcpyAsync(sl.ids_host, sl.ids_dev, (size_t)qp * k_run * 8, hipMemcpyDeviceToHost, sl.st);
             if (e == hipSuccess)
                 e = hipMemcpyAsync(sl.d2_host, sl.d2_dev, (size_t)qp * k_run * 4, hipMemcpyDeviceToHost, sl.st);
-            if (e == hipSuccess && ge.call.mixed)
+            if (e == hipSuccess)
                 e = hipMemcpyAsync(sl.err_host, sl.err_dev, (size_t)qp * k_run * 8, hipMemcpyDeviceToHost, sl.st);
             if (e != hipSuccess) hs_st = fail(HS_EHIP, "capture: %s", hipGetErrorString(e));
         }
@@ -174,12 +174,12 @@ void finish_batch(hs_server* s, StreamSlot& sl, hs_status failed = HS_OK) {
         msg = "non-finite query in a batch";
     } else if (sl.redo_host[0]) {
         const KnnCall& c = sl.running->call;
-        status = knn_finish(c, sl.ids_dev, sl.d2_dev, c.mixed ? sl.err_dev : nullptr, nullptr, sl.st, nullptr);
+        status = knn_finish(c, sl.ids_dev, sl.d2_dev, sl.err_dev, nullptr, sl.st, nullptr);
         hipError_t e = hipSuccess;
         if (!status) e = hipMemcpyAsync(sl.ids_host, sl.ids_dev, (size_t)qp * k_run * 8, hipMemcpyDeviceToHost, sl.st);
         if (!status && e == hipSuccess)
             e = hipMemcpyAsync(sl.d2_host, sl.d2_dev, (size_t)qp * k_run * 4, hipMemcpyDeviceToHost, sl.st);
-        if (!status && e == hipSuccess && c.mixed)
+        if (!status && e == hipSuccess)
             e = hipMemcpyAsync(sl.err_host, sl.err_dev, (size_t)qp * k_run * 8, hipMemcpyDeviceToHost, sl.st);
         if (!status && e == hipSuccess) e = hipStreamSynchronize(sl.st);
         if (!status && e != hipSuccess) status = fail(HS_EHIP, "overflow round: %s", hipGetErrorString(e));
@@ -202,7 +202,7 @@ void finish_batch(hs_server* s, StreamSlot& sl, hs_status failed = HS_OK) {
         for (int j = 0; j < r.k; ++j) {
             c.ids[j] = sl.ids_host[i * k_run + j];
             c.d2[j] = sl.d2_host[i * k_run + j];
-            c.err[j] = s->form[sl.coll] ? sl.err_host[i * k_run + j] : 0.0;
+            c.err[j] = sl.err_host[i * k_run + j];
         }
     }
     std::lock_guard<std::mutex> g(s->mu);

@@ -72,7 +72,8 @@ _SIGS = {
     "hs_get_leaves": (ctypes.c_int32, [_P, _P, _P]),
     "hs_get_chunks": (ctypes.c_int32, [_P, _P, _P]),
     "hs_query_workspace_bytes": (ctypes.c_int32, [_P, ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(ctypes.c_int64)]),
-    "hs_knn_exact": (ctypes.c_int32, [_P, _P, ctypes.c_int32, ctypes.c_int32, _P, ctypes.c_int64, _P, _P, _P, _P]),
+    "hs_knn_exact": (ctypes.c_int32, [_P, _P, ctypes.c_int32, ctypes.c_int32, _P, ctypes.c_int64, _P, _P, _P, _P,
+                                      _P]),
     "hs_shadow_bytes": (ctypes.c_int32, [_P, ctypes.c_int32, ctypes.POINTER(ctypes.c_int64)]),
     "hs_build_shadow": (ctypes.c_int32, [_P, ctypes.c_int32, _P, ctypes.c_int64, _P]),
     "hs_knn_mixed": (ctypes.c_int32, [_P, _P, ctypes.c_int32, ctypes.c_int32, _P, ctypes.c_int64, _P, _P, _P, _P,
@@ -173,8 +174,8 @@ def hs_query_workspace_bytes(h, Q: int, k: int) -> int:
 
 
 def hs_knn_exact(h, q_ptr: int, Q: int, k: int, ws_ptr: int, ws_bytes: int, ids_ptr: int, d2_ptr: int,
-                 stats_ptr: int, stream: int) -> None:
-    _check(load().hs_knn_exact(h, q_ptr, Q, k, ws_ptr, ws_bytes, ids_ptr, d2_ptr, stats_ptr, stream))
+                 err_ptr: int, stats_ptr: int, stream: int) -> None:
+    _check(load().hs_knn_exact(h, q_ptr, Q, k, ws_ptr, ws_bytes, ids_ptr, d2_ptr, err_ptr, stats_ptr, stream))
 
 
 def hs_shadow_bytes(h, kind: int) -> int:
@@ -420,8 +421,9 @@ class Index:
             return ids, d2, err, {f: st[:, i] for i, f in enumerate(STATS_FIELDS)}
         return ids, d2, err
 
-    def knn(self, q, k: int, stats: bool = False, stream=None, out=None):
-        """Exact k-NN: returns (ids int64 [Q, k], d2 float32 [Q, k]) [, stats dict of tensors]."""
+    def knn(self, q, k: int, stats: bool = False, stream=None, out=None, err: bool = False):
+        """Exact k-NN: returns (ids int64 [Q, k], d2 float32 [Q, k]) [, err float64 [Q, k] if err]
+        [, stats dict of tensors]."""
         import torch
         Q = self._check_q(q)
         ws, nbytes = self.workspace(Q, k)
@@ -430,12 +432,15 @@ class Index:
             d2 = torch.empty((Q, k), dtype=torch.float32, device=self.device)
         else:
             ids, d2 = out
+        eb = torch.empty((Q, k), dtype=torch.float64, device=self.device) if err else None
         st = torch.zeros((Q, 8), dtype=torch.int64, device=self.device) if stats else None
         hs_knn_exact(self.h, q.data_ptr(), Q, k, ws.data_ptr(), nbytes, ids.data_ptr(), d2.data_ptr(),
-                     st.data_ptr() if st is not None else None, _stream_ptr(stream))
+                     eb.data_ptr() if eb is not None else None, st.data_ptr() if st is not None else None,
+                     _stream_ptr(stream))
+        res = (ids, d2) + ((eb,) if err else ())
         if stats:
-            return ids, d2, {f: st[:, i] for i, f in enumerate(STATS_FIELDS)}
-        return ids, d2
+            return res + ({f: st[:, i] for i, f in enumerate(STATS_FIELDS)},)
+        return res
 
     def close(self):
         if getattr(self, "h", None):

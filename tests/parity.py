@@ -43,3 +43,17 @@ def check_knn(x, q, k, ids, d2, oids=None, od=None, qsel=None):
             da = od[j][list(oids[j]).index(a)]
             assert abs(da - dk) <= band, f"query {i}: oracle id {a} (d={da}) missing (kth={dk})"
     return oids, od
+
+
+def check_err(x, q, ids, d2, err):
+    """|d2 - d64| <= err <= 1e-5 d64 for every result; returns the largest
+    measured relative error."""
+    ids = np.asarray(ids)
+    Q, k = ids.shape
+    qi = np.repeat(np.arange(Q, dtype=np.int32), k)
+    d64 = brute.pair_dist(x, q, qi, ids.reshape(-1)).reshape(Q, k)
+    meas = np.abs(np.asarray(d2, dtype=np.float64) - d64)
+    err = np.asarray(err, dtype=np.float64)
+    assert np.all(meas <= err), f"measured error above the reported bound: {np.max(meas - err)}"
+    assert np.all(err <= REL_D * d64), "reported bound above 1e-5 relative"
+    return float(np.max(meas / np.maximum(d64, 1e-30)))

@@ -14,7 +14,7 @@ from oracle import brute
 from oracle import summaries as S
 from paper_2212_13297_amd import datagen as G
 
-from parity import check_knn
+from parity import check_err, check_knn
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -161,8 +161,10 @@ def test_long_candidate_list():
 def test_knn_parity(N, n, w, tau, l_max, k):
     x, q = workload(N, n, coll=N % 97 + n)
     idx = make_index(x, w=w, leaf_size=tau, l_max=l_max)
-    ids, d2, st = run_knn(idx, q, k, stats=True)
+    ids, d2, err, st = run_knn(idx, q, k, stats=True, err=True)
     check_knn(x, q, k, ids, d2)
+    # every distance within its stated a-priori bound (about 1.2e-7 relative)
+    check_err(x, q, ids, d2, err)
     st = {f: v.cpu().numpy() for f, v in st.items()}
     assert np.all(st["rounds"] >= 1)
     assert np.all(st["rows_refined"] >= k)
@@ -200,16 +202,117 @@ def test_results_do_not_depend_on_access_path():
 
 
 def test_overflow_fallback_rounds():
-    # one series per leaf and a seed that cannot fill k: every series is an
-    # LB_SAX survivor, the 16-entry candidate lists overflow, and the fused
-    # fallback appends one entry per single-series item, overflowing the
-    # 4096-entry result pool too: the answer still matches the oracle
-    x, q = workload(6000, 64, coll=13, per_level=1, ood=1)
+    # One series per leaf and a seed that cannot fill k = 128: every series is
+    # an LB_SAX survivor and the candidate list (a handful of entries per
+    # filter wavefront) overflows, so the first round refines only about a
+    # thousand candidates per query and its 128-th key is loose (about the
+    # 12 % quantile of the distances).  In the fallback round every
+    # single-series item is its own block, whose top list never fills k, so
+    # the bound does not tighten inside the round: every series below that
+    # key (about 12,000 of 100,000) is appended, more than the 4096-entry
+    # result pool holds.  A third round follows, with the bound from the
+    # entries that fit; the answer still matches the oracle.
+    x, q = workload(100_000, 64, coll=13, per_level=1, ood=1)
     idx = make_index(x, w=8, leaf_size=1, l_max=1, cand_per_query=16)
-    ids, d2, st = run_knn(idx, q, 10, stats=True)
-    check_knn(x, q, 10, ids, d2)
+    ids, d2, st = run_knn(idx, q, 128, stats=True)
+    check_knn(x, q, 128, ids, d2)
     rounds = st["rounds"].cpu().numpy()
+    print(f"[fallback] rounds {rounds.tolist()}", flush=True)
     assert np.all(rounds >= 2)
+    assert rounds.max() >= 3
+    idx.close()
+
+
+def test_many_exact_duplicates_at_the_kth_distance():
+    # 9,000 exact copies of one series (more than the 4096-entry result pool):
+    # a query equal to it, or near it, has all of them at one distance.  The
+    # pool takes entries by result key (d, id), not by distance alone, so the
+    # rounds end and the answer is the copies with the smallest ids.
+    x = G.random_walks(30_000, 128, coll=31).copy()
+    dup = np.arange(7, 30_000, 3)[:9000]
+    x[dup] = x[5]
+    g = np.random.Generator(np.random.PCG64(np.random.SeedSequence([31, 2])))
+    near = x[5].astype(np.float64) + 0.01 * g.standard_normal(128)
+    near = ((near - near.mean()) / near.std()).astype(np.float32)
+    q = np.stack([x[5], near, x[20_000]]).astype(np.float32)
+    for cpq in (0, 16):
+        idx = make_index(x, w=16, leaf_size=1000, l_max=1, cand_per_query=cpq)
+        ids, d2, st = run_knn(idx, q, 10, stats=True)
+        oids, od = check_knn(x, q, 10, ids, d2)
+        assert np.array_equal(ids, oids)
+        assert list(ids[0]) == [5] + list(dup[:9]) and np.all(d2[0] == 0)
+        print(f"[duplicates] cand_per_query {cpq}: rounds {st['rounds'].cpu().numpy().tolist()}", flush=True)
+        idx.close()
+
+
+def _grid_offsets(rng, n, m, delta, lim):
+    """m integer vectors c_j (|c| <= lim) whose sums of squares are
+    T_j = T_0 (1 + j delta), each rounded up to the next integer that the
+    two adjusted coordinates reach as a sum of two squares (a few units in
+    about 1e9).  Returns (c [m, n], T [m])."""
+    from math import isqrt
+    base = rng.integers(-(lim // 2), lim // 2 + 1, n).astype(np.int64)
+    base[:2] = 0
+    S = int((base ** 2).sum())
+    T0 = S + lim * lim // 4
+    cs, Ts = [], []
+    for j in range(m):
+        R = round(T0 * (1.0 + j * delta)) - S
+        assert 0 <= R <= lim * lim
+        c = base.copy()
+        while True:
+            a = isqrt(R)
+            while a >= 0 and 2 * a * a >= R:
+                b2 = R - a * a
+                b = isqrt(b2)
+                if b * b == b2:
+                    break
+                a -= 1
+            if a >= 0 and 2 * a * a >= R:
+                c[0], c[1] = a, isqrt(R - a * a)
+                break
+            R += 1
+        cs.append(c)
+        Ts.append(S + R)
+    return np.stack(cs), np.asarray(Ts, dtype=np.int64)
+
+
+@pytest.mark.parametrize("n,w,l_max", [(256, 16, 0), (256, 16, 2), (1024, 32, 1)])
+def test_planted_near_ties_outside_the_tie_band(n, w, l_max):
+    # Around each query's k-th position, 2k planted series whose exact squared
+    # distances T_j 2^-42 are spaced 1.2e-6, 2e-6 or 3e-6 relative apart, just
+    # outside the 1e-6 tie band.  The query and the offsets lie on grids the
+    # float32 format holds exactly (query multiples of 2^-12 below 4 in
+    # magnitude, offsets c 2^-21 with integer c), so the FP64 distances are
+    # exact: the id lists must equal the oracle's, each distance within its
+    # stated bound.
+    N, k = 20_000, 10
+    x = G.random_walks(N, n, coll=200 + n).copy()
+    qsrc, _, _ = G.workload(x, [1, 5, 10], 2, coll=200 + n)
+    rng = np.random.Generator(np.random.PCG64(np.random.SeedSequence([n, 3])))
+    lim = 8191
+    qs = []
+    slots = rng.permutation(N)
+    used = 0
+    for i, delta in enumerate([1.2e-6, 2e-6, 3e-6, 1.2e-6, 2e-6, 3e-6]):
+        qv = np.clip(np.round(qsrc[i].astype(np.float64) * 4096.0) / 4096.0, -3.9, 3.9).astype(np.float32)
+        c, T = _grid_offsets(rng, n, 2 * k, delta, lim)
+        assert np.all(np.diff(T) / T[:-1] > 1e-6)
+        y = (qv[None, :].astype(np.float64) + c * 2.0 ** -21).astype(np.float32)
+        assert np.array_equal(y.astype(np.float64) - qv.astype(np.float64), c * 2.0 ** -21)  # exact
+        pos = slots[used:used + 2 * k]
+        used += 2 * k
+        x[pos] = y
+        qs.append(qv)
+    q = np.stack(qs)
+    idx = make_index(x, w=w, leaf_size=500, l_max=l_max)
+    ids, d2, err = run_knn(idx, q, k, err=True)
+    oids, od = check_knn(x, q, k, ids, d2)
+    for i in range(len(q)):
+        gaps = np.diff(od[i]) / od[i, :-1]
+        assert np.all(gaps > 1e-6), gaps  # the planted spacing survives in FP64
+    assert np.array_equal(ids, oids)
+    check_err(x, q, ids, d2, err)
     idx.close()
 
 
@@ -310,18 +413,19 @@ def test_errors():
     d2 = torch.empty((2, 3), dtype=torch.float32, device=DEV)
     with pytest.raises(hs.HSError) as e:
         hs.hs_knn_exact(idx.h, qt.data_ptr(), 2, 3, ws.data_ptr(), need - 1, ids.data_ptr(), d2.data_ptr(),
-                        None, 0)
+                        None, None, 0)
     assert e.value.code == hs.HS_ENOMEM
     with pytest.raises(hs.HSError) as e:
-        hs.hs_knn_exact(idx.h, None, 2, 3, ws.data_ptr(), need, ids.data_ptr(), d2.data_ptr(), None, 0)
+        hs.hs_knn_exact(idx.h, None, 2, 3, ws.data_ptr(), need, ids.data_ptr(), d2.data_ptr(), None, None, 0)
     assert e.value.code == hs.HS_EINVAL
     # at most 2^24 - 1 queries per call (rejected before any access to the arrays)
     with pytest.raises(hs.HSError) as e:
         hs.hs_knn_exact(idx.h, qt.data_ptr(), 1 << 24, 3, ws.data_ptr(), need, ids.data_ptr(), d2.data_ptr(),
-                        None, 0)
+                        None, None, 0)
     assert e.value.code == hs.HS_EINVAL
     # Q = 0 is a no-op
-    hs.hs_knn_exact(idx.h, qt.data_ptr(), 0, 3, ws.data_ptr(), need, ids.data_ptr(), d2.data_ptr(), None, 0)
+    hs.hs_knn_exact(idx.h, qt.data_ptr(), 0, 3, ws.data_ptr(), need, ids.data_ptr(), d2.data_ptr(), None, None,
+                    0)
     # the index still answers correctly after the failed calls
     a, b = run_knn(idx, x[:2], 3)
     check_knn(x, x[:2], 3, a, b)
