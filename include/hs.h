@@ -187,6 +187,27 @@ hs_status hs_knn_exact(hs_index* idx, const float* q_dev, int32_t Q, int32_t k, 
                        void* stream);
 
 /*
+ * hs_knn_exact without a workspace argument and without any device memory
+ * allocation, for callers that cannot allocate (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc).  The query
+ * workspace lives in a static device array of HS_NOALLOC_SCRATCH_BYTES that
+ * the library holds on each GPU it runs on until the process ends.  Same
+ * kernels and results as hs_knn_exact (ids, d2, err and stats bit for bit);
+ * the candidate list is sized to what the array holds beside the per-query
+ * tables, so more queries may take the overflow rounds, which do not change
+ * results.  The calling thread's current device must be the index's.  Every
+ * call on a GPU shares that GPU's array: calls that overlap on one GPU (other
+ * streams or threads) race and must be serialised by the caller.
+ * Synchronises the stream once, at the end, like hs_knn_exact.
+ * Errors: as hs_knn_exact; HS_EINVAL also when Q queries at this k need more
+ * per-query tables than the array holds (split the batch), or when the
+ * current device is not the index's.
+ */
+#define HS_NOALLOC_SCRATCH_BYTES (128LL << 20)
+hs_status hs_knn_exact_noalloc(hs_index* idx, const float* q_dev, int32_t Q, int32_t k, int64_t* ids_dev,
+                               float* d2_dev, double* err_dev, void* stats_dev, void* stream);
+
+/*
  * Precision form (beside the paper's method; it returns the same exact k-NN).
  * A low-precision copy x~ of every stored series (bf16 or fp16, round to
  * nearest even) replaces LB_SAX as the per-series filter of Sec. 3.4 step 3:

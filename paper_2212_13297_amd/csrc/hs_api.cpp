@@ -243,7 +243,7 @@ void carve(char*& cur, void** out, int64_t bytes) {
     cur += align_up(bytes, 256);
 }
 
-int64_t ws_layout(const hs_index* idx, int32_t Q, int32_t k, QueryWs* ws, char* base) {
+int64_t ws_layout(const hs_index* idx, int32_t Q, int32_t k, QueryWs* ws, char* base, int64_t cand_fixed) {
     const IndexView& ix = idx->view;
     const int P = kPoolMin;
     const int64_t items = (int64_t)Q * ix.parts + 1;
@@ -251,10 +251,12 @@ int64_t ws_layout(const hs_index* idx, int32_t Q, int32_t k, QueryWs* ws, char* 
     // between 64 Ki and 2 Gi entries (24 GB with the slices' 12 bytes each; the
     // 32-bit slice prefix stays below 2^32); a query whose candidates do not
     // fit is answered by the fused scan instead (no result changes)
-    const int64_t cpq = idx->p.cand_per_query;
+    const int64_t cpq = cand_fixed > 0 ? 1 : idx->p.cand_per_query;
     const int64_t per_q = cpq > 0 ? cpq : std::max<int64_t>((ix.N + 7) / 8, 4096);
     const int64_t floor_c = cpq > 0 ? 1 : (1 << 16);
-    const int64_t cand_total = std::min<int64_t>(std::max<int64_t>((int64_t)Q * per_q, floor_c), (int64_t)1 << 31);
+    const int64_t cand_total =
+        cand_fixed > 0 ? std::min<int64_t>(cand_fixed, (int64_t)1 << 31)
+                       : std::min<int64_t>(std::max<int64_t>((int64_t)Q * per_q, floor_c), (int64_t)1 << 31);
     // 3/4 in the filter wavefronts' private slices, 1/4 in a shared overflow slice
     const int n_slices = idx->filter_waves;
     const int64_t slice_cap = (cand_total * 3 / 4 + n_slices - 1) / n_slices;
@@ -567,7 +569,7 @@ static int32_t chunk_order_lg(const IndexView& ix) {
 }
 
 hs_status knn_prepare(hs_index* idx, int32_t Q, int32_t k, void* ws_dev, int64_t ws_bytes, bool mixed,
-                      KnnCall* c) {
+                      KnnCall* c, int64_t cand_total) {
     if (!idx) return fail(HS_EINVAL, "idx is NULL");
     if (Q < 0) return fail(HS_EINVAL, "Q=%d < 0", Q);
     if (k < 1 || k > HS_KMAX) return fail(HS_EINVAL, "k=%d out of range [1, %d]", k, HS_KMAX);
@@ -583,9 +585,9 @@ hs_status knn_prepare(hs_index* idx, int32_t Q, int32_t k, void* ws_dev, int64_t
     c->err_rel = comp_err_rel(idx->view.stride);
     if (Q == 0) return HS_OK;
     if (!ws_dev) return fail(HS_EINVAL, "NULL workspace");
-    const int64_t need = ws_layout(idx, Q, k, nullptr, nullptr);
+    const int64_t need = ws_layout(idx, Q, k, nullptr, nullptr, cand_total);
     if (ws_bytes < need) return fail(HS_ENOMEM, "ws_bytes=%lld < required %lld", (long long)ws_bytes, (long long)need);
-    ws_layout(idx, Q, k, &c->ws, (char*)ws_dev);
+    ws_layout(idx, Q, k, &c->ws, (char*)ws_dev, cand_total);
     const IndexView& ix = idx->view;
     c->sp = ScanParams{};
     c->sp.Q = Q;

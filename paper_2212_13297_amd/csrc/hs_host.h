@@ -40,7 +40,9 @@ hs_status fail(hs_status code, const char* fmt, ...);
 int64_t align_up(int64_t v, int64_t a);
 
 // Query workspace layout for Q queries (bytes; fills *ws when base is given).
-int64_t ws_layout(const hs_index* idx, int32_t Q, int32_t k, QueryWs* ws, char* base);
+// cand_total > 0 fixes the candidate-list entries (otherwise they follow the
+// index's cand_per_query).
+int64_t ws_layout(const hs_index* idx, int32_t Q, int32_t k, QueryWs* ws, char* base, int64_t cand_total = 0);
 
 struct ScanTimer;
 
@@ -54,7 +56,8 @@ struct KnnCall {
     ScanParams sp{};
 };
 
-hs_status knn_prepare(hs_index* idx, int32_t Q, int32_t k, void* ws_dev, int64_t ws_bytes, bool mixed, KnnCall* c);
+hs_status knn_prepare(hs_index* idx, int32_t Q, int32_t k, void* ws_dev, int64_t ws_bytes, bool mixed, KnnCall* c,
+                      int64_t cand_total = 0);
 hs_status knn_enqueue(const KnnCall& c, const float* q_dev, int64_t* ids_dev, float* d2_dev, double* err_dev,
                       hs_query_stats* stats_out, hipStream_t st, uint32_t* redo_host, ScanTimer* timer);
 hs_status knn_finish(const KnnCall& c, int64_t* ids_dev, float* d2_dev, double* err_dev, hs_query_stats* stats_out,

@@ -74,6 +74,7 @@ _SIGS = {
     "hs_query_workspace_bytes": (ctypes.c_int32, [_P, ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(ctypes.c_int64)]),
     "hs_knn_exact": (ctypes.c_int32, [_P, _P, ctypes.c_int32, ctypes.c_int32, _P, ctypes.c_int64, _P, _P, _P, _P,
                                       _P]),
+    "hs_knn_exact_noalloc": (ctypes.c_int32, [_P, _P, ctypes.c_int32, ctypes.c_int32, _P, _P, _P, _P, _P]),
     "hs_shadow_bytes": (ctypes.c_int32, [_P, ctypes.c_int32, ctypes.POINTER(ctypes.c_int64)]),
     "hs_build_shadow": (ctypes.c_int32, [_P, ctypes.c_int32, _P, ctypes.c_int64, _P]),
     "hs_knn_mixed": (ctypes.c_int32, [_P, _P, ctypes.c_int32, ctypes.c_int32, _P, ctypes.c_int64, _P, _P, _P, _P,
@@ -176,6 +177,11 @@ def hs_query_workspace_bytes(h, Q: int, k: int) -> int:
 def hs_knn_exact(h, q_ptr: int, Q: int, k: int, ws_ptr: int, ws_bytes: int, ids_ptr: int, d2_ptr: int,
                  err_ptr: int, stats_ptr: int, stream: int) -> None:
     _check(load().hs_knn_exact(h, q_ptr, Q, k, ws_ptr, ws_bytes, ids_ptr, d2_ptr, err_ptr, stats_ptr, stream))
+
+
+def hs_knn_exact_noalloc(h, q_ptr: int, Q: int, k: int, ids_ptr: int, d2_ptr: int, err_ptr: int, stats_ptr: int,
+                         stream: int) -> None:
+    _check(load().hs_knn_exact_noalloc(h, q_ptr, Q, k, ids_ptr, d2_ptr, err_ptr, stats_ptr, stream))
 
 
 def hs_shadow_bytes(h, kind: int) -> int:
