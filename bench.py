@@ -85,31 +85,35 @@ def measured_traffic(kernel, workload):
 
 
 MFMA_PEAK_TFLOPS = {"bf16": 2500.0, "fp16": 2500.0}
+# LDS: 256 compute units x 32 banks x one 4-byte access per bank per clock x 2.4 GHz
+LDS_PEAK_TLOOKUPS = 256 * 32 * 2.4e9 / 1e12
 
 
-def run_mixed(args, hs, torch, idx, qt, Q, plain_ids, plain_stats):
+def run_mixed(hs, torch, idx, qt, k, steps, warmup, wl, plain_ids, plain_d2):
     """Precision form on the same index and batch: bf16 copy of the series,
     matrix-core bounding pass, compensated float32 refinement."""
+    Q = qt.shape[0]
     t0 = time.time()
     idx.build_shadow(hs.HS_SHADOW_BF16)
     torch.cuda.synchronize()
     shadow_s = time.time() - t0
-    for _ in range(args.warmup):
-        idx.knn_mixed(qt, args.k)
+    for _ in range(warmup):
+        idx.knn_mixed(qt, k)
     torch.cuda.synchronize()
     hs.profile_read_all(reset=True)
     hs.hs_profile_enable(True)
     t0 = time.perf_counter()
-    for _ in range(args.steps):
-        ids, d2, err, st = idx.knn_mixed(qt, args.k, stats=True)
+    for _ in range(steps):
+        ids, d2, err, st = idx.knn_mixed(qt, k, stats=True)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     hs.hs_profile_enable(False)
     prof = hs.profile_read_all(reset=True)
-    ms = (t1 - t0) * 1000.0 / args.steps
+    ms = (t1 - t0) * 1000.0 / steps
     qps = Q / (ms / 1000.0)
     log(f"precision form: {ms:.3f} ms/step, {qps:.0f} queries/s; kernels {prof}")
     same = int((ids == plain_ids).all(dim=1).sum().item())
+    same_d = bool(torch.equal(d2.view(torch.int32), plain_d2.view(torch.int32)))
     stats = {f: v.cpu().numpy().astype(np.int64) for f, v in st.items()}
     info = idx.info
     K = info.row_stride
@@ -119,11 +123,11 @@ def run_mixed(args, hs, torch, idx, qt, Q, plain_ids, plain_stats):
         avg = bms / bl
         # algorithmic work of the bounding pass: one q~.x~ (2K flop) per bounded
         # (query, series) pair; the low-precision rows and norms it must read once
-        flops = 2.0 * K * float(stats["rows_filtered"].sum()) / (bl / args.steps)
+        flops = 2.0 * K * float(stats["rows_filtered"].sum()) / (bl / steps)
         # what the matrix cores computed: every (query, series) pair of the
         # tiles each wavefront of 32 queries took (padding queries not counted)
-        xflops = 2.0 * K * float(stats["chunks_tested"].sum()) / (bl / args.steps)
-        kern["bound"] = {"avg_launch_ms": round(avg, 4), "launches_per_step": bl / args.steps,
+        xflops = 2.0 * K * float(stats["chunks_tested"].sum()) / (bl / steps)
+        kern["bound"] = {"avg_launch_ms": round(avg, 4), "launches_per_step": bl / steps,
                          "flops_per_launch": int(flops),
                          "TFLOP_s": round(flops / (avg / 1e3) / 1e12, 2),
                          "executed_flops_per_launch": int(xflops),
@@ -133,12 +137,12 @@ def run_mixed(args, hs, torch, idx, qt, Q, plain_ids, plain_stats):
     rms, rl = prof["refine"]
     if rl:
         avg = rms / rl
-        nbytes = (int(stats["chunks_read"].sum()) * 256 + int(stats["candidates"].sum()) * 12) / (rl / args.steps)
-        kern["refine"] = {"avg_launch_ms": round(avg, 4), "launches_per_step": rl / args.steps,
+        nbytes = (int(stats["chunks_read"].sum()) * 256 + int(stats["candidates"].sum()) * 12) / (rl / steps)
+        kern["refine"] = {"avg_launch_ms": round(avg, 4), "launches_per_step": rl / steps,
                           "bytes_per_launch": int(nbytes), "GB_s": round(nbytes / (avg / 1e3) / 1e9, 2)}
-    traffic = measured_traffic("k_bound", {"N": args.N, "n": args.n, "Q": Q, "k": args.k})
+    traffic = measured_traffic("k_bound", wl)
     out = {"value": round(qps, 2), "unit": "queries/s", "ms_per_step": round(ms, 4), "dtype": "bf16 bound, f32 refine",
-           "identical_id_lists_vs_plain": same, "queries": Q,
+           "identical_id_lists_vs_plain": same, "identical_distances_vs_plain": same_d, "queries": Q,
            "max_err_bound_rel": float((err / d2.double()).max().item()),
            "shadow_build_s": round(shadow_s, 2),
            "kernels": kern,
@@ -153,6 +157,140 @@ def run_mixed(args, hs, torch, idx, qt, Q, plain_ids, plain_stats):
                        "rounds_max": int(stats["rounds"].max())}}
     log(f"precision form: {out}")
     return out
+
+
+def measure_plain(hs, torch, idx, qt, k, steps, warmup, w, wl, read_gbs):
+    """The plain form's timed steps (inputs resident in HBM), the scan kernels'
+    event-timed launches, and the algorithmic bytes both per (query, unit)
+    pair and as the batch union (distinct units read, one untimed call with
+    the marking kernels)."""
+    Q = qt.shape[0]
+    info = idx.info
+    for _ in range(warmup):
+        idx.knn(qt, k)
+    torch.cuda.synchronize()
+    hs.profile_read_all(reset=True)
+    hs.hs_profile_enable(True)
+    log(f"timing {steps} steps, Q={Q}, k={k}")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        ids, d2, st = idx.knn(qt, k, stats=True)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    hs.hs_profile_enable(False)
+    prof = hs.profile_read_all(reset=True)
+    ms_per_step = (t1 - t0) * 1000.0 / steps
+    qps = Q / (ms_per_step / 1000.0)
+    log(f"{ms_per_step:.3f} ms/step, {qps:.0f} queries/s; scan kernels {prof}")
+    stats = {f: v.cpu().numpy().astype(np.int64) for f, v in st.items()}
+    # per pair: what each (query, unit) pair reads (the seed step's series included)
+    word_bytes = int(stats["rows_filtered"].sum()) * w + int(stats["chunks_tested"].sum()) * w * 16
+    cand_bytes = int(stats["candidates"].sum()) * 12
+    raw_bytes = int(stats["chunks_read"].sum()) * 64 * 4
+    # batch union: distinct (series, chunk) pairs the refine reads, distinct
+    # words and chunk envelopes the filter reads; candidate entries are per pair
+    ust = {}
+
+    def ucall():
+        ust["st"] = idx.knn(qt, k, stats=True)[2]
+
+    u_raw, u_words, u_env = hs.union_counts(idx, ucall)
+    u_cand = int(ust["st"]["candidates"].sum().item()) * 12
+    union = {"filter": u_words * w + u_env * w * 16 + u_cand, "refine": u_raw * 256 + u_cand}
+    pair = {"filter": word_bytes + cand_bytes, "refine": raw_bytes + cand_bytes}
+    log(f"batch union: {u_raw} raw chunk pairs, {u_words} words, {u_env} envelopes "
+        f"(per pair: {stats['chunks_read'].sum()}, {stats['rows_filtered'].sum()}, {stats['chunks_tested'].sum()})")
+    kern = {}
+    for name in ("filter", "refine"):
+        kms, launches = prof[name]
+        if launches:
+            avg = kms / launches
+            per = launches / steps
+            ub, pb = union[name] / per, pair[name] / per
+            kern[name] = {"avg_launch_ms": round(avg, 4), "launches_per_step": per,
+                          "bytes_per_launch": int(ub), "GB_s": round(ub / (avg / 1e3) / 1e9, 2),
+                          "bytes_per_launch_per_pair": int(pb), "GB_s_per_pair": round(pb / (avg / 1e3) / 1e9, 2)}
+    if "filter" in kern:
+        # its words (w B per series) and chunk envelopes come back for every query
+        # that keeps their leaf and are served mostly from the 256 MB Infinity
+        # Cache; its time goes to the LB_SAX table lookups in LDS (one 4-byte
+        # lookup per segment per filtered (query, series) pair) and VALU work
+        kms, launches = prof["filter"]
+        avg = kms / launches
+        lookups = int(stats["rows_filtered"].sum()) * w / (launches / steps)
+        kern["filter"].update({"bound": "lds", "lds_lookups_per_launch": int(lookups),
+                               "lds_lookups_T_s": round(lookups / (avg / 1e3) / 1e12, 3),
+                               "lds_frac": round(lookups / (avg / 1e3) / 1e12 / LDS_PEAK_TLOOKUPS, 4)})
+    if "refine" in kern:
+        kern["refine"]["bound"] = "hbm"
+    dom = max(kern, key=lambda n: kern[n]["avg_launch_ms"] * kern[n]["launches_per_step"]) if kern else None
+    traffic = measured_traffic(f"k_{dom}", wl) if dom else None
+    env_union = info.n_leaves * w * 16              # leaf envelopes: read once per batch
+    out_bytes = Q * k * 12
+    path_union = union["filter"] + union["refine"] + env_union + out_bytes
+    path_pair = word_bytes + raw_bytes + Q * info.n_leaves * w * 16 + out_bytes
+    if dom == "filter":
+        kf = kern["filter"]
+        roof = {**kf, "bound": "lds", "achieved": kf["lds_lookups_T_s"], "peak": LDS_PEAK_TLOOKUPS,
+                "unit": "T lookups/s", "frac": kf["lds_frac"],
+                "work": "one 4-byte LB_SAX table lookup per segment per filtered (query, series) pair",
+                "hbm_union_GB_s": kf["GB_s"], "hbm_union_frac": round(kf["GB_s"] / HBM_PEAK_GBS, 4),
+                "traffic": traffic.get("bytes_per_launch") if traffic else None, "traffic_detail": traffic,
+                "kernel": "k_filter"}
+    elif dom == "refine":
+        kr = kern["refine"]
+        roof = {**kr, "bound": "hbm", "achieved": kr["GB_s"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(kr["GB_s"] / HBM_PEAK_GBS, 4),
+                "bytes": "batch union: distinct (series, 64-point chunk) pairs x 256 B + 12 B per candidate entry",
+                "per_pair": {"achieved": kr["GB_s_per_pair"], "frac": round(kr["GB_s_per_pair"] / HBM_PEAK_GBS, 4)},
+                "achievable_read_GB_s": round(read_gbs, 1),
+                "frac_of_achievable": round(kr["GB_s"] / read_gbs, 4),
+                "traffic": traffic.get("bytes_per_launch") if traffic else None, "traffic_detail": traffic,
+                "kernel": "k_refine"}
+    else:
+        roof = None
+    return {
+        "ids": ids, "d2": d2, "stats": stats, "ms_per_step": ms_per_step, "qps": qps, "kern": kern, "roofline": roof,
+        "algorithmic_bytes_per_step": {"union": {"raw_chunk_pairs": u_raw, "words": u_words, "envelopes": u_env,
+                                                 "total": path_union},
+                                       "per_pair": {"words": word_bytes, "raw": raw_bytes, "total": path_pair}},
+        "path_frac_of_hbm_peak": round(path_union / (ms_per_step / 1000.0) / 1e9 / HBM_PEAK_GBS, 4),
+        "path_frac_of_hbm_peak_per_pair": round(path_pair / (ms_per_step / 1000.0) / 1e9 / HBM_PEAK_GBS, 4),
+    }
+
+
+def pruning_summary(stats, pct, levels):
+    return {"leaves_kept_mean": float(stats["leaves_kept"].mean()),
+            "rows_filtered_mean": float(stats["rows_filtered"].mean()),
+            "rows_refined_mean": float(stats["rows_refined"].mean()),
+            "candidates_mean": float(stats["candidates"].mean()),
+            "per_level_refined_mean": [float(stats["rows_refined"][pct == p].mean()) for p in levels],
+            "per_level_candidates_mean": [float(stats["candidates"][pct == p].mean()) for p in levels],
+            "rounds_max": int(stats["rounds"].max()),
+            "queries_on_fallback": int((stats["rounds"] > 1).sum()),
+            "candidates_max": int(stats["candidates"].max())}
+
+
+def cpu_oracle(x, q, sel, k, note):
+    """The FP64 oracle (C/OpenMP brute force) on the host cores for the
+    queries sel, and parity of the GPU's lists on them (caller compares)."""
+    from oracle import brute
+    log(f"CPU oracle on {len(sel)} queries ({brute.threads()} threads)")
+    t0 = time.perf_counter()
+    oids, od = brute.knn(x, q[sel], k)
+    cpu_s = time.perf_counter() - t0
+    cpu = {"value": round(len(sel) / cpu_s, 4), "unit": "queries/s", "cores": brute.threads(), "kind": "oracle",
+           "sample": f"{note}; FP64 brute force over all {x.shape[0]} series; {cpu_s:.1f} s"}
+    return cpu, oids, od
+
+
+def parity_of(ids, d2, sel, oids, od):
+    g_ids = ids.cpu().numpy()[sel]
+    g_d = d2.cpu().numpy()[sel].astype(np.float64)
+    same = int((g_ids == oids).all(axis=1).sum())
+    rel = float(np.max(np.abs(g_d - od) / np.maximum(od, 1e-30)))
+    return {"queries_checked": int(len(sel)), "identical_id_lists": same, "max_rel_d_err": rel}
 
 
 def run_serving(args, hs, torch, G, idx256, x256):
@@ -300,6 +438,56 @@ def run_ablation(args, torch, variants, q, pct, levels, ref_ids):
     return out
 
 
+def run_large(args, hs, torch, G, dev):
+    """The precision form's own configuration: 100M random walks of length 256
+    (102.4 GB float32 plus a 51.2 GB bf16 copy), 1,000 queries at 5 % noise,
+    k = 10; plain and precision form on the same index, the oracle on the
+    first 50 queries."""
+    N, n, k, w = args.large_N, 256, args.large_k, args.w
+    log(f"large: generating {N} x {n} random walks")
+    t0 = time.time()
+    x = G.random_walks(N, n, coll=0)
+    q, _, _ = G.workload(x, [args.large_level], args.large_queries)
+    log(f"large: generated in {time.time() - t0:.1f}s; uploading")
+    xt = torch.from_numpy(x).to(dev)
+    qt = torch.from_numpy(q).to(dev)
+    torch.cuda.synchronize()
+    t0 = time.time()
+    idx = hs.Index(xt, hs.Params(w=w, leaf_size=args.leaf, l_max=args.l_max, seed_rows=args.seed_rows))
+    torch.cuda.synchronize()
+    build_s = time.time() - t0
+    log(f"large: built in {build_s:.1f}s, {idx.info.n_leaves} leaves")
+    read_gbs = hs.read_probe_gbs(xt, passes=2)
+    del xt
+    torch.cuda.empty_cache()
+    Q = q.shape[0]
+    wl = {"N": N, "n": n, "Q": Q, "k": k}
+    res = measure_plain(hs, torch, idx, qt, k, args.large_steps, args.large_warmup, w, wl, read_gbs)
+    mixed = run_mixed(hs, torch, idx, qt, k, args.large_steps, args.large_warmup, wl, res["ids"], res["d2"])
+    out = {"workload": f"random-walk {N}x{n} f32, {Q} queries at {args.large_level}% noise, k={k}, w={w}, "
+                       f"card 256, leaf {args.leaf}, l_max {args.l_max}",
+           "value": round(res["qps"], 2), "unit": "queries/s", "ms_per_step": round(res["ms_per_step"], 4),
+           "steps": args.large_steps, "warmup": args.large_warmup, "n_leaves": int(idx.info.n_leaves),
+           "build_s": round(build_s, 2), "roofline": res["roofline"], "scan_kernels": res["kern"],
+           "algorithmic_bytes_per_step": res["algorithmic_bytes_per_step"],
+           "path_frac_of_hbm_peak": res["path_frac_of_hbm_peak"],
+           "pruning": pruning_summary(res["stats"], np.full(Q, args.large_level), [args.large_level]),
+           "precision_form": mixed,
+           "precision_vs_plain_speedup": round(mixed["value"] / res["qps"], 3)}
+    if args.large_cpu > 0:
+        sel = np.arange(min(args.large_cpu, Q))
+        cpu, oids, od = cpu_oracle(x, q, sel, k, f"the first {len(sel)} of the {Q} queries, k={k}")
+        out["cpu_baseline"] = cpu
+        out["parity_sample"] = {"plain": parity_of(res["ids"], res["d2"], sel, oids, od)}
+        log(f"large: CPU oracle {cpu['value']} q/s; parity {out['parity_sample']}")
+    idx.close()
+    del idx, x, q, qt
+    gc.collect()
+    torch.cuda.empty_cache()
+    log(f"large: {out['value']} q/s plain, {mixed['value']} q/s precision")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -317,12 +505,21 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=180, help="queries timed on the CPU oracle")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--latency-queries", type=int, default=300)
-    ap.add_argument("--forms", default="plain,mixed,serving",
+    ap.add_argument("--forms", default="plain,mixed,serving,large",
                     help="plain: the paper's filter-and-refine (always timed, the headline value); mixed: also "
                          "the precision form (bf16 copy, matrix-core bound, compensated refine) on the same index; "
                          "serving: the continuous-batching server over three collections under Poisson arrivals; "
+                         "large: the precision form's own configuration (100M x 256, 1,000 queries at 5 %%, "
+                         "k = 10), plain and precision form, after the headline index is freed; "
                          "ablation: the plain form per noise level with the LB_SAX filter always on (the default), "
                          "skipped (NoSAX) and skipped below the paper's leaf-pruning threshold 0.25")
+    ap.add_argument("--large-N", type=int, default=100_000_000)
+    ap.add_argument("--large-queries", type=int, default=1000)
+    ap.add_argument("--large-level", type=int, default=5)
+    ap.add_argument("--large-k", type=int, default=10)
+    ap.add_argument("--large-steps", type=int, default=5)
+    ap.add_argument("--large-warmup", type=int, default=2)
+    ap.add_argument("--large-cpu", type=int, default=50, help="queries of the large workload timed on the oracle")
     ap.add_argument("--serve-rate", type=float, default=2000.0, help="Poisson arrival rate (queries/s)")
     ap.add_argument("--serve-seconds", type=float, default=30.0, help="measured arrival window (s)")
     ap.add_argument("--serve-warmup", type=float, default=5.0, help="arrivals before the measured window (s)")
@@ -342,7 +539,8 @@ def main():
               "(the leaf-sharded design is described in DESIGN.md); run with --gpus 1.", file=sys.stderr)
         sys.exit(2)
 
-    if "serving" in args.forms.split(","):
+    forms = args.forms.split(",")
+    if "serving" in forms:
         # the server runs streams_per_coll streams per collection; give each its
         # own hardware queue (set before the HIP runtime starts)
         os.environ.setdefault("GPU_MAX_HW_QUEUES", str(min(16, 3 * args.serve_streams + 1)))
@@ -375,19 +573,13 @@ def main():
     log(f"read stream (probe over {xt.numel() * 4 / 1e9:.2f} GB): {read_gbs:.0f} GB/s")
     # ablation indexes: same data and leaves, other access-path thresholds (eapca_th)
     abl_idx = {}
-    if "ablation" in args.forms.split(",") and not args.profile_run:
+    if "ablation" in forms and not args.profile_run:
         for name, th in (("nosax", 1.1), ("thresh_0.25", 0.25)):
             abl_idx[name] = hs.Index(xt, hs.Params(w=args.w, leaf_size=args.leaf, l_max=args.l_max,
                                                    seed_rows=args.seed_rows, eapca_th=th))
         torch.cuda.synchronize()
     del xt
     torch.cuda.empty_cache()
-
-    def run(k, steps, stats=False):
-        out = None
-        for _ in range(steps):
-            out = idx.knn(qt, k, stats=stats)
-        return out
 
     if args.profile_run:
         # a plain 1 GiB device-to-device copy: the known-size kernel against which
@@ -400,56 +592,42 @@ def main():
         del src_buf, dst_buf
         torch.cuda.empty_cache()
 
-    log(f"warmup {args.warmup} steps")
-    run(args.k, args.warmup)
-    torch.cuda.synchronize()
-    hs.profile_read_all(reset=True)
-    hs.hs_profile_enable(True)
-    log(f"timing {args.steps} steps, Q={Q}, k={args.k}")
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    ids, d2, st = run(args.k, args.steps, stats=True)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    hs.hs_profile_enable(False)
-    prof = hs.profile_read_all(reset=True)
-    ms_per_step = (t1 - t0) * 1000.0 / args.steps
-    qps = Q / (ms_per_step / 1000.0)
-    log(f"{ms_per_step:.3f} ms/step, {qps:.0f} queries/s; scan kernels {prof}")
+    def run(k, steps, stats=False):
+        out = None
+        for _ in range(steps):
+            out = idx.knn(qt, k, stats=stats)
+        return out
 
-    stats = {f: v.cpu().numpy().astype(np.int64) for f, v in st.items()}
-    # algorithmic bytes (the seed step's few thousand series per query are included)
-    word_bytes = int(stats["rows_filtered"].sum()) * args.w + int(stats["chunks_tested"].sum()) * args.w * 16
-    cand_bytes = int(stats["candidates"].sum()) * 12
-    raw_bytes = int(stats["chunks_read"].sum()) * 64 * 4
-    kern = {}
-    for name, nbytes in (("filter", word_bytes + cand_bytes), ("refine", raw_bytes + cand_bytes)):
-        ms, launches = prof[name]
-        if launches:
-            avg = ms / launches
-            per_launch = nbytes / (launches / args.steps)
-            kern[name] = {"avg_launch_ms": round(avg, 4), "launches_per_step": launches / args.steps,
-                          "bytes_per_launch": int(per_launch), "GB_s": round(per_launch / (avg / 1e3) / 1e9, 2)}
-    dom = max(kern, key=lambda n: kern[n]["avg_launch_ms"] * kern[n]["launches_per_step"]) if kern else None
-    achieved = kern[dom]["GB_s"] if dom else 0.0
-    traffic = measured_traffic(f"k_{dom}", {"N": args.N, "n": args.n, "Q": Q, "k": args.k}) if dom else None
-    env_bytes = Q * info.n_leaves * args.w * 16
-    path_bytes_step = word_bytes + raw_bytes + env_bytes + Q * args.k * 12
-
-    # k = 1 on the same batch
-    qps_k1 = None
-    if not args.profile_run:
-        run(1, max(1, args.warmup // 2))
+    wl = {"N": args.N, "n": args.n, "Q": Q, "k": args.k}
+    if args.profile_run:
+        # warmup and timed steps only: the profiler's averages cover exactly these launches
+        run(args.k, args.warmup)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        run(1, args.steps)
+        run(args.k, args.steps, stats=True)
         torch.cuda.synchronize()
-        qps_k1 = round(Q * args.steps / (time.perf_counter() - t0), 2)
-        log(f"k=1: {qps_k1:.0f} queries/s")
+        ms = (time.perf_counter() - t0) * 1000.0 / args.steps
+        log(f"profile run: {ms:.3f} ms/step")
+        print(json.dumps({"profile_run": True, "ms_per_step": round(ms, 4), "queries": Q}), flush=True)
+        idx.close()
+        return
+
+    res = measure_plain(hs, torch, idx, qt, args.k, args.steps, args.warmup, args.w, wl, read_gbs)
+    ids, d2, stats = res["ids"], res["d2"], res["stats"]
+    ms_per_step, qps = res["ms_per_step"], res["qps"]
+
+    # k = 1 on the same batch
+    run(1, max(1, args.warmup // 2))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    run(1, args.steps)
+    torch.cuda.synchronize()
+    qps_k1 = round(Q * args.steps / (time.perf_counter() - t0), 2)
+    log(f"k=1: {qps_k1:.0f} queries/s")
 
     # single-query latency
     lat = []
-    nl = 0 if args.profile_run else min(args.latency_queries, Q)
+    nl = min(args.latency_queries, Q)
     for i in range(nl):
         qi = qt[i:i + 1]
         torch.cuda.synchronize()
@@ -461,10 +639,10 @@ def main():
     log(f"single-query latency p50 {np.percentile(lat, 50):.3f} ms p99 {np.percentile(lat, 99):.3f} ms")
 
     mixed = None
-    if "mixed" in args.forms.split(","):
-        mixed = run_mixed(args, hs, torch, idx, qt, Q, ids, st)
+    if "mixed" in forms:
+        mixed = run_mixed(hs, torch, idx, qt, args.k, args.steps, args.warmup, wl, ids, d2)
     serving = None
-    if "serving" in args.forms.split(",") and not args.profile_run:
+    if "serving" in forms:
         serving = run_serving(args, hs, torch, G, idx, x)
 
     ablation = None
@@ -475,23 +653,22 @@ def main():
 
     cpu = None
     parity = None
-    if not args.no_cpu_baseline and not args.profile_run and args.cpu_sample > 0:
-        from oracle import brute
+    if not args.no_cpu_baseline and args.cpu_sample > 0:
         sel = np.linspace(0, Q - 1, min(args.cpu_sample, Q)).round().astype(np.int64)
-        log(f"CPU oracle on {len(sel)} queries ({brute.threads()} threads)")
-        t0 = time.perf_counter()
-        oids, od = brute.knn(x, q[sel], args.k)
-        cpu_s = time.perf_counter() - t0
-        cpu = {"value": round(len(sel) / cpu_s, 4), "unit": "queries/s", "cores": brute.threads(),
-               "kind": "oracle",
-               "sample": f"{len(sel)} of the {Q} queries (evenly spaced over the {'/'.join(map(str, levels))}% levels), k={args.k}, "
-                         f"FP64 brute force over all {args.N} series; {cpu_s:.1f} s"}
-        g_ids = ids.cpu().numpy()[sel]
-        g_d = d2.cpu().numpy()[sel].astype(np.float64)
-        same = int((g_ids == oids).all(axis=1).sum())
-        rel = float(np.max(np.abs(g_d - od) / np.maximum(od, 1e-30)))
-        parity = {"queries_checked": int(len(sel)), "identical_id_lists": same, "max_rel_d_err": rel}
+        cpu, oids, od = cpu_oracle(x, q, sel, args.k,
+                                   f"{len(sel)} of the {Q} queries (evenly spaced over the "
+                                   f"{'/'.join(map(str, levels))}% levels), k={args.k}")
+        parity = parity_of(ids, d2, sel, oids, od)
         log(f"CPU oracle {cpu['value']} q/s; parity {parity}")
+
+    ids_cpu = ids.cpu()
+    idx.close()
+    del idx, qt, x
+    gc.collect()
+    torch.cuda.empty_cache()
+    large = None
+    if "large" in forms and args.large_N > 0:
+        large = run_large(args, hs, torch, G, dev)
 
     out = {
         "metric": METRIC,
@@ -517,35 +694,22 @@ def main():
         "latency_ms": {"p50": round(float(np.percentile(lat, 50)), 4),
                        "p99": round(float(np.percentile(lat, 99)), 4), "mode": "one query per call",
                        "queries": int(nl)},
-        "roofline": {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "achievable_read_GB_s": round(read_gbs, 1),
-                     "frac_of_achievable": round(achieved / read_gbs, 4),
-                     "traffic": traffic.get("bytes_per_launch") if traffic else None,
-                     "traffic_detail": traffic,
-                     "kernel": f"k_{dom}" if dom else None, **(kern.get(dom, {}))},
-        "scan_kernels": kern,
-        "algorithmic_bytes_per_step": {"words": word_bytes, "raw": raw_bytes, "envelopes": env_bytes,
-                                       "total": path_bytes_step},
-        "path_frac_of_hbm_peak": round(path_bytes_step / (ms_per_step / 1000.0) / 1e9 / HBM_PEAK_GBS, 4),
-        "pruning": {"leaves_kept_mean": float(stats["leaves_kept"].mean()),
-                    "rows_filtered_mean": float(stats["rows_filtered"].mean()),
-                    "rows_refined_mean": float(stats["rows_refined"].mean()),
-                    "candidates_mean": float(stats["candidates"].mean()),
-                    "per_level_refined_mean": [float(stats["rows_refined"][pct == p].mean()) for p in levels],
-                    "per_level_candidates_mean": [float(stats["candidates"][pct == p].mean()) for p in levels],
-                    "rounds_max": int(stats["rounds"].max()),
-                    "queries_on_fallback": int((stats["rounds"] > 1).sum()),
-                    "candidates_max": int(stats["candidates"].max())},
+        "roofline": res["roofline"],
+        "scan_kernels": res["kern"],
+        "algorithmic_bytes_per_step": res["algorithmic_bytes_per_step"],
+        "path_frac_of_hbm_peak": res["path_frac_of_hbm_peak"],
+        "path_frac_of_hbm_peak_per_pair": res["path_frac_of_hbm_peak_per_pair"],
+        "pruning": pruning_summary(stats, pct, levels),
         "build_s": round(build_s, 2),
         "cpu_baseline": cpu,
         "parity_sample": parity,
         "precision_form": mixed,
         "serving_form": serving,
         "ablation": ablation,
+        "large_config": large,
     }
+    del ids_cpu
     print(json.dumps(out), flush=True)
-    idx.close()
 
 
 if __name__ == "__main__":

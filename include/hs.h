@@ -368,6 +368,27 @@ hs_status hs_profile_enable(int32_t on);
  * Errors: HS_EINVAL for an unknown kind. */
 hs_status hs_profile_read(int32_t kind, double* ms, int64_t* launches, int32_t reset);
 
+/* Diagnostics: batch-union counters.  Sec. 4.1 measures the fraction of the
+ * data a query accesses; for a batch of queries the units that count are the
+ * distinct ones, since a unit read once can serve every query of the batch.
+ * While enabled with a caller-owned device bit array (zeroed by the caller,
+ * at least hs_union_bytes bytes), hs_knn_exact and hs_knn_mixed mark every
+ * distinct unit their filter and refine kernels read (in diagnostic variants
+ * of those kernels; the timed ones are not changed; the seed step's reads are
+ * not marked):
+ *   region 0: (stored series, 64-point chunk) pairs of raw values,
+ *   region 1: stored series whose iSAX word was read,
+ *   region 2: 64-series chunk envelopes tested.
+ * hs_union_count adds the marked units of each region to counts_dev[0..2]
+ * (uint64, caller-zeroed), asynchronously on the stream.  Process-wide; not
+ * meant for concurrent calls.  hs_union_enable(NULL, 0) turns it off.
+ * Errors: HS_EINVAL (NULL, a size that is not a positive multiple of 4);
+ * hs_knn_* return HS_ENOMEM while enabled with an array too small for their
+ * index. */
+hs_status hs_union_bytes(const hs_index* idx, int64_t* bytes);
+hs_status hs_union_enable(void* bits_dev, int64_t bytes);
+hs_status hs_union_count(const hs_index* idx, const void* bits_dev, uint64_t* counts_dev, void* stream);
+
 /* Diagnostics: the device's achievable read-stream rate, reported beside
  * the nominal HBM peak.  Reads the first `bytes` of device memory buf_dev
  * (a multiple of 16, at least 1 MiB; contents do not matter, only read)

@@ -1,8 +1,8 @@
 """Compile the HIP library in-tree for gfx950.
 
 Produces ``paper_2212_13297_amd/libhercules_hip.so`` from ``csrc/`` with
-hipcc.  Every HIP translation unit is built with packed-FP32 instruction
-generation disabled.
+hipcc (one compiler process per source file, then one link).  Every HIP
+translation unit is built with packed-FP32 instruction generation disabled.
 """
 from __future__ import annotations
 
@@ -26,16 +26,33 @@ def hipcc() -> str:
 
 
 def build(verbose: bool = False) -> str:
-    srcs = [os.path.join(HERE, s) for s in SOURCES]
-    tmp = LIB + ".tmp"
-    cmd = [hipcc(), f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC", "-shared",
-           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-           "-Wno-unused-command-line-argument",
-           "-I", os.path.join(ROOT, "include"), "-o", tmp] + srcs
-    if verbose:
-        print(" ".join(cmd), flush=True)
-    subprocess.run(cmd, check=True)
-    os.replace(tmp, LIB)
+    """Compile every source to an object in parallel (one hipcc per file),
+    then link the shared library."""
+    import concurrent.futures as cf
+    import tempfile
+    flags = [f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC",
+             "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+             "-Wno-unused-command-line-argument", "-I", os.path.join(ROOT, "include")]
+    with tempfile.TemporaryDirectory(prefix="hs_build_") as tmpdir:
+        objs = []
+        cmds = []
+        for src in SOURCES:
+            obj = os.path.join(tmpdir, os.path.basename(src) + ".o")
+            objs.append(obj)
+            cmds.append([hipcc()] + flags + ["-c", os.path.join(HERE, src), "-o", obj])
+
+        def run(cmd):
+            if verbose:
+                print(" ".join(cmd), flush=True)
+            subprocess.run(cmd, check=True)
+
+        workers = max(1, min(len(cmds), os.cpu_count() or 1, 8))
+        with cf.ThreadPoolExecutor(workers) as ex:
+            list(ex.map(run, cmds))
+        tmp = LIB + ".tmp"
+        link = [hipcc(), f"--offload-arch={ARCH}", "-fPIC", "-shared", "-o", tmp] + objs
+        run(link)
+        os.replace(tmp, LIB)
     return LIB
 
 

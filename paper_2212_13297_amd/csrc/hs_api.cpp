@@ -38,6 +38,8 @@ thread_local std::string g_err;
 
 std::mutex g_prof_mu;
 bool g_prof_on = false;
+uint32_t* g_union_bits = nullptr;  // batch-union diagnostics (guarded by g_prof_mu)
+int64_t g_union_bytes = 0;
 double g_prof_ms[HS_PROF_KINDS] = {};
 int64_t g_prof_launches[HS_PROF_KINDS] = {};
 
@@ -588,6 +590,18 @@ hs_status knn_prepare(hs_index* idx, int32_t Q, int32_t k, void* ws_dev, int64_t
     const int64_t need = ws_layout(idx, Q, k, nullptr, nullptr, cand_total);
     if (ws_bytes < need) return fail(HS_ENOMEM, "ws_bytes=%lld < required %lld", (long long)ws_bytes, (long long)need);
     ws_layout(idx, Q, k, &c->ws, (char*)ws_dev, cand_total);
+    {
+        std::lock_guard<std::mutex> g(g_prof_mu);
+        if (g_union_bits) {
+            const int64_t need_bits = union_bits(idx->view);
+            if (g_union_bytes * 8 < need_bits)
+                return fail(HS_ENOMEM, "batch-union array of %lld bytes < %lld needed for this index",
+                            (long long)g_union_bytes, (long long)((need_bits + 31) / 32 * 4));
+            c->ws.ubits = g_union_bits;
+            c->ws.word_bit0 = idx->view.N * (int64_t)(idx->view.stride / kChunk);
+            c->ws.env_bit0 = c->ws.word_bit0 + idx->view.N;
+        }
+    }
     const IndexView& ix = idx->view;
     c->sp = ScanParams{};
     c->sp.Q = Q;
@@ -750,6 +764,27 @@ hs_status hs_build_shadow(hs_index* idx, int32_t kind, void* shadow_dev, int64_t
 hs_status hs_profile_enable(int32_t on) {
     std::lock_guard<std::mutex> g(g_prof_mu);
     g_prof_on = on != 0;
+    return HS_OK;
+}
+
+hs_status hs_union_bytes(const hs_index* idx, int64_t* bytes) {
+    if (!idx || !bytes) return fail(HS_EINVAL, "NULL argument");
+    *bytes = (union_bits(idx->view) + 31) / 32 * 4;
+    return HS_OK;
+}
+
+hs_status hs_union_enable(void* bits_dev, int64_t bytes) {
+    if (bits_dev && (bytes < 4 || bytes % 4)) return fail(HS_EINVAL, "bytes=%lld: a positive multiple of 4", (long long)bytes);
+    std::lock_guard<std::mutex> g(g_prof_mu);
+    g_union_bits = (uint32_t*)bits_dev;
+    g_union_bytes = bits_dev ? bytes : 0;
+    return HS_OK;
+}
+
+hs_status hs_union_count(const hs_index* idx, const void* bits_dev, uint64_t* counts_dev, void* stream) {
+    if (!idx || !bits_dev || !counts_dev) return fail(HS_EINVAL, "NULL argument");
+    HIP_TRY(launch_union_count(idx->view, (const uint32_t*)bits_dev, (unsigned long long*)counts_dev,
+                               (hipStream_t)stream));
     return HS_OK;
 }
 

@@ -39,8 +39,9 @@ struct FilterOut {
 // the word loads of all chunks are issued before the first table lookup, and
 // rows past a chunk (or slots past the batch) load zeros from no memory.
 // skip: the skip-sequential path, where every series is a candidate with
-// bound 0 and no word is read.
-template <int W16>
+// bound 0 and no word is read.  U: batch-union diagnostics (marks the series
+// whose words are read).
+template <int W16, bool U>
 __device__ __forceinline__ void filter_batch(const IndexView& ix, const QueryWs& ws, const uint2* queue,
                                              uint32_t head, int nb, int q, float thr, bool skip,
                                              const float* s_lut, int lane, FilterOut& o) {
@@ -72,6 +73,10 @@ __device__ __forceinline__ void filter_batch(const IndexView& ix, const QueryWs&
                 pk[s] = pack_quarters(a[0], a[1], a[2], a[3]);
             }
             o.filt += r1[s] - r0[s];
+            if (U && !skip && (uint32_t)lane < r1[s] - r0[s]) {
+                const int64_t bit = ws.word_bit0 + (int64_t)(r0[s] + (uint32_t)lane);
+                atomicOr(&ws.ubits[bit >> 5], 1u << (bit & 31));
+            }
             if ((uint32_t)lane < r1[s] - r0[s] && lb <= thr) mask |= 1u << s;
         }
     }
@@ -131,7 +136,8 @@ __device__ __forceinline__ void filter_batch(const IndexView& ix, const QueryWs&
 // over the L lanes by a butterfly.  Chunks that pass join the wavefront's
 // queue in LDS, and every kBatch queued chunks go through filter_batch, so
 // the LB_SAX work comes in full batches whatever fraction of chunks pass.
-template <int W16>
+// U: batch-union diagnostics (marks the envelopes tested and the words read).
+template <int W16, bool U>
 __global__ void __launch_bounds__(256, 4) k_filter(IndexView ix, ScanParams sp, QueryWs ws) {
     // the table first, at a fixed LDS address, so its row offsets fold into
     // the lookups' immediate offsets
@@ -217,7 +223,7 @@ __global__ void __launch_bounds__(256, 4) k_filter(IndexView ix, ScanParams sp, 
                     tail += add;
                     __builtin_amdgcn_wave_barrier();
                     while (tail - head >= kBatch) {
-                        filter_batch<W16>(ix, ws, queue, head, kBatch, q, thr, true, s_lut, lane, o);
+                        filter_batch<W16, U>(ix, ws, queue, head, kBatch, q, thr, true, s_lut, lane, o);
                         head += kBatch;
                     }
                 }
@@ -247,6 +253,10 @@ __global__ void __launch_bounds__(256, 4) k_filter(IndexView ix, ScanParams sp, 
                     for (int sh = L >> 1; sh > 0; sh >>= 1) term += __shfl_xor(term, sh, 64);
                     const bool live = valid && head_lane && term <= thr;
                     o.tests += (unsigned long long)__popcll(__ballot(valid && head_lane));
+                    if (U && valid && head_lane) {
+                        const int64_t bit = ws.env_bit0 + (int64_t)c0 + lane_chunk + kWaves * sb;
+                        atomicOr(&ws.ubits[bit >> 5], 1u << (bit & 31));
+                    }
                     const uint64_t lm = __ballot(live);
                     if (live) {
                         const uint32_t a = pb + (uint32_t)((lane_chunk + kWaves * sb) * kChunkRows);
@@ -256,14 +266,14 @@ __global__ void __launch_bounds__(256, 4) k_filter(IndexView ix, ScanParams sp, 
                     tail += (uint32_t)__popcll(lm);
                     __builtin_amdgcn_wave_barrier();
                     while (tail - head >= kBatch) {
-                        filter_batch<W16>(ix, ws, queue, head, kBatch, q, thr, false, s_lut, lane, o);
+                        filter_batch<W16, U>(ix, ws, queue, head, kBatch, q, thr, false, s_lut, lane, o);
                         head += kBatch;
                     }
                 }
             }
         }
         if (tail != head)
-            filter_batch<W16>(ix, ws, queue, head, (int)(tail - head), q, thr, skip, s_lut, lane, o);
+            filter_batch<W16, U>(ix, ws, queue, head, (int)(tail - head), q, thr, skip, s_lut, lane, o);
         idx += m;
         if (lane == 0) {
             atomicAdd(&ws.stats[(int64_t)q * 8 + 1], skip ? 0ull : o.filt);
@@ -319,7 +329,7 @@ __global__ void __launch_bounds__(1024) k_slice_prefix(QueryWs ws) {
 
 template <int W16>
 int filter_blocks(const IndexView& ix, int cus) {
-    return resident_grid(k_filter<W16>, kTile, 0, cus);
+    return resident_grid(k_filter<W16, false>, kTile, 0, cus);
 }
 
 }  // namespace
@@ -338,7 +348,21 @@ int filter_waves(const IndexView& ix, int device_cus) {
 hipError_t launch_filter(const IndexView& ix, const ScanParams& sp, const QueryWs& ws, int device_cus,
                          hipStream_t st) {
     const dim3 grid(ws.n_slices / kWaves);  // one slice per wavefront
-    HS_DISPATCH_W16(ix, k_filter, grid, dim3(kTile), 0, st, ix, sp, ws);
+    if (ws.ubits) {
+        switch (w16_of(ix)) {
+            case 1: k_filter<1, true><<<grid, dim3(kTile), 0, st>>>(ix, sp, ws); break;
+            case 2: k_filter<2, true><<<grid, dim3(kTile), 0, st>>>(ix, sp, ws); break;
+            case 3: k_filter<3, true><<<grid, dim3(kTile), 0, st>>>(ix, sp, ws); break;
+            default: k_filter<4, true><<<grid, dim3(kTile), 0, st>>>(ix, sp, ws); break;
+        }
+    } else {
+        switch (w16_of(ix)) {
+            case 1: k_filter<1, false><<<grid, dim3(kTile), 0, st>>>(ix, sp, ws); break;
+            case 2: k_filter<2, false><<<grid, dim3(kTile), 0, st>>>(ix, sp, ws); break;
+            case 3: k_filter<3, false><<<grid, dim3(kTile), 0, st>>>(ix, sp, ws); break;
+            default: k_filter<4, false><<<grid, dim3(kTile), 0, st>>>(ix, sp, ws); break;
+        }
+    }
     return hipGetLastError();
 }
 

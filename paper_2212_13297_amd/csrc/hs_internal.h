@@ -122,6 +122,12 @@ struct QueryWs {
     int64_t ovf_cap;      // entries of the shared overflow slice (slice index n_slices)
     int32_t n_slices;
     int32_t P;
+    // batch-union diagnostics (NULL when off): one bit per distinct unit read,
+    // raw (series, 64-point chunk) pairs at bit pos * nchunks + c, then
+    // series whose word was read at bit word_bit0 + pos, then chunk envelopes
+    // at bit env_bit0 + chunk
+    uint32_t* ubits;
+    int64_t word_bit0, env_bit0;
 };
 
 struct ScanParams {
@@ -143,6 +149,11 @@ struct ScanParams {
     // the rounding of the product
     float marg;
 };
+
+// bits of the batch-union array for an index: raw chunk pairs, words, envelopes
+inline int64_t union_bits(const IndexView& ix) {
+    return ix.N * (int64_t)(ix.stride / kChunk) + ix.N + ix.chunks;
+}
 
 // kernel launchers (hs_kernels.hip); all asynchronous on `st`
 hipError_t launch_series_stats(const float* x, int64_t N, int32_t n, int32_t w, float2* st_out,
@@ -170,6 +181,8 @@ hipError_t launch_refine(const IndexView& ix, const ScanParams& sp, const QueryW
 hipError_t launch_leaf_scan(const IndexView& ix, const ScanParams& sp, const QueryWs& ws, int device_cus, int form,
                             hipStream_t st);
 // err_out (may be NULL): err_rel * d2 per result
+// counts[0..2] = marked raw chunk pairs, words, envelopes of a batch-union array
+hipError_t launch_union_count(const IndexView& ix, const uint32_t* bits, unsigned long long* counts, hipStream_t st);
 hipError_t launch_merge(const IndexView& ix, const ScanParams& sp, bool redo_only, const QueryWs& ws,
                         int64_t* ids_out, float* d2_out, double* err_out, double err_rel, hs_query_stats* stats_out,
                         hipStream_t st);

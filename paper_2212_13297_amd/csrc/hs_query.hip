@@ -404,6 +404,42 @@ __global__ void __launch_bounds__(1024) k_merge(IndexView ix, ScanParams sp, int
     }
 }
 
+// Batch-union diagnostics: the marked units of each region of the bit array
+// (raw chunk pairs [0, word_bit0), words [word_bit0, env_bit0), envelopes
+// [env_bit0, end)) added to counts[0..2].
+__global__ void __launch_bounds__(256) k_union_count(const uint32_t* __restrict__ bits, int64_t nwords,
+                                                      int64_t word_bit0, int64_t env_bit0, int64_t end_bit,
+                                                      unsigned long long* counts) {
+    __shared__ unsigned long long s_c[3][4];
+    const int64_t b0[3] = {0, word_bit0, env_bit0}, b1[3] = {word_bit0, env_bit0, end_bit};
+    unsigned long long c[3] = {0ull, 0ull, 0ull};
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < nwords; i += (int64_t)gridDim.x * blockDim.x) {
+        const uint32_t v = bits[i];
+        if (!v) continue;
+        const int64_t lo = i * 32, hi = lo + 32;
+#pragma unroll
+        for (int r = 0; r < 3; ++r) {
+            const int64_t a = max(lo, b0[r]), b = min(hi, b1[r]);
+            if (a >= b) continue;
+            const int sh = (int)(a - lo), len = (int)(b - a);
+            const uint32_t m = (len == 32 ? 0xffffffffu : ((1u << len) - 1u)) << sh;
+            c[r] += (unsigned long long)__popc(v & m);
+        }
+    }
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int r = 0; r < 3; ++r) {
+        unsigned long long x = c[r];
+        for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
+        if (lane == 0) s_c[r][wave] = x;
+    }
+    __syncthreads();
+    if (threadIdx.x < 3) {
+        const unsigned long long s = s_c[threadIdx.x][0] + s_c[threadIdx.x][1] + s_c[threadIdx.x][2] + s_c[threadIdx.x][3];
+        if (s) atomicAdd(&counts[threadIdx.x], s);
+    }
+}
+
 __global__ void k_reset_items(uint32_t* c) {
     if (threadIdx.x == 0) {
         c[kCtrItems] = 0;
@@ -453,6 +489,15 @@ hipError_t launch_emit(const IndexView& ix, const ScanParams& sp, bool redo_only
         hipLaunchKernelGGL(k_reset_items, dim3(1), dim3(64), 0, st, ws.counters);
     }
     hipLaunchKernelGGL(k_emit, dim3(sp.Q), dim3(kTile), 0, st, ix, sp, redo_only ? 1 : 0, ws);
+    return hipGetLastError();
+}
+
+hipError_t launch_union_count(const IndexView& ix, const uint32_t* bits, unsigned long long* counts, hipStream_t st) {
+    const int64_t end_bit = union_bits(ix);
+    const int64_t word_bit0 = ix.N * (int64_t)(ix.stride / kChunk);
+    const int64_t nwords = (end_bit + 31) / 32;
+    hipLaunchKernelGGL(k_union_count, dim3(grid_for(nwords, 256, 4096)), dim3(256), 0, st, bits, nwords, word_bit0,
+                       word_bit0 + ix.N, end_bit, counts);
     return hipGetLastError();
 }
 

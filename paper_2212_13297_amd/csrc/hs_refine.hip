@@ -145,7 +145,8 @@ __device__ __forceinline__ uint4 ring_entry(const Meta& m, bool ord, uint32_t& r
 // publishes its improvements with atomicMin.
 // Q1: one chunk per quarter in the chunk order (n = 256): the chunk index is a
 // field of the order word and the cascade's bounds shift out as it is read.
-template <int F, int NS, bool Q1>
+// U: batch-union diagnostics (marks every (series, chunk) pair read).
+template <int F, int NS, bool Q1, bool U>
 __global__ void __launch_bounds__(256, 4) k_refine(IndexView ix, ScanParams sp, QueryWs ws) {
     constexpr int kRing = 128;
     __shared__ unsigned long long s_top[kTile / 64][HS_KMAX];
@@ -380,6 +381,10 @@ __global__ void __launch_bounds__(256, 4) k_refine(IndexView ix, ScanParams sp, 
                                 : sc[s];
             x[s] = *reinterpret_cast<const float4*>(xp[s] + c * kChunk);
             qv[s] = *reinterpret_cast<const float4*>(qp[s] + c * kChunk);
+            if (U && sq[s] >= 0 && sub == 0) {
+                const int64_t bit = (int64_t)((xp[s] - rows_sub) / ix.stride) * nchunks + c;
+                atomicOr(&ws.ubits[bit >> 5], 1u << (bit & 31));
+            }
         }
         bool adm[NS];
         bool slow = false;
@@ -505,15 +510,24 @@ __global__ void __launch_bounds__(256, 4) k_refine(IndexView ix, ScanParams sp, 
 
 hipError_t launch_refine(const IndexView& ix, const ScanParams& sp, const QueryWs& ws, int device_cus, int form,
                          hipStream_t st) {
-#define HS_REFINE(FF, NS, QQ) \
-    k_refine<FF, NS, QQ><<<dim3(resident_grid(k_refine<FF, NS, QQ>, kTile, 0, device_cus)), dim3(kTile), 0, st>>>(ix, sp, ws)
+#define HS_REFINE(FF, NS, QQ, UU)                                                                 \
+    k_refine<FF, NS, QQ, UU><<<dim3(resident_grid(k_refine<FF, NS, QQ, UU>, kTile, 0, device_cus)), dim3(kTile), 0, \
+                               st>>>(ix, sp, ws)
     const bool q1 = sp.order_lg == 0;
-    if (form == kComp) {
-        if (q1) HS_REFINE(kComp, kRefineSlots, true);
-        else HS_REFINE(kComp, kRefineSlots, false);
+    if (ws.ubits) {
+        if (form == kComp) {
+            if (q1) HS_REFINE(kComp, kRefineSlots, true, true);
+            else HS_REFINE(kComp, kRefineSlots, false, true);
+        } else {
+            if (q1) HS_REFINE(kPlain, kRefineSlots, true, true);
+            else HS_REFINE(kPlain, kRefineSlots, false, true);
+        }
+    } else if (form == kComp) {
+        if (q1) HS_REFINE(kComp, kRefineSlots, true, false);
+        else HS_REFINE(kComp, kRefineSlots, false, false);
     } else {
-        if (q1) HS_REFINE(kPlain, kRefineSlots, true);
-        else HS_REFINE(kPlain, kRefineSlots, false);
+        if (q1) HS_REFINE(kPlain, kRefineSlots, true, false);
+        else HS_REFINE(kPlain, kRefineSlots, false, false);
     }
 #undef HS_REFINE
     return hipGetLastError();

@@ -101,6 +101,9 @@ _SIGS = {
     "hs_profile_read": (ctypes.c_int32, [ctypes.c_int32, ctypes.POINTER(ctypes.c_double),
                                          ctypes.POINTER(ctypes.c_int64), ctypes.c_int32]),
     "hs_read_probe": (ctypes.c_int32, [_P, ctypes.c_int64, ctypes.c_int32, _P, _P, ctypes.POINTER(ctypes.c_double)]),
+    "hs_union_bytes": (ctypes.c_int32, [_P, ctypes.POINTER(ctypes.c_int64)]),
+    "hs_union_enable": (ctypes.c_int32, [_P, ctypes.c_int64]),
+    "hs_union_count": (ctypes.c_int32, [_P, _P, _P, _P]),
 }
 
 _LIB = None
@@ -323,6 +326,38 @@ def read_probe_gbs(buf, passes: int = 5, stream=None) -> float:
     sink = torch.zeros(1, dtype=torch.int32, device=buf.device)
     ms = hs_read_probe(buf.data_ptr(), nbytes, passes, sink.data_ptr(), _stream_ptr(stream))
     return nbytes * passes / (ms / 1e3) / 1e9
+
+
+def hs_union_bytes(h) -> int:
+    out = ctypes.c_int64()
+    _check(load().hs_union_bytes(h, ctypes.byref(out)))
+    return out.value
+
+
+def hs_union_enable(bits_ptr, nbytes: int) -> None:
+    _check(load().hs_union_enable(bits_ptr, nbytes))
+
+
+def hs_union_count(h, bits_ptr: int, counts_ptr: int, stream: int) -> None:
+    _check(load().hs_union_count(h, bits_ptr, counts_ptr, stream))
+
+
+def union_counts(index, fn):
+    """Run fn() with batch-union marking on for `index`; returns the distinct
+    (raw chunk pairs, words, envelopes) its calls read."""
+    import torch
+    nbytes = hs_union_bytes(index.h)
+    bits = torch.zeros(nbytes // 4, dtype=torch.int32, device=index.device)
+    counts = torch.zeros(3, dtype=torch.int64, device=index.device)
+    torch.cuda.synchronize()
+    hs_union_enable(bits.data_ptr(), nbytes)
+    try:
+        fn()
+    finally:
+        hs_union_enable(None, 0)
+    hs_union_count(index.h, bits.data_ptr(), counts.data_ptr(), _stream_ptr(None))
+    torch.cuda.synchronize()
+    return tuple(int(v) for v in counts.cpu().tolist())
 
 
 def profile_read_all(reset: bool = False):

@@ -432,6 +432,40 @@ def test_errors():
     idx.close()
 
 
+def test_batch_union_counters():
+    # Distinct units read by the filter and refine of one batch: each at most
+    # the per-query totals, the envelopes at least any one query's (a query
+    # tests a chunk envelope once), and the results unchanged by the marking
+    # variants of the kernels.  The same batch twice over tests no further
+    # envelope: the chunks tested follow from the leaves the seeds keep.
+    hs = hs_mod()
+    x, q = workload(30_000, 256, coll=17, per_level=4)
+    idx = make_index(x, w=16, leaf_size=500, l_max=2)
+    qt = torch.from_numpy(q).to(DEV)
+    ref = idx.knn(qt, 10)
+    out = {}
+
+    def call(qq, key):
+        out[key] = idx.knn(qq, 10, stats=True)
+
+    raw, words, env = hs.union_counts(idx, lambda: call(qt, "a"))
+    ids, d2, st = out["a"]
+    torch.cuda.synchronize()
+    assert torch.equal(ids, ref[0]) and torch.equal(d2, ref[1])
+    st = {f: v.cpu().numpy() for f, v in st.items()}
+    print(f"[union] raw {raw} words {words} env {env}; per query sums {st['chunks_read'].sum()} "
+          f"{st['rows_filtered'].sum()} {st['chunks_tested'].sum()}", flush=True)
+    nch = idx.info.row_stride // 64
+    assert 0 < raw <= st["chunks_read"].sum() and raw <= x.shape[0] * nch
+    assert 0 < words <= st["rows_filtered"].sum() and words <= x.shape[0]
+    assert st["chunks_tested"].max() <= env <= st["chunks_tested"].sum() and env <= idx.info.n_chunks
+    q2 = torch.cat([qt, qt]).contiguous()
+    raw2, words2, env2 = hs.union_counts(idx, lambda: call(q2, "b"))
+    assert env2 == env
+    assert torch.equal(out["b"][0][:len(q)], ref[0])
+    idx.close()
+
+
 def test_read_probe_reads_without_writing():
     hs = hs_mod()
     buf = torch.arange(1 << 22, dtype=torch.int32, device=DEV)  # 16 MiB
