@@ -10,12 +10,11 @@
  *
  * Conventions for every entry point:
  *  - Pointers named *_dev are device pointers; pointers without the suffix are
- *    host pointers.  The caller owns and frees every large device buffer
- *    (input series, index memory, low-precision copy, query workspace,
- *    outputs).  The library owns the opaque host handle returned by
- *    hs_build_summaries and the index's small device tables (leaf, part and
- *    chunk tables, envelopes, breakpoints: O(N / 64) entries), which
- *    hs_index_free releases.
+ *    host pointers.  The caller owns and frees every device buffer (input
+ *    series, index memory -- which also holds the index's tables and the
+ *    build's scratch --, low-precision copy, query workspace, outputs).  The
+ *    library owns only opaque host handles (index, server, scheduler) and
+ *    calls no device allocator (hs_knn_exact_noalloc's static array aside).
  *  - `stream` is a hipStream_t passed as void* (NULL = the null stream).  All
  *    device work is enqueued on it.  hs_build_summaries synchronises the
  *    stream (the leaf partition runs on the host); hs_knn_exact synchronises
@@ -67,8 +66,14 @@ typedef int32_t hs_status;
  *             workspace (0 = max(N/8, 4096)).  A query whose LB_SAX
  *             survivors do not fit is answered by the fused filter+refine
  *             kernel instead; results do not depend on it.
+ *  build_flags  0, or HS_BUILD_HOST_PARTITION: partition the series on the
+ *             host (the reference the device partition is tested against;
+ *             needs N * w * 16 bytes of host memory) instead of on the device.
+ *             Both give the same leaves and order.
+ *  reserved   0.
  * Every field is validated by hs_index_bytes / hs_build_summaries.
  */
+#define HS_BUILD_HOST_PARTITION 1
 typedef struct {
     int32_t n;
     int32_t w;
@@ -78,6 +83,8 @@ typedef struct {
     int32_t seed_rows;
     float eapca_th;
     int32_t cand_per_query;
+    int32_t build_flags;
+    int32_t reserved;
 } hs_params;
 
 typedef struct hs_index hs_index; /* opaque, library-owned host handle */
@@ -99,7 +106,12 @@ typedef struct {
  * Device bytes hs_build_summaries needs in `index_mem_dev` for N series:
  * the leaf-ordered copy of the series (the LRDFile analogue, Sec. 3.3),
  * the iSAX words in the same order (the LSDFile analogue), the id map,
- * the leaf table and envelopes, plus build-time scratch.
+ * the leaf, part and chunk tables with their envelopes (sized for at most
+ * min(N, 4 ceil(N / leaf_size) + 1024) leaves: the device partition stops
+ * splitting nodes into more leaves than that), and the build's scratch,
+ * which shares the rows' area when it fits there (it does whenever
+ * row_stride * 4 >= w * 16 + 64 bytes or so).  The library allocates no
+ * device memory of its own.
  * Errors: HS_EINVAL for N < 1, N >= 2^32, or invalid params.
  */
 hs_status hs_index_bytes(int64_t N, const hs_params* params, int64_t* bytes);
@@ -111,10 +123,13 @@ hs_status hs_index_bytes(int64_t N, const hs_params* params, int64_t* bytes);
  * (Sec. 3.2; see DESIGN notes for the split policy), stores the series in
  * leaf order, and computes every leaf's synopsis (Sec. 3.2, min/max of
  * segment mean and std, rounded outward to float32).
+ * The partition runs on the device, level by level (all nodes of one depth
+ * together); HS_BUILD_HOST_PARTITION runs it on the host instead.
  * x_dev may be freed after the call returns.  index_mem_dev must hold
  * hs_index_bytes() bytes and stay allocated until hs_index_free.
  * Errors: HS_EINVAL (NULL pointers, bad params, N out of range, non-finite
- * values in x), HS_ENOMEM (index_bytes too small or host memory), HS_EHIP.
+ * values in x), HS_ENOMEM (index_bytes too small, host memory, or a host
+ * partition with more leaves than the tables hold), HS_EHIP.
  */
 hs_status hs_build_summaries(const float* x_dev, int64_t N, const hs_params* params,
                              void* index_mem_dev, int64_t index_bytes, void* stream,

@@ -14,7 +14,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libhercules_hip.so")
 SOURCES = ["csrc/hs_build.hip", "csrc/hs_query.hip", "csrc/hs_filter.hip", "csrc/hs_refine.hip", "csrc/hs_scan.hip",
-           "csrc/hs_precision.hip", "csrc/hs_static.hip", "csrc/hs_api.cpp", "csrc/hs_server.cpp"]
+           "csrc/hs_precision.hip", "csrc/hs_static.hip", "csrc/hs_partition.hip", "csrc/hs_api.cpp", "csrc/hs_server.cpp"]
 ARCH = os.environ.get("HS_OFFLOAD_ARCH", "gfx950")
 
 

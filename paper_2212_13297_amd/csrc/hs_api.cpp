@@ -20,19 +20,6 @@
 using namespace hs;
 
 namespace {
-void free_owned(hs_index* idx) {
-    if (idx->leaf_start_dev) (void)hipFree(idx->leaf_start_dev);
-    if (idx->env_dev) (void)hipFree(idx->env_dev);
-    if (idx->beta_dev) (void)hipFree(idx->beta_dev);
-    if (idx->part_start_dev) (void)hipFree(idx->part_start_dev);
-    if (idx->part_leaf_dev) (void)hipFree(idx->part_leaf_dev);
-    if (idx->part_chunk_dev) (void)hipFree(idx->part_chunk_dev);
-    if (idx->chunk_start_dev) (void)hipFree(idx->chunk_start_dev);
-    if (idx->cenv_dev) (void)hipFree(idx->cenv_dev);
-}
-}  // namespace
-
-namespace {
 
 thread_local std::string g_err;
 
@@ -119,6 +106,8 @@ hs_status check_params(const hs_params* p) {
     if (p->seed_rows < 0) return fail(HS_EINVAL, "seed_rows=%d must be >= 0", p->seed_rows);
     if (!(p->eapca_th >= 0.0f) || !std::isfinite(p->eapca_th)) return fail(HS_EINVAL, "eapca_th must be finite, >= 0");
     if (p->cand_per_query < 0) return fail(HS_EINVAL, "cand_per_query=%d must be >= 0", p->cand_per_query);
+    if (p->build_flags & ~HS_BUILD_HOST_PARTITION) return fail(HS_EINVAL, "unknown build_flags 0x%x", p->build_flags);
+    if (p->reserved != 0) return fail(HS_EINVAL, "reserved must be 0");
     return HS_OK;
 }
 
@@ -245,6 +234,46 @@ void carve(char*& cur, void** out, int64_t bytes) {
     cur += align_up(bytes, 256);
 }
 
+// Leaves the index's tables are sized for: far above what a midpoint
+// partition makes (about 2 N / tau on random walks), and N for tiny leaves.
+int64_t leaf_budget(int64_t N, int64_t tau) {
+    return std::min<int64_t>(N, 4 * ((N + tau - 1) / tau) + 1024);
+}
+
+// Byte offsets inside the caller's index memory (base may be NULL: sizes only).
+IndexLayout index_layout(int64_t N, const hs_params& p, char* base) {
+    (void)base;
+    IndexLayout l{};
+    const int64_t stride = row_stride(p.n), wstride = word_stride(p.w);
+    l.leaf_budget = leaf_budget(N, p.leaf_size);
+    l.chunk_cap = (N + kChunkRows - 1) / kChunkRows + l.leaf_budget;  // each leaf cut from its first series
+    int64_t cur = 0;
+    auto take = [&](int64_t bytes) {
+        const int64_t at = cur;
+        cur += align_up(bytes, 256);
+        return at;
+    };
+    const int64_t rows_bytes = N * stride * 4;
+    l.rows = take(rows_bytes);
+    l.ids = take(N * 4);
+    l.words = take(N * wstride);
+    l.flag = take(256);
+    l.beta = take((kCard + 1) * 4);
+    l.leaf_start = take((l.leaf_budget + 1) * 8);
+    l.env = take(l.leaf_budget * p.w * 16);
+    l.part_start = take((l.chunk_cap + 1) * 8);
+    l.part_leaf = take(l.chunk_cap * 4);
+    l.part_chunk = take(l.chunk_cap * 8);
+    l.chunk_start = take((l.chunk_cap + 1) * 8);
+    l.cenv = take(l.chunk_cap * p.w * 16);
+    // build scratch: the device partition's buffers (the host partition needs
+    // only the statistics at their start), inside the rows' area when they fit
+    const int64_t scratch = partition_scratch_bytes(N, p.w, p.leaf_size, l.leaf_budget);
+    l.scratch = scratch <= rows_bytes ? l.rows : take(scratch);
+    l.total = cur;
+    return l;
+}
+
 int64_t ws_layout(const hs_index* idx, int32_t Q, int32_t k, QueryWs* ws, char* base, int64_t cand_fixed) {
     const IndexView& ix = idx->view;
     const int P = kPoolMin;
@@ -317,10 +346,7 @@ hs_status hs_index_bytes(int64_t N, const hs_params* params, int64_t* bytes) {
     if (s) return s;
     if (!bytes) return fail(HS_EINVAL, "bytes is NULL");
     if (N < 1 || N >= (int64_t)1 << 32) return fail(HS_EINVAL, "N=%lld out of range [1, 2^32)", (long long)N);
-    const int64_t rows = align_up(N * row_stride(params->n) * 4, 256);
-    const int64_t ids = align_up(N * 4, 256);
-    const int64_t words = align_up(N * word_stride(params->w), 256);
-    *bytes = rows + ids + words;
+    *bytes = index_layout(N, *params, nullptr).total;
     return HS_OK;
 }
 
@@ -344,30 +370,7 @@ hs_status hs_build_summaries(const float* x_dev, int64_t N, const hs_params* par
     idx->p = p;
     idx->device = device;
     idx->cus = cus;
-
-    IndexView& ix = idx->view;
-    ix.N = N;
-    ix.n = p.n;
-    ix.w = p.w;
-    ix.stride = row_stride(p.n);
-    ix.wstride = word_stride(p.w);
-    char* cur = (char*)index_mem_dev;
-    carve(cur, (void**)&ix.rows, N * ix.stride * 4);
-    carve(cur, (void**)&ix.ids, N * 4);
-    carve(cur, (void**)&ix.words, N * ix.wstride);
-    idx->index_bytes = need;
-
-    // 1. segment statistics for the partition (float32 copies are enough to
-    //    choose splits; envelopes are recomputed in FP64 below)
-    float2* st_dev = nullptr;
-    uint32_t* bad_dev = nullptr;
-    auto cleanup = [&]() {
-        if (st_dev) (void)hipFree(st_dev);
-        if (bad_dev) (void)hipFree(bad_dev);
-    };
     auto bail = [&](hs_status code) {
-        cleanup();
-        free_owned(idx);
         delete idx;
         return code;
     };
@@ -377,47 +380,81 @@ hs_status hs_build_summaries(const float* x_dev, int64_t N, const hs_params* par
         if (e_ != hipSuccess) return bail(fail(HS_EHIP, "%s: %s", #expr, hipGetErrorString(e_))); \
     } while (0)
 
-    BUILD_TRY(hipMalloc(&st_dev, sizeof(float2) * N * p.w));
-    BUILD_TRY(hipMalloc(&bad_dev, sizeof(uint32_t)));
+    // everything lives in the caller's index memory: the stored arrays, the
+    // small tables (sized for at most `budget` leaves) and, until the rows
+    // are gathered, the build's scratch (inside the rows' area when it fits)
+    char* base = (char*)index_mem_dev;
+    const IndexLayout lay = index_layout(N, p, base);
+    IndexView& ix = idx->view;
+    ix.N = N;
+    ix.n = p.n;
+    ix.w = p.w;
+    ix.stride = row_stride(p.n);
+    ix.wstride = word_stride(p.w);
+    ix.rows = (const float*)(base + lay.rows);
+    ix.ids = (const uint32_t*)(base + lay.ids);
+    ix.words = (const uint8_t*)(base + lay.words);
+    idx->index_bytes = need;
+    idx->beta_dev = (float*)(base + lay.beta);
+    idx->leaf_start_dev = (int64_t*)(base + lay.leaf_start);
+    idx->env_dev = (float4*)(base + lay.env);
+    idx->part_start_dev = (int64_t*)(base + lay.part_start);
+    idx->part_leaf_dev = (uint32_t*)(base + lay.part_leaf);
+    idx->part_chunk_dev = (int64_t*)(base + lay.part_chunk);
+    idx->chunk_start_dev = (int64_t*)(base + lay.chunk_start);
+    idx->cenv_dev = (float4*)(base + lay.cenv);
+    char* scratch = base + lay.scratch;
+    uint32_t* bad_dev = (uint32_t*)(base + lay.flag);
+
+    // 1. segment statistics (float32 copies of FP64 mean / std) for the partition
+    float2* st_dev = partition_stats_buffer(scratch, N, p.w, p.leaf_size, lay.leaf_budget);
     BUILD_TRY(hipMemsetAsync(bad_dev, 0, sizeof(uint32_t), st));
     BUILD_TRY(launch_series_stats(x_dev, N, p.n, p.w, st_dev, bad_dev, st));
-    Partition part;
-    part.w = p.w;
-    part.tau = p.leaf_size;
-    std::vector<float2> st_host;
-    std::vector<uint32_t> id_host;
-    try {
-        st_host.resize((size_t)N * p.w);
-        id_host.resize((size_t)N);
-        part.tmp_st.resize((size_t)N * p.w);
-        part.tmp_id.resize((size_t)N);
-    } catch (...) {
-        return bail(fail(HS_ENOMEM, "host allocation for the leaf partition failed"));
-    }
     uint32_t bad = 0;
-    BUILD_TRY(hipMemcpyAsync(st_host.data(), st_dev, sizeof(float2) * N * p.w, hipMemcpyDeviceToHost, st));
     BUILD_TRY(hipMemcpyAsync(&bad, bad_dev, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
     BUILD_TRY(hipStreamSynchronize(st));
     if (bad) return bail(fail(HS_EINVAL, "x contains NaN or Inf"));
 
-    // 2. host partition
-    for (int64_t i = 0; i < N; ++i) id_host[i] = (uint32_t)i;
-    part.st = st_host.data();
-    part.id = id_host.data();
-    part.run(0, N, 0, false);
-    std::sort(part.leaves.begin(), part.leaves.end());
-    const int64_t L = (int64_t)part.leaves.size();
-    std::vector<int64_t> leaf_start(L + 1);
-    int64_t max_leaf = 0;
-    for (int64_t i = 0; i < L; ++i) {
-        leaf_start[i] = part.leaves[i].first;
-        max_leaf = std::max(max_leaf, part.leaves[i].second - part.leaves[i].first);
+    // 2. leaf partition: on the device, or on the host (the reference the
+    //    device partition is tested against)
+    std::vector<int64_t> leaf_start;
+    if (p.build_flags & HS_BUILD_HOST_PARTITION) {
+        Partition part;
+        part.w = p.w;
+        part.tau = p.leaf_size;
+        std::vector<float2> st_host;
+        std::vector<uint32_t> id_host;
+        try {
+            st_host.resize((size_t)N * p.w);
+            id_host.resize((size_t)N);
+            part.tmp_st.resize((size_t)N * p.w);
+            part.tmp_id.resize((size_t)N);
+        } catch (...) {
+            return bail(fail(HS_ENOMEM, "host allocation for the leaf partition failed"));
+        }
+        BUILD_TRY(hipMemcpyAsync(st_host.data(), st_dev, sizeof(float2) * N * p.w, hipMemcpyDeviceToHost, st));
+        BUILD_TRY(hipStreamSynchronize(st));
+        for (int64_t i = 0; i < N; ++i) id_host[i] = (uint32_t)i;
+        part.st = st_host.data();
+        part.id = id_host.data();
+        part.run(0, N, 0, false);
+        std::sort(part.leaves.begin(), part.leaves.end());
+        for (auto& lf : part.leaves) leaf_start.push_back(lf.first);
+        if ((int64_t)leaf_start.size() > lay.leaf_budget)
+            return bail(fail(HS_ENOMEM, "the host partition made %lld leaves; the index memory holds tables for %lld",
+                             (long long)leaf_start.size(), (long long)lay.leaf_budget));
+        BUILD_TRY(hipMemcpyAsync((void*)ix.ids, id_host.data(), sizeof(uint32_t) * N, hipMemcpyHostToDevice, st));
+        BUILD_TRY(hipStreamSynchronize(st));
+    } else {
+        s = partition_device(N, p.w, p.leaf_size, lay.leaf_budget, scratch, cus, (uint32_t*)ix.ids, &leaf_start, st);
+        if (s) return bail(s);
     }
-    leaf_start[L] = N;
+    const int64_t L = (int64_t)leaf_start.size();
+    leaf_start.push_back(N);
+    int64_t max_leaf = 0;
+    for (int64_t i = 0; i < L; ++i) max_leaf = std::max(max_leaf, leaf_start[i + 1] - leaf_start[i]);
     ix.L = L;
     idx->max_leaf = max_leaf;
-    std::vector<float2>().swap(part.tmp_st);
-    std::vector<float2>().swap(st_host);
     // work items: every leaf cut into parts of at most kPartRows series;
     // chunks: every leaf cut into kChunkRows-series chunks (parts start on a
     // chunk boundary, so a part's chunks are consecutive)
@@ -438,23 +475,17 @@ hs_status hs_build_summaries(const float* x_dev, int64_t N, const hs_params* par
     const int64_t chunks = (int64_t)chunk_start.size();
     part_start.push_back(N);
     chunk_start.push_back(N);
+    if (chunks > lay.chunk_cap || parts > lay.chunk_cap)
+        return bail(fail(HS_EHIP, "table sizes exceed their reservation (%lld chunks)", (long long)chunks));
     ix.parts = parts;
     ix.chunks = chunks;
     idx->filter_waves = filter_waves(ix, idx->cus);
 
-    // 3. leaf-ordered copy, words, envelopes
+    // 3. tables, leaf-ordered copy, words, envelopes
     float beta_host[kCard + 1];
     beta_host[0] = -INFINITY;
     compute_breakpoints(beta_host + 1);
     beta_host[kCard] = INFINITY;
-    BUILD_TRY(hipMalloc(&idx->leaf_start_dev, sizeof(int64_t) * (L + 1)));
-    BUILD_TRY(hipMalloc(&idx->env_dev, sizeof(float4) * L * p.w));
-    BUILD_TRY(hipMalloc(&idx->beta_dev, sizeof(float) * (kCard + 1)));
-    BUILD_TRY(hipMalloc(&idx->part_start_dev, sizeof(int64_t) * (parts + 1)));
-    BUILD_TRY(hipMalloc(&idx->part_leaf_dev, sizeof(uint32_t) * parts));
-    BUILD_TRY(hipMalloc(&idx->part_chunk_dev, sizeof(int64_t) * parts));
-    BUILD_TRY(hipMalloc(&idx->chunk_start_dev, sizeof(int64_t) * (chunks + 1)));
-    BUILD_TRY(hipMalloc(&idx->cenv_dev, sizeof(float4) * chunks * p.w));
     BUILD_TRY(hipMemcpyAsync(idx->part_chunk_dev, part_chunk.data(), sizeof(int64_t) * parts,
                              hipMemcpyHostToDevice, st));
     BUILD_TRY(hipMemcpyAsync(idx->chunk_start_dev, chunk_start.data(), sizeof(int64_t) * (chunks + 1),
@@ -466,7 +497,6 @@ hs_status hs_build_summaries(const float* x_dev, int64_t N, const hs_params* par
     BUILD_TRY(hipMemcpyAsync(idx->part_leaf_dev, part_leaf.data(), sizeof(uint32_t) * parts,
                              hipMemcpyHostToDevice, st));
     BUILD_TRY(hipMemcpyAsync(idx->beta_dev, beta_host, sizeof(beta_host), hipMemcpyHostToDevice, st));
-    BUILD_TRY(hipMemcpyAsync((void*)ix.ids, id_host.data(), sizeof(uint32_t) * N, hipMemcpyHostToDevice, st));
     ix.leaf_start = idx->leaf_start_dev;
     ix.env = idx->env_dev;
     ix.beta = idx->beta_dev;
@@ -474,12 +504,12 @@ hs_status hs_build_summaries(const float* x_dev, int64_t N, const hs_params* par
     ix.part_leaf = idx->part_leaf_dev;
     ix.part_chunk = idx->part_chunk_dev;
     ix.cenv = idx->cenv_dev;
+    // the gather overwrites the scratch inside the rows' area: the partition is done
     BUILD_TRY(launch_gather_rows(x_dev, ix.ids, N, p.n, ix.stride, (float*)ix.rows, st));
     BUILD_TRY(launch_words(ix, (uint8_t*)ix.words, st));
     BUILD_TRY(launch_envelopes(ix, idx->leaf_start_dev, L, idx->env_dev, st));
     BUILD_TRY(launch_envelopes(ix, idx->chunk_start_dev, chunks, idx->cenv_dev, st));
     BUILD_TRY(hipStreamSynchronize(st));
-    cleanup();
 #undef BUILD_TRY
     *out = idx;
     return HS_OK;
@@ -827,9 +857,7 @@ hs_status hs_read_probe(const void* buf_dev, int64_t bytes, int32_t passes, uint
 }
 
 hs_status hs_index_free(hs_index* idx) {
-    if (!idx) return HS_OK;
-    free_owned(idx);
-    delete idx;
+    delete idx;  // the tables live in the caller's index memory
     return HS_OK;
 }
 

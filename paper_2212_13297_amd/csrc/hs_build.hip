@@ -1,6 +1,6 @@
 // Index-build kernels (Hercules Sec. 2 summaries, Sec. 3.2 tree):
 //   series_stats  per (series, segment) mean and population std (FP64 math),
-//                 used by the host to choose the leaf splits
+//                 from which the partition chooses the leaf splits
 //   gather_rows   leaf-ordered, zero-padded copy of the series
 //   words         iSAX symbol per (series, segment): FP64 PAA against the
 //                 float32 Gaussian breakpoints
@@ -54,11 +54,15 @@ __global__ void k_words(IndexView ix, uint8_t* __restrict__ words) {
     for (int j = threadIdx.x; j <= kCard; j += blockDim.x) s_beta[j] = ix.beta[j];
     __syncthreads();
     const int32_t l = ix.n / ix.w;
-    const int64_t total = ix.N * (int64_t)ix.w;
+    const int64_t total = ix.N * (int64_t)ix.wstride;  // padding symbols are written as 0
     for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < total;
          t += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t pos = t / ix.w;
-        const int32_t seg = (int32_t)(t - pos * ix.w);
+        const int64_t pos = t / ix.wstride;
+        const int32_t seg = (int32_t)(t - pos * ix.wstride);
+        if (seg >= ix.w) {
+            words[pos * ix.wstride + seg] = 0;
+            continue;
+        }
         const float* p = ix.rows + pos * ix.stride + (int64_t)seg * l;
         double s = 0.0;
         for (int j = 0; j < l; ++j) s += (double)p[j];
@@ -163,7 +167,7 @@ hipError_t launch_gather_rows(const float* x, const uint32_t* perm, int64_t N, i
 }
 
 hipError_t launch_words(const IndexView& ix, uint8_t* words, hipStream_t st) {
-    hipLaunchKernelGGL(k_words, dim3(grid_for(ix.N * ix.w, 256)), dim3(256), 0, st, ix, words);
+    hipLaunchKernelGGL(k_words, dim3(grid_for(ix.N * ix.wstride, 256)), dim3(256), 0, st, ix, words);
     return hipGetLastError();
 }
 

@@ -5,6 +5,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <vector>
+
 #include "hs_internal.h"
 
 struct hs_index {
@@ -14,14 +16,15 @@ struct hs_index {
     int cus = 0;
     int64_t max_leaf = 0;
     int64_t index_bytes = 0;
-    int64_t* leaf_start_dev = nullptr;  // library-owned
-    float4* env_dev = nullptr;          // library-owned
-    float* beta_dev = nullptr;          // library-owned
-    int64_t* part_start_dev = nullptr;  // library-owned
-    uint32_t* part_leaf_dev = nullptr;  // library-owned
-    int64_t* part_chunk_dev = nullptr;  // library-owned
-    int64_t* chunk_start_dev = nullptr; // library-owned
-    float4* cenv_dev = nullptr;         // library-owned
+    // the small tables, inside the caller's index memory
+    int64_t* leaf_start_dev = nullptr;
+    float4* env_dev = nullptr;
+    float* beta_dev = nullptr;
+    int64_t* part_start_dev = nullptr;
+    uint32_t* part_leaf_dev = nullptr;
+    int64_t* part_chunk_dev = nullptr;
+    int64_t* chunk_start_dev = nullptr;
+    float4* cenv_dev = nullptr;
     int filter_waves = 4;               // wavefronts of the filter kernel (candidate slices)
     hs::ShadowView shadow{};            // low-precision copy (caller-owned memory), kind 0 = none
 };
@@ -38,6 +41,24 @@ hs_status fail(hs_status code, const char* fmt, ...);
     } while (0)
 
 int64_t align_up(int64_t v, int64_t a);
+
+// Byte offsets of an index's arrays inside the caller's index memory.
+struct IndexLayout {
+    int64_t rows, ids, words, flag, beta, leaf_start, env, part_start, part_leaf, part_chunk, chunk_start, cenv;
+    int64_t scratch;      // the build's scratch (the rows' area when it fits)
+    int64_t total;
+    int64_t leaf_budget;  // leaves the tables hold
+    int64_t chunk_cap;    // chunks (and parts) the tables hold
+};
+IndexLayout index_layout(int64_t N, const hs_params& p, char* base);
+
+// Device leaf partition (hs_partition.hip).  The statistics [N][w] go into
+// partition_stats_buffer(scratch) before the call; on return ids_out holds the
+// original id of every stored position and *leaf_starts the sorted leaf starts.
+int64_t partition_scratch_bytes(int64_t N, int w, int64_t tau, int64_t budget);
+float2* partition_stats_buffer(char* scratch, int64_t N, int w, int64_t tau, int64_t budget);
+hs_status partition_device(int64_t N, int w, int64_t tau, int64_t budget, char* scratch, int cus,
+                           uint32_t* ids_out, std::vector<int64_t>* leaf_starts, hipStream_t st);
 
 // Query workspace layout for Q queries (bytes; fills *ws when base is given).
 // cand_total > 0 fixes the candidate-list entries (otherwise they follow the

@@ -25,10 +25,14 @@ HS_SHADOW_BF16 = 1
 HS_SHADOW_FP16 = 2
 
 
+HS_BUILD_HOST_PARTITION = 1
+
+
 class hs_params(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int32), ("w", ctypes.c_int32), ("card_bits", ctypes.c_int32),
                 ("leaf_size", ctypes.c_int32), ("l_max", ctypes.c_int32), ("seed_rows", ctypes.c_int32),
-                ("eapca_th", ctypes.c_float), ("cand_per_query", ctypes.c_int32)]
+                ("eapca_th", ctypes.c_float), ("cand_per_query", ctypes.c_int32), ("build_flags", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
 
 
 class hs_index_info(ctypes.Structure):
@@ -376,10 +380,11 @@ class Params:
     eapca_th: float = 0.0
     card_bits: int = 8
     cand_per_query: int = 0
+    build_flags: int = 0
 
     def c(self, n: int) -> hs_params:
         return hs_params(n, self.w, self.card_bits, self.leaf_size, self.l_max, self.seed_rows,
-                         float(self.eapca_th), self.cand_per_query)
+                         float(self.eapca_th), self.cand_per_query, self.build_flags, 0)
 
 
 def _stream_ptr(stream):

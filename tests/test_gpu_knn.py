@@ -97,6 +97,38 @@ def test_build_summaries_against_oracle():
     idx.close()
 
 
+@pytest.mark.parametrize("N,n,w,tau,dup", [(30_011, 256, 16, 700, 0), (3_000, 64, 8, 1, 0), (12_000, 64, 64, 50, 0),
+                                           (9_000, 200, 5, 333, 2_000), (70_000, 128, 16, 10_000, 0)])
+def test_device_partition_equals_host_partition(N, n, w, tau, dup):
+    # The level-by-level device partition and the recursive host partition
+    # make the same leaves and store the series in the same order (same
+    # float32 statistics, same FP64 thresholds and scores); hence the same
+    # words, envelopes and chunk tables.  Cases: ragged N, one series per
+    # leaf, w = 64 (its scratch outside the rows' area), w = 5 (2w = 10
+    # statistics), thousands of exact duplicates (unsplittable nodes), and
+    # leaves of 10,000.
+    hs = hs_mod()
+    x = G.random_walks(N, n, coll=40 + w).copy()
+    if dup:
+        x[np.arange(3, N, 4)[:dup]] = x[1]
+    a = make_index(x, w=w, leaf_size=tau)
+    b = make_index(x, w=w, leaf_size=tau, build_flags=hs.HS_BUILD_HOST_PARTITION)
+    ra, ia, wa, la, ea = a.layout()
+    rb, ib, wb, lb, eb = b.layout()
+    assert np.array_equal(la, lb)
+    assert torch.equal(ia, ib) and torch.equal(ra, rb) and torch.equal(wa, wb)
+    assert np.array_equal(ea, eb)
+    ca, cea = hs.hs_get_chunks(a.h, a.info)
+    cb, ceb = hs.hs_get_chunks(b.h, b.info)
+    assert np.array_equal(ca, cb) and np.array_equal(cea, ceb)
+    sizes = np.diff(la)
+    print(f"[partition] {len(la) - 1} leaves, largest {sizes.max()}, smallest {sizes.min()}", flush=True)
+    if not dup:
+        assert sizes.max() <= tau
+    a.close()
+    b.close()
+
+
 # ----------------------------------------------------------------- parity
 
 CASES = [
