@@ -40,7 +40,8 @@ typedef int32_t hs_status;
 #define HS_EINVAL (-1)   /* invalid argument (sizes, NULL pointers, non-finite input) */
 #define HS_ENOMEM (-2)   /* caller-provided buffer too small, or host allocation failed */
 #define HS_EHIP (-3)     /* a HIP runtime call failed */
-#define HS_EBUSY (-4)    /* reserved */
+#define HS_EBUSY (-4)    /* no free slot (hs_submit, hs_sched_submit); request already running (hs_cancel) */
+#define HS_ECANCEL (-5)  /* status of a completion whose request was withdrawn by hs_cancel */
 
 /* Largest k accepted by hs_knn_exact (the per-workgroup top-k lives in LDS). */
 #define HS_KMAX 128
@@ -311,7 +312,7 @@ typedef struct {
     uint64_t tag;            /* the caller's tag */
     int32_t coll;            /* collection */
     int32_t k;               /* neighbours requested */
-    hs_status status;        /* HS_OK, or the error that failed its batch */
+    hs_status status;        /* HS_OK, HS_ECANCEL (withdrawn), or the error that failed its batch */
     int32_t batch;           /* requests in the batch it ran in */
     double t_submit;         /* seconds on hs_server_now's clock: hs_submit accepted it */
     double t_launch;         /* its batch was launched */
@@ -340,6 +341,12 @@ hs_status hs_server_create(hs_index* const* colls, const int32_t* forms, int32_t
  * value beyond the fp16 range for an fp16 precision-form collection),
  * HS_EBUSY (no free slot), HS_EHIP (the server failed earlier). */
 hs_status hs_submit(hs_server* srv, int32_t coll, const float* q_host, int32_t k, uint64_t tag);
+/* Withdraw a queued request (the oldest one with this tag): its slot is free
+ * at once and hs_poll hands out its completion with status HS_ECANCEL (and no
+ * results), so every accepted request still completes exactly once.
+ * Errors: HS_EBUSY (its batch is already on the device: it completes
+ * normally), HS_EINVAL (no request with that tag is queued). */
+hs_status hs_cancel(hs_server* srv, uint64_t tag);
 /* Up to max completions, oldest first; *got of them written. */
 hs_status hs_poll(hs_server* srv, hs_completion* out, int32_t max, int32_t* got);
 hs_status hs_server_info(hs_server* srv, hs_server_stats* out);
@@ -358,12 +365,15 @@ double hs_server_now(void);
  * none.  tags must hold max_tags >= the largest max_q entry.  The stream stays
  * busy until hs_sched_complete.  hs_sched_submit: HS_EBUSY when max_slots
  * requests are in the system, HS_EINVAL for a k no region holds.
+ * hs_sched_cancel withdraws the oldest queued request with the tag (HS_EINVAL
+ * if none is queued; a request in a formed batch is not).
  */
 typedef struct hs_sched hs_sched;
 hs_status hs_sched_create(int32_t C, int32_t streams, int32_t max_slots, const int32_t* max_q, hs_sched** out);
 hs_status hs_sched_submit(hs_sched* s, int32_t coll, int32_t k, uint64_t tag);
 hs_status hs_sched_next(hs_sched* s, int32_t coll, int32_t stream, int32_t* q_pad, int32_t* k_batch, uint64_t* tags,
                         int32_t max_tags, int32_t* count);
+hs_status hs_sched_cancel(hs_sched* s, uint64_t tag);
 hs_status hs_sched_complete(hs_sched* s, int32_t coll, int32_t stream);
 hs_status hs_sched_in_system(hs_sched* s, int32_t* n);
 hs_status hs_sched_destroy(hs_sched* s);

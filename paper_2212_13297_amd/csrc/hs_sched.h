@@ -94,6 +94,22 @@ public:
         return true;
     }
 
+    // Withdraw the oldest queued request with this tag (searching every
+    // collection): 0 = withdrawn (*out holds it; its slot is free again),
+    // 1 = none queued.  A request already in a batch is not queued any more.
+    int cancel(uint64_t tag, SchedRequest* out) {
+        for (auto& q : pending_) {
+            for (auto it = q.begin(); it != q.end(); ++it) {
+                if (it->tag != tag) continue;
+                if (out) *out = *it;
+                q.erase(it);
+                --used_;
+                return 0;
+            }
+        }
+        return 1;
+    }
+
     void complete(int coll, int stream) {
         if (coll < 0 || coll >= colls_ || stream < 0 || stream >= streams_) return;
         const int s = coll * streams_ + stream;

@@ -209,6 +209,7 @@ void finish_batch(hs_server* s, StreamSlot& sl, hs_status failed = HS_OK) {
     if (status && s->error.empty()) s->error = msg;
     for (auto& c : out) s->done.push_back(c);
     s->sched->complete(sl.coll, sl.index);
+    sl.batch.reqs.clear();  // hs_cancel looks for running requests here (under mu)
     sl.busy = false;
     sl.running = nullptr;
 }
@@ -439,6 +440,31 @@ hs_status hs_submit(hs_server* s, int32_t coll, const float* q_host, int32_t k, 
     return HS_OK;
 }
 
+hs_status hs_cancel(hs_server* s, uint64_t tag) {
+    if (!s) return fail(HS_EINVAL, "NULL argument");
+    std::lock_guard<std::mutex> g(s->mu);
+    SchedRequest r;
+    if (s->sched->cancel(tag, &r) != 0) {
+        // launched (it completes normally) or unknown; a slot's batch is
+        // formed and cleared under mu
+        for (auto& sl : s->slots)
+            for (auto& q : sl.batch.reqs)
+                if (q.tag == tag) return fail(HS_EBUSY, "request %llu is running", (unsigned long long)tag);
+        return fail(HS_EINVAL, "no queued request with tag %llu", (unsigned long long)tag);
+    }
+    s->qdata.erase(r.seq);
+    hs_completion c;
+    std::memset(&c, 0, sizeof c);
+    c.tag = r.tag;
+    c.coll = r.coll;
+    c.k = r.k;
+    c.status = HS_ECANCEL;
+    c.t_submit = r.t_submit;
+    c.t_done = now_s();
+    s->done.push_back(c);
+    return HS_OK;
+}
+
 hs_status hs_poll(hs_server* s, hs_completion* out, int32_t max, int32_t* got) {
     if (!s || !got || (max > 0 && !out)) return fail(HS_EINVAL, "NULL argument");
     std::lock_guard<std::mutex> g(s->mu);
@@ -525,6 +551,12 @@ hs_status hs_sched_next(hs_sched* h, int32_t coll, int32_t stream, int32_t* q_pa
     *count = m;
     *q_pad = h->scratch.q_pad;
     *k_batch = h->scratch.k_batch;
+    return HS_OK;
+}
+
+hs_status hs_sched_cancel(hs_sched* h, uint64_t tag) {
+    if (!h) return fail(HS_EINVAL, "NULL argument");
+    if (h->s->cancel(tag, nullptr) != 0) return fail(HS_EINVAL, "no queued request with tag %llu", (unsigned long long)tag);
     return HS_OK;
 }
 

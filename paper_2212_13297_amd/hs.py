@@ -20,6 +20,7 @@ HS_EINVAL = -1
 HS_ENOMEM = -2
 HS_EHIP = -3
 HS_EBUSY = -4
+HS_ECANCEL = -5
 HS_KMAX = 128
 HS_SHADOW_BF16 = 1
 HS_SHADOW_FP16 = 2
@@ -87,6 +88,8 @@ _SIGS = {
                                           ctypes.POINTER(hs_server_config), ctypes.POINTER(_P)]),
     "hs_submit": (ctypes.c_int32, [_P, ctypes.c_int32, _P, ctypes.c_int32, ctypes.c_uint64]),
     "hs_poll": (ctypes.c_int32, [_P, _P, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)]),
+    "hs_cancel": (ctypes.c_int32, [_P, ctypes.c_uint64]),
+    "hs_sched_cancel": (ctypes.c_int32, [_P, ctypes.c_uint64]),
     "hs_server_info": (ctypes.c_int32, [_P, ctypes.POINTER(hs_server_stats)]),
     "hs_server_destroy": (ctypes.c_int32, [_P]),
     "hs_server_now": (ctypes.c_double, []),
@@ -222,6 +225,18 @@ def hs_submit(srv, coll: int, q_ptr: int, k: int, tag: int) -> int:
     if code not in (HS_OK, HS_EBUSY):
         _check(code)
     return code
+
+
+def hs_cancel(srv, tag: int) -> int:
+    """Returns HS_OK (withdrawn) or HS_EBUSY (already running); raises on other errors."""
+    code = load().hs_cancel(srv, tag)
+    if code not in (HS_OK, HS_EBUSY):
+        _check(code)
+    return code
+
+
+def hs_sched_cancel(h, tag: int) -> None:
+    _check(load().hs_sched_cancel(h, tag))
 
 
 def hs_poll(srv, buf, max_n: int) -> int:
@@ -523,6 +538,11 @@ class Server:
         if 0 <= coll < len(self.indexes) and (q.ndim != 1 or q.shape[0] != self.indexes[coll].n):
             raise ValueError("q must be float32 [n] of the collection")
         return hs_submit(self.h, coll, q.ctypes.data, k, tag) == HS_OK
+
+    def cancel(self, tag: int) -> bool:
+        """Withdraw a queued request (its completion comes with status HS_ECANCEL);
+        False if it is already running."""
+        return hs_cancel(self.h, tag) == HS_OK
 
     def poll(self):
         """List of completions (dicts with tag, coll, k, status, batch, times, ids, d2, err)."""

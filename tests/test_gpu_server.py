@@ -159,6 +159,44 @@ def test_busy_slots_and_stream_of_arrivals():
         ix.close()
 
 
+def test_cancel_queued_requests():
+    # One stream per collection and batches of at most 2: a burst queues most
+    # requests behind the running batches.  Withdrawing some of them frees
+    # their slots and completes them with HS_ECANCEL (no results); a request
+    # already on the device completes normally (HS_EBUSY from cancel).  Every
+    # accepted request completes exactly once, the others with the eager
+    # path's results.
+    hs = hs_mod()
+    xs, idxs = build_collections()
+    srv = hs.Server(idxs, [0, 1, 0], budget_bytes=1 << 30, streams_per_coll=1, max_slots=256, max_batch=2)
+    reqs = requests(xs, 60, seed=11)
+    for t, (c, q, k) in enumerate(reqs):
+        assert srv.submit(c, q, k, t)
+    withdrawn, running = set(), set()
+    for t in range(len(reqs) - 1, 19, -3):      # the latest requests are the likeliest still queued
+        (withdrawn if srv.cancel(t) else running).add(t)
+    with pytest.raises(hs.HSError):
+        srv.cancel(10_000)                        # no such request
+    done = drain(srv, len(reqs))
+    assert sorted(done) == list(range(len(reqs)))
+    print(f"[cancel] withdrawn {len(withdrawn)}, already running {len(running)}", flush=True)
+    assert len(withdrawn) >= 5
+    for t, r in done.items():
+        if t in withdrawn:
+            assert r["status"] == hs.HS_ECANCEL
+        else:
+            assert r["status"] == 0
+    for t in list(running)[:5] + [t for t in range(0, 20, 4)]:
+        c, q, k = reqs[t]
+        ids, d2 = eager(idxs[c], q, k, c == 1)
+        assert list(ids) == done[t]["ids"] and list(d2) == done[t]["d2"]
+    with pytest.raises(hs.HSError):
+        srv.cancel(0)                             # completed: not queued any more
+    srv.close()
+    for ix in idxs:
+        ix.close()
+
+
 def test_server_argument_errors():
     hs = hs_mod()
     xs, idxs = build_collections()

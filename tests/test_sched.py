@@ -48,6 +48,26 @@ def test_slots_limit_and_release(lib):
     hs.hs_sched_destroy(h)
 
 
+def test_cancel_withdraws_queued_requests_only(lib):
+    h = make(2, 1, 4, [[4] * 8, [4] * 8])
+    for t, c in ((10, 0), (11, 0), (12, 1), (13, 0)):
+        assert hs.hs_sched_submit(h, c, 1, t) == HS_OK
+    assert hs.hs_sched_submit(h, 0, 1, 14) == HS_EBUSY   # four slots, all taken
+    hs.hs_sched_cancel(h, 11)                           # queued: withdrawn, its slot freed
+    assert hs.hs_sched_in_system(h) == 3
+    assert hs.hs_sched_submit(h, 0, 1, 14) == HS_OK
+    assert hs.hs_sched_next(h, 0, 0) == (4, 1, [10, 13, 14])  # FIFO without the withdrawn one
+    with pytest.raises(hs.HSError):
+        hs.hs_sched_cancel(h, 13)                       # in a formed batch: no longer queued
+    with pytest.raises(hs.HSError):
+        hs.hs_sched_cancel(h, 99)                       # unknown tag
+    hs.hs_sched_cancel(h, 12)                           # the other collection's queue
+    assert hs.hs_sched_next(h, 1, 0) is None
+    hs.hs_sched_complete(h, 0, 0)
+    assert hs.hs_sched_in_system(h) == 0
+    hs.hs_sched_destroy(h)
+
+
 def test_capacity_depends_on_k_bucket(lib):
     # regions hold 8 queries at small k, 2 at k in (32, 64], none beyond
     h = make(1, 2, 100, [[8, 8, 8, 8, 8, 8, 2, 0]])
