@@ -240,15 +240,26 @@ hs_status hs_knn_exact_noalloc(hs_index* idx, const float* q_dev, int32_t Q, int
 #define HS_SHADOW_BF16 1
 #define HS_SHADOW_FP16 2
 
-/* Device bytes of the low-precision copy of kind HS_SHADOW_*: (N + 32) x
- * row_stride 16-bit values and (N + 32) x 16 bytes of per-series constants
- * (the last 32 rows are zero padding), plus 256 bytes of scratch.
+/* Device bytes of the low-precision copy of kind HS_SHADOW_*: (R + 32) x
+ * row_stride 16-bit values and (R + 32) x 16 bytes of per-series constants
+ * (the last 32 rows are zero padding), plus 256 bytes of scratch.  R is the
+ * number of stored series the copy holds: all N when shadow_rows < 0 or
+ * shadow_rows >= N; otherwise the series of the whole work parts (leaf
+ * pieces of at most 8192 series, in stored order) that fit in the first
+ * shadow_rows -- a partial copy for collections whose full copy does not fit
+ * beside the float32 series.
  * Errors: HS_EINVAL (NULL, unknown kind). */
-hs_status hs_shadow_bytes(const hs_index* idx, int32_t kind, int64_t* bytes);
+hs_status hs_shadow_bytes(const hs_index* idx, int32_t kind, int64_t shadow_rows, int64_t* bytes);
 
-/* Build the low-precision copy into caller-owned device memory shadow_dev
+/* Build the low-precision copy of (the first R stored series, as for
+ * hs_shadow_bytes, of) the index into caller-owned device memory shadow_dev
  * (hs_shadow_bytes bytes, kept allocated until hs_index_free or the next
- * hs_build_shadow).  Per series it stores x~ in leaf order and four floats:
+ * hs_build_shadow).  With a partial copy, hs_knn_mixed bounds the series the
+ * copy holds on the matrix cores and filters the others by LB_SAX, both
+ * feeding one candidate list refined in the compensated form (same results);
+ * the query workspace then holds twice the candidate slices, so
+ * hs_query_workspace_bytes is to be taken after this call.
+ * Per series it stores x~ in leaf order and four floats:
  * beta (the series' term of the bounding pass's float32 test, computed in
  * float64 from the next two, rounded down), ||x - x~||_2 (float64, stored
  * rounded up), ||x~||^2 (float64, stored rounded down) and, for series of
@@ -260,7 +271,8 @@ hs_status hs_shadow_bytes(const hs_index* idx, int32_t kind, int64_t* bytes);
  * call replaces it.
  * Errors: HS_EINVAL (NULL, unknown kind, a value beyond the fp16 range for
  * HS_SHADOW_FP16), HS_ENOMEM (shadow_bytes too small), HS_EHIP. */
-hs_status hs_build_shadow(hs_index* idx, int32_t kind, void* shadow_dev, int64_t shadow_bytes, void* stream);
+hs_status hs_build_shadow(hs_index* idx, int32_t kind, int64_t shadow_rows, void* shadow_dev, int64_t shadow_bytes,
+                          void* stream);
 
 /*
  * Exact k-NN of Q queries through the precision form.  Arguments, result

@@ -289,7 +289,10 @@ int64_t ws_layout(const hs_index* idx, int32_t Q, int32_t k, QueryWs* ws, char* 
         cand_fixed > 0 ? std::min<int64_t>(cand_fixed, (int64_t)1 << 31)
                        : std::min<int64_t>(std::max<int64_t>((int64_t)Q * per_q, floor_c), (int64_t)1 << 31);
     // 3/4 in the filter wavefronts' private slices, 1/4 in a shared overflow slice
-    const int n_slices = idx->filter_waves;
+    // a partial low-precision copy: the bounding pass and the LB_SAX filter
+    // each fill their own half of the slices
+    const bool hybrid = idx->shadow.kind != 0 && idx->shadow.rows_n < ix.N;
+    const int n_slices = idx->filter_waves * (hybrid ? 2 : 1);
     const int64_t slice_cap = (cand_total * 3 / 4 + n_slices - 1) / n_slices;
     const int64_t ovf_cap = std::max<int64_t>(cand_total / 4, cpq > 0 ? 1 : 4096);
     const int64_t cand = slice_cap * n_slices + ovf_cap;
@@ -475,6 +478,7 @@ hs_status hs_build_summaries(const float* x_dev, int64_t N, const hs_params* par
     const int64_t chunks = (int64_t)chunk_start.size();
     part_start.push_back(N);
     chunk_start.push_back(N);
+    idx->part_start_host = part_start;
     if (chunks > lay.chunk_cap || parts > lay.chunk_cap)
         return bail(fail(HS_EHIP, "table sizes exceed their reservation (%lld chunks)", (long long)chunks));
     ix.parts = parts;
@@ -641,6 +645,9 @@ hs_status knn_prepare(hs_index* idx, int32_t Q, int32_t k, void* ws_dev, int64_t
     c->sp.seed_rows = idx->p.seed_rows;
     c->sp.order_lg = chunk_order_lg(ix);
     c->sp.marg = abandon_margin(ix.stride);
+    c->sp.emit_part0 = 0;
+    c->sp.slice0 = 0;
+    c->sp.slices = c->ws.n_slices;
     return HS_OK;
 }
 
@@ -666,12 +673,26 @@ hs_status knn_enqueue(const KnnCall& c, const float* q_dev, int64_t* ids_dev, fl
     HIP_TRY(launch_seed(ix, sp, ws, c.form, st));
     // step 2: candidate leaves; step 3: per-series filter (LB_SAX, or the
     // matrix-core bound of the precision form); step 4: refinement
-    HIP_TRY(launch_emit(ix, sp, false, ws, st));
+    const ShadowView& sv = c.idx->shadow;
+    const bool hybrid = c.mixed && sv.rows_n < ix.N;
+    {
+        ScanParams se = sp;
+        if (hybrid) se.emit_part0 = sv.parts_n;  // items only where the copy does not reach
+        HIP_TRY(launch_emit(ix, se, false, ws, st));
+    }
     if (c.mixed) {
+        ScanParams sb = sp;
+        if (hybrid) {
+            sb.slice0 = ws.n_slices / 2;
+            sb.slices = ws.n_slices / 2;
+        }
         HIP_TRY(launch_query_order(sp.Q, ws, st));
-        HIP_TRY(timed(HS_PROF_BOUND, [&] { return launch_bound(ix, c.idx->shadow, sp, ws, c.idx->cus, st); }));
-    } else {
-        HIP_TRY(timed(HS_PROF_FILTER, [&] { return launch_filter(ix, sp, ws, c.idx->cus, st); }));
+        HIP_TRY(timed(HS_PROF_BOUND, [&] { return launch_bound(ix, sv, sb, ws, c.idx->cus, st); }));
+    }
+    if (!c.mixed || hybrid) {
+        ScanParams sf = sp;
+        if (hybrid) sf.slices = ws.n_slices / 2;
+        HIP_TRY(timed(HS_PROF_FILTER, [&] { return launch_filter(ix, sf, ws, c.idx->cus, st); }));
     }
     HIP_TRY(launch_slice_prefix(ws, st));
     HIP_TRY(timed(HS_PROF_REFINE, [&] { return launch_refine(ix, sp, ws, c.idx->cus, c.form, st); }));
@@ -730,18 +751,35 @@ hs_status run_knn(hs_index* idx, const float* q_dev, int32_t Q, int32_t k, void*
     return knn_finish(c, ids_dev, d2_dev, err_dev, stats_out, st, &timer);
 }
 
-// The copy is followed by kBoundRows zero rows (and zero norms), so the
-// bounding pass may stage a whole tile past the last series.
-int64_t shadow_layout(const IndexView& ix, uint16_t** rows, float4** norms, uint32_t** flag, char* base) {
+// The copy of the first R stored series is followed by kBoundRows zero rows
+// (and zero norms), so the bounding pass may stage a whole tile past its last
+// series.
+int64_t shadow_layout(const IndexView& ix, int64_t R, uint16_t** rows, float4** norms, uint32_t** flag, char* base) {
     char* cur = base;
     void* a;
-    carve(cur, &a, (ix.N + kBoundRows) * ix.stride * 2);
+    carve(cur, &a, (R + kBoundRows) * ix.stride * 2);
     if (rows) *rows = (uint16_t*)a;
-    carve(cur, &a, (ix.N + kBoundRows) * 16);
+    carve(cur, &a, (R + kBoundRows) * 16);
     if (norms) *norms = (float4*)a;
     carve(cur, &a, 256);
     if (flag) *flag = (uint32_t*)a;
     return (int64_t)(cur - base);
+}
+
+// Series and parts a copy of (at most) shadow_rows series covers: whole parts
+// from the first, all N for shadow_rows < 0 or >= N.
+void shadow_extent(const hs_index* idx, int64_t shadow_rows, int64_t* rows, int64_t* parts) {
+    const IndexView& ix = idx->view;
+    if (shadow_rows < 0 || shadow_rows >= ix.N) {
+        *rows = ix.N;
+        *parts = ix.parts;
+        return;
+    }
+    // parts cover [part_start[p], part_start[p + 1]) in order: the last whole one
+    const std::vector<int64_t>& ps = idx->part_start_host;
+    const int64_t p = (int64_t)(std::upper_bound(ps.begin(), ps.end(), shadow_rows) - ps.begin()) - 1;
+    *parts = std::max<int64_t>(0, p);
+    *rows = ps[(size_t)*parts];
 }
 
 }  // namespace
@@ -758,29 +796,34 @@ hs_status hs_knn_mixed(hs_index* idx, const float* q_dev, int32_t Q, int32_t k, 
     return run_knn(idx, q_dev, Q, k, ws_dev, ws_bytes, ids_dev, d2_dev, err_dev, stats_dev, stream, true);
 }
 
-hs_status hs_shadow_bytes(const hs_index* idx, int32_t kind, int64_t* bytes) {
+hs_status hs_shadow_bytes(const hs_index* idx, int32_t kind, int64_t shadow_rows, int64_t* bytes) {
     if (!idx || !bytes) return fail(HS_EINVAL, "NULL argument");
     if (kind != kShadowBf16 && kind != kShadowF16) return fail(HS_EINVAL, "unknown shadow kind %d", kind);
-    *bytes = shadow_layout(idx->view, nullptr, nullptr, nullptr, nullptr);
+    int64_t R, P;
+    shadow_extent(idx, shadow_rows, &R, &P);
+    *bytes = shadow_layout(idx->view, R, nullptr, nullptr, nullptr, nullptr);
     return HS_OK;
 }
 
-hs_status hs_build_shadow(hs_index* idx, int32_t kind, void* shadow_dev, int64_t shadow_bytes, void* stream) {
+hs_status hs_build_shadow(hs_index* idx, int32_t kind, int64_t shadow_rows, void* shadow_dev, int64_t shadow_bytes,
+                          void* stream) {
     if (!idx || !shadow_dev) return fail(HS_EINVAL, "NULL argument");
     if (kind != kShadowBf16 && kind != kShadowF16) return fail(HS_EINVAL, "unknown shadow kind %d", kind);
-    const int64_t need = shadow_layout(idx->view, nullptr, nullptr, nullptr, nullptr);
+    int64_t R, P;
+    shadow_extent(idx, shadow_rows, &R, &P);
+    const int64_t need = shadow_layout(idx->view, R, nullptr, nullptr, nullptr, nullptr);
     if (shadow_bytes < need)
         return fail(HS_ENOMEM, "shadow_bytes=%lld < required %lld", (long long)shadow_bytes, (long long)need);
     hipStream_t st = (hipStream_t)stream;
     uint16_t* rows;
     float4* norms;
     uint32_t* flag;
-    shadow_layout(idx->view, &rows, &norms, &flag, (char*)shadow_dev);
+    shadow_layout(idx->view, R, &rows, &norms, &flag, (char*)shadow_dev);
     idx->shadow = ShadowView{};
     HIP_TRY(hipMemsetAsync(flag, 0, 4, st));
-    HIP_TRY(hipMemsetAsync(rows + idx->view.N * idx->view.stride, 0, (size_t)kBoundRows * idx->view.stride * 2, st));
-    HIP_TRY(hipMemsetAsync(norms + idx->view.N, 0, (size_t)kBoundRows * 16, st));
-    HIP_TRY(launch_shadow(idx->view, kind, rows, norms, flag, st));
+    HIP_TRY(hipMemsetAsync(rows + R * idx->view.stride, 0, (size_t)kBoundRows * idx->view.stride * 2, st));
+    HIP_TRY(hipMemsetAsync(norms + R, 0, (size_t)kBoundRows * 16, st));
+    HIP_TRY(launch_shadow(idx->view, kind, R, rows, norms, flag, st));
     uint32_t bad = 0;
     HIP_TRY(hipMemcpyAsync(&bad, flag, 4, hipMemcpyDeviceToHost, st));
     HIP_TRY(hipStreamSynchronize(st));
@@ -788,6 +831,8 @@ hs_status hs_build_shadow(hs_index* idx, int32_t kind, void* shadow_dev, int64_t
     idx->shadow.rows = rows;
     idx->shadow.norms = norms;
     idx->shadow.kind = kind;
+    idx->shadow.rows_n = R;
+    idx->shadow.parts_n = P;
     return HS_OK;
 }
 

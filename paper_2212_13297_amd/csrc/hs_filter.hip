@@ -163,7 +163,7 @@ __global__ void __launch_bounds__(256, 4) k_filter(IndexView ix, ScanParams sp, 
     const uint32_t pass_eoff = (uint32_t)(kWaves * cpp * ix.w * 16);
     uint2* queue = s_queue[wave];
 
-    const int64_t slice = (int64_t)blockIdx.x * kWaves + wave;
+    const int64_t slice = (int64_t)sp.slice0 + (int64_t)blockIdx.x * kWaves + wave;
     FilterOut o{ws.slice_pos + slice * ws.slice_cap, ws.slice_q + slice * ws.slice_cap,
                 ws.slice_part + slice * ws.slice_cap, 0u, 0ull, 0ull, 0ull, false};
     // Items are dealt out in units of up to kUnit (fewer for a short item
@@ -347,7 +347,7 @@ int filter_waves(const IndexView& ix, int device_cus) {
 
 hipError_t launch_filter(const IndexView& ix, const ScanParams& sp, const QueryWs& ws, int device_cus,
                          hipStream_t st) {
-    const dim3 grid(ws.n_slices / kWaves);  // one slice per wavefront
+    const dim3 grid(sp.slices / kWaves);  // one slice per wavefront
     if (ws.ubits) {
         switch (w16_of(ix)) {
             case 1: k_filter<1, true><<<grid, dim3(kTile), 0, st>>>(ix, sp, ws); break;

@@ -26,6 +26,7 @@ struct hs_index {
     int64_t* chunk_start_dev = nullptr;
     float4* cenv_dev = nullptr;
     int filter_waves = 4;               // wavefronts of the filter kernel (candidate slices)
+    std::vector<int64_t> part_start_host;  // [parts + 1] (host copy, for partial low-precision copies)
     hs::ShadowView shadow{};            // low-precision copy (caller-owned memory), kind 0 = none
 };
 

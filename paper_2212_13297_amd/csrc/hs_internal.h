@@ -61,11 +61,13 @@ constexpr int kBoundQueries = 128;  // queries per workgroup of the bounding pas
 constexpr int kBoundRows = 32;      // series per tile of the bounding pass
 
 struct ShadowView {
-    const uint16_t* rows;  // [N + kBoundRows][stride] bf16 / fp16 bits of the stored series, zero padded
+    const uint16_t* rows;  // [rows_n + kBoundRows][stride] bf16 / fp16 bits of the first rows_n stored series, zero padded
     const float4* norms;   // [N + kBoundRows] (beta, ||x - x~||_2 rounded up, ||x~||^2 rounded down, aug), float32;
                            // beta = ((1 - g) ||x~||^2 - eps^2) / 2 - 3u (||x~||^2 + eps^2), float64, rounded down;
                            // aug: bits of the augmented unit (a*, ebar) as two low-precision values
     int32_t kind;          // kShadowBf16 / kShadowF16
+    int64_t rows_n;        // stored series the copy holds: all N, or the first parts_n parts
+    int64_t parts_n;       // parts wholly in the copy (the rest take the LB_SAX filter)
 };
 
 // Everything a kernel needs to know about an index.
@@ -120,7 +122,8 @@ struct QueryWs {
     int64_t item_cap;
     int64_t slice_cap;    // entries per slice
     int64_t ovf_cap;      // entries of the shared overflow slice (slice index n_slices)
-    int32_t n_slices;
+    int32_t n_slices;     // all slices; with a partial low-precision copy the
+                          // bounding pass writes the upper half, the filter the lower
     int32_t P;
     // batch-union diagnostics (NULL when off): one bit per distinct unit read,
     // raw (series, 64-point chunk) pairs at bit pos * nchunks + c, then
@@ -140,6 +143,9 @@ struct ScanParams {
     // chunks per quarter of the series (stride = n = 256 2^order_lg, w a
     // multiple of 16)
     int32_t order_lg;
+    int64_t emit_part0;   // first part k_emit makes items for (a partial copy's uncovered parts)
+    int32_t slice0;       // first slice of the kernel that runs (filter or bounding pass)
+    int32_t slices;       // slices it owns
     // abandoning margin: a running distance (any chunk order, either form,
     // plus the cascade's bounds of unread quarters) above fl(limit * marg)
     // proves the pair's result key, its compensated natural-order distance,
@@ -188,8 +194,8 @@ hipError_t launch_merge(const IndexView& ix, const ScanParams& sp, bool redo_onl
                         hipStream_t st);
 
 // precision form (hs_precision.hip)
-hipError_t launch_shadow(const IndexView& ix, int kind, uint16_t* rows, float4* norms, uint32_t* bad_flag,
-                         hipStream_t st);
+hipError_t launch_shadow(const IndexView& ix, int kind, int64_t nrows, uint16_t* rows, float4* norms,
+                         uint32_t* bad_flag, hipStream_t st);
 hipError_t launch_query_low(const IndexView& ix, int kind, int32_t Q, const QueryWs& ws, hipStream_t st);
 // order the queries by their best leaf (queries of one wavefront then keep
 // similar leaves, so the bounding pass skips more)

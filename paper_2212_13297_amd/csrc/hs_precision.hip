@@ -115,12 +115,13 @@ __device__ __forceinline__ float beta_of(float xn, float eps, const BoundConsts&
 // One wavefront per series: the low-precision copy and, in float64,
 // ||x~||^2 (stored rounded down), ||x - x~||_2 (stored rounded up) and beta_x.
 template <int KIND>
-__global__ void __launch_bounds__(256) k_shadow(IndexView ix, uint16_t* __restrict__ out, float4* __restrict__ norms,
-                                                uint32_t* __restrict__ bad, BoundConsts bc) {
+__global__ void __launch_bounds__(256) k_shadow(IndexView ix, int64_t nrows, uint16_t* __restrict__ out,
+                                                float4* __restrict__ norms, uint32_t* __restrict__ bad,
+                                                BoundConsts bc) {
     const int lane = threadIdx.x & 63;
     const int64_t w0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
     const int64_t nw = ((int64_t)gridDim.x * blockDim.x) >> 6;
-    for (int64_t r = w0; r < ix.N; r += nw) {
+    for (int64_t r = w0; r < nrows; r += nw) {
         const float* xr = ix.rows + r * ix.stride;
         uint16_t* orow = out + r * ix.stride;
         double s2 = 0.0, e2 = 0.0;
@@ -149,6 +150,10 @@ __global__ void __launch_bounds__(256) k_shadow(IndexView ix, uint16_t* __restri
             norms[r] = make_float4(beta_of(xn, eps, bc), eps, xn, __uint_as_float(augmented_unit<KIND>(xn, eps, bc)));
         }
     }
+}
+
+__global__ void k_empty_slices(QueryWs ws, int32_t slice0, int32_t slices) {
+    for (int e = threadIdx.x; e < slices; e += blockDim.x) ws.slice_cnt[slice0 + e] = 0;
 }
 
 // One wavefront per (padded) query: q~, ||q~||^2 and ||q - q~||_2 in float64.
@@ -296,15 +301,15 @@ __global__ void __launch_bounds__(256) k_bound(IndexView ix, ShadowView sv, Scan
     const int K = ix.stride, nkb = ONE ? 1 : (K + kKBlock - 1) / kKBlock;
     const uint64_t lt_mask = (1ull << lane) - 1ull;
 
-    const int64_t slice = (int64_t)blockIdx.x * (kTile / 64) + wave;
+    const int64_t slice = (int64_t)sp.slice0 + (int64_t)blockIdx.x * (kTile / 64) + wave;
     uint32_t* spos = ws.slice_pos + slice * ws.slice_cap;
     uint32_t* sq = ws.slice_q + slice * ws.slice_cap;
     uint32_t* spart = ws.slice_part + slice * ws.slice_cap;
     uint32_t cnt = 0;  // entries in this wavefront's slice (uniform)
     // slices of wavefronts beyond this grid stay empty
-    for (int64_t e = (int64_t)gridDim.x * (kTile / 64) + (int64_t)blockIdx.x * kTile + t; e < ws.n_slices;
+    for (int64_t e = (int64_t)gridDim.x * (kTile / 64) + (int64_t)blockIdx.x * kTile + t; e < sp.slices;
          e += (int64_t)gridDim.x * kTile)
-        ws.slice_cnt[e] = 0;
+        ws.slice_cnt[sp.slice0 + e] = 0;
 
     // Work items (q-group g, row range r).  XCD-aware: the workgroups of XCD x
     // (b mod 8) take items i = u G + g, r = 8 u + x, from the XCD's counter, so
@@ -330,7 +335,8 @@ __global__ void __launch_bounds__(256) k_bound(IndexView ix, ShadowView sv, Scan
             if (g >= bm.G) break;
             ++wi;
         }
-        const int64_t row0 = ix.N * r / bm.R, row1 = ix.N * (r + 1) / bm.R;
+        // the copy holds the first sv.rows_n stored series (whole parts)
+        const int64_t row0 = sv.rows_n * r / bm.R, row1 = sv.rows_n * (r + 1) / bm.R;
         // first part that ends after row0
         int64_t lo = 0, hi = ix.parts;
         while (lo < hi) {
@@ -611,14 +617,15 @@ __global__ void __launch_bounds__(256) k_bound(IndexView ix, ShadowView sv, Scan
 
 }  // namespace
 
-hipError_t launch_shadow(const IndexView& ix, int kind, uint16_t* rows, float4* norms, uint32_t* bad_flag,
-                         hipStream_t st) {
-    const int grid = grid_for(ix.N * 64, 256, 1 << 16);
+hipError_t launch_shadow(const IndexView& ix, int kind, int64_t nrows, uint16_t* rows, float4* norms,
+                         uint32_t* bad_flag, hipStream_t st) {
+    if (nrows <= 0) return hipSuccess;
+    const int grid = grid_for(nrows * 64, 256, 1 << 16);
     const BoundConsts bc = bound_consts(ix.stride);
     if (kind == kShadowF16)
-        k_shadow<kShadowF16><<<dim3(grid), dim3(256), 0, st>>>(ix, rows, norms, bad_flag, bc);
+        k_shadow<kShadowF16><<<dim3(grid), dim3(256), 0, st>>>(ix, nrows, rows, norms, bad_flag, bc);
     else
-        k_shadow<kShadowBf16><<<dim3(grid), dim3(256), 0, st>>>(ix, rows, norms, bad_flag, bc);
+        k_shadow<kShadowBf16><<<dim3(grid), dim3(256), 0, st>>>(ix, nrows, rows, norms, bad_flag, bc);
     return hipGetLastError();
 }
 
@@ -638,7 +645,12 @@ hipError_t launch_query_order(int32_t Q, const QueryWs& ws, hipStream_t st) {
 hipError_t launch_bound(const IndexView& ix, const ShadowView& sv, const ScanParams& sp, const QueryWs& ws,
                         int device_cus, hipStream_t st) {
     // one candidate slice per wavefront; no more workgroups than are resident
-    int grid = ws.n_slices / (kTile / 64);
+    int grid = sp.slices / (kTile / 64);
+    if (sv.rows_n <= 0) {
+        // nothing to bound: the pass only marks its slices empty
+        hipLaunchKernelGGL(k_empty_slices, dim3(1), dim3(256), 0, st, ws, sp.slice0, sp.slices);
+        return hipGetLastError();
+    }
     const bool one = ix.stride <= kKBlock;
     int resident;
     if (sv.kind == kShadowF16)
@@ -654,7 +666,7 @@ hipError_t launch_bound(const IndexView& ix, const ShadowView& sv, const ScanPar
         // about 8 items per workgroup, dealt out per XCD
         bm.xcd_aware = 1;
         bm.GS = bm.G;
-        bm.R = 8 * std::max(1, (int)std::min<int64_t>(8 * (grid / (8 * bm.G)), ix.N / (8 * 64)));
+        bm.R = 8 * std::max(1, (int)std::min<int64_t>(8 * (grid / (8 * bm.G)), sv.rows_n / (8 * 64)));
         bm.nper = (bm.R / 8) * bm.G;
     } else {
         bm.xcd_aware = 0;

@@ -300,15 +300,17 @@ __global__ void __launch_bounds__(256) k_emit(IndexView ix, ScanParams sp, int32
                 ws.flags[q] = f | kFlagSkipSax;
         }
     }
+    // parts from emit_part0 on (a partial low-precision copy bounds the others)
+    const int64_t p0 = redo_only ? 0 : sp.emit_part0;
     int cnt = 0;
-    for (int64_t p = t; p < ix.parts; p += blockDim.x) cnt += (double)lbe[ix.part_leaf[p]] <= thr;
+    for (int64_t p = p0 + t; p < ix.parts; p += blockDim.x) cnt += (double)lbe[ix.part_leaf[p]] <= thr;
     int total;
     block_exclusive_scan(cnt, s_w, &total);
     if (t == 0) s_base = total ? atomicAdd(&ws.counters[kCtrItems], (uint32_t)total) : 0u;
     __syncthreads();
     uint32_t base = s_base;
-    for (int64_t p0 = 0; p0 < ix.parts; p0 += blockDim.x) {
-        const int64_t p = p0 + t;
+    for (int64_t pb = p0; pb < ix.parts; pb += blockDim.x) {
+        const int64_t p = pb + t;
         const bool c = p < ix.parts && (double)lbe[ix.part_leaf[p]] <= thr;
         int tot;
         const int off = block_exclusive_scan(c ? 1 : 0, s_w, &tot);

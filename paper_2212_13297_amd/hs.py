@@ -80,8 +80,8 @@ _SIGS = {
     "hs_knn_exact": (ctypes.c_int32, [_P, _P, ctypes.c_int32, ctypes.c_int32, _P, ctypes.c_int64, _P, _P, _P, _P,
                                       _P]),
     "hs_knn_exact_noalloc": (ctypes.c_int32, [_P, _P, ctypes.c_int32, ctypes.c_int32, _P, _P, _P, _P, _P]),
-    "hs_shadow_bytes": (ctypes.c_int32, [_P, ctypes.c_int32, ctypes.POINTER(ctypes.c_int64)]),
-    "hs_build_shadow": (ctypes.c_int32, [_P, ctypes.c_int32, _P, ctypes.c_int64, _P]),
+    "hs_shadow_bytes": (ctypes.c_int32, [_P, ctypes.c_int32, ctypes.c_int64, ctypes.POINTER(ctypes.c_int64)]),
+    "hs_build_shadow": (ctypes.c_int32, [_P, ctypes.c_int32, ctypes.c_int64, _P, ctypes.c_int64, _P]),
     "hs_knn_mixed": (ctypes.c_int32, [_P, _P, ctypes.c_int32, ctypes.c_int32, _P, ctypes.c_int64, _P, _P, _P, _P,
                                       _P]),
     "hs_server_create": (ctypes.c_int32, [_P, _P, ctypes.c_int32, _P, ctypes.c_int64,
@@ -194,14 +194,14 @@ def hs_knn_exact_noalloc(h, q_ptr: int, Q: int, k: int, ids_ptr: int, d2_ptr: in
     _check(load().hs_knn_exact_noalloc(h, q_ptr, Q, k, ids_ptr, d2_ptr, err_ptr, stats_ptr, stream))
 
 
-def hs_shadow_bytes(h, kind: int) -> int:
+def hs_shadow_bytes(h, kind: int, shadow_rows: int = -1) -> int:
     out = ctypes.c_int64()
-    _check(load().hs_shadow_bytes(h, kind, ctypes.byref(out)))
+    _check(load().hs_shadow_bytes(h, kind, shadow_rows, ctypes.byref(out)))
     return out.value
 
 
-def hs_build_shadow(h, kind: int, mem_ptr: int, mem_bytes: int, stream: int) -> None:
-    _check(load().hs_build_shadow(h, kind, mem_ptr, mem_bytes, stream))
+def hs_build_shadow(h, kind: int, shadow_rows: int, mem_ptr: int, mem_bytes: int, stream: int) -> None:
+    _check(load().hs_build_shadow(h, kind, shadow_rows, mem_ptr, mem_bytes, stream))
 
 
 def hs_knn_mixed(h, q_ptr: int, Q: int, k: int, ws_ptr: int, ws_bytes: int, ids_ptr: int, d2_ptr: int,
@@ -428,13 +428,17 @@ class Index:
         self.shadow = None
         self.shadow_kind = 0
 
-    def build_shadow(self, kind: int = HS_SHADOW_BF16, stream=None):
-        """Build the low-precision copy that the precision form (knn_mixed) reads."""
+    def build_shadow(self, kind: int = HS_SHADOW_BF16, stream=None, shadow_rows: int = -1):
+        """Build the low-precision copy that the precision form (knn_mixed) reads:
+        of every stored series, or (shadow_rows >= 0) of the whole parts that fit
+        in the first shadow_rows stored series."""
         import torch
-        nbytes = hs_shadow_bytes(self.h, kind)
+        nbytes = hs_shadow_bytes(self.h, kind, shadow_rows)
+        self.shadow = None
         mem = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
-        hs_build_shadow(self.h, kind, mem.data_ptr(), nbytes, _stream_ptr(stream))
+        hs_build_shadow(self.h, kind, shadow_rows, mem.data_ptr(), nbytes, _stream_ptr(stream))
         self.shadow, self.shadow_kind = mem, kind
+        self._ws = None  # a partial copy changes the workspace layout
 
     def layout(self):
         """Views of the stored arrays inside the index memory (rows, ids, words)

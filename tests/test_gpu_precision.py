@@ -139,6 +139,32 @@ def test_mixed_parity(N, n, w, k, leaf, lmax, per, kind):
     assert np.array_equal(pd2.view(np.uint32), d2.view(np.uint32))
 
 
+@pytest.mark.parametrize("N,n,w,k,kind,fracs", [(30000, 256, 16, 10, P.BF16, (0.0, 0.3, 0.97)),
+                                                 (12000, 1024, 32, 100, P.FP16, (0.6,))])
+def test_mixed_partial_copy(N, n, w, k, kind, fracs):
+    # A low-precision copy of only the first whole parts (shadow_rows): the
+    # matrix-core bound covers those series, LB_SAX the rest, one candidate
+    # list, the compensated refine; ids and distances equal the plain path's
+    # and the oracle's.  From no series at all to nearly all of them.
+    hs = hs_mod()
+    x, q = workload(N, n, coll=90 + n, per_level=3, ood=3)
+    idx = make_index(x, 0, w=w, leaf_size=700, l_max=2)
+    pids, pd2 = knn_plain(idx, q, k)
+    oids, od = check_knn(x, q, k, pids, pd2)
+    for f in fracs:
+        rows = int(f * N)
+        idx.build_shadow(kind, shadow_rows=rows)
+        covered = hs.hs_shadow_bytes(idx.h, kind, rows)
+        print(f"[partial] shadow_rows {rows}: {covered} bytes", flush=True)
+        ids, d2, err, st = knn_mixed(idx, q, k, stats=True)
+        assert np.array_equal(ids, pids)
+        assert np.array_equal(d2.view(np.uint32), pd2.view(np.uint32))
+        check_knn(x, q, k, ids, d2, oids, od)
+        check_err(x, q, ids, d2, err)
+        assert np.all(st["rows_filtered"] > 0)
+    idx.close()
+
+
 def test_mixed_many_query_groups():
     # Q = 300: three q-groups of 128, the last one partial
     x = G.random_walks(15000, 256, coll=61)
