@@ -89,12 +89,14 @@ MFMA_PEAK_TFLOPS = {"bf16": 2500.0, "fp16": 2500.0}
 LDS_PEAK_TLOOKUPS = 256 * 32 * 2.4e9 / 1e12
 
 
-def run_mixed(hs, torch, idx, qt, k, steps, warmup, wl, plain_ids, plain_d2):
-    """Precision form on the same index and batch: bf16 copy of the series,
-    matrix-core bounding pass, compensated float32 refinement."""
+def run_mixed(hs, torch, idx, qt, k, steps, warmup, wl, plain_ids, plain_d2, build=True):
+    """Precision form on the same index and batch: bf16 copy of the series
+    (unless the caller built a copy already), matrix-core bounding pass,
+    compensated float32 refinement."""
     Q = qt.shape[0]
     t0 = time.time()
-    idx.build_shadow(hs.HS_SHADOW_BF16)
+    if build:
+        idx.build_shadow(hs.HS_SHADOW_BF16)
     torch.cuda.synchronize()
     shadow_s = time.time() - t0
     for _ in range(warmup):
@@ -141,14 +143,16 @@ def run_mixed(hs, torch, idx, qt, k, steps, warmup, wl, plain_ids, plain_d2):
         kern["refine"] = {"avg_launch_ms": round(avg, 4), "launches_per_step": rl / steps,
                           "bytes_per_launch": int(nbytes), "GB_s": round(nbytes / (avg / 1e3) / 1e9, 2)}
     traffic = measured_traffic("k_bound", wl)
-    out = {"value": round(qps, 2), "unit": "queries/s", "ms_per_step": round(ms, 4), "dtype": "bf16 bound, f32 refine",
+    low = "fp16" if idx.shadow_kind == hs.HS_SHADOW_FP16 else "bf16"
+    out = {"value": round(qps, 2), "unit": "queries/s", "ms_per_step": round(ms, 4),
+           "dtype": f"{low} bound, f32 compensated refine",
            "identical_id_lists_vs_plain": same, "identical_distances_vs_plain": same_d, "queries": Q,
            "max_err_bound_rel": float((err / d2.double()).max().item()),
            "shadow_build_s": round(shadow_s, 2),
            "kernels": kern,
-           "roofline": ({"bound": "mfma", "achieved": kern["bound"]["TFLOP_s"], "peak": MFMA_PEAK_TFLOPS["bf16"],
-                         "unit": "TFLOP/s", "frac": round(kern["bound"]["TFLOP_s"] / MFMA_PEAK_TFLOPS["bf16"], 4),
-                         "executed_frac": round(kern["bound"]["executed_TFLOP_s"] / MFMA_PEAK_TFLOPS["bf16"], 4),
+           "roofline": ({"bound": "mfma", "achieved": kern["bound"]["TFLOP_s"], "peak": MFMA_PEAK_TFLOPS[low],
+                         "unit": "TFLOP/s", "frac": round(kern["bound"]["TFLOP_s"] / MFMA_PEAK_TFLOPS[low], 4),
+                         "executed_frac": round(kern["bound"]["executed_TFLOP_s"] / MFMA_PEAK_TFLOPS[low], 4),
                          "kernel": "k_bound", "traffic": traffic.get("bytes_per_launch") if traffic else None,
                          "traffic_detail": traffic} if "bound" in kern else None),
            "pruning": {"rows_bounded_mean": float(stats["rows_filtered"].mean()),
@@ -488,6 +492,127 @@ def run_large(args, hs, torch, G, dev):
     return out
 
 
+def run_hard(args, hs, torch, G, dev):
+    """The hard-large configuration: 50M random walks of length 1024 (204.8 GB
+    float32, generated on the GPU chunk by chunk and built by the streaming
+    build, so they are never in device memory twice), w = 32, k = 100, 500
+    queries at 10 % noise plus 100 out-of-dataset queries; the plain form, the
+    precision form with an fp16 copy of as many series as fit beside them, and
+    the serving form over that precision-form collection; the oracle on 50
+    sampled queries, its data streamed back chunk by chunk."""
+    N, n, w, k = args.hard_N, 1024, 32, 100
+    coll = 4
+    CH = G.DEV_CHUNK
+    src = np.sort(G.query_sources(N, args.hard_queries, coll=coll))
+    src_rows = {}
+
+    def chunk(r0):
+        rows = min(CH, N - r0)
+        x = G.walk_chunk_device(r0 // CH, rows, n, coll=coll, device=dev)
+        lo, hi = np.searchsorted(src, [r0, r0 + rows])
+        if hi > lo and r0 not in src_rows:
+            src_rows[r0] = (src[lo:hi], x[torch.as_tensor(src[lo:hi] - r0, device=dev)].cpu().numpy())
+        return x
+
+    log(f"hard: streaming build of {N} x {n} (generated on the device)")
+    t0 = time.time()
+    params = hs.Params(w=w, leaf_size=args.leaf, l_max=args.l_max, seed_rows=args.seed_rows,
+                       cand_per_query=args.hard_cand_per_query)
+    idx = hs.Index.from_chunks(chunk, N, n, params, device=dev)
+    torch.cuda.synchronize()
+    build_s = time.time() - t0
+    log(f"hard: built in {build_s:.1f}s, {idx.info.n_leaves} leaves, index {idx.info.index_bytes / 1e9:.1f} GB")
+    rows_src = np.concatenate([v[1] for _, v in sorted(src_rows.items())])
+    ids_src = np.concatenate([v[0] for _, v in sorted(src_rows.items())])
+    assert np.array_equal(ids_src, src)
+    q = np.concatenate([G.noisy_queries(rows_src, 10.0, coll=coll), G.ood_queries(args.hard_ood, n, coll=coll)])
+    Q = q.shape[0]
+    qt = torch.from_numpy(q).to(dev)
+    wl = {"N": N, "n": n, "Q": Q, "k": k}
+    read_gbs = hs.read_probe_gbs(idx.mem[:idx.info.n_series * idx.info.row_stride * 4], passes=1)
+    res = measure_plain(hs, torch, idx, qt, k, args.hard_steps, 1, w, wl, read_gbs)
+    ids_plain, d2_plain = res["ids"], res["d2"]
+    # the fp16 copy: as many series as fit beside the index, the workspace and
+    # the server's budget
+    ws_bytes = hs.hs_query_workspace_bytes(idx.h, Q, k)
+    budget = int(args.hard_serve_budget_gb * (1 << 30))
+    idx._ws = None
+    torch.cuda.empty_cache()
+    free = torch.cuda.mem_get_info(dev)[0]
+    spare = free - 2 * ws_bytes - budget - (4 << 30)
+    shadow_rows = int(max(0, min(N, spare // (2 * idx.info.row_stride + 16))))
+    log(f"hard: fp16 copy of {shadow_rows} of {N} series ({shadow_rows / N:.1%})")
+    t0 = time.time()
+    idx.build_shadow(hs.HS_SHADOW_FP16, shadow_rows=shadow_rows)
+    torch.cuda.synchronize()
+    shadow_s = time.time() - t0
+    mixed = run_mixed(hs, torch, idx, qt, k, args.hard_steps, 1, wl, ids_plain, d2_plain, build=False)
+    mixed["shadow_rows"] = shadow_rows
+    mixed["shadow_build_s"] = round(shadow_s, 2)
+    # serving: every query submitted at once to a server over the
+    # precision-form collection; results equal the plain form's
+    srv = hs.Server([idx], [1], budget_bytes=budget, streams_per_coll=2, max_slots=4096, max_batch=128)
+    done = {}
+    t1 = hs.hs_server_now()
+    for i in range(Q):
+        while not srv.submit(0, q[i], k, i):
+            for r in srv.poll():
+                done[r["tag"]] = r
+    while len(done) < Q:
+        for r in srv.poll():
+            done[r["tag"]] = r
+    span = max(r["t_done"] for r in done.values()) - t1
+    lat = np.array([(r["t_done"] - r["t_submit"]) * 1e3 for r in done.values()])
+    ip = ids_plain.cpu().numpy()
+    same_srv = sum(int(done[i]["ids"] == list(ip[i])) for i in range(Q))
+    info = srv.info()
+    srv.close()
+    serving = {"value": round(Q / span, 2), "unit": "queries/s", "mode": "all queries submitted at once",
+               "latency_ms": {"p50": round(float(np.percentile(lat, 50)), 3),
+                              "p99": round(float(np.percentile(lat, 99)), 3), "from": "submission"},
+               "batches": info["batches"], "identical_id_lists_vs_plain": same_srv}
+    log(f"hard: serving {serving}")
+    out = {"workload": f"random-walk {N}x{n} f32 (generated on the device), {args.hard_queries} queries at 10% noise "
+                       f"+ {args.hard_ood} out-of-dataset, k={k}, w={w}, card 256, leaf {args.leaf}, "
+                       f"l_max {args.l_max}",
+           "value": round(res["qps"], 2), "unit": "queries/s", "ms_per_step": round(res["ms_per_step"], 4),
+           "steps": args.hard_steps, "n_leaves": int(idx.info.n_leaves), "build_s": round(build_s, 2),
+           "index_GB": round(idx.info.index_bytes / 1e9, 2),
+           "roofline": res["roofline"], "scan_kernels": res["kern"],
+           "algorithmic_bytes_per_step": res["algorithmic_bytes_per_step"],
+           "pruning": pruning_summary(res["stats"], np.concatenate([np.full(args.hard_queries, 10),
+                                                                     np.full(args.hard_ood, -1)]), [10, -1]),
+           "precision_form": mixed, "serving_form": serving}
+    if args.hard_cpu > 0:
+        sel = np.unique(np.concatenate([np.linspace(0, args.hard_queries - 1, args.hard_cpu - args.hard_cpu // 5),
+                                        args.hard_queries + np.arange(args.hard_cpu // 5)]).round().astype(np.int64))
+        from oracle import brute
+        log(f"hard: CPU oracle on {len(sel)} queries, the collection streamed back chunk by chunk")
+        t0 = time.perf_counter()
+
+        def host_chunks():
+            for c in range((N + CH - 1) // CH):
+                rows = min(CH, N - c * CH)
+                yield G.walk_chunk_device(c, rows, n, coll=coll, device=dev).cpu().numpy()
+
+        oids, od = brute.knn_chunked(host_chunks(), q[sel], k)
+        cpu_s = time.perf_counter() - t0
+        out["cpu_baseline"] = {"value": round(len(sel) / cpu_s, 4), "unit": "queries/s", "cores": brute.threads(),
+                               "kind": "oracle",
+                               "sample": f"{len(sel)} of the {Q} queries, k={k}; FP64 brute force over all {N} "
+                                         f"series; {cpu_s:.1f} s (including regenerating the chunks)"}
+        out["parity_sample"] = {"plain": parity_of(ids_plain, d2_plain, sel, oids, od)}
+        mids = torch.from_numpy(np.array([done[i]["ids"] for i in range(Q)]))
+        md2 = torch.from_numpy(np.array([done[i]["d2"] for i in range(Q)], dtype=np.float32))
+        out["parity_sample"]["serving_precision"] = parity_of(mids, md2, sel, oids, od)
+        log(f"hard: parity {out['parity_sample']}")
+    idx.close()
+    del idx, qt
+    gc.collect()
+    torch.cuda.empty_cache()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -511,6 +636,9 @@ def main():
                          "serving: the continuous-batching server over three collections under Poisson arrivals; "
                          "large: the precision form's own configuration (100M x 256, 1,000 queries at 5 %%, "
                          "k = 10), plain and precision form, after the headline index is freed; "
+                         "hard: the hard-large configuration (50M x 1024 generated on the device, streaming "
+                         "build, 500 queries at 10 %% + 100 ood, k = 100, w = 32; plain, partial fp16 copy, "
+                         "serving); "
                          "ablation: the plain form per noise level with the LB_SAX filter always on (the default), "
                          "skipped (NoSAX) and skipped below the paper's leaf-pruning threshold 0.25")
     ap.add_argument("--large-N", type=int, default=100_000_000)
@@ -520,6 +648,13 @@ def main():
     ap.add_argument("--large-steps", type=int, default=5)
     ap.add_argument("--large-warmup", type=int, default=2)
     ap.add_argument("--large-cpu", type=int, default=50, help="queries of the large workload timed on the oracle")
+    ap.add_argument("--hard-N", type=int, default=50_000_000)
+    ap.add_argument("--hard-queries", type=int, default=500)
+    ap.add_argument("--hard-ood", type=int, default=100)
+    ap.add_argument("--hard-steps", type=int, default=3)
+    ap.add_argument("--hard-cpu", type=int, default=50, help="queries of the hard workload checked on the oracle")
+    ap.add_argument("--hard-cand-per-query", type=int, default=2_000_000)
+    ap.add_argument("--hard-serve-budget-gb", type=float, default=8.0)
     ap.add_argument("--serve-rate", type=float, default=2000.0, help="Poisson arrival rate (queries/s)")
     ap.add_argument("--serve-seconds", type=float, default=30.0, help="measured arrival window (s)")
     ap.add_argument("--serve-warmup", type=float, default=5.0, help="arrivals before the measured window (s)")
@@ -669,6 +804,9 @@ def main():
     large = None
     if "large" in forms and args.large_N > 0:
         large = run_large(args, hs, torch, G, dev)
+    hard = None
+    if "hard" in forms and args.hard_N > 0:
+        hard = run_hard(args, hs, torch, G, dev)
 
     out = {
         "metric": METRIC,
@@ -707,6 +845,7 @@ def main():
         "serving_form": serving,
         "ablation": ablation,
         "large_config": large,
+        "hard_config": hard,
     }
     del ids_cpu
     print(json.dumps(out), flush=True)

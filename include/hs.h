@@ -136,6 +136,36 @@ hs_status hs_build_summaries(const float* x_dev, int64_t N, const hs_params* par
                              void* index_mem_dev, int64_t index_bytes, void* stream,
                              hs_index** out);
 
+/*
+ * Streaming build: the same index as hs_build_summaries, for collections that
+ * do not fit in device memory twice (as input and as the leaf-ordered copy).
+ * The series arrive in row chunks, twice: first for their segment statistics
+ * (the partition's input), then, after hs_build_partition, for their values,
+ * which go straight to their stored positions.  Each pass covers rows
+ * [0, N) in order (chunk i starts where chunk i - 1 ended), with the same
+ * values both times; a chunk's device memory may be reused once the call
+ * returns and the stream has passed it (calls are stream-ordered).
+ *   hs_build_begin      validates like hs_build_summaries (index memory of
+ *                       hs_index_bytes bytes, caller-owned)
+ *   hs_build_add_stats  x_dev: float32 [rows][n], rows row0 .. row0 + rows - 1
+ *   hs_build_partition  after the first pass; synchronises the stream
+ *   hs_build_add_rows   the second pass
+ *   hs_build_finish     words and envelopes; returns the index and frees the
+ *                       builder
+ *   hs_build_abort      frees a builder that will not finish
+ * Errors: HS_EINVAL (NULL, chunks out of order or range, a step out of turn,
+ * NaN/Inf in the series -- reported by hs_build_partition), HS_ENOMEM,
+ * HS_EHIP.  After an error the builder may only be aborted.
+ */
+typedef struct hs_builder hs_builder;
+hs_status hs_build_begin(int64_t N, const hs_params* params, void* index_mem_dev, int64_t index_bytes, void* stream,
+                         hs_builder** out);
+hs_status hs_build_add_stats(hs_builder* b, const float* x_dev, int64_t row0, int64_t rows);
+hs_status hs_build_partition(hs_builder* b);
+hs_status hs_build_add_rows(hs_builder* b, const float* x_dev, int64_t row0, int64_t rows);
+hs_status hs_build_finish(hs_builder* b, hs_index** out);
+hs_status hs_build_abort(hs_builder* b);
+
 /* Properties of a built index (host copy). */
 hs_status hs_get_info(const hs_index* idx, hs_index_info* out);
 

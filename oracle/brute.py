@@ -69,6 +69,34 @@ def knn(x: np.ndarray, q: np.ndarray, k: int, threads: int = 0):
     return ids, d2
 
 
+def knn_chunked(chunks, q: np.ndarray, k: int, threads: int = 0):
+    """Exact k-NN over a collection given as consecutive row chunks (an
+    iterable of float32 [rows, n] arrays, rows numbered from 0 across them):
+    each chunk's own top-k by ``knn``, ids offset by the chunk's first row,
+    merged with the running top-k by (d2, id).  The k nearest of the whole
+    collection are among the union of the chunks' k nearest, so the merge is
+    exact.  Returns (ids int64 [Q, k], d2 float64 [Q, k])."""
+    q = np.ascontiguousarray(q, dtype=np.float32)
+    Q = q.shape[0]
+    best_i = np.empty((Q, 0), dtype=np.int64)
+    best_d = np.empty((Q, 0), dtype=np.float64)
+    base = 0
+    for x in chunks:
+        rows = x.shape[0]
+        kk = min(k, rows)
+        ci, cd = knn(x, q, kk, threads)
+        ids = np.concatenate([best_i, ci + base], axis=1)
+        ds = np.concatenate([best_d, cd], axis=1)
+        keep = min(k, ids.shape[1])
+        order = np.lexsort((ids, ds), axis=1)[:, :keep]   # primary key d2, then id
+        best_i = np.take_along_axis(ids, order, axis=1)
+        best_d = np.take_along_axis(ds, order, axis=1)
+        base += rows
+    if best_i.shape[1] < k:
+        raise ValueError("k exceeds the collection")
+    return best_i, best_d
+
+
 def pair_dist(x: np.ndarray, q: np.ndarray, qidx, rows) -> np.ndarray:
     """FP64 squared distances d(q[qidx[p]], x[rows[p]]) for sampled pairs."""
     x = np.ascontiguousarray(x, dtype=np.float32)

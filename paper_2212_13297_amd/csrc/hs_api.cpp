@@ -353,41 +353,37 @@ hs_status hs_index_bytes(int64_t N, const hs_params* params, int64_t* bytes) {
     return HS_OK;
 }
 
-hs_status hs_build_summaries(const float* x_dev, int64_t N, const hs_params* params, void* index_mem_dev,
-                             int64_t index_bytes, void* stream, hs_index** out) {
+hs_status hs_build_begin(int64_t N, const hs_params* params, void* index_mem_dev, int64_t index_bytes, void* stream,
+                         hs_builder** out) {
     if (!out) return fail(HS_EINVAL, "out is NULL");
     *out = nullptr;
-    if (!x_dev || !index_mem_dev) return fail(HS_EINVAL, "x_dev or index_mem_dev is NULL");
+    if (!index_mem_dev) return fail(HS_EINVAL, "index_mem_dev is NULL");
     int64_t need = 0;
     hs_status s = hs_index_bytes(N, params, &need);
     if (s) return s;
     if (index_bytes < need) return fail(HS_ENOMEM, "index_bytes=%lld < required %lld", (long long)index_bytes, (long long)need);
-    hipStream_t st = (hipStream_t)stream;
     const hs_params p = *params;
-
     int device = 0, cus = 0;
     HIP_TRY(hipGetDevice(&device));
     HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device));
+    hs_builder* b = new (std::nothrow) hs_builder();
     hs_index* idx = new (std::nothrow) hs_index();
-    if (!idx) return fail(HS_ENOMEM, "host allocation failed");
+    if (!b || !idx) {
+        delete b;
+        delete idx;
+        return fail(HS_ENOMEM, "host allocation failed");
+    }
+    b->idx = idx;
+    b->st = (hipStream_t)stream;
     idx->p = p;
     idx->device = device;
     idx->cus = cus;
-    auto bail = [&](hs_status code) {
-        delete idx;
-        return code;
-    };
-#define BUILD_TRY(expr)                                                                 \
-    do {                                                                                \
-        hipError_t e_ = (expr);                                                         \
-        if (e_ != hipSuccess) return bail(fail(HS_EHIP, "%s: %s", #expr, hipGetErrorString(e_))); \
-    } while (0)
-
     // everything lives in the caller's index memory: the stored arrays, the
-    // small tables (sized for at most `budget` leaves) and, until the rows
-    // are gathered, the build's scratch (inside the rows' area when it fits)
+    // small tables (sized for at most lay.leaf_budget leaves) and, until the
+    // rows arrive, the build's scratch (inside the rows' area when it fits)
     char* base = (char*)index_mem_dev;
-    const IndexLayout lay = index_layout(N, p, base);
+    b->lay = index_layout(N, p, base);
+    const IndexLayout& lay = b->lay;
     IndexView& ix = idx->view;
     ix.N = N;
     ix.n = p.n;
@@ -406,20 +402,49 @@ hs_status hs_build_summaries(const float* x_dev, int64_t N, const hs_params* par
     idx->part_chunk_dev = (int64_t*)(base + lay.part_chunk);
     idx->chunk_start_dev = (int64_t*)(base + lay.chunk_start);
     idx->cenv_dev = (float4*)(base + lay.cenv);
-    char* scratch = base + lay.scratch;
-    uint32_t* bad_dev = (uint32_t*)(base + lay.flag);
+    b->scratch = base + lay.scratch;
+    b->bad = (uint32_t*)(base + lay.flag);
+    b->st_dev = partition_stats_buffer(b->scratch, N, p.w, p.leaf_size, lay.leaf_budget);
+    // until the rows arrive, the words' area holds each series' stored position
+    b->pos = (uint32_t*)ix.words;
+    const hipError_t e = hipMemsetAsync(b->bad, 0, sizeof(uint32_t), b->st);
+    if (e != hipSuccess) {
+        delete idx;
+        delete b;
+        return fail(HS_EHIP, "hipMemsetAsync: %s", hipGetErrorString(e));
+    }
+    *out = b;
+    return HS_OK;
+}
 
-    // 1. segment statistics (float32 copies of FP64 mean / std) for the partition
-    float2* st_dev = partition_stats_buffer(scratch, N, p.w, p.leaf_size, lay.leaf_budget);
-    BUILD_TRY(hipMemsetAsync(bad_dev, 0, sizeof(uint32_t), st));
-    BUILD_TRY(launch_series_stats(x_dev, N, p.n, p.w, st_dev, bad_dev, st));
+hs_status hs_build_add_stats(hs_builder* b, const float* x_dev, int64_t row0, int64_t rows) {
+    if (!b || !x_dev) return fail(HS_EINVAL, "NULL argument");
+    if (b->stage != 0) return fail(HS_EINVAL, "statistics come before hs_build_partition");
+    const IndexView& ix = b->idx->view;
+    if (row0 != b->next_row || rows < 1 || row0 + rows > ix.N)
+        return fail(HS_EINVAL, "rows [%lld, %lld): chunks must cover [0, N) in order (next row %lld)", (long long)row0,
+                    (long long)(row0 + rows), (long long)b->next_row);
+    HIP_TRY(launch_series_stats(x_dev, rows, ix.n, ix.w, b->st_dev + row0 * ix.w, b->bad, b->st));
+    b->next_row = row0 + rows;
+    return HS_OK;
+}
+
+hs_status hs_build_partition(hs_builder* b) {
+    if (!b) return fail(HS_EINVAL, "NULL argument");
+    hs_index* idx = b->idx;
+    IndexView& ix = idx->view;
+    const hs_params& p = idx->p;
+    const IndexLayout& lay = b->lay;
+    const int64_t N = ix.N;
+    hipStream_t st = b->st;
+    if (b->stage != 0 || b->next_row != N) return fail(HS_EINVAL, "the statistics of all N rows come first");
     uint32_t bad = 0;
-    BUILD_TRY(hipMemcpyAsync(&bad, bad_dev, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
-    BUILD_TRY(hipStreamSynchronize(st));
-    if (bad) return bail(fail(HS_EINVAL, "x contains NaN or Inf"));
+    HIP_TRY(hipMemcpyAsync(&bad, b->bad, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    if (bad) return fail(HS_EINVAL, "x contains NaN or Inf");
 
-    // 2. leaf partition: on the device, or on the host (the reference the
-    //    device partition is tested against)
+    // leaf partition: on the device, or on the host (the reference the
+    // device partition is tested against)
     std::vector<int64_t> leaf_start;
     if (p.build_flags & HS_BUILD_HOST_PARTITION) {
         Partition part;
@@ -433,10 +458,10 @@ hs_status hs_build_summaries(const float* x_dev, int64_t N, const hs_params* par
             part.tmp_st.resize((size_t)N * p.w);
             part.tmp_id.resize((size_t)N);
         } catch (...) {
-            return bail(fail(HS_ENOMEM, "host allocation for the leaf partition failed"));
+            return fail(HS_ENOMEM, "host allocation for the leaf partition failed");
         }
-        BUILD_TRY(hipMemcpyAsync(st_host.data(), st_dev, sizeof(float2) * N * p.w, hipMemcpyDeviceToHost, st));
-        BUILD_TRY(hipStreamSynchronize(st));
+        HIP_TRY(hipMemcpyAsync(st_host.data(), b->st_dev, sizeof(float2) * N * p.w, hipMemcpyDeviceToHost, st));
+        HIP_TRY(hipStreamSynchronize(st));
         for (int64_t i = 0; i < N; ++i) id_host[i] = (uint32_t)i;
         part.st = st_host.data();
         part.id = id_host.data();
@@ -444,13 +469,14 @@ hs_status hs_build_summaries(const float* x_dev, int64_t N, const hs_params* par
         std::sort(part.leaves.begin(), part.leaves.end());
         for (auto& lf : part.leaves) leaf_start.push_back(lf.first);
         if ((int64_t)leaf_start.size() > lay.leaf_budget)
-            return bail(fail(HS_ENOMEM, "the host partition made %lld leaves; the index memory holds tables for %lld",
-                             (long long)leaf_start.size(), (long long)lay.leaf_budget));
-        BUILD_TRY(hipMemcpyAsync((void*)ix.ids, id_host.data(), sizeof(uint32_t) * N, hipMemcpyHostToDevice, st));
-        BUILD_TRY(hipStreamSynchronize(st));
+            return fail(HS_ENOMEM, "the host partition made %lld leaves; the index memory holds tables for %lld",
+                        (long long)leaf_start.size(), (long long)lay.leaf_budget);
+        HIP_TRY(hipMemcpyAsync((void*)ix.ids, id_host.data(), sizeof(uint32_t) * N, hipMemcpyHostToDevice, st));
+        HIP_TRY(hipStreamSynchronize(st));
     } else {
-        s = partition_device(N, p.w, p.leaf_size, lay.leaf_budget, scratch, cus, (uint32_t*)ix.ids, &leaf_start, st);
-        if (s) return bail(s);
+        hs_status s = partition_device(N, p.w, p.leaf_size, lay.leaf_budget, b->scratch, idx->cus, (uint32_t*)ix.ids,
+                                       &leaf_start, st);
+        if (s) return s;
     }
     const int64_t L = (int64_t)leaf_start.size();
     leaf_start.push_back(N);
@@ -478,29 +504,25 @@ hs_status hs_build_summaries(const float* x_dev, int64_t N, const hs_params* par
     const int64_t chunks = (int64_t)chunk_start.size();
     part_start.push_back(N);
     chunk_start.push_back(N);
-    idx->part_start_host = part_start;
     if (chunks > lay.chunk_cap || parts > lay.chunk_cap)
-        return bail(fail(HS_EHIP, "table sizes exceed their reservation (%lld chunks)", (long long)chunks));
+        return fail(HS_EHIP, "table sizes exceed their reservation (%lld chunks)", (long long)chunks);
+    idx->part_start_host = part_start;
     ix.parts = parts;
     ix.chunks = chunks;
     idx->filter_waves = filter_waves(ix, idx->cus);
 
-    // 3. tables, leaf-ordered copy, words, envelopes
     float beta_host[kCard + 1];
     beta_host[0] = -INFINITY;
     compute_breakpoints(beta_host + 1);
     beta_host[kCard] = INFINITY;
-    BUILD_TRY(hipMemcpyAsync(idx->part_chunk_dev, part_chunk.data(), sizeof(int64_t) * parts,
-                             hipMemcpyHostToDevice, st));
-    BUILD_TRY(hipMemcpyAsync(idx->chunk_start_dev, chunk_start.data(), sizeof(int64_t) * (chunks + 1),
-                             hipMemcpyHostToDevice, st));
-    BUILD_TRY(hipMemcpyAsync(idx->leaf_start_dev, leaf_start.data(), sizeof(int64_t) * (L + 1),
-                             hipMemcpyHostToDevice, st));
-    BUILD_TRY(hipMemcpyAsync(idx->part_start_dev, part_start.data(), sizeof(int64_t) * (parts + 1),
-                             hipMemcpyHostToDevice, st));
-    BUILD_TRY(hipMemcpyAsync(idx->part_leaf_dev, part_leaf.data(), sizeof(uint32_t) * parts,
-                             hipMemcpyHostToDevice, st));
-    BUILD_TRY(hipMemcpyAsync(idx->beta_dev, beta_host, sizeof(beta_host), hipMemcpyHostToDevice, st));
+    HIP_TRY(hipMemcpyAsync(idx->part_chunk_dev, part_chunk.data(), sizeof(int64_t) * parts, hipMemcpyHostToDevice, st));
+    HIP_TRY(hipMemcpyAsync(idx->chunk_start_dev, chunk_start.data(), sizeof(int64_t) * (chunks + 1),
+                           hipMemcpyHostToDevice, st));
+    HIP_TRY(hipMemcpyAsync(idx->leaf_start_dev, leaf_start.data(), sizeof(int64_t) * (L + 1), hipMemcpyHostToDevice, st));
+    HIP_TRY(hipMemcpyAsync(idx->part_start_dev, part_start.data(), sizeof(int64_t) * (parts + 1),
+                           hipMemcpyHostToDevice, st));
+    HIP_TRY(hipMemcpyAsync(idx->part_leaf_dev, part_leaf.data(), sizeof(uint32_t) * parts, hipMemcpyHostToDevice, st));
+    HIP_TRY(hipMemcpyAsync(idx->beta_dev, beta_host, sizeof(beta_host), hipMemcpyHostToDevice, st));
     ix.leaf_start = idx->leaf_start_dev;
     ix.env = idx->env_dev;
     ix.beta = idx->beta_dev;
@@ -508,15 +530,70 @@ hs_status hs_build_summaries(const float* x_dev, int64_t N, const hs_params* par
     ix.part_leaf = idx->part_leaf_dev;
     ix.part_chunk = idx->part_chunk_dev;
     ix.cenv = idx->cenv_dev;
-    // the gather overwrites the scratch inside the rows' area: the partition is done
-    BUILD_TRY(launch_gather_rows(x_dev, ix.ids, N, p.n, ix.stride, (float*)ix.rows, st));
-    BUILD_TRY(launch_words(ix, (uint8_t*)ix.words, st));
-    BUILD_TRY(launch_envelopes(ix, idx->leaf_start_dev, L, idx->env_dev, st));
-    BUILD_TRY(launch_envelopes(ix, idx->chunk_start_dev, chunks, idx->cenv_dev, st));
-    BUILD_TRY(hipStreamSynchronize(st));
-#undef BUILD_TRY
-    *out = idx;
+    // each series' stored position, for the rows of the second pass (the
+    // partition's scratch in the rows' area is no longer needed)
+    HIP_TRY(launch_inverse_ids(ix.ids, N, b->pos, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    b->stage = 1;
+    b->next_row = 0;
     return HS_OK;
+}
+
+hs_status hs_build_add_rows(hs_builder* b, const float* x_dev, int64_t row0, int64_t rows) {
+    if (!b || !x_dev) return fail(HS_EINVAL, "NULL argument");
+    if (b->stage != 1) return fail(HS_EINVAL, "rows come after hs_build_partition");
+    const IndexView& ix = b->idx->view;
+    if (row0 != b->next_row || rows < 1 || row0 + rows > ix.N)
+        return fail(HS_EINVAL, "rows [%lld, %lld): chunks must cover [0, N) in order (next row %lld)", (long long)row0,
+                    (long long)(row0 + rows), (long long)b->next_row);
+    HIP_TRY(launch_scatter_rows(x_dev, row0, rows, b->pos, ix.n, ix.stride, (float*)ix.rows, b->st));
+    b->next_row = row0 + rows;
+    return HS_OK;
+}
+
+hs_status hs_build_finish(hs_builder* b, hs_index** out) {
+    if (!b || !out) return fail(HS_EINVAL, "NULL argument");
+    *out = nullptr;
+    hs_index* idx = b->idx;
+    const IndexView& ix = idx->view;
+    if (b->stage != 1 || b->next_row != ix.N) return fail(HS_EINVAL, "the rows of all N series come first");
+    hipStream_t st = b->st;
+    HIP_TRY(launch_words(ix, (uint8_t*)ix.words, st));
+    HIP_TRY(launch_envelopes(ix, idx->leaf_start_dev, ix.L, idx->env_dev, st));
+    HIP_TRY(launch_envelopes(ix, idx->chunk_start_dev, ix.chunks, idx->cenv_dev, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    *out = idx;
+    b->idx = nullptr;
+    delete b;
+    return HS_OK;
+}
+
+hs_status hs_build_abort(hs_builder* b) {
+    if (!b) return HS_OK;
+    if (b->st) (void)hipStreamSynchronize(b->st);
+    delete b->idx;
+    delete b;
+    return HS_OK;
+}
+
+hs_status hs_build_summaries(const float* x_dev, int64_t N, const hs_params* params, void* index_mem_dev,
+                             int64_t index_bytes, void* stream, hs_index** out) {
+    if (!out) return fail(HS_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!x_dev || !index_mem_dev) return fail(HS_EINVAL, "x_dev or index_mem_dev is NULL");
+    hs_builder* b = nullptr;
+    hs_status s = hs_build_begin(N, params, index_mem_dev, index_bytes, stream, &b);
+    if (s) return s;
+    s = hs_build_add_stats(b, x_dev, 0, N);
+    if (!s) s = hs_build_partition(b);
+    if (!s) s = hs_build_add_rows(b, x_dev, 0, N);
+    if (!s) s = hs_build_finish(b, out);
+    if (s) {
+        const std::string msg = g_err;
+        hs_build_abort(b);
+        g_err = msg;
+    }
+    return s;
 }
 
 hs_status hs_get_info(const hs_index* idx, hs_index_info* out) {

@@ -49,6 +49,23 @@ __global__ void k_gather_rows(const float* __restrict__ x, const uint32_t* __res
     }
 }
 
+__global__ void k_inverse_ids(const uint32_t* __restrict__ ids, int64_t N, uint32_t* __restrict__ pos) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < N; i += (int64_t)gridDim.x * blockDim.x)
+        pos[ids[i]] = (uint32_t)i;
+}
+
+// One wavefront per series of the chunk: its row to its stored position.
+__global__ void k_scatter_rows(const float* __restrict__ x, int64_t row0, int64_t count,
+                               const uint32_t* __restrict__ pos, int32_t n, int32_t stride, float* __restrict__ rows) {
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    for (int64_t r = blockIdx.x * (int64_t)(blockDim.x >> 6) + wave; r < count;
+         r += (int64_t)gridDim.x * (blockDim.x >> 6)) {
+        const float* src = x + r * n;
+        float* dst = rows + (int64_t)pos[row0 + r] * stride;
+        for (int j = lane; j < stride; j += 64) dst[j] = j < n ? src[j] : 0.0f;
+    }
+}
+
 __global__ void k_words(IndexView ix, uint8_t* __restrict__ words) {
     __shared__ float s_beta[kCard + 1];
     for (int j = threadIdx.x; j <= kCard; j += blockDim.x) s_beta[j] = ix.beta[j];
@@ -163,6 +180,18 @@ hipError_t launch_series_stats(const float* x, int64_t N, int32_t n, int32_t w, 
 hipError_t launch_gather_rows(const float* x, const uint32_t* perm, int64_t N, int32_t n, int32_t stride,
                               float* rows, hipStream_t st) {
     hipLaunchKernelGGL(k_gather_rows, dim3(grid_for(N, 4)), dim3(256), 0, st, x, perm, N, n, stride, rows);
+    return hipGetLastError();
+}
+
+hipError_t launch_inverse_ids(const uint32_t* ids, int64_t N, uint32_t* pos, hipStream_t st) {
+    hipLaunchKernelGGL(k_inverse_ids, dim3(grid_for(N, 256)), dim3(256), 0, st, ids, N, pos);
+    return hipGetLastError();
+}
+
+hipError_t launch_scatter_rows(const float* x, int64_t row0, int64_t count, const uint32_t* pos, int32_t n,
+                               int32_t stride, float* rows, hipStream_t st) {
+    hipLaunchKernelGGL(k_scatter_rows, dim3(grid_for(count, 4)), dim3(256), 0, st, x, row0, count, pos, n, stride,
+                       rows);
     return hipGetLastError();
 }
 

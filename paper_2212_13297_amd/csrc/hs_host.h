@@ -31,6 +31,10 @@ struct hs_index {
 };
 
 namespace hs {
+struct IndexLayout;
+}
+
+namespace hs {
 
 // Records the message for hs_last_error (this thread) and returns code.
 hs_status fail(hs_status code, const char* fmt, ...);
@@ -52,6 +56,23 @@ struct IndexLayout {
     int64_t chunk_cap;    // chunks (and parts) the tables hold
 };
 IndexLayout index_layout(int64_t N, const hs_params& p, char* base);
+
+}  // namespace hs
+
+// A streaming build in progress (hs_build_begin .. hs_build_finish).
+struct hs_builder {
+    hs_index* idx = nullptr;
+    hs::IndexLayout lay{};
+    hipStream_t st = nullptr;
+    char* scratch = nullptr;
+    uint32_t* bad = nullptr;     // NaN / Inf flag
+    float2* st_dev = nullptr;    // [N][w] segment statistics (first pass)
+    uint32_t* pos = nullptr;     // [N] stored position of each series (second pass)
+    int stage = 0;               // 0: statistics, 1: rows
+    int64_t next_row = 0;
+};
+
+namespace hs {
 
 // Device leaf partition (hs_partition.hip).  The statistics [N][w] go into
 // partition_stats_buffer(scratch) before the call; on return ids_out holds the

@@ -166,6 +166,11 @@ hipError_t launch_series_stats(const float* x, int64_t N, int32_t n, int32_t w, 
                                uint32_t* bad_flag, hipStream_t st);
 hipError_t launch_gather_rows(const float* x, const uint32_t* perm, int64_t N, int32_t n, int32_t stride,
                               float* rows, hipStream_t st);
+// pos[ids[i]] = i
+hipError_t launch_inverse_ids(const uint32_t* ids, int64_t N, uint32_t* pos, hipStream_t st);
+// rows[pos[row0 + r]] = x[r] (zero padded to stride), r < count
+hipError_t launch_scatter_rows(const float* x, int64_t row0, int64_t count, const uint32_t* pos, int32_t n,
+                               int32_t stride, float* rows, hipStream_t st);
 hipError_t launch_words(const IndexView& ix, uint8_t* words, hipStream_t st);
 hipError_t launch_read_probe(const void* buf, int64_t bytes, uint32_t* sink, int device_cus, hipStream_t st);
 hipError_t launch_envelopes(const IndexView& ix, const int64_t* starts, int64_t count, float4* env,

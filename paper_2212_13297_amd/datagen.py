@@ -86,6 +86,42 @@ def random_walks(N: int, n: int, seed: int = SEED_DATA, coll: int = 0,
     return out
 
 
+DEV_CHUNK = 1 << 18
+
+
+def walk_chunk_device(chunk: int, rows: int, n: int, seed: int = SEED_DATA, coll: int = 0, device="cuda:0"):
+    """Rows chunk * DEV_CHUNK .. + rows - 1 of a collection generated on the
+    GPU (for collections too large for host memory): the same recipe -- i.i.d.
+    N(0, 1) steps, cumulative sum, z-normalisation with the population std in
+    FP64, cast to float32 -- drawn from torch's generator seeded per
+    (seed, coll, chunk), so any chunk can be regenerated on its own.  A
+    different stream of random numbers than ``random_walks``: a collection
+    is generated one way or the other throughout."""
+    import torch
+    if rows < 1 or rows > DEV_CHUNK:
+        raise ValueError("rows must be in [1, DEV_CHUNK]")
+    g = torch.Generator(device=device)
+    g.manual_seed(((seed * 1_000_003 + coll) * 1_000_003 + chunk) & ((1 << 63) - 1))
+    x = torch.randn((rows, n), generator=g, dtype=torch.float64, device=device)
+    torch.cumsum(x, dim=1, out=x)
+    x -= x.mean(dim=1, keepdim=True)
+    sd = torch.sqrt((x * x).mean(dim=1, keepdim=True))
+    sd[sd < 1e-12] = 1.0
+    x /= sd
+    return x.to(torch.float32)
+
+
+def walks_device(N: int, n: int, row0: int, rows: int, seed: int = SEED_DATA, coll: int = 0, device="cuda:0"):
+    """Rows row0 .. row0 + rows - 1 (within one DEV_CHUNK chunk) of the
+    N-row collection that ``walk_chunk_device`` generates."""
+    c = row0 // DEV_CHUNK
+    if (row0 + rows - 1) // DEV_CHUNK != c or row0 + rows > N:
+        raise ValueError("rows must lie in one chunk of the collection")
+    full = walk_chunk_device(c, min(DEV_CHUNK, N - c * DEV_CHUNK), n, seed, coll, device)
+    off = row0 - c * DEV_CHUNK
+    return full[off:off + rows].contiguous()
+
+
 def query_sources(N: int, Q: int, seed: int = SEED_QUERY, coll: int = 0, tag: int = 0) -> np.ndarray:
     """Indices of ``Q`` distinct dataset rows used as query sources (int64)."""
     if Q > N:

@@ -74,6 +74,13 @@ _SIGS = {
     "hs_build_summaries": (ctypes.c_int32, [_P, ctypes.c_int64, ctypes.POINTER(hs_params), _P, ctypes.c_int64, _P,
                                             ctypes.POINTER(_P)]),
     "hs_get_info": (ctypes.c_int32, [_P, ctypes.POINTER(hs_index_info)]),
+    "hs_build_begin": (ctypes.c_int32, [ctypes.c_int64, ctypes.POINTER(hs_params), _P, ctypes.c_int64, _P,
+                                        ctypes.POINTER(_P)]),
+    "hs_build_add_stats": (ctypes.c_int32, [_P, _P, ctypes.c_int64, ctypes.c_int64]),
+    "hs_build_partition": (ctypes.c_int32, [_P]),
+    "hs_build_add_rows": (ctypes.c_int32, [_P, _P, ctypes.c_int64, ctypes.c_int64]),
+    "hs_build_finish": (ctypes.c_int32, [_P, ctypes.POINTER(_P)]),
+    "hs_build_abort": (ctypes.c_int32, [_P]),
     "hs_get_leaves": (ctypes.c_int32, [_P, _P, _P]),
     "hs_get_chunks": (ctypes.c_int32, [_P, _P, _P]),
     "hs_query_workspace_bytes": (ctypes.c_int32, [_P, ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(ctypes.c_int64)]),
@@ -154,6 +161,34 @@ def hs_build_summaries(x_ptr: int, N: int, params: hs_params, mem_ptr: int, mem_
     h = _P()
     _check(load().hs_build_summaries(x_ptr, N, ctypes.byref(params), mem_ptr, mem_bytes, stream, ctypes.byref(h)))
     return h
+
+
+def hs_build_begin(N: int, params: hs_params, mem_ptr: int, mem_bytes: int, stream: int):
+    b = _P()
+    _check(load().hs_build_begin(N, ctypes.byref(params), mem_ptr, mem_bytes, stream, ctypes.byref(b)))
+    return b
+
+
+def hs_build_add_stats(b, x_ptr: int, row0: int, rows: int) -> None:
+    _check(load().hs_build_add_stats(b, x_ptr, row0, rows))
+
+
+def hs_build_partition(b) -> None:
+    _check(load().hs_build_partition(b))
+
+
+def hs_build_add_rows(b, x_ptr: int, row0: int, rows: int) -> None:
+    _check(load().hs_build_add_rows(b, x_ptr, row0, rows))
+
+
+def hs_build_finish(b):
+    h = _P()
+    _check(load().hs_build_finish(b, ctypes.byref(h)))
+    return h
+
+
+def hs_build_abort(b) -> None:
+    _check(load().hs_build_abort(b))
 
 
 def hs_get_info(h) -> hs_index_info:
@@ -427,6 +462,45 @@ class Index:
         self._ws = None
         self.shadow = None
         self.shadow_kind = 0
+
+    @classmethod
+    def from_chunks(cls, chunk, N: int, n: int, params: Params | None = None, device="cuda:0", stream=None):
+        """Streaming build: chunk(row0) returns a contiguous float32 [rows, n]
+        GPU tensor of series row0 .. row0 + rows - 1 (rows >= 1); it is called
+        twice per chunk, in order, and must return the same values both times."""
+        import torch
+        self = cls.__new__(cls)
+        self.params = params or Params()
+        self.n = n
+        self.device = torch.device(device)
+        cp = self.params.c(n)
+        nbytes = hs_index_bytes(N, cp)
+        self.mem = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        sp = _stream_ptr(stream)
+        b = hs_build_begin(N, cp, self.mem.data_ptr(), nbytes, sp)
+        try:
+            for add in (hs_build_add_stats, hs_build_add_rows):
+                r0 = 0
+                while r0 < N:
+                    x = chunk(r0)
+                    if not (x.is_cuda and x.dtype == torch.float32 and x.dim() == 2 and x.shape[1] == n
+                            and x.is_contiguous() and 1 <= x.shape[0] <= N - r0):
+                        raise ValueError("chunk must be a contiguous float32 [rows, n] GPU tensor within [0, N)")
+                    add(b, x.data_ptr(), r0, x.shape[0])
+                    torch.cuda.current_stream().synchronize()  # the chunk may be freed once the build has read it
+                    r0 += x.shape[0]
+                if add is hs_build_add_stats:
+                    hs_build_partition(b)
+            self.h = hs_build_finish(b)
+            b = None
+        finally:
+            if b is not None:
+                hs_build_abort(b)
+        self.info = hs_get_info(self.h)
+        self._ws = None
+        self.shadow = None
+        self.shadow_kind = 0
+        return self
 
     def build_shadow(self, kind: int = HS_SHADOW_BF16, stream=None, shadow_rows: int = -1):
         """Build the low-precision copy that the precision form (knn_mixed) reads:

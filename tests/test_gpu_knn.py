@@ -129,6 +129,60 @@ def test_device_partition_equals_host_partition(N, n, w, tau, dup):
     b.close()
 
 
+def test_streaming_build_equals_one_call_build():
+    # The same index from uneven row chunks given twice (statistics, then
+    # rows) as from one call; chunk order and turn are enforced; NaN in a
+    # chunk is reported by the partition step.
+    hs = hs_mod()
+    N, n = 25_013, 256
+    x = G.random_walks(N, n, coll=33)
+    xt = torch.from_numpy(x).to(DEV)
+    a = hs.Index(xt, hs.Params(w=16, leaf_size=600))
+    sizes = [7001, 1, 9000, N - 16002]
+    starts = np.concatenate([[0], np.cumsum(sizes)])
+    calls = []
+
+    def chunk(r0):
+        i = int(np.searchsorted(starts, r0))
+        calls.append(r0)
+        return xt[r0:r0 + sizes[i]].contiguous()
+
+    b = hs.Index.from_chunks(chunk, N, n, hs.Params(w=16, leaf_size=600))
+    assert calls == list(starts[:-1]) * 2
+    ra, ia, wa, la, ea = a.layout()
+    rb, ib, wb, lb, eb = b.layout()
+    assert np.array_equal(la, lb) and np.array_equal(ea, eb)
+    assert torch.equal(ia, ib) and torch.equal(ra, rb) and torch.equal(wa, wb)
+    q = G.workload(x, [1, 10], 3, coll=33)[0]
+    r1 = run_knn(a, q, 10)
+    r2 = run_knn(b, q, 10)
+    assert np.array_equal(r1[0], r2[0]) and np.array_equal(r1[1], r2[1])
+    check_knn(x, q, 10, r2[0], r2[1])
+    # steps out of turn and chunks out of order are refused
+    p = hs.Params(w=16, leaf_size=600).c(n)
+    nb = hs.hs_index_bytes(N, p)
+    mem = torch.empty(nb, dtype=torch.uint8, device=DEV)
+    st = int(torch.cuda.current_stream().cuda_stream)
+    h = hs.hs_build_begin(N, p, mem.data_ptr(), nb, st)
+    with pytest.raises(hs.HSError):
+        hs.hs_build_add_stats(h, xt.data_ptr(), 5, 10)       # must start at row 0
+    with pytest.raises(hs.HSError):
+        hs.hs_build_partition(h)                             # statistics of all rows first
+    with pytest.raises(hs.HSError):
+        hs.hs_build_add_rows(h, xt.data_ptr(), 0, 10)        # rows after the partition
+    hs.hs_build_abort(h)
+    bad = xt.clone()
+    bad[20_000, 7] = float("nan")
+    h = hs.hs_build_begin(N, p, mem.data_ptr(), nb, st)
+    hs.hs_build_add_stats(h, bad.data_ptr(), 0, N)
+    with pytest.raises(hs.HSError) as e:
+        hs.hs_build_partition(h)
+    assert e.value.code == hs.HS_EINVAL
+    hs.hs_build_abort(h)
+    a.close()
+    b.close()
+
+
 # ----------------------------------------------------------------- parity
 
 CASES = [

@@ -103,3 +103,21 @@ def test_invalid_arguments():
         brute.knn(x, q, 0)
     with pytest.raises(ValueError):
         brute.knn(x, np.zeros((1, 5), np.float32), 1)
+
+
+def test_knn_chunked_equals_whole_collection():
+    # Ties across chunk boundaries (exact copies in different chunks) must be
+    # broken by the global id, and a chunk smaller than k must not truncate.
+    rng = np.random.default_rng(7)
+    x = rng.standard_normal((700, 24)).astype(np.float32)
+    x[650] = x[3]
+    x[420] = x[3]
+    q = rng.standard_normal((6, 24)).astype(np.float32)
+    q[0] = x[3]
+    for k in (1, 5, 9):
+        whole = brute.knn(x, q, k)
+        parts = brute.knn_chunked([x[:4], x[4:421], x[421:422], x[422:]], q, k)
+        assert np.array_equal(whole[0], parts[0]) and np.array_equal(whole[1], parts[1])
+        twin = brute.knn_numpy(x, q, k)
+        assert np.array_equal(parts[0], twin[0])
+    assert list(brute.knn_chunked([x[:100], x[100:]], q[:1], 3)[0][0]) == [3, 420, 650]
