@@ -319,8 +319,11 @@ int64_t ws_layout(const hs_index* idx, int32_t Q, int32_t k, QueryWs* ws, char* 
     const int32_t Qpad = (Q + kBoundQueries - 1) / kBoundQueries * kBoundQueries;
     carve(cur, (void**)&w.qlow, (int64_t)Qpad * ix.stride * 2);
     carve(cur, (void**)&w.qnorm, (int64_t)Q * 16);
-    carve(cur, (void**)&w.best_leaf, (int64_t)Qpad * 4);
-    carve(cur, (void**)&w.qorder, (int64_t)Qpad * 4);
+    carve(cur, (void**)&w.plist, (int64_t)Q * ix.parts * 4);
+    carve(cur, (void**)&w.pcnt, (ix.parts + 1) * 4);
+    carve(cur, (void**)&w.pnb, (ix.parts + 1) * 4);
+    carve(cur, (void**)&w.pbo, (ix.parts + 2) * 4);
+    carve(cur, (void**)&w.pscan, ((ix.parts + 1) / 1024 + 2) * 4);
     w.Qpad = Qpad;
     w.item_cap = items;
     w.slice_cap = slice_cap;
@@ -753,8 +756,10 @@ hs_status knn_enqueue(const KnnCall& c, const float* q_dev, int64_t* ids_dev, fl
     const ShadowView& sv = c.idx->shadow;
     const bool hybrid = c.mixed && sv.rows_n < ix.N;
     {
+        // the precision form makes items only where its copy does not reach
+        // (the bounding pass takes the parts of the copy from their lists)
         ScanParams se = sp;
-        if (hybrid) se.emit_part0 = sv.parts_n;  // items only where the copy does not reach
+        if (c.mixed) se.emit_part0 = sv.parts_n;
         HIP_TRY(launch_emit(ix, se, false, ws, st));
     }
     if (c.mixed) {
@@ -763,7 +768,6 @@ hs_status knn_enqueue(const KnnCall& c, const float* q_dev, int64_t* ids_dev, fl
             sb.slice0 = ws.n_slices / 2;
             sb.slices = ws.n_slices / 2;
         }
-        HIP_TRY(launch_query_order(sp.Q, ws, st));
         HIP_TRY(timed(HS_PROF_BOUND, [&] { return launch_bound(ix, sv, sb, ws, c.idx->cus, st); }));
     }
     if (!c.mixed || hybrid) {

@@ -116,8 +116,12 @@ struct QueryWs {
     // precision form
     uint16_t* qlow;       // [Qpad][stride] low-precision queries (zero rows beyond Q)
     double2* qnorm;       // [Q] (||q~||^2, ||q - q~||_2 rounded up)
-    uint32_t* best_leaf;  // [Qpad] the query's smallest-LB_EAPCA leaf (written by the seed)
-    int32_t* qorder;      // [Qpad] queries in bounding-pass order (-1 beyond Q)
+    // bounding pass: per part, the queries that keep its leaf
+    uint32_t* plist;      // [parts][Q] the part's list, in query order
+    uint32_t* pcnt;       // [parts] its length
+    uint32_t* pnb;        // [parts + 1] its blocks of kBoundQueries (work items)
+    uint32_t* pbo;        // [parts + 2] exclusive prefix of pnb: the part's first work item
+    uint32_t* pscan;      // scan scratch
     int32_t Qpad;         // Q rounded up to kBoundQueries
     int64_t item_cap;
     int64_t slice_cap;    // entries per slice
@@ -202,10 +206,10 @@ hipError_t launch_merge(const IndexView& ix, const ScanParams& sp, bool redo_onl
 hipError_t launch_shadow(const IndexView& ix, int kind, int64_t nrows, uint16_t* rows, float4* norms,
                          uint32_t* bad_flag, hipStream_t st);
 hipError_t launch_query_low(const IndexView& ix, int kind, int32_t Q, const QueryWs& ws, hipStream_t st);
-// order the queries by their best leaf (queries of one wavefront then keep
-// similar leaves, so the bounding pass skips more)
-hipError_t launch_query_order(int32_t Q, const QueryWs& ws, hipStream_t st);
 hipError_t launch_bound(const IndexView& ix, const ShadowView& sv, const ScanParams& sp, const QueryWs& ws,
                         int device_cus, hipStream_t st);
+// out[i] = in[0] + .. + in[i - 1], out[n] = the total (n + 1 entries); bsum
+// holds n / 1024 + 2 entries of scratch
+hipError_t launch_exclusive_scan(const uint32_t* in, int64_t n, uint32_t* out, uint32_t* bsum, hipStream_t st);
 
 }  // namespace hs

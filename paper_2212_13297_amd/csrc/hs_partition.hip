@@ -116,13 +116,6 @@ __global__ void __launch_bounds__(256) k_scan_add(uint32_t* __restrict__ out, in
     if (blockIdx.x == 0 && threadIdx.x == 0) out[n] = bsum[gridDim.x];
 }
 
-hipError_t exclusive_scan(const uint32_t* in, int64_t n, uint32_t* out, uint32_t* bsum, hipStream_t st) {
-    const int64_t nb = std::max<int64_t>(1, (n + kScanBlock - 1) / kScanBlock);
-    hipLaunchKernelGGL(k_scan_blocks, dim3((unsigned)nb), dim3(256), 0, st, in, n, out, bsum);
-    hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(1024), 0, st, bsum, nb);
-    hipLaunchKernelGGL(k_scan_add, dim3((unsigned)nb), dim3(256), 0, st, out, n, bsum);
-    return hipGetLastError();
-}
 
 // ---------------------------------------------------------------- levels
 struct Level {
@@ -519,6 +512,18 @@ int64_t layout(int64_t N, int w, int64_t tau, int64_t budget, char* base, Bufs* 
 inline unsigned blocks_for(int64_t n, int block) { return (unsigned)std::max<int64_t>(1, (n + block - 1) / block); }
 
 }  // namespace
+
+hipError_t exclusive_scan(const uint32_t* in, int64_t n, uint32_t* out, uint32_t* bsum, hipStream_t st) {
+    const int64_t nb = std::max<int64_t>(1, (n + kScanBlock - 1) / kScanBlock);
+    hipLaunchKernelGGL(k_scan_blocks, dim3((unsigned)nb), dim3(256), 0, st, in, n, out, bsum);
+    hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(1024), 0, st, bsum, nb);
+    hipLaunchKernelGGL(k_scan_add, dim3((unsigned)nb), dim3(256), 0, st, out, n, bsum);
+    return hipGetLastError();
+}
+
+hipError_t launch_exclusive_scan(const uint32_t* in, int64_t n, uint32_t* out, uint32_t* bsum, hipStream_t st) {
+    return exclusive_scan(in, n, out, bsum, st);
+}
 
 int64_t partition_scratch_bytes(int64_t N, int w, int64_t tau, int64_t budget) {
     return layout(N, w, tau, budget, nullptr, nullptr);

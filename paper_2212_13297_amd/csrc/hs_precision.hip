@@ -191,71 +191,35 @@ __global__ void __launch_bounds__(64) k_query_low(IndexView ix, int32_t Q, Query
     if (lane == 0) ws.qnorm[q] = make_double2(s2 * (1.0 - 0x1p-40), sqrt(e2) * (1.0 + 0x1p-40));
 }
 
-// Queries in the bounding pass's order: by their smallest-LB_EAPCA leaf (leaf
-// numbers follow the split tree, so neighbouring leaves hold similar series),
-// then by query.  Queries of one wavefront then keep similar leaves, and a
-// wavefront skips a part only when none of its queries keeps the leaf.  One
-// workgroup, bitonic sort in LDS (Q <= kOrderMax; beyond that, query order).
-constexpr int kOrderMax = 4096;
-
-__global__ void __launch_bounds__(1024) k_query_order(int32_t Q, QueryWs ws) {
-    __shared__ unsigned long long s_key[kOrderMax];
+// Per part of the copy: the queries whose LB_EAPCA of the part's leaf does
+// not exceed their BSF_k (1 + slack), in query order, and the number of
+// kBoundQueries-query blocks (work items of the bounding pass) they make.
+__global__ void __launch_bounds__(256) k_part_lists(IndexView ix, ScanParams sp, QueryWs ws) {
+    __shared__ int s_w[kTile / 64];
+    const int64_t p = blockIdx.x;
     const int t = threadIdx.x;
-    if (Q > kOrderMax) {
-        for (int i = t; i < ws.Qpad; i += blockDim.x) ws.qorder[i] = i < Q ? i : -1;
-        return;
+    const int64_t leaf = ix.part_leaf[p];
+    uint32_t* list = ws.plist + p * (int64_t)sp.Q;
+    int base = 0;
+    for (int q0 = 0; q0 < sp.Q; q0 += blockDim.x) {
+        const int q = q0 + t;
+        bool k = false;
+        if (q < sp.Q && !(ws.flags[q] & kFlagNonFinite))
+            k = (double)ws.lbe[(int64_t)q * ix.L + leaf] <= prune_limit(bits_to_float(bsf_bits(ws, q)));
+        int tot;
+        const int off = block_exclusive_scan(k ? 1 : 0, s_w, &tot);
+        if (k) list[base + off] = (uint32_t)q;
+        base += tot;
     }
-    int P = 1;
-    while (P < Q) P <<= 1;
-    for (int i = t; i < P; i += blockDim.x)
-        s_key[i] = i < Q ? (((unsigned long long)ws.best_leaf[i] << 32) | (unsigned)i) : ~0ull;
-    __syncthreads();
-    for (int size = 2; size <= P; size <<= 1) {
-        for (int stride = size >> 1; stride > 0; stride >>= 1) {
-            for (int i = t; i < P; i += blockDim.x) {
-                const int j2 = i ^ stride;
-                if (j2 > i) {
-                    const bool up = (i & size) == 0;
-                    const unsigned long long a = s_key[i], c = s_key[j2];
-                    if ((a > c) == up) {
-                        s_key[i] = c;
-                        s_key[j2] = a;
-                    }
-                }
-            }
-            __syncthreads();
-        }
-    }
-    for (int i = t; i < ws.Qpad; i += blockDim.x) ws.qorder[i] = i < Q ? (int)(s_key[i] & 0xffffffffu) : -1;
-}
-
-// Which q-group and row range a workgroup takes.  With enough workgroups the
-// G q-groups of one row range run on the same XCD (workgroup b sits on XCD
-// b % 8), next to each other in launch order, so the staged series are read
-// from HBM about once and from that XCD's L2 by the other q-groups.
-struct BoundMap {
-    int R;   // row ranges
-    int G;   // q-groups (kBoundQueries queries each)
-    int GS;  // q-group stride of one workgroup
-    int used;
-    int xcd_aware;
-    int nper;  // xcd_aware: (row range, q-group) items per XCD, dealt from the XCD's counter
-};
-
-__device__ __forceinline__ void bound_block(const BoundMap& m, int b, int& g0, int& r) {
-    if (m.xcd_aware) {
-        const int x = b & 7, tt = b >> 3;
-        g0 = tt % m.G;
-        r = (tt / m.G) * 8 + x;
-    } else {
-        g0 = b % m.GS;
-        r = b / m.GS;
+    if (t == 0) {
+        ws.pcnt[p] = (uint32_t)base;
+        ws.pnb[p] = (uint32_t)((base + kBoundQueries - 1) / kBoundQueries);
     }
 }
 
-// The bounding pass.  Workgroup = 4 wavefronts x 32 queries (one q-group);
-// it walks its row range part by part (a part lies in one leaf) in tiles of
-// 32 series.  Per tile and K-block the 32 x 256 low-precision series are
+// The bounding pass.  Workgroup = 4 wavefronts x 32 queries: a block of the
+// queries that keep one part (a part lies in one leaf); it walks the part in
+// tiles of 32 series.  Per tile and K-block the 32 x 256 low-precision series are
 // staged in LDS (double buffered: the next stage's global loads are in flight
 // during this stage's matrix-core steps).  Every wavefront computes the 32 x 32 block
 // acc[series][query] with 16 v_mfma 32x32x16 steps; its query fragments stay
@@ -288,7 +252,7 @@ __device__ __forceinline__ void bound_block(const BoundMap& m, int b, int& g0, i
 // takes the accumulation bound g2 S of the K + 2 products.
 template <int KIND, bool ONE>
 __global__ void __launch_bounds__(256) k_bound(IndexView ix, ShadowView sv, ScanParams sp, QueryWs ws,
-                                               BoundConsts bc, BoundMap bm) {
+                                               BoundConsts bc) {
 #pragma clang fp contract(off)
     __shared__ __attribute__((aligned(16))) uint16_t s_tile[2][kBoundRows * kLdsRow];
     __shared__ float2 s_norm[2][kBoundRows];  // (beta', eps_x) per staged series
@@ -311,49 +275,32 @@ __global__ void __launch_bounds__(256) k_bound(IndexView ix, ShadowView sv, Scan
          e += (int64_t)gridDim.x * kTile)
         ws.slice_cnt[sp.slice0 + e] = 0;
 
-    // Work items (q-group g, row range r).  XCD-aware: the workgroups of XCD x
-    // (b mod 8) take items i = u G + g, r = 8 u + x, from the XCD's counter, so
-    // the q-groups of one row range run at about the same time on one XCD
-    // (its L2 serves them the same series) and every workgroup keeps taking
-    // items while any are left.  Otherwise a fixed item per workgroup.
-    int wi = 0;
+    // Work items (part p, block b): the queries of p's list (every query whose
+    // LB_EAPCA of p's leaf does not exceed its BSF_k) are cut into blocks of
+    // kBoundQueries, 32 per wavefront; items are dealt from one counter in
+    // part order, so the blocks of a part run about together.  A part's rows
+    // are staged once per block: with at most kBoundQueries queries keeping a
+    // leaf, once per batch.
+    const uint32_t nitems = ws.pbo[sv.parts_n];
     for (;;) {
-        int g, r;
-        if (bm.xcd_aware) {
-            __syncthreads();  // every wave has read s_item
-            if (t == 0) s_item = (int)atomicAdd(&ws.counters[kCtrBound + (blockIdx.x & 7)], 1u);
-            __syncthreads();
-            const int it = s_item;
-            if (it >= bm.nper) break;
-            g = it % bm.G;
-            r = (it / bm.G) * 8 + (int)(blockIdx.x & 7);
-        } else {
-            if ((int)blockIdx.x >= bm.used) break;
-            int g0;
-            bound_block(bm, blockIdx.x, g0, r);
-            g = g0 + wi * bm.GS;
-            if (g >= bm.G) break;
-            ++wi;
+        __syncthreads();  // every wave has read s_item
+        if (t == 0) s_item = (int)atomicAdd(&ws.counters[kCtrBound], 1u);
+        __syncthreads();
+        const uint32_t it = (uint32_t)s_item;
+        if (it >= nitems) break;
+        // the part of the item: the last p with pbo[p] <= it
+        int64_t plo = 0, phi = sv.parts_n - 1;
+        while (plo < phi) {
+            const int64_t mid = (plo + phi + 1) >> 1;
+            if (ws.pbo[mid] <= it) plo = mid;
+            else phi = mid - 1;
         }
-        // the copy holds the first sv.rows_n stored series (whole parts)
-        const int64_t row0 = sv.rows_n * r / bm.R, row1 = sv.rows_n * (r + 1) / bm.R;
-        // first part that ends after row0
-        int64_t lo = 0, hi = ix.parts;
-        while (lo < hi) {
-            const int64_t mid = (lo + hi) >> 1;
-            if (ix.part_start[mid + 1] <= row0) lo = mid + 1;
-            else hi = mid;
-        }
-        const int64_t p_first = lo;
-
+        const int64_t p = plo;
+        const uint32_t lq = (it - ws.pbo[p]) * kBoundQueries + (uint32_t)(wave * 32 + j);
         {
-            // q-group g takes positions g 128 .. g 128 + 127 of the query order
-            // (queries sorted by their best leaf), so the queries of one
-            // wavefront tend to keep the same leaves and skip the same parts
-            const int pos = g * kBoundQueries + wave * 32 + j;
-            const int qo = ws.qorder[pos];
-            const bool qvalid = qo >= 0 && !(ws.flags[qo] & kFlagNonFinite);
-            const int qj = qo >= 0 ? qo : pos;  // padded positions read a zero row of the query copy
+            // lanes past the part's list read query 0's copy; their results are masked
+            const bool qvalid = lq < ws.pcnt[p];
+            const int qj = qvalid ? (int)ws.plist[p * (int64_t)sp.Q + lq] : 0;
             float alpha = -3.0e38f, sT = 0.0f, sTb = 0.0f, bsf_j = 0.0f;
             uint4 bq_aug = make_uint4(0, 0, 0, 0);  // ONE: (1, sTbar) at k = 256, 257 (half 0)
             if (qvalid) {
@@ -388,13 +335,10 @@ __global__ void __launch_bounds__(256) k_bound(IndexView ix, ShadowView sv, Scan
             unsigned long long tested = 0, cands = 0, staged = 0;  // staged: pairs the matrix cores evaluated
             bool lost = false;
 
-            for (int64_t p = p_first; p < ix.parts && ix.part_start[p] < row1; ++p) {
-                const int64_t ps = max(ix.part_start[p], row0), pe = min(ix.part_start[p + 1], row1);
-                if (pe <= ps) continue;
-                const int64_t leaf = ix.part_leaf[p];
-                const bool keep = qvalid && (double)ws.lbe[(int64_t)qj * ix.L + leaf] <= prune_limit(bsf_j);
+            {
+                const int64_t ps = ix.part_start[p], pe = ix.part_start[p + 1];
+                const bool keep = qvalid;  // every listed query keeps the part's leaf
                 const bool wkeep = __ballot(keep) != 0ull;
-                if (!__syncthreads_or(wkeep ? 1 : 0)) continue;
                 const int64_t ntiles = (pe - ps + kBoundRows - 1) / kBoundRows;
                 const int64_t nst = ntiles * nkb;
 
@@ -602,8 +546,12 @@ __global__ void __launch_bounds__(256) k_bound(IndexView ix, ShadowView sv, Scan
                     __syncthreads();
                 }
             }
-            // per-query counters: lanes l and l + 32 hold the same query
+            // per-query counters: lanes l and l + 32 hold the same query.  The
+            // matrix cores also computed the wavefront's lanes past the list:
+            // their pairs count with its first query's
             cands += __shfl_down(cands, 32, 64);
+            const int nvalid = __popcll(__ballot(qvalid && half == 0));
+            if (lane == 0 && nvalid > 0) staged += (unsigned long long)(32 - nvalid) * staged;
             if (half == 0 && qvalid) {
                 if (tested) atomicAdd(&ws.stats[(int64_t)qj * 8 + 1], tested);
                 if (cands) atomicAdd(&ws.stats[(int64_t)qj * 8 + 6], cands);
@@ -637,20 +585,19 @@ hipError_t launch_query_low(const IndexView& ix, int kind, int32_t Q, const Quer
     return hipGetLastError();
 }
 
-hipError_t launch_query_order(int32_t Q, const QueryWs& ws, hipStream_t st) {
-    k_query_order<<<dim3(1), dim3(1024), 0, st>>>(Q, ws);
-    return hipGetLastError();
-}
-
 hipError_t launch_bound(const IndexView& ix, const ShadowView& sv, const ScanParams& sp, const QueryWs& ws,
                         int device_cus, hipStream_t st) {
     // one candidate slice per wavefront; no more workgroups than are resident
     int grid = sp.slices / (kTile / 64);
-    if (sv.rows_n <= 0) {
+    if (sv.rows_n <= 0 || sv.parts_n <= 0) {
         // nothing to bound: the pass only marks its slices empty
         hipLaunchKernelGGL(k_empty_slices, dim3(1), dim3(256), 0, st, ws, sp.slice0, sp.slices);
         return hipGetLastError();
     }
+    // per part: the queries that keep it, then the first work item of each part
+    hipLaunchKernelGGL(k_part_lists, dim3((unsigned)sv.parts_n), dim3(kTile), 0, st, ix, sp, ws);
+    hipError_t e = launch_exclusive_scan(ws.pnb, sv.parts_n, ws.pbo, ws.pscan, st);
+    if (e != hipSuccess) return e;
     const bool one = ix.stride <= kKBlock;
     int resident;
     if (sv.kind == kShadowF16)
@@ -660,27 +607,13 @@ hipError_t launch_bound(const IndexView& ix, const ShadowView& sv, const ScanPar
         resident = one ? resident_grid(k_bound<kShadowBf16, true>, kTile, 0, device_cus)
                        : resident_grid(k_bound<kShadowBf16, false>, kTile, 0, device_cus);
     grid = std::max(1, std::min(grid, resident));
-    BoundMap bm{};
-    bm.G = ws.Qpad / kBoundQueries;
-    if (bm.G * 8 <= grid) {
-        // about 8 items per workgroup, dealt out per XCD
-        bm.xcd_aware = 1;
-        bm.GS = bm.G;
-        bm.R = 8 * std::max(1, (int)std::min<int64_t>(8 * (grid / (8 * bm.G)), sv.rows_n / (8 * 64)));
-        bm.nper = (bm.R / 8) * bm.G;
-    } else {
-        bm.xcd_aware = 0;
-        bm.GS = bm.G < grid ? bm.G : grid;
-        bm.R = grid / bm.GS;
-    }
-    bm.used = bm.R * bm.GS;
     const BoundConsts bc = bound_consts(ix.stride);
     if (sv.kind == kShadowF16) {
-        if (one) k_bound<kShadowF16, true><<<dim3(grid), dim3(kTile), 0, st>>>(ix, sv, sp, ws, bc, bm);
-        else k_bound<kShadowF16, false><<<dim3(grid), dim3(kTile), 0, st>>>(ix, sv, sp, ws, bc, bm);
+        if (one) k_bound<kShadowF16, true><<<dim3(grid), dim3(kTile), 0, st>>>(ix, sv, sp, ws, bc);
+        else k_bound<kShadowF16, false><<<dim3(grid), dim3(kTile), 0, st>>>(ix, sv, sp, ws, bc);
     } else {
-        if (one) k_bound<kShadowBf16, true><<<dim3(grid), dim3(kTile), 0, st>>>(ix, sv, sp, ws, bc, bm);
-        else k_bound<kShadowBf16, false><<<dim3(grid), dim3(kTile), 0, st>>>(ix, sv, sp, ws, bc, bm);
+        if (one) k_bound<kShadowBf16, true><<<dim3(grid), dim3(kTile), 0, st>>>(ix, sv, sp, ws, bc);
+        else k_bound<kShadowBf16, false><<<dim3(grid), dim3(kTile), 0, st>>>(ix, sv, sp, ws, bc);
     }
     return hipGetLastError();
 }

@@ -268,7 +268,6 @@ __global__ void __launch_bounds__(kSeedThreads) k_seed(IndexView ix, ScanParams 
     const int n = min(k, M);
     for (int j = t; j < n; j += blockDim.x) ws.pool[(int64_t)q * ws.P + j] = s_keys[j];
     if (t == 0) {
-        if (ws.best_leaf) ws.best_leaf[q] = s_leaves[0];
         ws.pool_cnt[q] = (uint32_t)n;
         if (n == k) ws.bkey[q] = s_keys[k - 1];
         unsigned long long* st = ws.stats + (int64_t)q * 8;
