@@ -1,29 +1,32 @@
-"""Serial FP64 run of Hercules' exact k-NN search (oracle; test infrastructure only).
+"""Serial FP64 exact k-NN by filter-and-refine (oracle; test infrastructure only).
 
-Takes the steps of the paper's exact search (Sec. 3.4, the Exact-kNN
-algorithm and its four steps) in order, over a flat list of leaves built by
-``summaries.build_leaves``:
+A self-check of the pruning rules of Hercules' exact search (Sec. 3.4), run
+on the CPU over the oracle's own leaves (``summaries.build_leaves``).  What
+makes the search exact is that every rule only discards work whose outcome
+cannot enter the result:
 
-1. Approximate search (the Approx-kNN algorithm): leaves in ascending
-   LB_EAPCA order; stop at the first whose bound exceeds BSF_k or after L_max
-   leaves; refine every series of each visited leaf.
-2. Candidate leaves (FindCandidateLeaves): the remaining leaves whose
-   LB_EAPCA does not exceed BSF_k, kept in file (leaf) order; eapca_pr is the
-   fraction pruned.
-3. If eapca_pr < EAPCA_TH: skip-sequential scan of the candidate leaves.
-   Otherwise candidate series (CSWorker): every series of a candidate leaf
-   whose LB_SAX against PAA(query) does not exceed BSF_k; sax_pr is the
-   fraction of all series pruned.
-4. If sax_pr < SAX_TH: skip-sequential scan; otherwise refine the candidate
-   series (CRWorker), re-checking each LB_SAX against the current BSF_k.
+* The result R holds the k best (d, id) pairs found so far, in (d, id)
+  order; BSF_k is the distance of its k-th entry (+inf while R is short).
+* A leaf is discarded when its LB_EAPCA (Sec. 2, the segment mean/std
+  envelope bound) exceeds BSF_k, a series when its LB_SAX (the PAA of the
+  query against the series' iSAX word) exceeds BSF_k, and a series'
+  distance stops accumulating once the partial sum exceeds BSF_k.  Each is a
+  lower bound of the series' true distance, and BSF_k only decreases, so a
+  discarded series could never precede R's k-th entry.
+* BSF_k starts from the leaves of smallest LB_EAPCA, at most L_max of them
+  while their bound is within BSF_k, refined in full (the approximate
+  search).
+* How the surviving leaves are read is an access-path choice: when too few
+  leaves were discarded (fraction below EAPCA_TH), or too few series would
+  be by LB_SAX (fraction below SAX_TH), their series are refined without the
+  LB_SAX test; otherwise only the LB_SAX survivors are, each bound tested
+  again against the current BSF_k.
 
-Readings (the paper's tests are strict ``<``, which can drop a candidate tied
-with BSF_k): a node or series is pruned only when its bound is strictly
-greater than BSF_k, and a refined series enters the result when (d, id)
-precedes the current k-th entry lexicographically.  Results start as k
-entries of (inf, none).  Refinement abandons a series once its partial sum
-(FP64, points in order) exceeds BSF_k.  The thresholds choose an access path
-only; all paths return the same result, which must equal brute force.
+Readings: the paper's tests are strict (LB < BSF_k, d < BSF_k), which can
+drop a series tied with the k-th; here a bound discards only when strictly
+greater, and a refined series enters R when its (d, id) precedes the k-th
+entry.  Partial sums are checked after every 64 points, in point order.  The
+result must equal brute force on every path.
 """
 from __future__ import annotations
 
@@ -35,7 +38,7 @@ from . import summaries as S
 
 
 class Results:
-    """k best (d, id) pairs in ascending order; BSF_k is the k-th distance."""
+    """k best (d, id) pairs in ascending (d, id) order; BSF_k is the k-th distance."""
 
     def __init__(self, k: int):
         self.k = k
@@ -46,32 +49,31 @@ class Results:
     def bsf(self) -> float:
         return self.d[-1]
 
-    def _precedes(self, d, i, j):
+    def _before(self, d, i, j):
+        """(d, i) precedes entry j (an empty entry is preceded by anything)."""
         if d != self.d[j]:
             return d < self.d[j]
         return self.id[j] is None or i < self.id[j]
 
     def offer(self, d: float, i: int) -> None:
-        if not self._precedes(d, i, self.k - 1):
+        if not self._before(d, i, self.k - 1):
             return
-        pos = self.k - 1
-        while pos > 0 and self._precedes(d, i, pos - 1):
-            self.d[pos] = self.d[pos - 1]
-            self.id[pos] = self.id[pos - 1]
-            pos -= 1
-        self.d[pos] = d
-        self.id[pos] = i
+        j = self.k - 1
+        while j > 0 and self._before(d, i, j - 1):
+            self.d[j], self.id[j] = self.d[j - 1], self.id[j - 1]
+            j -= 1
+        self.d[j], self.id[j] = d, i
 
 
 def refine(q64: np.ndarray, x_row: np.ndarray, bsf: float) -> float:
-    """Squared ED in FP64 with early abandoning (UCR-Suite style, Sec. 2):
-    returns the full sum, or a partial sum > bsf once it exceeds bsf."""
+    """Squared ED in FP64 with early abandoning (UCR-Suite style, Sec. 2): the
+    full sum, or the first 64-point partial sum that exceeds bsf."""
     diff = q64 - x_row.astype(np.float64)
-    partial = np.cumsum(diff * diff)          # sequential running sums, FP64
-    for end in range(63, len(partial), 64):   # checked after every 64 points
-        if partial[end] > bsf:
-            return float(partial[end])
-    return float(partial[-1])
+    running = np.cumsum(diff * diff)
+    over = np.nonzero(running[63::64] > bsf)[0]
+    if over.size:
+        return float(running[63 + 64 * int(over[0])])
+    return float(running[-1])
 
 
 class LeafIndex:
@@ -88,75 +90,64 @@ class LeafIndex:
         self.words = S.sax_word(S.paa(self.x, w), self.beta)
 
 
+def _refine_all(res: Results, q64, x, rows):
+    for r in rows:
+        res.offer(refine(q64, x[r], res.bsf), int(r))
+
+
 def exact_knn(index: LeafIndex, q: np.ndarray, k: int, l_max: int = 1,
               eapca_th: float = 0.25, sax_th: float = 0.50, stats: dict | None = None):
     """Exact k-NN of one query.  Returns (ids int64 [k], d2 float64 [k])."""
     if k < 1 or k > index.x.shape[0]:
         raise ValueError("k out of range")
     q64 = np.asarray(q, dtype=np.float64)
-    x = index.x
+    x, leaves = index.x, index.leaves
+    L = len(leaves)
     res = Results(k)
-
     mu_q, sd_q = S.segment_stats(q64, index.ends)
     lb_leaf = S.lb_eapca(mu_q, sd_q, index.syn, index.ends)
-    L = len(index.leaves)
-    order = sorted(range(L), key=lambda i: (lb_leaf[i], i))
+    by_bound = sorted(range(L), key=lambda i: (lb_leaf[i], i))
 
-    # Step 1: approximate search over at most l_max leaves
-    visited = set()
-    pos = 0
-    while len(visited) < l_max and pos < L:
-        leaf = order[pos]
+    # initial BSF_k: the most promising leaves, refined in full
+    seeded = []
+    for leaf in by_bound[:l_max]:
         if lb_leaf[leaf] > res.bsf:
             break
-        for r in index.leaves[leaf]:
-            d = refine(q64, x[r], res.bsf)
-            res.offer(d, int(r))
-        visited.add(leaf)
-        pos += 1
+        _refine_all(res, q64, x, leaves[leaf])
+        seeded.append(leaf)
+    rest = by_bound[len(seeded):]
 
-    # Step 2: candidate leaves, file order
-    bsf = res.bsf
-    lclist = sorted(i for i in order[pos:] if lb_leaf[i] <= bsf)
-    eapca_pr = 1.0 - len(lclist) / L
-    path = "sax"
+    # the leaves LB_EAPCA cannot discard at this BSF_k, in leaf order
+    kept = sorted(leaf for leaf in rest if lb_leaf[leaf] <= res.bsf)
+    leaf_pruned = 1.0 - len(kept) / L
 
-    def skip_sequential():
-        for leaf in lclist:
-            if lb_leaf[leaf] > res.bsf:
-                continue
-            for r in index.leaves[leaf]:
-                d = refine(q64, x[r], res.bsf)
-                res.offer(d, int(r))
+    def read_whole_leaves():
+        for leaf in kept:
+            if lb_leaf[leaf] <= res.bsf:   # BSF_k may have tightened meanwhile
+                _refine_all(res, q64, x, leaves[leaf])
 
-    sax_pr = None
-    if eapca_pr < eapca_th:
+    series_pruned = None
+    if leaf_pruned < eapca_th:
         path = "skipseq_eapca"
-        skip_sequential()
+        read_whole_leaves()
     else:
-        # Step 3: candidate series by LB_SAX against PAA(query)
         paa_q = S.paa(q64, index.w)
-        sclist = []
-        for leaf in lclist:
-            ids = index.leaves[leaf]
-            lbs = S.lb_sax(paa_q, index.words[ids], index.beta, index.n)
-            for r, lb in zip(ids, lbs):
-                if lb <= bsf:
-                    sclist.append((int(r), float(lb)))
-        sax_pr = 1.0 - len(sclist) / x.shape[0]
-        if sax_pr < sax_th:
+        bsf0 = res.bsf
+        rows = np.concatenate([leaves[leaf] for leaf in kept]) if kept else np.zeros(0, dtype=np.int64)
+        lb_rows = S.lb_sax(paa_q, index.words[rows], index.beta, index.n) if len(rows) else np.zeros(0)
+        survivors = [(int(r), float(b)) for r, b in zip(rows, lb_rows) if b <= bsf0]
+        series_pruned = 1.0 - len(survivors) / x.shape[0]
+        if series_pruned < sax_th:
             path = "skipseq_sax"
-            skip_sequential()
+            read_whole_leaves()
         else:
-            # Step 4: refine candidate series against the current BSF_k
-            for r, lb in sclist:
-                if lb > res.bsf:
-                    continue
-                d = refine(q64, x[r], res.bsf)
-                res.offer(d, r)
+            path = "sax"
+            for r, b in survivors:
+                if b <= res.bsf:
+                    res.offer(refine(q64, x[r], res.bsf), r)
 
     if stats is not None:
-        stats.update(dict(path=path, leaves=L, visited=len(visited), lclist=len(lclist),
-                          eapca_pr=eapca_pr, sax_pr=sax_pr))
+        stats.update(dict(path=path, leaves=L, visited=len(seeded), lclist=len(kept),
+                          eapca_pr=leaf_pruned, sax_pr=series_pruned))
     ids = np.asarray([i if i is not None else -1 for i in res.id], dtype=np.int64)
     return ids, np.asarray(res.d, dtype=np.float64)
