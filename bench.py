@@ -125,10 +125,10 @@ def run_mixed(hs, torch, idx, qt, k, steps, warmup, wl, plain_ids, plain_d2, bui
         avg = bms / bl
         # algorithmic work of the bounding pass: one q~.x~ (2K flop) per bounded
         # (query, series) pair; the low-precision rows and norms it must read once
-        flops = 2.0 * K * float(stats["rows_filtered"].sum()) / (bl / steps)
+        flops = 2.0 * K * float(stats["rows_bounded"].sum()) / (bl / steps)
         # what the matrix cores computed: every (query, series) pair of the
         # tiles each wavefront of 32 queries took (padding queries not counted)
-        xflops = 2.0 * K * float(stats["chunks_tested"].sum()) / (bl / steps)
+        xflops = 2.0 * K * float(stats["bound_pairs"].sum()) / (bl / steps)
         kern["bound"] = {"avg_launch_ms": round(avg, 4), "launches_per_step": bl / steps,
                          "flops_per_launch": int(flops),
                          "TFLOP_s": round(flops / (avg / 1e3) / 1e12, 2),
@@ -155,7 +155,8 @@ def run_mixed(hs, torch, idx, qt, k, steps, warmup, wl, plain_ids, plain_d2, bui
                          "executed_frac": round(kern["bound"]["executed_TFLOP_s"] / MFMA_PEAK_TFLOPS[low], 4),
                          "kernel": "k_bound", "traffic": traffic.get("bytes_per_launch") if traffic else None,
                          "traffic_detail": traffic} if "bound" in kern else None),
-           "pruning": {"rows_bounded_mean": float(stats["rows_filtered"].mean()),
+           "pruning": {"rows_bounded_mean": float(stats["rows_bounded"].mean()),
+                       "rows_filtered_mean": float(stats["rows_filtered"].mean()),
                        "candidates_mean": float(stats["candidates"].mean()),
                        "rows_refined_mean": float(stats["rows_refined"].mean()),
                        "rounds_max": int(stats["rounds"].max())}}

@@ -195,15 +195,18 @@ hs_status hs_query_workspace_bytes(const hs_index* idx, int32_t Q, int32_t k, in
  */
 typedef struct {
     uint64_t leaves_kept;     /* candidate leaves after LB_EAPCA (seed leaves included) */
-    uint64_t rows_filtered;   /* series whose LB_SAX (precision form: matrix-core bound) was evaluated */
+    uint64_t rows_filtered;   /* series whose LB_SAX was evaluated */
     uint64_t rows_refined;    /* series whose raw values were read */
     uint64_t chunks_read;     /* 64-point chunks of raw values read (early abandoning stops early) */
     uint64_t path;            /* 0 = LB_SAX path, 1 = skip-sequential (no LB_SAX) */
     uint64_t rounds;          /* refinement rounds (1 unless the candidate pool overflowed) */
     uint64_t candidates;      /* LB_SAX survivors put on the candidate list (two-stage path) */
-    uint64_t chunks_tested;   /* 64-series chunk envelopes whose LB_EAPCA was evaluated; precision
-                                 form: series whose dot product with this query the matrix cores
-                                 computed (every series of a tile its wavefront of 32 queries took) */
+    uint64_t chunks_tested;   /* 64-series chunk envelopes whose LB_EAPCA was evaluated */
+    uint64_t rows_bounded;    /* precision form: series of the low-precision copy whose matrix-core
+                                 bound was evaluated for this query (0 in the plain form) */
+    uint64_t bound_pairs;     /* precision form: series whose dot product with this query the matrix
+                                 cores computed (every series of the parts its wavefront took,
+                                 padding lanes counted with the wavefront's first query) */
 } hs_query_stats;
 
 /*

@@ -400,6 +400,8 @@ __global__ void __launch_bounds__(1024) k_merge(IndexView ix, ScanParams sp, int
             o.rounds = st[5];
             o.candidates = st[6];
             o.chunks_tested = st[7];
+            o.rows_bounded = st[0];
+            o.bound_pairs = st[4];
             stats_out[q] = o;
         }
     }

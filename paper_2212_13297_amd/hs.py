@@ -45,7 +45,8 @@ class hs_index_info(ctypes.Structure):
 class hs_query_stats(ctypes.Structure):
     _fields_ = [("leaves_kept", ctypes.c_uint64), ("rows_filtered", ctypes.c_uint64),
                 ("rows_refined", ctypes.c_uint64), ("chunks_read", ctypes.c_uint64), ("path", ctypes.c_uint64),
-                ("rounds", ctypes.c_uint64), ("candidates", ctypes.c_uint64), ("chunks_tested", ctypes.c_uint64)]
+                ("rounds", ctypes.c_uint64), ("candidates", ctypes.c_uint64), ("chunks_tested", ctypes.c_uint64),
+                ("rows_bounded", ctypes.c_uint64), ("bound_pairs", ctypes.c_uint64)]
 
 
 class hs_server_config(ctypes.Structure):
@@ -65,8 +66,7 @@ class hs_server_stats(ctypes.Structure):
                 ("padded_queries", ctypes.c_int64), ("graphs", ctypes.c_int64), ("failed", ctypes.c_int64)]
 
 
-STATS_FIELDS = ["leaves_kept", "rows_filtered", "rows_refined", "chunks_read", "path", "rounds", "candidates",
-                "chunks_tested"]
+STATS_FIELDS = [f for f, _ in hs_query_stats._fields_]
 
 _P = ctypes.c_void_p
 _SIGS = {
@@ -553,7 +553,7 @@ class Index:
         ids = torch.empty((Q, k), dtype=torch.int64, device=self.device)
         d2 = torch.empty((Q, k), dtype=torch.float32, device=self.device)
         err = torch.empty((Q, k), dtype=torch.float64, device=self.device)
-        st = torch.zeros((Q, 8), dtype=torch.int64, device=self.device) if stats else None
+        st = torch.zeros((Q, len(STATS_FIELDS)), dtype=torch.int64, device=self.device) if stats else None
         hs_knn_mixed(self.h, q.data_ptr(), Q, k, ws.data_ptr(), nbytes, ids.data_ptr(), d2.data_ptr(),
                      err.data_ptr(), st.data_ptr() if st is not None else None, _stream_ptr(stream))
         if stats:
@@ -572,7 +572,7 @@ class Index:
         else:
             ids, d2 = out
         eb = torch.empty((Q, k), dtype=torch.float64, device=self.device) if err else None
-        st = torch.zeros((Q, 8), dtype=torch.int64, device=self.device) if stats else None
+        st = torch.zeros((Q, len(STATS_FIELDS)), dtype=torch.int64, device=self.device) if stats else None
         hs_knn_exact(self.h, q.data_ptr(), Q, k, ws.data_ptr(), nbytes, ids.data_ptr(), d2.data_ptr(),
                      eb.data_ptr() if eb is not None else None, st.data_ptr() if st is not None else None,
                      _stream_ptr(stream))

@@ -126,7 +126,7 @@ def test_mixed_parity(N, n, w, k, leaf, lmax, per, kind):
     x, q = workload(N, n, coll=50 + n, per_level=per, ood=4 if n == 1024 else 2)
     idx = make_index(x, kind, w=w, leaf_size=leaf, l_max=lmax)
     ids, d2, err, st = knn_mixed(idx, q, k, stats=True)
-    print(f"[case] rows bounded {st['rows_filtered'].mean():.0f}, candidates {st['candidates'].mean():.1f}, "
+    print(f"[case] rows bounded {st['rows_bounded'].mean():.0f}, candidates {st['candidates'].mean():.1f}, "
           f"refined {st['rows_refined'].mean():.1f}", flush=True)
     oids, od = check_knn(x, q, k, ids, d2)
     rel = check_err(x, q, ids, d2, err)
@@ -161,7 +161,13 @@ def test_mixed_partial_copy(N, n, w, k, kind, fracs):
         assert np.array_equal(d2.view(np.uint32), pd2.view(np.uint32))
         check_knn(x, q, k, ids, d2, oids, od)
         check_err(x, q, ids, d2, err)
-        assert np.all(st["rows_filtered"] > 0)
+        # the copy's series are bounded on the matrix cores, the others by LB_SAX
+        assert np.all(st["rows_filtered"] + st["rows_bounded"] > 0)
+        assert np.all(st["bound_pairs"] >= st["rows_bounded"])
+        if rows == 0:
+            assert st["rows_bounded"].sum() == 0
+        else:
+            assert st["rows_bounded"].sum() > 0
     idx.close()
 
 
