@@ -3,18 +3,26 @@
 // re-checked against the current BSF_k; per-wavefront top-k, BSF_k published
 // with atomicMin, results appended to the per-query pool.
 //
-// Wavefronts take runs of consecutive candidates (the list is ordered by
-// query, so a run holds long stretches of one query) and never wait for one
-// another.  Their 16-lane groups refine a few series each, one 64-point chunk
-// per round, in the order of the series' LB_SAX quarter bounds, abandoning a
-// series as soon as its running distance, plus the bounds of its unread
-// quarters, exceeds the limit, and taking the next candidate in its place.
+// Wavefronts take runs of consecutive candidates (a run holds long stretches
+// of one query) and never wait for one another.  Their 4-lane groups refine
+// one series each, one 64-point chunk per round, in the order of the series'
+// LB_SAX quarter bounds, abandoning a series as soon as its running
+// distance, plus the bounds of its unread quarters, exceeds the limit, and
+// taking the next candidate in its place.
+//
+// What bounds the kernel is the latency of its scattered chunk reads: the
+// memory system serves about the batch's distinct chunks (re-reads of a
+// chunk by other queries mostly hit the caches), and a wavefront waits for
+// its round's chunks before it can hand out the next candidates.  So
+// resident wavefronts count more than candidates in flight per wavefront:
+// one slot per group at four wavefronts per SIMD is faster than two slots at
+// three or four slots at two.
 #include "hs_device.h"
 
 namespace hs {
 namespace {
 
-constexpr int kRefineSlots = 4;  // candidates in flight per 16-lane group
+constexpr int kRefineSlots = 1;  // candidates in flight per 4-lane group
 constexpr int kSeg = 512;        // candidates per segment of a long list (a multiple of 64, >= 128)
 constexpr uint32_t kNaturalPerm = 0xE4u;  // quarters 0, 1, 2, 3
 
@@ -120,18 +128,53 @@ __device__ __forceinline__ uint4 ring_entry(const Meta& m, bool ord, uint32_t& r
                       __float_as_uint(__double2float_rd(lb / (1.0 + kSlack))), 0x7f800000u);
 }
 
-// F: distance form.  NS: candidates in flight per 16-lane group.
+// The partial of one 64-point chunk for a group of 4 lanes: lane j holds
+// points 4 (j + 4 i) .. + 3 for i = 0..3 (so each of the four loads of a
+// group reads 64 contiguous bytes).  The lane squares its 16 differences into
+// four accumulators (a chain of 4 each), adds them pairwise, and two quad
+// permutations sum the group.  A term passes through at most as many
+// roundings as in the 16-lane partial (4 in the chain, 2 in the pairwise
+// sum, 2 in the butterfly), so the abandoning margin holds unchanged.
+__device__ __forceinline__ float quad_partial(const float4 (&q)[4], const float4 (&x)[4]) {
+    float4 a;
+    {
+        const float t0 = q[0].x - x[0].x, t1 = q[0].y - x[0].y, t2 = q[0].z - x[0].z, t3 = q[0].w - x[0].w;
+        a = make_float4(t0 * t0, t1 * t1, t2 * t2, t3 * t3);
+    }
+#pragma unroll
+    for (int i = 1; i < 4; ++i) {
+        const float t0 = q[i].x - x[i].x, t1 = q[i].y - x[i].y, t2 = q[i].z - x[i].z, t3 = q[i].w - x[i].w;
+        a.x = fmaf(t0, t0, a.x);
+        a.y = fmaf(t1, t1, a.y);
+        a.z = fmaf(t2, t2, a.z);
+        a.w = fmaf(t3, t3, a.w);
+    }
+    float p = (a.x + a.y) + (a.z + a.w);
+    p += row_xor<1>(p);
+    p += row_xor<2>(p);
+    return p;
+}
+
+// NS: candidates in flight per 4-lane group.
 //
 // A wavefront refines a stream of candidates: one contiguous range of a short
 // list, or segments of kSeg of a long one, its first by its index and each
 // next one from a counter when its ring reaches it (so wavefronts that meet
-// costly candidates take fewer segments).  Each of its four groups keeps NS
-// slots; a round loads one 64-point chunk of every slot's series (and the
-// query's chunk), adds the chunk's partial to the slot's running distance,
-// and retires the slots whose distance exceeds their limit (abandoned) or
-// whose series is complete.  Retired slots take the next candidates of the
-// stream at once, so every round reads NS useful chunks per group however
-// early candidates are abandoned.
+// costly candidates take fewer segments).  Each of its 16 groups of 4 lanes
+// keeps NS slots; a round loads one 64-point chunk of every slot's series
+// (and the query's chunk), adds the chunk's partial to the slot's running
+// distance, and retires the slots whose distance exceeds their limit
+// (abandoned) or whose series is complete.  Retired slots take the next
+// candidates of the stream at once, so every round reads NS useful chunks
+// per group however early candidates are abandoned.  With 4 lanes per series
+// the per-candidate bookkeeping (hand-out, order, cascade, limits) is spread
+// over 4 lanes instead of 16, and a round covers 16 NS series.
+//
+// The running distance is plain float32 in any chunk order.  A series that
+// completes within its limit is read again for its result key, the
+// compensated distance in natural chunk order (key_distance, by one 16-lane
+// row of the wavefront; up to four such series per pass), the value every
+// kernel keys the pair with.
 //
 // The candidates' metadata pass through a ring of 128 entries in LDS per
 // wavefront (the next 64 are loaded while the current ones are handed out),
@@ -146,14 +189,18 @@ __device__ __forceinline__ uint4 ring_entry(const Meta& m, bool ord, uint32_t& r
 // Q1: one chunk per quarter in the chunk order (n = 256): the chunk index is a
 // field of the order word and the cascade's bounds shift out as it is read.
 // U: batch-union diagnostics (marks every (series, chunk) pair read).
-template <int F, int NS, bool Q1, bool U>
+template <int NS, bool Q1, bool U>
 __global__ void __launch_bounds__(256, 4) k_refine(IndexView ix, ScanParams sp, QueryWs ws) {
     constexpr int kRing = 128;
+    constexpr int kGroups = 16;                           // 4-lane groups per wavefront
+    constexpr uint64_t kHeads = 0x1111111111111111ull;    // the first lane of every group
+    static_assert(kGroups * NS <= 64, "a hand-out must stay within the ring's loaded half");
     __shared__ unsigned long long s_top[kTile / 64][HS_KMAX];
     // ring_entry of the stream's candidate v at v mod 128
     __shared__ uint4 s_ring[kTile / 64][kRing];
     __shared__ uint32_t s_rem[kTile / 64][kRing];  // the entries' rem (chunk_perm)
-    const int t = threadIdx.x, lane = t & 63, wave = t >> 6, sub = t & 15, grp = (t >> 4) & 3;
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6, sub = lane & 3, grp = lane >> 2;
+    const uint64_t below = ((1ull << (4 * grp)) - 1ull) & kHeads;  // heads of the lower groups
     const int k = sp.k;
     const int nchunks = ix.stride / kChunk;
     // chunk order: quarters in the ring entry's order, chunks of a quarter in
@@ -203,20 +250,22 @@ __global__ void __launch_bounds__(256, 4) k_refine(IndexView ix, ScanParams sp, 
     float lk = INFINITY;
     int topn = 0;                                     // lane 0
     unsigned long long pub = kInfKey;                 // lane 0: k-th key last published for cur_q
-    // refined series and chunks read for query st_q (uniform), per group
+    // refined series and chunks read for query st_q (uniform), per group (the
+    // group's lanes hold the same values)
     int st_q = -1;
     uint32_t g_ref = 0u;  // < 2^31 candidates per wavefront
     unsigned long long g_ch = 0ull;
     auto flush_counters = [&]() {
-        unsigned long long r = 0ull, c = 0ull;
+        // sum over the group heads (lanes 4 g): xor steps 4 .. 32 gather them in lane 0
+        uint32_t r = sub == 0 ? g_ref : 0u;
+        unsigned long long c = sub == 0 ? g_ch : 0ull;
 #pragma unroll
-        for (int g = 0; g < 4; ++g) {
-            r += (uint32_t)__builtin_amdgcn_readlane(g_ref, 16 * g);
-            c += ((unsigned long long)(uint32_t)__builtin_amdgcn_readlane((uint32_t)(g_ch >> 32), 16 * g) << 32) |
-                 (uint32_t)__builtin_amdgcn_readlane((uint32_t)g_ch, 16 * g);
+        for (int o = 32; o >= 4; o >>= 1) {
+            r += __shfl_xor(r, o, 64);
+            c += __shfl_xor(c, o, 64);
         }
         if (lane == 0 && st_q >= 0 && r) {
-            atomicAdd(&ws.stats[(int64_t)st_q * 8 + 2], r);
+            atomicAdd(&ws.stats[(int64_t)st_q * 8 + 2], (unsigned long long)r);
             atomicAdd(&ws.stats[(int64_t)st_q * 8 + 3], c);
         }
         g_ref = 0u;
@@ -263,34 +312,40 @@ __global__ void __launch_bounds__(256, 4) k_refine(IndexView ix, ScanParams sp, 
     };
     long long next = 0;  // stream position of the next candidate to hand out (uniform)
 
-    const float* rows_sub = ix.rows + sub * 4;  // the lane's first point of stored row 0 and of query 0
+    // the lane's first point of stored row 0 and of query 0 in each load
+    const float* rows_sub = ix.rows + sub * 4;
     const float* qrow_sub = ws.qrow + sub * 4;
-    // slots, each the same in the 16 lanes of its group
+    const float* rows16 = ix.rows + (lane & 15) * 4;  // the same for a 16-lane row (result keys)
+    const float* qrow16 = ws.qrow + (lane & 15) * 4;
+    // slots, each the same in the 4 lanes of its group
     int sq[NS];            // query (-1: empty)
+    uint32_t spos[NS];     // stored position of the series
     int sc[NS];            // chunks added so far
     uint32_t sperm[NS];    // order of the quarters
     uint32_t srem[NS];     // bounds of the quarters unread after one and after two (fp16 pair)
     float sthr[NS];        // abandoning limit times marg
     const float* xp[NS];   // the lane's first point of the series and of the query
     const float* qp[NS];
-    Dist<F> sd[NS];
+    float sd[NS];          // running distance
     bool fin[NS];          // slot wants a candidate
 #pragma unroll
     for (int s = 0; s < NS; ++s) {
         sq[s] = -1;
+        spos[s] = 0u;
         sc[s] = 0;
         sperm[s] = kNaturalPerm;
         srem[s] = 0u;
         sthr[s] = INFINITY;
         xp[s] = rows_sub;
         qp[s] = qrow_sub;
+        sd[s] = 0.0f;
         fin[s] = true;
     }
 
     for (;;) {
-        // hand out candidates to the slots that want one, in slot order
-        // (group g, slot s) -> g NS + s; a candidate whose LB_SAX exceeds its
-        // limit is skipped and the slot asks again
+        // hand out candidates to the slots that want one: slot 0 of every
+        // wanting group in group order, then slot 1, ...; a candidate whose
+        // LB_SAX exceeds its limit is skipped and the slot asks again
         for (;;) {
             if (next - mb >= 64) {
                 // the ring moves on by 64: the entries now handed out have
@@ -323,38 +378,30 @@ __global__ void __launch_bounds__(256, 4) k_refine(IndexView ix, ScanParams sp, 
                 pend = load_meta(ws, cp, vp, T, cur);
                 has_pend = true;
             }
-            if (has_pend && next + 4 * NS > mb + 64) {
+            if (has_pend && next + kGroups * NS > mb + 64) {
                 // this hand-out reaches the entries still in flight (after many
                 // skipped candidates): they are written now
                 write_pend();
             }
-            int rank[NS], nf = 0;
-#pragma unroll
-            for (int s = 0; s < NS; ++s) {
-                rank[s] = nf;
-                nf += fin[s] ? 1 : 0;
-            }
-            const int f0 = __builtin_amdgcn_readlane(nf, 0), f1 = __builtin_amdgcn_readlane(nf, 16),
-                      f2 = __builtin_amdgcn_readlane(nf, 32), f3 = __builtin_amdgcn_readlane(nf, 48);
-            const int total = f0 + f1 + f2 + f3;
-            if (total == 0) break;
-            const int goff = (int)next + (grp > 0 ? f0 : 0) + (grp > 1 ? f1 : 0) + (grp > 2 ? f2 : 0);
+            int total = 0;
             bool again = false;
 #pragma unroll
             for (int s = 0; s < NS; ++s) {
-                if (!__ballot(fin[s])) continue;
+                const uint64_t m = __ballot(fin[s]) & kHeads;
+                if (!m) continue;
                 if (fin[s]) {
-                    const int ri = goff + rank[s];  // stream position
+                    const int ri = (int)next + total + __popcll(m & below);  // stream position (low bits)
                     const uint4 e = ring[ri & (kRing - 1)];
                     const int q = e.x != 0xffffffffu ? (int)(e.x & 0xffffffu) : -1;  // -1 past the stream's end
                     float lim = __uint_as_float(e.w);
                     if (q == cur_q) lim = fminf(lim, lk);
                     const uint32_t pos = q >= 0 ? e.y : 0u;
                     sq[s] = q;
+                    spos[s] = pos;
                     sc[s] = 0;
                     sperm[s] = e.x >> 24;
                     srem[s] = rring[ri & (kRing - 1)];
-                    sd[s] = Dist<F>{};
+                    sd[s] = 0.0f;
                     sthr[s] = lim * marg;
                     // one 32 x 32 -> 64-bit multiply each (pos, q and stride are non-negative)
                     xp[s] = rows_sub + (uint64_t)pos * (uint32_t)ix.stride;
@@ -362,7 +409,9 @@ __global__ void __launch_bounds__(256, 4) k_refine(IndexView ix, ScanParams sp, 
                     fin[s] = q >= 0 && __uint_as_float(e.z) > lim;  // skipped: ask again
                     again = again || fin[s];
                 }
+                total += __popcll(m);
             }
+            if (total == 0) break;
             next += total;
             if (!__ballot(again)) break;
         }
@@ -370,19 +419,23 @@ __global__ void __launch_bounds__(256, 4) k_refine(IndexView ix, ScanParams sp, 
 #pragma unroll
         for (int s = 0; s < NS; ++s) any = any || sq[s] >= 0;
         if (!__ballot(any)) break;
-
         // one chunk of every slot's series (its next in the slot's order);
         // empty slots read a chunk of row 0
-        float4 x[NS], qv[NS];
+        float4 xa[NS][4], qa[NS][4];
 #pragma unroll
         for (int s = 0; s < NS; ++s) {
             const int c = Q1    ? (int)((sperm[s] >> (2 * sc[s])) & 3u)
                           : ord ? ((int)((sperm[s] >> ((sc[s] >> olg) << 1)) & 3u) << olg) | (sc[s] & omask)
                                 : sc[s];
-            x[s] = *reinterpret_cast<const float4*>(xp[s] + c * kChunk);
-            qv[s] = *reinterpret_cast<const float4*>(qp[s] + c * kChunk);
+            const float* xb = xp[s] + c * kChunk;
+            const float* qb = qp[s] + c * kChunk;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                xa[s][i] = *reinterpret_cast<const float4*>(xb + 16 * i);
+                qa[s][i] = *reinterpret_cast<const float4*>(qb + 16 * i);
+            }
             if (U && sq[s] >= 0 && sub == 0) {
-                const int64_t bit = (int64_t)((xp[s] - rows_sub) / ix.stride) * nchunks + c;
+                const int64_t bit = (int64_t)spos[s] * nchunks + c;
                 atomicOr(&ws.ubits[bit >> 5], 1u << (bit & 31));
             }
         }
@@ -393,7 +446,7 @@ __global__ void __launch_bounds__(256, 4) k_refine(IndexView ix, ScanParams sp, 
             adm[s] = false;
             fin[s] = false;
             if (sq[s] >= 0) {
-                sd[s].add(qv[s], x[s]);
+                sd[s] += quad_partial(qa[s], xa[s]);
                 sc[s] += 1;
                 // cascade: after the first and the second quarter, the bounds of
                 // the quarters still unread are added to the running distance
@@ -405,7 +458,7 @@ __global__ void __launch_bounds__(256, 4) k_refine(IndexView ix, ScanParams sp, 
                     const half2_t h = __builtin_bit_cast(half2_t, srem[s]);
                     rest = sc[s] == cpq ? (float)h.x : (sc[s] == 2 * cpq ? (float)h.y : 0.0f);
                 }
-                const bool over = sd[s].value() + rest > sthr[s];
+                const bool over = sd[s] + rest > sthr[s];
                 fin[s] = over || sc[s] == nchunks;
                 adm[s] = fin[s] && !over;
                 slow = slow || adm[s] || (fin[s] && sq[s] != st_q);
@@ -426,25 +479,48 @@ __global__ void __launch_bounds__(256, 4) k_refine(IndexView ix, ScanParams sp, 
         }
         // a series completed within its limit gets its result key distance,
         // the compensated one in natural chunk order that every kernel keys
-        // the pair with: read again unless the running sum already is that
-        // (precision form, natural order)
+        // the pair with: read again by one 16-lane row of the wavefront, up
+        // to four series per pass
         float kv[NS];
-        {
-            bool rc[NS], anyrc = false;
 #pragma unroll
-            for (int s = 0; s < NS; ++s) {
-                kv[s] = sd[s].value();
-                rc[s] = adm[s] && (F == kPlain || sperm[s] != kNaturalPerm);
-                anyrc = anyrc || rc[s];
-            }
-            if (__ballot(anyrc)) {
+        for (int s = 0; s < NS; ++s) {
+            kv[s] = sd[s];
+            uint64_t m = __ballot(adm[s]) & kHeads;
+            while (m) {
+                // the batch: the lowest four admitted groups, row j of the
+                // wavefront taking the j-th
+                uint64_t batch = 0ull, r = m;
 #pragma unroll
-                for (int s = 0; s < NS; ++s) {
-                    if (!__ballot(rc[s])) continue;
-                    if (rc[s]) {
-                        kv[s] = key_distance(xp[s], qp[s], nchunks);
-                        sc[s] += nchunks;  // chunks read again
+                for (int j = 0; j < 4; ++j) {
+                    const uint64_t lo = r & (~r + 1ull);
+                    batch |= lo;
+                    r ^= lo;
+                }
+                m = r;
+                const int row = lane >> 4;
+                int src = -1;
+                {
+                    uint64_t b = batch;
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) {
+                        const int l = b ? __builtin_ctzll(b) : -1;
+                        if (j == row) src = l;
+                        b &= b - 1ull;
                     }
+                }
+                float v = 0.0f;
+                const int sl = max(src, 0);
+                const uint32_t kpos = (uint32_t)__shfl((int)spos[s], sl, 64);
+                const int kq = __shfl(max(sq[s], 0), sl, 64);
+                if (src >= 0)
+                    v = key_distance(rows16 + (uint64_t)kpos * (uint32_t)ix.stride,
+                                     qrow16 + (uint64_t)(uint32_t)kq * (uint32_t)ix.stride, nchunks);
+                // the group whose head is the j-th of the batch takes row j's value
+                const int j = __popcll(batch & ((1ull << (4 * grp)) - 1ull));
+                const float vj = __shfl(v, 16 * min(j, 3), 64);
+                if ((batch >> (4 * grp)) & 1ull) {
+                    kv[s] = vj;
+                    sc[s] += nchunks;  // chunks read again
                 }
             }
         }
@@ -452,24 +528,22 @@ __global__ void __launch_bounds__(256, 4) k_refine(IndexView ix, ScanParams sp, 
         int new_q = cur_q;
 #pragma unroll
         for (int s = 0; s < NS; ++s) {
-            const uint64_t b = __ballot(fin[s]);
-#pragma unroll
-            for (int g = 0; g < 4; ++g) {
-                if (!((b >> (16 * g)) & 1ull)) continue;
-                const int kq = __builtin_amdgcn_readlane(sq[s], 16 * g);
+            uint64_t m = __ballot(fin[s]) & kHeads;
+            while (m) {
+                const int l = __builtin_ctzll(m);
+                m &= m - 1ull;
+                const int kq = __builtin_amdgcn_readlane(sq[s], l);
                 if (kq != st_q) {
                     flush_counters();
                     st_q = kq;
                 }
-                if (grp == g) {
+                if (grp == (l >> 2)) {
                     g_ref += 1u;
                     g_ch += (unsigned long long)sc[s];
                 }
-                if (__builtin_amdgcn_readlane((int)adm[s], 16 * g)) {
-                    const float v = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(kv[s]), 16 * g));
-                    // stored position of the series, from the lane's pointer (sub * 4 < stride)
-                    const uint32_t kp = (uint32_t)__builtin_amdgcn_readlane(
-                        (int)(uint32_t)((xp[s] - ix.rows) / ix.stride), 16 * g);
+                if (__builtin_amdgcn_readlane((int)adm[s], l)) {
+                    const float v = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(kv[s]), l));
+                    const uint32_t kp = (uint32_t)__builtin_amdgcn_readlane((int)spos[s], l);
                     if (lane == 0) {
                         if (kq != new_q) {
                             flush_topk(ws, new_q, k, top, topn);
@@ -508,26 +582,21 @@ __global__ void __launch_bounds__(256, 4) k_refine(IndexView ix, ScanParams sp, 
 
 }  // namespace
 
+// Both forms refine with the plain running distance; the result keys are the
+// compensated ones either way.
 hipError_t launch_refine(const IndexView& ix, const ScanParams& sp, const QueryWs& ws, int device_cus, int form,
                          hipStream_t st) {
-#define HS_REFINE(FF, NS, QQ, UU)                                                                 \
-    k_refine<FF, NS, QQ, UU><<<dim3(resident_grid(k_refine<FF, NS, QQ, UU>, kTile, 0, device_cus)), dim3(kTile), 0, \
-                               st>>>(ix, sp, ws)
+    (void)form;
+#define HS_REFINE(QQ, UU)                                                                                        \
+    k_refine<kRefineSlots, QQ, UU><<<dim3(resident_grid(k_refine<kRefineSlots, QQ, UU>, kTile, 0, device_cus)), \
+                                     dim3(kTile), 0, st>>>(ix, sp, ws)
     const bool q1 = sp.order_lg == 0;
     if (ws.ubits) {
-        if (form == kComp) {
-            if (q1) HS_REFINE(kComp, kRefineSlots, true, true);
-            else HS_REFINE(kComp, kRefineSlots, false, true);
-        } else {
-            if (q1) HS_REFINE(kPlain, kRefineSlots, true, true);
-            else HS_REFINE(kPlain, kRefineSlots, false, true);
-        }
-    } else if (form == kComp) {
-        if (q1) HS_REFINE(kComp, kRefineSlots, true, false);
-        else HS_REFINE(kComp, kRefineSlots, false, false);
+        if (q1) HS_REFINE(true, true);
+        else HS_REFINE(false, true);
     } else {
-        if (q1) HS_REFINE(kPlain, kRefineSlots, true, false);
-        else HS_REFINE(kPlain, kRefineSlots, false, false);
+        if (q1) HS_REFINE(true, false);
+        else HS_REFINE(false, false);
     }
 #undef HS_REFINE
     return hipGetLastError();
