@@ -290,6 +290,47 @@ def cpu_oracle(x, q, sel, k, note):
     return cpu, oids, od
 
 
+def cpu_method(args, hs, torch, G, dev, N=100_000, n=256, nq=10, level=5, k=1, leaf=1000, coll=1):
+    """The method on the CPU: the oracle's serial FP64 filter-and-refine
+    (leaf pruning by LB_EAPCA, series pruning by LB_SAX, early-abandoning
+    refinement) on the small random-walk workload, beside the GPU's plain
+    form on the same queries.  The oracle's index over 10M series would take
+    minutes to build, so the comparison runs at 100k x 256."""
+    from oracle import search
+    x = G.random_walks(N, n, coll=coll)
+    q, _, _ = G.workload(x, [level], nq, coll=coll)
+    t0 = time.perf_counter()
+    oix = search.LeafIndex(x, args.w, leaf)
+    build_cpu = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    res = [search.exact_knn(oix, q[i], k, l_max=args.l_max) for i in range(nq)]
+    cpu_s = time.perf_counter() - t0
+    xt = torch.from_numpy(x).to(dev)
+    qt = torch.from_numpy(q).to(dev)
+    idx = hs.Index(xt, hs.Params(w=args.w, leaf_size=leaf, l_max=args.l_max, seed_rows=args.seed_rows))
+    for _ in range(5):
+        idx.knn(qt, k)
+    torch.cuda.synchronize()
+    calls = 50
+    t0 = time.perf_counter()
+    for _ in range(calls):
+        ids, d2 = idx.knn(qt, k)
+    torch.cuda.synchronize()
+    gpu_s = (time.perf_counter() - t0) / calls
+    g = ids.cpu().numpy()
+    same = int(sum(np.array_equal(g[i], res[i][0]) for i in range(nq)))
+    idx.close()
+    out = {"workload": f"random-walk {N}x{n} f32, {nq} queries at {level}% noise, k={k}, w={args.w}, leaf {leaf}, "
+                       f"l_max {args.l_max}",
+           "cpu": {"value": round(nq / cpu_s, 3), "unit": "queries/s", "cores": 1,
+                   "kind": "oracle filter-and-refine (serial, FP64)", "index_build_s": round(build_cpu, 2)},
+           "gpu": {"value": round(nq / gpu_s, 2), "unit": "queries/s", "ms_per_call": round(gpu_s * 1e3, 4),
+                   "mode": f"one call of {nq} queries"},
+           "identical_id_lists": same}
+    log(f"method on the CPU: {out}")
+    return out
+
+
 def parity_of(ids, d2, sel, oids, od):
     g_ids = ids.cpu().numpy()[sel]
     g_d = d2.cpu().numpy()[sel].astype(np.float64)
@@ -807,6 +848,7 @@ def main():
 
     cpu = None
     parity = None
+    method = None
     if not args.no_cpu_baseline and args.cpu_sample > 0:
         sel = np.linspace(0, Q - 1, min(args.cpu_sample, Q)).round().astype(np.int64)
         cpu, oids, od = cpu_oracle(x, q, sel, args.k,
@@ -814,6 +856,7 @@ def main():
                                    f"{'/'.join(map(str, levels))}% levels), k={args.k}")
         parity = parity_of(ids, d2, sel, oids, od)
         log(f"CPU oracle {cpu['value']} q/s; parity {parity}")
+        method = cpu_method(args, hs, torch, G, dev)
 
     ids_cpu = ids.cpu()
     idx.close()
@@ -859,6 +902,7 @@ def main():
         "pruning": pruning_summary(stats, pct, levels),
         "build_s": round(build_s, 2),
         "cpu_baseline": cpu,
+        "cpu_method": method,
         "parity_sample": parity,
         "precision_form": mixed,
         "serving_form": serving,

@@ -91,6 +91,10 @@ __device__ __forceinline__ float lb_sax_word(const uint4 (&v)[W16], const float*
 // these partial bounds, largest first.
 template <int W16>
 __device__ __forceinline__ void lb_sax_quarters(const uint4 (&v)[W16], const float* s_lut, float (&a)[4]) {
+    // every table read is issued before the first sum, then each quarter's
+    // entries are added as a balanced tree (table entries are >= 0)
+    constexpr int kSeg = 16 * W16, kQ = 4 * W16;
+    float e[kSeg];
 #pragma unroll
     for (int u = 0; u < W16; ++u) {
         const uint32_t parts[4] = {v[u].x, v[u].y, v[u].z, v[u].w};
@@ -99,11 +103,20 @@ __device__ __forceinline__ void lb_sax_quarters(const uint4 (&v)[W16], const flo
 #pragma unroll
             for (int b = 0; b < 4; ++b) {
                 const int i = u * 16 + p * 4 + b;
-                const int qt = i / (4 * W16);
-                const float e = s_lut[i * kCard + ((parts[p] >> (8 * b)) & 0xffu)];
-                a[qt] = i % (4 * W16) == 0 ? e : a[qt] + e;  // table entries are >= 0
+                e[i] = s_lut[i * kCard + ((parts[p] >> (8 * b)) & 0xffu)];
             }
         }
+    }
+#pragma unroll
+    for (int qt = 0; qt < 4; ++qt) {
+        float t[kQ];
+#pragma unroll
+        for (int j = 0; j < kQ; ++j) t[j] = e[qt * kQ + j];
+#pragma unroll
+        for (int h = kQ / 2; h >= 1; h >>= 1)
+#pragma unroll
+            for (int j = 0; j < h; ++j) t[j] = t[j] + t[j + h];
+        a[qt] = t[0];
     }
 }
 
