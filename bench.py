@@ -438,6 +438,19 @@ def run_serving(args, hs, torch, G, idx256, x256):
             done[r["tag"]] = r
     sat_s = max(done[R + t]["t_done"] for t in range(S)) - t1
     info2 = srv.info()
+    # the same request mix without batching: one eager call per request (plain
+    # form, queries already on the device), in submission order
+    E = min(S, 3000)
+    qdev = [torch.from_numpy(qs[t][None, :].copy()).to(dev) for t in range(E)]
+    for t in range(min(E, 50)):
+        idxs[int(coll[t])].knn(qdev[t], int(ks[t]))
+    torch.cuda.synchronize()
+    t0e = time.perf_counter()
+    for t in range(E):
+        idxs[int(coll[t])].knn(qdev[t], int(ks[t]))
+    torch.cuda.synchronize()
+    eager_qps = E / (time.perf_counter() - t0e)
+    del qdev
     out = {"value": round(len(meas) / span, 2), "unit": "queries/s", "offered_rate": args.serve_rate,
            "latency_ms": {"p50": round(float(np.percentile(lat, 50)), 4), "p99": round(float(np.percentile(lat, 99)), 4),
                           "mean": round(float(lat.mean()), 4), "from": "scheduled arrival"},
@@ -448,6 +461,9 @@ def run_serving(args, hs, torch, G, idx256, x256):
            "batches": info["batches"], "mean_batch": round(info["queries"] / max(1, info["batches"]), 2),
            "graphs": info2["graphs"], "identical_to_eager": f"{same}/{len(checked)}",
            "saturation_queries_per_s": round(S / sat_s, 2), "saturation_requests": S,
+           "saturation_mean_batch": round((info2["queries"] - info["queries"]) /
+                                          max(1, info2["batches"] - info["batches"]), 2),
+           "eager_one_call_per_request_queries_per_s": round(eager_qps, 2), "eager_requests": E,
            "collections": [f"{len(xc)}x{xc.shape[1]}" for xc in xs], "k": "U{1..100}",
            "noise_variance": "U[0.01, 0.10]", "wall_s": round(wall, 1)}
     log(f"serving: {out}")

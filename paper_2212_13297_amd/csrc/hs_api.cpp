@@ -785,26 +785,40 @@ hs_status knn_enqueue(const KnnCall& c, const float* q_dev, int64_t* ids_dev, fl
 }
 
 // Queries whose candidate list or result pool overflowed: rescan their
-// candidate parts with the fused kernel and the tightened BSF_k until nothing
-// overflows (each merge keeps the best k so far, without repeats).  Synchronises.
+// candidate parts with the tightened BSF_k until nothing overflows (each merge
+// keeps the best k so far, without repeats).  While no round has dropped
+// candidates (only result pools overflowed), a round takes the main path:
+// filter, candidate list and refine over the round's queries' items.  Once
+// one has, every later round takes the fused scan, which needs no list.
+// Synchronises.
 hs_status knn_finish(const KnnCall& c, int64_t* ids_dev, float* d2_dev, double* err_dev, hs_query_stats* stats_out,
                      hipStream_t st, ScanTimer* timer) {
     const IndexView& ix = c.idx->view;
     const QueryWs& ws = c.ws;
     ScanParams sp = c.sp;
     sp.final_pass = 1;
+    bool fused = false;
     for (int round = 0;; ++round) {
-        uint32_t cnt[2] = {0, 0};
+        uint32_t cnt[2] = {0, 0}, lost = 0;
         HIP_TRY(hipMemcpyAsync(cnt, ws.counters + kCtrRedo, sizeof cnt, hipMemcpyDeviceToHost, st));
+        HIP_TRY(hipMemcpyAsync(&lost, ws.counters + kCtrLost, sizeof lost, hipMemcpyDeviceToHost, st));
         HIP_TRY(hipStreamSynchronize(st));
         if (cnt[1])
             return fail(HS_EINVAL, "%u queries contain NaN or Inf%s", cnt[1],
                         c.mixed && c.idx->shadow.kind == kShadowF16 ? " or values beyond the fp16 range" : "");
         if (cnt[0] == 0) break;
         if (round >= 64) return fail(HS_EHIP, "result pool still overflowing after %d rounds", round);
+        if (lost) fused = true;
         HIP_TRY(launch_emit(ix, sp, true, ws, st));
         hipError_t e = timer ? timer->begin(st, HS_PROF_FUSED) : hipSuccess;
-        if (e == hipSuccess) e = launch_leaf_scan(ix, sp, ws, c.idx->cus, c.form, st);
+        if (fused) {
+            if (e == hipSuccess) e = launch_leaf_scan(ix, sp, ws, c.idx->cus, c.form, st);
+        } else {
+            // every slice takes part (the LB_SAX filter over all of the round's items)
+            if (e == hipSuccess) e = launch_filter(ix, sp, ws, c.idx->cus, st);
+            if (e == hipSuccess) e = launch_slice_prefix(ws, st);
+            if (e == hipSuccess) e = launch_refine(ix, sp, ws, c.idx->cus, c.form, st);
+        }
         if (e == hipSuccess && timer) e = timer->end(st);
         HIP_TRY(e);
         HIP_TRY(launch_merge(ix, sp, true, ws, ids_dev, d2_dev, err_dev, c.err_rel, stats_out, st));

@@ -46,7 +46,8 @@ constexpr int kCtrOvf = 6;       // entries reserved in the overflow slice
 constexpr int kCtrOvfEnd = 7;    // smallest base of an overflow range that did not fit (UINT32_MAX if none):
                                  // overflow entries at or above it were never written
 constexpr int kCtrBound = 8;     // 8 slots: the bounding pass's work counter of each XCD
-constexpr int kNumCounters = 16;
+constexpr int kCtrLost = 16;     // queries of the last merge whose candidates were dropped
+constexpr int kNumCounters = 17;
 
 // Distance forms of the refinement (template argument F of the kernels that
 // refine): float32 sum in a fixed order, or compensated float32 (error-free

@@ -367,6 +367,7 @@ __global__ void __launch_bounds__(1024) k_merge(IndexView ix, ScanParams sp, int
         if (again) {
             nf |= kFlagRedo;
             atomicAdd(&ws.counters[kCtrRedo], 1u);
+            if (f & kFlagCandLost) atomicAdd(&ws.counters[kCtrLost], 1u);
         }
         ws.flags[q] = nf;
         ws.pool_cnt[q] = (uint32_t)u;
@@ -456,6 +457,10 @@ __global__ void k_arm_redo(QueryWs ws, int32_t Q) {
         ws.counters[kCtrItems] = 0;
         ws.counters[kCtrWork] = 0;
         ws.counters[kCtrRedo] = 0;
+        ws.counters[kCtrLost] = 0;
+        // the candidate list's overflow slice, for a round that refills it
+        ws.counters[kCtrOvf] = 0;
+        ws.counters[kCtrOvfEnd] = 0xffffffffu;
     }
     if (q >= Q) return;
     uint32_t f = ws.flags[q];
