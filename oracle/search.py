@@ -22,6 +22,15 @@ cannot enter the result:
   LB_SAX test; otherwise only the LB_SAX survivors are, each bound tested
   again against the current BSF_k.
 
+The same search also runs over the tree (``TreeIndex``, ``exact_knn_tree``):
+the approximate search and the candidate-leaf step take nodes from one
+priority queue ordered by LB_EAPCA, as Sec. 3.4 describes, with internal
+synopses made from their children's.  On one segmentation a parent's box
+contains its children's, so no node's bound exceeds a descendant's: leaves
+leave the queue in increasing bound order, and the tree picks the same seed
+and candidate leaves as sorting every leaf's own bound (ties broken by leaf
+position; the queue orders nodes by their first leaf's position too).
+
 Readings: the paper's tests are strict (LB < BSF_k, d < BSF_k), which can
 drop a series tied with the k-th; here a bound discards only when strictly
 greater, and a refined series enters R when its (d, id) precedes the k-th
@@ -95,30 +104,13 @@ def _refine_all(res: Results, q64, x, rows):
         res.offer(refine(q64, x[r], res.bsf), int(r))
 
 
-def exact_knn(index: LeafIndex, q: np.ndarray, k: int, l_max: int = 1,
-              eapca_th: float = 0.25, sax_th: float = 0.50, stats: dict | None = None):
-    """Exact k-NN of one query.  Returns (ids int64 [k], d2 float64 [k])."""
-    if k < 1 or k > index.x.shape[0]:
-        raise ValueError("k out of range")
-    q64 = np.asarray(q, dtype=np.float64)
+def _finish(index, q64, res: Results, L: int, seeded: list, kept: list, eapca_th: float, sax_th: float,
+            stats: dict | None):
+    """The search after the seed: LB_SAX filter or skip-sequential reading of
+    the kept leaves (in leaf order), then the result lists."""
     x, leaves = index.x, index.leaves
-    L = len(leaves)
-    res = Results(k)
     mu_q, sd_q = S.segment_stats(q64, index.ends)
     lb_leaf = S.lb_eapca(mu_q, sd_q, index.syn, index.ends)
-    by_bound = sorted(range(L), key=lambda i: (lb_leaf[i], i))
-
-    # initial BSF_k: the most promising leaves, refined in full
-    seeded = []
-    for leaf in by_bound[:l_max]:
-        if lb_leaf[leaf] > res.bsf:
-            break
-        _refine_all(res, q64, x, leaves[leaf])
-        seeded.append(leaf)
-    rest = by_bound[len(seeded):]
-
-    # the leaves LB_EAPCA cannot discard at this BSF_k, in leaf order
-    kept = sorted(leaf for leaf in rest if lb_leaf[leaf] <= res.bsf)
     leaf_pruned = 1.0 - len(kept) / L
 
     def read_whole_leaves():
@@ -148,6 +140,107 @@ def exact_knn(index: LeafIndex, q: np.ndarray, k: int, l_max: int = 1,
 
     if stats is not None:
         stats.update(dict(path=path, leaves=L, visited=len(seeded), lclist=len(kept),
-                          eapca_pr=leaf_pruned, sax_pr=series_pruned))
+                          eapca_pr=leaf_pruned, sax_pr=series_pruned, seeded=list(seeded), kept=list(kept)))
     ids = np.asarray([i if i is not None else -1 for i in res.id], dtype=np.int64)
     return ids, np.asarray(res.d, dtype=np.float64)
+
+
+def exact_knn(index: LeafIndex, q: np.ndarray, k: int, l_max: int = 1,
+              eapca_th: float = 0.25, sax_th: float = 0.50, stats: dict | None = None):
+    """Exact k-NN of one query.  Returns (ids int64 [k], d2 float64 [k])."""
+    if k < 1 or k > index.x.shape[0]:
+        raise ValueError("k out of range")
+    q64 = np.asarray(q, dtype=np.float64)
+    x, leaves = index.x, index.leaves
+    L = len(leaves)
+    res = Results(k)
+    mu_q, sd_q = S.segment_stats(q64, index.ends)
+    lb_leaf = S.lb_eapca(mu_q, sd_q, index.syn, index.ends)
+    by_bound = sorted(range(L), key=lambda i: (lb_leaf[i], i))
+
+    # initial BSF_k: the most promising leaves, refined in full
+    seeded = []
+    for leaf in by_bound[:l_max]:
+        if lb_leaf[leaf] > res.bsf:
+            break
+        _refine_all(res, q64, x, leaves[leaf])
+        seeded.append(leaf)
+    rest = by_bound[len(seeded):]
+
+    # the leaves LB_EAPCA cannot discard at this BSF_k, in leaf order
+    kept = sorted(leaf for leaf in rest if lb_leaf[leaf] <= res.bsf)
+    return _finish(index, q64, res, L, seeded, kept, eapca_th, sax_th, stats)
+
+
+class TreeIndex(LeafIndex):
+    """LeafIndex plus the tree above its leaves: each node's synopsis (a
+    leaf's over its series, an internal node's the union of its children's)
+    and the position of the first leaf under it."""
+
+    def __init__(self, x: np.ndarray, w: int, tau: int, card: int = 256):
+        super().__init__(x, w, tau, card)
+        self.nodes, _ = S.build_tree(self.x, w, tau)
+        nn = len(self.nodes)
+        self.node_syn = [None] * nn
+        self.first_leaf = [0] * nn
+        # children are appended after their parent: a reverse sweep is bottom-up
+        for v in range(nn - 1, -1, -1):
+            node = self.nodes[v]
+            if node["children"] is None:
+                self.node_syn[v] = self.syn[node["leaf"]]
+                self.first_leaf[v] = node["leaf"]
+            else:
+                a, b = node["children"]
+                self.node_syn[v] = S.union_synopsis(self.node_syn[a], self.node_syn[b])
+                self.first_leaf[v] = min(self.first_leaf[a], self.first_leaf[b])
+
+
+def exact_knn_tree(index: TreeIndex, q: np.ndarray, k: int, l_max: int = 1,
+                   eapca_th: float = 0.25, sax_th: float = 0.50, stats: dict | None = None):
+    """Exact k-NN of one query through the tree's priority queue: the
+    approximate search pops nodes in increasing LB_EAPCA until l_max leaves
+    are refined (a node whose bound exceeds BSF_k ends it), pushing the
+    children of internal nodes whose bound does not exceed BSF_k; the
+    candidate-leaf step resumes the same queue with BSF_k fixed and collects
+    the leaves it pops, sorted by leaf position.  Returns (ids, d2)."""
+    import heapq
+    if k < 1 or k > index.x.shape[0]:
+        raise ValueError("k out of range")
+    q64 = np.asarray(q, dtype=np.float64)
+    res = Results(k)
+    mu_q, sd_q = S.segment_stats(q64, index.ends)
+
+    def bound(v):
+        return float(S.lb_eapca(mu_q, sd_q, index.node_syn[v], index.ends))
+
+    pq = [(bound(0), index.first_leaf[0], 0)]
+
+    def expand(v):
+        for c in index.nodes[v]["children"]:
+            b = bound(c)
+            if b <= res.bsf:
+                heapq.heappush(pq, (b, index.first_leaf[c], c))
+
+    seeded = []
+    while len(seeded) < l_max and pq:
+        b, _, v = heapq.heappop(pq)
+        if b > res.bsf:
+            pq.clear()
+            break
+        node = index.nodes[v]
+        if node["children"] is None:
+            _refine_all(res, q64, index.x, index.leaves[node["leaf"]])
+            seeded.append(node["leaf"])
+        else:
+            expand(v)
+    kept = []
+    while pq:
+        b, _, v = heapq.heappop(pq)
+        if b > res.bsf:
+            break
+        node = index.nodes[v]
+        if node["children"] is None:
+            kept.append(node["leaf"])
+        else:
+            expand(v)
+    return _finish(index, q64, res, len(index.leaves), seeded, sorted(kept), eapca_th, sax_th, stats)

@@ -233,3 +233,45 @@ def build_leaves(x: np.ndarray, w: int, tau: int):
         stack.append(ids[~left])
         stack.append(ids[left])
     return leaves, ends
+
+
+def build_tree(x: np.ndarray, w: int, tau: int):
+    """The H-split tree itself (Sec. 3.2-3.3): the same splits as
+    ``build_leaves``, with the internal nodes kept.
+
+    Returns (nodes, ends).  nodes[0] is the root; each node is a dict with
+    ``ids`` (its series, ascending), ``children`` (indices of the left and
+    right child, or None for a leaf) and ``leaf`` (the leaf's position in
+    ``build_leaves``' in-order list, -1 for an internal node).
+    """
+    x = np.asarray(x)
+    n = x.shape[1]
+    ends = equal_segmentation(n, w)
+    mu, sd = segment_stats(x, ends)
+    nodes = [dict(ids=np.arange(x.shape[0], dtype=np.int64), children=None, leaf=-1)]
+    stack = [0]
+    n_leaves = 0
+    while stack:                      # depth-first, left child before right
+        v = stack.pop()
+        ids = nodes[v]["ids"]
+        pol = None if len(ids) <= tau else choose_split(mu[ids], sd[ids], ends)
+        if pol is None:
+            nodes[v]["leaf"] = n_leaves
+            n_leaves += 1
+            continue
+        i, st = pol
+        val = (mu if st == 0 else sd)[ids, i]
+        left = hsplit_goes_left(val, float(val.min()), float(val.max()))
+        nodes.append(dict(ids=ids[left], children=None, leaf=-1))
+        nodes.append(dict(ids=ids[~left], children=None, leaf=-1))
+        nodes[v]["children"] = (len(nodes) - 2, len(nodes) - 1)
+        stack.append(len(nodes) - 1)
+        stack.append(len(nodes) - 2)
+    return nodes, ends
+
+
+def union_synopsis(a: np.ndarray, b: np.ndarray) -> np.ndarray:
+    """A parent's synopsis from its children's (Sec. 3.3, HSplitSynopsis): per
+    segment the smallest minima and the largest maxima.  a, b: [m, 4]."""
+    return np.stack([np.minimum(a[:, 0], b[:, 0]), np.maximum(a[:, 1], b[:, 1]),
+                     np.minimum(a[:, 2], b[:, 2]), np.maximum(a[:, 3], b[:, 3])], axis=-1)

@@ -247,3 +247,20 @@ def test_build_leaves_partition():
         assert np.all(np.diff(l) > 0)
         z = S.synopsis(mu[l], sd[l])
         assert np.all(mu[l] >= z[:, 0]) and np.all(mu[l] <= z[:, 1])
+
+
+def test_build_tree_has_the_leaves_of_build_leaves():
+    from paper_2212_13297_amd import datagen as G
+    x = G.random_walks(3000, 64, coll=8)
+    leaves, ends = S.build_leaves(x, 8, 100)
+    nodes, ends2 = S.build_tree(x, 8, 100)
+    np.testing.assert_array_equal(ends, ends2)
+    tree_leaves = sorted((nd["leaf"], nd["ids"]) for nd in nodes if nd["children"] is None)
+    assert [p for p, _ in tree_leaves] == list(range(len(leaves)))
+    for (p, ids), ref in zip(tree_leaves, leaves):
+        np.testing.assert_array_equal(ids, ref)
+    # every internal node's series are its children's, split without loss
+    for nd in nodes:
+        if nd["children"] is not None:
+            a, b = nd["children"]
+            np.testing.assert_array_equal(np.sort(np.concatenate([nodes[a]["ids"], nodes[b]["ids"]])), nd["ids"])
