@@ -22,7 +22,8 @@
 namespace hs {
 namespace {
 
-constexpr int kRefineSlots = 1;  // candidates in flight per 4-lane group
+constexpr int kRefineLanes = 4;  // lanes per series
+constexpr int kRefineSlots = 1;  // candidates in flight per group
 constexpr int kSeg = 512;        // candidates per segment of a long list (a multiple of 64, >= 128)
 constexpr uint32_t kNaturalPerm = 0xE4u;  // quarters 0, 1, 2, 3
 
@@ -128,21 +129,23 @@ __device__ __forceinline__ uint4 ring_entry(const Meta& m, bool ord, uint32_t& r
                       __float_as_uint(__double2float_rd(lb / (1.0 + kSlack))), 0x7f800000u);
 }
 
-// The partial of one 64-point chunk for a group of 4 lanes: lane j holds
-// points 4 (j + 4 i) .. + 3 for i = 0..3 (so each of the four loads of a
-// group reads 64 contiguous bytes).  The lane squares its 16 differences into
-// four accumulators (a chain of 4 each), adds them pairwise, and two quad
-// permutations sum the group.  A term passes through at most as many
-// roundings as in the 16-lane partial (4 in the chain, 2 in the pairwise
-// sum, 2 in the butterfly), so the abandoning margin holds unchanged.
-__device__ __forceinline__ float quad_partial(const float4 (&q)[4], const float4 (&x)[4]) {
+// The partial of one 64-point chunk for a group of LG lanes (4 or 8): lane j
+// holds points 4 (j + LG i) .. + 3 for i < 16 / LG (so each load of a group
+// reads 4 LG contiguous floats).  The lane squares its differences into four
+// accumulators (a chain of 16 / LG each), adds them pairwise, and log2(LG)
+// DPP steps sum the group.  A term passes through at most as many roundings
+// as in the 16-lane partial (at LG = 4: 4 in the chain, 2 pairwise, 2 in
+// the butterfly; at LG = 8: 2, 2 and 3), so the abandoning margin holds
+// unchanged.
+template <int LG>
+__device__ __forceinline__ float group_partial(const float4 (&q)[16 / LG], const float4 (&x)[16 / LG]) {
     float4 a;
     {
         const float t0 = q[0].x - x[0].x, t1 = q[0].y - x[0].y, t2 = q[0].z - x[0].z, t3 = q[0].w - x[0].w;
         a = make_float4(t0 * t0, t1 * t1, t2 * t2, t3 * t3);
     }
 #pragma unroll
-    for (int i = 1; i < 4; ++i) {
+    for (int i = 1; i < 16 / LG; ++i) {
         const float t0 = q[i].x - x[i].x, t1 = q[i].y - x[i].y, t2 = q[i].z - x[i].z, t3 = q[i].w - x[i].w;
         a.x = fmaf(t0, t0, a.x);
         a.y = fmaf(t1, t1, a.y);
@@ -152,23 +155,31 @@ __device__ __forceinline__ float quad_partial(const float4 (&q)[4], const float4
     float p = (a.x + a.y) + (a.z + a.w);
     p += row_xor<1>(p);
     p += row_xor<2>(p);
+    if (LG >= 8) p += row_xor<4>(p);
     return p;
 }
 
-// NS: candidates in flight per 4-lane group.
+// One bit per LG-lane group: its first lane.
+constexpr uint64_t group_heads(int lg) {
+    uint64_t m = 0ull;
+    for (int i = 0; i < 64; i += lg) m |= 1ull << i;
+    return m;
+}
+
+// LG: lanes per series (4 or 8).  NS: candidates in flight per group.
 //
 // A wavefront refines a stream of candidates: one contiguous range of a short
 // list, or segments of kSeg of a long one, its first by its index and each
 // next one from a counter when its ring reaches it (so wavefronts that meet
-// costly candidates take fewer segments).  Each of its 16 groups of 4 lanes
-// keeps NS slots; a round loads one 64-point chunk of every slot's series
+// costly candidates take fewer segments).  Each of its 64 / LG groups of LG
+// lanes keeps NS slots; a round loads one 64-point chunk of every slot's series
 // (and the query's chunk), adds the chunk's partial to the slot's running
 // distance, and retires the slots whose distance exceeds their limit
 // (abandoned) or whose series is complete.  Retired slots take the next
 // candidates of the stream at once, so every round reads NS useful chunks
-// per group however early candidates are abandoned.  With 4 lanes per series
-// the per-candidate bookkeeping (hand-out, order, cascade, limits) is spread
-// over 4 lanes instead of 16, and a round covers 16 NS series.
+// per group however early candidates are abandoned.  With few lanes per
+// series the per-candidate bookkeeping (hand-out, order, cascade, limits) is
+// spread over LG lanes instead of 16, and a round covers 64 / LG NS series.
 //
 // The running distance is plain float32 in any chunk order.  A series that
 // completes within its limit is read again for its result key, the
@@ -189,18 +200,20 @@ __device__ __forceinline__ float quad_partial(const float4 (&q)[4], const float4
 // Q1: one chunk per quarter in the chunk order (n = 256): the chunk index is a
 // field of the order word and the cascade's bounds shift out as it is read.
 // U: batch-union diagnostics (marks every (series, chunk) pair read).
-template <int NS, bool Q1, bool U>
+template <int LG, int NS, bool Q1, bool U>
 __global__ void __launch_bounds__(256, 4) k_refine(IndexView ix, ScanParams sp, QueryWs ws) {
+    static_assert(LG == 4 || LG == 8, "4 or 8 lanes per series");
     constexpr int kRing = 128;
-    constexpr int kGroups = 16;                           // 4-lane groups per wavefront
-    constexpr uint64_t kHeads = 0x1111111111111111ull;    // the first lane of every group
+    constexpr int kGroups = 64 / LG;                      // groups per wavefront
+    constexpr int kNV = 16 / LG;                          // float4 loads per lane per chunk
+    constexpr uint64_t kHeads = group_heads(LG);          // the first lane of every group
     static_assert(kGroups * NS <= 64, "a hand-out must stay within the ring's loaded half");
     __shared__ unsigned long long s_top[kTile / 64][HS_KMAX];
     // ring_entry of the stream's candidate v at v mod 128
     __shared__ uint4 s_ring[kTile / 64][kRing];
     __shared__ uint32_t s_rem[kTile / 64][kRing];  // the entries' rem (chunk_perm)
-    const int t = threadIdx.x, lane = t & 63, wave = t >> 6, sub = lane & 3, grp = lane >> 2;
-    const uint64_t below = ((1ull << (4 * grp)) - 1ull) & kHeads;  // heads of the lower groups
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6, sub = lane & (LG - 1), grp = lane / LG;
+    const uint64_t below = ((1ull << (LG * grp)) - 1ull) & kHeads;  // heads of the lower groups
     const int k = sp.k;
     const int nchunks = ix.stride / kChunk;
     // chunk order: quarters in the ring entry's order, chunks of a quarter in
@@ -256,11 +269,11 @@ __global__ void __launch_bounds__(256, 4) k_refine(IndexView ix, ScanParams sp, 
     uint32_t g_ref = 0u;  // < 2^31 candidates per wavefront
     unsigned long long g_ch = 0ull;
     auto flush_counters = [&]() {
-        // sum over the group heads (lanes 4 g): xor steps 4 .. 32 gather them in lane 0
+        // sum over the group heads (lanes LG g): xor steps LG .. 32 gather them in lane 0
         uint32_t r = sub == 0 ? g_ref : 0u;
         unsigned long long c = sub == 0 ? g_ch : 0ull;
 #pragma unroll
-        for (int o = 32; o >= 4; o >>= 1) {
+        for (int o = 32; o >= LG; o >>= 1) {
             r += __shfl_xor(r, o, 64);
             c += __shfl_xor(c, o, 64);
         }
@@ -421,7 +434,7 @@ __global__ void __launch_bounds__(256, 4) k_refine(IndexView ix, ScanParams sp, 
         if (!__ballot(any)) break;
         // one chunk of every slot's series (its next in the slot's order);
         // empty slots read a chunk of row 0
-        float4 xa[NS][4], qa[NS][4];
+        float4 xa[NS][kNV], qa[NS][kNV];
 #pragma unroll
         for (int s = 0; s < NS; ++s) {
             const int c = Q1    ? (int)((sperm[s] >> (2 * sc[s])) & 3u)
@@ -430,9 +443,9 @@ __global__ void __launch_bounds__(256, 4) k_refine(IndexView ix, ScanParams sp, 
             const float* xb = xp[s] + c * kChunk;
             const float* qb = qp[s] + c * kChunk;
 #pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                xa[s][i] = *reinterpret_cast<const float4*>(xb + 16 * i);
-                qa[s][i] = *reinterpret_cast<const float4*>(qb + 16 * i);
+            for (int i = 0; i < kNV; ++i) {
+                xa[s][i] = *reinterpret_cast<const float4*>(xb + 4 * LG * i);
+                qa[s][i] = *reinterpret_cast<const float4*>(qb + 4 * LG * i);
             }
             if (U && sq[s] >= 0 && sub == 0) {
                 const int64_t bit = (int64_t)spos[s] * nchunks + c;
@@ -446,7 +459,7 @@ __global__ void __launch_bounds__(256, 4) k_refine(IndexView ix, ScanParams sp, 
             adm[s] = false;
             fin[s] = false;
             if (sq[s] >= 0) {
-                sd[s] += quad_partial(qa[s], xa[s]);
+                sd[s] += group_partial<LG>(qa[s], xa[s]);
                 sc[s] += 1;
                 // cascade: after the first and the second quarter, the bounds of
                 // the quarters still unread are added to the running distance
@@ -516,9 +529,9 @@ __global__ void __launch_bounds__(256, 4) k_refine(IndexView ix, ScanParams sp, 
                     v = key_distance(rows16 + (uint64_t)kpos * (uint32_t)ix.stride,
                                      qrow16 + (uint64_t)(uint32_t)kq * (uint32_t)ix.stride, nchunks);
                 // the group whose head is the j-th of the batch takes row j's value
-                const int j = __popcll(batch & ((1ull << (4 * grp)) - 1ull));
+                const int j = __popcll(batch & ((1ull << (LG * grp)) - 1ull));
                 const float vj = __shfl(v, 16 * min(j, 3), 64);
-                if ((batch >> (4 * grp)) & 1ull) {
+                if ((batch >> (LG * grp)) & 1ull) {
                     kv[s] = vj;
                     sc[s] += nchunks;  // chunks read again
                 }
@@ -537,7 +550,7 @@ __global__ void __launch_bounds__(256, 4) k_refine(IndexView ix, ScanParams sp, 
                     flush_counters();
                     st_q = kq;
                 }
-                if (grp == (l >> 2)) {
+                if (grp == l / LG) {
                     g_ref += 1u;
                     g_ch += (unsigned long long)sc[s];
                 }
@@ -587,9 +600,11 @@ __global__ void __launch_bounds__(256, 4) k_refine(IndexView ix, ScanParams sp, 
 hipError_t launch_refine(const IndexView& ix, const ScanParams& sp, const QueryWs& ws, int device_cus, int form,
                          hipStream_t st) {
     (void)form;
-#define HS_REFINE(QQ, UU)                                                                                        \
-    k_refine<kRefineSlots, QQ, UU><<<dim3(resident_grid(k_refine<kRefineSlots, QQ, UU>, kTile, 0, device_cus)), \
-                                     dim3(kTile), 0, st>>>(ix, sp, ws)
+#define HS_REFINE(QQ, UU)                                                                     \
+    do {                                                                                      \
+        auto kern = k_refine<kRefineLanes, kRefineSlots, QQ, UU>;                             \
+        hipLaunchKernelGGL(kern, dim3(resident_grid(kern, kTile, 0, device_cus)), dim3(kTile), 0, st, ix, sp, ws); \
+    } while (0)
     const bool q1 = sp.order_lg == 0;
     if (ws.ubits) {
         if (q1) HS_REFINE(true, true);
