@@ -250,7 +250,15 @@ __global__ void __launch_bounds__(256, 4) k_filter(IndexView ix, ScanParams sp, 
                         const float gs = fmaxf(0.0f, fmaxf(ez - qs.w, qs.z - ew));
                         term = lseg * (gm * gm + gs * gs);
                     }
-                    for (int sh = L >> 1; sh > 0; sh >>= 1) term += __shfl_xor(term, sh, 64);
+                    // butterfly over the test's L lanes: DPP moves within a row of 16
+                    // (xor 1 and 2 first, so the mirrors for 4 and 8 are exact), a
+                    // shuffle across rows only when w > 16 (L is uniform)
+                    if (L >= 2) term += row_xor<1>(term);
+                    if (L >= 4) term += row_xor<2>(term);
+                    if (L >= 8) term += row_xor<4>(term);
+                    if (L >= 16) term += row_xor<8>(term);
+                    if (L >= 32) term += __shfl_xor(term, 16, 64);
+                    if (L >= 64) term += __shfl_xor(term, 32, 64);
                     const bool live = valid && head_lane && term <= thr;
                     o.tests += (unsigned long long)__popcll(__ballot(valid && head_lane));
                     if (U && valid && head_lane) {
