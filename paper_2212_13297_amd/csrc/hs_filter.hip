@@ -16,7 +16,18 @@ namespace {
 
 constexpr int kWaves = kTile / 64;  // wavefronts per workgroup
 constexpr int kWin = 256;           // items per window
-constexpr int kBatch = 6;           // chunks whose words one wavefront loads together
+// Chunks whose words one wavefront loads together, and the kernel's
+// occupancy target: with one 16-byte word per series, 4 chunks at 5
+// wavefronts per SIMD (9 registers spilled) beat 6 chunks at 4 (1.78 against
+// 1.84 ms on 10M x 256); longer words keep 6 chunks at 4.
+template <int W16>
+constexpr int batch_chunks() {
+    return W16 == 1 ? 4 : 6;
+}
+template <int W16>
+constexpr int filter_occupancy() {
+    return W16 == 1 ? 5 : 4;
+}
 constexpr int kQueue = 128;         // live-chunk queue per wavefront (power of two)
 constexpr int kUnit = 16;           // most items per unit of work
 
@@ -34,7 +45,7 @@ struct FilterOut {
     bool lost;
 };
 
-// LB_SAX of up to kBatch queued chunks (rows [r0, r1) each, r1 - r0 <= 64)
+// LB_SAX of up to batch_chunks<W16>() queued chunks (rows [r0, r1) each, r1 - r0 <= 64)
 // and the wavefront's survivors.  Lane l takes series r0 + l of every chunk;
 // the word loads of all chunks are issued before the first table lookup, and
 // rows past a chunk (or slots past the batch) load zeros from no memory.
@@ -46,6 +57,7 @@ __device__ __forceinline__ void filter_batch(const IndexView& ix, const QueryWs&
                                              uint32_t head, int nb, int q, float thr, bool skip,
                                              const float* s_lut, int lane, FilterOut& o) {
     const uint32_t wb = (uint32_t)ix.wstride;
+    constexpr int kBatch = batch_chunks<W16>();
     uint32_t r0[kBatch], r1[kBatch];
     uint4 v[kBatch][W16];
 #pragma unroll
@@ -134,11 +146,12 @@ __device__ __forceinline__ void filter_batch(const IndexView& ix, const QueryWs&
 // time (a test spans L = pow2 >= w lanes, one segment each, so a load covers
 // 64 / L chunks); LB_EAPCA is float32 over outward-rounded intervals, summed
 // over the L lanes by a butterfly.  Chunks that pass join the wavefront's
-// queue in LDS, and every kBatch queued chunks go through filter_batch, so
+// queue in LDS, and every batch_chunks<W16>() queued chunks go through filter_batch, so
 // the LB_SAX work comes in full batches whatever fraction of chunks pass.
 // U: batch-union diagnostics (marks the envelopes tested and the words read).
 template <int W16, bool U>
-__global__ void __launch_bounds__(256, 4) k_filter(IndexView ix, ScanParams sp, QueryWs ws) {
+__global__ void __launch_bounds__(256, filter_occupancy<W16>()) k_filter(IndexView ix, ScanParams sp, QueryWs ws) {
+    constexpr int kBatch = batch_chunks<W16>();
     // the table first, at a fixed LDS address, so its row offsets fold into
     // the lookups' immediate offsets
     __shared__ float s_lut[lut_floats<W16>()];  // [16 W16][256], rows beyond w zero

@@ -583,8 +583,8 @@ __global__ void __launch_bounds__(256, 4) k_refine(IndexView ix, ScanParams sp, 
                 }
             }
         }
-        cur_q = __shfl(new_q, 0, 64);
-        lk = __shfl(new_lk, 0, 64);
+        cur_q = __builtin_amdgcn_readlane(new_q, 0);
+        lk = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(new_lk), 0));
 #pragma unroll
         for (int s = 0; s < NS; ++s)
             if (sq[s] == cur_q) sthr[s] = fminf(sthr[s], lk * marg);
