@@ -309,6 +309,29 @@ def test_overflow_fallback_rounds():
     idx.close()
 
 
+def test_pool_overflow_round_takes_the_main_path():
+    # No seed (l_max = 0) and k = 128: BSF_k is +inf while the first round
+    # filters, so every series is a candidate, and every wavefront run appends
+    # up to 128 entries: the 4096-entry result pools overflow.  The list has
+    # room for every series (8N entries per query: a wavefront's private slice
+    # holds a few hundred, the shared overflow slice the rest), so no
+    # candidate is dropped and the second round runs the filter, list and
+    # refine again with the merged bound: its LB_SAX survivors are counted on
+    # top of the first round's N (the fused scan, which needs no list, counts
+    # none), and the answer equals the oracle.
+    N = 40_000
+    x, q = workload(N, 128, coll=15, per_level=1, ood=2)
+    idx = make_index(x, w=16, leaf_size=500, l_max=0, cand_per_query=8 * N)
+    ids, d2, st = run_knn(idx, q, 128, stats=True)
+    check_knn(x, q, 128, ids, d2)
+    rounds = st["rounds"].cpu().numpy()
+    cand = st["candidates"].cpu().numpy()
+    print(f"[pool] rounds {rounds.tolist()} candidates {cand.tolist()}", flush=True)
+    assert np.all(rounds >= 2)
+    assert np.all(cand[rounds >= 2] > N)
+    idx.close()
+
+
 def test_many_exact_duplicates_at_the_kth_distance():
     # 9,000 exact copies of one series (more than the 4096-entry result pool):
     # a query equal to it, or near it, has all of them at one distance.  The
