@@ -17,6 +17,9 @@ Written from Hercules (PVLDB 15(10), 2022):
 * LB_SAX and LB_EAPCA: Sec. 2 names both lower-bounding distances but does not
   print their formulas; the readings used here are the standard ones and are
   derived in the docstrings below.
+* Deviation codes (``sigma_codes``, ``lb_sax_sigma``): not in the paper; an
+  8-bit code of each segment's standard deviation adds LB_EAPCA's deviation
+  term to LB_SAX (derived below).
 
 Readings where the paper is silent (each one listed in the design notes):
 
@@ -103,6 +106,52 @@ def lb_sax(paa_q: np.ndarray, word: np.ndarray, beta: np.ndarray, n: int) -> np.
     above = np.where(paa_q > hi, paa_q - hi, 0.0)
     delta = below + above
     return (n / w) * (delta * delta).sum(axis=-1)
+
+
+# ------------------------------------------- deviation codes (an extension)
+#
+# Not in the paper: an 8-bit code per (series, segment) for the segment's
+# standard deviation, which adds the deviation term of LB_EAPCA (Sec. 2) to
+# LB_SAX.  Exactness does not depend on it; it only prunes more.
+
+def sigma_step(sd: np.ndarray, levels: int = 256) -> float:
+    """Code width h: the largest segment deviation spread over ``levels``
+    codes, widened by 2^-20 so that every deviation lies below levels * h."""
+    return float(np.max(sd)) * (1.0 + 2.0 ** -20) / levels if np.size(sd) else 1.0
+
+
+def sigma_codes(sd: np.ndarray, h: float, levels: int = 256) -> np.ndarray:
+    """Code of each segment deviation: c = floor(sd / h) (at most levels - 1),
+    so that c h <= sd < (c + 1) h."""
+    c = np.floor(np.asarray(sd, dtype=np.float64) / h).astype(np.int64)
+    return np.clip(c, 0, levels - 1).astype(np.uint8 if levels <= 256 else np.int32)
+
+
+def lb_sax_sigma(paa_q: np.ndarray, sd_q: np.ndarray, word: np.ndarray, code: np.ndarray, beta: np.ndarray,
+                 h: float, n: int) -> np.ndarray:
+    """Squared LB_SAX plus the deviation term:
+
+        lb^2 = (n / w) * sum_i [delta_i^2 + gamma_i^2]
+
+    delta_i as in ``lb_sax``; gamma_i the distance from the query's segment
+    deviation sd_q[i] to the code's interval [c_i h, (c_i + 1) h].  Valid
+    because, per segment of length l, sum (q - x)^2 = l [(mu_q - mu_x)^2 +
+    (sd_q - sd_x)^2 + 2 sd_q sd_x (1 - rho)] >= l [(mu_q - mu_x)^2 +
+    (sd_q - sd_x)^2] (rho <= 1, the inequality behind LB_EAPCA), with mu_x in
+    the symbol's region and sd_x in the code's interval.
+
+    paa_q, sd_q: [w]; word, code: [..., w] integers.  Returns [...] FP64.
+    """
+    paa_q = np.asarray(paa_q, dtype=np.float64)
+    sd_q = np.asarray(sd_q, dtype=np.float64)
+    w = paa_q.shape[-1]
+    word = np.asarray(word).astype(np.int64)
+    code = np.asarray(code).astype(np.float64)
+    lo, hi = beta[word], beta[word + 1]
+    delta = np.where(paa_q < lo, lo - paa_q, 0.0) + np.where(paa_q > hi, paa_q - hi, 0.0)
+    slo, shi = code * h, (code + 1.0) * h
+    gamma = np.where(sd_q < slo, slo - sd_q, 0.0) + np.where(sd_q > shi, sd_q - shi, 0.0)
+    return (n / w) * (delta * delta + gamma * gamma).sum(axis=-1)
 
 
 # -------------------------------------------------------------------- EAPCA

@@ -264,3 +264,64 @@ def test_build_tree_has_the_leaves_of_build_leaves():
         if nd["children"] is not None:
             a, b = nd["children"]
             np.testing.assert_array_equal(np.sort(np.concatenate([nodes[a]["ids"], nodes[b]["ids"]])), nd["ids"])
+
+
+# ------------------------------------------------------ deviation codes
+
+def test_sigma_codes_contain_the_deviation():
+    from paper_2212_13297_amd import datagen as G
+    x = G.random_walks(3000, 128, coll=41)
+    _, sd = S.segment_stats(x, S.equal_segmentation(128, 16))
+    h = S.sigma_step(sd)
+    c = S.sigma_codes(sd, h).astype(np.float64)
+    assert np.all(c * h <= sd) and np.all(sd < (c + 1) * h)
+    assert c.max() == 255 and h * 256 > sd.max()
+
+
+@pytest.mark.parametrize("n,w", [(128, 16), (256, 16), (256, 32), (96, 8)])
+def test_lb_sax_sigma_is_a_lower_bound_above_lb_sax(n, w):
+    # against the exact squared distance of every pair (brute force), and
+    # never below LB_SAX of the same pair
+    from paper_2212_13297_amd import datagen as G
+    x = G.random_walks(1500, n, coll=42)
+    q, _, _ = G.workload(x, [1, 10], 3, coll=42)
+    q = np.concatenate([q, G.ood_queries(3, n, coll=42)])
+    beta = S.breakpoints(256)
+    ends = S.equal_segmentation(n, w)
+    words = S.sax_word(S.paa(x, w), beta)
+    _, sd = S.segment_stats(x, ends)
+    h = S.sigma_step(sd)
+    codes = S.sigma_codes(sd, h)
+    x64 = x.astype(np.float64)
+    for qi in q.astype(np.float64):
+        d = ((x64 - qi) ** 2).sum(1)
+        pq = S.paa(qi, w)
+        _, sq = S.segment_stats(qi, ends)
+        lb = S.lb_sax_sigma(pq, sq, words, codes, beta, h, n)
+        lbs = S.lb_sax(pq, words, beta, n)
+        assert np.all(lb <= d * (1 + 1e-12))
+        assert np.all(lb >= lbs)
+        assert np.mean(lb > lbs) > 0.5  # the deviation term adds something for most series
+
+
+def test_lb_sax_sigma_closed_forms():
+    # a series against itself: its symbols and codes contain its own PAA and
+    # deviations, so the bound is 0; a constant query (deviation 0 in every
+    # segment) against a series whose codes are c_i: the deviation term is
+    # (n/w) sum (c_i h)^2 on top of LB_SAX
+    from paper_2212_13297_amd import datagen as G
+    n, w = 128, 8
+    x = G.random_walks(200, n, coll=43)
+    beta = S.breakpoints(256)
+    ends = S.equal_segmentation(n, w)
+    words = S.sax_word(S.paa(x, w), beta)
+    _, sd = S.segment_stats(x, ends)
+    h = S.sigma_step(sd)
+    codes = S.sigma_codes(sd, h)
+    for i in range(0, 200, 37):
+        xi = x[i].astype(np.float64)
+        assert S.lb_sax_sigma(S.paa(xi, w), S.segment_stats(xi, ends)[1], words[i], codes[i], beta, h, n) == 0.0
+    qc = np.zeros(n)
+    lb = S.lb_sax_sigma(S.paa(qc, w), np.zeros(w), words, codes, beta, h, n)
+    extra = (n / w) * ((codes.astype(np.float64) * h) ** 2).sum(1)
+    np.testing.assert_allclose(lb, S.lb_sax(S.paa(qc, w), words, beta, n) + extra, rtol=1e-12, atol=0)
