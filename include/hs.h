@@ -101,6 +101,9 @@ typedef struct {
     int64_t max_leaf;    /* largest leaf (series) */
     int64_t index_bytes; /* device bytes the index occupies */
     int64_t n_chunks;    /* 64-series chunks (each leaf cut from its first series) */
+    double sigma_step;   /* width h of the deviation codes: the std of segment i of a stored
+                            series lies in [c h, (c + 1) h], c its code (uint8, stored after the
+                            words in the same layout) */
 } hs_index_info;
 
 /*

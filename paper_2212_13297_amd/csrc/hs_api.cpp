@@ -240,6 +240,24 @@ int64_t leaf_budget(int64_t N, int64_t tau) {
     return std::min<int64_t>(N, 4 * ((N + tau - 1) / tau) + 1024);
 }
 
+float bits_to_float_host(uint32_t b) {
+    float f;
+    std::memcpy(&f, &b, sizeof f);
+    return f;
+}
+
+// Width h of the deviation codes: the largest segment std, widened by 2^-20
+// (the float32 statistics lie within an ulp of the FP64 ones), over 256
+// codes, rounded up to 16 significant bits so that c h and (c + 1) h are
+// exact in float32 for every code c.  All stds zero: h = 1.
+float sigma_step(float smax) {
+    const double hh = (double)smax * (1.0 + std::ldexp(1.0, -20)) / 256.0;
+    if (!(hh > 0.0) || !std::isfinite(hh)) return 1.0f;
+    int e = 0;
+    const double m = std::frexp(hh, &e);  // hh = m 2^e, m in [0.5, 1)
+    return (float)std::ldexp(std::ceil(m * 65536.0) / 65536.0, e);
+}
+
 // Byte offsets inside the caller's index memory (base may be NULL: sizes only).
 IndexLayout index_layout(int64_t N, const hs_params& p, char* base) {
     (void)base;
@@ -257,6 +275,7 @@ IndexLayout index_layout(int64_t N, const hs_params& p, char* base) {
     l.rows = take(rows_bytes);
     l.ids = take(N * 4);
     l.words = take(N * wstride);
+    l.sig = take(N * wstride);
     l.flag = take(256);
     l.beta = take((kCard + 1) * 4);
     l.leaf_start = take((l.leaf_budget + 1) * 8);
@@ -396,6 +415,8 @@ hs_status hs_build_begin(int64_t N, const hs_params* params, void* index_mem_dev
     ix.rows = (const float*)(base + lay.rows);
     ix.ids = (const uint32_t*)(base + lay.ids);
     ix.words = (const uint8_t*)(base + lay.words);
+    ix.sig = (const uint8_t*)(base + lay.sig);
+    ix.sig_h = 1.0f;
     idx->index_bytes = need;
     idx->beta_dev = (float*)(base + lay.beta);
     idx->leaf_start_dev = (int64_t*)(base + lay.leaf_start);
@@ -410,7 +431,8 @@ hs_status hs_build_begin(int64_t N, const hs_params* params, void* index_mem_dev
     b->st_dev = partition_stats_buffer(b->scratch, N, p.w, p.leaf_size, lay.leaf_budget);
     // until the rows arrive, the words' area holds each series' stored position
     b->pos = (uint32_t*)ix.words;
-    const hipError_t e = hipMemsetAsync(b->bad, 0, sizeof(uint32_t), b->st);
+    // flag area: [0] NaN / Inf seen, [1] largest segment std (float bits)
+    const hipError_t e = hipMemsetAsync(b->bad, 0, 2 * sizeof(uint32_t), b->st);
     if (e != hipSuccess) {
         delete idx;
         delete b;
@@ -441,10 +463,14 @@ hs_status hs_build_partition(hs_builder* b) {
     const int64_t N = ix.N;
     hipStream_t st = b->st;
     if (b->stage != 0 || b->next_row != N) return fail(HS_EINVAL, "the statistics of all N rows come first");
-    uint32_t bad = 0;
-    HIP_TRY(hipMemcpyAsync(&bad, b->bad, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
+    // the deviation codes' width, from the largest segment std (the
+    // statistics are overwritten by the rows later)
+    HIP_TRY(launch_max_sigma(b->st_dev, N * p.w, b->bad + 1, st));
+    uint32_t flags[2] = {0, 0};
+    HIP_TRY(hipMemcpyAsync(flags, b->bad, sizeof flags, hipMemcpyDeviceToHost, st));
     HIP_TRY(hipStreamSynchronize(st));
-    if (bad) return fail(HS_EINVAL, "x contains NaN or Inf");
+    if (flags[0]) return fail(HS_EINVAL, "x contains NaN or Inf");
+    ix.sig_h = sigma_step(bits_to_float_host(flags[1]));
 
     // leaf partition: on the device, or on the host (the reference the
     // device partition is tested against)
@@ -561,7 +587,7 @@ hs_status hs_build_finish(hs_builder* b, hs_index** out) {
     const IndexView& ix = idx->view;
     if (b->stage != 1 || b->next_row != ix.N) return fail(HS_EINVAL, "the rows of all N series come first");
     hipStream_t st = b->st;
-    HIP_TRY(launch_words(ix, (uint8_t*)ix.words, st));
+    HIP_TRY(launch_words(ix, (uint8_t*)ix.words, (uint8_t*)ix.sig, st));
     HIP_TRY(launch_envelopes(ix, idx->leaf_start_dev, ix.L, idx->env_dev, st));
     HIP_TRY(launch_envelopes(ix, idx->chunk_start_dev, ix.chunks, idx->cenv_dev, st));
     HIP_TRY(hipStreamSynchronize(st));
@@ -610,6 +636,7 @@ hs_status hs_get_info(const hs_index* idx, hs_index_info* out) {
     out->max_leaf = idx->max_leaf;
     out->index_bytes = idx->index_bytes;
     out->n_chunks = idx->view.chunks;
+    out->sigma_step = (double)idx->view.sig_h;
     return HS_OK;
 }
 

@@ -3,7 +3,10 @@
 //                 from which the partition chooses the leaf splits
 //   gather_rows   leaf-ordered, zero-padded copy of the series
 //   words         iSAX symbol per (series, segment): FP64 PAA against the
-//                 float32 Gaussian breakpoints
+//                 float32 Gaussian breakpoints; with it the deviation code,
+//                 the segment's FP64 std in units of the code width
+//                 (not in the paper: it adds LB_EAPCA's deviation term to
+//                 LB_SAX in the filter)
 //   envelopes     per (leaf, segment) min/max of mean and std, rounded
 //                 outward to float32 so they contain the FP64 statistics
 #include "hs_device.h"
@@ -66,7 +69,7 @@ __global__ void k_scatter_rows(const float* __restrict__ x, int64_t row0, int64_
     }
 }
 
-__global__ void k_words(IndexView ix, uint8_t* __restrict__ words) {
+__global__ void k_words(IndexView ix, uint8_t* __restrict__ words, uint8_t* __restrict__ sig) {
     __shared__ float s_beta[kCard + 1];
     for (int j = threadIdx.x; j <= kCard; j += blockDim.x) s_beta[j] = ix.beta[j];
     __syncthreads();
@@ -78,12 +81,24 @@ __global__ void k_words(IndexView ix, uint8_t* __restrict__ words) {
         const int32_t seg = (int32_t)(t - pos * ix.wstride);
         if (seg >= ix.w) {
             words[pos * ix.wstride + seg] = 0;
+            sig[pos * ix.wstride + seg] = 0;
             continue;
         }
         const float* p = ix.rows + pos * ix.stride + (int64_t)seg * l;
         double s = 0.0;
         for (int j = 0; j < l; ++j) s += (double)p[j];
         const double paa = s / l;
+        double ss = 0.0;
+        for (int j = 0; j < l; ++j) {
+            const double d = (double)p[j] - paa;
+            ss += d * d;
+        }
+        // code c with c h <= std < (c + 1) h (c h is exact in FP64: 9 by 16 bits)
+        const double sd = sqrt(ss / l), h = (double)ix.sig_h;
+        int c = (int)fmin(255.0, floor(sd / h));
+        if (c > 0 && (double)c * h > sd) --c;
+        if (c < 255 && (double)(c + 1) * h <= sd) ++c;
+        sig[pos * ix.wstride + seg] = (uint8_t)c;
         // symbol = #{j in 1..255 : beta_j <= paa}: upper bound over beta[1..255]
         int lo = 1, hi = kCard;  // answer index in [1, 256]; symbol = index - 1
         while (lo < hi) {
@@ -142,6 +157,16 @@ __global__ void __launch_bounds__(256) k_envelopes(IndexView ix, const int64_t* 
     }
 }
 
+// Largest std of the statistics: non-negative floats order as their bits.
+__global__ void __launch_bounds__(256) k_max_sigma(const float2* __restrict__ stats, int64_t count,
+                                                   uint32_t* out) {
+    uint32_t m = 0u;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < count; i += (int64_t)gridDim.x * blockDim.x)
+        m = max(m, __float_as_uint(fmaxf(stats[i].y, 0.0f)));
+    for (int o = 32; o > 0; o >>= 1) m = max(m, (uint32_t)__shfl_xor((int)m, o, 64));
+    if ((threadIdx.x & 63) == 0 && m) atomicMax(out, m);
+}
+
 // Read-stream probe: every thread reads 16-byte units in a grid-stride loop,
 // eight in flight, and folds them into a word that is stored only if it
 // equals a fixed constant (so the loads stay but practically nothing is
@@ -195,8 +220,13 @@ hipError_t launch_scatter_rows(const float* x, int64_t row0, int64_t count, cons
     return hipGetLastError();
 }
 
-hipError_t launch_words(const IndexView& ix, uint8_t* words, hipStream_t st) {
-    hipLaunchKernelGGL(k_words, dim3(grid_for(ix.N * ix.wstride, 256)), dim3(256), 0, st, ix, words);
+hipError_t launch_words(const IndexView& ix, uint8_t* words, uint8_t* sig, hipStream_t st) {
+    hipLaunchKernelGGL(k_words, dim3(grid_for(ix.N * ix.wstride, 256)), dim3(256), 0, st, ix, words, sig);
+    return hipGetLastError();
+}
+
+hipError_t launch_max_sigma(const float2* stats, int64_t count, uint32_t* out, hipStream_t st) {
+    hipLaunchKernelGGL(k_max_sigma, dim3(grid_for(count, 256, 4096)), dim3(256), 0, st, stats, count, out);
     return hipGetLastError();
 }
 

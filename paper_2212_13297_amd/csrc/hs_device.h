@@ -130,6 +130,12 @@ __device__ __forceinline__ uint32_t pack_quarters(float a0, float a1, float a2, 
     return __builtin_amdgcn_perm(h23, h01, 0x07050301u);  // bytes 1, 3 of h01, then of h23
 }
 
+// The value a byte of the packed quarter bounds stands for (at most the
+// float32 value it was packed from).
+__device__ __forceinline__ float quarter_value(uint32_t byte) {
+    return (float)__builtin_bit_cast(_Float16, (uint16_t)(byte << 8));
+}
+
 // Raw buffer loads.  A load whose offset lies past the resource's byte size
 // returns zeros and reads no memory, so a masked-out load is an ordinary
 // instruction with no traffic: loads need no branch around them, every load

@@ -17,16 +17,18 @@ namespace {
 constexpr int kWaves = kTile / 64;  // wavefronts per workgroup
 constexpr int kWin = 256;           // items per window
 // Chunks whose words one wavefront loads together, and the kernel's
-// occupancy target: with one 16-byte word per series, 4 chunks at 5
-// wavefronts per SIMD (9 registers spilled) beat 6 chunks at 4 (1.78 against
-// 1.84 ms on 10M x 256); longer words keep 6 chunks at 4.
+// occupancy target.  The deviation stage's queue (12 bytes per entry, 64
+// (chunks + 1) entries per wavefront) shares the LDS with the LB_SAX table:
+// one 16-byte word per series takes 4 chunks at 4 wavefronts per SIMD (40 KB
+// per workgroup); two words 3 chunks at 3 (166 registers, 52 KB); longer
+// words 3 chunks at 2.
 template <int W16>
 constexpr int batch_chunks() {
-    return W16 == 1 ? 4 : 6;
+    return W16 == 1 ? 4 : 3;
 }
 template <int W16>
 constexpr int filter_occupancy() {
-    return W16 == 1 ? 5 : 4;
+    return W16 == 1 ? 4 : (W16 == 2 ? 3 : 2);
 }
 constexpr int kQueue = 128;         // live-chunk queue per wavefront (power of two)
 constexpr int kUnit = 16;           // most items per unit of work
@@ -45,56 +47,16 @@ struct FilterOut {
     bool lost;
 };
 
-// LB_SAX of up to batch_chunks<W16>() queued chunks (rows [r0, r1) each, r1 - r0 <= 64)
-// and the wavefront's survivors.  Lane l takes series r0 + l of every chunk;
-// the word loads of all chunks are issued before the first table lookup, and
-// rows past a chunk (or slots past the batch) load zeros from no memory.
-// skip: the skip-sequential path, where every series is a candidate with
-// bound 0 and no word is read.  U: batch-union diagnostics (marks the series
-// whose words are read).
-template <int W16, bool U>
-__device__ __forceinline__ void filter_batch(const IndexView& ix, const QueryWs& ws, const uint2* queue,
-                                             uint32_t head, int nb, int q, float thr, bool skip,
-                                             const float* s_lut, int lane, FilterOut& o) {
-    const uint32_t wb = (uint32_t)ix.wstride;
-    constexpr int kBatch = batch_chunks<W16>();
-    uint32_t r0[kBatch], r1[kBatch];
-    uint4 v[kBatch][W16];
-#pragma unroll
-    for (int s = 0; s < kBatch; ++s) {
-        const uint2 e = queue[(head + s) & (kQueue - 1)];
-        r0[s] = __builtin_amdgcn_readfirstlane(e.x);
-        r1[s] = s < nb ? __builtin_amdgcn_readfirstlane(e.y) : r0[s];
-        const __amdgpu_buffer_rsrc_t rs =
-            buffer_rsrc(ix.words + (int64_t)r0[s] * wb, skip ? 0u : (r1[s] - r0[s]) * wb);
-#pragma unroll
-        for (int u = 0; u < W16; ++u) v[s][u] = buffer_load16(rs, (uint32_t)lane * wb + 16u * u);
-    }
+// Appends the lanes' candidates of NSL rows each (pos[s], pk[s] where bit s of
+// mask is set) to the wavefront's private slice, or to a reserved range of
+// the shared overflow slice once the private one is full.
+template <int NSL>
+__device__ __forceinline__ void emit_candidates(const QueryWs& ws, FilterOut& o, int lane, int q, uint32_t mask,
+                                                const uint32_t (&pos)[NSL], const uint32_t (&pk)[NSL]) {
     const uint64_t lt_mask = (1ull << lane) - 1ull;
-    uint32_t pk[kBatch];  // the bounds by quarters
-    uint32_t mask = 0;
-#pragma unroll
-    for (int s = 0; s < kBatch; ++s) {
-        pk[s] = 0u;
-        if (s < nb) {
-            float lb = 0.0f;
-            if (!skip) {
-                float a[4];
-                lb_sax_quarters<W16>(v[s], s_lut, a);
-                lb = (a[0] + a[1]) + (a[2] + a[3]);
-                pk[s] = pack_quarters(a[0], a[1], a[2], a[3]);
-            }
-            o.filt += r1[s] - r0[s];
-            if (U && !skip && (uint32_t)lane < r1[s] - r0[s]) {
-                const int64_t bit = ws.word_bit0 + (int64_t)(r0[s] + (uint32_t)lane);
-                atomicOr(&ws.ubits[bit >> 5], 1u << (bit & 31));
-            }
-            if ((uint32_t)lane < r1[s] - r0[s] && lb <= thr) mask |= 1u << s;
-        }
-    }
     uint32_t total = 0;
 #pragma unroll
-    for (int s = 0; s < kBatch; ++s) total += (uint32_t)__popcll(__ballot((mask >> s) & 1u));
+    for (int s = 0; s < NSL; ++s) total += (uint32_t)__popcll(__ballot((mask >> s) & 1u));
     if (total == 0) return;
     uint32_t* dpos = o.spos;
     uint32_t* dq = o.sq;
@@ -127,11 +89,11 @@ __device__ __forceinline__ void filter_batch(const IndexView& ix, const QueryWs&
         off = (uint32_t)b;
     }
 #pragma unroll
-    for (int s = 0; s < kBatch; ++s) {
+    for (int s = 0; s < NSL; ++s) {
         const uint64_t bal = __ballot((mask >> s) & 1u);
         if ((mask >> s) & 1u) {
             const uint32_t slot = off + (uint32_t)__popcll(bal & lt_mask);
-            dpos[slot] = r0[s] + (uint32_t)lane;
+            dpos[slot] = pos[s];
             dq[slot] = (uint32_t)q;
             dpart[slot] = pk[s];
         }
@@ -139,6 +101,163 @@ __device__ __forceinline__ void filter_batch(const IndexView& ix, const QueryWs&
     }
     if (own) o.cnt += total;
     o.cand += total;
+}
+
+// The deviation stage for the first m (<= 64) of the wavefront's queued
+// LB_SAX survivors (position, LB_SAX, LB_SAX by quarters packed): lane l
+// loads series sq_pos[l]'s deviation codes and adds the deviation term
+// (segment length x the squared distance from the query's std interval to
+// the code's interval [c h, (c + 1) h], both ends exact in float32) to the
+// bound and to each packed quarter (whose stored values are lower bounds),
+// and keeps the series when the bound does not exceed thr.  s_qst holds
+// zeros for segments past w.
+template <int W16>
+__device__ __forceinline__ void sigma_stage(const IndexView& ix, const QueryWs& ws, const uint32_t* sq_pos,
+                                            const float* sq_lb, const uint32_t* sq_pk, int m, int q, float thr,
+                                            const float4* s_qst, int lane, FilterOut& o) {
+    constexpr int kQ = 4 * W16;
+    const bool valid = lane < m;
+    const int e = valid ? lane : 0;
+    const uint32_t pos = sq_pos[e], pk0 = sq_pk[e];
+    const float lb0 = sq_lb[e];
+    uint4 c[W16];
+    load_word<W16>(ix.sig + (int64_t)pos * ix.wstride, c);
+    const float h = ix.sig_h, lseg = (float)(ix.n / ix.w);
+    float a[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+    for (int u = 0; u < W16; ++u) {
+        const uint32_t parts[4] = {c[u].x, c[u].y, c[u].z, c[u].w};
+#pragma unroll
+        for (int p = 0; p < 4; ++p) {
+#pragma unroll
+            for (int b = 0; b < 4; ++b) {
+                const int i = u * 16 + p * 4 + b;
+                const float code = (float)((parts[p] >> (8 * b)) & 0xffu);
+                const float4 qs = s_qst[i];
+                const float gap = fmaxf(0.0f, fmaxf(code * h - qs.w, qs.z - (code + 1.0f) * h));
+                a[i / kQ] += lseg * gap * gap;
+            }
+        }
+    }
+    const float lb = lb0 + ((a[0] + a[1]) + (a[2] + a[3]));
+#pragma unroll
+    for (int p = 0; p < 4; ++p) a[p] += quarter_value((pk0 >> (8 * p)) & 0xffu);
+    const uint32_t posv[1] = {pos}, pkv[1] = {pack_quarters(a[0], a[1], a[2], a[3])};
+    emit_candidates<1>(ws, o, lane, q, (valid && lb <= thr) ? 1u : 0u, posv, pkv);
+}
+
+// The wavefront's queue of LB_SAX survivors waiting for the deviation stage.
+struct SigQueue {
+    uint32_t* pos;
+    float* lb;
+    uint32_t* pk;
+    uint32_t cnt;  // entries (uniform)
+};
+
+// Runs the deviation stage on the queued survivors 64 at a time; with
+// flush, also on the last fewer than 64.  The rest move to the queue's front.
+template <int W16>
+__device__ __forceinline__ void drain_sigma(const IndexView& ix, const QueryWs& ws, SigQueue& sq, bool flush, int q,
+                                            float thr, const float4* s_qst, int lane, FilterOut& o) {
+    uint32_t done = 0;
+    while (sq.cnt - done >= 64) {
+        sigma_stage<W16>(ix, ws, sq.pos + done, sq.lb + done, sq.pk + done, 64, q, thr, s_qst, lane, o);
+        done += 64;
+    }
+    const uint32_t rem = sq.cnt - done;
+    if (flush && rem) {
+        sigma_stage<W16>(ix, ws, sq.pos + done, sq.lb + done, sq.pk + done, (int)rem, q, thr, s_qst, lane, o);
+        sq.cnt = 0;
+        return;
+    }
+    if (done) {
+        // rem < 64 <= done: the source and destination ranges do not overlap
+        const bool mv = (uint32_t)lane < rem;
+        const uint32_t a = mv ? sq.pos[done + lane] : 0u, c = mv ? sq.pk[done + lane] : 0u;
+        const float b = mv ? sq.lb[done + lane] : 0.0f;
+        __builtin_amdgcn_wave_barrier();
+        if (mv) {
+            sq.pos[lane] = a;
+            sq.lb[lane] = b;
+            sq.pk[lane] = c;
+        }
+        __builtin_amdgcn_wave_barrier();
+    }
+    sq.cnt = rem;
+}
+
+// LB_SAX of up to batch_chunks<W16>() queued chunks (rows [r0, r1) each, r1 - r0 <= 64).
+// Lane l takes series r0 + l of every chunk; the word loads of all chunks
+// are issued before the first table lookup, and rows past a chunk (or slots
+// past the batch) load zeros from no memory.  The survivors (position,
+// LB_SAX, quarters) join the wavefront's deviation queue sq (fewer than 64
+// entries on entry, so it holds at most 63 + 64 kBatch), which is drained 64
+// at a time.
+// skip: the skip-sequential path, where every series is a candidate with
+// bound 0 and no word is read.  U: batch-union diagnostics (marks the series
+// whose words are read).
+template <int W16, bool U>
+__device__ __forceinline__ void filter_batch(const IndexView& ix, const QueryWs& ws, const uint2* queue,
+                                             uint32_t head, int nb, int q, float thr, bool skip,
+                                             const float* s_lut, const float4* s_qst, SigQueue& sq, int lane,
+                                             FilterOut& o) {
+    const uint32_t wb = (uint32_t)ix.wstride;
+    constexpr int kBatch = batch_chunks<W16>();
+    uint32_t r0[kBatch], r1[kBatch];
+    uint4 v[kBatch][W16];
+#pragma unroll
+    for (int s = 0; s < kBatch; ++s) {
+        const uint2 e = queue[(head + s) & (kQueue - 1)];
+        r0[s] = __builtin_amdgcn_readfirstlane(e.x);
+        r1[s] = s < nb ? __builtin_amdgcn_readfirstlane(e.y) : r0[s];
+        const __amdgpu_buffer_rsrc_t rs =
+            buffer_rsrc(ix.words + (int64_t)r0[s] * wb, skip ? 0u : (r1[s] - r0[s]) * wb);
+#pragma unroll
+        for (int u = 0; u < W16; ++u) v[s][u] = buffer_load16(rs, (uint32_t)lane * wb + 16u * u);
+    }
+    const uint64_t lt_mask = (1ull << lane) - 1ull;
+    uint32_t mask = 0;
+    uint32_t pos[kBatch], pk[kBatch];
+    float lbv[kBatch];
+#pragma unroll
+    for (int s = 0; s < kBatch; ++s) {
+        pos[s] = r0[s] + (uint32_t)lane;
+        pk[s] = 0u;
+        lbv[s] = 0.0f;
+        if (s < nb) {
+            float lb = 0.0f;
+            if (!skip) {
+                float a[4];
+                lb_sax_quarters<W16>(v[s], s_lut, a);
+                lb = (a[0] + a[1]) + (a[2] + a[3]);
+                pk[s] = pack_quarters(a[0], a[1], a[2], a[3]);
+                lbv[s] = lb;
+            }
+            o.filt += r1[s] - r0[s];
+            if (U && !skip && (uint32_t)lane < r1[s] - r0[s]) {
+                const int64_t bit = ws.word_bit0 + (int64_t)(r0[s] + (uint32_t)lane);
+                atomicOr(&ws.ubits[bit >> 5], 1u << (bit & 31));
+            }
+            if ((uint32_t)lane < r1[s] - r0[s] && lb <= thr) mask |= 1u << s;
+        }
+    }
+    if (skip) {
+        emit_candidates<kBatch>(ws, o, lane, q, mask, pos, pk);
+        return;
+    }
+#pragma unroll
+    for (int s = 0; s < kBatch; ++s) {
+        const uint64_t bal = __ballot((mask >> s) & 1u);
+        if ((mask >> s) & 1u) {
+            const uint32_t at = sq.cnt + (uint32_t)__popcll(bal & lt_mask);
+            sq.pos[at] = pos[s];
+            sq.lb[at] = lbv[s];
+            sq.pk[at] = pk[s];
+        }
+        sq.cnt += (uint32_t)__popcll(bal);
+    }
+    __builtin_amdgcn_wave_barrier();
+    drain_sigma<W16>(ix, ws, sq, false, q, thr, s_qst, lane, o);
 }
 
 // Every wavefront walks the items of the window; of item j's chunks it owns
@@ -156,6 +275,10 @@ __global__ void __launch_bounds__(256, filter_occupancy<W16>()) k_filter(IndexVi
     // the lookups' immediate offsets
     __shared__ float s_lut[lut_floats<W16>()];  // [16 W16][256], rows beyond w zero
     __shared__ uint2 s_queue[kWaves][kQueue];   // (r0, r1) of live chunks
+    // LB_SAX survivors waiting for the deviation stage
+    constexpr int kSigCap = 64 * (batch_chunks<W16>() + 1);
+    __shared__ uint32_t s_sq_pos[kWaves][kSigCap], s_sq_pk[kWaves][kSigCap];
+    __shared__ float s_sq_lb[kWaves][kSigCap];
     __shared__ uint32_t s_pb[kWin], s_pe[kWin], s_c0[kWin];
     __shared__ float4 s_qst[64];                // query segment mean / std intervals
     __shared__ int s_end;
@@ -175,6 +298,7 @@ __global__ void __launch_bounds__(256, filter_occupancy<W16>()) k_filter(IndexVi
     const uint32_t lane_eoff = (uint32_t)((lane_chunk * ix.w + seg) * 16);
     const uint32_t pass_eoff = (uint32_t)(kWaves * cpp * ix.w * 16);
     uint2* queue = s_queue[wave];
+    SigQueue sq{s_sq_pos[wave], s_sq_lb[wave], s_sq_pk[wave], 0u};
 
     const int64_t slice = (int64_t)sp.slice0 + (int64_t)blockIdx.x * kWaves + wave;
     FilterOut o{ws.slice_pos + slice * ws.slice_cap, ws.slice_q + slice * ws.slice_cap,
@@ -204,7 +328,8 @@ __global__ void __launch_bounds__(256, filter_occupancy<W16>()) k_filter(IndexVi
         }
         if (q != cur_q) {
             load_lut<W16>(s_lut, ws.lut + (int64_t)q * ix.w * kCard, ix.w, t, blockDim.x);
-            if (t < ix.w) s_qst[t] = ws.qst32[(int64_t)q * ix.w + t];
+            // zeros past w: the padding segments add nothing to the deviation term
+            if (t < 64) s_qst[t] = t < ix.w ? ws.qst32[(int64_t)q * ix.w + t] : make_float4(0.f, 0.f, 0.f, 0.f);
             cur_q = q;
         }
         __syncthreads();
@@ -236,7 +361,7 @@ __global__ void __launch_bounds__(256, filter_occupancy<W16>()) k_filter(IndexVi
                     tail += add;
                     __builtin_amdgcn_wave_barrier();
                     while (tail - head >= kBatch) {
-                        filter_batch<W16, U>(ix, ws, queue, head, kBatch, q, thr, true, s_lut, lane, o);
+                        filter_batch<W16, U>(ix, ws, queue, head, kBatch, q, thr, true, s_lut, s_qst, sq, lane, o);
                         head += kBatch;
                     }
                 }
@@ -287,14 +412,16 @@ __global__ void __launch_bounds__(256, filter_occupancy<W16>()) k_filter(IndexVi
                     tail += (uint32_t)__popcll(lm);
                     __builtin_amdgcn_wave_barrier();
                     while (tail - head >= kBatch) {
-                        filter_batch<W16, U>(ix, ws, queue, head, kBatch, q, thr, false, s_lut, lane, o);
+                        filter_batch<W16, U>(ix, ws, queue, head, kBatch, q, thr, false, s_lut, s_qst, sq, lane, o);
                         head += kBatch;
                     }
                 }
             }
         }
         if (tail != head)
-            filter_batch<W16, U>(ix, ws, queue, head, (int)(tail - head), q, thr, skip, s_lut, lane, o);
+            filter_batch<W16, U>(ix, ws, queue, head, (int)(tail - head), q, thr, skip, s_lut, s_qst, sq, lane, o);
+        // the window's last survivors, before the next window's query and table
+        drain_sigma<W16>(ix, ws, sq, true, q, thr, s_qst, lane, o);
         idx += m;
         if (lane == 0) {
             atomicAdd(&ws.stats[(int64_t)q * 8 + 1], skip ? 0ull : o.filt);

@@ -49,7 +49,7 @@ int64_t align_up(int64_t v, int64_t a);
 
 // Byte offsets of an index's arrays inside the caller's index memory.
 struct IndexLayout {
-    int64_t rows, ids, words, flag, beta, leaf_start, env, part_start, part_leaf, part_chunk, chunk_start, cenv;
+    int64_t rows, ids, words, sig, flag, beta, leaf_start, env, part_start, part_leaf, part_chunk, chunk_start, cenv;
     int64_t scratch;      // the build's scratch (the rows' area when it fits)
     int64_t total;
     int64_t leaf_budget;  // leaves the tables hold

@@ -76,6 +76,7 @@ struct IndexView {
     const float* rows;         // [N][stride] leaf-ordered series, zero padded
     const uint32_t* ids;       // [N] original row id of each stored series
     const uint8_t* words;      // [N][wstride] iSAX symbols
+    const uint8_t* sig;        // [N][wstride] deviation codes: segment std in [c sig_h, (c + 1) sig_h]
     const int64_t* leaf_start; // [L + 1]
     const float4* env;         // [L][w] (mu_min, mu_max, sd_min, sd_max), rounded outward
     const float* beta;         // [257] float32 breakpoints, beta[0] = -inf, beta[256] = +inf
@@ -88,6 +89,7 @@ struct IndexView {
     int64_t parts;
     int64_t chunks;
     int32_t n, w, stride, wstride;
+    float sig_h;               // width of a deviation code (at most 16 significant bits)
 };
 
 // Query-side workspace carved out of the caller's buffer.
@@ -176,7 +178,10 @@ hipError_t launch_inverse_ids(const uint32_t* ids, int64_t N, uint32_t* pos, hip
 // rows[pos[row0 + r]] = x[r] (zero padded to stride), r < count
 hipError_t launch_scatter_rows(const float* x, int64_t row0, int64_t count, const uint32_t* pos, int32_t n,
                                int32_t stride, float* rows, hipStream_t st);
-hipError_t launch_words(const IndexView& ix, uint8_t* words, hipStream_t st);
+hipError_t launch_words(const IndexView& ix, uint8_t* words, uint8_t* sig, hipStream_t st);
+// Largest segment standard deviation of the statistics (float2 (mean, std)
+// each, std >= 0) as float bits, by atomicMax into *out.
+hipError_t launch_max_sigma(const float2* st, int64_t count, uint32_t* out, hipStream_t st_);
 hipError_t launch_read_probe(const void* buf, int64_t bytes, uint32_t* sink, int device_cus, hipStream_t st);
 hipError_t launch_envelopes(const IndexView& ix, const int64_t* starts, int64_t count, float4* env,
                             hipStream_t st);

@@ -78,11 +78,6 @@ __device__ __forceinline__ Meta load_meta(const QueryWs& ws, long long c, bool v
 
 typedef _Float16 half2_t __attribute__((ext_vector_type(2)));
 
-// The value a byte of the packed quarter bounds stands for.
-__device__ __forceinline__ float quarter_value(uint32_t byte) {
-    return (float)__builtin_bit_cast(_Float16, (uint16_t)(byte << 8));
-}
-
 // The order in which a series' quarters are read: the largest partial bound
 // first, equal bounds in natural order.  Quarter j of the order sits in bits
 // 2j and 2j + 1.  The bytes of the packed bounds order as their values; the

@@ -39,7 +39,8 @@ class hs_params(ctypes.Structure):
 class hs_index_info(ctypes.Structure):
     _fields_ = [("n_series", ctypes.c_int64), ("n", ctypes.c_int32), ("w", ctypes.c_int32),
                 ("row_stride", ctypes.c_int32), ("word_stride", ctypes.c_int32), ("n_leaves", ctypes.c_int64),
-                ("max_leaf", ctypes.c_int64), ("index_bytes", ctypes.c_int64), ("n_chunks", ctypes.c_int64)]
+                ("max_leaf", ctypes.c_int64), ("index_bytes", ctypes.c_int64), ("n_chunks", ctypes.c_int64),
+                ("sigma_step", ctypes.c_double)]
 
 
 class hs_query_stats(ctypes.Structure):
@@ -530,6 +531,17 @@ class Index:
         words = self.mem[up(rb) + up(ib):up(rb) + up(ib) + N * info.word_stride].view(N, info.word_stride)
         ls, env = hs_get_leaves(self.h, info)
         return rows, ids, words, ls, env
+
+    def sigma_codes(self):
+        """The deviation codes ([N, word_stride] uint8 view, stored after the
+        words) and their width h."""
+        N, info = self.info.n_series, self.info
+
+        def up(v):
+            return (v + 255) // 256 * 256
+
+        at = up(N * info.row_stride * 4) + up(N * 4) + up(N * info.word_stride)
+        return self.mem[at:at + N * info.word_stride].view(N, info.word_stride), info.sigma_step
 
     def workspace(self, Q: int, k: int):
         import torch

@@ -94,6 +94,21 @@ def test_build_summaries_against_oracle():
         assert np.all(sd[a:b] >= e[:, 2]) and np.all(sd[a:b] <= e[:, 3])
         syn = S.synopsis(mu[a:b], sd[a:b])
         assert np.all(np.abs(syn - e) <= 1e-6 * (1 + np.abs(syn)))   # and are tight
+    # deviation codes: the width covers the largest std over 256 codes with at
+    # most 16 significant bits (so c h is exact in float32), every code's
+    # interval contains its FP64 std, and the codes equal the oracle's except
+    # where the std lies within 1e-9 relative of a code boundary
+    codes, h = idx.sigma_codes()
+    codes = codes.cpu().numpy()
+    assert h > 0 and 256 * h > sd.max() and 128 * h <= sd.max() * (1 + 1e-5)
+    m, e = np.frexp(h)
+    assert (m * 65536) == np.floor(m * 65536)
+    gc = codes[:, :w].astype(np.float64)
+    assert np.all(codes[:, w:] == 0)
+    assert np.all(gc * h <= sd) and np.all(sd < (gc + 1) * h)
+    oc = S.sigma_codes(sd, h).astype(np.float64)
+    for r, c in zip(*np.nonzero(oc != gc)):
+        assert abs(sd[r, c] / h - round(sd[r, c] / h)) < 1e-9 * (1 + sd[r, c] / h), (r, c, sd[r, c], gc[r, c])
     idx.close()
 
 
