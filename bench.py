@@ -191,10 +191,12 @@ def measure_plain(hs, torch, idx, qt, k, steps, warmup, w, wl, read_gbs):
     stats = {f: v.cpu().numpy().astype(np.int64) for f, v in st.items()}
     # per pair: what each (query, unit) pair reads (the seed step's series included)
     word_bytes = int(stats["rows_filtered"].sum()) * w + int(stats["chunks_tested"].sum()) * w * 16
+    sig_bytes = int(stats["rows_sigma"].sum()) * w  # deviation codes of the LB_SAX survivors
     cand_bytes = int(stats["candidates"].sum()) * 12
     raw_bytes = int(stats["chunks_read"].sum()) * 64 * 4
     # batch union: distinct (series, chunk) pairs the refine reads, distinct
-    # words and chunk envelopes the filter reads; candidate entries are per pair
+    # words and chunk envelopes the filter reads; deviation codes and candidate
+    # entries are counted per pair
     ust = {}
 
     def ucall():
@@ -202,8 +204,9 @@ def measure_plain(hs, torch, idx, qt, k, steps, warmup, w, wl, read_gbs):
 
     u_raw, u_words, u_env = hs.union_counts(idx, ucall)
     u_cand = int(ust["st"]["candidates"].sum().item()) * 12
-    union = {"filter": u_words * w + u_env * w * 16 + u_cand, "refine": u_raw * 256 + u_cand}
-    pair = {"filter": word_bytes + cand_bytes, "refine": raw_bytes + cand_bytes}
+    u_sig = int(ust["st"]["rows_sigma"].sum().item()) * w
+    union = {"filter": u_words * w + u_env * w * 16 + u_sig + u_cand, "refine": u_raw * 256 + u_cand}
+    pair = {"filter": word_bytes + sig_bytes + cand_bytes, "refine": raw_bytes + cand_bytes}
     log(f"batch union: {u_raw} raw chunk pairs, {u_words} words, {u_env} envelopes "
         f"(per pair: {stats['chunks_read'].sum()}, {stats['rows_filtered'].sum()}, {stats['chunks_tested'].sum()})")
     kern = {}
@@ -234,7 +237,7 @@ def measure_plain(hs, torch, idx, qt, k, steps, warmup, w, wl, read_gbs):
     env_union = info.n_leaves * w * 16              # leaf envelopes: read once per batch
     out_bytes = Q * k * 12
     path_union = union["filter"] + union["refine"] + env_union + out_bytes
-    path_pair = word_bytes + raw_bytes + Q * info.n_leaves * w * 16 + out_bytes
+    path_pair = word_bytes + sig_bytes + raw_bytes + Q * info.n_leaves * w * 16 + out_bytes
     if dom == "filter":
         kf = kern["filter"]
         roof = {**kf, "bound": "lds", "achieved": kf["lds_lookups_T_s"], "peak": LDS_PEAK_TLOOKUPS,
@@ -258,8 +261,9 @@ def measure_plain(hs, torch, idx, qt, k, steps, warmup, w, wl, read_gbs):
     return {
         "ids": ids, "d2": d2, "stats": stats, "ms_per_step": ms_per_step, "qps": qps, "kern": kern, "roofline": roof,
         "algorithmic_bytes_per_step": {"union": {"raw_chunk_pairs": u_raw, "words": u_words, "envelopes": u_env,
-                                                 "total": path_union},
-                                       "per_pair": {"words": word_bytes, "raw": raw_bytes, "total": path_pair}},
+                                                 "deviation_code_bytes": u_sig, "total": path_union},
+                                       "per_pair": {"words": word_bytes, "deviation_codes": sig_bytes,
+                                                    "raw": raw_bytes, "total": path_pair}},
         "path_frac_of_hbm_peak": round(path_union / (ms_per_step / 1000.0) / 1e9 / HBM_PEAK_GBS, 4),
         "path_frac_of_hbm_peak_per_pair": round(path_pair / (ms_per_step / 1000.0) / 1e9 / HBM_PEAK_GBS, 4),
     }
@@ -268,6 +272,7 @@ def measure_plain(hs, torch, idx, qt, k, steps, warmup, w, wl, read_gbs):
 def pruning_summary(stats, pct, levels):
     return {"leaves_kept_mean": float(stats["leaves_kept"].mean()),
             "rows_filtered_mean": float(stats["rows_filtered"].mean()),
+            "rows_sigma_mean": float(stats["rows_sigma"].mean()),
             "rows_refined_mean": float(stats["rows_refined"].mean()),
             "candidates_mean": float(stats["candidates"].mean()),
             "per_level_refined_mean": [float(stats["rows_refined"][pct == p].mean()) for p in levels],

@@ -203,13 +203,16 @@ typedef struct {
     uint64_t chunks_read;     /* 64-point chunks of raw values read (early abandoning stops early) */
     uint64_t path;            /* 0 = LB_SAX path, 1 = skip-sequential (no LB_SAX) */
     uint64_t rounds;          /* refinement rounds (1 unless the candidate pool overflowed) */
-    uint64_t candidates;      /* LB_SAX survivors put on the candidate list (two-stage path) */
+    uint64_t candidates;      /* series put on the candidate list (two-stage path): LB_SAX survivors
+                                 whose bound with the deviation term also stays within the threshold */
     uint64_t chunks_tested;   /* 64-series chunk envelopes whose LB_EAPCA was evaluated */
     uint64_t rows_bounded;    /* precision form: series of the low-precision copy whose matrix-core
                                  bound was evaluated for this query (0 in the plain form) */
     uint64_t bound_pairs;     /* precision form: series whose dot product with this query the matrix
                                  cores computed (every series of the parts its wavefront took,
                                  padding lanes counted with the wavefront's first query) */
+    uint64_t rows_sigma;      /* LB_SAX survivors whose deviation codes were read to add the
+                                 deviation term (two-stage path) */
 } hs_query_stats;
 
 /*

@@ -327,7 +327,7 @@ int64_t ws_layout(const hs_index* idx, int32_t Q, int32_t k, QueryWs* ws, char* 
     carve(cur, (void**)&w.flags, (int64_t)Q * 4);
     carve(cur, (void**)&w.kept, (int64_t)Q * 4);
     carve(cur, (void**)&w.pool, (int64_t)Q * P * 8);
-    carve(cur, (void**)&w.stats, (int64_t)Q * 64);
+    carve(cur, (void**)&w.stats, (int64_t)Q * kStatSlots * 8);
     carve(cur, (void**)&w.items, items * 8);
     carve(cur, (void**)&w.slice_pos, cand * 4);
     carve(cur, (void**)&w.slice_q, cand * 4);

@@ -15,7 +15,7 @@ namespace hs {
 namespace {
 
 constexpr int kWaves = kTile / 64;  // wavefronts per workgroup
-constexpr int kWin = 256;           // items per window
+constexpr int kUnit = 16;           // most items per unit of work (and per window)
 // Chunks whose words one wavefront loads together, and the kernel's
 // occupancy target.  The deviation stage's queue (12 bytes per entry, 64
 // (chunks + 1) entries per wavefront) shares the LDS with the LB_SAX table:
@@ -31,7 +31,6 @@ constexpr int filter_occupancy() {
     return W16 == 1 ? 4 : (W16 == 2 ? 3 : 2);
 }
 constexpr int kQueue = 128;         // live-chunk queue per wavefront (power of two)
-constexpr int kUnit = 16;           // most items per unit of work
 
 __device__ __forceinline__ int64_t item_count(const QueryWs& ws) {
     return min((int64_t)ws.counters[kCtrItems], ws.item_cap);
@@ -43,7 +42,7 @@ struct FilterOut {
     uint32_t* sq;
     uint32_t* spart;
     uint32_t cnt;  // entries in this wavefront's slice (uniform)
-    unsigned long long filt, cand, tests;
+    unsigned long long filt, cand, tests, sig;
     bool lost;
 };
 
@@ -120,6 +119,7 @@ __device__ __forceinline__ void sigma_stage(const IndexView& ix, const QueryWs& 
     const int e = valid ? lane : 0;
     const uint32_t pos = sq_pos[e], pk0 = sq_pk[e];
     const float lb0 = sq_lb[e];
+    o.sig += (unsigned long long)m;
     uint4 c[W16];
     load_word<W16>(ix.sig + (int64_t)pos * ix.wstride, c);
     const float h = ix.sig_h, lseg = (float)(ix.n / ix.w);
@@ -260,13 +260,14 @@ __device__ __forceinline__ void filter_batch(const IndexView& ix, const QueryWs&
     drain_sigma<W16>(ix, ws, sq, false, q, thr, s_qst, lane, o);
 }
 
-// Every wavefront walks the items of the window; of item j's chunks it owns
-// wave, wave + 4, wave + 8, ...  Its chunk envelopes are tested kPass at a
-// time (a test spans L = pow2 >= w lanes, one segment each, so a load covers
-// 64 / L chunks); LB_EAPCA is float32 over outward-rounded intervals, summed
-// over the L lanes by a butterfly.  Chunks that pass join the wavefront's
-// queue in LDS, and every batch_chunks<W16>() queued chunks go through filter_batch, so
-// the LB_SAX work comes in full batches whatever fraction of chunks pass.
+// Every wavefront takes part in every item of the window (a unit of up to
+// kUnit items of one query); of item j's chunks it owns wave, wave + 4,
+// wave + 8, ...  Its owned chunks of all the window's items are numbered in
+// item order and tested 64 at a time, one lane per chunk: LB_EAPCA in float32
+// over the chunk's outward-rounded segment intervals, summed segment by
+// segment in the lane.  Chunks that pass join the wavefront's queue in LDS,
+// and every batch_chunks<W16>() queued chunks go through filter_batch, so the
+// LB_SAX work comes in full batches whatever fraction of chunks pass.
 // U: batch-union diagnostics (marks the envelopes tested and the words read).
 template <int W16, bool U>
 __global__ void __launch_bounds__(256, filter_occupancy<W16>()) k_filter(IndexView ix, ScanParams sp, QueryWs ws) {
@@ -279,25 +280,16 @@ __global__ void __launch_bounds__(256, filter_occupancy<W16>()) k_filter(IndexVi
     constexpr int kSigCap = 64 * (batch_chunks<W16>() + 1);
     __shared__ uint32_t s_sq_pos[kWaves][kSigCap], s_sq_pk[kWaves][kSigCap];
     __shared__ float s_sq_lb[kWaves][kSigCap];
-    __shared__ uint32_t s_pb[kWin], s_pe[kWin], s_c0[kWin];
+    __shared__ uint32_t s_pb[kUnit], s_pe[kUnit], s_c0[kUnit];
+    __shared__ uint32_t s_pre[kWaves][kUnit + 1];  // owned chunks before each item, per wavefront
     __shared__ float4 s_qst[64];                // query segment mean / std intervals
     __shared__ int s_end;
     __shared__ long long s_unit;
-    constexpr int kPass = 4;  // envelope loads in flight together
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
-    int L = 1;
-    while (L < ix.w) L <<= 1;
-    const int cpp = 64 / L;                 // chunks per envelope load
-    const int seg = lane % L;
-    const bool seg_ok = seg < ix.w;
-    const bool head_lane = seg == 0;
     const float lseg = (float)(ix.n / ix.w);
     const uint64_t lt_mask = (1ull << lane) - 1ull;
-    // envelope of owned chunk number s = i cpp + lane / L of an item: chunk wave + 4 s
-    const int lane_chunk = wave + kWaves * (lane / L);
-    const uint32_t lane_eoff = (uint32_t)((lane_chunk * ix.w + seg) * 16);
-    const uint32_t pass_eoff = (uint32_t)(kWaves * cpp * ix.w * 16);
     uint2* queue = s_queue[wave];
+    uint32_t* pre = s_pre[wave];
     SigQueue sq{s_sq_pos[wave], s_sq_lb[wave], s_sq_pk[wave], 0u};
 
     const int64_t slice = (int64_t)sp.slice0 + (int64_t)blockIdx.x * kWaves + wave;
@@ -313,7 +305,7 @@ __global__ void __launch_bounds__(256, filter_occupancy<W16>()) k_filter(IndexVi
     int64_t idx = (int64_t)blockIdx.x * unit, uend = min(total, idx + unit);
     int cur_q = -1;
     while (idx < uend) {
-        const int n = (int)min((int64_t)kWin, uend - idx);
+        const int n = (int)min((int64_t)kUnit, uend - idx);
         const int q = (int)(ws.items[idx] >> 32);
         __syncthreads();  // no wave still reads the previous window or table
         if (t == 0) s_end = n;
@@ -338,83 +330,101 @@ __global__ void __launch_bounds__(256, filter_occupancy<W16>()) k_filter(IndexVi
         // largest float32 not above the prune limit: for a float32 bound b,
         // b <= thr exactly when (double) b <= limit
         const float thr = __double2float_rd(prune_limit(bits_to_float(bsf_bits(ws, q))));
-        const float4 qs = s_qst[seg];
-        o.filt = o.cand = o.tests = 0;
+        o.filt = o.cand = o.tests = o.sig = 0;
         o.lost = false;
         uint32_t head = 0, tail = 0;  // queue positions (uniform)
 
-        for (int j = 0; j < m; ++j) {
-            const uint32_t pb = s_pb[j], pe = s_pe[j], c0 = s_c0[j];
+        // skip-sequential path: every chunk of every item is queued untested,
+        // and every series becomes a candidate
+        for (int j = 0; skip && j < m; ++j) {
+            const uint32_t pb = s_pb[j], pe = s_pe[j];
             const int nch = (int)((pe - pb + kChunkRows - 1) / kChunkRows);
             const int owned = nch > wave ? (nch - wave + kWaves - 1) / kWaves : 0;
-            if (skip) {
-                // skip-sequential path: every chunk of the item is queued
-                // untested, and every series becomes a candidate
-                for (int s0 = 0; s0 < owned; s0 += 64) {
-                    const int s = s0 + lane;
-                    if (s < owned) {
-                        const uint32_t a = pb + (uint32_t)((wave + kWaves * s) * kChunkRows);
-                        queue[(tail + (uint32_t)s - (uint32_t)s0) & (kQueue - 1)] = make_uint2(a, min(pe, a + kChunkRows));
+            for (int s0 = 0; s0 < owned; s0 += 64) {
+                const int s = s0 + lane;
+                if (s < owned) {
+                    const uint32_t a = pb + (uint32_t)((wave + kWaves * s) * kChunkRows);
+                    queue[(tail + (uint32_t)s - (uint32_t)s0) & (kQueue - 1)] = make_uint2(a, min(pe, a + kChunkRows));
+                }
+                const uint32_t add = (uint32_t)min(64, owned - s0);
+                // drain as the queue fills (at most kBatch - 1 + 64 < kQueue entries)
+                tail += add;
+                __builtin_amdgcn_wave_barrier();
+                while (tail - head >= kBatch) {
+                    filter_batch<W16, U>(ix, ws, queue, head, kBatch, q, thr, true, s_lut, s_qst, sq, lane, o);
+                    head += kBatch;
+                }
+            }
+        }
+        if (!skip) {
+            // the wavefront's owned chunks per item (lanes 0..m-1) and their
+            // running total: owned chunk g lies in the last item j with pre[j] <= g
+            uint32_t own = 0;
+            if (lane < m) {
+                const uint32_t nch = (s_pe[lane] - s_pb[lane] + kChunkRows - 1) / kChunkRows;
+                own = nch > (uint32_t)wave ? (nch - (uint32_t)wave + kWaves - 1) / kWaves : 0u;
+            }
+            uint32_t inc = own;
+#pragma unroll
+            for (int d = 1; d < kUnit; d <<= 1) {
+                const uint32_t y = __shfl_up(inc, d, 64);
+                if (lane >= d) inc += y;
+            }
+            if (lane < m) pre[lane + 1] = inc;
+            if (lane == 0) pre[0] = 0u;
+            const uint32_t total_owned = (uint32_t)__shfl(inc, m - 1, 64);
+            __builtin_amdgcn_wave_barrier();
+            for (uint32_t g0 = 0; g0 < total_owned; g0 += 64) {
+                const uint32_t g = g0 + (uint32_t)lane;
+                const bool valid = g < total_owned;
+                int j = 0;
+#pragma unroll
+                for (int step = kUnit / 2; step; step >>= 1)
+                    if (j + step < m && pre[j + step] <= g) j += step;
+                const uint32_t cn = (uint32_t)wave + kWaves * (g - pre[j]);  // chunk number in item j
+                const uint32_t pb = s_pb[j], pe = s_pe[j];
+                const int64_t chunk = (int64_t)s_c0[j] + cn;
+                float acc = 0.0f;
+                if (valid) {
+                    const float4* e = ix.cenv + chunk * ix.w;
+                    int i = 0;
+                    for (; i + 4 <= ix.w; i += 4) {
+                        float4 ce[4];
+#pragma unroll
+                        for (int u = 0; u < 4; ++u) ce[u] = e[i + u];
+#pragma unroll
+                        for (int u = 0; u < 4; ++u) {
+                            const float4 qs = s_qst[i + u];
+                            const float gm = fmaxf(0.0f, fmaxf(ce[u].x - qs.y, qs.x - ce[u].y));
+                            const float gs = fmaxf(0.0f, fmaxf(ce[u].z - qs.w, qs.z - ce[u].w));
+                            acc = fmaf(gm, gm, acc);
+                            acc = fmaf(gs, gs, acc);
+                        }
                     }
-                    const uint32_t add = (uint32_t)min(64, owned - s0);
-                    // drain as the queue fills (at most kBatch - 1 + 64 < kQueue entries)
-                    tail += add;
-                    __builtin_amdgcn_wave_barrier();
-                    while (tail - head >= kBatch) {
-                        filter_batch<W16, U>(ix, ws, queue, head, kBatch, q, thr, true, s_lut, s_qst, sq, lane, o);
-                        head += kBatch;
+                    for (; i < ix.w; ++i) {
+                        const float4 ce = e[i], qs = s_qst[i];
+                        const float gm = fmaxf(0.0f, fmaxf(ce.x - qs.y, qs.x - ce.y));
+                        const float gs = fmaxf(0.0f, fmaxf(ce.z - qs.w, qs.z - ce.w));
+                        acc = fmaf(gm, gm, acc);
+                        acc = fmaf(gs, gs, acc);
                     }
                 }
-                continue;
-            }
-            const __amdgpu_buffer_rsrc_t rs = buffer_rsrc(ix.cenv + (int64_t)c0 * ix.w, (uint32_t)(nch * ix.w * 16));
-            for (int i0p = 0; i0p * cpp < owned; i0p += kPass) {
-                // kPass envelope loads in flight; chunks past the part load zeros
-                u32x4_t ce[kPass];
-#pragma unroll
-                for (int i = 0; i < kPass; ++i)
-                    ce[i] = __builtin_amdgcn_raw_buffer_load_b128(
-                        rs, (int)(lane_eoff + (uint32_t)(i0p + i) * pass_eoff), 0, 0);
-#pragma unroll
-                for (int i = 0; i < kPass; ++i) {
-                    const int sb = (i0p + i) * cpp;  // first owned chunk number of this load
-                    if (sb >= owned) break;
-                    const bool valid = sb + lane / L < owned;
-                    float term = 0.0f;
-                    if (seg_ok) {
-                        const float ex = __uint_as_float(ce[i].x), ey = __uint_as_float(ce[i].y);
-                        const float ez = __uint_as_float(ce[i].z), ew = __uint_as_float(ce[i].w);
-                        const float gm = fmaxf(0.0f, fmaxf(ex - qs.y, qs.x - ey));
-                        const float gs = fmaxf(0.0f, fmaxf(ez - qs.w, qs.z - ew));
-                        term = lseg * (gm * gm + gs * gs);
-                    }
-                    // butterfly over the test's L lanes: DPP moves within a row of 16
-                    // (xor 1 and 2 first, so the mirrors for 4 and 8 are exact), a
-                    // shuffle across rows only when w > 16 (L is uniform)
-                    if (L >= 2) term += row_xor<1>(term);
-                    if (L >= 4) term += row_xor<2>(term);
-                    if (L >= 8) term += row_xor<4>(term);
-                    if (L >= 16) term += row_xor<8>(term);
-                    if (L >= 32) term += __shfl_xor(term, 16, 64);
-                    if (L >= 64) term += __shfl_xor(term, 32, 64);
-                    const bool live = valid && head_lane && term <= thr;
-                    o.tests += (unsigned long long)__popcll(__ballot(valid && head_lane));
-                    if (U && valid && head_lane) {
-                        const int64_t bit = ws.env_bit0 + (int64_t)c0 + lane_chunk + kWaves * sb;
-                        atomicOr(&ws.ubits[bit >> 5], 1u << (bit & 31));
-                    }
-                    const uint64_t lm = __ballot(live);
-                    if (live) {
-                        const uint32_t a = pb + (uint32_t)((lane_chunk + kWaves * sb) * kChunkRows);
-                        queue[(tail + (uint32_t)__popcll(lm & lt_mask)) & (kQueue - 1)] =
-                            make_uint2(a, min(pe, a + kChunkRows));
-                    }
-                    tail += (uint32_t)__popcll(lm);
-                    __builtin_amdgcn_wave_barrier();
-                    while (tail - head >= kBatch) {
-                        filter_batch<W16, U>(ix, ws, queue, head, kBatch, q, thr, false, s_lut, s_qst, sq, lane, o);
-                        head += kBatch;
-                    }
+                const bool live = valid && lseg * acc <= thr;
+                o.tests += (unsigned long long)__popcll(__ballot(valid));
+                if (U && valid) {
+                    const int64_t bit = ws.env_bit0 + chunk;
+                    atomicOr(&ws.ubits[bit >> 5], 1u << (bit & 31));
+                }
+                const uint64_t lm = __ballot(live);
+                if (live) {
+                    const uint32_t a = pb + cn * kChunkRows;
+                    queue[(tail + (uint32_t)__popcll(lm & lt_mask)) & (kQueue - 1)] = make_uint2(a, min(pe, a + kChunkRows));
+                }
+                tail += (uint32_t)__popcll(lm);
+                __builtin_amdgcn_wave_barrier();
+                while (tail - head >= kBatch) {
+                    filter_batch<W16, U>(ix, ws, queue, head, kBatch, q, thr, false, s_lut, s_qst, sq, lane, o);
+                    head += kBatch;
                 }
             }
         }
@@ -424,9 +434,10 @@ __global__ void __launch_bounds__(256, filter_occupancy<W16>()) k_filter(IndexVi
         drain_sigma<W16>(ix, ws, sq, true, q, thr, s_qst, lane, o);
         idx += m;
         if (lane == 0) {
-            atomicAdd(&ws.stats[(int64_t)q * 8 + 1], skip ? 0ull : o.filt);
-            atomicAdd(&ws.stats[(int64_t)q * 8 + 6], o.cand);
-            atomicAdd(&ws.stats[(int64_t)q * 8 + 7], o.tests);
+            atomicAdd(&ws.stats[(int64_t)q * kStatSlots + 1], skip ? 0ull : o.filt);
+            atomicAdd(&ws.stats[(int64_t)q * kStatSlots + 6], o.cand);
+            atomicAdd(&ws.stats[(int64_t)q * kStatSlots + 7], o.tests);
+            atomicAdd(&ws.stats[(int64_t)q * kStatSlots + 8], o.sig);
             if (o.lost) atomicOr(&ws.flags[q], kFlagCandLost);
         }
         if (idx >= uend) {

@@ -48,6 +48,7 @@ constexpr int kCtrOvfEnd = 7;    // smallest base of an overflow range that did 
 constexpr int kCtrBound = 8;     // 8 slots: the bounding pass's work counter of each XCD
 constexpr int kCtrLost = 16;     // queries of the last merge whose candidates were dropped
 constexpr int kNumCounters = 17;
+constexpr int kStatSlots = 16;   // per-query counters in the workspace (hs_query_stats reads 10)
 
 // Distance forms of the refinement (template argument F of the kernels that
 // refine): float32 sum in a fixed order, or compensated float32 (error-free
@@ -107,7 +108,7 @@ struct QueryWs {
     uint32_t* flags;      // [Q] kFlag* bits
     uint32_t* kept;       // [Q] candidate leaves after the leaf filter
     uint64_t* pool;       // [Q][P]
-    unsigned long long* stats;  // [Q][8]
+    unsigned long long* stats;  // [Q][kStatSlots]
     uint64_t* items;      // [item_cap] (q << 32 | part)
     // filter output: one private slice per filter wavefront
     uint32_t* slice_pos;  // [n_slices][slice_cap] stored position of a candidate series

@@ -553,9 +553,9 @@ __global__ void __launch_bounds__(256) k_bound(IndexView ix, ShadowView sv, Scan
             const int nvalid = __popcll(__ballot(qvalid && half == 0));
             if (lane == 0 && nvalid > 0) staged += (unsigned long long)(32 - nvalid) * staged;
             if (half == 0 && qvalid) {
-                if (tested) atomicAdd(&ws.stats[(int64_t)qj * 8 + 0], tested);
-                if (cands) atomicAdd(&ws.stats[(int64_t)qj * 8 + 6], cands);
-                if (staged) atomicAdd(&ws.stats[(int64_t)qj * 8 + 4], staged);
+                if (tested) atomicAdd(&ws.stats[(int64_t)qj * kStatSlots + 0], tested);
+                if (cands) atomicAdd(&ws.stats[(int64_t)qj * kStatSlots + 6], cands);
+                if (staged) atomicAdd(&ws.stats[(int64_t)qj * kStatSlots + 4], staged);
             }
             if (lost) atomicOr(&ws.flags[qj], kFlagCandLost);
         }

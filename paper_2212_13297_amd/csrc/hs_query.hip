@@ -66,7 +66,7 @@ __global__ void __launch_bounds__(256) k_query_prep(IndexView ix, const float* _
         ws.kept[q] = 0;
         if (s_bad) atomicAdd(&ws.counters[kCtrNonFinite], 1u);
     }
-    if (t < 8) ws.stats[(int64_t)q * 8 + t] = 0;
+    if (t < kStatSlots) ws.stats[(int64_t)q * kStatSlots + t] = 0;
 }
 
 // LB_EAPCA^2 = sum_i l_i [gap(mu_q, [mu_min, mu_max])^2 + gap(sd_q, [sd_min, sd_max])^2]
@@ -270,7 +270,7 @@ __global__ void __launch_bounds__(kSeedThreads) k_seed(IndexView ix, ScanParams 
     if (t == 0) {
         ws.pool_cnt[q] = (uint32_t)n;
         if (n == k) ws.bkey[q] = s_keys[k - 1];
-        unsigned long long* st = ws.stats + (int64_t)q * 8;
+        unsigned long long* st = ws.stats + (int64_t)q * kStatSlots;
         st[1] += (unsigned long long)rows;
         st[2] += (unsigned long long)M;
         st[3] += (unsigned long long)M * nchunks;
@@ -372,7 +372,7 @@ __global__ void __launch_bounds__(1024) k_merge(IndexView ix, ScanParams sp, int
         ws.flags[q] = nf;
         ws.pool_cnt[q] = (uint32_t)u;
         if (u == k) atomicMin(&ws.bkey[q], s_keys[k - 1]);
-        if (sp.final_pass) ws.stats[(int64_t)q * 8 + 5] += 1;
+        if (sp.final_pass) ws.stats[(int64_t)q * kStatSlots + 5] += 1;
     }
     __syncthreads();
     const int u = s_u;
@@ -391,7 +391,7 @@ __global__ void __launch_bounds__(1024) k_merge(IndexView ix, ScanParams sp, int
             }
         }
         if (stats_out && t == 0) {
-            const unsigned long long* st = ws.stats + (int64_t)q * 8;
+            const unsigned long long* st = ws.stats + (int64_t)q * kStatSlots;
             hs_query_stats o;
             o.leaves_kept = ws.kept[q];
             o.rows_filtered = st[1];
@@ -403,6 +403,7 @@ __global__ void __launch_bounds__(1024) k_merge(IndexView ix, ScanParams sp, int
             o.chunks_tested = st[7];
             o.rows_bounded = st[0];
             o.bound_pairs = st[4];
+            o.rows_sigma = st[8];
             stats_out[q] = o;
         }
     }

@@ -273,8 +273,8 @@ __global__ void __launch_bounds__(256, 4) k_refine(IndexView ix, ScanParams sp, 
             c += __shfl_xor(c, o, 64);
         }
         if (lane == 0 && st_q >= 0 && r) {
-            atomicAdd(&ws.stats[(int64_t)st_q * 8 + 2], (unsigned long long)r);
-            atomicAdd(&ws.stats[(int64_t)st_q * 8 + 3], c);
+            atomicAdd(&ws.stats[(int64_t)st_q * kStatSlots + 2], (unsigned long long)r);
+            atomicAdd(&ws.stats[(int64_t)st_q * kStatSlots + 3], c);
         }
         g_ref = 0u;
         g_ch = 0ull;

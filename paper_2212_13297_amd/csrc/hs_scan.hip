@@ -106,7 +106,7 @@ __global__ void __launch_bounds__(256) k_leaf_scan(IndexView ix, ScanParams sp, 
         __syncthreads();
         if (t == 0) {
             flush_topk(ws, q, k, sh.top, sh.topn);
-            unsigned long long* st = ws.stats + (int64_t)q * 8;
+            unsigned long long* st = ws.stats + (int64_t)q * kStatSlots;
             atomicAdd(&st[1], (unsigned long long)sh.st_filt);
             atomicAdd(&st[2], (unsigned long long)sh.st_ref);
             atomicAdd(&st[3], (unsigned long long)sh.st_chunks);

@@ -47,7 +47,8 @@ class hs_query_stats(ctypes.Structure):
     _fields_ = [("leaves_kept", ctypes.c_uint64), ("rows_filtered", ctypes.c_uint64),
                 ("rows_refined", ctypes.c_uint64), ("chunks_read", ctypes.c_uint64), ("path", ctypes.c_uint64),
                 ("rounds", ctypes.c_uint64), ("candidates", ctypes.c_uint64), ("chunks_tested", ctypes.c_uint64),
-                ("rows_bounded", ctypes.c_uint64), ("bound_pairs", ctypes.c_uint64)]
+                ("rows_bounded", ctypes.c_uint64), ("bound_pairs", ctypes.c_uint64),
+                ("rows_sigma", ctypes.c_uint64)]
 
 
 class hs_server_config(ctypes.Structure):

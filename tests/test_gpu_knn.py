@@ -269,6 +269,9 @@ def test_knn_parity(N, n, w, tau, l_max, k):
     st = {f: v.cpu().numpy() for f, v in st.items()}
     assert np.all(st["rounds"] >= 1)
     assert np.all(st["rows_refined"] >= k)
+    # the deviation stage sees only LB_SAX survivors and passes only candidates
+    assert np.all(st["candidates"] <= st["rows_sigma"])
+    assert np.all(st["rows_sigma"] <= st["rows_filtered"])
     idx.close()
 
 
@@ -278,6 +281,7 @@ def test_knn_k128_and_skip_sequential_path():
     ids, d2, st = run_knn(idx, q, 128, stats=True)
     check_knn(x, q, 128, ids, d2)
     assert np.all(st["path"].cpu().numpy() == 1)
+    assert int(st["rows_sigma"].sum().item()) == 0
     idx.close()
 
 
