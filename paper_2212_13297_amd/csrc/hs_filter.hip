@@ -105,15 +105,17 @@ __device__ __forceinline__ void emit_candidates(const QueryWs& ws, FilterOut& o,
 // The deviation stage for the first m (<= 64) of the wavefront's queued
 // LB_SAX survivors (position, LB_SAX, LB_SAX by quarters packed): lane l
 // loads series sq_pos[l]'s deviation codes and adds the deviation term
-// (segment length x the squared distance from the query's std interval to
-// the code's interval [c h, (c + 1) h], both ends exact in float32) to the
-// bound and to each packed quarter (whose stored values are lower bounds),
-// and keeps the series when the bound does not exceed thr.  s_qst holds
-// zeros for segments past w.
+// (segment length x the squared distance from the query's std interval
+// [lo, hi] to the code's interval [c h, (c + 1) h]) to the bound and to each
+// packed quarter (whose stored values are lower bounds), and keeps the series
+// when the bound does not exceed thr.  s_sig[i] = (-hi, lo - h rounded down)
+// of segment i, zeros past w: the gap max(0, c h - hi, (lo - h) - c h) takes
+// one rounding on each side (c h is exact) and is at most the exact gap
+// before it.
 template <int W16>
 __device__ __forceinline__ void sigma_stage(const IndexView& ix, const QueryWs& ws, const uint32_t* sq_pos,
                                             const float* sq_lb, const uint32_t* sq_pk, int m, int q, float thr,
-                                            const float4* s_qst, int lane, FilterOut& o) {
+                                            const float2* s_sig, int lane, FilterOut& o) {
     constexpr int kQ = 4 * W16;
     const bool valid = lane < m;
     const int e = valid ? lane : 0;
@@ -133,12 +135,14 @@ __device__ __forceinline__ void sigma_stage(const IndexView& ix, const QueryWs& 
             for (int b = 0; b < 4; ++b) {
                 const int i = u * 16 + p * 4 + b;
                 const float code = (float)((parts[p] >> (8 * b)) & 0xffu);
-                const float4 qs = s_qst[i];
-                const float gap = fmaxf(0.0f, fmaxf(code * h - qs.w, qs.z - (code + 1.0f) * h));
-                a[i / kQ] += lseg * gap * gap;
+                const float2 qs = s_sig[i];
+                const float gap = fmaxf(0.0f, fmaxf(fmaf(code, h, qs.x), fmaf(-code, h, qs.y)));
+                a[i / kQ] = fmaf(gap, gap, a[i / kQ]);
             }
         }
     }
+#pragma unroll
+    for (int p = 0; p < 4; ++p) a[p] *= lseg;
     const float lb = lb0 + ((a[0] + a[1]) + (a[2] + a[3]));
 #pragma unroll
     for (int p = 0; p < 4; ++p) a[p] += quarter_value((pk0 >> (8 * p)) & 0xffu);
@@ -158,15 +162,15 @@ struct SigQueue {
 // flush, also on the last fewer than 64.  The rest move to the queue's front.
 template <int W16>
 __device__ __forceinline__ void drain_sigma(const IndexView& ix, const QueryWs& ws, SigQueue& sq, bool flush, int q,
-                                            float thr, const float4* s_qst, int lane, FilterOut& o) {
+                                            float thr, const float2* s_sig, int lane, FilterOut& o) {
     uint32_t done = 0;
     while (sq.cnt - done >= 64) {
-        sigma_stage<W16>(ix, ws, sq.pos + done, sq.lb + done, sq.pk + done, 64, q, thr, s_qst, lane, o);
+        sigma_stage<W16>(ix, ws, sq.pos + done, sq.lb + done, sq.pk + done, 64, q, thr, s_sig, lane, o);
         done += 64;
     }
     const uint32_t rem = sq.cnt - done;
     if (flush && rem) {
-        sigma_stage<W16>(ix, ws, sq.pos + done, sq.lb + done, sq.pk + done, (int)rem, q, thr, s_qst, lane, o);
+        sigma_stage<W16>(ix, ws, sq.pos + done, sq.lb + done, sq.pk + done, (int)rem, q, thr, s_sig, lane, o);
         sq.cnt = 0;
         return;
     }
@@ -199,7 +203,7 @@ __device__ __forceinline__ void drain_sigma(const IndexView& ix, const QueryWs& 
 template <int W16, bool U>
 __device__ __forceinline__ void filter_batch(const IndexView& ix, const QueryWs& ws, const uint2* queue,
                                              uint32_t head, int nb, int q, float thr, bool skip,
-                                             const float* s_lut, const float4* s_qst, SigQueue& sq, int lane,
+                                             const float* s_lut, const float2* s_sig, SigQueue& sq, int lane,
                                              FilterOut& o) {
     const uint32_t wb = (uint32_t)ix.wstride;
     constexpr int kBatch = batch_chunks<W16>();
@@ -257,7 +261,7 @@ __device__ __forceinline__ void filter_batch(const IndexView& ix, const QueryWs&
         sq.cnt += (uint32_t)__popcll(bal);
     }
     __builtin_amdgcn_wave_barrier();
-    drain_sigma<W16>(ix, ws, sq, false, q, thr, s_qst, lane, o);
+    drain_sigma<W16>(ix, ws, sq, false, q, thr, s_sig, lane, o);
 }
 
 // Every wavefront takes part in every item of the window (a unit of up to
@@ -283,6 +287,7 @@ __global__ void __launch_bounds__(256, filter_occupancy<W16>()) k_filter(IndexVi
     __shared__ uint32_t s_pb[kUnit], s_pe[kUnit], s_c0[kUnit];
     __shared__ uint32_t s_pre[kWaves][kUnit + 1];  // owned chunks before each item, per wavefront
     __shared__ float4 s_qst[64];                // query segment mean / std intervals
+    __shared__ float2 s_sig[64];                // the deviation stage's terms of the std intervals
     __shared__ int s_end;
     __shared__ long long s_unit;
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
@@ -321,7 +326,11 @@ __global__ void __launch_bounds__(256, filter_occupancy<W16>()) k_filter(IndexVi
         if (q != cur_q) {
             load_lut<W16>(s_lut, ws.lut + (int64_t)q * ix.w * kCard, ix.w, t, blockDim.x);
             // zeros past w: the padding segments add nothing to the deviation term
-            if (t < 64) s_qst[t] = t < ix.w ? ws.qst32[(int64_t)q * ix.w + t] : make_float4(0.f, 0.f, 0.f, 0.f);
+            if (t < 64) {
+                const float4 qs = t < ix.w ? ws.qst32[(int64_t)q * ix.w + t] : make_float4(0.f, 0.f, 0.f, 0.f);
+                s_qst[t] = qs;
+                s_sig[t] = t < ix.w ? make_float2(-qs.w, __double2float_rd((double)qs.z - (double)ix.sig_h)) : make_float2(0.f, 0.f);
+            }
             cur_q = q;
         }
         __syncthreads();
@@ -351,7 +360,7 @@ __global__ void __launch_bounds__(256, filter_occupancy<W16>()) k_filter(IndexVi
                 tail += add;
                 __builtin_amdgcn_wave_barrier();
                 while (tail - head >= kBatch) {
-                    filter_batch<W16, U>(ix, ws, queue, head, kBatch, q, thr, true, s_lut, s_qst, sq, lane, o);
+                    filter_batch<W16, U>(ix, ws, queue, head, kBatch, q, thr, true, s_lut, s_sig, sq, lane, o);
                     head += kBatch;
                 }
             }
@@ -423,15 +432,15 @@ __global__ void __launch_bounds__(256, filter_occupancy<W16>()) k_filter(IndexVi
                 tail += (uint32_t)__popcll(lm);
                 __builtin_amdgcn_wave_barrier();
                 while (tail - head >= kBatch) {
-                    filter_batch<W16, U>(ix, ws, queue, head, kBatch, q, thr, false, s_lut, s_qst, sq, lane, o);
+                    filter_batch<W16, U>(ix, ws, queue, head, kBatch, q, thr, false, s_lut, s_sig, sq, lane, o);
                     head += kBatch;
                 }
             }
         }
         if (tail != head)
-            filter_batch<W16, U>(ix, ws, queue, head, (int)(tail - head), q, thr, skip, s_lut, s_qst, sq, lane, o);
+            filter_batch<W16, U>(ix, ws, queue, head, (int)(tail - head), q, thr, skip, s_lut, s_sig, sq, lane, o);
         // the window's last survivors, before the next window's query and table
-        drain_sigma<W16>(ix, ws, sq, true, q, thr, s_qst, lane, o);
+        drain_sigma<W16>(ix, ws, sq, true, q, thr, s_sig, lane, o);
         idx += m;
         if (lane == 0) {
             atomicAdd(&ws.stats[(int64_t)q * kStatSlots + 1], skip ? 0ull : o.filt);
