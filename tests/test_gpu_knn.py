@@ -210,6 +210,9 @@ CASES = [
     (9_000, 256, 16, 100, 0, 10),        # no seed leaves
     (9_000, 256, 16, 50, 5, 3),          # several seed leaves, small leaves
     (5_000, 64, 4, 5_000, 1, 20),        # a single leaf
+    (8_000, 320, 20, 400, 1, 5),         # w = 20: two-block words with 12 padding segments
+    (6_000, 384, 48, 300, 2, 10),        # w = 48: three-block words
+    (4_000, 256, 64, 500, 1, 4),         # w = 64: four-block words, 4 points per segment
 ]
 
 
