@@ -87,6 +87,17 @@ def measured_traffic(kernel, workload):
 MFMA_PEAK_TFLOPS = {"bf16": 2500.0, "fp16": 2500.0}
 # LDS: 256 compute units x 32 banks x one 4-byte access per bank per clock x 2.4 GHz
 LDS_PEAK_TLOOKUPS = 256 * 32 * 2.4e9 / 1e12
+_LDS_PROBE = {}
+
+
+def lds_probe(hs):
+    """Achievable LDS lookup rates (T/s), measured once per process: 16 lookups
+    per round into a 16 x 256 table, conflict-free and at random symbols."""
+    if not _LDS_PROBE:
+        _LDS_PROBE["conflict_free"] = round(hs.lds_probe_tps(0) / 1e12, 3)
+        _LDS_PROBE["random"] = round(hs.lds_probe_tps(1) / 1e12, 3)
+        log(f"LDS lookup probe: {_LDS_PROBE} T/s")
+    return dict(_LDS_PROBE)
 
 
 def run_mixed(hs, torch, idx, qt, k, steps, warmup, wl, plain_ids, plain_d2, build=True):
@@ -227,9 +238,13 @@ def measure_plain(hs, torch, idx, qt, k, steps, warmup, w, wl, read_gbs):
         kms, launches = prof["filter"]
         avg = kms / launches
         lookups = int(stats["rows_filtered"].sum()) * w / (launches / steps)
+        probe = lds_probe(hs)
+        tps = lookups / (avg / 1e3) / 1e12
         kern["filter"].update({"bound": "lds", "lds_lookups_per_launch": int(lookups),
-                               "lds_lookups_T_s": round(lookups / (avg / 1e3) / 1e12, 3),
-                               "lds_frac": round(lookups / (avg / 1e3) / 1e12 / LDS_PEAK_TLOOKUPS, 4)})
+                               "lds_lookups_T_s": round(tps, 3),
+                               "lds_frac": round(tps / LDS_PEAK_TLOOKUPS, 4),
+                               "achievable_lookups_T_s": probe,
+                               "frac_of_achievable_random": round(tps / probe["random"], 4)})
     if "refine" in kern:
         kern["refine"]["bound"] = "hbm"
     dom = max(kern, key=lambda n: kern[n]["avg_launch_ms"] * kern[n]["launches_per_step"]) if kern else None

@@ -476,6 +476,23 @@ hs_status hs_union_count(const hs_index* idx, const void* bits_dev, uint64_t* co
 hs_status hs_read_probe(const void* buf_dev, int64_t bytes, int32_t passes, uint32_t* sink_dev, void* stream,
                         double* ms);
 
+/* Diagnostics: the device's achievable rate of 4-byte LDS table lookups,
+ * reported beside the nominal LDS peak for the LB_SAX filter.  Each compute
+ * unit runs 4 workgroups of 256 threads; each thread makes `rounds` rounds of
+ * 16 lookups into a 16 x 256 float table in LDS, one per row, at the
+ * same per-thread symbols every round.  pattern 0: row r at symbol
+ * (lane + 7 r) mod 64, so a wavefront's lanes read 64 consecutive words of
+ * the row (no bank conflicts); pattern 1: pseudo-random symbols (a hash of
+ * thread and row), as the words of unrelated series give.  One warm-up
+ * launch, then `passes` timed ones;
+ * *lookups_per_s = lookups of the timed launches / their event-timed
+ * seconds.  sink_dev: 4 caller-owned device bytes the probe may write (it
+ * practically never does).  Synchronises the stream.
+ * Errors: HS_EINVAL (NULL, pattern not 0 or 1, rounds outside 1..2^20,
+ * passes < 1), HS_EHIP. */
+hs_status hs_lds_probe(int32_t pattern, int32_t rounds, int32_t passes, uint32_t* sink_dev, void* stream,
+                       double* lookups_per_s);
+
 /* Release the host handle (does not free index_mem_dev). NULL is allowed. */
 hs_status hs_index_free(hs_index* idx);
 

@@ -997,6 +997,34 @@ hs_status hs_profile_read(int32_t kind, double* ms, int64_t* launches, int32_t r
     return HS_OK;
 }
 
+hs_status hs_lds_probe(int32_t pattern, int32_t rounds, int32_t passes, uint32_t* sink_dev, void* stream,
+                       double* lookups_per_s) {
+    if (!sink_dev || !lookups_per_s) return fail(HS_EINVAL, "NULL argument");
+    if ((pattern != 0 && pattern != 1) || rounds < 1 || rounds > (1 << 20) || passes < 1)
+        return fail(HS_EINVAL, "pattern=%d (0 or 1), rounds=%d (1..2^20), passes=%d (>= 1)", pattern, rounds, passes);
+    hipStream_t st = (hipStream_t)stream;
+    int device = 0, cus = 0;
+    HIP_TRY(hipGetDevice(&device));
+    HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device));
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    hipError_t e = hipEventCreate(&e0);
+    if (e == hipSuccess) e = hipEventCreate(&e1);
+    if (e == hipSuccess) e = launch_lds_probe(pattern, rounds, sink_dev, cus, st);  // warm-up launch
+    if (e == hipSuccess) e = hipEventRecord(e0, st);
+    for (int32_t i = 0; i < passes && e == hipSuccess; ++i) e = launch_lds_probe(pattern, rounds, sink_dev, cus, st);
+    if (e == hipSuccess) e = hipEventRecord(e1, st);
+    if (e == hipSuccess) e = hipEventSynchronize(e1);
+    float t = 0.0f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&t, e0, e1);
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    if (e != hipSuccess) return fail(HS_EHIP, "LDS probe: %s", hipGetErrorString(e));
+    if (!(t > 0.0f)) return fail(HS_EHIP, "LDS probe: no elapsed time");
+    const double lookups = (double)cus * 4 * 256 * (double)rounds * 16 * passes;
+    *lookups_per_s = lookups / ((double)t / 1e3);
+    return HS_OK;
+}
+
 hs_status hs_read_probe(const void* buf_dev, int64_t bytes, int32_t passes, uint32_t* sink_dev, void* stream,
                         double* ms) {
     if (!buf_dev || !sink_dev || !ms) return fail(HS_EINVAL, "NULL argument");

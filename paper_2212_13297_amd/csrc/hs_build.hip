@@ -189,7 +189,49 @@ __global__ void __launch_bounds__(256) k_read_probe(const uint4* __restrict__ p,
     if (acc == 0x9e3779b9u) sink[0] = acc;
 }
 
+// LDS lookup probe: a 16 x 256 float table (the LB_SAX table's shape at 16
+// segments) and, per round, one lookup per row at the lane's symbol for that
+// row: pattern 0 takes (lane + 7 row) mod 64 (a wavefront's 64 lanes read 64
+// consecutive words of the row, no two in one bank), pattern 1 a
+// pseudo-random byte per (thread, row) (as the words of unrelated series
+// give).  The lookup addresses are computed once; an empty asm statement
+// with a memory clobber makes every round load them again, so a round costs
+// 16 loads and 16 adds.  The sums are stored only if they equal a fixed
+// constant, so the lookups stay and practically nothing is written.
+constexpr int kProbeRows = 16;
+template <int P>
+__global__ void __launch_bounds__(256) k_lds_probe(int32_t rounds, uint32_t* sink) {
+    __shared__ float s_tab[kProbeRows * 256];
+    for (int j = threadIdx.x; j < kProbeRows * 256; j += blockDim.x) s_tab[j] = (float)(j & 1023) * 0.5f;
+    __syncthreads();
+    const uint32_t lane = threadIdx.x & 63u, tid = blockIdx.x * blockDim.x + threadIdx.x;
+    uint32_t idx[kProbeRows];
+#pragma unroll
+    for (int row = 0; row < kProbeRows; ++row) {
+        uint32_t h = (tid * 16u + (uint32_t)row) * 2654435761u;
+        h ^= h >> 15;
+        h *= 2246822519u;
+        h ^= h >> 13;
+        idx[row] = (uint32_t)row * 256u + (P == 0 ? ((lane + 7u * row) & 63u) : (h >> 24));
+    }
+    float acc[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+    for (int32_t r = 0; r < rounds; ++r) {
+        asm volatile("" ::: "memory");
+#pragma unroll
+        for (int row = 0; row < kProbeRows; ++row) acc[row % 4] += s_tab[idx[row]];
+    }
+    if (__float_as_uint((acc[0] + acc[1]) + (acc[2] + acc[3])) == 0x9e3779b9u) sink[0] = 1u;
+}
+
 }  // namespace
+
+hipError_t launch_lds_probe(int pattern, int32_t rounds, uint32_t* sink, int device_cus, hipStream_t st) {
+    if (pattern == 0)
+        hipLaunchKernelGGL(k_lds_probe<0>, dim3(device_cus * 4), dim3(256), 0, st, rounds, sink);
+    else
+        hipLaunchKernelGGL(k_lds_probe<1>, dim3(device_cus * 4), dim3(256), 0, st, rounds, sink);
+    return hipGetLastError();
+}
 
 hipError_t launch_read_probe(const void* buf, int64_t bytes, uint32_t* sink, int device_cus, hipStream_t st) {
     hipLaunchKernelGGL(k_read_probe, dim3(device_cus * 8), dim3(256), 0, st, (const uint4*)buf, bytes / 16, sink);

@@ -103,24 +103,23 @@ __device__ __forceinline__ void emit_candidates(const QueryWs& ws, FilterOut& o,
 }
 
 // The deviation stage for the first m (<= 64) of the wavefront's queued
-// LB_SAX survivors (position, LB_SAX, LB_SAX by quarters packed): lane l
-// loads series sq_pos[l]'s deviation codes and adds the deviation term
-// (segment length x the squared distance from the query's std interval
-// [lo, hi] to the code's interval [c h, (c + 1) h]) to the bound and to each
-// packed quarter (whose stored values are lower bounds), and keeps the series
-// when the bound does not exceed thr.  s_sig[i] = (-hi, lo - h rounded down)
+// LB_SAX survivors (position; LB_SAX by quarters as fp16 pairs rounded toward
+// zero, so at most the float32 quarters): lane l loads series sq_pos[l]'s
+// deviation codes and adds the deviation term (segment length x the squared
+// distance from the query's std interval [lo, hi] to the code's interval
+// [c h, (c + 1) h]) to each quarter, and keeps the series when the sum of the
+// four does not exceed thr; a kept series carries them packed.  s_sig[i] = (-hi, lo - h rounded down)
 // of segment i, zeros past w: the gap max(0, c h - hi, (lo - h) - c h) takes
 // one rounding on each side (c h is exact) and is at most the exact gap
 // before it.
 template <int W16>
 __device__ __forceinline__ void sigma_stage(const IndexView& ix, const QueryWs& ws, const uint32_t* sq_pos,
-                                            const float* sq_lb, const uint32_t* sq_pk, int m, int q, float thr,
-                                            const float2* s_sig, int lane, FilterOut& o) {
+                                            const uint32_t* sq_h01, const uint32_t* sq_h23, int m, int q,
+                                            float thr, const float2* s_sig, int lane, FilterOut& o) {
     constexpr int kQ = 4 * W16;
     const bool valid = lane < m;
     const int e = valid ? lane : 0;
-    const uint32_t pos = sq_pos[e], pk0 = sq_pk[e];
-    const float lb0 = sq_lb[e];
+    const uint32_t pos = sq_pos[e], h01 = sq_h01[e], h23 = sq_h23[e];
     o.sig += (unsigned long long)m;
     uint4 c[W16];
     load_word<W16>(ix.sig + (int64_t)pos * ix.wstride, c);
@@ -141,11 +140,13 @@ __device__ __forceinline__ void sigma_stage(const IndexView& ix, const QueryWs& 
             }
         }
     }
+    const float q16[4] = {(float)__builtin_bit_cast(_Float16, (uint16_t)(h01 & 0xffffu)),
+                          (float)__builtin_bit_cast(_Float16, (uint16_t)(h01 >> 16)),
+                          (float)__builtin_bit_cast(_Float16, (uint16_t)(h23 & 0xffffu)),
+                          (float)__builtin_bit_cast(_Float16, (uint16_t)(h23 >> 16))};
 #pragma unroll
-    for (int p = 0; p < 4; ++p) a[p] *= lseg;
-    const float lb = lb0 + ((a[0] + a[1]) + (a[2] + a[3]));
-#pragma unroll
-    for (int p = 0; p < 4; ++p) a[p] += quarter_value((pk0 >> (8 * p)) & 0xffu);
+    for (int p = 0; p < 4; ++p) a[p] = fmaf(a[p], lseg, q16[p]);
+    const float lb = (a[0] + a[1]) + (a[2] + a[3]);
     const uint32_t posv[1] = {pos}, pkv[1] = {pack_quarters(a[0], a[1], a[2], a[3])};
     emit_candidates<1>(ws, o, lane, q, (valid && lb <= thr) ? 1u : 0u, posv, pkv);
 }
@@ -153,9 +154,9 @@ __device__ __forceinline__ void sigma_stage(const IndexView& ix, const QueryWs& 
 // The wavefront's queue of LB_SAX survivors waiting for the deviation stage.
 struct SigQueue {
     uint32_t* pos;
-    float* lb;
-    uint32_t* pk;
-    uint32_t cnt;  // entries (uniform)
+    uint32_t* h01;  // quarters 0 and 1 as fp16, rounded toward zero
+    uint32_t* h23;  // quarters 2 and 3
+    uint32_t cnt;   // entries (uniform)
 };
 
 // Runs the deviation stage on the queued survivors 64 at a time; with
@@ -165,25 +166,25 @@ __device__ __forceinline__ void drain_sigma(const IndexView& ix, const QueryWs& 
                                             float thr, const float2* s_sig, int lane, FilterOut& o) {
     uint32_t done = 0;
     while (sq.cnt - done >= 64) {
-        sigma_stage<W16>(ix, ws, sq.pos + done, sq.lb + done, sq.pk + done, 64, q, thr, s_sig, lane, o);
+        sigma_stage<W16>(ix, ws, sq.pos + done, sq.h01 + done, sq.h23 + done, 64, q, thr, s_sig, lane, o);
         done += 64;
     }
     const uint32_t rem = sq.cnt - done;
     if (flush && rem) {
-        sigma_stage<W16>(ix, ws, sq.pos + done, sq.lb + done, sq.pk + done, (int)rem, q, thr, s_sig, lane, o);
+        sigma_stage<W16>(ix, ws, sq.pos + done, sq.h01 + done, sq.h23 + done, (int)rem, q, thr, s_sig, lane, o);
         sq.cnt = 0;
         return;
     }
     if (done) {
         // rem < 64 <= done: the source and destination ranges do not overlap
         const bool mv = (uint32_t)lane < rem;
-        const uint32_t a = mv ? sq.pos[done + lane] : 0u, c = mv ? sq.pk[done + lane] : 0u;
-        const float b = mv ? sq.lb[done + lane] : 0.0f;
+        const uint32_t a = mv ? sq.pos[done + lane] : 0u, b = mv ? sq.h01[done + lane] : 0u,
+                       c = mv ? sq.h23[done + lane] : 0u;
         __builtin_amdgcn_wave_barrier();
         if (mv) {
             sq.pos[lane] = a;
-            sq.lb[lane] = b;
-            sq.pk[lane] = c;
+            sq.h01[lane] = b;
+            sq.h23[lane] = c;
         }
         __builtin_amdgcn_wave_barrier();
     }
@@ -193,8 +194,8 @@ __device__ __forceinline__ void drain_sigma(const IndexView& ix, const QueryWs& 
 // LB_SAX of up to batch_chunks<W16>() queued chunks (rows [r0, r1) each, r1 - r0 <= 64).
 // Lane l takes series r0 + l of every chunk; the word loads of all chunks
 // are issued before the first table lookup, and rows past a chunk (or slots
-// past the batch) load zeros from no memory.  The survivors (position,
-// LB_SAX, quarters) join the wavefront's deviation queue sq (fewer than 64
+// past the batch) load zeros from no memory.  The survivors (position and
+// quarters) join the wavefront's deviation queue sq (fewer than 64
 // entries on entry, so it holds at most 63 + 64 kBatch), which is drained 64
 // at a time.
 // skip: the skip-sequential path, where every series is a candidate with
@@ -219,46 +220,43 @@ __device__ __forceinline__ void filter_batch(const IndexView& ix, const QueryWs&
 #pragma unroll
         for (int u = 0; u < W16; ++u) v[s][u] = buffer_load16(rs, (uint32_t)lane * wb + 16u * u);
     }
-    const uint64_t lt_mask = (1ull << lane) - 1ull;
-    uint32_t mask = 0;
-    uint32_t pos[kBatch], pk[kBatch];
-    float lbv[kBatch];
-#pragma unroll
-    for (int s = 0; s < kBatch; ++s) {
-        pos[s] = r0[s] + (uint32_t)lane;
-        pk[s] = 0u;
-        lbv[s] = 0.0f;
-        if (s < nb) {
-            float lb = 0.0f;
-            if (!skip) {
-                float a[4];
-                lb_sax_quarters<W16>(v[s], s_lut, a);
-                lb = (a[0] + a[1]) + (a[2] + a[3]);
-                pk[s] = pack_quarters(a[0], a[1], a[2], a[3]);
-                lbv[s] = lb;
-            }
-            o.filt += r1[s] - r0[s];
-            if (U && !skip && (uint32_t)lane < r1[s] - r0[s]) {
-                const int64_t bit = ws.word_bit0 + (int64_t)(r0[s] + (uint32_t)lane);
-                atomicOr(&ws.ubits[bit >> 5], 1u << (bit & 31));
-            }
-            if ((uint32_t)lane < r1[s] - r0[s] && lb <= thr) mask |= 1u << s;
-        }
-    }
     if (skip) {
+        uint32_t mask = 0;
+        uint32_t pos[kBatch], pk[kBatch];
+#pragma unroll
+        for (int s = 0; s < kBatch; ++s) {
+            pos[s] = r0[s] + (uint32_t)lane;
+            pk[s] = 0u;
+            if (s < nb) {
+                o.filt += r1[s] - r0[s];
+                if ((uint32_t)lane < r1[s] - r0[s]) mask |= 1u << s;
+            }
+        }
         emit_candidates<kBatch>(ws, o, lane, q, mask, pos, pk);
         return;
     }
+    const uint64_t lt_mask = (1ull << lane) - 1ull;
 #pragma unroll
     for (int s = 0; s < kBatch; ++s) {
-        const uint64_t bal = __ballot((mask >> s) & 1u);
-        if ((mask >> s) & 1u) {
-            const uint32_t at = sq.cnt + (uint32_t)__popcll(bal & lt_mask);
-            sq.pos[at] = pos[s];
-            sq.lb[at] = lbv[s];
-            sq.pk[at] = pk[s];
+        if (s < nb) {
+            float a[4];
+            lb_sax_quarters<W16>(v[s], s_lut, a);
+            const float lb = (a[0] + a[1]) + (a[2] + a[3]);
+            o.filt += r1[s] - r0[s];
+            if (U && (uint32_t)lane < r1[s] - r0[s]) {
+                const int64_t bit = ws.word_bit0 + (int64_t)(r0[s] + (uint32_t)lane);
+                atomicOr(&ws.ubits[bit >> 5], 1u << (bit & 31));
+            }
+            const bool keep = (uint32_t)lane < r1[s] - r0[s] && lb <= thr;
+            const uint64_t bal = __ballot(keep);
+            if (keep) {
+                const uint32_t at = sq.cnt + (uint32_t)__popcll(bal & lt_mask);
+                sq.pos[at] = r0[s] + (uint32_t)lane;
+                sq.h01[at] = __builtin_bit_cast(uint32_t, __builtin_amdgcn_cvt_pkrtz(a[0], a[1]));
+                sq.h23[at] = __builtin_bit_cast(uint32_t, __builtin_amdgcn_cvt_pkrtz(a[2], a[3]));
+            }
+            sq.cnt += (uint32_t)__popcll(bal);
         }
-        sq.cnt += (uint32_t)__popcll(bal);
     }
     __builtin_amdgcn_wave_barrier();
     drain_sigma<W16>(ix, ws, sq, false, q, thr, s_sig, lane, o);
@@ -282,8 +280,7 @@ __global__ void __launch_bounds__(256, filter_occupancy<W16>()) k_filter(IndexVi
     __shared__ uint2 s_queue[kWaves][kQueue];   // (r0, r1) of live chunks
     // LB_SAX survivors waiting for the deviation stage
     constexpr int kSigCap = 64 * (batch_chunks<W16>() + 1);
-    __shared__ uint32_t s_sq_pos[kWaves][kSigCap], s_sq_pk[kWaves][kSigCap];
-    __shared__ float s_sq_lb[kWaves][kSigCap];
+    __shared__ uint32_t s_sq_pos[kWaves][kSigCap], s_sq_h01[kWaves][kSigCap], s_sq_h23[kWaves][kSigCap];
     __shared__ uint32_t s_pb[kUnit], s_pe[kUnit], s_c0[kUnit];
     __shared__ uint32_t s_pre[kWaves][kUnit + 1];  // owned chunks before each item, per wavefront
     __shared__ float4 s_qst[64];                // query segment mean / std intervals
@@ -295,7 +292,7 @@ __global__ void __launch_bounds__(256, filter_occupancy<W16>()) k_filter(IndexVi
     const uint64_t lt_mask = (1ull << lane) - 1ull;
     uint2* queue = s_queue[wave];
     uint32_t* pre = s_pre[wave];
-    SigQueue sq{s_sq_pos[wave], s_sq_lb[wave], s_sq_pk[wave], 0u};
+    SigQueue sq{s_sq_pos[wave], s_sq_h01[wave], s_sq_h23[wave], 0u};
 
     const int64_t slice = (int64_t)sp.slice0 + (int64_t)blockIdx.x * kWaves + wave;
     FilterOut o{ws.slice_pos + slice * ws.slice_cap, ws.slice_q + slice * ws.slice_cap,

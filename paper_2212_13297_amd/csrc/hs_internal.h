@@ -184,6 +184,7 @@ hipError_t launch_words(const IndexView& ix, uint8_t* words, uint8_t* sig, hipSt
 // each, std >= 0) as float bits, by atomicMax into *out.
 hipError_t launch_max_sigma(const float2* st, int64_t count, uint32_t* out, hipStream_t st_);
 hipError_t launch_read_probe(const void* buf, int64_t bytes, uint32_t* sink, int device_cus, hipStream_t st);
+hipError_t launch_lds_probe(int pattern, int32_t rounds, uint32_t* sink, int device_cus, hipStream_t st);
 hipError_t launch_envelopes(const IndexView& ix, const int64_t* starts, int64_t count, float4* env,
                             hipStream_t st);
 

@@ -117,6 +117,8 @@ _SIGS = {
     "hs_profile_read": (ctypes.c_int32, [ctypes.c_int32, ctypes.POINTER(ctypes.c_double),
                                          ctypes.POINTER(ctypes.c_int64), ctypes.c_int32]),
     "hs_read_probe": (ctypes.c_int32, [_P, ctypes.c_int64, ctypes.c_int32, _P, _P, ctypes.POINTER(ctypes.c_double)]),
+    "hs_lds_probe": (ctypes.c_int32, [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, _P, _P,
+                                      ctypes.POINTER(ctypes.c_double)]),
     "hs_union_bytes": (ctypes.c_int32, [_P, ctypes.POINTER(ctypes.c_int64)]),
     "hs_union_enable": (ctypes.c_int32, [_P, ctypes.c_int64]),
     "hs_union_count": (ctypes.c_int32, [_P, _P, _P, _P]),
@@ -382,6 +384,19 @@ def read_probe_gbs(buf, passes: int = 5, stream=None) -> float:
     sink = torch.zeros(1, dtype=torch.int32, device=buf.device)
     ms = hs_read_probe(buf.data_ptr(), nbytes, passes, sink.data_ptr(), _stream_ptr(stream))
     return nbytes * passes / (ms / 1e3) / 1e9
+
+
+def hs_lds_probe(pattern: int, rounds: int, passes: int, sink_dev: int, stream: int) -> float:
+    out = ctypes.c_double()
+    _check(load().hs_lds_probe(pattern, rounds, passes, sink_dev, stream, ctypes.byref(out)))
+    return out.value
+
+
+def lds_probe_tps(pattern: int, rounds: int = 4096, passes: int = 3, device="cuda", stream=None) -> float:
+    """Achievable LDS table lookups per second (pattern 0: conflict-free, 1: random symbols)."""
+    import torch
+    sink = torch.zeros(1, dtype=torch.int32, device=device)
+    return hs_lds_probe(pattern, rounds, passes, sink.data_ptr(), _stream_ptr(stream))
 
 
 def hs_union_bytes(h) -> int:

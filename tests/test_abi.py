@@ -69,3 +69,19 @@ def test_read_probe_rejects_bad_arguments():
     assert lib.hs_read_probe(ctypes.addressof(sink), 1 << 20, 1, None, None, ctypes.byref(ms)) == -1
     assert lib.hs_read_probe(ctypes.addressof(sink), 1000, 1, ctypes.addressof(sink), None, ctypes.byref(ms)) == -1
     assert lib.hs_read_probe(ctypes.addressof(sink), 1 << 20, 0, ctypes.addressof(sink), None, ctypes.byref(ms)) == -1
+
+
+def test_lds_probe_rejects_bad_arguments():
+    import ctypes
+    from paper_2212_13297_amd import hs
+    lib = hs.load()
+    out = ctypes.c_double()
+    sink = ctypes.c_uint32()
+    # argument errors are reported before any device call
+    assert lib.hs_lds_probe(0, 16, 1, None, None, ctypes.byref(out)) == -1
+    assert lib.hs_lds_probe(0, 16, 1, ctypes.addressof(sink), None, None) == -1
+    assert lib.hs_lds_probe(2, 16, 1, ctypes.addressof(sink), None, ctypes.byref(out)) == -1
+    assert lib.hs_lds_probe(0, 0, 1, ctypes.addressof(sink), None, ctypes.byref(out)) == -1
+    assert lib.hs_lds_probe(1, (1 << 20) + 1, 1, ctypes.addressof(sink), None, ctypes.byref(out)) == -1
+    assert lib.hs_lds_probe(1, 16, 0, ctypes.addressof(sink), None, ctypes.byref(out)) == -1
+    assert "pattern" in hs.hs_last_error()

@@ -597,6 +597,19 @@ def test_batch_union_counters():
     idx.close()
 
 
+def test_lds_probe_rates():
+    # Both patterns run their lookups without writing the sink; the
+    # conflict-free pattern is not slower than random symbols.
+    hs = hs_mod()
+    sink = torch.zeros(1, dtype=torch.int32, device=DEV)
+    free = hs.hs_lds_probe(0, 512, 2, sink.data_ptr(), 0)
+    rand = hs.hs_lds_probe(1, 512, 2, sink.data_ptr(), 0)
+    torch.cuda.synchronize()
+    print(f"[lds probe] conflict-free {free / 1e12:.2f} T/s, random {rand / 1e12:.2f} T/s", flush=True)
+    assert 1e11 < rand <= 1.05 * free < 1e14
+    assert int(sink.item()) == 0
+
+
 def test_read_probe_reads_without_writing():
     hs = hs_mod()
     buf = torch.arange(1 << 22, dtype=torch.int32, device=DEV)  # 16 MiB
