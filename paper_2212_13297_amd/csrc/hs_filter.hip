@@ -19,9 +19,9 @@ constexpr int kUnit = 16;           // most items per unit of work (and per wind
 // Chunks whose words one wavefront loads together, and the kernel's
 // occupancy target.  The deviation stage's queue (12 bytes per entry, 64
 // (chunks + 1) entries per wavefront) shares the LDS with the LB_SAX table:
-// one 16-byte word per series takes 4 chunks at 4 wavefronts per SIMD (40 KB
-// per workgroup); two words 3 chunks at 3 (166 registers, 52 KB); longer
-// words 3 chunks at 2.
+// one 16-byte word per series takes 4 chunks at 4 wavefronts per SIMD (about
+// 120 registers, 37 KB per workgroup); two words 3 chunks at 3 (50 KB); three
+// words 3 chunks at 2 (66 KB); four words fit one workgroup per CU (82 KB).
 template <int W16>
 constexpr int batch_chunks() {
     return W16 == 1 ? 4 : 3;
