@@ -108,10 +108,10 @@ __device__ __forceinline__ void emit_candidates(const QueryWs& ws, FilterOut& o,
 // deviation codes and adds the deviation term (segment length x the squared
 // distance from the query's std interval [lo, hi] to the code's interval
 // [c h, (c + 1) h]) to each quarter, and keeps the series when the sum of the
-// four does not exceed thr; a kept series carries them packed.  s_sig[i] = (-hi, lo - h rounded down)
-// of segment i, zeros past w: the gap max(0, c h - hi, (lo - h) - c h) takes
-// one rounding on each side (c h is exact) and is at most the exact gap
-// before it.
+// four does not exceed thr; a kept series carries them packed.
+// s_sig[i] = (-hi, lo - h rounded down) of segment i, zeros past w: the gap
+// max(0, c h - hi, (lo - h) - c h) takes one rounding on each side (c h is
+// exact) and is at most the exact gap before it.
 template <int W16>
 __device__ __forceinline__ void sigma_stage(const IndexView& ix, const QueryWs& ws, const uint32_t* sq_pos,
                                             const uint32_t* sq_h01, const uint32_t* sq_h23, int m, int q,
@@ -296,7 +296,7 @@ __global__ void __launch_bounds__(256, filter_occupancy<W16>()) k_filter(IndexVi
 
     const int64_t slice = (int64_t)sp.slice0 + (int64_t)blockIdx.x * kWaves + wave;
     FilterOut o{ws.slice_pos + slice * ws.slice_cap, ws.slice_q + slice * ws.slice_cap,
-                ws.slice_part + slice * ws.slice_cap, 0u, 0ull, 0ull, 0ull, false};
+                ws.slice_part + slice * ws.slice_cap, 0u, 0ull, 0ull, 0ull, 0ull, false};
     // Items are dealt out in units of up to kUnit (fewer for a short item
     // list, so that a small batch still spreads over the GPU): a workgroup's
     // first unit by its index, each next one from a counter once it has

@@ -113,7 +113,7 @@ struct QueryWs {
     // filter output: one private slice per filter wavefront
     uint32_t* slice_pos;  // [n_slices][slice_cap] stored position of a candidate series
     uint32_t* slice_q;    // [n_slices][slice_cap] its query
-    uint32_t* slice_part; // [n_slices][slice_cap] its LB_SAX by quarters: four bytes, the high bytes of fp16 values rounded toward zero
+    uint32_t* slice_part; // [n_slices][slice_cap] its lower bound by quarters (LB_SAX plus the deviation term, or the precision form's bound in the first): four bytes, the high bytes of fp16 values rounded toward zero
     uint32_t* slice_cnt;  // [n_slices] entries written in each slice
     uint32_t* slice_start;// [n_slices + 1] exclusive prefix of slice_cnt
     uint32_t* counters;   // [kNumCounters]

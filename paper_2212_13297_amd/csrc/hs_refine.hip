@@ -6,9 +6,10 @@
 // Wavefronts take runs of consecutive candidates (a run holds long stretches
 // of one query) and never wait for one another.  Their 4-lane groups refine
 // one series each, one 64-point chunk per round, in the order of the series'
-// LB_SAX quarter bounds, abandoning a series as soon as its running
-// distance, plus the bounds of its unread quarters, exceeds the limit, and
-// taking the next candidate in its place.
+// quarter bounds (the filter's lower bound -- LB_SAX plus the deviation term
+// -- split by quarters of the word), abandoning a series as soon as its
+// running distance, plus the bounds of its unread quarters, exceeds the
+// limit, and taking the next candidate in its place.
 //
 // What bounds the kernel is the latency of its scattered chunk reads: the
 // memory system serves about the batch's distinct chunks (re-reads of a
@@ -30,7 +31,7 @@ constexpr uint32_t kNaturalPerm = 0xE4u;  // quarters 0, 1, 2, 3
 struct Meta {
     int q;
     uint32_t pos;
-    uint32_t part;  // LB_SAX by quarters, four bytes
+    uint32_t part;  // the filter's lower bound by quarters, four bytes
 };
 
 // The candidate list is the concatenation of the filter's slices (the private
@@ -108,9 +109,10 @@ __device__ __forceinline__ uint32_t chunk_perm(uint32_t part, uint32_t& rem) {
     return perm;
 }
 
-// Ring entry (q | perm << 24, pos, lbs, bsf): lbs = LB_SAX / (1 + slack)
-// rounded down, from the exact float64 sum of the four packed partials (each
-// at most the float32 one), so lbs > limit implies LB_SAX > limit (1 + slack);
+// Ring entry (q | perm << 24, pos, lbs, bsf): lbs = the lower bound / (1 +
+// slack) rounded down, from the exact float64 sum of the four packed partials
+// (each at most the float32 one), so lbs > limit implies a bound above
+// limit (1 + slack);
 // bsf, a BSF_k of the entry's query read before it is handed out (+inf until
 // then).  An entry without a candidate has x = 0xffffffff.  rem: chunk_perm's
 // (0 in natural order).
@@ -353,7 +355,7 @@ __global__ void __launch_bounds__(256, 4) k_refine(IndexView ix, ScanParams sp, 
     for (;;) {
         // hand out candidates to the slots that want one: slot 0 of every
         // wanting group in group order, then slot 1, ...; a candidate whose
-        // LB_SAX exceeds its limit is skipped and the slot asks again
+        // lower bound exceeds its limit is skipped and the slot asks again
         for (;;) {
             if (next - mb >= 64) {
                 // the ring moves on by 64: the entries now handed out have
