@@ -103,8 +103,9 @@ __device__ __forceinline__ void emit_candidates(const QueryWs& ws, FilterOut& o,
 }
 
 // The deviation stage for the first m (<= 64) of the wavefront's queued
-// LB_SAX survivors (position; LB_SAX by quarters as fp16 pairs rounded toward
-// zero, so at most the float32 quarters): lane l loads series sq_pos[l]'s
+// LB_SAX survivors (position; LB_SAX by quarters times the queue's power-of-2
+// scale, as fp16 pairs rounded toward zero, so at most the float32 quarters
+// once unscaled): lane l loads series sq_pos[l]'s
 // deviation codes and adds the deviation term (segment length x the squared
 // distance from the query's std interval [lo, hi] to the code's interval
 // [c h, (c + 1) h]) to each quarter, and keeps the series when the sum of the
@@ -114,8 +115,8 @@ __device__ __forceinline__ void emit_candidates(const QueryWs& ws, FilterOut& o,
 // exact) and is at most the exact gap before it.
 template <int W16>
 __device__ __forceinline__ void sigma_stage(const IndexView& ix, const QueryWs& ws, const uint32_t* sq_pos,
-                                            const uint32_t* sq_h01, const uint32_t* sq_h23, int m, int q,
-                                            float thr, const float2* s_sig, int lane, FilterOut& o) {
+                                            const uint32_t* sq_h01, const uint32_t* sq_h23, float unscale, int m,
+                                            int q, float thr, const float2* s_sig, int lane, FilterOut& o) {
     constexpr int kQ = 4 * W16;
     const bool valid = lane < m;
     const int e = valid ? lane : 0;
@@ -140,10 +141,10 @@ __device__ __forceinline__ void sigma_stage(const IndexView& ix, const QueryWs& 
             }
         }
     }
-    const float q16[4] = {(float)__builtin_bit_cast(_Float16, (uint16_t)(h01 & 0xffffu)),
-                          (float)__builtin_bit_cast(_Float16, (uint16_t)(h01 >> 16)),
-                          (float)__builtin_bit_cast(_Float16, (uint16_t)(h23 & 0xffffu)),
-                          (float)__builtin_bit_cast(_Float16, (uint16_t)(h23 >> 16))};
+    const float q16[4] = {(float)__builtin_bit_cast(_Float16, (uint16_t)(h01 & 0xffffu)) * unscale,
+                          (float)__builtin_bit_cast(_Float16, (uint16_t)(h01 >> 16)) * unscale,
+                          (float)__builtin_bit_cast(_Float16, (uint16_t)(h23 & 0xffffu)) * unscale,
+                          (float)__builtin_bit_cast(_Float16, (uint16_t)(h23 >> 16)) * unscale};
 #pragma unroll
     for (int p = 0; p < 4; ++p) a[p] = fmaf(a[p], lseg, q16[p]);
     const float lb = (a[0] + a[1]) + (a[2] + a[3]);
@@ -152,11 +153,17 @@ __device__ __forceinline__ void sigma_stage(const IndexView& ix, const QueryWs& 
 }
 
 // The wavefront's queue of LB_SAX survivors waiting for the deviation stage.
+// The quarters are stored times scale = 2^-e, e >= 0 the smallest putting
+// the threshold below 2^14, so that quarters up to four times the threshold
+// keep fp16's relative precision; a larger quarter is stored as the largest
+// finite fp16, still above the threshold once unscaled (a series holding one
+// is pruned either way).  Scaling by a power of 2 is exact.
 struct SigQueue {
     uint32_t* pos;
-    uint32_t* h01;  // quarters 0 and 1 as fp16, rounded toward zero
+    uint32_t* h01;  // quarters 0 and 1 (scaled) as fp16, rounded toward zero
     uint32_t* h23;  // quarters 2 and 3
     uint32_t cnt;   // entries (uniform)
+    float scale, unscale;  // 2^-e and 2^e
 };
 
 // Runs the deviation stage on the queued survivors 64 at a time; with
@@ -166,12 +173,14 @@ __device__ __forceinline__ void drain_sigma(const IndexView& ix, const QueryWs& 
                                             float thr, const float2* s_sig, int lane, FilterOut& o) {
     uint32_t done = 0;
     while (sq.cnt - done >= 64) {
-        sigma_stage<W16>(ix, ws, sq.pos + done, sq.h01 + done, sq.h23 + done, 64, q, thr, s_sig, lane, o);
+        sigma_stage<W16>(ix, ws, sq.pos + done, sq.h01 + done, sq.h23 + done, sq.unscale, 64, q, thr, s_sig, lane,
+                         o);
         done += 64;
     }
     const uint32_t rem = sq.cnt - done;
     if (flush && rem) {
-        sigma_stage<W16>(ix, ws, sq.pos + done, sq.h01 + done, sq.h23 + done, (int)rem, q, thr, s_sig, lane, o);
+        sigma_stage<W16>(ix, ws, sq.pos + done, sq.h01 + done, sq.h23 + done, sq.unscale, (int)rem, q, thr, s_sig,
+                         lane, o);
         sq.cnt = 0;
         return;
     }
@@ -252,8 +261,8 @@ __device__ __forceinline__ void filter_batch(const IndexView& ix, const QueryWs&
             if (keep) {
                 const uint32_t at = sq.cnt + (uint32_t)__popcll(bal & lt_mask);
                 sq.pos[at] = r0[s] + (uint32_t)lane;
-                sq.h01[at] = __builtin_bit_cast(uint32_t, __builtin_amdgcn_cvt_pkrtz(a[0], a[1]));
-                sq.h23[at] = __builtin_bit_cast(uint32_t, __builtin_amdgcn_cvt_pkrtz(a[2], a[3]));
+                sq.h01[at] = __builtin_bit_cast(uint32_t, __builtin_amdgcn_cvt_pkrtz(a[0] * sq.scale, a[1] * sq.scale));
+                sq.h23[at] = __builtin_bit_cast(uint32_t, __builtin_amdgcn_cvt_pkrtz(a[2] * sq.scale, a[3] * sq.scale));
             }
             sq.cnt += (uint32_t)__popcll(bal);
         }
@@ -292,7 +301,7 @@ __global__ void __launch_bounds__(256, filter_occupancy<W16>()) k_filter(IndexVi
     const uint64_t lt_mask = (1ull << lane) - 1ull;
     uint2* queue = s_queue[wave];
     uint32_t* pre = s_pre[wave];
-    SigQueue sq{s_sq_pos[wave], s_sq_h01[wave], s_sq_h23[wave], 0u};
+    SigQueue sq{s_sq_pos[wave], s_sq_h01[wave], s_sq_h23[wave], 0u, 1.0f, 1.0f};
 
     const int64_t slice = (int64_t)sp.slice0 + (int64_t)blockIdx.x * kWaves + wave;
     FilterOut o{ws.slice_pos + slice * ws.slice_cap, ws.slice_q + slice * ws.slice_cap,
@@ -336,6 +345,11 @@ __global__ void __launch_bounds__(256, filter_occupancy<W16>()) k_filter(IndexVi
         // largest float32 not above the prune limit: for a float32 bound b,
         // b <= thr exactly when (double) b <= limit
         const float thr = __double2float_rd(prune_limit(bits_to_float(bsf_bits(ws, q))));
+        {
+            const int e = thr < INFINITY && thr >= 16384.0f ? ilogbf(thr) - 13 : 0;  // thr 2^-e < 2^14
+            sq.scale = ldexpf(1.0f, -e);
+            sq.unscale = ldexpf(1.0f, e);
+        }
         o.filt = o.cand = o.tests = o.sig = 0;
         o.lost = false;
         uint32_t head = 0, tail = 0;  // queue positions (uniform)

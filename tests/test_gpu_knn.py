@@ -278,6 +278,28 @@ def test_knn_parity(N, n, w, tau, l_max, k):
     idx.close()
 
 
+def test_large_magnitude_data_scales_exactly():
+    # Series and queries times 1024 (exact in float32): iSAX words and LB_SAX
+    # change (the breakpoints are for z-normalised data) but the search stays
+    # exact, and every distance key scales by exactly 2^20, so the id lists
+    # equal the unscaled run's.  Bounds and thresholds here exceed the fp16
+    # range that the filter's survivor queue stores quarters in (its per-query
+    # power-of-2 scale keeps them in range).
+    x, q = workload(20_000, 256, coll=9, per_level=2, ood=1)
+    idx = make_index(x, w=16, leaf_size=500, l_max=2)
+    ids, d2 = run_knn(idx, q, 10)
+    idx.close()
+    xb, qb = x * np.float32(1024.0), q * np.float32(1024.0)
+    idx = make_index(xb, w=16, leaf_size=500, l_max=2)
+    ids_b, d2_b, st = run_knn(idx, qb, 10, stats=True)
+    idx.close()
+    check_knn(xb, qb, 10, ids_b, d2_b)
+    assert np.array_equal(ids_b, ids)
+    assert np.array_equal(d2_b, d2 * np.float32(2.0 ** 20))
+    print(f"[large magnitude] candidates {st['candidates'].float().mean().item():.0f}, "
+          f"deviation stage {st['rows_sigma'].float().mean().item():.0f}", flush=True)
+
+
 def test_knn_k128_and_skip_sequential_path():
     x, q = workload(15_000, 256, coll=5)
     idx = make_index(x, w=16, leaf_size=400, eapca_th=1.1)   # every query skips LB_SAX
