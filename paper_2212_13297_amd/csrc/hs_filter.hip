@@ -28,7 +28,7 @@ constexpr int batch_chunks() {
 }
 template <int W16>
 constexpr int filter_occupancy() {
-    return W16 == 1 ? 4 : (W16 == 2 ? 3 : 2);
+    return W16 == 1 ? 4 : (W16 == 2 ? 3 : (W16 == 3 ? 2 : 1));
 }
 constexpr int kQueue = 128;         // live-chunk queue per wavefront (power of two)
 
@@ -507,7 +507,7 @@ __global__ void __launch_bounds__(1024) k_slice_prefix(QueryWs ws) {
 }
 
 template <int W16>
-int filter_blocks(const IndexView& ix, int cus) {
+int filter_blocks(int cus) {
     return resident_grid(k_filter<W16, false>, kTile, 0, cus);
 }
 
@@ -516,15 +516,15 @@ int filter_blocks(const IndexView& ix, int cus) {
 int filter_waves(const IndexView& ix, int device_cus) {
     int blocks = 1;
     switch (w16_of(ix)) {
-        case 1: blocks = filter_blocks<1>(ix, device_cus); break;
-        case 2: blocks = filter_blocks<2>(ix, device_cus); break;
-        case 3: blocks = filter_blocks<3>(ix, device_cus); break;
-        default: blocks = filter_blocks<4>(ix, device_cus); break;
+        case 1: blocks = filter_blocks<1>(device_cus); break;
+        case 2: blocks = filter_blocks<2>(device_cus); break;
+        case 3: blocks = filter_blocks<3>(device_cus); break;
+        default: blocks = filter_blocks<4>(device_cus); break;
     }
     return blocks * kWaves;
 }
 
-hipError_t launch_filter(const IndexView& ix, const ScanParams& sp, const QueryWs& ws, int device_cus,
+hipError_t launch_filter(const IndexView& ix, const ScanParams& sp, const QueryWs& ws, int /*device_cus*/,
                          hipStream_t st) {
     const dim3 grid(sp.slices / kWaves);  // one slice per wavefront
     if (ws.ubits) {
