@@ -162,6 +162,9 @@ struct ScanParams {
     // for m chunks), e_c the compensated distance's relative error, u = 2^-24
     // the rounding of the product
     float marg;
+    // a short candidate list is split into one range per wavefront, of at
+    // least this many candidates (the refine sets it per form)
+    int32_t min_range;
 };
 
 // bits of the batch-union array for an index: raw chunk pairs, words, envelopes

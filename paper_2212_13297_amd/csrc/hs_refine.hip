@@ -228,7 +228,8 @@ __global__ void __launch_bounds__(256, 4) k_refine(IndexView ix, ScanParams sp, 
     // A long list is cut into segments of kSeg, the wavefront's first by its
     // index and each next one taken from a counter when the ring reaches it
     // (wavefronts that meet costly candidates take fewer); a short one into
-    // one contiguous range per wavefront.
+    // one contiguous range per wavefront, of at least sp.min_range candidates
+    // (the wavefronts past them have none).
     const long long nseg = (T + kSeg - 1) / kSeg;
     const bool dyn = nseg >= 2 * GW;
     long long vbase = 0, startA, lenA, startB = 0, lenB = 0;
@@ -237,8 +238,9 @@ __global__ void __launch_bounds__(256, 4) k_refine(IndexView ix, ScanParams sp, 
         startA = gw * kSeg;
         lenA = kSeg;
     } else {
-        startA = T * gw / GW;
-        lenA = T * (gw + 1) / GW - startA;
+        const long long GWr = max(1ll, min(GW, T / max(1, sp.min_range)));
+        startA = gw < GWr ? T * gw / GWr : T;
+        lenA = gw < GWr ? T * (gw + 1) / GWr - startA : 0;
     }
     if (lenA <= 0) return;
     // list index c of stream position v (false: past the stream's end)
@@ -593,10 +595,16 @@ __global__ void __launch_bounds__(256, 4) k_refine(IndexView ix, ScanParams sp, 
 }  // namespace
 
 // Both forms refine with the plain running distance; the result keys are the
-// compensated ones either way.
-hipError_t launch_refine(const IndexView& ix, const ScanParams& sp, const QueryWs& ws, int device_cus, int form,
+// compensated ones either way.  A short list of the plain form (a few
+// queries' LB_SAX candidates) goes to wavefronts 32 candidates or more each:
+// one query's list over every wavefront left most of them a handful of
+// candidates and had thousands of them append to that query's result pool
+// (single-query latency 0.42 -> 0.34 ms at 10M x 256).  The precision form's
+// few candidates per query, each refined in full, keep the widest spread.
+hipError_t launch_refine(const IndexView& ix, const ScanParams& sp_in, const QueryWs& ws, int device_cus, int form,
                          hipStream_t st) {
-    (void)form;
+    ScanParams sp = sp_in;
+    sp.min_range = form == kPlain ? 32 : 1;
 #define HS_REFINE(QQ, UU)                                                                     \
     do {                                                                                      \
         auto kern = k_refine<kRefineLanes, kRefineSlots, QQ, UU>;                             \
