@@ -15,7 +15,7 @@ namespace hs {
 namespace {
 
 constexpr int kWaves = kTile / 64;  // wavefronts per workgroup
-constexpr int kUnit = 16;           // most items per unit of work (and per window)
+constexpr int kUnit = 8;            // most items per unit of work (and per window)
 // Chunks whose words one wavefront loads together, and the kernel's
 // occupancy target.  The deviation stage's queue (12 bytes per entry, 64
 // (chunks + 1) entries per wavefront) shares the LDS with the LB_SAX table:
